@@ -1,0 +1,450 @@
+"""CPU reference ("oracle") of the affine-body contact path.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and
+by the CPU-baseline leg of the benchmark, never by the product package.  It
+shares no code with the GPU library.  Per-pair and per-body arithmetic lives
+in ``abd_oracle.cpp`` (plain FP64 loops); this module marshals arrays, solves
+the Newton system with a sparse direct solver (SciPy's SuperLU, used as a
+library primitive) and runs the Newton loop and time step.
+
+Paper passages followed (Lan et al., Affine Body Dynamics):
+  kinematics            sec. 3, Eq. kinematic / kinematic-vel
+  mass matrix           sec. 3.1, Eq. mass
+  orthogonality         sec. 3.2, Eq. orthogonality, ortho-energy, ortho-poly
+  incremental potential sec. 4 (per-body IP and q-tilde)
+  barrier               sec. 4, Eq. barrier, Eq. clamped-b
+  CCD                   sec. 4.1 (linear trajectories, additive CCD)
+  culling               sec. 4.2 (box predicate; i-AABB is an exact filter)
+  assembly              sec. 4.3 (J^T H J into 12x12 body blocks)
+Readings where the paper is silent (IPC / ACCD conventions, distance case
+tie-breaks, mollifier, line search, convergence) are listed in the
+project's design notes and restated at each function.
+"""
+import ctypes
+import os
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_u8 = ctypes.POINTER(ctypes.c_uint8)
+_int = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        src = os.path.join(_HERE, "abd_oracle.cpp")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        L = ctypes.CDLL(path)
+        L.ora_mass.argtypes = [ctypes.c_int, _i32, _i32, _d, _d, _u8, _d, _d]
+        L.ora_vertex_map.argtypes = [ctypes.c_int, _d, _i32, _d, _d]
+        L.ora_candidates.argtypes = [ctypes.c_int] * 4 + [_i32] * 5 + [_u8, _i32, _d, _d, ctypes.c_double,
+                                                                       _i32, ctypes.c_int64, _i64, _i32,
+                                                                       ctypes.c_int64, _i64]
+        L.ora_candidates.restype = ctypes.c_int
+        L.ora_classify.argtypes = [ctypes.c_int64, ctypes.c_int, _i32, _i32, _i32, _d, ctypes.c_double, _u8, _d, _u8]
+        L.ora_barrier.argtypes = [ctypes.c_int64, ctypes.c_int, _i32, _i32, _i32, _i32, _u8, _d, _d,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, _d, _d, _d, _d, _i32,
+                                  ctypes.c_int64, _d, _d]
+        L.ora_barrier.restype = ctypes.c_int64
+        L.ora_barrier_energy.argtypes = [ctypes.c_int64, ctypes.c_int, _i32, _i32, _i32, _d, _d,
+                                         ctypes.c_double, ctypes.c_double, _int]
+        L.ora_barrier_energy.restype = ctypes.c_double
+        L.ora_ccd.argtypes = [ctypes.c_int64, ctypes.c_int, _i32, _i32, _i32, _d, _d, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_int, _d]
+        L.ora_orthogonality.argtypes = [ctypes.c_int, _u8, _d, _d, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int, _d, _d, _d]
+        L.ora_orthogonality_energy.argtypes = [ctypes.c_int, _u8, _d, _d, ctypes.c_double, ctypes.c_double]
+        L.ora_orthogonality_energy.restype = ctypes.c_double
+        L.ora_psd_project.argtypes = [ctypes.c_int, _d]
+        L.ora_pair_local.argtypes = [ctypes.c_int, _d, _d, ctypes.c_double, ctypes.c_double, _d, _d, _d]
+        L.ora_pair_local.restype = ctypes.c_int
+        L.ora_pair_distance.argtypes = [ctypes.c_int, _d, _int]
+        L.ora_pair_distance.restype = ctypes.c_double
+        _LIB = L
+    return _LIB
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class NotConverged(RuntimeError):
+    pass
+
+
+class LineSearchFailed(RuntimeError):
+    pass
+
+
+class Intersection(RuntimeError):
+    pass
+
+
+# ----------------------------------------------------------------- body ----
+
+def mass_properties(S):
+    """(mass[nb,10], volume[nb]): m, first moment (3), second moment
+    (xx,xy,xz,yy,yz,zz) per body by the divergence theorem."""
+    nb = len(S["body_fixed"])
+    mass = np.zeros((nb, 10))
+    vol = np.zeros(nb)
+    lib().ora_mass(nb, _p(_c(S["body_tri_off"], np.int32), _i32), _p(_c(S["tris"], np.int32), _i32),
+                   _p(_c(S["xbar"], np.float64), _d), _p(_c(S["density"], np.float64), _d),
+                   _p(_c(S["body_fixed"], np.uint8), _u8), _p(mass, _d), _p(vol, _d))
+    return mass, vol
+
+
+def mass_matrix(mass):
+    """Generalized mass matrix per body (Eq. mass), M = int rho J^T J with
+    J = [I_3 | I_3 (x) xbar^T] in q = (p, a1, a2, a3) order: M[p_i,p_j] = m
+    delta_ij, M[p_i, a_jn] = delta_ij h_n, M[a_im, a_jn] = delta_ij S_mn."""
+    nb = len(mass)
+    M = np.zeros((nb, 12, 12))
+    m, h = mass[:, 0], mass[:, 1:4]
+    Sm = np.zeros((nb, 3, 3))
+    iu = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    for k, (i, j) in enumerate(iu):
+        Sm[:, i, j] = mass[:, 4 + k]
+        Sm[:, j, i] = mass[:, 4 + k]
+    for i in range(3):
+        M[:, i, i] = m
+        for n in range(3):
+            M[:, i, 3 + 3 * i + n] = h[:, n]
+            M[:, 3 + 3 * i + n, i] = h[:, n]
+            for mm in range(3):
+                M[:, 3 + 3 * i + mm, 3 + 3 * i + n] = Sm[:, mm, n]
+    return M
+
+
+def vertex_map(S, q):
+    nv = len(S["xbar"])
+    x = np.empty((nv, 3))
+    lib().ora_vertex_map(nv, _p(_c(S["xbar"], np.float64), _d), _p(_c(S["vert_body"], np.int32), _i32),
+                         _p(_c(q, np.float64), _d), _p(x, _d))
+    return x
+
+
+# ---------------------------------------------------------- collisions ----
+
+def candidates(S, x0, x1=None, inflate=1e-3):
+    """Sorted PT (v,t) and EE (e_lo,e_hi) candidate pairs of the box
+    predicate over the swept boxes of x0 -> x1 inflated by `inflate`."""
+    L = lib()
+    nb = len(S["body_fixed"])
+    args = [nb, len(S["xbar"]), len(S["tris"]), len(S["edges"]),
+            _p(_c(S["body_vert_off"], np.int32), _i32), _p(_c(S["body_tri_off"], np.int32), _i32),
+            _p(_c(S["body_edge_off"], np.int32), _i32), _p(_c(S["tris"], np.int32), _i32),
+            _p(_c(S["edges"], np.int32), _i32), _p(_c(S["body_fixed"], np.uint8), _u8),
+            _p(_c(S["body_scene"], np.int32), _i32)]
+    x0 = _c(x0, np.float64)
+    x1 = x0 if x1 is None else _c(x1, np.float64)
+    cap_pt = cap_ee = 1 << 16
+    while True:
+        pt = np.empty((cap_pt, 2), np.int32)
+        ee = np.empty((cap_ee, 2), np.int32)
+        npt = ctypes.c_int64(0)
+        nee = ctypes.c_int64(0)
+        rc = L.ora_candidates(*args, _p(x0, _d), _p(x1, _d), float(inflate), _p(pt, _i32), cap_pt,
+                              ctypes.byref(npt), _p(ee, _i32), cap_ee, ctypes.byref(nee))
+        if rc == 0:
+            return pt[:npt.value].copy(), ee[:nee.value].copy()
+        cap_pt = max(cap_pt, npt.value)
+        cap_ee = max(cap_ee, nee.value)
+
+
+def classify(S, x, pairs, is_ee, dhat):
+    """Per pair: distance case code, squared distance, active flag."""
+    n = len(pairs)
+    ty = np.zeros(n, np.uint8)
+    d2 = np.zeros(n)
+    act = np.zeros(n, np.uint8)
+    if n:
+        lib().ora_classify(n, int(is_ee), _p(_c(pairs, np.int32), _i32), _p(_c(S["tris"], np.int32), _i32),
+                           _p(_c(S["edges"], np.int32), _i32), _p(_c(x, np.float64), _d), float(dhat),
+                           _p(ty, _u8), _p(d2, _d), _p(act, _u8))
+    return ty, d2, act
+
+
+def off_keys(S, pt, ee):
+    """Sorted unique body pairs (a<b, both free) touched by candidate pairs:
+    the off-diagonal block pattern of the global Hessian (sec. 4.3)."""
+    vb, tb, eb, fx = S["vert_body"], S["tri_body"], S["edge_body"], S["body_fixed"]
+    a = np.concatenate([vb[pt[:, 0]], eb[ee[:, 0]]]) if len(pt) + len(ee) else np.zeros(0, np.int64)
+    b = np.concatenate([tb[pt[:, 1]], eb[ee[:, 1]]]) if len(pt) + len(ee) else np.zeros(0, np.int64)
+    keep = (fx[a] == 0) & (fx[b] == 0)
+    lo = np.minimum(a, b)[keep].astype(np.int64)
+    hi = np.maximum(a, b)[keep].astype(np.int64)
+    k = np.unique(lo * (1 << 32) + hi)
+    return np.stack([k >> 32, k & 0xFFFFFFFF], axis=1).astype(np.int32) if len(k) else np.zeros((0, 2), np.int32)
+
+
+def barrier(S, x, pt, ee, params, keys, project=True, local=False):
+    """Barrier energy, body gradient [nb,12], diagonal blocks [nb,144],
+    off-diagonal blocks [len(keys),144] and active count."""
+    nb = len(S["body_fixed"])
+    e = np.zeros(1)
+    g = np.zeros((nb, 12))
+    D = np.zeros((nb, 144))
+    O = np.zeros((max(len(keys), 1), 144))
+    keys = _c(keys, np.int32)
+    out = {}
+    n_act = 0
+    for is_ee, pairs in ((0, pt), (1, ee)):
+        n = len(pairs)
+        lg = np.zeros((n, 12)) if local else None
+        lH = np.zeros((n, 144)) if local else None
+        if n:
+            r = lib().ora_barrier(n, is_ee, _p(_c(pairs, np.int32), _i32), _p(_c(S["vert_body"], np.int32), _i32),
+                                  _p(_c(S["tris"], np.int32), _i32), _p(_c(S["edges"], np.int32), _i32),
+                                  _p(_c(S["body_fixed"], np.uint8), _u8), _p(_c(S["xbar"], np.float64), _d),
+                                  _p(_c(x, np.float64), _d), float(params["dhat"]), float(params["kappa_b"]),
+                                  int(project), _p(e, _d), _p(g, _d), _p(D, _d), _p(O, _d), _p(keys, _i32),
+                                  len(keys), _p(lg, _d) if local else None, _p(lH, _d) if local else None)
+            if r == -3:
+                raise Intersection("pair at zero distance")
+            if r < 0:
+                raise RuntimeError("off-diagonal key missing")
+            n_act += r
+        if local:
+            out["ee" if is_ee else "pt"] = (lg, lH)
+    res = dict(energy=e[0], grad=g, diag=D, off=O[:len(keys)], n_active=n_act)
+    if local:
+        res["local"] = out
+    return res
+
+
+def barrier_energy(S, x, pt, ee, params):
+    tot = 0.0
+    st = ctypes.c_int(0)
+    for is_ee, pairs in ((0, pt), (1, ee)):
+        if len(pairs):
+            tot += lib().ora_barrier_energy(len(pairs), is_ee, _p(_c(pairs, np.int32), _i32),
+                                            _p(_c(S["tris"], np.int32), _i32), _p(_c(S["edges"], np.int32), _i32),
+                                            _p(_c(S["xbar"], np.float64), _d), _p(_c(x, np.float64), _d),
+                                            float(params["dhat"]), float(params["kappa_b"]), ctypes.byref(st))
+            if st.value:
+                return np.inf
+    return tot
+
+
+def ccd(S, x, dx, pt, ee, params):
+    """Per-pair additive-CCD safe fractions and alpha_max = min(1, min t)."""
+    out = []
+    for is_ee, pairs in ((0, pt), (1, ee)):
+        t = np.ones(len(pairs)) * params["ccd_tmax"]
+        if len(pairs):
+            lib().ora_ccd(len(pairs), is_ee, _p(_c(pairs, np.int32), _i32), _p(_c(S["tris"], np.int32), _i32),
+                          _p(_c(S["edges"], np.int32), _i32), _p(_c(x, np.float64), _d),
+                          _p(_c(dx, np.float64), _d), float(params["ccd_s"]), float(params["ccd_tmax"]),
+                          int(params["ccd_max_iter"]), _p(t, _d))
+        out.append(t)
+    alpha = min([1.0] + [float(t.min()) for t in out if len(t)])
+    return out[0], out[1], alpha
+
+
+# ------------------------------------------------------ body potentials ----
+
+def orthogonality(S, vol, q, params, project=True, w=None):
+    nb = len(S["body_fixed"])
+    w = params["dt"] ** 2 if w is None else w
+    e = np.zeros(1)
+    g = np.zeros((nb, 12))
+    D = np.zeros((nb, 144))
+    lib().ora_orthogonality(nb, _p(_c(S["body_fixed"], np.uint8), _u8), _p(_c(vol, np.float64), _d),
+                            _p(_c(q, np.float64), _d), float(params["kappa_o"]), float(w), int(project),
+                            _p(e, _d), _p(g, _d), _p(D, _d))
+    return e[0], g, D
+
+
+def orthogonality_energy(S, vol, q, params, w=None):
+    w = params["dt"] ** 2 if w is None else w
+    return lib().ora_orthogonality_energy(len(S["body_fixed"]), _p(_c(S["body_fixed"], np.uint8), _u8),
+                                          _p(_c(vol, np.float64), _d), _p(_c(q, np.float64), _d),
+                                          float(params["kappa_o"]), float(w))
+
+
+def inertia(S, M, q, qt):
+    """Incremental-potential inertia term 1/2 |q - q~|_M^2 (sec. 4),
+    gradient M (q - q~), Hessian M; fixed bodies excluded."""
+    free = S["body_fixed"] == 0
+    dq = (q - qt) * free[:, None]
+    Mq = np.einsum("bij,bj->bi", M, dq)
+    e = 0.5 * float(np.sum(dq * Mq))
+    D = (M * free[:, None, None]).reshape(-1, 144)
+    return e, Mq, D
+
+
+def q_tilde(S, q, qd, params):
+    """q~ = q + dt qdot + dt^2 M^-1 f.  Gravity f = int rho J^T g has
+    M^-1 f = (g, 0, 0, 0) exactly, whatever the mass distribution."""
+    dt = params["dt"]
+    qt = q + dt * qd
+    qt[:, :3] += dt * dt * np.asarray(params["gravity"])
+    fx = S["body_fixed"] != 0
+    qt[fx] = q[fx]
+    return qt
+
+
+# -------------------------------------------------------------- solver ----
+
+def assemble(S, diag, off, keys):
+    """Sparse symmetric matrix over the free DOFs from 12x12 blocks."""
+    nb = len(S["body_fixed"])
+    free = np.flatnonzero(S["body_fixed"] == 0)
+    pos = -np.ones(nb, np.int64)
+    pos[free] = np.arange(len(free))
+    rows, cols, vals = [], [], []
+    ii, jj = np.meshgrid(np.arange(12), np.arange(12), indexing="ij")
+    for b in free:
+        rows.append(12 * pos[b] + ii.ravel())
+        cols.append(12 * pos[b] + jj.ravel())
+        vals.append(diag[b])
+    for k, (a, b) in enumerate(keys):
+        if pos[a] < 0 or pos[b] < 0:
+            continue
+        rows.append(12 * pos[a] + ii.ravel())
+        cols.append(12 * pos[b] + jj.ravel())
+        vals.append(off[k])
+        rows.append(12 * pos[b] + jj.ravel())
+        cols.append(12 * pos[a] + ii.ravel())
+        vals.append(off[k])
+    n = 12 * len(free)
+    if not rows:
+        return sp.csr_matrix((n, n)), free
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).tocsc()
+    return A, free
+
+
+def solve(S, diag, off, keys, rhs):
+    """Direct sparse solve of H p = rhs over free DOFs (fixed: p = 0)."""
+    A, free = assemble(S, diag, off, keys)
+    p = np.zeros_like(rhs)
+    if len(free):
+        sol = spla.spsolve(A, rhs[free].reshape(-1))
+        p[free] = sol.reshape(-1, 12)
+    return p
+
+
+# -------------------------------------------------------------- Newton ----
+
+class Body:
+    """Per-scene constant data of the oracle: mass matrix and volumes."""
+
+    def __init__(self, S):
+        self.mass, self.vol = mass_properties(S)
+        self.M = mass_matrix(self.mass)
+
+
+def total_energy(S, B, q, qt, x, pt, ee, params):
+    e_in, _, _ = inertia(S, B.M, q, qt)
+    return e_in + orthogonality_energy(S, B.vol, q, params) + barrier_energy(S, x, pt, ee, params)
+
+
+def grad_hess(S, B, q, qt, params, x=None, pt=None, ee=None, project=True):
+    """Energy, gradient and (projected) Hessian blocks of the incremental
+    potential E = sum_b E_b + V_C at q."""
+    if x is None:
+        x = vertex_map(S, q)
+    if pt is None:
+        pt, ee = candidates(S, x, None, params["dhat"])
+    keys = off_keys(S, pt, ee)
+    e_in, g_in, D_in = inertia(S, B.M, q, qt)
+    e_o, g_o, D_o = orthogonality(S, B.vol, q, params, project=project)
+    bar = barrier(S, x, pt, ee, params, keys, project=project)
+    return dict(energy=e_in + e_o + bar["energy"], grad=g_in + g_o + bar["grad"],
+                diag=D_in + D_o + bar["diag"], off=bar["off"], keys=keys, pt=pt, ee=ee,
+                n_active=bar["n_active"])
+
+
+def newton_iteration(S, B, q, qt, params):
+    """One projected-Newton iteration with CCD-filtered backtracking line
+    search (IPC's scheme, which ABD builds on):
+      p = -H^-1 g;  converged if max_k |J_k p|_inf <= tol_v dt;
+      swept candidates over x(q) -> x(q+p); alpha = min(1, min_pairs t_ccd);
+      halve alpha until E(q + alpha p) <= E(q).
+    Returns (q_new, converged, info)."""
+    dt = params["dt"]
+    x = vertex_map(S, q)
+    gh = grad_hess(S, B, q, qt, params, x=x)
+    p = solve(S, gh["diag"], gh["off"], gh["keys"], -gh["grad"])
+    disp = np.abs(vertex_map(S, p)).max() if len(p) else 0.0
+    info = dict(n_pt=len(gh["pt"]), n_ee=len(gh["ee"]), n_active=gh["n_active"], disp=disp, p=p,
+                grad=gh["grad"], energy=gh["energy"])
+    if disp <= params["newton_tol"] * dt:
+        return q, True, info
+    x1 = vertex_map(S, q + p)
+    pts, ees = candidates(S, x, x1, params["dhat"])
+    tpt, tee, alpha = ccd(S, x, x1 - x, pts, ees, params)
+    e0 = total_energy(S, B, q, qt, x, pts, ees, params)
+    for _ in range(params["max_ls"]):
+        qa = q + alpha * p
+        ea = total_energy(S, B, qa, qt, vertex_map(S, qa), pts, ees, params)
+        if ea <= e0:
+            break
+        alpha *= 0.5
+    else:
+        raise LineSearchFailed("line search did not decrease the energy")
+    info.update(alpha=alpha, n_pt_swept=len(pts), n_ee_swept=len(ees), e0=e0, e1=ea)
+    return q + alpha * p, False, info
+
+
+def time_step(S, B, q, qd, params, log=None):
+    """Implicit-Euler time step: minimise the incremental potential starting
+    from q^t; qdot^{t+1} = (q^{t+1} - q^t) / dt."""
+    qt = q_tilde(S, q, qd, params)
+    qn = q.copy()
+    its = 0
+    for its in range(1, params["max_newton"] + 1):
+        qn, conv, info = newton_iteration(S, B, qn, qt, params)
+        if log is not None:
+            log.append(info)
+        if conv:
+            break
+    else:
+        raise NotConverged("Newton did not converge")
+    qdn = (qn - q) / params["dt"]
+    qdn[S["body_fixed"] != 0] = 0.0
+    return qn, qdn, its
+
+
+def pair_local(is_ee, X, xb, dhat, kappa):
+    """Local barrier energy/gradient/Hessian of one pair of explicit
+    vertices X[4,3] (rest positions xb[4,3] for the EE mollifier)."""
+    X = _c(X, np.float64).reshape(12)
+    xb = _c(xb, np.float64).reshape(12)
+    e = np.zeros(1)
+    g = np.zeros(12)
+    H = np.zeros(144)
+    ty = lib().ora_pair_local(int(is_ee), _p(X, _d), _p(xb, _d), float(dhat), float(kappa), _p(e, _d),
+                              _p(g, _d), _p(H, _d))
+    return ty, e[0], g, H.reshape(12, 12)
+
+
+def pair_distance(is_ee, X):
+    X = _c(X, np.float64).reshape(12)
+    ty = ctypes.c_int(0)
+    d = lib().ora_pair_distance(int(is_ee), _p(X, _d), ctypes.byref(ty))
+    return d, ty.value
+
+
+def psd_project(H):
+    H = _c(H, np.float64).copy()
+    n = H.shape[0]
+    lib().ora_psd_project(n, _p(H, _d))
+    return H

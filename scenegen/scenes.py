@@ -1,0 +1,322 @@
+"""Seeded synthetic scenes shaped like the paper's workloads.
+
+Every scene is a plain dict of numpy arrays (structure of arrays, body-major
+ranges) plus a parameter dict.  Both the CPU oracle and the GPU library
+consume exactly these arrays; nothing here evaluates the simulation method
+(no mass properties, distances, energies or derivatives).  Random numbers are
+drawn with ``numpy.random.default_rng(seed)`` in the order documented per
+builder.
+
+Arrays of a scene dict
+  xbar        f64 (nv,3)  body-frame vertex positions
+  vert_body   i32 (nv,)   owning body of each vertex
+  tris        i32 (nt,3)  global vertex ids, per body contiguous
+  tri_body    i32 (nt,)
+  edges       i32 (ne,2)  global vertex ids (i<j), per body contiguous
+  edge_body   i32 (ne,)
+  body_vert_off, body_tri_off, body_edge_off  i32 (nb+1,)
+  body_fixed  u8  (nb,)   1 = kinematically fixed (Dirichlet)
+  body_scene  i32 (nb,)   scene id (independent sub-scenes of a batch)
+  scene_body_off i32 (n_scenes+1,)
+  density     f64 (nb,)
+  q0, qd0     f64 (nb,12) affine DOFs (p, a1, a2, a3) with a_i the rows of A
+"""
+import math
+
+import numpy as np
+
+from . import meshes
+
+GRAVITY = (0.0, -9.8, 0.0)
+
+
+def _rot(axis, angle):
+    """Rotation matrix from unit axis and angle (Rodrigues' formula)."""
+    k = np.asarray(axis, dtype=np.float64)
+    kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + math.sin(angle) * kx + (1.0 - math.cos(angle)) * (kx @ kx)
+
+
+def random_rotation(rng, max_angle):
+    """Axis uniform on the sphere (normalised Gaussian), angle U[0,max]."""
+    axis = rng.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    angle = rng.uniform(0.0, max_angle)
+    return _rot(axis, angle)
+
+
+def q_from(R, p):
+    q = np.zeros(12)
+    q[:3] = p
+    q[3:] = np.asarray(R, dtype=np.float64).reshape(9)  # rows of A
+    return q
+
+
+class SceneBuilder:
+    """Accumulates bodies (mesh + initial affine state) into SoA arrays."""
+
+    def __init__(self):
+        self.bodies = []
+
+    def add(self, verts, tris, R=None, p=(0, 0, 0), fixed=False, density=1000.0,
+            qd=None, scene=0):
+        R = np.eye(3) if R is None else np.asarray(R, dtype=np.float64)
+        self.bodies.append(dict(v=np.asarray(verts, np.float64), t=np.asarray(tris, np.int32),
+                                q=q_from(R, p), qd=np.zeros(12) if qd is None else np.asarray(qd, np.float64),
+                                fixed=bool(fixed), density=float(density), scene=int(scene)))
+
+    def build(self):
+        xb, vb, tr, tb, ed, eb = [], [], [], [], [], []
+        voff, toff, eoff = [0], [0], [0]
+        q0, qd0, fixed, dens, bscene = [], [], [], [], []
+        nv = 0
+        for b, body in enumerate(self.bodies):
+            v, t = body["v"], body["t"]
+            e = meshes.edges_from_tris(t)
+            xb.append(v)
+            vb.append(np.full(len(v), b, np.int32))
+            tr.append(t + nv)
+            tb.append(np.full(len(t), b, np.int32))
+            ed.append(e + nv)
+            eb.append(np.full(len(e), b, np.int32))
+            nv += len(v)
+            voff.append(nv)
+            toff.append(toff[-1] + len(t))
+            eoff.append(eoff[-1] + len(e))
+            q0.append(body["q"])
+            qd0.append(body["qd"])
+            fixed.append(1 if body["fixed"] else 0)
+            dens.append(body["density"])
+            bscene.append(body["scene"])
+        bscene = np.array(bscene, np.int32)
+        if len(bscene) and np.any(np.diff(bscene) < 0):
+            raise ValueError("bodies must be grouped by scene")
+        n_scenes = int(bscene.max()) + 1 if len(bscene) else 0
+        soff = np.searchsorted(bscene, np.arange(n_scenes + 1)).astype(np.int32)
+        return dict(
+            xbar=np.ascontiguousarray(np.concatenate(xb)),
+            vert_body=np.concatenate(vb),
+            tris=np.ascontiguousarray(np.concatenate(tr).astype(np.int32)),
+            tri_body=np.concatenate(tb),
+            edges=np.ascontiguousarray(np.concatenate(ed).astype(np.int32)),
+            edge_body=np.concatenate(eb),
+            body_vert_off=np.array(voff, np.int32),
+            body_tri_off=np.array(toff, np.int32),
+            body_edge_off=np.array(eoff, np.int32),
+            body_fixed=np.array(fixed, np.uint8),
+            body_scene=bscene,
+            scene_body_off=soff,
+            density=np.array(dens, np.float64),
+            q0=np.ascontiguousarray(np.array(q0, np.float64)),
+            qd0=np.ascontiguousarray(np.array(qd0, np.float64)),
+        )
+
+
+def default_params(**kw):
+    """Method parameters.  kappa_b is the barrier stiffness (fixed per
+    scene), kappa_o the orthogonality stiffness (multiplied by body volume),
+    ccd_s / ccd_tmax / ccd_max_iter the additive-CCD constants."""
+    p = dict(dt=1e-2, dhat=1e-3, kappa_b=80.0, kappa_o=1e8, mu=0.0, eps_v=1e-3,
+             gravity=GRAVITY, newton_tol=1e-5, pcg_rtol=1e-10, ccd_s=0.1,
+             ccd_tmax=1.0, ccd_max_iter=10000, max_newton=100, max_pcg=5000,
+             max_ls=40, steps=100)
+    p.update(kw)
+    return p
+
+
+# --------------------------------------------------------------------------
+# Configurations
+# --------------------------------------------------------------------------
+
+def three_cubes(seed=1):
+    """3 unit cubes stacked along y with 1e-2 m AABB gaps; bottom fixed and
+    axis aligned, the two above rotated (axis uniform, angle U[0,0.3]).
+    Draw order: rotation of cube 1, rotation of cube 2."""
+    rng = np.random.default_rng(seed)
+    v, t = meshes.cube(0.5)
+    sb = SceneBuilder()
+    sb.add(v, t, p=(0.0, 0.0, 0.0), fixed=True)
+    top = 0.5
+    for _ in range(2):
+        R = random_rotation(rng, 0.3)
+        w = v @ R.T
+        lo, hi = w[:, 1].min(), w[:, 1].max()
+        y = top + 1e-2 - lo
+        sb.add(v, t, R=R, p=(0.0, y, 0.0))
+        top = y + hi
+    scene = sb.build()
+    # barrier stiffness: a 1000 kg cube resting on one contact sits at dhat/10
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=80.0, mu=0.0, steps=100)
+    return scene, params
+
+
+def icosphere_box(seed=2, n_side=10, n_layers=10, spacing=0.25, friction=0.5):
+    """Icospheres (subdivision 2) of radius U[0.05,0.1] with random rotations
+    on a jittered n_side x n_layers x n_side grid inside a fixed open box of
+    12 quads (inner 2.6 m, height 2.6 m).  Draw order per body (grid order
+    layer-major, then x, then z): radius, rotation axis (3), angle,
+    jitter (3)."""
+    rng = np.random.default_rng(seed)
+    sv, st = meshes.icosphere(2, 1.0)
+    bv, bt = meshes.open_box(2.6, 2.6)
+    sb = SceneBuilder()
+    sb.add(bv, bt, fixed=True)
+    x0 = -spacing * (n_side - 1) / 2.0
+    for j in range(n_layers):
+        for i in range(n_side):
+            for k in range(n_side):
+                r = rng.uniform(0.05, 0.1)
+                R = random_rotation(rng, math.pi)
+                jit = rng.uniform(-0.02, 0.02, size=3)
+                p = np.array([x0 + spacing * i, 0.3 + spacing * j, x0 + spacing * k]) + jit
+                sb.add(sv * r, st, R=R, p=p)
+    scene = sb.build()
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=0.33, mu=friction, steps=200)
+    return scene, params
+
+
+def torus_chains(seed=3, n_chains=8, n_links=8, n_major=200, n_minor=50,
+                 sigma=1e-3, gap=2e-3):
+    """n_chains parallel chains of n_links interlocked tori (major 0.3,
+    minor 0.1), alternating flat (ring in x-z) and upright (ring in x-y)
+    links; noiseless tube gaps `gap` both along and across chains.  Vertices
+    are pushed inward along the tube normal by |N(0,sigma)|, so gaps only
+    grow.  End links fixed; the others get velocity N(0,0.5^2) per
+    translation component.  Draw order: per body (chain-major) the noise of
+    all vertices, then for free bodies the 3 velocity components."""
+    rng = np.random.default_rng(seed)
+    Rm, rm = 0.3, 0.1
+    v0, t0 = meshes.torus(Rm, rm, n_major, n_minor)
+    uu = np.repeat(2 * np.pi * np.arange(n_major) / n_major, n_minor)
+    ww = np.tile(2 * np.pi * np.arange(n_minor) / n_minor, n_major)
+    nrm = np.stack([np.cos(ww) * np.cos(uu), np.sin(ww), np.cos(ww) * np.sin(uu)], -1)
+    pitch = 2 * Rm - 2 * rm - gap
+    wpitch = 2 * (Rm + rm) + gap
+    upright = _rot((1.0, 0.0, 0.0), math.pi / 2)
+    sb = SceneBuilder()
+    for c in range(n_chains):
+        for l in range(n_links):
+            noise = np.abs(rng.normal(0.0, sigma, size=len(v0)))
+            v = v0 - noise[:, None] * nrm
+            fixed = l == 0 or l == n_links - 1
+            qd = np.zeros(12)
+            if not fixed:
+                qd[:3] = rng.normal(0.0, 0.5, size=3)
+            R = np.eye(3) if l % 2 == 0 else upright
+            p = (pitch * (l - (n_links - 1) / 2.0), 1.0, wpitch * (c - (n_chains - 1) / 2.0))
+            sb.add(v, t0, R=R, p=p, fixed=fixed, qd=qd)
+    scene = sb.build()
+    params = default_params(dt=5e-3, dhat=5e-4, kappa_b=2.4, mu=0.0, steps=100)
+    return scene, params
+
+
+def batched_drops(seed=4, n_scenes=256, n_min=2, n_max=200):
+    """n_scenes independent scenes; scene k holds n_k ~ U{n_min..n_max}
+    bodies, each a cube (half-edge r/sqrt(3)) or an icosphere, 50/50, with
+    r ~ U[0.05,0.1], random rotation, on 10x10 layers at spacing 0.25 with
+    jitter U[-0.02,0.02]^3, above one fixed 3x3 m ground quad.  Draw order:
+    all n_k first, then per scene per body: shape coin, radius, rotation
+    axis (3), angle, jitter (3)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_min, n_max + 1, size=n_scenes)
+    sv, st = meshes.icosphere(2, 1.0)
+    cv, ct = meshes.cube(0.5)
+    gv, gt = meshes.ground_quad(3.0)
+    sb = SceneBuilder()
+    x0 = -0.25 * 4.5
+    for s in range(n_scenes):
+        sb.add(gv, gt, fixed=True, scene=s)
+        for b in range(int(ns[s])):
+            is_cube = rng.uniform() < 0.5
+            r = rng.uniform(0.05, 0.1)
+            R = random_rotation(rng, math.pi)
+            jit = rng.uniform(-0.02, 0.02, size=3)
+            layer, rem = divmod(b, 100)
+            i, k = divmod(rem, 10)
+            p = np.array([x0 + 0.25 * i, 0.3 + 0.25 * layer, x0 + 0.25 * k]) + jit
+            if is_cube:
+                sb.add(cv * (2.0 * r / math.sqrt(3.0)), ct, R=R, p=p, scene=s)
+            else:
+                sb.add(sv * r, st, R=R, p=p, scene=s)
+    scene = sb.build()
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=0.33, mu=0.0, steps=100)
+    return scene, params
+
+
+def adjoint_drop(seed=5):
+    """500 icospheres as the box drop (10x5x10), friction 0.5, plus a target
+    point U(box interior, y in [0.1,0.5]).  Draw order: the scene as in
+    icosphere_box with this seed, then the target (x, y, z)."""
+    scene, params = icosphere_box(seed=seed, n_side=10, n_layers=5, friction=0.5)
+    rng = np.random.default_rng(seed + 1000)
+    target = np.array([rng.uniform(-1.2, 1.2), rng.uniform(0.1, 0.5), rng.uniform(-1.2, 1.2)])
+    params = dict(params, steps=100, checkpoint_every=10)
+    return scene, params, target
+
+
+CONFIGS = {
+    "three_cubes": three_cubes,
+    "icosphere_box": icosphere_box,
+    "torus_chains": torus_chains,
+    "batched_drops": batched_drops,
+}
+
+
+# --------------------------------------------------------------------------
+# Small scenes for parity tests
+# --------------------------------------------------------------------------
+
+def near_contact_cubes(seed, n=6, gap_range=(1e-4, 6e-4), tilt=3e-4):
+    """n unit-ish cubes in a vertical stack, face gaps drawn in gap_range,
+    small tilts and spins so that vertex-face, edge-edge and degenerate
+    configurations all occur within dhat=1e-3.  Bottom cube fixed.  Draw
+    order per cube above the first: gap, spin angle about y, tilt axis
+    (3), tilt angle, horizontal offset (2)."""
+    rng = np.random.default_rng(seed)
+    v, t = meshes.cube(0.5)
+    sb = SceneBuilder()
+    sb.add(v, t, fixed=True)
+    top = 0.5
+    for _ in range(n - 1):
+        g = rng.uniform(*gap_range)
+        spin = _rot((0.0, 1.0, 0.0), rng.uniform(0, 2 * math.pi))
+        R = random_rotation(rng, tilt) @ spin
+        off = rng.uniform(-0.3, 0.3, size=2)
+        w = v @ R.T
+        y = top + g - w[:, 1].min()
+        sb.add(v, t, R=R, p=(off[0], y, off[1]))
+        top = y + w[:, 1].max()
+    return sb.build()
+
+
+def triangle_soup(seed, n_bodies=24, extent=0.02, tri_size=0.01):
+    """Free single-triangle bodies (3 vertices, 1 triangle, 3 edges) with
+    random vertices in a small box, so that every point-triangle and
+    edge-edge distance case is exercised at distances around dhat=1e-3.
+    Bodies are placed on a line with random jitter.  Draw order per body:
+    3 vertices (9 uniforms), body offset (3)."""
+    rng = np.random.default_rng(seed)
+    sb = SceneBuilder()
+    for b in range(n_bodies):
+        v = rng.uniform(-tri_size, tri_size, size=(3, 3))
+        off = rng.uniform(-extent, extent, size=3)
+        sb.add(v, np.array([[0, 1, 2]], np.int32), p=off)
+    return sb.build()
+
+
+def random_state(scene, seed, rot_angle=0.0, stretch=0.0, shift=0.0):
+    """Perturb q0 of the free bodies: A <- (I + stretch*G) R A with R a random
+    rotation of angle <= rot_angle, G Gaussian; p <- p + shift*N(0,1).
+    Draw order per free body: rotation (4), G (9), shift (3)."""
+    rng = np.random.default_rng(seed)
+    q = scene["q0"].copy()
+    for b in range(len(q)):
+        if scene["body_fixed"][b]:
+            continue
+        R = random_rotation(rng, rot_angle)
+        G = rng.normal(size=(3, 3))
+        A = q[b, 3:].reshape(3, 3)
+        A = (np.eye(3) + stretch * G) @ R @ A
+        q[b, 3:] = A.reshape(9)
+        q[b, :3] += shift * rng.normal(size=3)
+    return q

@@ -1,0 +1,227 @@
+/*
+ * abd.h - C ABI of the MI355X (gfx950) affine-body-dynamics contact path.
+ *
+ * Method: Lan, Kaufman, Li, Jiang, Yang, "Affine Body Dynamics: Fast, Stable
+ * and Intersection-free Simulation of Stiff Materials" (ABD).  Every stiff
+ * body carries 12 affine DOFs q = (p, a1, a2, a3) with a_i the rows of A
+ * (sec. 3); its surface vertices move as x = A xbar + p (Eq. kinematic).
+ * One Newton iteration of the incremental potential (sec. 4) evaluates the
+ * orthogonality potential (Eq. orthogonality), the clamped log barrier on
+ * point-triangle (PT) and edge-edge (EE) pairs of different bodies
+ * (Eq. barrier, Eq. clamped-b), culled by box overlap (sec. 4.2), assembles
+ * J^T H J into 12x12 body blocks (sec. 4.3), solves, and limits the step by
+ * linear CCD (sec. 4.1).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers (caller-owned, contiguous, row-major
+ *    as documented) unless marked "host".  The library never frees them.
+ *  - Calls are enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and return after enqueueing, except calls documented as "syncs": those
+ *    need a count or scalar on the host and synchronise `stream` first.
+ *  - "accumulated" outputs are added to (callers zero them first).
+ *  - Return value: ABD_OK or a negative ABD_E_* code; abd_last_error gives
+ *    the message.  No exception crosses the ABI.  One context per host
+ *    thread; calls on one context are not thread-safe.
+ *  - The library allocates only its own workspace (inside the context,
+ *    grown on demand, released by abd_destroy).
+ */
+#ifndef ABD_H
+#define ABD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ABD_OK = 0,
+  ABD_E_INVALID = -1,        /* null pointer, bad size, bad index, non-finite input */
+  ABD_E_CAPACITY = -2,       /* output capacity too small; required count returned */
+  ABD_E_INTERSECT = -3,      /* a pair at zero distance (intersecting input) */
+  ABD_E_NOT_CONVERGED = -4,  /* Newton iteration cap reached */
+  ABD_E_LINESEARCH = -5,     /* no energy decrease after max_ls halvings */
+  ABD_E_PCG = -6,            /* PCG breakdown (non-positive curvature) or cap */
+  ABD_E_HIP = -7             /* HIP runtime error */
+};
+
+/* Distance case codes written by abd_classify (vertex slots: PT pair =
+ * (p, t0, t1, t2), EE pair = (a0, a1, b0, b1)).
+ *   PT: 0,1,2 point-point with t0,t1,t2; 3 point-edge (t0,t1);
+ *       4 point-edge (t1,t2); 5 point-edge (t0,t2); 6 point-face.
+ *   EE: 16 + 3k + c for the endpoint-vs-segment side k (0: a0 vs b,
+ *       1: a1 vs b, 2: b0 vs a, 3: b1 vs a) with c = 0/1 the segment's
+ *       first/second endpoint, c = 2 its interior; 28 line-line.      */
+
+typedef struct abd_ctx abd_ctx;
+
+/* Scene geometry (device arrays; counts are host values).  Bodies are
+ * contiguous ranges of vertices, triangles and edges.  Vertex, triangle and
+ * edge indices are global.  Sub-scenes (batched mode) are contiguous body
+ * ranges; pairs never cross sub-scenes. */
+typedef struct abd_scene {
+  int32_t n_bodies, n_verts, n_tris, n_edges, n_scenes;
+  const double *xbar;           /* [n_verts][3] body-frame rest positions */
+  const int32_t *vert_body;     /* [n_verts] */
+  const int32_t *tris;          /* [n_tris][3] */
+  const int32_t *tri_body;      /* [n_tris] */
+  const int32_t *edges;         /* [n_edges][2], first < second */
+  const int32_t *edge_body;     /* [n_edges] */
+  const int32_t *body_vert_off; /* [n_bodies+1] */
+  const int32_t *body_tri_off;  /* [n_bodies+1] */
+  const int32_t *body_edge_off; /* [n_bodies+1] */
+  const uint8_t *body_fixed;    /* [n_bodies], 1 = Dirichlet (never moves) */
+  const int32_t *body_scene;    /* [n_bodies] sub-scene id, non-decreasing */
+  const double *mass;           /* [n_bodies][10] from abd_body_mass (may be NULL
+                                   for calls that do not use it) */
+  const double *volume;         /* [n_bodies] from abd_body_mass */
+} abd_scene;
+
+/* Method parameters (host struct). */
+typedef struct abd_params {
+  double dt;          /* time step */
+  double dhat;        /* barrier activation distance (Eq. clamped-b) */
+  double kappa_b;     /* barrier stiffness (Eq. barrier) */
+  double kappa_o;     /* orthogonality stiffness, times body volume (Eq. orthogonality) */
+  double mu, eps_v;   /* friction coefficient and static-velocity threshold */
+  double gravity[3];
+  double newton_tol;  /* converged when max_k |J_k p|_inf <= newton_tol * dt */
+  double pcg_rtol;    /* PCG stop: |r| <= pcg_rtol |b| */
+  double ccd_s;       /* ACCD gap fraction s */
+  double ccd_tmax;    /* ACCD maximal step fraction */
+  int32_t ccd_max_iter, max_newton, max_pcg, max_ls;
+} abd_params;
+
+/* Per-iteration statistics (host struct). */
+typedef struct abd_stats {
+  int64_t n_pt, n_ee;             /* candidates at the current iterate */
+  int64_t n_active_pt, n_active_ee;
+  int64_t n_pt_swept, n_ee_swept; /* candidates over the step's sweep */
+  int64_t n_offdiag;              /* off-diagonal blocks of the system */
+  int32_t pcg_iters, ls_halvings, converged, newton_iters;
+  double alpha_ccd, alpha;        /* CCD bound and accepted step */
+  double disp;                    /* max_k |J_k p|_inf of the Newton direction */
+  double energy0, energy1;        /* E(q), E(q + alpha p) */
+  double t_barrier_ms, t_ccd_ms, t_candidates_ms, t_solve_ms, t_total_ms;
+} abd_stats;
+
+int abd_create(abd_ctx **ctx, int device);
+int abd_destroy(abd_ctx *ctx);
+const char *abd_last_error(const abd_ctx *ctx);
+
+/* Mass properties (sec. 3.1, Eq. mass: M = int rho J^T J).  For every free
+ * body: mass[b] = (m, h_x, h_y, h_z, S_xx, S_xy, S_xz, S_yy, S_yz, S_zz) with
+ * m = int rho, h = int rho xbar, S = int rho xbar xbar^T over the closed,
+ * outward-oriented surface (divergence theorem), and volume[b]; zeros for
+ * fixed bodies.  density: [n_bodies]. */
+int abd_body_mass(abd_ctx *ctx, const abd_scene *sc, const double *density, double *mass, double *volume,
+                  hipStream_t stream);
+
+/* Kinematic map (sec. 3, Eq. kinematic): x_k = A_b xbar_k + p_b for every
+ * vertex, component i evaluated as p_i + ((a_i0 xbar_0 + a_i1 xbar_1) +
+ * a_i2 xbar_2) without fused multiply-add, so results are bit-reproducible.
+ * q: [n_bodies][12]; x: [n_verts][3]. */
+int abd_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t stream);
+
+/* Candidate pairs (sec. 4.2).  A primitive's box spans its vertices at x0
+ * and x1 (x1 = NULL: x0 only); a pair is a candidate iff the primitives lie
+ * on different bodies of one sub-scene, not both fixed, and on every axis
+ * lo_a <= hi_b + inflate and lo_b <= hi_a + inflate.  Whole-body boxes and
+ * their pairwise intersections (i-AABBs) cull exactly for this predicate.
+ * Output: pt [cap_pt][2] = (vertex, triangle) of either body against the
+ * other; ee [cap_ee][2] = (edge_lo, edge_hi).  Order: grouped by body pair
+ * (min body, max body) ascending; inside a group PT pairs by (vertex,
+ * triangle) and EE pairs by (edge_lo, edge_hi) ascending.  Syncs; *n_pt and
+ * *n_ee (host) receive the counts; ABD_E_CAPACITY if either exceeds its
+ * capacity (outputs then undefined, counts valid). */
+int abd_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1, double inflate,
+                   int32_t *pt, int64_t cap_pt, int64_t *n_pt, int32_t *ee, int64_t cap_ee, int64_t *n_ee,
+                   hipStream_t stream);
+
+/* Off-diagonal block pattern of the global Hessian (sec. 4.3): sorted unique
+ * body pairs (a < b, both free) touched by the given pairs.  keys:
+ * [cap][2].  Syncs; *n_keys (host) receives the count. */
+int abd_offdiag_pattern(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee,
+                        int64_t n_ee, int32_t *keys, int64_t cap, int64_t *n_keys, hipStream_t stream);
+
+/* Narrow phase (sec. 4, distances of Eq. barrier): per pair the distance
+ * case (codes above), the squared distance num/den of that case, and
+ * active = (num < dhat^2 den), i.e. d < dhat decided without division.
+ * is_ee selects the pair kind.  Outputs [n]; any may be NULL. */
+int abd_classify(abd_ctx *ctx, const abd_scene *sc, const double *x, double dhat, const int32_t *pairs, int64_t n,
+                 int is_ee, uint8_t *type, double *d2, uint8_t *active, hipStream_t stream);
+
+/* Barrier term (Eq. barrier, Eq. clamped-b; EE pairs mollified by
+ * m(c) = (2 - c/eps) c/eps, c = |(a1-a0)x(b1-b0)|^2, eps = 1e-3 |abar|^2
+ * |bbar|^2): energy kappa_b sum m B(d); per active pair the local 12x12
+ * Hessian, PSD-projected when project_psd != 0; J^T g and J^T H J reduced
+ * into grad [n_bodies][12], diag [n_bodies][144] and off [n_keys][144]
+ * (block (a,b) of keys[k] = (a,b), row-major 12x12, rows = DOFs of a).
+ * energy [1], grad, diag, off are accumulated; diag/off may be NULL
+ * (gradient only).  Contributions to fixed bodies are dropped.  Any pair
+ * order is accepted.  ABD_E_INTERSECT is raised asynchronously: it is
+ * reported by the next syncing call. */
+int abd_barrier_grad_hess(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
+                          const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, const int32_t *keys,
+                          int64_t n_keys, double *energy, double *grad, double *diag, double *off, int project_psd,
+                          hipStream_t stream);
+
+/* Barrier energy only (line search): accumulates kappa_b sum m B(d) into
+ * energy [1]; +inf when a pair is at zero distance. */
+int abd_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
+                       int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy, hipStream_t stream);
+
+/* CCD step bound (sec. 4.1: linear trajectories x0 + t dx, additive CCD):
+ * per pair a conservative safe fraction t in [0, ccd_tmax] (t_pt [n_pt],
+ * t_ee [n_ee], either may be NULL) and alpha [n_scenes] = min(1, min t)
+ * over each sub-scene's pairs. */
+int abd_ccd_max_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x0, const double *dx,
+                     const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *t_pt, double *t_ee,
+                     double *alpha, hipStream_t stream);
+
+/* Orthogonality potential (Eq. orthogonality / ortho-energy / ortho-poly)
+ * scaled by `weight` (dt^2 inside the incremental potential): energy [1],
+ * grad [n_bodies][12], diag [n_bodies][144] accumulated; the 9x9 A-block of
+ * the Hessian PSD-projected when project_psd != 0.  Fixed bodies skipped. */
+int abd_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,
+                      double *energy, double *grad, double *diag, int project_psd, hipStream_t stream);
+
+/* Inertia term of the incremental potential (sec. 4): energy 1/2 |q - q~|_M^2,
+ * gradient M (q - q~), Hessian M, accumulated; fixed bodies skipped. */
+int abd_inertia(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *q_tilde, double *energy,
+                double *grad, double *diag, hipStream_t stream);
+
+/* q~ = q + dt qdot + dt^2 M^-1 f with gravity (M^-1 f = (g, 0, 0, 0));
+ * fixed bodies: q~ = q. */
+int abd_q_tilde(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qdot,
+                double *q_tilde, hipStream_t stream);
+
+/* Block-Jacobi preconditioned CG on the symmetric block matrix (diag +
+ * off/off^T) restricted to free bodies: solves H p = rhs, p = 0 on fixed
+ * bodies.  Syncs; *iters (host) receives the iteration count. */
+int abd_pcg_solve(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
+                  int64_t n_keys, const double *rhs, double *p, double rtol, int32_t max_iter, int32_t *iters,
+                  hipStream_t stream);
+
+/* One projected-Newton iteration on q (in/out) towards the minimiser of
+ * the incremental potential with target q_tilde: direction p = -H^-1 g;
+ * if max_k |J_k p|_inf <= newton_tol dt, sets stats->converged and leaves q;
+ * else the CCD bound over the swept candidates of x(q) -> x(q+p) starts a
+ * backtracking search halving alpha until E(q + alpha p) <= E(q).
+ * Syncs.  stats (host) may be NULL. */
+int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, const double *q_tilde,
+                    abd_stats *stats, hipStream_t stream);
+
+/* One implicit-Euler time step: q~ from (q, qdot), Newton iterations until
+ * converged (ABD_E_NOT_CONVERGED after max_newton), then
+ * qdot = (q_new - q_old) / dt.  q, qdot [n_bodies][12] in/out.  Syncs.
+ * stats (host, may be NULL) receives totals of the step. */
+int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot,
+                  abd_stats *stats, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABD_H */

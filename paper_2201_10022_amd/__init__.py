@@ -1,0 +1,250 @@
+"""MI355X (gfx950) affine-body-dynamics contact path.
+
+Python binding of the C ABI in include/abd.h.  Functions keep the ABI's
+names (without the ``abd_`` prefix on methods of ``Context``) and only
+marshal arguments: torch tensors provide device memory and the current HIP
+stream, every computation runs in libabd.so.  There is no CPU fallback: if
+the library or a GPU is missing, calls raise.
+
+Method: Lan et al., Affine Body Dynamics (sec. 3 kinematics and mass,
+sec. 3.2 orthogonality, sec. 4 incremental potential and barrier, sec. 4.1
+CCD, sec. 4.2 culling, sec. 4.3 assembly).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import AbdParams, AbdScene, AbdStats  # noqa: F401
+
+
+class AbdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_params(p):
+    """abd_params from a parameter dict (see scenegen.default_params)."""
+    out = AbdParams()
+    for k in ("dt", "dhat", "kappa_b", "kappa_o", "mu", "eps_v", "newton_tol", "pcg_rtol", "ccd_s", "ccd_tmax"):
+        setattr(out, k, float(p[k]))
+    for i in range(3):
+        out.gravity[i] = float(p["gravity"][i])
+    for k in ("ccd_max_iter", "max_newton", "max_pcg", "max_ls"):
+        setattr(out, k, int(p[k]))
+    return out
+
+
+class Scene:
+    """Device copy of a scene dict (numpy arrays as produced by scenegen)."""
+
+    def __init__(self, S, device="cuda:0"):
+        dev = torch.device(device)
+
+        def t(a, dt):
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+
+        self.device = dev
+        self.xbar = t(S["xbar"], torch.float64)
+        self.vert_body = t(S["vert_body"], torch.int32)
+        self.tris = t(S["tris"], torch.int32)
+        self.tri_body = t(S["tri_body"], torch.int32)
+        self.edges = t(S["edges"], torch.int32)
+        self.edge_body = t(S["edge_body"], torch.int32)
+        self.body_vert_off = t(S["body_vert_off"], torch.int32)
+        self.body_tri_off = t(S["body_tri_off"], torch.int32)
+        self.body_edge_off = t(S["body_edge_off"], torch.int32)
+        self.body_fixed = t(S["body_fixed"], torch.uint8)
+        self.body_scene = t(S["body_scene"], torch.int32)
+        self.density = t(S["density"], torch.float64)
+        self.n_bodies = len(S["body_fixed"])
+        self.n_scenes = int(S["body_scene"].max()) + 1 if self.n_bodies else 0
+        self.mass = torch.zeros((self.n_bodies, 10), dtype=torch.float64, device=dev)
+        self.volume = torch.zeros(self.n_bodies, dtype=torch.float64, device=dev)
+        self.c = self._struct()
+
+    def _struct(self):
+        s = AbdScene()
+        s.n_bodies = self.n_bodies
+        s.n_verts = self.xbar.shape[0]
+        s.n_tris = self.tris.shape[0]
+        s.n_edges = self.edges.shape[0]
+        s.n_scenes = self.n_scenes
+        for name in ("xbar", "vert_body", "tris", "tri_body", "edges", "edge_body", "body_vert_off", "body_tri_off",
+                     "body_edge_off", "body_fixed", "body_scene", "mass", "volume"):
+            setattr(s, name, getattr(self, name).data_ptr())
+        return s
+
+
+class Context:
+    """An abd_ctx on one device; methods mirror the C ABI calls."""
+
+    def __init__(self, device=0):
+        self.L = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the ABD library has no CPU path")
+        self.device = device
+        torch.cuda.set_device(device)
+        h = ctypes.c_void_p()
+        self._check(self.L.abd_create(ctypes.byref(h), int(device)), ctx=None)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.abd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, ctx="self"):
+        if rc != 0:
+            msg = self.L.abd_last_error(self.h if ctx else None)
+            raise AbdError(rc, msg.decode() if msg else "")
+
+    # -- setup ---------------------------------------------------------
+    def body_mass(self, scene):
+        self._check(self.L.abd_body_mass(self.h, ctypes.byref(scene.c), _ptr(scene.density), _ptr(scene.mass),
+                                         _ptr(scene.volume), _stream()))
+        return scene.mass, scene.volume
+
+    # -- hot path ------------------------------------------------------
+    def vertex_map(self, scene, q, x=None):
+        x = torch.empty((scene.c.n_verts, 3), dtype=torch.float64, device=q.device) if x is None else x
+        self._check(self.L.abd_vertex_map(self.h, ctypes.byref(scene.c), _ptr(q), _ptr(x), _stream()))
+        return x
+
+    def candidates(self, scene, x0, x1=None, inflate=1e-3, cap_pt=1 << 20, cap_ee=1 << 20):
+        while True:
+            pt = torch.empty((max(cap_pt, 1), 2), dtype=torch.int32, device=x0.device)
+            ee = torch.empty((max(cap_ee, 1), 2), dtype=torch.int32, device=x0.device)
+            npt, nee = ctypes.c_int64(0), ctypes.c_int64(0)
+            rc = self.L.abd_candidates(self.h, ctypes.byref(scene.c), _ptr(x0), _ptr(x1), float(inflate), _ptr(pt),
+                                       cap_pt, ctypes.byref(npt), _ptr(ee), cap_ee, ctypes.byref(nee), _stream())
+            if rc == -2:
+                cap_pt, cap_ee = max(cap_pt, npt.value), max(cap_ee, nee.value)
+                continue
+            self._check(rc)
+            return pt[:npt.value], ee[:nee.value]
+
+    def offdiag_pattern(self, scene, pt, ee):
+        cap = pt.shape[0] + ee.shape[0] + 1
+        keys = torch.empty((cap, 2), dtype=torch.int32, device=pt.device)
+        n = ctypes.c_int64(0)
+        self._check(self.L.abd_offdiag_pattern(self.h, ctypes.byref(scene.c), _ptr(pt), pt.shape[0], _ptr(ee),
+                                               ee.shape[0], _ptr(keys), cap, ctypes.byref(n), _stream()))
+        return keys[:n.value]
+
+    def classify(self, scene, x, pairs, is_ee, dhat):
+        n = pairs.shape[0]
+        ty = torch.zeros(n, dtype=torch.uint8, device=x.device)
+        d2 = torch.zeros(n, dtype=torch.float64, device=x.device)
+        act = torch.zeros(n, dtype=torch.uint8, device=x.device)
+        self._check(self.L.abd_classify(self.h, ctypes.byref(scene.c), _ptr(x), float(dhat), _ptr(pairs), n,
+                                        int(is_ee), _ptr(ty), _ptr(d2), _ptr(act), _stream()))
+        return ty, d2, act
+
+    def barrier_grad_hess(self, scene, params, x, pt, ee, keys, project=True, hessian=True):
+        nb = scene.n_bodies
+        dev = x.device
+        energy = torch.zeros(1, dtype=torch.float64, device=dev)
+        grad = torch.zeros((nb, 12), dtype=torch.float64, device=dev)
+        diag = torch.zeros((nb, 144), dtype=torch.float64, device=dev) if hessian else None
+        off = torch.zeros((max(keys.shape[0], 1), 144), dtype=torch.float64, device=dev) if hessian else None
+        prm = make_params(params)
+        self._check(self.L.abd_barrier_grad_hess(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(x),
+                                                 _ptr(pt), pt.shape[0], _ptr(ee), ee.shape[0], _ptr(keys),
+                                                 keys.shape[0], _ptr(energy), _ptr(grad), _ptr(diag), _ptr(off),
+                                                 int(project), _stream()))
+        return energy, grad, diag, (off[:keys.shape[0]] if hessian else None)
+
+    def barrier_energy(self, scene, params, x, pt, ee):
+        energy = torch.zeros(1, dtype=torch.float64, device=x.device)
+        prm = make_params(params)
+        self._check(self.L.abd_barrier_energy(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(x), _ptr(pt),
+                                              pt.shape[0], _ptr(ee), ee.shape[0], _ptr(energy), _stream()))
+        return energy
+
+    def ccd_max_step(self, scene, params, x0, dx, pt, ee):
+        dev = x0.device
+        t_pt = torch.zeros(pt.shape[0], dtype=torch.float64, device=dev)
+        t_ee = torch.zeros(ee.shape[0], dtype=torch.float64, device=dev)
+        alpha = torch.zeros(max(scene.n_scenes, 1), dtype=torch.float64, device=dev)
+        prm = make_params(params)
+        self._check(self.L.abd_ccd_max_step(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(x0), _ptr(dx),
+                                            _ptr(pt), pt.shape[0], _ptr(ee), ee.shape[0], _ptr(t_pt), _ptr(t_ee),
+                                            _ptr(alpha), _stream()))
+        return t_pt, t_ee, alpha
+
+    def orthogonality(self, scene, params, q, weight, project=True):
+        nb = scene.n_bodies
+        dev = q.device
+        e = torch.zeros(1, dtype=torch.float64, device=dev)
+        g = torch.zeros((nb, 12), dtype=torch.float64, device=dev)
+        D = torch.zeros((nb, 144), dtype=torch.float64, device=dev)
+        prm = make_params(params)
+        self._check(self.L.abd_orthogonality(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q),
+                                             float(weight), _ptr(e), _ptr(g), _ptr(D), int(project), _stream()))
+        return e, g, D
+
+    def inertia(self, scene, q, q_tilde):
+        nb = scene.n_bodies
+        dev = q.device
+        e = torch.zeros(1, dtype=torch.float64, device=dev)
+        g = torch.zeros((nb, 12), dtype=torch.float64, device=dev)
+        D = torch.zeros((nb, 144), dtype=torch.float64, device=dev)
+        self._check(self.L.abd_inertia(self.h, ctypes.byref(scene.c), _ptr(q), _ptr(q_tilde), _ptr(e), _ptr(g),
+                                       _ptr(D), _stream()))
+        return e, g, D
+
+    def q_tilde(self, scene, params, q, qd):
+        out = torch.empty_like(q)
+        prm = make_params(params)
+        self._check(self.L.abd_q_tilde(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q), _ptr(qd),
+                                       _ptr(out), _stream()))
+        return out
+
+    def pcg_solve(self, scene, diag, off, keys, rhs, rtol=1e-12, max_iter=10000):
+        p = torch.zeros_like(rhs)
+        it = ctypes.c_int32(0)
+        self._check(self.L.abd_pcg_solve(self.h, ctypes.byref(scene.c), _ptr(diag), _ptr(off), _ptr(keys),
+                                         keys.shape[0], _ptr(rhs), _ptr(p), float(rtol), int(max_iter),
+                                         ctypes.byref(it), _stream()))
+        return p, it.value
+
+    def newton_step(self, scene, params, q, q_tilde):
+        st = AbdStats()
+        prm = make_params(params)
+        self._check(self.L.abd_newton_step(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q),
+                                           _ptr(q_tilde), ctypes.byref(st), _stream()))
+        return st.as_dict()
+
+    def time_step(self, scene, params, q, qd):
+        st = AbdStats()
+        prm = make_params(params)
+        self._check(self.L.abd_time_step(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q), _ptr(qd),
+                                         ctypes.byref(st), _stream()))
+        return st.as_dict()
+
+
+def setup(S, device=0):
+    """Context + device scene with mass properties computed on the GPU."""
+    ctx = Context(device)
+    scene = Scene(S, f"cuda:{device}")
+    ctx.body_mass(scene)
+    return ctx, scene

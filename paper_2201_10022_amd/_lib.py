@@ -1,0 +1,91 @@
+"""ctypes view of the C ABI declared in include/abd.h (argument marshalling
+only; every step runs in the HIP library)."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabd.so")
+
+ABD_OK = 0
+ERRORS = {-1: "ABD_E_INVALID", -2: "ABD_E_CAPACITY", -3: "ABD_E_INTERSECT", -4: "ABD_E_NOT_CONVERGED",
+          -5: "ABD_E_LINESEARCH", -6: "ABD_E_PCG", -7: "ABD_E_HIP"}
+
+EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_body_mass", "abd_vertex_map", "abd_candidates",
+           "abd_offdiag_pattern", "abd_classify", "abd_barrier_grad_hess", "abd_barrier_energy",
+           "abd_ccd_max_step", "abd_orthogonality", "abd_inertia", "abd_q_tilde", "abd_pcg_solve",
+           "abd_newton_step", "abd_time_step"]
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+
+
+class AbdScene(ctypes.Structure):
+    _fields_ = [("n_bodies", _i32), ("n_verts", _i32), ("n_tris", _i32), ("n_edges", _i32), ("n_scenes", _i32),
+                ("xbar", _vp), ("vert_body", _vp), ("tris", _vp), ("tri_body", _vp), ("edges", _vp),
+                ("edge_body", _vp), ("body_vert_off", _vp), ("body_tri_off", _vp), ("body_edge_off", _vp),
+                ("body_fixed", _vp), ("body_scene", _vp), ("mass", _vp), ("volume", _vp)]
+
+
+class AbdParams(ctypes.Structure):
+    _fields_ = [("dt", _dbl), ("dhat", _dbl), ("kappa_b", _dbl), ("kappa_o", _dbl), ("mu", _dbl), ("eps_v", _dbl),
+                ("gravity", _dbl * 3), ("newton_tol", _dbl), ("pcg_rtol", _dbl), ("ccd_s", _dbl),
+                ("ccd_tmax", _dbl), ("ccd_max_iter", _i32), ("max_newton", _i32), ("max_pcg", _i32),
+                ("max_ls", _i32)]
+
+
+class AbdStats(ctypes.Structure):
+    _fields_ = [("n_pt", _i64), ("n_ee", _i64), ("n_active_pt", _i64), ("n_active_ee", _i64),
+                ("n_pt_swept", _i64), ("n_ee_swept", _i64), ("n_offdiag", _i64), ("pcg_iters", _i32),
+                ("ls_halvings", _i32), ("converged", _i32), ("newton_iters", _i32), ("alpha_ccd", _dbl),
+                ("alpha", _dbl), ("disp", _dbl), ("energy0", _dbl), ("energy1", _dbl), ("t_barrier_ms", _dbl),
+                ("t_ccd_ms", _dbl), ("t_candidates_ms", _dbl), ("t_solve_ms", _dbl), ("t_total_ms", _dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_PS = ctypes.POINTER(AbdScene)
+_PP = ctypes.POINTER(AbdParams)
+_PST = ctypes.POINTER(AbdStats)
+
+SIGNATURES = {
+    "abd_create": ([ctypes.POINTER(_vp), ctypes.c_int], ctypes.c_int),
+    "abd_destroy": ([_vp], ctypes.c_int),
+    "abd_last_error": ([_vp], ctypes.c_char_p),
+    "abd_body_mass": ([_vp, _PS, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "abd_vertex_map": ([_vp, _PS, _vp, _vp, _vp], ctypes.c_int),
+    "abd_candidates": ([_vp, _PS, _vp, _vp, _dbl, _vp, _i64, _pi64, _vp, _i64, _pi64, _vp], ctypes.c_int),
+    "abd_offdiag_pattern": ([_vp, _PS, _vp, _i64, _vp, _i64, _vp, _i64, _pi64, _vp], ctypes.c_int),
+    "abd_classify": ([_vp, _PS, _vp, _dbl, _vp, _i64, ctypes.c_int, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "abd_barrier_grad_hess": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp,
+                               ctypes.c_int, _vp], ctypes.c_int),
+    "abd_barrier_energy": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "abd_ccd_max_step": ([_vp, _PS, _PP, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "abd_orthogonality": ([_vp, _PS, _PP, _vp, _dbl, _vp, _vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
+    "abd_inertia": ([_vp, _PS, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "abd_q_tilde": ([_vp, _PS, _PP, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "abd_pcg_solve": ([_vp, _PS, _vp, _vp, _vp, _i64, _vp, _vp, _dbl, _i32, _pi32, _vp], ctypes.c_int),
+    "abd_newton_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
+    "abd_time_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
+}
+
+_LIB = None
+
+
+def load():
+    """Loads the in-tree libabd.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2201_10022_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB

@@ -1,0 +1,329 @@
+// Per-vertex and per-body kernels: mass properties, the kinematic map, the
+// inertia and orthogonality terms of the incremental potential.
+#include "abd_internal.h"
+#include "abd_jacobi.h"
+
+namespace {
+
+// Mass properties by the divergence theorem (one 64-lane wave per body;
+// triangles strided over lanes, fixed-order wave reduction).
+__global__ void __launch_bounds__(64) k_body_mass(int nb, const int32_t *tri_off, const int32_t *tris,
+                                                  const double *xbar, const double *density, const uint8_t *fixed,
+                                                  double *mass, double *volume) {
+  const int b = blockIdx.x;
+  if (b >= nb) return;
+  double acc[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) acc[i] = 0.0;
+  if (!fixed[b]) {
+    for (int t = tri_off[b] + threadIdx.x; t < tri_off[b + 1]; t += 64) {
+      const d3 v0 = ld3(xbar, tris[3 * t]), v1 = ld3(xbar, tris[3 * t + 1]), v2 = ld3(xbar, tris[3 * t + 2]);
+      const d3 c12 = {v1.y * v2.z - v1.z * v2.y, v1.z * v2.x - v1.x * v2.z, v1.x * v2.y - v1.y * v2.x};
+      const double vt = (v0.x * c12.x + v0.y * c12.y + v0.z * c12.z) / 6.0;
+      const double s[3] = {v0.x + v1.x + v2.x, v0.y + v1.y + v2.y, v0.z + v1.z + v2.z};
+      const double a0[3] = {v0.x, v0.y, v0.z}, a1[3] = {v1.x, v1.y, v1.z}, a2[3] = {v2.x, v2.y, v2.z};
+      acc[0] += vt;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[1 + i] += 0.25 * vt * s[i];
+      int k = 4;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j)
+          acc[k++] += (vt / 20.0) * (a0[i] * a0[j] + a1[i] * a1[j] + a2[i] * a2[j] + s[i] * s[j]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 10; ++i) acc[i] = wave_sum(acc[i]);
+  if (threadIdx.x == 0) {
+    const double rho = fixed[b] ? 0.0 : density[b];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) mass[10 * b + i] = rho * acc[i];
+    volume[b] = fixed[b] ? 0.0 : acc[0];
+  }
+}
+
+// x_k = p + A xbar_k, each component as p_i + ((a_i0 xb0 + a_i1 xb1) + a_i2 xb2)
+// with contraction off: bit-identical to any IEEE evaluation in this order.
+__global__ void __launch_bounds__(256) k_vertex_map(int nv, const double *__restrict__ xbar,
+                                                    const int32_t *__restrict__ vert_body,
+                                                    const double *__restrict__ q, double *__restrict__ x) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nv) return;
+  const double *qb = q + 12 * (int64_t)vert_body[k];
+  const double xb0 = xbar[3 * k], xb1 = xbar[3 * k + 1], xb2 = xbar[3 * k + 2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double *a = qb + 3 + 3 * i;
+    x[3 * k + i] = qb[i] + ((a[0] * xb0 + a[1] * xb1) + a[2] * xb2);
+  }
+}
+
+// max_k |J_k p|_inf over vertices (p of fixed bodies is zero): per-block max
+__global__ void __launch_bounds__(256) k_disp_max(int nv, const double *__restrict__ xbar,
+                                                  const int32_t *__restrict__ vert_body, const double *__restrict__ p,
+                                                  double *__restrict__ part) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < nv; k += gridDim.x * 256) {
+    const double *qb = p + 12 * (int64_t)vert_body[k];
+    const double xb0 = xbar[3 * k], xb1 = xbar[3 * k + 1], xb2 = xbar[3 * k + 2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double *a = qb + 3 + 3 * i;
+      m = fmax(m, fabs(qb[i] + ((a[0] * xb0 + a[1] * xb1) + a[2] * xb2)));
+    }
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__global__ void k_max_fold(const double *part, int n, double *out) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) m = fmax(m, part[i]);
+  m = wave_max(m);
+  if (threadIdx.x == 0) *out = m;
+}
+
+// (M dq) for one body, M = I_3 (x) [[m, h^T], [h, S]] in (p_i, a_i) groups
+__device__ __forceinline__ void mass_apply(const double *mb, const double *dq, double *out) {
+  const double m = mb[0], h[3] = {mb[1], mb[2], mb[3]};
+  const double S[3][3] = {{mb[4], mb[5], mb[6]}, {mb[5], mb[7], mb[8]}, {mb[6], mb[8], mb[9]}};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double *a = dq + 3 + 3 * i;
+    out[i] = m * dq[i] + h[0] * a[0] + h[1] * a[1] + h[2] * a[2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) out[3 + 3 * i + r] = h[r] * dq[i] + S[r][0] * a[0] + S[r][1] * a[1] + S[r][2] * a[2];
+  }
+}
+
+// Orthogonality potential V = kn (sum_i (a_i.a_i - 1)^2 + sum_{i!=j} (a_i.a_j)^2)
+// and its derivatives (ABD Eq. ortho-energy / ortho-poly; off-diagonal
+// blocks 4 kn ((a_i.a_j) I + a_j a_i^T)), times w.
+struct Ortho {
+  double e;
+  double g[9];
+  double H[45];  // packed upper 9x9
+};
+__device__ __forceinline__ void ortho_eval(const double *A, double kn, double w, Ortho &o, bool want_h) {
+  double dots[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dots[i][j] = A[3 * i] * A[3 * j] + A[3 * i + 1] * A[3 * j + 1] + A[3 * i + 2] * A[3 * j + 2];
+  double V = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V += i == j ? (dots[i][i] - 1.0) * (dots[i][i] - 1.0) : dots[i][j] * dots[i][j];
+  o.e = w * kn * V;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double gi = (dots[i][i] - 1.0) * A[3 * i + c];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (j != i) gi += dots[i][j] * A[3 * j + c];
+      o.g[3 * i + c] = w * 4.0 * kn * gi;
+    }
+  if (!want_h) return;
+  using S = SymIdx<9>;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int j = i; j < 3; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (3 * j + c < 3 * i + r) continue;
+          double h;
+          if (i == j) {
+            h = 4.0 * A[3 * i + r] * A[3 * i + c] + (r == c ? 2.0 * (dots[i][i] - 1.0) : 0.0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+              if (k != i) h += 2.0 * A[3 * k + r] * A[3 * k + c];
+            h *= 2.0 * kn;
+          } else {
+            h = 4.0 * kn * ((r == c ? dots[i][j] : 0.0) + A[3 * j + r] * A[3 * i + c]);
+          }
+          o.H[S::at(3 * i + r, 3 * j + c)] = w * h;
+        }
+}
+
+// inertia + weighted orthogonality per body: energies to e_out[b], gradient
+// and diagonal blocks accumulated (thread per body)
+__global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed, const double *mass,
+                                                  const double *volume, const double *q, const double *qt,
+                                                  double kappa_o, double w, int do_inertia, int do_ortho,
+                                                  int project, int want_grad, double *e_out, double *grad,
+                                                  double *diag) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  if (fixed[b]) {
+    e_out[b] = 0.0;
+    return;
+  }
+  const double *qb = q + 12 * (int64_t)b;
+  double e = 0.0;
+  if (do_inertia) {
+    double dq[12], Mq[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) dq[i] = qb[i] - qt[12 * (int64_t)b + i];
+    mass_apply(mass + 10 * (int64_t)b, dq, Mq);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) s += dq[i] * Mq[i];
+    e += 0.5 * s;
+    if (want_grad)
+#pragma unroll
+      for (int i = 0; i < 12; ++i) grad[12 * (int64_t)b + i] += Mq[i];
+    if (diag) {
+      const double *mb = mass + 10 * (int64_t)b;
+      double *D = diag + 144 * (int64_t)b;
+      const double S[3][3] = {{mb[4], mb[5], mb[6]}, {mb[5], mb[7], mb[8]}, {mb[6], mb[8], mb[9]}};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        D[12 * i + i] += mb[0];
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+          D[12 * i + 3 + 3 * i + n] += mb[1 + n];
+          D[12 * (3 + 3 * i + n) + i] += mb[1 + n];
+#pragma unroll
+          for (int m = 0; m < 3; ++m) D[12 * (3 + 3 * i + m) + 3 + 3 * i + n] += S[m][n];
+        }
+      }
+    }
+  }
+  if (do_ortho) {
+    Ortho o;
+    ortho_eval(qb + 3, kappa_o * volume[b], w, o, diag != nullptr);
+    e += o.e;
+    if (want_grad)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) grad[12 * (int64_t)b + 3 + i] += o.g[i];
+    if (diag) {
+      if (project) psd_project_packed<9>(o.H);
+      using S = SymIdx<9>;
+      double *D = diag + 144 * (int64_t)b;
+#pragma unroll
+      for (int r = 0; r < 9; ++r)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) D[12 * (3 + r) + 3 + c] += o.H[S::at(r, c)];
+    }
+  }
+  e_out[b] = e;
+}
+
+__global__ void k_q_tilde(int nb, const uint8_t *fixed, const double *q, const double *qd, double dt, double gx,
+                          double gy, double gz, double *qt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb * 12) return;
+  const int b = i / 12, c = i % 12;
+  if (fixed[b]) {
+    qt[i] = q[i];
+    return;
+  }
+  double v = q[i] + dt * qd[i];
+  if (c < 3) v += dt * dt * (c == 0 ? gx : (c == 1 ? gy : gz));
+  qt[i] = v;
+}
+
+}  // namespace
+
+int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t s) {
+  if (sc->n_verts <= 0) return ABD_OK;
+  hipLaunchKernelGGL(k_vertex_map, dim3(grid_for(sc->n_verts, 256)), dim3(256), 0, s, sc->n_verts, sc->xbar,
+                     sc->vert_body, q, x);
+  return abd_hip_check(ctx, hipGetLastError(), "k_vertex_map");
+}
+
+int op_max_abs_disp(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s) {
+  int nblk = (int)grid_for(sc->n_verts, 256 * 8);
+  if (nblk < 1) nblk = 1;
+  if (nblk > 1024) nblk = 1024;
+  double *part;
+  ABD_TRY(ws(ctx, "disp_part", nblk, &part, s));
+  hipLaunchKernelGGL(k_disp_max, dim3(nblk), dim3(256), 0, s, sc->n_verts, sc->xbar, sc->vert_body, p, part);
+  hipLaunchKernelGGL(k_max_fold, dim3(1), dim3(64), 0, s, part, nblk, out_dev);
+  return abd_hip_check(ctx, hipGetLastError(), "k_disp_max");
+}
+
+static int body_terms(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double kappa_o,
+                      double w, int do_inertia, int do_ortho, int project, double *energy, double *grad,
+                      double *diag, hipStream_t s) {
+  if (sc->n_bodies <= 0) return ABD_OK;
+  if (!sc->mass && do_inertia) return abd_fail(ctx, ABD_E_INVALID, "scene mass is NULL");
+  if (!sc->volume && do_ortho) return abd_fail(ctx, ABD_E_INVALID, "scene volume is NULL");
+  double *eb;
+  ABD_TRY(ws(ctx, "body_e", sc->n_bodies, &eb, s));
+  hipLaunchKernelGGL(k_body_terms, dim3(grid_for(sc->n_bodies, 64)), dim3(64), 0, s, sc->n_bodies, sc->body_fixed,
+                     sc->mass, sc->volume, q, qt, kappa_o, w, do_inertia, do_ortho, project, grad != nullptr ? 1 : 0,
+                     eb, grad, diag);
+  HIP_TRY(ctx, hipGetLastError());
+  if (energy) ABD_TRY(reduce_sum_f64(ctx, eb, sc->n_bodies, energy, s));
+  return ABD_OK;
+}
+
+int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
+                  double *energy, double *grad, double *diag, int project, hipStream_t s) {
+  return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, project, energy, grad, diag, s);
+}
+
+int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
+                   double *energy, hipStream_t s) {
+  return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, energy, nullptr, nullptr, s);
+}
+
+int op_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,
+                     double *energy, double *grad, double *diag, int project, hipStream_t s) {
+  return body_terms(ctx, sc, q, nullptr, prm->kappa_o, weight, 0, 1, project, energy, grad, diag, s);
+}
+
+int op_inertia(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double *energy, double *grad,
+               double *diag, hipStream_t s) {
+  return body_terms(ctx, sc, q, qt, 0.0, 0.0, 1, 0, 0, energy, grad, diag, s);
+}
+
+// ------------------------------------------------------------------ ABI ----
+extern "C" int abd_body_mass(abd_ctx *ctx, const abd_scene *sc, const double *density, double *mass,
+                             double *volume, hipStream_t stream) {
+  if (!ctx || !sc || !density || !mass || !volume) return abd_fail(ctx, ABD_E_INVALID, "abd_body_mass: null");
+  if (sc->n_bodies <= 0) return ABD_OK;
+  hipLaunchKernelGGL(k_body_mass, dim3(sc->n_bodies), dim3(64), 0, stream, sc->n_bodies, sc->body_tri_off, sc->tris,
+                     sc->xbar, density, sc->body_fixed, mass, volume);
+  return abd_hip_check(ctx, hipGetLastError(), "k_body_mass");
+}
+
+extern "C" int abd_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t stream) {
+  if (!ctx || !sc || !q || !x) return abd_fail(ctx, ABD_E_INVALID, "abd_vertex_map: null");
+  return op_vertex_map(ctx, sc, q, x, stream);
+}
+
+extern "C" int abd_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
+                                 double weight, double *energy, double *grad, double *diag, int project_psd,
+                                 hipStream_t stream) {
+  if (!ctx || !sc || !prm || !q) return abd_fail(ctx, ABD_E_INVALID, "abd_orthogonality: null");
+  return op_orthogonality(ctx, sc, prm, q, weight, energy, grad, diag, project_psd, stream);
+}
+
+extern "C" int abd_inertia(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *q_tilde,
+                           double *energy, double *grad, double *diag, hipStream_t stream) {
+  if (!ctx || !sc || !q || !q_tilde) return abd_fail(ctx, ABD_E_INVALID, "abd_inertia: null");
+  return op_inertia(ctx, sc, q, q_tilde, energy, grad, diag, stream);
+}
+
+extern "C" int abd_q_tilde(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
+                           const double *qdot, double *q_tilde, hipStream_t stream) {
+  if (!ctx || !sc || !prm || !q || !qdot || !q_tilde) return abd_fail(ctx, ABD_E_INVALID, "abd_q_tilde: null");
+  const int n = sc->n_bodies * 12;
+  if (n <= 0) return ABD_OK;
+  hipLaunchKernelGGL(k_q_tilde, dim3(grid_for(n, 256)), dim3(256), 0, stream, sc->n_bodies, sc->body_fixed, q, qdot,
+                     prm->dt, prm->gravity[0], prm->gravity[1], prm->gravity[2], q_tilde);
+  return abd_hip_check(ctx, hipGetLastError(), "k_q_tilde");
+}

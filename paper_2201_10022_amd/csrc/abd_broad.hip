@@ -1,0 +1,457 @@
+// Broad phase (ABD sec. 4.2): swept, inflated primitive boxes -> body boxes
+// -> overlapping body pairs -> per body pair the primitives inside the
+// other body's box (the i-AABB cull) -> tiled primitive-pair box tests with
+// wave ballot compaction.  Count and write passes run the same tests, so
+// the output order is a pure function of the candidate set.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "abd_internal.h"
+
+namespace {
+
+// Box of a primitive: lo = min over its vertices at x0 and x1, hi' =
+// max(...) + inflate (rounded once; max commutes with the monotone rounding
+// so body boxes built from hi' equal body max + inflate).
+struct Box {
+  double lo[3], hi[3];
+};
+
+__device__ __forceinline__ bool box_overlap(const double *a, const double *b) {
+  // a, b: [lo0 lo1 lo2 hi'0 hi'1 hi'2]
+  return a[0] <= b[3] && b[0] <= a[3] && a[1] <= b[4] && b[1] <= a[4] && a[2] <= b[5] && b[2] <= a[5];
+}
+
+__global__ void __launch_bounds__(256) k_vert_boxes(int nv, const double *x0, const double *x1, double inflate,
+                                                    double *vb) {
+#pragma clang fp contract(off)
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= nv) return;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double a = x0[3 * v + i], b = x1[3 * v + i];
+    vb[6 * (int64_t)v + i] = fmin(a, b);
+    vb[6 * (int64_t)v + 3 + i] = fmax(a, b) + inflate;
+  }
+}
+
+template <int K>  // vertices per primitive
+__global__ void __launch_bounds__(256) k_prim_boxes(int n, const int32_t *prims, const double *vb, double *pb) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  double b[6];
+  const int v0 = prims[K * (int64_t)p];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) b[i] = vb[6 * (int64_t)v0 + i];
+#pragma unroll
+  for (int k = 1; k < K; ++k) {
+    const int v = prims[K * (int64_t)p + k];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      b[i] = fmin(b[i], vb[6 * (int64_t)v + i]);
+      b[3 + i] = fmax(b[3 + i], vb[6 * (int64_t)v + 3 + i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) pb[6 * (int64_t)p + i] = b[i];
+}
+
+__global__ void __launch_bounds__(256) k_body_boxes(int nb, const int32_t *voff, const double *vb, double *bb) {
+  __shared__ double sh[6][4];
+  const int b = blockIdx.x;
+  double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int v = voff[b] + threadIdx.x; v < voff[b + 1]; v += 256) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      m[i] = fmin(m[i], vb[6 * (int64_t)v + i]);
+      m[3 + i] = fmax(m[3 + i], vb[6 * (int64_t)v + 3 + i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    m[i] = wave_min(m[i]);
+    m[3 + i] = wave_max(m[3 + i]);
+  }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sh[i][threadIdx.x >> 6] = m[i];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int i = threadIdx.x;
+    double r = sh[i][0];
+    for (int w = 1; w < 4; ++w) r = i < 3 ? fmin(r, sh[i][w]) : fmax(r, sh[i][w]);
+    bb[6 * (int64_t)b + i] = r;
+  }
+}
+
+// body pairs (a < b) in one sub-scene, not both fixed, boxes overlapping.
+// Pass 0 counts per a, pass 1 writes in (a, b) order.
+template <int WRITE>
+__global__ void __launch_bounds__(64) k_body_pairs(int nb, const int32_t *body_scene, const uint8_t *fixed,
+                                                   const double *bb, const int32_t *scene_end_of_body,
+                                                   int64_t *cnt, const int64_t *off, int32_t *pairs) {
+  const int a = blockIdx.x;
+  if (a >= nb) return;
+  const int end = scene_end_of_body[a];
+  double ba[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) ba[i] = bb[6 * (int64_t)a + i];
+  const bool fa = fixed[a] != 0;
+  int64_t base = WRITE ? off[a] : 0;
+  int64_t c = 0;
+  for (int b0 = a + 1; b0 < end; b0 += 64) {
+    const int b = b0 + (int)threadIdx.x;
+    bool ok = false;
+    if (b < end && !(fa && fixed[b])) ok = box_overlap(ba, bb + 6 * (int64_t)b);
+    const unsigned long long m = __ballot(ok);
+    if (WRITE && ok) {
+      const int64_t pos = base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull));
+      pairs[2 * pos] = a;
+      pairs[2 * pos + 1] = b;
+    }
+    c += __popcll(m);
+  }
+  if (!WRITE && threadIdx.x == 0) cnt[a] = c;
+}
+
+__global__ void k_scene_end(int nb, const int32_t *body_scene, int32_t *end) {
+  // end of the sub-scene containing body b (body_scene is non-decreasing)
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int s = body_scene[b];
+  int lo = b, hi = nb;  // first index with scene > s
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (body_scene[mid] > s)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  end[b] = lo;
+}
+
+// List kinds per body pair (a,b):
+//   0: vertices of a in box(b)   1: triangles of b in box(a)
+//   2: vertices of b in box(a)   3: triangles of a in box(b)
+//   4: edges of a in box(b)      5: edges of b in box(a)
+// Capacity of each list = primitive count of its body; region offsets per
+// body pair from a scan of the summed capacities.
+__global__ void k_list_caps(int64_t nbp, const int32_t *bpairs, const int32_t *voff, const int32_t *toff,
+                            const int32_t *eoff, int64_t *cap) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nbp) return;
+  const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
+  cap[p] = (int64_t)(voff[a + 1] - voff[a]) + (toff[b + 1] - toff[b]) + (voff[b + 1] - voff[b]) +
+           (toff[a + 1] - toff[a]) + (eoff[a + 1] - eoff[a]) + (eoff[b + 1] - eoff[b]);
+}
+
+__global__ void __launch_bounds__(256) k_cull_lists(const int32_t *bpairs, const int64_t *region,
+                                                    const int32_t *voff, const int32_t *toff, const int32_t *eoff,
+                                                    const double *bb, const double *vbox, const double *tbox,
+                                                    const double *ebox, int32_t *lists, int64_t *list_start,
+                                                    int32_t *list_len) {
+  __shared__ int wcnt[4];
+  const int64_t p = blockIdx.x;
+  const int kind = blockIdx.y;
+  const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
+  // (body owning the primitives, body whose box culls them)
+  const int own = (kind == 0 || kind == 3 || kind == 4) ? a : b;
+  const int oth = own == a ? b : a;
+  const int32_t *offs = (kind == 0 || kind == 2) ? voff : (kind == 1 || kind == 3) ? toff : eoff;
+  const double *boxes = (kind == 0 || kind == 2) ? vbox : (kind == 1 || kind == 3) ? tbox : ebox;
+  // start of this list inside the body pair's region
+  int64_t start = region[p];
+  {
+    const int la = voff[a + 1] - voff[a], lb = voff[b + 1] - voff[b];
+    const int ta = toff[a + 1] - toff[a], tb = toff[b + 1] - toff[b];
+    const int ea = eoff[a + 1] - eoff[a];
+    const int caps[6] = {la, tb, lb, ta, ea, 0};
+    for (int k = 0; k < kind; ++k) start += caps[k];
+  }
+  double ob[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) ob[i] = bb[6 * (int64_t)oth + i];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int total = 0;
+  for (int c0 = offs[own]; c0 < offs[own + 1]; c0 += 256) {
+    const int i = c0 + (int)threadIdx.x;
+    const bool ok = i < offs[own + 1] && box_overlap(boxes + 6 * (int64_t)i, ob);
+    const unsigned long long m = __ballot(ok);
+    if (lane == 0) wcnt[wid] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wid; ++w) before += wcnt[w];
+    if (ok) lists[start + total + before + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    total += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    list_start[6 * p + kind] = start;
+    list_len[6 * p + kind] = total;
+  }
+}
+
+constexpr int TROWS = 16;
+
+// tiles per sub-problem: sub 3p+0: rows list 0 x cols list 1 (PT),
+// 3p+1: list 2 x list 3 (PT), 3p+2: list 4 x list 5 (EE)
+__global__ void k_sub_tiles(int64_t nbp, const int32_t *list_len, int64_t *tiles_pt, int64_t *tiles_ee) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nbp) return;
+  for (int s = 0; s < 3; ++s) {
+    const int nr = list_len[6 * p + 2 * s], nc = list_len[6 * p + 2 * s + 1];
+    const int64_t t = nc > 0 ? (nr + TROWS - 1) / TROWS : 0;
+    if (s < 2)
+      tiles_pt[2 * p + s] = t;
+    else
+      tiles_ee[p] = t;
+  }
+}
+
+// One wave per tile of TROWS rows x all columns.  WRITE=0 counts the
+// passing tests of the tile, WRITE=1 writes them row-major at the tile's
+// offset.  is_ee selects the sub-problem family.
+template <int WRITE>
+__global__ void __launch_bounds__(64) k_pair_tiles(int is_ee, int64_t n_sub, const int64_t *sub_tile_off,
+                                                   int64_t n_tiles, const int64_t *list_start,
+                                                   const int32_t *list_len, const int32_t *lists,
+                                                   const double *row_boxes, const double *col_boxes,
+                                                   int64_t *tile_cnt, const int64_t *tile_off, int32_t *out) {
+  const int64_t tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  // sub-problem owning the tile: last s with sub_tile_off[s] <= tile
+  int64_t lo = 0, hi = n_sub - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (sub_tile_off[mid] <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t s = lo;
+  const int64_t p = is_ee ? s : s / 2;
+  const int li = is_ee ? 4 : 2 * (int)(s % 2);
+  const int64_t rstart = list_start[6 * p + li], cstart = list_start[6 * p + li + 1];
+  const int nr = list_len[6 * p + li], nc = list_len[6 * p + li + 1];
+  const int r0 = (int)(tile - sub_tile_off[s]) * TROWS;
+  const int r1 = min(nr, r0 + TROWS);
+  const int lane = threadIdx.x;
+  int64_t pos = WRITE ? tile_off[tile] : 0;
+  int64_t cnt = 0;
+  for (int r = r0; r < r1; ++r) {
+    const int rp = lists[rstart + r];
+    double rb[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) rb[i] = row_boxes[6 * (int64_t)rp + i];
+    for (int c0 = 0; c0 < nc; c0 += 64) {
+      const int c = c0 + lane;
+      int cp = 0;
+      bool ok = false;
+      if (c < nc) {
+        cp = lists[cstart + c];
+        ok = box_overlap(rb, col_boxes + 6 * (int64_t)cp);
+      }
+      const unsigned long long m = __ballot(ok);
+      if (WRITE && ok) {
+        const int64_t o = pos + cnt + __popcll(m & ((1ull << lane) - 1ull));
+        out[2 * o] = rp;
+        out[2 * o + 1] = cp;
+      }
+      cnt += __popcll(m);
+    }
+  }
+  if (!WRITE && lane == 0) tile_cnt[tile] = cnt;
+}
+
+}  // namespace
+
+int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1, double inflate,
+                  int32_t **pt_out, int64_t *n_pt, int32_t **ee_out, int64_t *n_ee, const char *tag,
+                  hipStream_t s) {
+  const int nb = sc->n_bodies, nv = sc->n_verts, nt = sc->n_tris, ne = sc->n_edges;
+  if (!x1) x1 = x0;
+  *n_pt = *n_ee = 0;
+  if (nb <= 1 || nv <= 0) return ABD_OK;
+  double *vbox, *tbox, *ebox, *bbox;
+  ABD_TRY(ws(ctx, "bp_vbox", 6 * (size_t)nv, &vbox, s));
+  ABD_TRY(ws(ctx, "bp_tbox", 6 * (size_t)nt + 6, &tbox, s));
+  ABD_TRY(ws(ctx, "bp_ebox", 6 * (size_t)ne + 6, &ebox, s));
+  ABD_TRY(ws(ctx, "bp_bbox", 6 * (size_t)nb, &bbox, s));
+  hipLaunchKernelGGL(k_vert_boxes, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv, x0, x1, inflate, vbox);
+  if (nt) hipLaunchKernelGGL(k_prim_boxes<3>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, sc->tris, vbox, tbox);
+  if (ne) hipLaunchKernelGGL(k_prim_boxes<2>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, sc->edges, vbox, ebox);
+  hipLaunchKernelGGL(k_body_boxes, dim3(nb), dim3(256), 0, s, nb, sc->body_vert_off, vbox, bbox);
+  HIP_TRY(ctx, hipGetLastError());
+
+  // body pairs
+  int32_t *send;
+  int64_t *bcnt, *boff, *btot;
+  ABD_TRY(ws(ctx, "bp_send", nb, &send, s));
+  ABD_TRY(ws(ctx, "bp_bcnt", nb, &bcnt, s));
+  ABD_TRY(ws(ctx, "bp_boff", nb, &boff, s));
+  ABD_TRY(ws(ctx, "bp_btot", 4, &btot, s));
+  hipLaunchKernelGGL(k_scene_end, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, sc->body_scene, send);
+  hipLaunchKernelGGL(k_body_pairs<0>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send, bcnt,
+                     nullptr, nullptr);
+  ABD_TRY(scan_exclusive_i64(ctx, bcnt, boff, nb, btot, s));
+  int64_t *hbuf;
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
+  HIP_TRY(ctx, hipMemcpyAsync(hbuf, btot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  const int64_t nbp = hbuf[0];
+  if (nbp == 0) return ABD_OK;
+  int32_t *bpairs;
+  ABD_TRY(ws(ctx, "bp_pairs", 2 * nbp, &bpairs, s));
+  hipLaunchKernelGGL(k_body_pairs<1>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
+                     nullptr, boff, bpairs);
+
+  // culled primitive lists per body pair
+  int64_t *cap, *region, *rtot;
+  ABD_TRY(ws(ctx, "bp_cap", nbp, &cap, s));
+  ABD_TRY(ws(ctx, "bp_region", nbp, &region, s));
+  ABD_TRY(ws(ctx, "bp_rtot", 1, &rtot, s));
+  hipLaunchKernelGGL(k_list_caps, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, bpairs, sc->body_vert_off,
+                     sc->body_tri_off, sc->body_edge_off, cap);
+  ABD_TRY(scan_exclusive_i64(ctx, cap, region, nbp, rtot, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hbuf, rtot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  const int64_t list_total = hbuf[0];
+  int32_t *lists, *llen;
+  int64_t *lstart;
+  ABD_TRY(ws(ctx, "bp_lists", list_total + 1, &lists, s));
+  ABD_TRY(ws(ctx, "bp_llen", 6 * nbp, &llen, s));
+  ABD_TRY(ws(ctx, "bp_lstart", 6 * nbp, &lstart, s));
+  hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 6), dim3(256), 0, s, bpairs, region, sc->body_vert_off,
+                     sc->body_tri_off, sc->body_edge_off, bbox, vbox, tbox, ebox, lists, lstart, llen);
+
+  // tiles
+  int64_t *tpt, *tee, *tpt_off, *tee_off, *ttot;
+  ABD_TRY(ws(ctx, "bp_tpt", 2 * nbp, &tpt, s));
+  ABD_TRY(ws(ctx, "bp_tee", nbp, &tee, s));
+  ABD_TRY(ws(ctx, "bp_tpt_off", 2 * nbp, &tpt_off, s));
+  ABD_TRY(ws(ctx, "bp_tee_off", nbp, &tee_off, s));
+  ABD_TRY(ws(ctx, "bp_ttot", 2, &ttot, s));
+  hipLaunchKernelGGL(k_sub_tiles, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, llen, tpt, tee);
+  ABD_TRY(scan_exclusive_i64(ctx, tpt, tpt_off, 2 * nbp, ttot, s));
+  ABD_TRY(scan_exclusive_i64(ctx, tee, tee_off, nbp, ttot + 1, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hbuf, ttot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  const int64_t ntile_pt = hbuf[0], ntile_ee = hbuf[1];
+  int64_t *cpt, *cee, *opt, *oee, *otot;
+  ABD_TRY(ws(ctx, "bp_cpt", ntile_pt + 1, &cpt, s));
+  ABD_TRY(ws(ctx, "bp_cee", ntile_ee + 1, &cee, s));
+  ABD_TRY(ws(ctx, "bp_opt", ntile_pt + 1, &opt, s));
+  ABD_TRY(ws(ctx, "bp_oee", ntile_ee + 1, &oee, s));
+  ABD_TRY(ws(ctx, "bp_otot", 2, &otot, s));
+  if (ntile_pt)
+    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, 2 * nbp, tpt_off, ntile_pt,
+                       lstart, llen, lists, vbox, tbox, cpt, nullptr, nullptr);
+  if (ntile_ee)
+    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, nbp, tee_off, ntile_ee, lstart,
+                       llen, lists, ebox, ebox, cee, nullptr, nullptr);
+  ABD_TRY(scan_exclusive_i64(ctx, cpt, opt, ntile_pt, otot, s));
+  ABD_TRY(scan_exclusive_i64(ctx, cee, oee, ntile_ee, otot + 1, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hbuf, otot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  *n_pt = hbuf[0];
+  *n_ee = hbuf[1];
+  std::string tpt_name = std::string(tag) + "_pt", tee_name = std::string(tag) + "_ee";
+  ABD_TRY(ws(ctx, tpt_name.c_str(), 2 * (*n_pt) + 2, pt_out, s));
+  ABD_TRY(ws(ctx, tee_name.c_str(), 2 * (*n_ee) + 2, ee_out, s));
+  if (ntile_pt && *n_pt)
+    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, 2 * nbp, tpt_off, ntile_pt,
+                       lstart, llen, lists, vbox, tbox, nullptr, opt, *pt_out);
+  if (ntile_ee && *n_ee)
+    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, nbp, tee_off, ntile_ee, lstart,
+                       llen, lists, ebox, ebox, nullptr, oee, *ee_out);
+  return abd_hip_check(ctx, hipGetLastError(), "candidates");
+}
+
+// ----------------------------------------------------- off-diag pattern ----
+namespace {
+__global__ void k_pair_keys(int64_t n, int is_ee, const int32_t *pairs, const int32_t *vert_body,
+                            const int32_t *tri_body, const int32_t *edge_body, const uint8_t *fixed, uint64_t *keys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = is_ee ? edge_body[pairs[2 * i]] : vert_body[pairs[2 * i]];
+  const int b = is_ee ? edge_body[pairs[2 * i + 1]] : tri_body[pairs[2 * i + 1]];
+  uint64_t k = ~0ull;
+  if (!fixed[a] && !fixed[b] && a != b) {
+    const uint64_t lo = (uint64_t)min(a, b), hi = (uint64_t)max(a, b);
+    k = (lo << 32) | hi;
+  }
+  keys[i] = k;
+}
+__global__ void k_unique_flags(int64_t n, const uint64_t *k, int64_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = (k[i] != ~0ull && (i == 0 || k[i] != k[i - 1])) ? 1 : 0;
+}
+__global__ void k_unique_write(int64_t n, const uint64_t *k, const int64_t *flag, const int64_t *pos, int32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  out[2 * pos[i]] = (int32_t)(k[i] >> 32);
+  out[2 * pos[i] + 1] = (int32_t)(k[i] & 0xffffffffu);
+}
+}  // namespace
+
+int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
+               int32_t **keys_out, int64_t *n_keys, const char *tag, hipStream_t s) {
+  const int64_t n = n_pt + n_ee;
+  *n_keys = 0;
+  std::string nm = std::string(tag) + "_keys";
+  ABD_TRY(ws(ctx, nm.c_str(), 2 * n + 2, keys_out, s));
+  if (n == 0) return ABD_OK;
+  uint64_t *k, *k2;
+  int64_t *flag, *pos, *tot;
+  ABD_TRY(ws(ctx, "od_k", n, &k, s));
+  ABD_TRY(ws(ctx, "od_k2", n, &k2, s));
+  ABD_TRY(ws(ctx, "od_flag", n, &flag, s));
+  ABD_TRY(ws(ctx, "od_pos", n, &pos, s));
+  ABD_TRY(ws(ctx, "od_tot", 1, &tot, s));
+  if (n_pt)
+    hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(n_pt, 256)), dim3(256), 0, s, n_pt, 0, pt, sc->vert_body,
+                       sc->tri_body, sc->edge_body, sc->body_fixed, k);
+  if (n_ee)
+    hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(n_ee, 256)), dim3(256), 0, s, n_ee, 1, ee, sc->vert_body,
+                       sc->tri_body, sc->edge_body, sc->body_fixed, k + n_pt);
+  size_t tmp_bytes = 0;
+  HIP_TRY(ctx, rocprim::radix_sort_keys(nullptr, tmp_bytes, k, k2, (size_t)n, 0, 64, s));
+  void *tmp;
+  ABD_TRY(ws_get(ctx, "od_tmp", tmp_bytes + 16, &tmp, s));
+  HIP_TRY(ctx, rocprim::radix_sort_keys(tmp, tmp_bytes, k, k2, (size_t)n, 0, 64, s));
+  hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, n, k2, flag);
+  ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s));
+  hipLaunchKernelGGL(k_unique_write, dim3(grid_for(n, 256)), dim3(256), 0, s, n, k2, flag, pos, *keys_out);
+  int64_t *hbuf;
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
+  HIP_TRY(ctx, hipMemcpyAsync(hbuf, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  *n_keys = hbuf[0];
+  return abd_hip_check(ctx, hipGetLastError(), "offdiag");
+}
+
+// ------------------------------------------------------------------ ABI ----
+extern "C" int abd_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1,
+                              double inflate, int32_t *pt, int64_t cap_pt, int64_t *n_pt, int32_t *ee,
+                              int64_t cap_ee, int64_t *n_ee, hipStream_t stream) {
+  if (!ctx || !sc || !x0 || !n_pt || !n_ee) return abd_fail(ctx, ABD_E_INVALID, "abd_candidates: null");
+  int32_t *ipt, *iee;
+  ABD_TRY(op_candidates(ctx, sc, x0, x1, inflate, &ipt, n_pt, &iee, n_ee, "abi_cand", stream));
+  if (*n_pt > cap_pt || *n_ee > cap_ee)
+    return abd_fail(ctx, ABD_E_CAPACITY, "candidates need pt %lld ee %lld", (long long)*n_pt, (long long)*n_ee);
+  if (*n_pt) HIP_TRY(ctx, hipMemcpyAsync(pt, ipt, 2 * sizeof(int32_t) * *n_pt, hipMemcpyDeviceToDevice, stream));
+  if (*n_ee) HIP_TRY(ctx, hipMemcpyAsync(ee, iee, 2 * sizeof(int32_t) * *n_ee, hipMemcpyDeviceToDevice, stream));
+  return ABD_OK;
+}
+
+extern "C" int abd_offdiag_pattern(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt,
+                                   const int32_t *ee, int64_t n_ee, int32_t *keys, int64_t cap, int64_t *n_keys,
+                                   hipStream_t stream) {
+  if (!ctx || !sc || !n_keys || (n_pt && !pt) || (n_ee && !ee))
+    return abd_fail(ctx, ABD_E_INVALID, "abd_offdiag_pattern: null");
+  int32_t *k;
+  ABD_TRY(op_offdiag(ctx, sc, pt, n_pt, ee, n_ee, &k, n_keys, "abi_od", stream));
+  if (*n_keys > cap) return abd_fail(ctx, ABD_E_CAPACITY, "offdiag needs %lld", (long long)*n_keys);
+  if (*n_keys) HIP_TRY(ctx, hipMemcpyAsync(keys, k, 2 * sizeof(int32_t) * *n_keys, hipMemcpyDeviceToDevice, stream));
+  return ABD_OK;
+}

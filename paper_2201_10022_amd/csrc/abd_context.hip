@@ -1,0 +1,190 @@
+// Context, workspace, errors and device-wide primitives (scan, sort,
+// deterministic reductions) of the gfx950 ABD library.
+#include <cstdarg>
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "abd_internal.h"
+
+int abd_fail(abd_ctx *ctx, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return code;
+}
+
+int abd_hip_check(abd_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipSuccess) return ABD_OK;
+  return abd_fail(ctx, ABD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ws_get(abd_ctx *ctx, const char *name, size_t bytes, void **out, hipStream_t stream) {
+  DevBuf &b = ctx->bufs[name];
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      HIP_TRY(ctx, hipStreamSynchronize(stream));
+      HIP_TRY(ctx, hipFree(b.ptr));
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    size_t nb = bytes + bytes / 4;
+    nb = (nb + 4095) & ~(size_t)4095;
+    HIP_TRY(ctx, hipMalloc(&b.ptr, nb));
+    HIP_TRY(ctx, hipMemsetAsync(b.ptr, 0, nb, stream));
+    b.bytes = nb;
+  }
+  *out = b.ptr;
+  return ABD_OK;
+}
+
+int pinned_get(abd_ctx *ctx, size_t bytes, void **out) {
+  if (ctx->pinned_bytes < bytes) {
+    if (ctx->pinned) HIP_TRY(ctx, hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    size_t nb = bytes < 4096 ? 4096 : bytes;
+    HIP_TRY(ctx, hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault));
+    ctx->pinned_bytes = nb;
+  }
+  *out = ctx->pinned;
+  return ABD_OK;
+}
+
+__global__ void k_add_i64(const int64_t *a, const int64_t *b, int64_t *o) { *o = *a + *b; }
+
+int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s) {
+  if (n <= 0) {
+    if (total) HIP_TRY(ctx, hipMemsetAsync(total, 0, sizeof(int64_t), s));
+    return ABD_OK;
+  }
+  // keep the last input for the total (in-place scans overwrite it)
+  int64_t *last = nullptr;
+  if (total) {
+    ABD_TRY(ws(ctx, "scan_last", 1, &last, s));
+    HIP_TRY(ctx, hipMemcpyAsync(last, in + n - 1, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  }
+  size_t tmp_bytes = 0;
+  HIP_TRY(ctx, rocprim::exclusive_scan(nullptr, tmp_bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), s));
+  void *tmp = nullptr;
+  ABD_TRY(ws_get(ctx, "scan_tmp", tmp_bytes + 16, &tmp, s));
+  HIP_TRY(ctx, rocprim::exclusive_scan(tmp, tmp_bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), s));
+  if (total) {
+    // total = out[n-1] + in[n-1]
+    hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, s, out + n - 1, last, total);
+  }
+  return ABD_OK;
+}
+
+int sort_pairs_u32(abd_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, hipStream_t s) {
+  if (n <= 1) return ABD_OK;
+  uint32_t *k2, *v2;
+  ABD_TRY(ws(ctx, "sort_k2", n, &k2, s));
+  ABD_TRY(ws(ctx, "sort_v2", n, &v2, s));
+  size_t tmp_bytes = 0;
+  HIP_TRY(ctx, rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, k2, vals, v2, (size_t)n, 0, key_bits, s));
+  void *tmp = nullptr;
+  ABD_TRY(ws_get(ctx, "sort_tmp", tmp_bytes + 16, &tmp, s));
+  HIP_TRY(ctx, rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, k2, vals, v2, (size_t)n, 0, key_bits, s));
+  HIP_TRY(ctx, hipMemcpyAsync(keys, k2, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(vals, v2, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  return ABD_OK;
+}
+
+// ---------------------------------------------------------- reductions ----
+namespace {
+constexpr int RB = 256;
+
+template <int OP>  // 0 sum, 1 min
+__global__ void __launch_bounds__(RB) k_reduce_pass(const double *in, int64_t n, double init, double *out) {
+  __shared__ double sh[RB / 64];
+  double v = init;
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+    const double a = in[i];
+    v = OP == 0 ? v + a : fmin(v, a);
+  }
+  v = OP == 0 ? wave_sum(v) : wave_min(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < RB / 64; ++w) r = OP == 0 ? r + sh[w] : fmin(r, sh[w]);
+    out[blockIdx.x] = r;
+  }
+}
+
+template <int OP>
+__global__ void __launch_bounds__(RB) k_reduce_final(const double *part, int np, double init, double *out,
+                                                     int accumulate) {
+  __shared__ double sh[RB / 64];
+  double v = init;
+  for (int i = threadIdx.x; i < np; i += RB) v = OP == 0 ? v + part[i] : fmin(v, part[i]);
+  v = OP == 0 ? wave_sum(v) : wave_min(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < RB / 64; ++w) r = OP == 0 ? r + sh[w] : fmin(r, sh[w]);
+    if (OP == 0)
+      *out = accumulate ? *out + r : r;
+    else
+      *out = accumulate ? fmin(*out, r) : r;
+  }
+}
+
+template <int OP>
+int reduce_f64(abd_ctx *ctx, const double *in, int64_t n, double init, double *out, int accumulate, hipStream_t s) {
+  int nblk = (int)((n + RB * 4 - 1) / (RB * 4));
+  if (nblk < 1) nblk = 1;
+  if (nblk > 1024) nblk = 1024;
+  double *part;
+  ABD_TRY(ws(ctx, OP == 0 ? "red_sum" : "red_min", nblk, &part, s));
+  hipLaunchKernelGGL(k_reduce_pass<OP>, dim3(nblk), dim3(RB), 0, s, in, n, init, part);
+  hipLaunchKernelGGL(k_reduce_final<OP>, dim3(1), dim3(RB), 0, s, part, nblk, init, out, accumulate);
+  return ABD_OK;
+}
+}  // namespace
+
+int reduce_sum_f64(abd_ctx *ctx, const double *in, int64_t n, double *out_accum, hipStream_t s) {
+  return reduce_f64<0>(ctx, in, n, 0.0, out_accum, 1, s);
+}
+int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, double *out, hipStream_t s) {
+  return reduce_f64<1>(ctx, in, n, init, out, 0, s);
+}
+
+// ------------------------------------------------------------ ABI: ctx ----
+extern "C" int abd_create(abd_ctx **out, int device) {
+  if (!out) return ABD_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return ABD_E_HIP;
+  if (device < 0 || device >= n) return ABD_E_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return ABD_E_HIP;
+  abd_ctx *c = new abd_ctx();
+  c->device = device;
+  for (auto &e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return ABD_E_HIP;
+    }
+  *out = c;
+  return ABD_OK;
+}
+
+extern "C" int abd_destroy(abd_ctx *ctx) {
+  if (!ctx) return ABD_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (auto &kv : ctx->bufs)
+    if (kv.second.ptr) hipFree(kv.second.ptr);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  for (auto &e : ctx->ev)
+    if (e) hipEventDestroy(e);
+  delete ctx;
+  return ABD_OK;
+}
+
+extern "C" const char *abd_last_error(const abd_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }

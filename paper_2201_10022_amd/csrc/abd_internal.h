@@ -1,0 +1,260 @@
+// Internal declarations of the gfx950 ABD library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/abd.h"
+
+// ------------------------------------------------------------ context ----
+
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct abd_ctx {
+  int device = 0;
+  std::string err;
+  std::map<std::string, DevBuf> bufs;
+  void *pinned = nullptr;  // small host staging area for scalar readbacks
+  size_t pinned_bytes = 0;
+  hipEvent_t ev[8] = {};
+};
+
+#define ABD_TRY(expr)                 \
+  do {                                \
+    int _rc = (expr);                 \
+    if (_rc != ABD_OK) return _rc;    \
+  } while (0)
+
+int abd_fail(abd_ctx *ctx, int code, const char *fmt, ...);
+int abd_hip_check(abd_ctx *ctx, hipError_t e, const char *what);
+#define HIP_TRY(ctx, expr) ABD_TRY(abd_hip_check((ctx), (expr), #expr))
+
+// Growable named device workspace.  Growing synchronises `stream` first so
+// that no queued kernel still reads the released memory.
+int ws_get(abd_ctx *ctx, const char *name, size_t bytes, void **out, hipStream_t stream);
+template <class T>
+int ws(abd_ctx *ctx, const char *name, size_t count, T **out, hipStream_t stream) {
+  return ws_get(ctx, name, count * sizeof(T) + 256, reinterpret_cast<void **>(out), stream);
+}
+int pinned_get(abd_ctx *ctx, size_t bytes, void **out);
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// ---------------------------------------------------- device-wide scan ----
+// Exclusive prefix sum of n int64 values (in != out allowed, or in-place);
+// total (device, may be NULL) receives the sum.
+int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s);
+// Stable sort of (key, value) pairs by key (keys in [0, 2^key_bits)).
+int sort_pairs_u32(abd_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, hipStream_t s);
+
+// ------------------------------------------------- internal operations ----
+// (shared by the ABI wrappers and the Newton driver)
+int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t s);
+int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1, double inflate,
+                  int32_t **pt, int64_t *n_pt, int32_t **ee, int64_t *n_ee, const char *tag, hipStream_t s);
+int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
+               int32_t **keys, int64_t *n_keys, const char *tag, hipStream_t s);
+int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
+               int64_t n_pt, const int32_t *ee, int64_t n_ee, const int32_t *keys, int64_t n_keys, double *energy,
+               double *grad, double *diag, double *off, int project, int64_t *n_active_pt, int64_t *n_active_ee,
+               hipStream_t s);
+int op_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
+                      int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy, hipStream_t s);
+int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x0, const double *dx,
+           const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *t_pt, double *t_ee,
+           double *alpha, hipStream_t s);
+int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
+                  double *energy, double *grad, double *diag, int project, hipStream_t s);
+int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
+                   double *energy, hipStream_t s);
+int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
+           int64_t n_keys, const double *rhs, double *p, double rtol, int max_iter, int *iters, hipStream_t s);
+int op_max_abs_disp(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s);
+int op_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,
+                     double *energy, double *grad, double *diag, int project, hipStream_t s);
+int op_inertia(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double *energy, double *grad,
+               double *diag, hipStream_t s);
+
+// ------------------------------------------- exact (set-deciding) math ----
+// Everything that decides a candidate or an active flag is evaluated with
+// fused multiply-add disabled and in a fixed operation order, so the result
+// is a pure function of the IEEE-754 inputs.
+struct d3 {
+  double x, y, z;
+};
+
+__host__ __device__ __forceinline__ d3 ld3(const double *p, int64_t i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+
+__host__ __device__ __forceinline__ d3 xsub(d3 a, d3 b) {
+#pragma clang fp contract(off)
+  return {a.x - b.x, a.y - b.y, a.z - b.z};
+}
+__host__ __device__ __forceinline__ double xdot(d3 a, d3 b) {
+#pragma clang fp contract(off)
+  return (a.x * b.x + a.y * b.y) + a.z * b.z;
+}
+__host__ __device__ __forceinline__ d3 xcross(d3 a, d3 b) {
+#pragma clang fp contract(off)
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+enum : int {
+  PT_PP0 = 0, PT_PP1 = 1, PT_PP2 = 2, PT_PE01 = 3, PT_PE12 = 4, PT_PE02 = 5, PT_FACE = 6,
+  EE_BASE = 16, EE_LL = 28
+};
+
+// Slots of each case. kind 0: point-point (i,j); 1: point-edge (i; j,k);
+// 2: point-face (0; 1,2,3); 3: line-line (0,1; 2,3)
+struct CaseSlots {
+  int kind, i, j, k;
+};
+__host__ __device__ __forceinline__ CaseSlots case_slots(int type) {
+  switch (type) {
+    case PT_PP0: return {0, 0, 1, -1};
+    case PT_PP1: return {0, 0, 2, -1};
+    case PT_PP2: return {0, 0, 3, -1};
+    case PT_PE01: return {1, 0, 1, 2};
+    case PT_PE12: return {1, 0, 2, 3};
+    case PT_PE02: return {1, 0, 1, 3};
+    case PT_FACE: return {2, 0, 1, 2};
+    case EE_LL: return {3, 0, 1, 2};
+    default: break;
+  }
+  const int k = (type - EE_BASE) / 3, c = (type - EE_BASE) % 3;
+  const int e0 = k < 2 ? 2 : 0, e1 = k < 2 ? 3 : 1;
+  if (c == 0) return {0, k, e0, -1};
+  if (c == 1) return {0, k, e1, -1};
+  return {1, k, e0, e1};
+}
+
+// squared distance of a case as num/den
+__host__ __device__ __forceinline__ void case_nd(int type, const d3 X[4], double &num, double &den) {
+#pragma clang fp contract(off)
+  const CaseSlots c = case_slots(type);
+  if (c.kind == 0) {
+    d3 d = xsub(X[c.i], X[c.j]);
+    num = xdot(d, d);
+    den = 1.0;
+  } else if (c.kind == 1) {
+    d3 e = xsub(X[c.k], X[c.j]);
+    d3 cr = xcross(xsub(X[c.i], X[c.j]), e);
+    num = xdot(cr, cr);
+    den = xdot(e, e);
+  } else if (c.kind == 2) {
+    d3 n = xcross(xsub(X[2], X[1]), xsub(X[3], X[1]));
+    double h = xdot(xsub(X[0], X[1]), n);
+    num = h * h;
+    den = xdot(n, n);
+  } else {
+    d3 n = xcross(xsub(X[1], X[0]), xsub(X[3], X[2]));
+    double h = xdot(xsub(X[2], X[0]), n);
+    num = h * h;
+    den = xdot(n, n);
+  }
+}
+
+// Point-triangle case from the Voronoi regions of the triangle (sign tests
+// of dot products; vertices before edges before the face on ties).
+__host__ __device__ __forceinline__ int classify_pt(d3 p, d3 t0, d3 t1, d3 t2) {
+#pragma clang fp contract(off)
+  d3 ab = xsub(t1, t0), ac = xsub(t2, t0), ap = xsub(p, t0);
+  double d1 = xdot(ab, ap), d2 = xdot(ac, ap);
+  if (d1 <= 0.0 && d2 <= 0.0) return PT_PP0;
+  d3 bp = xsub(p, t1);
+  double d3v = xdot(ab, bp), d4 = xdot(ac, bp);
+  if (d3v >= 0.0 && d4 <= d3v) return PT_PP1;
+  double vc = d1 * d4 - d3v * d2;
+  if (vc <= 0.0 && d1 >= 0.0 && d3v <= 0.0) return PT_PE01;
+  d3 cp = xsub(p, t2);
+  double d5 = xdot(ab, cp), d6 = xdot(ac, cp);
+  if (d6 >= 0.0 && d5 <= d6) return PT_PP2;
+  double vb = d5 * d2 - d1 * d6;
+  if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) return PT_PE02;
+  double va = d3v * d6 - d5 * d4;
+  if (va <= 0.0 && (d4 - d3v) >= 0.0 && (d5 - d6) >= 0.0) return PT_PE12;
+  return PT_FACE;
+}
+
+// Edge-edge case: line-line when the lines' closest points are strictly
+// inside both segments and the edges are not parallel; otherwise the
+// smallest of the four endpoint-vs-segment distances (division-free
+// comparison, first minimum wins).
+__host__ __device__ __forceinline__ int classify_ee(const d3 X[4]) {
+#pragma clang fp contract(off)
+  d3 u = xsub(X[1], X[0]), v = xsub(X[3], X[2]), w = xsub(X[0], X[2]);
+  double a = xdot(u, u), b = xdot(u, v), c = xdot(v, v), d = xdot(u, w), e = xdot(v, w);
+  d3 n = xcross(u, v);
+  double nn = xdot(n, n);
+  double D = a * c - b * b;
+  double sN = b * e - c * d, tN = a * e - b * d;
+  if (nn > (1e-20 * a) * c && sN > 0.0 && sN < D && tN > 0.0 && tN < D) return EE_LL;
+  int best = -1;
+  double bn = 0.0, bd = 1.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const d3 P = X[k], E0 = X[k < 2 ? 2 : 0], E1 = X[k < 2 ? 3 : 1];
+    d3 ev = xsub(E1, E0);
+    double tn = xdot(xsub(P, E0), ev);
+    int sub = tn <= 0.0 ? 0 : (tn >= xdot(ev, ev) ? 1 : 2);
+    const int type = EE_BASE + 3 * k + sub;
+    double num, den;
+    case_nd(type, X, num, den);
+    if (best < 0 || num * bd < bn * den) {
+      best = type;
+      bn = num;
+      bd = den;
+    }
+  }
+  return best;
+}
+
+__host__ __device__ __forceinline__ void pair_vids(int is_ee, const int32_t *pr, const int32_t *tris, const int32_t *edges,
+                                          int vid[4]) {
+  if (!is_ee) {
+    const int t = pr[1];
+    vid[0] = pr[0];
+    vid[1] = tris[3 * t];
+    vid[2] = tris[3 * t + 1];
+    vid[3] = tris[3 * t + 2];
+  } else {
+    vid[0] = edges[2 * pr[0]];
+    vid[1] = edges[2 * pr[0] + 1];
+    vid[2] = edges[2 * pr[1]];
+    vid[3] = edges[2 * pr[1] + 1];
+  }
+}
+
+__host__ __device__ __forceinline__ int classify_pair(int is_ee, const d3 X[4]) {
+  return is_ee ? classify_ee(X) : classify_pt(X[0], X[1], X[2], X[3]);
+}
+
+// ------------------------------------------------------ reductions ----
+// Wave-level (64 lanes) sums via cross-lane moves; the lane order of the
+// tree is fixed, so results are run-to-run reproducible.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Deterministic device-wide sums: per-block partials then one block folds them.
+int reduce_sum_f64(abd_ctx *ctx, const double *in, int64_t n, double *out_accum, hipStream_t s);
+int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, double *out, hipStream_t s);

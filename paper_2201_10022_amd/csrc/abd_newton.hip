@@ -1,0 +1,239 @@
+// Newton iteration and implicit-Euler time step (ABD sec. 4: minimise the
+// incremental potential E = sum_b E_b + V_C; sec. 4.1: CCD at every
+// iteration keeps the line search intersection free).  Host orchestration of
+// the device operations; scalars cross to the host only where a decision is
+// taken (counts, convergence, step bound, line-search comparison).
+#include <chrono>
+#include <cmath>
+
+#include "abd_internal.h"
+
+namespace {
+
+__global__ void k_axpy(int n, const double *a, double alpha, const double *b, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + alpha * b[i];
+}
+__global__ void k_neg(int n, const double *a, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = -a[i];
+}
+__global__ void k_sub(int n, const double *a, const double *b, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+__global__ void k_velocity(int n, const uint8_t *fixed, const double *qn, const double *qo, double inv_dt,
+                           double *qd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  qd[i] = fixed[i / 12] ? 0.0 : (qn[i] - qo[i]) * inv_dt;
+}
+__global__ void k_zero(int64_t n, double *a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
+int zero(abd_ctx *ctx, double *a, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_zero, dim3(grid_for(n, 256)), dim3(256), 0, s, n, a);
+  return abd_hip_check(ctx, hipGetLastError(), "k_zero");
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int read_err(abd_ctx *ctx, hipStream_t s) {
+  int *err, *h;
+  ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
+  HIP_TRY(ctx, hipMemcpyAsync(h, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  const int e = h[0];
+  if (e) HIP_TRY(ctx, hipMemsetAsync(err, 0, sizeof(int), s));
+  if (e & 1) return abd_fail(ctx, ABD_E_INTERSECT, "pair at zero distance");
+  if (e & 2) return abd_fail(ctx, ABD_E_INVALID, "pair's body pair missing from the off-diagonal keys");
+  if (e & 4) return abd_fail(ctx, ABD_E_PCG, "diagonal block not positive definite");
+  if (e & 8) return abd_fail(ctx, ABD_E_PCG, "PCG breakdown (non-positive curvature)");
+  return ABD_OK;
+}
+
+// E(q) over the given (swept) candidates; result in *h (host)
+int energy_at(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
+              double *x, const int32_t *pt, int64_t npt, const int32_t *ee, int64_t nee, double *e_dev, double *out,
+              hipStream_t s) {
+  ABD_TRY(zero(ctx, e_dev, 1, s));
+  ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
+  ABD_TRY(op_body_energy(ctx, sc, prm, q, qt, e_dev, s));
+  ABD_TRY(op_barrier_energy(ctx, sc, prm, x, pt, npt, ee, nee, e_dev, s));
+  double *h;
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
+  HIP_TRY(ctx, hipMemcpyAsync(h + 2, e_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  *out = h[2];
+  return ABD_OK;
+}
+
+}  // namespace
+
+int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, const double *qt,
+                     abd_stats *st, hipStream_t s) {
+  auto t_all = std::chrono::steady_clock::now();
+  const int nb = sc->n_bodies, nv = sc->n_verts;
+  const int n12 = 12 * nb;
+  double *x, *x1, *dx, *g, *diag, *off, *p, *qa, *e;
+  ABD_TRY(ws(ctx, "nt_x", 3 * (size_t)nv, &x, s));
+  ABD_TRY(ws(ctx, "nt_x1", 3 * (size_t)nv, &x1, s));
+  ABD_TRY(ws(ctx, "nt_dx", 3 * (size_t)nv, &dx, s));
+  ABD_TRY(ws(ctx, "nt_g", n12, &g, s));
+  ABD_TRY(ws(ctx, "nt_diag", 144 * (size_t)nb, &diag, s));
+  ABD_TRY(ws(ctx, "nt_p", n12, &p, s));
+  ABD_TRY(ws(ctx, "nt_qa", n12, &qa, s));
+  ABD_TRY(ws(ctx, "nt_e", 4, &e, s));
+  double *h;
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
+
+  // gradient and projected Hessian at q
+  auto t0 = std::chrono::steady_clock::now();
+  ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
+  int32_t *pt, *ee, *keys;
+  int64_t npt, nee, nk;
+  ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s));
+  ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", s));
+  st->n_pt = npt;
+  st->n_ee = nee;
+  st->n_offdiag = nk;
+  st->t_candidates_ms += ms_since(t0);
+  ABD_TRY(ws(ctx, "nt_off", 144 * (size_t)(nk + 1), &off, s));
+  ABD_TRY(zero(ctx, g, n12, s));
+  ABD_TRY(zero(ctx, diag, 144 * (int64_t)nb, s));
+  ABD_TRY(zero(ctx, off, 144 * nk, s));
+  ABD_TRY(zero(ctx, e, 1, s));
+  t0 = std::chrono::steady_clock::now();
+  ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, e, g, diag, 1, s));
+  int64_t nap = 0, nae = 0;
+  ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 1, &nap, &nae, s));
+  ABD_TRY(read_err(ctx, s));
+  st->t_barrier_ms += ms_since(t0);
+  st->n_active_pt = nap;
+  st->n_active_ee = nae;
+
+  // Newton direction
+  t0 = std::chrono::steady_clock::now();
+  double *rhs;
+  ABD_TRY(ws(ctx, "nt_rhs", n12, &rhs, s));
+  hipLaunchKernelGGL(k_neg, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, g, rhs);
+  int its = 0;
+  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s));
+  ABD_TRY(read_err(ctx, s));
+  st->pcg_iters = its;
+  st->t_solve_ms += ms_since(t0);
+  ABD_TRY(op_max_abs_disp(ctx, sc, p, e + 1, s));
+  HIP_TRY(ctx, hipMemcpyAsync(h, e + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  st->disp = h[0];
+  if (!(std::isfinite(h[0]))) return abd_fail(ctx, ABD_E_PCG, "non-finite Newton direction");
+  if (h[0] <= prm->newton_tol * prm->dt) {
+    st->converged = 1;
+    st->alpha = 0.0;
+    st->t_total_ms += ms_since(t_all);
+    return ABD_OK;
+  }
+  st->converged = 0;
+
+  // CCD over the swept candidates of x(q) -> x(q + p)
+  t0 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, q, 1.0, p, qa);
+  ABD_TRY(op_vertex_map(ctx, sc, qa, x1, s));
+  int32_t *spt, *see;
+  int64_t nspt, nsee;
+  ABD_TRY(op_candidates(ctx, sc, x, x1, prm->dhat, &spt, &nspt, &see, &nsee, "nt_sw", s));
+  st->n_pt_swept = nspt;
+  st->n_ee_swept = nsee;
+  st->t_candidates_ms += ms_since(t0);
+  t0 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(3 * nv, 256)), dim3(256), 0, s, 3 * nv, x1, x, dx);
+  ABD_TRY(op_ccd(ctx, sc, prm, x, dx, spt, nspt, see, nsee, nullptr, nullptr, e + 2, s));
+  HIP_TRY(ctx, hipMemcpyAsync(h, e + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  st->t_ccd_ms += ms_since(t0);
+  double alpha = h[0];
+  st->alpha_ccd = alpha;
+
+  // backtracking line search
+  double e0, e1 = 0.0;
+  ABD_TRY(energy_at(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, e + 3, &e0, s));
+  int k = 0;
+  for (; k < prm->max_ls; ++k) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, q, alpha, p, qa);
+    ABD_TRY(energy_at(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, e + 3, &e1, s));
+    if (e1 <= e0) break;
+    alpha *= 0.5;
+  }
+  if (k == prm->max_ls) return abd_fail(ctx, ABD_E_LINESEARCH, "line search found no decrease");
+  st->ls_halvings = k;
+  st->alpha = alpha;
+  st->energy0 = e0;
+  st->energy1 = e1;
+  HIP_TRY(ctx, hipMemcpyAsync(q, qa, sizeof(double) * n12, hipMemcpyDeviceToDevice, s));
+  st->t_total_ms += ms_since(t_all);
+  return ABD_OK;
+}
+
+extern "C" int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q,
+                               const double *q_tilde, abd_stats *stats, hipStream_t stream) {
+  if (!ctx || !sc || !prm || !q || !q_tilde || !sc->mass || !sc->volume)
+    return abd_fail(ctx, ABD_E_INVALID, "abd_newton_step: null");
+  abd_stats local = {};
+  abd_stats *st = stats ? stats : &local;
+  *st = abd_stats{};
+  ABD_TRY(newton_iteration(ctx, sc, prm, q, q_tilde, st, stream));
+  st->newton_iters = 1;
+  return ABD_OK;
+}
+
+extern "C" int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot,
+                             abd_stats *stats, hipStream_t stream) {
+  if (!ctx || !sc || !prm || !q || !qdot || !sc->mass || !sc->volume)
+    return abd_fail(ctx, ABD_E_INVALID, "abd_time_step: null");
+  const int n12 = 12 * sc->n_bodies;
+  double *qt, *qo;
+  ABD_TRY(ws(ctx, "ts_qt", n12, &qt, stream));
+  ABD_TRY(ws(ctx, "ts_qo", n12, &qo, stream));
+  ABD_TRY(abd_q_tilde(ctx, sc, prm, q, qdot, qt, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(qo, q, sizeof(double) * n12, hipMemcpyDeviceToDevice, stream));
+  abd_stats total = {};
+  int it = 0;
+  bool conv = false;
+  for (; it < prm->max_newton; ++it) {
+    abd_stats st = {};
+    ABD_TRY(newton_iteration(ctx, sc, prm, q, qt, &st, stream));
+    total.n_pt = st.n_pt;
+    total.n_ee = st.n_ee;
+    total.n_active_pt += st.n_active_pt;
+    total.n_active_ee += st.n_active_ee;
+    total.n_pt_swept += st.n_pt_swept;
+    total.n_ee_swept += st.n_ee_swept;
+    total.n_offdiag = st.n_offdiag;
+    total.pcg_iters += st.pcg_iters;
+    total.ls_halvings += st.ls_halvings;
+    total.t_barrier_ms += st.t_barrier_ms;
+    total.t_ccd_ms += st.t_ccd_ms;
+    total.t_candidates_ms += st.t_candidates_ms;
+    total.t_solve_ms += st.t_solve_ms;
+    total.t_total_ms += st.t_total_ms;
+    total.disp = st.disp;
+    if (st.converged) {
+      conv = true;
+      break;
+    }
+    total.alpha_ccd = st.alpha_ccd;
+    total.alpha = st.alpha;
+  }
+  total.newton_iters = it + 1;
+  total.converged = conv ? 1 : 0;
+  if (stats) *stats = total;
+  if (!conv) return abd_fail(ctx, ABD_E_NOT_CONVERGED, "Newton did not converge in %d iterations", prm->max_newton);
+  hipLaunchKernelGGL(k_velocity, dim3(grid_for(n12, 256)), dim3(256), 0, stream, n12, sc->body_fixed, q, qo,
+                     1.0 / prm->dt, qdot);
+  return abd_hip_check(ctx, hipGetLastError(), "k_velocity");
+}

@@ -221,6 +221,16 @@ int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, do
 int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot,
                   abd_stats *stats, hipStream_t stream);
 
+/* Kernel timing with HIP events on the calls' streams, for measurement:
+ * abd_profile(enable, reset) switches recording on/off (reset clears the
+ * totals); abd_profile_query returns, for one instrumented kernel
+ * ("barrier_local", "assemble_chunks", "energy_only", "accd",
+ * "pair_tiles_write", "spmv"), the summed duration in ms, the number of
+ * launches and the work units processed (pairs, records, tiles, block rows).
+ * Query synchronises the device. */
+int abd_profile(abd_ctx *ctx, int enable, int reset);
+int abd_profile_query(abd_ctx *ctx, const char *kernel, double *ms, int64_t *launches, int64_t *units);
+
 #ifdef __cplusplus
 }
 #endif

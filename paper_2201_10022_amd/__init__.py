@@ -241,6 +241,16 @@ class Context:
                                          ctypes.byref(st), _stream()))
         return st.as_dict()
 
+    # -- measurement ---------------------------------------------------
+    def profile(self, enable=True, reset=True):
+        self._check(self.L.abd_profile(self.h, int(enable), int(reset)))
+
+    def profile_query(self, kernel):
+        ms, la, un = ctypes.c_double(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self.L.abd_profile_query(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(la),
+                                             ctypes.byref(un)))
+        return dict(ms=ms.value, launches=la.value, units=un.value)
+
 
 def setup(S, device=0):
     """Context + device scene with mass properties computed on the GPU."""

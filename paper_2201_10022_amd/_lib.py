@@ -13,7 +13,7 @@ ERRORS = {-1: "ABD_E_INVALID", -2: "ABD_E_CAPACITY", -3: "ABD_E_INTERSECT", -4: 
 EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_body_mass", "abd_vertex_map", "abd_candidates",
            "abd_offdiag_pattern", "abd_classify", "abd_barrier_grad_hess", "abd_barrier_energy",
            "abd_ccd_max_step", "abd_orthogonality", "abd_inertia", "abd_q_tilde", "abd_pcg_solve",
-           "abd_newton_step", "abd_time_step"]
+           "abd_newton_step", "abd_time_step", "abd_profile", "abd_profile_query"]
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -71,6 +71,8 @@ SIGNATURES = {
     "abd_pcg_solve": ([_vp, _PS, _vp, _vp, _vp, _i64, _vp, _vp, _dbl, _i32, _pi32, _vp], ctypes.c_int),
     "abd_newton_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
     "abd_time_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
+    "abd_profile": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "abd_profile_query": ([_vp, ctypes.c_char_p, ctypes.POINTER(_dbl), _pi64, _pi64], ctypes.c_int),
 }
 
 _LIB = None

@@ -357,12 +357,14 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   std::string tpt_name = std::string(tag) + "_pt", tee_name = std::string(tag) + "_ee";
   ABD_TRY(ws(ctx, tpt_name.c_str(), 2 * (*n_pt) + 2, pt_out, s));
   ABD_TRY(ws(ctx, tee_name.c_str(), 2 * (*n_ee) + 2, ee_out, s));
+  hipEvent_t pe = prof_begin(ctx, s);
   if (ntile_pt && *n_pt)
     hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, 2 * nbp, tpt_off, ntile_pt,
                        lstart, llen, lists, vbox, tbox, nullptr, opt, *pt_out);
   if (ntile_ee && *n_ee)
     hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, nbp, tee_off, ntile_ee, lstart,
                        llen, lists, ebox, ebox, nullptr, oee, *ee_out);
+  prof_end(ctx, pe, "pair_tiles_write", ntile_pt + ntile_ee, s);
   return abd_hip_check(ctx, hipGetLastError(), "candidates");
 }
 

@@ -97,10 +97,12 @@ int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const doubl
   const int ns = sc->n_scenes > 0 ? sc->n_scenes : 1;
   if (alpha) hipLaunchKernelGGL(k_fill, dim3(grid_for(ns, 256)), dim3(256), 0, s, alpha, ns, 1.0);
   const int64_t n = n_pt + n_ee;
+  hipEvent_t pe = n > 0 ? prof_begin(ctx, s) : nullptr;
   if (n > 0)
     hipLaunchKernelGGL(k_accd, dim3(grid_for(n, 128)), dim3(128), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges,
                        sc->vert_body, sc->body_scene, x0, dx, prm->ccd_s, prm->ccd_tmax, prm->ccd_max_iter, t_pt,
                        t_ee, alpha);
+  prof_end(ctx, pe, "accd", n, s);
   return abd_hip_check(ctx, hipGetLastError(), "k_accd");
 }
 

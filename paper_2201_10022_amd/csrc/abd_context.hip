@@ -155,6 +155,67 @@ int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, doubl
   return reduce_f64<1>(ctx, in, n, init, out, 0, s);
 }
 
+// ----------------------------------------------------------- profiling ----
+static hipEvent_t pool_get(abd_ctx *ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+hipEvent_t prof_begin(abd_ctx *ctx, hipStream_t s) {
+  if (!ctx->profiling) return nullptr;
+  hipEvent_t a = pool_get(ctx);
+  if (a) hipEventRecord(a, s);
+  return a;
+}
+
+void prof_end(abd_ctx *ctx, hipEvent_t a, const char *name, int64_t units, hipStream_t s) {
+  if (!a) return;
+  hipEvent_t b = pool_get(ctx);
+  if (!b) return;
+  hipEventRecord(b, s);
+  ctx->pending.push_back({a, b, name, units});
+}
+
+void prof_flush(abd_ctx *ctx) {
+  for (auto &p : ctx->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      KStat &k = ctx->kstats[p.name];
+      k.ms += ms;
+      k.launches += 1;
+      k.units += p.units;
+    }
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+extern "C" int abd_profile(abd_ctx *ctx, int enable, int reset) {
+  if (!ctx) return ABD_E_INVALID;
+  prof_flush(ctx);
+  if (reset) ctx->kstats.clear();
+  ctx->profiling = enable != 0;
+  return ABD_OK;
+}
+
+extern "C" int abd_profile_query(abd_ctx *ctx, const char *kernel, double *ms, int64_t *launches, int64_t *units) {
+  if (!ctx || !kernel || !ms || !launches || !units) return abd_fail(ctx, ABD_E_INVALID, "abd_profile_query: null");
+  hipDeviceSynchronize();
+  prof_flush(ctx);
+  auto it = ctx->kstats.find(kernel);
+  *ms = it == ctx->kstats.end() ? 0.0 : it->second.ms;
+  *launches = it == ctx->kstats.end() ? 0 : it->second.launches;
+  *units = it == ctx->kstats.end() ? 0 : it->second.units;
+  return ABD_OK;
+}
+
 // ------------------------------------------------------------ ABI: ctx ----
 extern "C" int abd_create(abd_ctx **out, int device) {
   if (!out) return ABD_E_INVALID;
@@ -183,6 +244,8 @@ extern "C" int abd_destroy(abd_ctx *ctx) {
   if (ctx->pinned) hipHostFree(ctx->pinned);
   for (auto &e : ctx->ev)
     if (e) hipEventDestroy(e);
+  prof_flush(ctx);
+  for (auto &e : ctx->ev_pool) hipEventDestroy(e);
   delete ctx;
   return ABD_OK;
 }

@@ -18,6 +18,19 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Per-kernel timing with HIP events (enabled by abd_profile): event pairs
+// are recorded around instrumented launches and resolved at the next host
+// synchronisation, so profiling adds no synchronisation of its own.
+struct KStat {
+  double ms = 0.0;
+  int64_t launches = 0, units = 0;
+};
+struct PendingEv {
+  hipEvent_t a, b;
+  std::string name;
+  int64_t units;
+};
+
 struct abd_ctx {
   int device = 0;
   std::string err;
@@ -25,7 +38,18 @@ struct abd_ctx {
   void *pinned = nullptr;  // small host staging area for scalar readbacks
   size_t pinned_bytes = 0;
   hipEvent_t ev[8] = {};
+  bool profiling = false;
+  std::map<std::string, KStat> kstats;
+  std::vector<PendingEv> pending;
+  std::vector<hipEvent_t> ev_pool;
 };
+
+// instrumentation: prof_begin returns an event recorded before the launch
+// (or null when profiling is off); prof_end records the end event and
+// queues the pair; prof_flush resolves queued pairs (call after a sync).
+hipEvent_t prof_begin(abd_ctx *ctx, hipStream_t s);
+void prof_end(abd_ctx *ctx, hipEvent_t a, const char *name, int64_t units, hipStream_t s);
+void prof_flush(abd_ctx *ctx);
 
 #define ABD_TRY(expr)                 \
   do {                                \

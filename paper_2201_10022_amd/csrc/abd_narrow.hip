@@ -376,9 +376,11 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   ABD_TRY(ws(ctx, "br_g", 12 * na, &g_loc, s));
   ABD_TRY(ws(ctx, "br_H", 78 * na, &H_loc, s));
   ABD_TRY(ws(ctx, "br_info", na, &info, s));
+  hipEvent_t pe = prof_begin(ctx, s);
   hipLaunchKernelGGL(k_barrier_local, dim3(grid_for(na, 64)), dim3(64), 0, s, nact, act, n_pt, pt, ee, sc->tris,
                      sc->edges, sc->vert_body, x, sc->xbar, dhat, prm->kappa_b, project, e_loc, g_loc, H_loc, info,
                      err);
+  prof_end(ctx, pe, "barrier_local", na, s);
   HIP_TRY(ctx, hipGetLastError());
   if (energy) ABD_TRY(reduce_sum_f64(ctx, e_loc, na, energy, s));
   if (!grad && !diag && !off) return ABD_OK;
@@ -405,8 +407,10 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   const int64_t max_chunks = (nrec + RCH - 1) / RCH + nblocks;
   double *partial;
   ABD_TRY(ws(ctx, "br_partial", (size_t)NENT * max_chunks, &partial, s));
+  pe = prof_begin(ctx, s);
   hipLaunchKernelGGL(k_assemble_chunks, dim3((unsigned)max_chunks), dim3(64), 0, s, nblocks, choff, nch_tot, bstart,
                      rval, info, g_loc, H_loc, sc->xbar, partial);
+  prof_end(ctx, pe, "assemble_chunks", nrec, s);
   hipLaunchKernelGGL(k_assemble_final, dim3(grid_for(nblocks * NENT, 256)), dim3(256), 0, s, nblocks, nb, choff, nchunk,
                      partial, keys, grad, diag, off);
   return abd_hip_check(ctx, hipGetLastError(), "barrier assemble");
@@ -418,8 +422,10 @@ int op_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, 
   if (n == 0) return ABD_OK;
   double *e;
   ABD_TRY(ws(ctx, "be_e", n, &e, s));
+  hipEvent_t pe = prof_begin(ctx, s);
   hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, 256)), dim3(256), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges, x,
                      sc->xbar, prm->dhat, prm->kappa_b, e);
+  prof_end(ctx, pe, "energy_only", n, s);
   HIP_TRY(ctx, hipGetLastError());
   return reduce_sum_f64(ctx, e, n, energy, s);
 }

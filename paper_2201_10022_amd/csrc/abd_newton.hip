@@ -176,6 +176,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->energy1 = e1;
   HIP_TRY(ctx, hipMemcpyAsync(q, qa, sizeof(double) * n12, hipMemcpyDeviceToDevice, s));
   st->t_total_ms += ms_since(t_all);
+  prof_flush(ctx);
   return ABD_OK;
 }
 

@@ -333,8 +333,10 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   int it = 0;
   for (; it < max_iter;) {
     for (int k = 0; k < CHECK && it < max_iter; ++k, ++it) {
+      hipEvent_t pe = prof_begin(ctx, s);
       hipLaunchKernelGGL(k_spmv, dim3(nblk), dim3(SB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2, lo_beg, hi_beg,
                          p, Ap, part);
+      prof_end(ctx, pe, "spmv", nb + 2 * n_keys, s);
       hipLaunchKernelGGL(k_fold_alpha, dim3(1), dim3(64), 0, s, part, nblk, scal, err);
       hipLaunchKernelGGL(k_update_xr, dim3(nblk), dim3(SB), 0, s, nb, inv, p, Ap, p_out, r, z, scal, part2);
       hipLaunchKernelGGL(k_fold_beta, dim3(1), dim3(64), 0, s, part2, nblk, scal);

@@ -171,7 +171,11 @@ def icosphere_box(seed=2, n_side=10, n_layers=10, spacing=0.25, friction=0.5):
                 p = np.array([x0 + spacing * i, 0.3 + spacing * j, x0 + spacing * k]) + jit
                 sb.add(sv * r, st, R=R, p=p)
     scene = sb.build()
-    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=0.33, mu=friction, steps=200)
+    # kappa_b: a 4 kg sphere landing at 2 m/s is stopped near dhat/2
+    # (kappa |B'(dhat/2)| = m v dt); Newton tolerance 1e-2 of the box
+    # diagonal per second (IPC's convention)
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=70.0, mu=friction, steps=200,
+                            newton_tol=1e-2 * math.sqrt(3.0) * 2.6, max_newton=500, pcg_rtol=1e-4)
     return scene, params
 
 
@@ -252,6 +256,22 @@ def adjoint_drop(seed=5):
     target = np.array([rng.uniform(-1.2, 1.2), rng.uniform(0.1, 0.5), rng.uniform(-1.2, 1.2)])
     params = dict(params, steps=100, checkpoint_every=10)
     return scene, params, target
+
+
+def icosphere_resting_layer(seed=2, dhat=1e-3):
+    """The bottom layer (10x10) of the icosphere box drop with each sphere
+    lowered until its lowest mesh vertex sits U[0.2,0.8] dhat above the
+    floor: a contact sample of the same workload.  Draw order: as
+    icosphere_box for the 100 spheres, then one height fraction per sphere."""
+    scene, params = icosphere_box(seed=seed, n_layers=1)
+    rng = np.random.default_rng(seed + 77)
+    q = scene["q0"]
+    for b in range(1, len(q)):
+        sl = slice(scene["body_vert_off"][b], scene["body_vert_off"][b + 1])
+        A = q[b, 3:].reshape(3, 3)
+        low = (scene["xbar"][sl] @ A.T)[:, 1].min()
+        q[b, 1] = rng.uniform(0.2, 0.8) * dhat - low
+    return scene, params
 
 
 CONFIGS = {

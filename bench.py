@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size (for counter calibration) before timing")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--start-at", type=float, default=0.0,
+                    help="start the timed steps this many seconds after process start (so a profiler's "
+                         "collection period can cover exactly the timed steps)")
     return ap.parse_args()
 
 
@@ -123,6 +126,12 @@ def main():
         del a, b
     ctx.profile(True, reset=True)
     torch.cuda.synchronize()
+    if args.start_at > 0:
+        import psutil
+        wait = args.start_at - (time.time() - psutil.Process().create_time())
+        if wait < 0:
+            log(args, f"--start-at {args.start_at}: already {-wait:.1f} s late")
+        time.sleep(max(wait, 0.0))
     tot = dict(newton=0, active=0, ccd=0, pcg=0)
     t0 = time.perf_counter()
     for i in range(args.steps):

@@ -62,7 +62,7 @@ def lib():
                                          ctypes.c_double, ctypes.c_double, _int]
         L.ora_barrier_energy.restype = ctypes.c_double
         L.ora_ccd.argtypes = [ctypes.c_int64, ctypes.c_int, _i32, _i32, _i32, _d, _d, ctypes.c_double,
-                              ctypes.c_double, ctypes.c_int, _d]
+                              ctypes.c_double, ctypes.c_int, _d, _i32]
         L.ora_orthogonality.argtypes = [ctypes.c_int, _u8, _d, _d, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int, _d, _d, _d]
         L.ora_orthogonality_energy.argtypes = [ctypes.c_int, _u8, _d, _d, ctypes.c_double, ctypes.c_double]
@@ -243,17 +243,21 @@ def barrier_energy(S, x, pt, ee, params):
     return tot
 
 
-def ccd(S, x, dx, pt, ee, params):
-    """Per-pair additive-CCD safe fractions and alpha_max = min(1, min t)."""
+def ccd(S, x, dx, pt, ee, params, iters=None):
+    """Per-pair additive-CCD safe fractions and alpha_max = min(1, min t).
+    If `iters` is a list, the per-pair advance counts are appended to it."""
     out = []
     for is_ee, pairs in ((0, pt), (1, ee)):
         t = np.ones(len(pairs)) * params["ccd_tmax"]
+        it = np.zeros(len(pairs), np.int32)
         if len(pairs):
             lib().ora_ccd(len(pairs), is_ee, _p(_c(pairs, np.int32), _i32), _p(_c(S["tris"], np.int32), _i32),
                           _p(_c(S["edges"], np.int32), _i32), _p(_c(x, np.float64), _d),
                           _p(_c(dx, np.float64), _d), float(params["ccd_s"]), float(params["ccd_tmax"]),
-                          int(params["ccd_max_iter"]), _p(t, _d))
+                          int(params["ccd_max_iter"]), _p(t, _d), _p(it, _i32))
         out.append(t)
+        if iters is not None:
+            iters.append(it)
     alpha = min([1.0] + [float(t.min()) for t in out if len(t)])
     return out[0], out[1], alpha
 

@@ -748,7 +748,8 @@ double ora_barrier_energy(int64_t n, int is_ee, const int32_t* pairs, const int3
 // below s d0 (the last safe t is returned) or t exceeds tmax (tmax is
 // returned).  A capped iteration count returns the current (safe) t.
 void ora_ccd(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, const int32_t* edges,
-             const double* x, const double* dx, double s, double tmax, int max_iter, double* tout) {
+             const double* x, const double* dx, double s, double tmax, int max_iter, double* tout,
+             int32_t* iters_out) {
   for (int64_t i = 0; i < n; ++i) {
     int vid[4];
     pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
@@ -769,6 +770,7 @@ void ora_ccd(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, co
       lp = len[0] + std::max(len[1], std::max(len[2], len[3]));
     else
       lp = std::max(len[0], len[1]) + std::max(len[2], len[3]);
+    if (iters_out) iters_out[i] = 0;
     if (lp == 0.0) {
       tout[i] = tmax;
       continue;
@@ -794,6 +796,7 @@ void ora_ccd(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, co
       tl = 0.9 * d / lp;
     }
     tout[i] = t;
+    if (iters_out) iters_out[i] = it;
   }
 }
 

@@ -30,102 +30,143 @@ __host__ __device__ __forceinline__ d3 lin(d3 a, double fa, d3 b, double fb) {
   return {fa * a.x + fb * b.x, fa * a.y + fb * b.y, fa * a.z + fb * b.z};
 }
 
-__host__ __device__ inline void case_deriv(int type, const d3 X[4], CaseDeriv &cd) {
-  const CaseSlots cs = case_slots(type);
+__host__ __device__ __forceinline__ void deriv_clear(CaseDeriv &cd) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) cd.w[k] = 0.0;
 #pragma unroll
   for (int i = 0; i < 12; ++i) cd.C[0][i] = cd.C[1][i] = 0.0;
   cd.Gi[0] = cd.Gi[1] = cd.Gi[2] = 0.0;
-  if (cs.kind == 0) {  // point-point
-    const d3 r = xsub(X[cs.i], X[cs.j]);
-    cd.w[cs.i] = 1.0;
-    cd.w[cs.j] = -1.0;
-    cd.r[0] = r.x, cd.r[1] = r.y, cd.r[2] = r.z;
-    cd.nc = 0;
-  } else if (cs.kind == 1) {  // point-edge: r = x_i - x_j - t e
-    const d3 e = xsub(X[cs.k], X[cs.j]);
-    const d3 dp = xsub(X[cs.i], X[cs.j]);
-    const double ee = e.x * e.x + e.y * e.y + e.z * e.z;
-    const double t = (dp.x * e.x + dp.y * e.y + dp.z * e.z) / ee;
-    // r = dp - t e written as e x (dp x e) / |e|^2 (no cancellation)
-    const d3 rc = xcross(e, xcross(dp, e));
-    const d3 r = {rc.x / ee, rc.y / ee, rc.z / ee};
-    cd.w[cs.i] = 1.0;
-    cd.w[cs.j] = -(1.0 - t);
-    cd.w[cs.k] = -t;
-    cd.r[0] = r.x, cd.r[1] = r.y, cd.r[2] = r.z;
-    cd.nc = 1;
-    set3(cd.C[0], cs.i, e, -2.0);
-    set3(cd.C[0], cs.j, lin(e, 1.0 - t, r, 1.0), 2.0);
-    set3(cd.C[0], cs.k, lin(e, t, r, -1.0), 2.0);
-    cd.Gi[0] = 1.0 / (2.0 * ee);
-  } else if (cs.kind == 2) {  // point-face: r = p - t0 - u e1 - v e2
-    const d3 e1 = xsub(X[2], X[1]), e2 = xsub(X[3], X[1]), dp = xsub(X[0], X[1]);
-    const double a = e1.x * e1.x + e1.y * e1.y + e1.z * e1.z;
-    const double b = e1.x * e2.x + e1.y * e2.y + e1.z * e2.z;
-    const double c = e2.x * e2.x + e2.y * e2.y + e2.z * e2.z;
-    // barycentric parameters and r from the normal n = e1 x e2 (Cramer's
-    // rule written with cross products: better conditioned than the
-    // normal equations, and det = |n|^2 exactly in exact arithmetic)
-    const d3 n = xcross(e1, e2);
-    const double det = xdot(n, n);
-    const double u = xdot(xcross(dp, e2), n) / det, v = xdot(xcross(e1, dp), n) / det;
-    const double hn = xdot(dp, n) / det;
-    const d3 r = {hn * n.x, hn * n.y, hn * n.z};
-    const double w0 = 1.0 - u - v;
-    cd.w[0] = 1.0;
-    cd.w[1] = -w0;
-    cd.w[2] = -u;
-    cd.w[3] = -v;
-    cd.r[0] = r.x, cd.r[1] = r.y, cd.r[2] = r.z;
-    cd.nc = 2;
-    set3(cd.C[0], 0, e1, -2.0);
-    set3(cd.C[0], 1, lin(e1, w0, r, 1.0), 2.0);
-    set3(cd.C[0], 2, lin(e1, u, r, -1.0), 2.0);
-    set3(cd.C[0], 3, e1, 2.0 * v);
-    set3(cd.C[1], 0, e2, -2.0);
-    set3(cd.C[1], 1, lin(e2, w0, r, 1.0), 2.0);
-    set3(cd.C[1], 2, e2, 2.0 * u);
-    set3(cd.C[1], 3, lin(e2, v, r, -1.0), 2.0);
-    // G_thth = 2 [[a, b], [b, c]]
-    const double id = 1.0 / (2.0 * det);
-    cd.Gi[0] = c * id;
-    cd.Gi[1] = -b * id;
-    cd.Gi[2] = a * id;
-  } else {  // line-line: r = (a0 + s u) - (b0 + t v)
-    const d3 u = xsub(X[1], X[0]), v = xsub(X[3], X[2]), w = xsub(X[0], X[2]);
-    const double a = u.x * u.x + u.y * u.y + u.z * u.z;
-    const double b = u.x * v.x + u.y * v.y + u.z * v.z;
-    const double c = v.x * v.x + v.y * v.y + v.z * v.z;
-    // with n = u x v: s = n.(v x w)/|n|^2, t = n.(u x w)/|n|^2 and the
-    // closest-point difference r = (w.n/|n|^2) n (Lagrange's identity turns
-    // the normal equations into these; they stay accurate for nearly
-    // parallel edges, where a c - b^2 cancels)
-    const d3 n = xcross(u, v);
-    const double D = xdot(n, n);
-    const double s = xdot(n, xcross(v, w)) / D, t = xdot(n, xcross(u, w)) / D;
-    const double hn = xdot(w, n) / D;
-    const d3 r = {hn * n.x, hn * n.y, hn * n.z};
-    cd.w[0] = 1.0 - s;
-    cd.w[1] = s;
-    cd.w[2] = -(1.0 - t);
-    cd.w[3] = -t;
-    cd.r[0] = r.x, cd.r[1] = r.y, cd.r[2] = r.z;
-    cd.nc = 2;
-    set3(cd.C[0], 0, lin(u, 1.0 - s, r, -1.0), 2.0);
-    set3(cd.C[0], 1, lin(u, s, r, 1.0), 2.0);
-    set3(cd.C[0], 2, u, -2.0 * (1.0 - t));
-    set3(cd.C[0], 3, u, -2.0 * t);
-    set3(cd.C[1], 0, v, -2.0 * (1.0 - s));
-    set3(cd.C[1], 1, v, -2.0 * s);
-    set3(cd.C[1], 2, lin(v, 1.0 - t, r, 1.0), 2.0);
-    set3(cd.C[1], 3, lin(v, t, r, -1.0), 2.0);
-    // G_thth = 2 [[a, -b], [-b, c]]
-    const double id = 1.0 / (2.0 * D);
-    cd.Gi[0] = c * id;
-    cd.Gi[1] = b * id;
-    cd.Gi[2] = a * id;
+}
+
+// point-point (slots I, J): r = x_I - x_J
+template <int I, int J>
+__host__ __device__ __forceinline__ void deriv_pp(const d3 X[4], CaseDeriv &cd) {
+  deriv_clear(cd);
+  const d3 r = xsub(X[I], X[J]);
+  cd.w[I] = 1.0;
+  cd.w[J] = -1.0;
+  cd.r[0] = r.x, cd.r[1] = r.y, cd.r[2] = r.z;
+  cd.nc = 0;
+}
+
+// point-edge (point I, edge J -> K): r = x_I - x_J - t e
+template <int I, int J, int K>
+__host__ __device__ __forceinline__ void deriv_pe(const d3 X[4], CaseDeriv &cd) {
+  deriv_clear(cd);
+  const d3 e = xsub(X[K], X[J]);
+  const d3 dp = xsub(X[I], X[J]);
+  const double ee = e.x * e.x + e.y * e.y + e.z * e.z;
+  const double t = (dp.x * e.x + dp.y * e.y + dp.z * e.z) / ee;
+  // r = dp - t e written as e x (dp x e) / |e|^2 (no cancellation)
+  const d3 rc = xcross(e, xcross(dp, e));
+  const d3 r = {rc.x / ee, rc.y / ee, rc.z / ee};
+  cd.w[I] = 1.0;
+  cd.w[J] = -(1.0 - t);
+  cd.w[K] = -t;
+  cd.r[0] = r.x, cd.r[1] = r.y, cd.r[2] = r.z;
+  cd.nc = 1;
+  set3(cd.C[0], I, e, -2.0);
+  set3(cd.C[0], J, lin(e, 1.0 - t, r, 1.0), 2.0);
+  set3(cd.C[0], K, lin(e, t, r, -1.0), 2.0);
+  cd.Gi[0] = 1.0 / (2.0 * ee);
+}
+
+// point-face: r = p - t0 - u e1 - v e2
+__host__ __device__ __forceinline__ void deriv_face(const d3 X[4], CaseDeriv &cd) {
+  deriv_clear(cd);
+  const d3 e1 = xsub(X[2], X[1]), e2 = xsub(X[3], X[1]), dp = xsub(X[0], X[1]);
+  const double a = e1.x * e1.x + e1.y * e1.y + e1.z * e1.z;
+  const double b = e1.x * e2.x + e1.y * e2.y + e1.z * e2.z;
+  const double c = e2.x * e2.x + e2.y * e2.y + e2.z * e2.z;
+  // barycentric parameters and r from the normal n = e1 x e2 (Cramer's rule
+  // written with cross products: better conditioned than the normal
+  // equations, and det = |n|^2 exactly in exact arithmetic)
+  const d3 n = xcross(e1, e2);
+  const double det = xdot(n, n);
+  const double u = xdot(xcross(dp, e2), n) / det, v = xdot(xcross(e1, dp), n) / det;
+  const double hn = xdot(dp, n) / det;
+  const d3 r = {hn * n.x, hn * n.y, hn * n.z};
+  const double w0 = 1.0 - u - v;
+  cd.w[0] = 1.0;
+  cd.w[1] = -w0;
+  cd.w[2] = -u;
+  cd.w[3] = -v;
+  cd.r[0] = r.x, cd.r[1] = r.y, cd.r[2] = r.z;
+  cd.nc = 2;
+  set3(cd.C[0], 0, e1, -2.0);
+  set3(cd.C[0], 1, lin(e1, w0, r, 1.0), 2.0);
+  set3(cd.C[0], 2, lin(e1, u, r, -1.0), 2.0);
+  set3(cd.C[0], 3, e1, 2.0 * v);
+  set3(cd.C[1], 0, e2, -2.0);
+  set3(cd.C[1], 1, lin(e2, w0, r, 1.0), 2.0);
+  set3(cd.C[1], 2, e2, 2.0 * u);
+  set3(cd.C[1], 3, lin(e2, v, r, -1.0), 2.0);
+  // G_thth = 2 [[a, b], [b, c]]
+  const double id = 1.0 / (2.0 * det);
+  cd.Gi[0] = c * id;
+  cd.Gi[1] = -b * id;
+  cd.Gi[2] = a * id;
+}
+
+// line-line: r = (a0 + s u) - (b0 + t v)
+__host__ __device__ __forceinline__ void deriv_ll(const d3 X[4], CaseDeriv &cd) {
+  deriv_clear(cd);
+  const d3 u = xsub(X[1], X[0]), v = xsub(X[3], X[2]), w = xsub(X[0], X[2]);
+  const double a = u.x * u.x + u.y * u.y + u.z * u.z;
+  const double b = u.x * v.x + u.y * v.y + u.z * v.z;
+  const double c = v.x * v.x + v.y * v.y + v.z * v.z;
+  // with n = u x v: s = n.(v x w)/|n|^2, t = n.(u x w)/|n|^2 and the
+  // closest-point difference r = (w.n/|n|^2) n (Lagrange's identity turns
+  // the normal equations into these; they stay accurate for nearly
+  // parallel edges, where a c - b^2 cancels)
+  const d3 n = xcross(u, v);
+  const double D = xdot(n, n);
+  const double s = xdot(n, xcross(v, w)) / D, t = xdot(n, xcross(u, w)) / D;
+  const double hn = xdot(w, n) / D;
+  const d3 r = {hn * n.x, hn * n.y, hn * n.z};
+  cd.w[0] = 1.0 - s;
+  cd.w[1] = s;
+  cd.w[2] = -(1.0 - t);
+  cd.w[3] = -t;
+  cd.r[0] = r.x, cd.r[1] = r.y, cd.r[2] = r.z;
+  cd.nc = 2;
+  set3(cd.C[0], 0, lin(u, 1.0 - s, r, -1.0), 2.0);
+  set3(cd.C[0], 1, lin(u, s, r, 1.0), 2.0);
+  set3(cd.C[0], 2, u, -2.0 * (1.0 - t));
+  set3(cd.C[0], 3, u, -2.0 * t);
+  set3(cd.C[1], 0, v, -2.0 * (1.0 - s));
+  set3(cd.C[1], 1, v, -2.0 * s);
+  set3(cd.C[1], 2, lin(v, 1.0 - t, r, 1.0), 2.0);
+  set3(cd.C[1], 3, lin(v, t, r, -1.0), 2.0);
+  // G_thth = 2 [[a, -b], [-b, c]]
+  const double id = 1.0 / (2.0 * D);
+  cd.Gi[0] = c * id;
+  cd.Gi[1] = b * id;
+  cd.Gi[2] = a * id;
+}
+
+__host__ __device__ inline void case_deriv(int type, const d3 X[4], CaseDeriv &cd) {
+  switch (type) {
+    case PT_PP0: deriv_pp<0, 1>(X, cd); break;
+    case PT_PP1: deriv_pp<0, 2>(X, cd); break;
+    case PT_PP2: deriv_pp<0, 3>(X, cd); break;
+    case PT_PE01: deriv_pe<0, 1, 2>(X, cd); break;
+    case PT_PE12: deriv_pe<0, 2, 3>(X, cd); break;
+    case PT_PE02: deriv_pe<0, 1, 3>(X, cd); break;
+    case PT_FACE: deriv_face(X, cd); break;
+    case EE_BASE + 0: deriv_pp<0, 2>(X, cd); break;
+    case EE_BASE + 1: deriv_pp<0, 3>(X, cd); break;
+    case EE_BASE + 2: deriv_pe<0, 2, 3>(X, cd); break;
+    case EE_BASE + 3: deriv_pp<1, 2>(X, cd); break;
+    case EE_BASE + 4: deriv_pp<1, 3>(X, cd); break;
+    case EE_BASE + 5: deriv_pe<1, 2, 3>(X, cd); break;
+    case EE_BASE + 6: deriv_pp<2, 0>(X, cd); break;
+    case EE_BASE + 7: deriv_pp<2, 1>(X, cd); break;
+    case EE_BASE + 8: deriv_pe<2, 0, 1>(X, cd); break;
+    case EE_BASE + 9: deriv_pp<3, 0>(X, cd); break;
+    case EE_BASE + 10: deriv_pp<3, 1>(X, cd); break;
+    case EE_BASE + 11: deriv_pe<3, 0, 1>(X, cd); break;
+    default: deriv_ll(X, cd); break;
   }
 }
 

@@ -4,6 +4,16 @@
 // l_p by the largest displacement on each side, and advance t by safe
 // increments (1-s) d0 / l_p, then 0.9 d / l_p, until the distance drops
 // below s d0 (return the last safe t) or t exceeds tmax.
+//
+// The number of advances per pair ranges from 1 (pairs far apart or
+// separating) to ~l_p / d0 (pairs sliding at a small distance), so a lane
+// per pair would leave most of a wave idle behind its slowest lane.  The
+// kernel is persistent instead: each lane runs a small state machine and,
+// whenever it finishes a pair, takes the next one from a global work
+// counter (one atomic per wave and refill), so a wave's lanes stay busy
+// until the queue is empty.  Every lane performs at most one distance
+// evaluation per loop trip; the sequence of operations per pair is the
+// same as the one-pair-per-lane form.
 #include "abd_internal.h"
 
 namespace {
@@ -21,72 +31,144 @@ __device__ __forceinline__ void atomic_min_nonneg(double *addr, double v) {
   atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ void __launch_bounds__(128) k_accd(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee,
-                                              const int32_t *tris, const int32_t *edges, const int32_t *vert_body,
-                                              const int32_t *body_scene, const double *x, const double *dx,
-                                              double s, double tmax, int max_iter, double *t_pt, double *t_ee,
-                                              double *alpha) {
+constexpr int CCD_BLOCK = 256;
+
+__global__ void __launch_bounds__(CCD_BLOCK) k_accd(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee,
+                                                    const int32_t *tris, const int32_t *edges,
+                                                    const int32_t *vert_body, const int32_t *body_scene,
+                                                    const double *x, const double *dx, double s, double tmax,
+                                                    int max_iter, unsigned long long *counter, double *t_pt,
+                                                    double *t_ee, double *alpha) {
 #pragma clang fp contract(off)
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int is_ee = i >= n_pt;
-  const int32_t *pr = is_ee ? ee + 2 * (i - n_pt) : pt + 2 * i;
-  int vid[4];
-  pair_vids(is_ee, pr, tris, edges, vid);
+  const int lane = threadIdx.x & 63;
+  int64_t cur = -1;   // pair index, -1 = needs work, >= n = queue exhausted
+  int phase = 0;      // 0: distance at start pending, 1: advancing
+  int is_ee = 0, it = 0, scene = 0;
+  // running minimum of this lane's finished pairs, per sub-scene (pairs come
+  // from the queue in index order, so a lane rarely changes scene); flushed
+  // with one atomic per wave and scene instead of one per pair
+  int mscene = -1;
+  double mval = 1.0;
   d3 X[4], U[4];
+  double lp = 0.0, gap = 0.0, t = 0.0, tl = 0.0;
+  for (;;) {
+    // ---- refill idle lanes from the global queue (one atomic per wave)
+    const unsigned long long need = __ballot(cur < 0);
+    if (need) {
+      unsigned long long base = 0;
+      const int leader = __ffsll((long long)need) - 1;
+      if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(need));
+      base = __shfl(base, leader, 64);
+      if (cur < 0) {
+        cur = (int64_t)(base + __popcll(need & ((1ull << lane) - 1ull)));
+        if (cur >= n) {
+          cur = n;
+        } else {
+          is_ee = cur >= n_pt;
+          const int32_t *pr = is_ee ? ee + 2 * (cur - n_pt) : pt + 2 * cur;
+          int vid[4];
+          pair_vids(is_ee, pr, tris, edges, vid);
+          scene = body_scene[vert_body[vid[0]]];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    X[k] = ld3(x, vid[k]);
-    U[k] = ld3(dx, vid[k]);
-  }
-  const d3 mean = {((U[0].x + U[1].x) + (U[2].x + U[3].x)) * 0.25, ((U[0].y + U[1].y) + (U[2].y + U[3].y)) * 0.25,
-                   ((U[0].z + U[1].z) + (U[2].z + U[3].z)) * 0.25};
-  double len[4];
+          for (int k = 0; k < 4; ++k) {
+            X[k] = ld3(x, vid[k]);
+            U[k] = ld3(dx, vid[k]);
+          }
+          const d3 mean = {((U[0].x + U[1].x) + (U[2].x + U[3].x)) * 0.25,
+                           ((U[0].y + U[1].y) + (U[2].y + U[3].y)) * 0.25,
+                           ((U[0].z + U[1].z) + (U[2].z + U[3].z)) * 0.25};
+          double len[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    U[k] = xsub(U[k], mean);
-    len[k] = sqrt(xdot(U[k], U[k]));
-  }
-  const double lp = is_ee ? fmax(len[0], len[1]) + fmax(len[2], len[3])
-                          : len[0] + fmax(len[1], fmax(len[2], len[3]));
-  double t;
-  if (lp == 0.0) {
-    t = tmax;
-  } else {
-    const double d0 = pair_distance(is_ee, X);
-    if (d0 == 0.0) {
-      t = 0.0;
-    } else {
-      const double gap = s * d0;
-      double tl = (1.0 - s) * d0 / lp;
-      t = 0.0;
-      int it = 0;
-      for (;;) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) X[k] = {X[k].x + tl * U[k].x, X[k].y + tl * U[k].y, X[k].z + tl * U[k].z};
-        const double d = pair_distance(is_ee, X);
-        if (t > 0.0 && d < gap) break;
-        t += tl;
-        if (t > tmax) {
-          t = tmax;
-          break;
+          for (int k = 0; k < 4; ++k) {
+            U[k] = xsub(U[k], mean);
+            len[k] = sqrt(xdot(U[k], U[k]));
+          }
+          lp = is_ee ? fmax(len[0], len[1]) + fmax(len[2], len[3]) : len[0] + fmax(len[1], fmax(len[2], len[3]));
+          phase = 0;
+          it = 0;
+          t = 0.0;
         }
-        if (++it >= max_iter) break;
-        tl = 0.9 * d / lp;
       }
     }
+    if (__all(cur >= n)) {
+      // flush the running minima: one wave-wide min and atomic per scene
+      if (alpha) {
+        for (;;) {
+          const unsigned long long has = __ballot(mscene >= 0);
+          if (!has) break;
+          const int leader = __ffsll((long long)has) - 1;
+          const int s0 = __shfl(mscene, leader, 64);
+          const double m = wave_min(mscene == s0 ? mval : 1.0);
+          if (lane == leader) atomic_min_nonneg(alpha + s0, m);
+          if (mscene == s0) mscene = -1;
+        }
+      }
+      break;
+    }
+    bool finish = false;
+    double result = 0.0;
+    if (cur >= 0 && cur < n) {
+      if (phase == 0 && lp == 0.0) {
+        finish = true;
+        result = tmax;
+      } else {
+        const double d = pair_distance(is_ee, X);
+        bool advance = false;
+        if (phase == 0) {
+          if (d == 0.0) {
+            finish = true;
+            result = 0.0;
+          } else {
+            gap = s * d;
+            tl = (1.0 - s) * d / lp;
+            phase = 1;
+            advance = true;
+          }
+        } else if (t > 0.0 && d < gap) {
+          finish = true;
+          result = t;
+        } else {
+          t += tl;
+          if (t > tmax) {
+            finish = true;
+            result = tmax;
+          } else if (++it >= max_iter) {
+            finish = true;
+            result = t;
+          } else {
+            tl = 0.9 * d / lp;
+            advance = true;
+          }
+        }
+        if (advance) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) X[k] = {X[k].x + tl * U[k].x, X[k].y + tl * U[k].y, X[k].z + tl * U[k].z};
+        }
+      }
+    }
+    if (finish) {
+      if (is_ee) {
+        if (t_ee) t_ee[cur - n_pt] = result;
+      } else if (t_pt) {
+        t_pt[cur] = result;
+      }
+      if (alpha) {
+        if (mscene != scene) {
+          if (mscene >= 0) atomic_min_nonneg(alpha + mscene, mval);
+          mscene = scene;
+          mval = 1.0;
+        }
+        mval = fmin(mval, result);
+      }
+      cur = -1;
+    }
   }
-  if (is_ee) {
-    if (t_ee) t_ee[i - n_pt] = t;
-  } else if (t_pt) {
-    t_pt[i] = t;
-  }
-  if (alpha) atomic_min_nonneg(alpha + body_scene[vert_body[vid[0]]], fmin(t, 1.0));
 }
 
-__global__ void k_fill(double *a, int n, double v) {
+__global__ void k_ccd_init(double *alpha, int ns, double v, unsigned long long *counter) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = v;
+  if (i < ns) alpha[i] = v;
+  if (i == 0) *counter = 0ull;
 }
 
 }  // namespace
@@ -95,14 +177,20 @@ int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const doubl
            const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *t_pt, double *t_ee,
            double *alpha, hipStream_t s) {
   const int ns = sc->n_scenes > 0 ? sc->n_scenes : 1;
-  if (alpha) hipLaunchKernelGGL(k_fill, dim3(grid_for(ns, 256)), dim3(256), 0, s, alpha, ns, 1.0);
+  unsigned long long *counter;
+  ABD_TRY(ws(ctx, "ccd_counter", 1, &counter, s));
+  hipLaunchKernelGGL(k_ccd_init, dim3(grid_for(ns, 256)), dim3(256), 0, s, alpha, alpha ? ns : 0, 1.0, counter);
   const int64_t n = n_pt + n_ee;
-  hipEvent_t pe = n > 0 ? prof_begin(ctx, s) : nullptr;
-  if (n > 0)
-    hipLaunchKernelGGL(k_accd, dim3(grid_for(n, 128)), dim3(128), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges,
-                       sc->vert_body, sc->body_scene, x0, dx, prm->ccd_s, prm->ccd_tmax, prm->ccd_max_iter, t_pt,
-                       t_ee, alpha);
-  prof_end(ctx, pe, "accd", n, s);
+  if (n > 0) {
+    // persistent grid: enough waves to fill the chip, never more than the work
+    int64_t blocks = (n + CCD_BLOCK - 1) / CCD_BLOCK;
+    if (blocks > 1024) blocks = 1024;
+    hipEvent_t pe = prof_begin(ctx, s);
+    hipLaunchKernelGGL(k_accd, dim3((unsigned)blocks), dim3(CCD_BLOCK), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges,
+                       sc->vert_body, sc->body_scene, x0, dx, prm->ccd_s, prm->ccd_tmax, prm->ccd_max_iter, counter,
+                       t_pt, t_ee, alpha);
+    prof_end(ctx, pe, "accd", n, s);
+  }
   return abd_hip_check(ctx, hipGetLastError(), "k_accd");
 }
 

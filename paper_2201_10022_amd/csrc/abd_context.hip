@@ -246,6 +246,8 @@ extern "C" int abd_destroy(abd_ctx *ctx) {
     if (e) hipEventDestroy(e);
   prof_flush(ctx);
   for (auto &e : ctx->ev_pool) hipEventDestroy(e);
+  if (ctx->pcg_exec) hipGraphExecDestroy(ctx->pcg_exec);
+  if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
   delete ctx;
   return ABD_OK;
 }

@@ -42,6 +42,10 @@ struct abd_ctx {
   std::map<std::string, KStat> kstats;
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> ev_pool;
+  // captured PCG iterations, re-captured when any argument changes
+  hipGraphExec_t pcg_exec = nullptr;
+  std::vector<uintptr_t> pcg_key;
+  hipStream_t capture_stream = nullptr;
 };
 
 // instrumentation: prof_begin returns an event recorded before the launch
@@ -159,29 +163,61 @@ __host__ __device__ __forceinline__ CaseSlots case_slots(int type) {
   return {1, k, e0, e1};
 }
 
-// squared distance of a case as num/den
-__host__ __device__ __forceinline__ void case_nd(int type, const d3 X[4], double &num, double &den) {
+// squared distance of a case as num/den.  Each case is instantiated with
+// compile-time vertex slots (a switch over the case code), so no register
+// array is indexed with a run-time value.
+template <int I, int J>
+__host__ __device__ __forceinline__ void nd_pp(const d3 X[4], double &num, double &den) {
 #pragma clang fp contract(off)
-  const CaseSlots c = case_slots(type);
-  if (c.kind == 0) {
-    d3 d = xsub(X[c.i], X[c.j]);
-    num = xdot(d, d);
-    den = 1.0;
-  } else if (c.kind == 1) {
-    d3 e = xsub(X[c.k], X[c.j]);
-    d3 cr = xcross(xsub(X[c.i], X[c.j]), e);
-    num = xdot(cr, cr);
-    den = xdot(e, e);
-  } else if (c.kind == 2) {
-    d3 n = xcross(xsub(X[2], X[1]), xsub(X[3], X[1]));
-    double h = xdot(xsub(X[0], X[1]), n);
-    num = h * h;
-    den = xdot(n, n);
-  } else {
-    d3 n = xcross(xsub(X[1], X[0]), xsub(X[3], X[2]));
-    double h = xdot(xsub(X[2], X[0]), n);
-    num = h * h;
-    den = xdot(n, n);
+  d3 d = xsub(X[I], X[J]);
+  num = xdot(d, d);
+  den = 1.0;
+}
+template <int I, int J, int K>
+__host__ __device__ __forceinline__ void nd_pe(const d3 X[4], double &num, double &den) {
+#pragma clang fp contract(off)
+  d3 e = xsub(X[K], X[J]);
+  d3 cr = xcross(xsub(X[I], X[J]), e);
+  num = xdot(cr, cr);
+  den = xdot(e, e);
+}
+__host__ __device__ __forceinline__ void nd_face(const d3 X[4], double &num, double &den) {
+#pragma clang fp contract(off)
+  d3 n = xcross(xsub(X[2], X[1]), xsub(X[3], X[1]));
+  double h = xdot(xsub(X[0], X[1]), n);
+  num = h * h;
+  den = xdot(n, n);
+}
+__host__ __device__ __forceinline__ void nd_ll(const d3 X[4], double &num, double &den) {
+#pragma clang fp contract(off)
+  d3 n = xcross(xsub(X[1], X[0]), xsub(X[3], X[2]));
+  double h = xdot(xsub(X[2], X[0]), n);
+  num = h * h;
+  den = xdot(n, n);
+}
+
+__host__ __device__ __forceinline__ void case_nd(int type, const d3 X[4], double &num, double &den) {
+  switch (type) {
+    case PT_PP0: nd_pp<0, 1>(X, num, den); break;
+    case PT_PP1: nd_pp<0, 2>(X, num, den); break;
+    case PT_PP2: nd_pp<0, 3>(X, num, den); break;
+    case PT_PE01: nd_pe<0, 1, 2>(X, num, den); break;
+    case PT_PE12: nd_pe<0, 2, 3>(X, num, den); break;
+    case PT_PE02: nd_pe<0, 1, 3>(X, num, den); break;
+    case PT_FACE: nd_face(X, num, den); break;
+    case EE_BASE + 0: nd_pp<0, 2>(X, num, den); break;
+    case EE_BASE + 1: nd_pp<0, 3>(X, num, den); break;
+    case EE_BASE + 2: nd_pe<0, 2, 3>(X, num, den); break;
+    case EE_BASE + 3: nd_pp<1, 2>(X, num, den); break;
+    case EE_BASE + 4: nd_pp<1, 3>(X, num, den); break;
+    case EE_BASE + 5: nd_pe<1, 2, 3>(X, num, den); break;
+    case EE_BASE + 6: nd_pp<2, 0>(X, num, den); break;
+    case EE_BASE + 7: nd_pp<2, 1>(X, num, den); break;
+    case EE_BASE + 8: nd_pe<2, 0, 1>(X, num, den); break;
+    case EE_BASE + 9: nd_pp<3, 0>(X, num, den); break;
+    case EE_BASE + 10: nd_pp<3, 1>(X, num, den); break;
+    case EE_BASE + 11: nd_pe<3, 0, 1>(X, num, den); break;
+    default: nd_ll(X, num, den); break;
   }
 }
 

@@ -1,15 +1,26 @@
 // Block-Jacobi preconditioned conjugate gradients on the symmetric
 // 12x12-block system H p = rhs (diagonal blocks per body, off-diagonal
-// blocks per contacting body pair, fixed bodies removed).  Scalars (alpha,
-// beta, r.z) stay on the device; the host reads the residual only every
-// CHECK iterations.  All dot products are fixed-order tree reductions.
+// blocks per contacting body pair, fixed bodies removed).
+//
+// Two kernels per iteration.  The first forms the search direction
+// p_new = z + beta p_old on the fly (p is double-buffered, so no block reads
+// a vector another block is writing), multiplies by H and reduces p.Hp; the
+// second updates x, r, z = P r and reduces r.z, r.r.  Each ends with the
+// last block to finish folding the per-block partials in a fixed order and
+// publishing the scalars (alpha; beta and the stop decision), so no
+// separate reduction launches are needed and results are run-to-run
+// reproducible.  Iterations are replayed from a captured hipGraph of ITER_G
+// iterations; once the stop flag is set the remaining kernels return at
+// once, and the host reads the flag once per replay.
+#include <cstdlib>
+
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "abd_internal.h"
 
 namespace {
 
-constexpr int CHECK = 8;
+constexpr int ITER_G = 16;  // iterations per graph replay (even: p buffers alternate)
 
 // inverse of each free body's diagonal block via Cholesky (thread per body)
 __global__ void __launch_bounds__(64) k_block_inverse(int nb, const uint8_t *fixed, const double *diag, double *inv,
@@ -114,72 +125,190 @@ __global__ void k_tkeys(int64_t nk, const int32_t *keys, uint64_t *tk, uint32_t 
   tv[k] = (uint32_t)k;
 }
 
-// y = H x (thread per body row component); partial dot x.y per block
-constexpr int SB = 192;  // 16 bodies x 12 rows
-__global__ void __launch_bounds__(SB) k_spmv(int nb, const uint8_t *fixed, const double *diag, const double *off,
-                                            const int32_t *keys, const uint32_t *tperm, const int64_t *lo_beg,
-                                            const int64_t *hi_beg, const double *x, double *y, double *part) {
-  __shared__ double sh[SB / 64];
-  const int t = blockIdx.x * SB + threadIdx.x;
-  const int b = t / 12, i = t % 12;
-  double v = 0.0, dotv = 0.0;
-  if (b < nb && !fixed[b]) {
-    const double *D = diag + 144 * (int64_t)b + 12 * i;
-    const double *xb = x + 12 * (int64_t)b;
-#pragma unroll
-    for (int j = 0; j < 12; ++j) v += D[j] * xb[j];
-    for (int64_t k = lo_beg[b]; k < lo_beg[b + 1]; ++k) {
-      const double *O = off + 144 * k + 12 * i;
-      const double *xc = x + 12 * (int64_t)keys[2 * k + 1];
-#pragma unroll
-      for (int j = 0; j < 12; ++j) v += O[j] * xc[j];
-    }
-    for (int64_t m = hi_beg[b]; m < hi_beg[b + 1]; ++m) {
-      const int64_t k = tperm[m];
-      const double *O = off + 144 * k + i;  // column i of block (lo, b)
-      const double *xc = x + 12 * (int64_t)keys[2 * k];
-#pragma unroll
-      for (int j = 0; j < 12; ++j) v += O[12 * j] * xc[j];
-    }
-    y[12 * (int64_t)b + i] = v;
-    dotv = v * x[12 * (int64_t)b + i];
-  } else if (b < nb) {
-    y[12 * (int64_t)b + i] = 0.0;
-  }
-  dotv = wave_sum(dotv);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = dotv;
+
+constexpr int PB = 192;  // init / update: 16 bodies x 12 rows per block
+constexpr int PBB = PB / 12;
+constexpr int SWB = 256;  // spmv: one 64-lane wave per body, 4 bodies per block
+
+// Device-side iteration state.  Every scalar is written by block 0 of one
+// kernel and read only by later kernels, so no fences or atomics are needed.
+struct PcgState {
+  double rz[2];    // r.z of iterations with parity 0/1 (written by spmv)
+  double bb, rr;   // initial and current r.r
+  int it_done;     // iterations completed (written by update's block 0)
+  int k_cur;       // iteration being run (written by spmv's block 0)
+  int stop, it_final;
+};
+
+// fixed-order sum of n per-block partials (stride `stride`, offset `off`),
+// identical in every block that calls it
+__device__ __forceinline__ double fold(const double *part, int n, int stride, int off, double *sh) {
+  double v = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) v += part[stride * j + off];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + sh[2];
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  __syncthreads();
+  return s;
 }
 
-// scalars: [0] rz, [1] pAp, [2] alpha, [3] beta, [4] rr, [5] bb, [6] rz_new, [7] stop flag
-__global__ void k_fold_alpha(const double *part, int np, double *sc, int *err) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < np; i += 64) v += part[i];
+__device__ __forceinline__ double block_sum(double v, double *sh) {
   v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  __syncthreads();
+  return s;
+}
+
+__global__ void k_pcg_reset(PcgState *st) {
+  st->it_done = 0;
+  st->k_cur = 0;
+  st->stop = 0;
+  st->it_final = 0;
+}
+
+// r = rhs (free bodies), x = 0, z = P r, p_old = 0; partials of r.z, r.r
+__global__ void __launch_bounds__(PB) k_pcg_init(int nb, const uint8_t *fixed, const double *inv, const double *rhs,
+                                                double *x, double *r, double *z, double *p_old, double *part2) {
+  __shared__ double sr[PBB][12];
+  __shared__ double sh[PB / 64];
+  const int t = blockIdx.x * PB + threadIdx.x;
+  const int b = t / 12, i = t % 12, lb = threadIdx.x / 12;
+  double rv = 0.0;
+  if (b < nb) {
+    const int64_t o = 12 * (int64_t)b + i;
+    rv = fixed[b] ? 0.0 : rhs[o];
+    x[o] = 0.0;
+    r[o] = rv;
+    p_old[o] = 0.0;
+  }
+  sr[lb][i] = rv;
+  __syncthreads();
+  double zv = 0.0;
+  if (b < nb) {
+    const double *M = inv + 144 * (int64_t)b + 12 * i;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) zv += M[j] * sr[lb][j];
+    z[12 * (int64_t)b + i] = zv;
+  }
+  const double rz = block_sum(rv * zv, sh), rr = block_sum(rv * rv, sh);
   if (threadIdx.x == 0) {
-    sc[1] = v;
-    double a = 0.0;
-    if (sc[7] == 0.0) {
-      if (v > 0.0)
-        a = sc[0] / v;
-      else {
-        sc[7] = 1.0;
-        if (!(v == 0.0 && sc[0] == 0.0)) atomicOr(err, 8);
+    part2[2 * blockIdx.x] = rz;
+    part2[2 * blockIdx.x + 1] = rr;
+  }
+}
+
+// Iteration k (k = it_done): fold r.z, r.r of the previous update, decide
+// stop, beta = rz_k / rz_{k-1}; p_new = z + beta p_old; Ap = H p_new with one
+// wave per body: lane = (entry slot 0..4, row 0..11), entries = the
+// diagonal block and the body's off-diagonal blocks (as row and as column),
+// five in flight per pass; per-row sums over slots in fixed order.
+__global__ void __launch_bounds__(SWB) k_pcg_spmv(int nb, const uint8_t *fixed, const double *diag,
+                                                 const double *off, const int32_t *keys, const uint32_t *tperm,
+                                                 const int64_t *lo_beg, const int64_t *hi_beg, const double *p_old,
+                                                 const double *z, double *p_new, double *Ap, const double *part2,
+                                                 int npart2, double *part, PcgState *st, double rtol2,
+                                                 int max_iter) {
+  __shared__ double sh[SWB / 64];
+  if (st->stop) return;
+  const int k = st->it_done;
+  const double rz = fold(part2, npart2, 2, 0, sh), rr = fold(part2, npart2, 2, 1, sh);
+  const double bb = k == 0 ? rr : st->bb;
+  const double beta = k == 0 ? 0.0 : rz / st->rz[(k - 1) & 1];
+  const bool stop = !(bb > 0.0) || rr <= rtol2 * bb || k >= max_iter || rz == 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rz[k & 1] = rz;
+    st->rr = rr;
+    st->k_cur = k;
+    if (k == 0) st->bb = rr;
+    if (stop) {
+      st->stop = 1;
+      st->it_final = k;
+    }
+  }
+  if (stop) return;
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (SWB / 64) + (threadIdx.x >> 6);
+  const int slot = lane / 12, i = lane % 12;
+  double acc = 0.0, pown = 0.0;
+  if (b < nb) {
+    pown = z[12 * (int64_t)b + i] + beta * p_old[12 * (int64_t)b + i];
+    const int64_t l0 = lo_beg[b], nlo = lo_beg[b + 1] - l0;
+    const int64_t h0 = hi_beg[b], nhi = hi_beg[b + 1] - h0;
+    const int64_t E = 1 + nlo + nhi;
+    for (int64_t e0 = 0; e0 < E; e0 += 5) {
+      const int64_t e = e0 + slot;
+      if (lane < 60 && e < E) {
+        const double *row;
+        int64_t c;
+        int stride;
+        if (e == 0) {
+          row = diag + 144 * (int64_t)b + 12 * i;
+          c = b;
+          stride = 1;
+        } else if (e <= nlo) {
+          const int64_t kk = l0 + e - 1;
+          row = off + 144 * kk + 12 * i;
+          c = keys[2 * kk + 1];
+          stride = 1;
+        } else {
+          const int64_t kk = tperm[h0 + e - 1 - nlo];
+          row = off + 144 * kk + i;  // column i of block (lo, b)
+          c = keys[2 * kk];
+          stride = 12;
+        }
+        const double *zc = z + 12 * c, *pc = p_old + 12 * c;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) acc += row[stride * j] * (zc[j] + beta * pc[j]);
       }
     }
-    sc[2] = a;
   }
+  // sum the five slots of row i (lanes i, i+12, ..., i+48) in fixed order
+  double v = acc;
+#pragma unroll
+  for (int q = 1; q < 5; ++q) {
+    const double o = __shfl(acc, (lane + 12 * q) & 63, 64);
+    v += o;
+  }
+  double dot = 0.0;
+  if (b < nb && slot == 0) {
+    const bool fx = fixed[b] != 0;
+    const int64_t o = 12 * (int64_t)b + i;
+    const double av = fx ? 0.0 : v;
+    Ap[o] = av;
+    p_new[o] = pown;
+    dot = av * pown;
+  }
+  const double s = block_sum(dot, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// x += alpha p; r -= alpha Ap; z = P r; partials of r.z and r.r
-__global__ void __launch_bounds__(SB) k_update_xr(int nb, const double *inv, const double *p, const double *Ap,
-                                                 double *x, double *r, double *z, const double *sc, double *part2) {
-  __shared__ double sr[16][12];
-  __shared__ double sh[2][SB / 64];
-  const int t = blockIdx.x * SB + threadIdx.x;
+// alpha = rz_k / p.Ap (folded from spmv partials); x += alpha p;
+// r -= alpha Ap; z = P r; partials of r.z, r.r for the next spmv
+__global__ void __launch_bounds__(PB) k_pcg_update(int nb, const double *inv, const double *p, const double *Ap,
+                                                  double *x, double *r, double *z, const double *part, int npart,
+                                                  double *part2, PcgState *st, int *err) {
+  __shared__ double sr[PBB][12];
+  __shared__ double sh[PB / 64];
+  if (st->stop) return;
+  const int k = st->k_cur;
+  const double pap = fold(part, npart, 1, 0, sh);
+  const double rz = st->rz[k & 1];
+  if (!(pap > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->stop = 1;
+      st->it_final = k;
+      if (!(pap == 0.0 && rz == 0.0)) atomicOr(err, 8);
+    }
+    return;
+  }
+  const double a = rz / pap;
+  const int t = blockIdx.x * PB + threadIdx.x;
   const int b = t / 12, i = t % 12, lb = threadIdx.x / 12;
-  const double a = sc[2];
   double rv = 0.0;
   if (b < nb) {
     const int64_t o = 12 * (int64_t)b + i;
@@ -196,122 +325,46 @@ __global__ void __launch_bounds__(SB) k_update_xr(int nb, const double *inv, con
     for (int j = 0; j < 12; ++j) zv += M[j] * sr[lb][j];
     z[12 * (int64_t)b + i] = zv;
   }
-  double rz = wave_sum(rv * zv), rr = wave_sum(rv * rv);
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = rz;
-    sh[1][threadIdx.x >> 6] = rr;
-  }
-  __syncthreads();
+  const double rzp = block_sum(rv * zv, sh), rrp = block_sum(rv * rv, sh);
   if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = (sh[0][0] + sh[0][1]) + sh[0][2];
-    part2[2 * blockIdx.x + 1] = (sh[1][0] + sh[1][1]) + sh[1][2];
-  }
-}
-
-__global__ void k_fold_beta(const double *part2, int np, double *sc) {
-  double rz = 0.0, rr = 0.0;
-  for (int i = threadIdx.x; i < np; i += 64) {
-    rz += part2[2 * i];
-    rr += part2[2 * i + 1];
-  }
-  rz = wave_sum(rz);
-  rr = wave_sum(rr);
-  if (threadIdx.x == 0) {
-    double beta = 0.0;
-    if (sc[7] == 0.0 && sc[0] != 0.0) beta = rz / sc[0];
-    if (sc[7] == 0.0) sc[0] = rz;
-    sc[3] = beta;
-    sc[4] = rr;
-  }
-}
-
-__global__ void k_update_p(int n, const double *z, double *p, const double *sc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (sc[7] != 0.0) return;
-  p[i] = z[i] + sc[3] * p[i];
-}
-
-// initial: r = rhs (x = 0), z = P r, p = z, rz, rr, bb
-__global__ void __launch_bounds__(SB) k_pcg_init(int nb, const uint8_t *fixed, const double *inv, const double *rhs,
-                                                double *x, double *r, double *z, double *p, double *part2) {
-  __shared__ double sr[16][12];
-  __shared__ double sh[2][SB / 64];
-  const int t = blockIdx.x * SB + threadIdx.x;
-  const int b = t / 12, i = t % 12, lb = threadIdx.x / 12;
-  double rv = 0.0;
-  if (b < nb) {
-    const int64_t o = 12 * (int64_t)b + i;
-    rv = fixed[b] ? 0.0 : rhs[o];
-    x[o] = 0.0;
-    r[o] = rv;
-  }
-  sr[lb][i] = rv;
-  __syncthreads();
-  double zv = 0.0;
-  if (b < nb) {
-    const double *M = inv + 144 * (int64_t)b + 12 * i;
-#pragma unroll
-    for (int j = 0; j < 12; ++j) zv += M[j] * sr[lb][j];
-    z[12 * (int64_t)b + i] = zv;
-    p[12 * (int64_t)b + i] = zv;
-  }
-  double rz = wave_sum(rv * zv), rr = wave_sum(rv * rv);
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = rz;
-    sh[1][threadIdx.x >> 6] = rr;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = (sh[0][0] + sh[0][1]) + sh[0][2];
-    part2[2 * blockIdx.x + 1] = (sh[1][0] + sh[1][1]) + sh[1][2];
-  }
-}
-
-__global__ void k_fold_init(const double *part2, int np, double *sc) {
-  double rz = 0.0, rr = 0.0;
-  for (int i = threadIdx.x; i < np; i += 64) {
-    rz += part2[2 * i];
-    rr += part2[2 * i + 1];
-  }
-  rz = wave_sum(rz);
-  rr = wave_sum(rr);
-  if (threadIdx.x == 0) {
-    sc[0] = rz;
-    sc[4] = rr;
-    sc[5] = rr;
-    sc[7] = rr == 0.0 ? 1.0 : 0.0;
+    part2[2 * blockIdx.x] = rzp;
+    part2[2 * blockIdx.x + 1] = rrp;
+    if (blockIdx.x == 0) st->it_done = k + 1;
   }
 }
 
 }  // namespace
 
+
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
-           int64_t n_keys, const double *rhs, double *p_out, double rtol, int max_iter, int *iters, hipStream_t s) {
+           int64_t n_keys, const double *rhs, double *x_out, double rtol, int max_iter, int *iters, hipStream_t s) {
   const int nb = sc->n_bodies;
   *iters = 0;
   if (nb <= 0) return ABD_OK;
   if (n_keys >= (1ll << 31) || nb >= (1 << 24)) return abd_fail(ctx, ABD_E_INVALID, "pcg: too many blocks");
-  double *inv, *r, *z, *p, *Ap, *scal, *part, *part2;
+  double *inv, *r, *z, *pa, *pb, *Ap, *part, *part2;
   int64_t *lo_beg, *hi_beg;
   uint64_t *tk, *tk2;
   uint32_t *tv, *tv2;
   int *err;
-  const int nblk = (int)grid_for((int64_t)nb * 12, SB);
+  PcgState *st;
+  const int nblk_u = (int)grid_for((int64_t)nb * 12, PB);
+  const int nblk_s = (int)grid_for(nb, SWB / 64);
   ABD_TRY(ws(ctx, "pcg_inv", 144 * (size_t)nb, &inv, s));
   ABD_TRY(ws(ctx, "pcg_r", 12 * (size_t)nb, &r, s));
   ABD_TRY(ws(ctx, "pcg_z", 12 * (size_t)nb, &z, s));
-  ABD_TRY(ws(ctx, "pcg_p", 12 * (size_t)nb, &p, s));
+  ABD_TRY(ws(ctx, "pcg_pa", 12 * (size_t)nb, &pa, s));
+  ABD_TRY(ws(ctx, "pcg_pb", 12 * (size_t)nb, &pb, s));
   ABD_TRY(ws(ctx, "pcg_Ap", 12 * (size_t)nb, &Ap, s));
-  ABD_TRY(ws(ctx, "pcg_sc", 8, &scal, s));
-  ABD_TRY(ws(ctx, "pcg_part", nblk, &part, s));
-  ABD_TRY(ws(ctx, "pcg_part2", 2 * nblk, &part2, s));
+  ABD_TRY(ws(ctx, "pcg_part", nblk_s, &part, s));
+  ABD_TRY(ws(ctx, "pcg_part2", 2 * nblk_u, &part2, s));
   ABD_TRY(ws(ctx, "pcg_lob", nb + 1, &lo_beg, s));
   ABD_TRY(ws(ctx, "pcg_hib", nb + 1, &hi_beg, s));
   ABD_TRY(ws(ctx, "pcg_tk", n_keys + 1, &tk, s));
   ABD_TRY(ws(ctx, "pcg_tk2", n_keys + 1, &tk2, s));
   ABD_TRY(ws(ctx, "pcg_tv", n_keys + 1, &tv, s));
   ABD_TRY(ws(ctx, "pcg_tv2", n_keys + 1, &tv2, s));
+  ABD_TRY(ws(ctx, "pcg_state", 1, &st, s));
   ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
   hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed, diag, inv, err);
   if (n_keys > 0) {
@@ -324,30 +377,59 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   }
   hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(nb + 1, 256)), dim3(256), 0, s, nb, n_keys, keys, tk2, lo_beg,
                      hi_beg);
-  hipLaunchKernelGGL(k_pcg_init, dim3(nblk), dim3(SB), 0, s, nb, sc->body_fixed, inv, rhs, p_out, r, z, p, part2);
-  hipLaunchKernelGGL(k_fold_init, dim3(1), dim3(64), 0, s, part2, nblk, scal);
+  hipLaunchKernelGGL(k_pcg_reset, dim3(1), dim3(1), 0, s, st);
+  hipLaunchKernelGGL(k_pcg_init, dim3(nblk_u), dim3(PB), 0, s, nb, sc->body_fixed, inv, rhs, x_out, r, z, pa, part2);
   HIP_TRY(ctx, hipGetLastError());
-  double *h;
-  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
   const double rtol2 = rtol * rtol;
-  int it = 0;
-  for (; it < max_iter;) {
-    for (int k = 0; k < CHECK && it < max_iter; ++k, ++it) {
-      hipEvent_t pe = prof_begin(ctx, s);
-      hipLaunchKernelGGL(k_spmv, dim3(nblk), dim3(SB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2, lo_beg, hi_beg,
-                         p, Ap, part);
-      prof_end(ctx, pe, "spmv", nb + 2 * n_keys, s);
-      hipLaunchKernelGGL(k_fold_alpha, dim3(1), dim3(64), 0, s, part, nblk, scal, err);
-      hipLaunchKernelGGL(k_update_xr, dim3(nblk), dim3(SB), 0, s, nb, inv, p, Ap, p_out, r, z, scal, part2);
-      hipLaunchKernelGGL(k_fold_beta, dim3(1), dim3(64), 0, s, part2, nblk, scal);
-      hipLaunchKernelGGL(k_update_p, dim3(grid_for(12 * nb, 256)), dim3(256), 0, s, 12 * nb, z, p, scal);
+  // ITER_G iterations: p alternates pa -> pb -> pa ... (ITER_G is even)
+  auto enqueue = [&](hipStream_t q) {
+    for (int k = 0; k < ITER_G; ++k) {
+      double *p_old = (k % 2 == 0) ? pa : pb, *p_new = (k % 2 == 0) ? pb : pa;
+      hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, q, nb, sc->body_fixed, diag, off, keys, tv2, lo_beg,
+                         hi_beg, p_old, z, p_new, Ap, part2, nblk_u, part, st, rtol2, max_iter);
+      hipLaunchKernelGGL(k_pcg_update, dim3(nblk_u), dim3(PB), 0, q, nb, inv, p_new, Ap, x_out, r, z, part, nblk_s,
+                         part2, st, err);
     }
-    HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(h, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    if (h[7] != 0.0 || h[4] <= rtol2 * h[5]) break;
+  };
+  const char *env = getenv("ABD_PCG_GRAPH");
+  const bool use_graph = !(env && env[0] == '0');
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    const std::vector<uintptr_t> key = {
+        (uintptr_t)diag, (uintptr_t)off, (uintptr_t)keys, (uintptr_t)tv2, (uintptr_t)lo_beg, (uintptr_t)hi_beg,
+        (uintptr_t)inv, (uintptr_t)x_out, (uintptr_t)r, (uintptr_t)z, (uintptr_t)pa, (uintptr_t)pb,
+        (uintptr_t)Ap, (uintptr_t)part, (uintptr_t)part2, (uintptr_t)st, (uintptr_t)err,
+        (uintptr_t)sc->body_fixed, (uintptr_t)nb, (uintptr_t)max_iter, (uintptr_t)(rtol2 * 1e300)};
+    if (ctx->pcg_exec == nullptr || ctx->pcg_key != key) {
+      if (ctx->pcg_exec) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec));
+      ctx->pcg_exec = nullptr;
+      if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+      enqueue(ctx->capture_stream);
+      HIP_TRY(ctx, hipStreamEndCapture(ctx->capture_stream, &g));
+      HIP_TRY(ctx, hipGraphInstantiate(&ctx->pcg_exec, g, nullptr, nullptr, 0));
+      HIP_TRY(ctx, hipGraphDestroy(g));
+      ctx->pcg_key = key;
+    }
+    exec = ctx->pcg_exec;
   }
-  *iters = it;
+  int *h;
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
+  const int max_rounds = max_iter / ITER_G + 2;
+  for (int round = 0; round < max_rounds; ++round) {
+    hipEvent_t pe = prof_begin(ctx, s);
+    if (exec)
+      HIP_TRY(ctx, hipGraphLaunch(exec, s));
+    else
+      enqueue(s);
+    prof_end(ctx, pe, "pcg_round", ITER_G, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(h, &st->stop, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h[0]) break;
+  }
+  *iters = h[1];
   return ABD_OK;
 }
 

@@ -394,3 +394,37 @@ def test_time_steps_three_cubes_trajectory(abd, ctx):
         # trajectories agree while contacts form (per-step tolerance loose:
         # different Newton paths converge to the same minimiser within tol)
         np.testing.assert_allclose(qg.cpu().numpy(), q, rtol=0, atol=1e-6)
+
+
+def test_pcg_graph_replays_match_eager(abd, ctx):
+    """The PCG iterations run from a captured graph; every replay (with eager
+    library work and synchronisations in between) must equal the eagerly
+    launched kernels bit for bit, and the direct solve to 1e-8."""
+    import os
+    S = sg.near_contact_cubes(1, n=4)
+    P = dict(sg.default_params())
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    B = oracle.Body(S)
+    q = _state(S, 71)
+    qt = q.copy()
+    qt[:, :3] += P["dt"] ** 2 * np.array(P["gravity"])
+    qt[S["body_fixed"] != 0] = q[S["body_fixed"] != 0]
+    gh = oracle.grad_hess(S, B, q, qt, P)
+    args = (_dev(gh["diag"]), _dev(gh["off"]), _dev(gh["keys"], torch.int32), _dev(-gh["grad"]))
+    p_ref = oracle.solve(S, gh["diag"], gh["off"], gh["keys"], -gh["grad"])
+    os.environ["ABD_PCG_GRAPH"] = "0"
+    try:
+        p_eager, it_eager = ctx.pcg_solve(sc, *args, rtol=1e-14, max_iter=20000)
+    finally:
+        del os.environ["ABD_PCG_GRAPH"]
+    p_eager = p_eager.cpu().numpy()
+    assert np.abs(p_eager - p_ref).max() <= 1e-8 * np.abs(p_ref).max()
+    x = _dev(oracle.vertex_map(S, q))
+    for rep in range(4):
+        p, it = ctx.pcg_solve(sc, *args, rtol=1e-14, max_iter=20000)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(p.cpu().numpy(), p_eager)
+        assert it == it_eager
+        ctx.vertex_map(sc, _dev(q))            # eager work between replays
+        ctx.candidates(sc, x, None, P["dhat"])

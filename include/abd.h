@@ -225,8 +225,10 @@ int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, doub
  * abd_profile(enable, reset) switches recording on/off (reset clears the
  * totals); abd_profile_query returns, for one instrumented kernel
  * ("barrier_local", "assemble_chunks", "energy_only", "accd",
- * "pair_tiles_write", "spmv"), the summed duration in ms, the number of
- * launches and the work units processed (pairs, records, tiles, block rows).
+ * "pair_tiles_write", "pcg_round"), the summed duration in ms, the number of
+ * launches and the work units processed (active pairs, records, pairs,
+ * pairs, tiles; for "pcg_round", one replay of the captured PCG iterations,
+ * the algorithmic HBM bytes of the iterations it executed).
  * Query synchronises the device. */
 int abd_profile(abd_ctx *ctx, int enable, int reset);
 int abd_profile_query(abd_ctx *ctx, const char *kernel, double *ms, int64_t *launches, int64_t *units);

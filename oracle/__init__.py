@@ -16,6 +16,8 @@ Paper passages followed (Lan et al., Affine Body Dynamics):
   CCD                   sec. 4.1 (linear trajectories, additive CCD)
   culling               sec. 4.2 (box predicate; i-AABB is an exact filter)
   assembly              sec. 4.3 (J^T H J into 12x12 body blocks)
+  friction              sec. 4, V_F (IPC's lagged model: normal force,
+                        closest points and tangent basis fixed at q^t)
 Readings where the paper is silent (IPC / ACCD conventions, distance case
 tie-breaks, mollifier, line search, convergence) are listed in the
 project's design notes and restated at each function.
@@ -67,6 +69,12 @@ def lib():
                                         ctypes.c_int, _d, _d, _d]
         L.ora_orthogonality_energy.argtypes = [ctypes.c_int, _u8, _d, _d, ctypes.c_double, ctypes.c_double]
         L.ora_orthogonality_energy.restype = ctypes.c_double
+        L.ora_friction_lag.argtypes = [ctypes.c_int64, ctypes.c_int, _i32, _i32, _i32, _d, _d, ctypes.c_double,
+                                       ctypes.c_double, _d, _d, _d]
+        L.ora_friction.argtypes = [ctypes.c_int64, ctypes.c_int, _i32, _i32, _i32, _i32, _u8, _d, _d, _d, _d, _d,
+                                   _d, ctypes.c_double, ctypes.c_double, _d, _d, _d, _d, _i32, ctypes.c_int64,
+                                   ctypes.c_int]
+        L.ora_friction.restype = ctypes.c_int64
         L.ora_psd_project.argtypes = [ctypes.c_int, _d]
         L.ora_pair_local.argtypes = [ctypes.c_int, _d, _d, ctypes.c_double, ctypes.c_double, _d, _d, _d]
         L.ora_pair_local.restype = ctypes.c_int
@@ -262,6 +270,68 @@ def ccd(S, x, dx, pt, ee, params, iters=None):
     return out[0], out[1], alpha
 
 
+# ------------------------------------------------------------- friction ----
+
+def friction_lag(S, xt, pt, ee, params, keep_inactive=False):
+    """Lagged friction state at the step start x^t (sec. 4, V_F; IPC's lagged
+    model): per active pair lambda = -kappa m B'(d), tangent basis T (6) and
+    closest-point weights w (4).  Inactive pairs are dropped unless
+    keep_inactive."""
+    out = {}
+    for is_ee, pairs, nm in ((0, pt, "pt"), (1, ee, "ee")):
+        n = len(pairs)
+        lam = np.zeros(n)
+        T = np.zeros((n, 6))
+        w = np.zeros((n, 4))
+        if n:
+            lib().ora_friction_lag(n, is_ee, _p(_c(pairs, np.int32), _i32), _p(_c(S["tris"], np.int32), _i32),
+                                   _p(_c(S["edges"], np.int32), _i32), _p(_c(S["xbar"], np.float64), _d),
+                                   _p(_c(xt, np.float64), _d), float(params["dhat"]), float(params["kappa_b"]),
+                                   _p(lam, _d), _p(T, _d), _p(w, _d))
+        keep = np.ones(n, bool) if keep_inactive else lam > 0
+        out[nm] = dict(pairs=_c(pairs, np.int32)[keep], lam=lam[keep], T=T[keep], w=w[keep])
+    out["xt"] = np.array(xt, dtype=np.float64)
+    return out
+
+
+def friction(S, x, F, params, keys, hess=True):
+    """Friction energy, gradient [nb,12] and Hessian blocks of the lagged
+    pairs F at x."""
+    nb = len(S["body_fixed"])
+    e = np.zeros(1)
+    g = np.zeros((nb, 12))
+    D = np.zeros((nb, 144))
+    O = np.zeros((max(len(keys), 1), 144))
+    keys = _c(keys, np.int32)
+    eps = params["eps_v"] * params["dt"]
+    for is_ee, nm in ((0, "pt"), (1, "ee")):
+        f = F[nm]
+        n = len(f["pairs"])
+        if n == 0:
+            continue
+        r = lib().ora_friction(n, is_ee, _p(f["pairs"], _i32), _p(_c(S["vert_body"], np.int32), _i32),
+                               _p(_c(S["tris"], np.int32), _i32), _p(_c(S["edges"], np.int32), _i32),
+                               _p(_c(S["body_fixed"], np.uint8), _u8), _p(_c(S["xbar"], np.float64), _d),
+                               _p(_c(x, np.float64), _d), _p(F["xt"], _d), _p(_c(f["lam"], np.float64), _d),
+                               _p(_c(f["T"], np.float64), _d), _p(_c(f["w"], np.float64), _d),
+                               float(params["mu"]), float(eps), _p(e, _d), _p(g, _d), _p(D, _d), _p(O, _d),
+                               _p(keys, _i32), len(keys), int(hess))
+        if r < 0:
+            raise RuntimeError("off-diagonal key missing for a friction pair")
+    return dict(energy=e[0], grad=g, diag=D, off=O[:len(keys)])
+
+
+def friction_energy(S, x, F, params):
+    return friction(S, x, F, params, np.zeros((0, 2), np.int32), hess=False)["energy"]
+
+
+def _with_friction_pairs(pt, ee, F):
+    if F is None:
+        return pt, ee
+    return (np.concatenate([pt, F["pt"]["pairs"]]).astype(np.int32),
+            np.concatenate([ee, F["ee"]["pairs"]]).astype(np.int32))
+
+
 # ------------------------------------------------------ body potentials ----
 
 def orthogonality(S, vol, q, params, project=True, w=None):
@@ -355,37 +425,50 @@ class Body:
         self.M = mass_matrix(self.mass)
 
 
-def total_energy(S, B, q, qt, x, pt, ee, params):
+def total_energy(S, B, q, qt, x, pt, ee, params, F=None):
     e_in, _, _ = inertia(S, B.M, q, qt)
-    return e_in + orthogonality_energy(S, B.vol, q, params) + barrier_energy(S, x, pt, ee, params)
+    e = e_in + orthogonality_energy(S, B.vol, q, params) + barrier_energy(S, x, pt, ee, params)
+    if F is not None:
+        e += friction_energy(S, x, F, params)
+    return e
 
 
-def grad_hess(S, B, q, qt, params, x=None, pt=None, ee=None, project=True):
+def grad_hess(S, B, q, qt, params, x=None, pt=None, ee=None, project=True, F=None):
     """Energy, gradient and (projected) Hessian blocks of the incremental
-    potential E = sum_b E_b + V_C at q."""
+    potential E = sum_b E_b + V_C (+ the lagged friction potential of F) at q.
+    The off-diagonal pattern is that of the candidate pairs and, with
+    friction, of the lagged pairs as well."""
     if x is None:
         x = vertex_map(S, q)
     if pt is None:
         pt, ee = candidates(S, x, None, params["dhat"])
-    keys = off_keys(S, pt, ee)
+    keys = off_keys(S, *_with_friction_pairs(pt, ee, F))
     e_in, g_in, D_in = inertia(S, B.M, q, qt)
     e_o, g_o, D_o = orthogonality(S, B.vol, q, params, project=project)
     bar = barrier(S, x, pt, ee, params, keys, project=project)
-    return dict(energy=e_in + e_o + bar["energy"], grad=g_in + g_o + bar["grad"],
-                diag=D_in + D_o + bar["diag"], off=bar["off"], keys=keys, pt=pt, ee=ee,
-                n_active=bar["n_active"])
+    out = dict(energy=e_in + e_o + bar["energy"], grad=g_in + g_o + bar["grad"],
+               diag=D_in + D_o + bar["diag"], off=bar["off"], keys=keys, pt=pt, ee=ee,
+               n_active=bar["n_active"])
+    if F is not None:
+        fr = friction(S, x, F, params, keys)
+        out["energy"] += fr["energy"]
+        out["grad"] = out["grad"] + fr["grad"]
+        out["diag"] = out["diag"] + fr["diag"]
+        out["off"] = out["off"] + fr["off"]
+    return out
 
 
-def newton_iteration(S, B, q, qt, params):
+def newton_iteration(S, B, q, qt, params, F=None):
     """One projected-Newton iteration with CCD-filtered backtracking line
     search (IPC's scheme, which ABD builds on):
       p = -H^-1 g;  converged if max_k |J_k p|_inf <= tol_v dt;
       swept candidates over x(q) -> x(q+p); alpha = min(1, min_pairs t_ccd);
       halve alpha until E(q + alpha p) <= E(q).
+    F: lagged friction state (friction_lag) or None.
     Returns (q_new, converged, info)."""
     dt = params["dt"]
     x = vertex_map(S, q)
-    gh = grad_hess(S, B, q, qt, params, x=x)
+    gh = grad_hess(S, B, q, qt, params, x=x, F=F)
     p = solve(S, gh["diag"], gh["off"], gh["keys"], -gh["grad"])
     disp = np.abs(vertex_map(S, p)).max() if len(p) else 0.0
     info = dict(n_pt=len(gh["pt"]), n_ee=len(gh["ee"]), n_active=gh["n_active"], disp=disp, p=p,
@@ -395,10 +478,10 @@ def newton_iteration(S, B, q, qt, params):
     x1 = vertex_map(S, q + p)
     pts, ees = candidates(S, x, x1, params["dhat"])
     tpt, tee, alpha = ccd(S, x, x1 - x, pts, ees, params)
-    e0 = total_energy(S, B, q, qt, x, pts, ees, params)
+    e0 = total_energy(S, B, q, qt, x, pts, ees, params, F)
     for _ in range(params["max_ls"]):
         qa = q + alpha * p
-        ea = total_energy(S, B, qa, qt, vertex_map(S, qa), pts, ees, params)
+        ea = total_energy(S, B, qa, qt, vertex_map(S, qa), pts, ees, params, F)
         if ea <= e0:
             break
         alpha *= 0.5
@@ -408,14 +491,25 @@ def newton_iteration(S, B, q, qt, params):
     return q + alpha * p, False, info
 
 
+def step_friction(S, q, params):
+    """Friction state lagged at the step start (None when mu = 0)."""
+    if params.get("mu", 0.0) <= 0.0:
+        return None
+    xt = vertex_map(S, q)
+    pt, ee = candidates(S, xt, None, params["dhat"])
+    return friction_lag(S, xt, pt, ee, params)
+
+
 def time_step(S, B, q, qd, params, log=None):
     """Implicit-Euler time step: minimise the incremental potential starting
-    from q^t; qdot^{t+1} = (q^{t+1} - q^t) / dt."""
+    from q^t; qdot^{t+1} = (q^{t+1} - q^t) / dt.  With mu > 0 the friction
+    state is lagged once at q^t."""
     qt = q_tilde(S, q, qd, params)
+    F = step_friction(S, q, params)
     qn = q.copy()
     its = 0
     for its in range(1, params["max_newton"] + 1):
-        qn, conv, info = newton_iteration(S, B, qn, qt, params)
+        qn, conv, info = newton_iteration(S, B, qn, qt, params, F)
         if log is not None:
             log.append(info)
         if conv:

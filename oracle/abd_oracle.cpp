@@ -871,6 +871,232 @@ double ora_orthogonality_energy(int nb, const uint8_t* fixed, const double* volu
   return esum;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ------------------------------------------------------------ friction ----
+// Lagged friction (ABD sec. 4, friction potential V_F = sum mu lambda_j
+// m_j(q) over the active pairs; details follow IPC's lagged model): at the
+// step start x^t every active pair gets the normal-force magnitude
+// lambda = -kappa m B'(d) (m = EE mollifier, held fixed), the closest-point
+// weights w (the point on each primitive nearest the other, as weights of the
+// 4 vertices with r = sum w_k x_k the closest-point difference) and a tangent
+// basis T (3x2) orthogonal to r.  T: n = r/|r|; t1 = n x e_a / |n x e_a| with
+// e_a the coordinate axis of smallest |n_a| (first on ties); t2 = n x t1.
+void closest_weights(int type, const D3 X[4], double w[4]) {
+  for (int k = 0; k < 4; ++k) w[k] = 0.0;
+  CaseSlots c = case_slots(type);
+  if (c.kind == 0) {
+    w[c.i] = 1.0;
+    w[c.j] = -1.0;
+  } else if (c.kind == 1) {
+    // closest point on the edge's line: parameter t of (x_i - x_j).e / e.e
+    D3 e = sub(X[c.k], X[c.j]);
+    const double t = dot(sub(X[c.i], X[c.j]), e) / dot(e, e);
+    w[c.i] = 1.0;
+    w[c.j] = -(1.0 - t);
+    w[c.k] = -t;
+  } else if (c.kind == 2) {
+    // barycentric coordinates of the projection: normal equations
+    D3 e1 = sub(X[2], X[1]), e2 = sub(X[3], X[1]), dp = sub(X[0], X[1]);
+    const double a = dot(e1, e1), b = dot(e1, e2), cc = dot(e2, e2), f1 = dot(e1, dp), f2 = dot(e2, dp);
+    const double det = a * cc - b * b;
+    const double u = (cc * f1 - b * f2) / det, v = (a * f2 - b * f1) / det;
+    w[0] = 1.0;
+    w[1] = -(1.0 - u - v);
+    w[2] = -u;
+    w[3] = -v;
+  } else {
+    // closest points of the two lines: normal equations
+    D3 u = sub(X[1], X[0]), v = sub(X[3], X[2]), r0 = sub(X[0], X[2]);
+    const double a = dot(u, u), b = dot(u, v), cc = dot(v, v), d = dot(u, r0), e = dot(v, r0);
+    const double den = a * cc - b * b;
+    const double s = (b * e - cc * d) / den, t = (a * e - b * d) / den;
+    w[0] = 1.0 - s;
+    w[1] = s;
+    w[2] = -(1.0 - t);
+    w[3] = -t;
+  }
+}
+
+void tangent_basis(const D3& r, double T[6]) {
+  const double nr = std::sqrt(dot(r, r));
+  const D3 n{r.x / nr, r.y / nr, r.z / nr};
+  const double an[3] = {std::fabs(n.x), std::fabs(n.y), std::fabs(n.z)};
+  int a = 0;
+  if (an[1] < an[a]) a = 1;
+  if (an[2] < an[a]) a = 2;
+  const D3 ea{a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0};
+  D3 t1 = cross(n, ea);
+  const double l1 = std::sqrt(dot(t1, t1));
+  t1 = {t1.x / l1, t1.y / l1, t1.z / l1};
+  const D3 t2 = cross(n, t1);
+  T[0] = t1.x, T[1] = t1.y, T[2] = t1.z;
+  T[3] = t2.x, T[4] = t2.y, T[5] = t2.z;
+}
+
+// IPC's C1 mollified sliding norm with eps = eps_v dt:
+// f0(y) = -y^3/(3 eps^2) + y^2/eps + eps/3 for y < eps, y beyond;
+// f1 = f0' = -y^2/eps^2 + 2y/eps, 1 beyond.
+double friction_f0(double y, double eps) {
+  return y < eps ? -y * y * y / (3.0 * eps * eps) + y * y / eps + eps / 3.0 : y;
+}
+double friction_f1(double y, double eps) { return y < eps ? -y * y / (eps * eps) + 2.0 * y / eps : 1.0; }
+
+}  // namespace
+
+extern "C" {
+
+// lagged quantities per pair at x^t: lambda (0 for inactive pairs), T [n][6]
+// (columns t1, t2), w [n][4]
+void ora_friction_lag(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, const int32_t* edges,
+                      const double* xbar, const double* xt, double dhat, double kappa, double* lam, double* T,
+                      double* w) {
+  const double dhat2 = dhat * dhat;
+  for (int64_t i = 0; i < n; ++i) {
+    int vid[4];
+    pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
+    D3 X[4];
+    for (int k = 0; k < 4; ++k) X[k] = ld3(xt, vid[k]);
+    const int ty = classify(is_ee, X);
+    double num, den;
+    case_nd<double>(ty, X, num, den, 1.0);
+    lam[i] = 0.0;
+    for (int k = 0; k < 6; ++k) T[6 * i + k] = 0.0;
+    for (int k = 0; k < 4; ++k) w[4 * i + k] = 0.0;
+    if (!(num < dhat2 * den) || num == 0.0) continue;
+    const double d = std::sqrt(num / den);
+    const double Bp = -2.0 * (d - dhat) * std::log(d / dhat) - (d - dhat) * (d - dhat) / d;
+    double m = 1.0;
+    if (is_ee) {
+      D3 nn = cross(sub(X[1], X[0]), sub(X[3], X[2]));
+      const double c = dot(nn, nn);
+      const double* a0 = xbar + 3 * vid[0];
+      const double* a1 = xbar + 3 * vid[1];
+      const double* b0 = xbar + 3 * vid[2];
+      const double* b1 = xbar + 3 * vid[3];
+      D3 u{a1[0] - a0[0], a1[1] - a0[1], a1[2] - a0[2]}, v{b1[0] - b0[0], b1[1] - b0[1], b1[2] - b0[2]};
+      const double eps = (1e-3 * dot(u, u)) * dot(v, v);
+      if (c < eps) m = (2.0 - c / eps) * (c / eps);
+    }
+    lam[i] = -kappa * m * Bp;
+    closest_weights(ty, X, w + 4 * i);
+    D3 r{0, 0, 0};
+    for (int k = 0; k < 4; ++k) {
+      const double wk = w[4 * i + k];
+      r = {r.x + wk * X[k].x, r.y + wk * X[k].y, r.z + wk * X[k].z};
+    }
+    tangent_basis(r, T + 6 * i);
+  }
+}
+
+// Friction energy, gradient and Hessian of the lagged pairs at x.
+// u = T^T sum_k w_k (x_k - x^t_k); D = mu lambda f0(|u|);
+// grad = mu lambda f1(|u|)/|u| Gamma u, Hessian = mu lambda Gamma M Gamma^T
+// with Gamma rows 3k..3k+2 = w_k T and
+// M = (f1'(y) y - f1(y))/y^3 u u^T + f1(y)/y I  (y = |u|; M = 2/eps I at y = 0),
+// PSD for this f1.  Accumulated like the barrier (J^T g, J^T H J).
+int64_t ora_friction(int64_t n, int is_ee, const int32_t* pairs, const int32_t* vert_body, const int32_t* tris,
+                     const int32_t* edges, const uint8_t* fixed, const double* xbar, const double* x, const double* xt,
+                     const double* lam, const double* T, const double* w, double mu, double eps, double* energy,
+                     double* grad, double* diag, double* off, const int32_t* off_keys, int64_t n_off, int want_hess) {
+  double esum = 0.0;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(lam[i] > 0.0)) continue;
+    ++cnt;
+    int vid[4];
+    pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
+    double dl[3] = {0, 0, 0};
+    for (int k = 0; k < 4; ++k)
+      for (int c = 0; c < 3; ++c) dl[c] += w[4 * i + k] * (x[3 * vid[k] + c] - xt[3 * vid[k] + c]);
+    const double* Ti = T + 6 * i;
+    const double u[2] = {Ti[0] * dl[0] + Ti[1] * dl[1] + Ti[2] * dl[2], Ti[3] * dl[0] + Ti[4] * dl[1] + Ti[5] * dl[2]};
+    const double y = std::sqrt(u[0] * u[0] + u[1] * u[1]);
+    const double ml = mu * lam[i];
+    esum += ml * friction_f0(y, eps);
+    double M[2][2];
+    double gs;  // f1(y)/y
+    if (y == 0.0) {
+      gs = 2.0 / eps;
+      M[0][0] = M[1][1] = 2.0 / eps;
+      M[0][1] = M[1][0] = 0.0;
+    } else {
+      gs = friction_f1(y, eps) / y;
+      const double f1p = y < eps ? -2.0 * y / (eps * eps) + 2.0 / eps : 0.0;
+      const double a = (f1p * y - friction_f1(y, eps)) / (y * y * y);
+      for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) M[r][c] = a * u[r] * u[c] + (r == c ? gs : 0.0);
+    }
+    // Gamma (12 x 2)
+    double G[12][2];
+    for (int k = 0; k < 4; ++k)
+      for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < 2; ++j) G[3 * k + c][j] = w[4 * i + k] * Ti[3 * j + c];
+    double g[12], H[144];
+    for (int r = 0; r < 12; ++r) g[r] = ml * gs * (G[r][0] * u[0] + G[r][1] * u[1]);
+    for (int r = 0; r < 12; ++r)
+      for (int c = 0; c < 12; ++c) {
+        double s = 0.0;
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) s += G[r][a] * M[a][b] * G[c][b];
+        H[12 * r + c] = ml * s;
+      }
+    // J^T g, J^T H J (same as the barrier)
+    const int ba = vert_body[vid[0]], bo = vert_body[vid[3]];
+    double Jp[12][24];
+    for (int r = 0; r < 12; ++r)
+      for (int c = 0; c < 24; ++c) Jp[r][c] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      const int sl = vert_body[vid[k]] == ba ? 0 : 1;
+      double J[3][12];
+      kin_jacobian(xbar + 3 * vid[k], J);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 12; ++c) Jp[3 * k + r][12 * sl + c] = J[r][c];
+    }
+    const int bodies[2] = {ba, bo};
+    double Gq[24], HH[24][24];
+    for (int c = 0; c < 24; ++c) {
+      double s = 0.0;
+      for (int r = 0; r < 12; ++r) s += Jp[r][c] * g[r];
+      Gq[c] = s;
+    }
+    if (want_hess)
+      for (int c = 0; c < 24; ++c)
+        for (int d = 0; d < 24; ++d) {
+          double s = 0.0;
+          for (int r = 0; r < 12; ++r)
+            for (int t = 0; t < 12; ++t) s += Jp[r][c] * H[r * 12 + t] * Jp[t][d];
+          HH[c][d] = s;
+        }
+    for (int sa = 0; sa < 2; ++sa) {
+      const int b = bodies[sa];
+      if (fixed[b]) continue;
+      for (int c = 0; c < 12; ++c) grad[12 * b + c] += Gq[12 * sa + c];
+      if (want_hess)
+        for (int c = 0; c < 12; ++c)
+          for (int d = 0; d < 12; ++d) diag[144 * b + 12 * c + d] += HH[12 * sa + c][12 * sa + d];
+    }
+    if (want_hess && !fixed[ba] && !fixed[bo] && off) {
+      const int lo = std::min(ba, bo), hi = std::max(ba, bo);
+      const int k = find_off(off_keys, n_off, lo, hi);
+      if (k < 0) return -1;
+      const int sl = (lo == ba) ? 0 : 1, sh = 1 - sl;
+      for (int c = 0; c < 12; ++c)
+        for (int d = 0; d < 12; ++d) off[144 * (int64_t)k + 12 * c + d] += HH[12 * sl + c][12 * sh + d];
+    }
+  }
+  *energy += esum;
+  return cnt;
+}
+
+}  // extern "C"
+
+namespace {
+}  // namespace
+
+extern "C" {
 // Local 12x12 projection entry point (for pins of the eigen routine).
 void ora_psd_project(int n, double* H) { psd_project(n, H); }
 

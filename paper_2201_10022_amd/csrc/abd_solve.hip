@@ -4,11 +4,12 @@
 //
 // Two kernels per iteration.  The first forms the search direction
 // p_new = z + beta p_old on the fly (p is double-buffered, so no block reads
-// a vector another block is writing), multiplies by H and reduces p.Hp; the
-// second updates x, r, z = P r and reduces r.z, r.r.  Each ends with the
-// last block to finish folding the per-block partials in a fixed order and
-// publishing the scalars (alpha; beta and the stop decision), so no
-// separate reduction launches are needed and results are run-to-run
+// a vector another block is writing), multiplies by H (one wave per body)
+// and writes per-block partials of p.Hp; the second updates x, r, z = P r and
+// writes per-block partials of r.z and r.r.  Each kernel starts by folding
+// the previous kernel's partials in a fixed order; every block does the same
+// fold, so all blocks take the same decisions (alpha, beta, stop) without
+// fences, atomics or separate reduction launches, and results are run-to-run
 // reproducible.  Iterations are replayed from a captured hipGraph of ITER_G
 // iterations; once the stop flag is set the remaining kernels return at
 // once, and the host reads the flag once per replay.
@@ -417,19 +418,29 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   int *h;
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
   const int max_rounds = max_iter / ITER_G + 2;
+  // algorithmic HBM bytes of one iteration: every 12x12 block of the
+  // matrix and of the preconditioner once, plus the 12-vectors read and
+  // written by the two kernels (spmv: z, p_old in, p_new, Ap out; update:
+  // p, Ap, x, r in, x, r, z out)
+  const int64_t bytes_it = (2 * (int64_t)nb + n_keys) * 1152 + 11 * 96 * (int64_t)nb;
+  int done = 0;
   for (int round = 0; round < max_rounds; ++round) {
     hipEvent_t pe = prof_begin(ctx, s);
     if (exec)
       HIP_TRY(ctx, hipGraphLaunch(exec, s));
     else
       enqueue(s);
-    prof_end(ctx, pe, "pcg_round", ITER_G, s);
+    prof_end(ctx, pe, "pcg_round", 0, s);
     HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(h, &st->stop, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    // it_done, k_cur, stop, it_final
+    HIP_TRY(ctx, hipMemcpyAsync(h, &st->it_done, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    if (h[0]) break;
+    const int now = h[2] ? h[3] : h[0];
+    if (pe && !ctx->pending.empty()) ctx->pending.back().units = (int64_t)(now - done) * bytes_it;
+    done = now;
+    if (h[2]) break;
   }
-  *iters = h[1];
+  *iters = done;
   return ABD_OK;
 }
 

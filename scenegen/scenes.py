@@ -274,6 +274,24 @@ def icosphere_resting_layer(seed=2, dhat=1e-3):
     return scene, params
 
 
+def cube_on_slope(theta, mu, v0=1.0, gap=5e-4, ground=40.0):
+    """A unit cube (side 1 m, 1000 kg) resting gap above a fixed ground quad,
+    with gravity tilted by theta about z so that the ground is an inclined
+    plane of slope theta falling towards +x; the cube starts sliding down
+    the slope at v0.  No random draws."""
+    v, t = meshes.cube(0.5)
+    gv, gt = meshes.ground_quad(ground)
+    sb = SceneBuilder()
+    sb.add(gv, gt, fixed=True)
+    qd = np.zeros(12)
+    qd[0] = v0
+    sb.add(v, t, p=(-ground / 4.0, 0.5 + gap, 0.0), qd=qd)
+    g = 9.8
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=80.0, mu=mu,
+                            gravity=(g * math.sin(theta), -g * math.cos(theta), 0.0))
+    return sb.build(), params
+
+
 CONFIGS = {
     "three_cubes": three_cubes,
     "icosphere_box": icosphere_box,

@@ -632,3 +632,154 @@ def test_three_cubes_energy_decrease_nonintersection_and_rest():
     m = B.mass[2, 0]
     fy = bar["grad"][2, 1]
     assert fy == pytest.approx(-m * P["dt"] ** 2 * P["gravity"][1] * -1, rel=0.05)
+
+
+# ------------------------------------------------------------- friction ----
+
+def _friction_setup(seed=3):
+    S, P = _near_scene(seed)
+    P = dict(P, mu=0.4)
+    xt = oracle.vertex_map(S, S["q0"])
+    pt, ee = oracle.candidates(S, xt, None, P["dhat"])
+    F = oracle.friction_lag(S, xt, pt, ee, P)
+    return S, P, xt, F
+
+
+def test_friction_lag_closest_points_and_tangent_basis():
+    # r = sum w_k x_k is the closest-point difference: |r| equals the
+    # pair distance, each side's weights are a convex combination (sum 1 on
+    # the first primitive, -1 on the second, magnitudes <= 1); T is an
+    # orthonormal pair orthogonal to r.
+    S, P, xt, F = _friction_setup()
+    n_checked = 0
+    for is_ee, nm in ((0, "pt"), (1, "ee")):
+        f = F[nm]
+        assert len(f["pairs"]) > 0
+        _, d2, _ = oracle.classify(S, xt, f["pairs"], is_ee, P["dhat"])
+        for i, pr in enumerate(f["pairs"]):
+            if is_ee:
+                vid = np.concatenate([S["edges"][pr[0]], S["edges"][pr[1]]])
+                sa = [0, 1]
+            else:
+                vid = np.concatenate([[pr[0]], S["tris"][pr[1]]])
+                sa = [0]
+            w = f["w"][i]
+            r = (w[:, None] * xt[vid]).sum(0)
+            assert np.dot(r, r) == pytest.approx(d2[i], rel=1e-8)
+            sb = [k for k in range(4) if k not in sa]
+            assert w[sa].sum() == pytest.approx(1.0, abs=1e-12)
+            assert w[sb].sum() == pytest.approx(-1.0, abs=1e-12)
+            assert np.all(np.abs(w) <= 1.0 + 1e-12)
+            T = f["T"][i].reshape(2, 3)
+            np.testing.assert_allclose(T @ T.T, np.eye(2), atol=1e-13)
+            np.testing.assert_allclose(T @ r, 0.0, atol=1e-13 * np.linalg.norm(r))
+            n_checked += 1
+    assert n_checked > 10
+
+
+def test_friction_lambda_is_barrier_force_magnitude():
+    # lambda = kappa |dB/dd|: the magnitude of the barrier force on the first
+    # primitive (the sum of the exact barrier gradient over its vertices),
+    # for pairs whose mollifier is 1.
+    S, P, xt, F = _friction_setup()
+    for is_ee, nm in ((0, "pt"), (1, "ee")):
+        f = F[nm]
+        for i, pr in enumerate(f["pairs"]):
+            if is_ee:
+                vid = np.concatenate([S["edges"][pr[0]], S["edges"][pr[1]]])
+                ua, ub = S["xbar"][vid[1]] - S["xbar"][vid[0]], S["xbar"][vid[3]] - S["xbar"][vid[2]]
+                X = xt[vid]
+                c = np.linalg.norm(np.cross(X[1] - X[0], X[3] - X[2])) ** 2
+                if c < 1e-3 * ua.dot(ua) * ub.dot(ub):
+                    continue
+                side = [0, 1]
+            else:
+                vid = np.concatenate([[pr[0]], S["tris"][pr[1]]])
+                side = [0]
+            _, _, g, _ = oracle.pair_local(is_ee, xt[vid], S["xbar"][vid], P["dhat"], P["kappa_b"])
+            force = g.reshape(4, 3)[side].sum(0)
+            assert f["lam"][i] == pytest.approx(np.linalg.norm(force), rel=1e-9)
+
+
+@pytest.mark.parametrize("scale", [0.3, 3.0])
+def test_friction_q_gradient_and_hessian_by_fd(scale):
+    # sliding displacements below (0.3) and beyond (3) eps_v dt: the
+    # gradient is the derivative of the friction energy, the Hessian the
+    # derivative of the gradient (exact and PSD for this f1), both through
+    # the affine map x(q).
+    S, P, xt, F = _friction_setup()
+    rng = np.random.default_rng(7)
+    eps = P["eps_v"] * P["dt"]
+    free = np.flatnonzero(S["body_fixed"] == 0)
+    q0 = S["q0"].copy()
+    for b in free:
+        d = rng.normal(size=3)
+        d[1] = 0.0
+        q0[b, :3] += scale * eps * d / np.linalg.norm(d)
+        q0[b, 3:] += rng.normal(size=9) * 1e-7
+    x0 = oracle.vertex_map(S, q0)
+    pt, ee = oracle.candidates(S, xt, None, P["dhat"])
+    keys = oracle.off_keys(S, pt, ee)
+    r = oracle.friction(S, x0, F, P, keys)
+    assert r["energy"] > 0
+
+    def energy(q):
+        return oracle.friction_energy(S, oracle.vertex_map(S, q), F, P)
+
+    def grad(q):
+        return oracle.friction(S, oracle.vertex_map(S, q), F, P, keys, hess=False)["grad"]
+
+    h = 1e-10
+    gs = np.abs(r["grad"]).max()
+    hs = np.abs(r["diag"]).max()
+    for b in free:
+        for c in range(12):
+            qp, qm = q0.copy(), q0.copy()
+            qp[b, c] += h
+            qm[b, c] -= h
+            fd = (energy(qp) - energy(qm)) / (2 * h)
+            assert fd == pytest.approx(r["grad"][b, c], abs=1e-5 * gs)
+            col = (grad(qp) - grad(qm)) / (2 * h)
+            np.testing.assert_allclose(r["diag"][b].reshape(12, 12)[:, c], col[b], atol=1e-4 * hs)
+            for k, (a1, b1) in enumerate(keys):
+                O = r["off"][k].reshape(12, 12)
+                if b == b1:
+                    np.testing.assert_allclose(O[:, c], col[a1], atol=1e-4 * hs)
+                if b == a1:
+                    np.testing.assert_allclose(O.T[:, c], col[b1], atol=1e-4 * hs)
+    # the assembled friction Hessian is PSD
+    Hd = oracle.assemble(S, r["diag"], r["off"], keys)[0].toarray()
+    w = np.linalg.eigvalsh(0.5 * (Hd + Hd.T))
+    assert w.min() >= -1e-10 * np.abs(w).max()
+
+
+def _slide(theta, mu, v0, n):
+    S, P = sg.cube_on_slope(theta, mu, v0=v0)
+    B = oracle.Body(S)
+    q, qd = S["q0"].copy(), S["qd0"].copy()
+    vs = []
+    for _ in range(n):
+        q, qd, _ = oracle.time_step(S, B, q, qd, P)
+        vs.append(qd[1, :3].copy())
+    return P, np.array(vs)
+
+
+def test_friction_slope_sliding_acceleration_closed_form():
+    # Coulomb sliding on an inclined plane: a = g (sin theta - mu cos theta)
+    # along the slope (eps_v dt is far below the per-step slide, so f1 = 1).
+    theta, mu = math.atan(0.75), 0.5
+    P, vs = _slide(theta, mu, 1.0, 40)
+    a = (vs[-1, 0] - vs[10, 0]) / ((len(vs) - 1 - 10) * P["dt"])
+    assert a == pytest.approx(9.8 * (math.sin(theta) - mu * math.cos(theta)), rel=1e-3)
+    assert np.abs(vs[10:, 2]).max() < 1e-6
+
+
+def test_friction_slope_static_creep_closed_form():
+    # tan theta < mu: the cube stops; the smoothed static friction then
+    # holds it with f1(|u|) = tan theta / mu, i.e. a creep speed of
+    # eps_v (1 - sqrt(1 - tan theta / mu)) below eps_v.
+    theta, mu = math.atan(0.75), 0.9
+    P, vs = _slide(theta, mu, 0.3, 60)
+    creep = P["eps_v"] * (1.0 - math.sqrt(1.0 - 0.75 / mu))
+    assert vs[-1, 0] == pytest.approx(creep, rel=1e-2)
+    assert vs[-10:, 0].max() < P["eps_v"]

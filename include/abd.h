@@ -105,6 +105,7 @@ typedef struct abd_stats {
   double disp;                    /* max_k |J_k p|_inf of the Newton direction */
   double energy0, energy1;        /* E(q), E(q + alpha p) */
   double t_barrier_ms, t_ccd_ms, t_candidates_ms, t_solve_ms, t_total_ms;
+  int64_t n_friction;             /* lagged friction pairs in use */
 } abd_stats;
 
 int abd_create(abd_ctx **ctx, int device);
@@ -221,13 +222,61 @@ int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, do
 int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot,
                   abd_stats *stats, hipStream_t stream);
 
+/* Lagged friction (sec. 4, friction potential V_F = sum of mu lambda f0 over
+ * the active contact pairs; lagging as in IPC): quantities held fixed over a
+ * time step are taken at the step-start positions xt.
+ *
+ * abd_friction_lag: for each pair (PT pairs then EE pairs, one combined
+ * index i in [0, n_pt + n_ee)) at positions xt: lambda [n] = kappa_b m |B'(d)|
+ * (m the EE mollifier of abd_barrier_grad_hess; 0 for inactive pairs, i.e.
+ * d >= dhat, whose T and w are zero), the closest-point weights w [n][4]
+ * over the pair's vertex slots (r = sum_k w_k x_k is the closest-point
+ * difference; w = (1, -1) on the two closest vertices for point-point
+ * cases, (1, -(1-t), -t) for a point against an edge, (1, -b0, -b1, -b2)
+ * with barycentric b for point-face, (1-s, s, -(1-t), -t) for line-line) and
+ * the tangent basis T [n][6] = (t1, t2): with n = r/|r| and e_a the
+ * coordinate axis of smallest |n_a| (first on ties), t1 = n x e_a normalised,
+ * t2 = n x t1. */
+int abd_friction_lag(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *xt,
+                     const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *lam, double *T,
+                     double *w, hipStream_t stream);
+
+/* Friction energy, gradient and Hessian at x of lagged pairs (arrays as
+ * written by abd_friction_lag at xt; pairs with lambda <= 0 contribute
+ * nothing): u = T^T sum_k w_k (x_k - xt_k), energy mu lambda f0(|u|) with
+ * f0(y) = -y^3/(3 eps^2) + y^2/eps + eps/3 for y < eps = eps_v dt, else y;
+ * local gradient and Hessian (exact, PSD) mapped by J^T . J and accumulated
+ * like abd_barrier_grad_hess (energy [1] may be NULL; diag/off may be NULL;
+ * keys must cover the pairs' body pairs). */
+int abd_friction_grad_hess(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
+                           const double *xt, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
+                           const double *lam, const double *T, const double *w, const int32_t *keys, int64_t n_keys,
+                           double *energy, double *grad, double *diag, double *off, hipStream_t stream);
+
+/* Friction energy only (line search), accumulated into energy [1]. */
+int abd_friction_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const double *xt,
+                        const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, const double *lam,
+                        const double *T, const double *w, double *energy, hipStream_t stream);
+
+/* Friction state of a time step, held by the context: begin_step lags the
+ * active pairs at x(q) (candidates within dhat, lambda > 0 kept, in
+ * candidate order) and makes every later abd_newton_step include their
+ * friction potential (when prm->mu > 0) and their body pairs in the
+ * off-diagonal pattern, until end_step.  abd_time_step begins (when
+ * mu > 0) and ends its own state.  begin_step syncs; *n_pairs (host, may be
+ * NULL) receives the number of lagged pairs. */
+int abd_friction_begin_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
+                            int64_t *n_pairs, hipStream_t stream);
+int abd_friction_end_step(abd_ctx *ctx);
+
 /* Kernel timing with HIP events on the calls' streams, for measurement:
  * abd_profile(enable, reset) switches recording on/off (reset clears the
  * totals); abd_profile_query returns, for one instrumented kernel
- * ("barrier_local", "assemble_chunks", "energy_only", "accd",
+ * ("barrier_local", "friction_local", "assemble_chunks", "energy_only", "accd",
  * "pair_tiles_write", "pcg_round"), the summed duration in ms, the number of
  * launches and the work units processed (active pairs, records, pairs,
- * pairs, tiles; for "pcg_round", one replay of the captured PCG iterations,
+ * pairs, tiles; friction pairs for "friction_local"; for "pcg_round", one
+ * replay of the captured PCG iterations,
  * the algorithmic HBM bytes of the iterations it executed).
  * Query synchronises the device. */
 int abd_profile(abd_ctx *ctx, int enable, int reset);

@@ -241,6 +241,52 @@ class Context:
                                          ctypes.byref(st), _stream()))
         return st.as_dict()
 
+    # -- friction --------------------------------------------------------
+    def friction_lag(self, scene, params, xt, pt, ee):
+        """Per pair (PT then EE) lambda [n], T [n,6], w [n,4] at xt."""
+        n = pt.shape[0] + ee.shape[0]
+        dev = xt.device
+        lam = torch.zeros(n, dtype=torch.float64, device=dev)
+        T = torch.zeros((n, 6), dtype=torch.float64, device=dev)
+        w = torch.zeros((n, 4), dtype=torch.float64, device=dev)
+        prm = make_params(params)
+        self._check(self.L.abd_friction_lag(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(xt), _ptr(pt),
+                                            pt.shape[0], _ptr(ee), ee.shape[0], _ptr(lam), _ptr(T), _ptr(w),
+                                            _stream()))
+        return lam, T, w
+
+    def friction_grad_hess(self, scene, params, x, xt, pt, ee, lam, T, w, keys, hessian=True):
+        nb = scene.n_bodies
+        dev = x.device
+        energy = torch.zeros(1, dtype=torch.float64, device=dev)
+        grad = torch.zeros((nb, 12), dtype=torch.float64, device=dev)
+        diag = torch.zeros((nb, 144), dtype=torch.float64, device=dev) if hessian else None
+        off = torch.zeros((max(keys.shape[0], 1), 144), dtype=torch.float64, device=dev) if hessian else None
+        prm = make_params(params)
+        self._check(self.L.abd_friction_grad_hess(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(x),
+                                                  _ptr(xt), _ptr(pt), pt.shape[0], _ptr(ee), ee.shape[0], _ptr(lam),
+                                                  _ptr(T), _ptr(w), _ptr(keys), keys.shape[0], _ptr(energy),
+                                                  _ptr(grad), _ptr(diag), _ptr(off), _stream()))
+        return energy, grad, diag, (off[:keys.shape[0]] if hessian else None)
+
+    def friction_energy(self, scene, params, x, xt, pt, ee, lam, T, w):
+        energy = torch.zeros(1, dtype=torch.float64, device=x.device)
+        prm = make_params(params)
+        self._check(self.L.abd_friction_energy(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(x), _ptr(xt),
+                                               _ptr(pt), pt.shape[0], _ptr(ee), ee.shape[0], _ptr(lam), _ptr(T),
+                                               _ptr(w), _ptr(energy), _stream()))
+        return energy
+
+    def friction_begin_step(self, scene, params, q):
+        n = ctypes.c_int64(0)
+        prm = make_params(params)
+        self._check(self.L.abd_friction_begin_step(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q),
+                                                   ctypes.byref(n), _stream()))
+        return n.value
+
+    def friction_end_step(self):
+        self._check(self.L.abd_friction_end_step(self.h))
+
     # -- measurement ---------------------------------------------------
     def profile(self, enable=True, reset=True):
         self._check(self.L.abd_profile(self.h, int(enable), int(reset)))

@@ -13,7 +13,9 @@ ERRORS = {-1: "ABD_E_INVALID", -2: "ABD_E_CAPACITY", -3: "ABD_E_INTERSECT", -4: 
 EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_body_mass", "abd_vertex_map", "abd_candidates",
            "abd_offdiag_pattern", "abd_classify", "abd_barrier_grad_hess", "abd_barrier_energy",
            "abd_ccd_max_step", "abd_orthogonality", "abd_inertia", "abd_q_tilde", "abd_pcg_solve",
-           "abd_newton_step", "abd_time_step", "abd_profile", "abd_profile_query"]
+           "abd_newton_step", "abd_time_step", "abd_friction_lag", "abd_friction_grad_hess",
+           "abd_friction_energy", "abd_friction_begin_step", "abd_friction_end_step", "abd_profile",
+           "abd_profile_query"]
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -42,7 +44,8 @@ class AbdStats(ctypes.Structure):
                 ("n_pt_swept", _i64), ("n_ee_swept", _i64), ("n_offdiag", _i64), ("pcg_iters", _i32),
                 ("ls_halvings", _i32), ("converged", _i32), ("newton_iters", _i32), ("alpha_ccd", _dbl),
                 ("alpha", _dbl), ("disp", _dbl), ("energy0", _dbl), ("energy1", _dbl), ("t_barrier_ms", _dbl),
-                ("t_ccd_ms", _dbl), ("t_candidates_ms", _dbl), ("t_solve_ms", _dbl), ("t_total_ms", _dbl)]
+                ("t_ccd_ms", _dbl), ("t_candidates_ms", _dbl), ("t_solve_ms", _dbl), ("t_total_ms", _dbl),
+                ("n_friction", _i64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,6 +74,12 @@ SIGNATURES = {
     "abd_pcg_solve": ([_vp, _PS, _vp, _vp, _vp, _i64, _vp, _vp, _dbl, _i32, _pi32, _vp], ctypes.c_int),
     "abd_newton_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
     "abd_time_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
+    "abd_friction_lag": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "abd_friction_grad_hess": ([_vp, _PS, _PP, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
+                                _vp, _vp, _vp], ctypes.c_int),
+    "abd_friction_energy": ([_vp, _PS, _PP, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "abd_friction_begin_step": ([_vp, _PS, _PP, _vp, _pi64, _vp], ctypes.c_int),
+    "abd_friction_end_step": ([_vp], ctypes.c_int),
     "abd_profile": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "abd_profile_query": ([_vp, ctypes.c_char_p, ctypes.POINTER(_dbl), _pi64, _pi64], ctypes.c_int),
 }

@@ -397,8 +397,9 @@ __global__ void k_unique_write(int64_t n, const uint64_t *k, const int64_t *flag
 }  // namespace
 
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
-               int32_t **keys_out, int64_t *n_keys, const char *tag, hipStream_t s) {
-  const int64_t n = n_pt + n_ee;
+               int32_t **keys_out, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2,
+               int64_t n_pt2, const int32_t *ee2, int64_t n_ee2) {
+  const int64_t n = n_pt + n_ee + n_pt2 + n_ee2;
   *n_keys = 0;
   std::string nm = std::string(tag) + "_keys";
   ABD_TRY(ws(ctx, nm.c_str(), 2 * n + 2, keys_out, s));
@@ -410,12 +411,15 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   ABD_TRY(ws(ctx, "od_flag", n, &flag, s));
   ABD_TRY(ws(ctx, "od_pos", n, &pos, s));
   ABD_TRY(ws(ctx, "od_tot", 1, &tot, s));
-  if (n_pt)
-    hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(n_pt, 256)), dim3(256), 0, s, n_pt, 0, pt, sc->vert_body,
-                       sc->tri_body, sc->edge_body, sc->body_fixed, k);
-  if (n_ee)
-    hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(n_ee, 256)), dim3(256), 0, s, n_ee, 1, ee, sc->vert_body,
-                       sc->tri_body, sc->edge_body, sc->body_fixed, k + n_pt);
+  const int32_t *lists[4] = {pt, ee, pt2, ee2};
+  const int64_t counts[4] = {n_pt, n_ee, n_pt2, n_ee2};
+  int64_t at = 0;
+  for (int l = 0; l < 4; ++l) {
+    if (counts[l] > 0)
+      hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(counts[l], 256)), dim3(256), 0, s, counts[l], l & 1, lists[l],
+                         sc->vert_body, sc->tri_body, sc->edge_body, sc->body_fixed, k + at);
+    at += counts[l];
+  }
   size_t tmp_bytes = 0;
   HIP_TRY(ctx, rocprim::radix_sort_keys(nullptr, tmp_bytes, k, k2, (size_t)n, 0, 64, s));
   void *tmp;

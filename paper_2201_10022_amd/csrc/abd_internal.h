@@ -46,6 +46,10 @@ struct abd_ctx {
   hipGraphExec_t pcg_exec = nullptr;
   std::vector<uintptr_t> pcg_key;
   hipStream_t capture_stream = nullptr;
+  // friction lagged at the start of the current time step (set by
+  // abd_friction_begin_step, used by the Newton iterations while set)
+  bool fr_set = false;
+  int64_t fr_n_pt = 0, fr_n_ee = 0;
 };
 
 // instrumentation: prof_begin returns an event recorded before the launch
@@ -83,17 +87,58 @@ int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n,
 // Stable sort of (key, value) pairs by key (keys in [0, 2^key_bits)).
 int sort_pairs_u32(abd_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, hipStream_t s);
 
+// ----------------------------------------------------- pair records ----
+// Local record of a pair whose 12x12 Hessian and 12-gradient are assembled
+// into body blocks (barrier and friction share the assembly).
+struct alignas(16) PairInfo {
+  int32_t vid[4];
+  int32_t body[2];  // body of slot 0 and of slot 3
+  int32_t is_ee;
+  int32_t pad;
+};
+
+// Lagged friction pairs: PT pairs then EE pairs, per pair (in that combined
+// order) lambda [n], tangent basis T [n][6] (columns t1, t2), closest-point
+// weights w [n][4]; xt the vertex positions they were lagged at.
+struct FrictionSet {
+  const int32_t *pt = nullptr, *ee = nullptr;
+  int64_t n_pt = 0, n_ee = 0;
+  const double *lam = nullptr, *T = nullptr, *w = nullptr, *xt = nullptr;
+  double mu = 0.0, eps = 0.0;
+  int64_t n() const { return n_pt + n_ee; }
+};
+
 // ------------------------------------------------- internal operations ----
 // (shared by the ABI wrappers and the Newton driver)
 int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t s);
 int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1, double inflate,
                   int32_t **pt, int64_t *n_pt, int32_t **ee, int64_t *n_ee, const char *tag, hipStream_t s);
+// pattern of the pairs (pt, ee) and, when given, the extra pairs (pt2, ee2)
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
-               int32_t **keys, int64_t *n_keys, const char *tag, hipStream_t s);
+               int32_t **keys, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2 = nullptr,
+               int64_t n_pt2 = 0, const int32_t *ee2 = nullptr, int64_t n_ee2 = 0);
+// barrier (and, when fr is given, the lagged friction of fr) energy,
+// gradient and Hessian blocks, assembled in one pass
 int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                int64_t n_pt, const int32_t *ee, int64_t n_ee, const int32_t *keys, int64_t n_keys, double *energy,
                double *grad, double *diag, double *off, int project, int64_t *n_active_pt, int64_t *n_active_ee,
-               hipStream_t s);
+               hipStream_t s, const FrictionSet *fr = nullptr);
+// fixed-order assembly of n local records (info, g_loc [n][12], H_loc
+// [n][78] packed symmetric) into grad / diag / off (accumulated)
+int op_assemble(abd_ctx *ctx, const abd_scene *sc, int64_t n, const PairInfo *info, const double *g_loc,
+                const double *H_loc, const int32_t *keys, int64_t n_keys, double *grad, double *diag, double *off,
+                hipStream_t s);
+// friction: lagged quantities of candidate pairs at xt; local records of
+// the pairs of fr at x (written at e/g/H/info); energy of fr at x
+int op_friction_lag(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *xt, const int32_t *pt,
+                    int64_t n_pt, const int32_t *ee, int64_t n_ee, double *lam, double *T, double *w, hipStream_t s);
+int op_friction_local(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x, double *e_loc,
+                      double *g_loc, double *H_loc, PairInfo *info, hipStream_t s);
+int op_friction_energy(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x, double *energy,
+                       hipStream_t s);
+// the friction state of the current time step (null when none is set)
+int op_friction_state(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, FrictionSet *fr, bool *active,
+                      hipStream_t s);
 int op_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                       int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy, hipStream_t s);
 int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x0, const double *dx,

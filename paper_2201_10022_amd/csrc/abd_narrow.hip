@@ -70,14 +70,6 @@ __global__ void k_compact(int64_t n, const int64_t *flag, const int64_t *pos, in
   if (i < n && flag[i]) out[pos[i]] = (int32_t)i;
 }
 
-// Local record of an active pair
-struct alignas(16) PairInfo {
-  int32_t vid[4];
-  int32_t body[2];  // body of slot 0 and of slot 3
-  int32_t is_ee;
-  int32_t pad;
-};
-
 __global__ void __launch_bounds__(64) k_barrier_local(const int64_t *n_act_dev, const int32_t *act, int64_t n_pt,
                                                       const int32_t *pt, const int32_t *ee, const int32_t *tris,
                                                       const int32_t *edges, const int32_t *vert_body,
@@ -144,11 +136,10 @@ __device__ __forceinline__ int find_key(const int32_t *keys, int64_t n, int a, i
 // records: key = block id (diag b -> b, off k -> nb + k), val = 4 a + role
 //   role 0 diag of slot-0 body, 1 diag of slot-1 body,
 //   2 off block with rows = slot-0 body, 3 off block with rows = slot-1 body
-__global__ void k_records(const int64_t *n_act_dev, const PairInfo *info, const uint8_t *fixed, int nb,
-                          const int32_t *keys, int64_t n_keys, uint32_t *rkey, uint32_t *rval, int want_off,
-                          int *err) {
+__global__ void k_records(int64_t n, const PairInfo *info, const uint8_t *fixed, int nb, const int32_t *keys,
+                          int64_t n_keys, uint32_t *rkey, uint32_t *rval, int want_off, int *err) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= *n_act_dev) return;
+  if (a >= n) return;
   const PairInfo pi = info[a];
   const int b0 = pi.body[0], b1 = pi.body[1];
   const bool f0 = fixed[b0] != 0, f1 = fixed[b1] != 0;
@@ -340,11 +331,12 @@ __global__ void k_energy_only(int64_t n_pt, int64_t n, const int32_t *pt, const 
 int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                int64_t n_pt, const int32_t *ee, int64_t n_ee, const int32_t *keys, int64_t n_keys, double *energy,
                double *grad, double *diag, double *off, int project, int64_t *n_active_pt, int64_t *n_active_ee,
-               hipStream_t s) {
+               hipStream_t s, const FrictionSet *fr) {
   const int64_t n = n_pt + n_ee;
+  const int64_t nf = fr ? fr->n() : 0;
   if (n_active_pt) *n_active_pt = 0;
   if (n_active_ee) *n_active_ee = 0;
-  if (n == 0) return ABD_OK;
+  if (n + nf == 0) return ABD_OK;
   const double dhat = prm->dhat, dhat2 = dhat * dhat;
   int64_t *flag, *pos, *nact;
   int32_t *act;
@@ -354,45 +346,60 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   ABD_TRY(ws(ctx, "br_nact", 2, &nact, s));
   ABD_TRY(ws(ctx, "br_act", n, &act, s));
   ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
-  hipLaunchKernelGGL(k_active_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges,
-                     x, dhat2, flag);
-  ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, nact, s));
-  hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, n, flag, pos, act);
-  // active counts (PT part = pos[n_pt] if n_pt < n)
-  int64_t *hbuf;
-  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
-  HIP_TRY(ctx, hipMemcpyAsync(hbuf, nact, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  if (n_ee > 0) HIP_TRY(ctx, hipMemcpyAsync(hbuf + 1, pos + n_pt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  const int64_t na = hbuf[0];
-  const int64_t na_pt = n_ee > 0 ? hbuf[1] : na;
+  int64_t na = 0, na_pt = 0;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_active_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges,
+                       x, dhat2, flag);
+    ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, nact, s));
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, n, flag, pos, act);
+    // active counts (PT part = pos[n_pt] if n_pt < n)
+    int64_t *hbuf;
+    ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
+    HIP_TRY(ctx, hipMemcpyAsync(hbuf, nact, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (n_ee > 0) HIP_TRY(ctx, hipMemcpyAsync(hbuf + 1, pos + n_pt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    na = hbuf[0];
+    na_pt = n_ee > 0 ? hbuf[1] : na;
+  }
   if (n_active_pt) *n_active_pt = na_pt;
   if (n_active_ee) *n_active_ee = na - na_pt;
-  if (na == 0) return ABD_OK;
+  const int64_t nl = na + nf;  // local records: active barrier pairs, then friction pairs
+  if (nl == 0) return ABD_OK;
 
   double *e_loc, *g_loc, *H_loc;
   PairInfo *info;
-  ABD_TRY(ws(ctx, "br_e", na, &e_loc, s));
-  ABD_TRY(ws(ctx, "br_g", 12 * na, &g_loc, s));
-  ABD_TRY(ws(ctx, "br_H", 78 * na, &H_loc, s));
-  ABD_TRY(ws(ctx, "br_info", na, &info, s));
-  hipEvent_t pe = prof_begin(ctx, s);
-  hipLaunchKernelGGL(k_barrier_local, dim3(grid_for(na, 64)), dim3(64), 0, s, nact, act, n_pt, pt, ee, sc->tris,
-                     sc->edges, sc->vert_body, x, sc->xbar, dhat, prm->kappa_b, project, e_loc, g_loc, H_loc, info,
-                     err);
-  prof_end(ctx, pe, "barrier_local", na, s);
-  HIP_TRY(ctx, hipGetLastError());
-  if (energy) ABD_TRY(reduce_sum_f64(ctx, e_loc, na, energy, s));
+  ABD_TRY(ws(ctx, "br_e", nl, &e_loc, s));
+  ABD_TRY(ws(ctx, "br_g", 12 * nl, &g_loc, s));
+  ABD_TRY(ws(ctx, "br_H", 78 * nl, &H_loc, s));
+  ABD_TRY(ws(ctx, "br_info", nl, &info, s));
+  if (na > 0) {
+    hipEvent_t pe = prof_begin(ctx, s);
+    hipLaunchKernelGGL(k_barrier_local, dim3(grid_for(na, 64)), dim3(64), 0, s, nact, act, n_pt, pt, ee, sc->tris,
+                       sc->edges, sc->vert_body, x, sc->xbar, dhat, prm->kappa_b, project, e_loc, g_loc, H_loc, info,
+                       err);
+    prof_end(ctx, pe, "barrier_local", na, s);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  if (nf > 0) ABD_TRY(op_friction_local(ctx, sc, fr, x, e_loc + na, g_loc + 12 * na, H_loc + 78 * na, info + na, s));
+  if (energy) ABD_TRY(reduce_sum_f64(ctx, e_loc, nl, energy, s));
   if (!grad && !diag && !off) return ABD_OK;
+  return op_assemble(ctx, sc, nl, info, g_loc, H_loc, keys, n_keys, grad, diag, off, s);
+}
 
-  // records -> stable sort by block -> chunked fixed-order reduction
+// records -> stable sort by block -> chunked fixed-order reduction
+int op_assemble(abd_ctx *ctx, const abd_scene *sc, int64_t n, const PairInfo *info, const double *g_loc,
+                const double *H_loc, const int32_t *keys, int64_t n_keys, double *grad, double *diag, double *off,
+                hipStream_t s) {
+  if (n == 0) return ABD_OK;
+  int *err;
+  ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
   const int nb = sc->n_bodies;
-  const int64_t nrec = 3 * na;
+  const int64_t nrec = 3 * n;
   const int64_t nblocks = nb + n_keys;
   uint32_t *rkey, *rval;
   ABD_TRY(ws(ctx, "br_rkey", nrec, &rkey, s));
   ABD_TRY(ws(ctx, "br_rval", nrec, &rval, s));
-  hipLaunchKernelGGL(k_records, dim3(grid_for(na, 256)), dim3(256), 0, s, nact, info, sc->body_fixed, nb, keys, n_keys,
+  hipLaunchKernelGGL(k_records, dim3(grid_for(n, 256)), dim3(256), 0, s, n, info, sc->body_fixed, nb, keys, n_keys,
                      rkey, rval, off != nullptr ? 1 : 0, err);
   ABD_TRY(sort_pairs_u32(ctx, rkey, rval, nrec, 32, s));
   int64_t *bstart, *nchunk, *choff, *nch_tot;
@@ -407,7 +414,7 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   const int64_t max_chunks = (nrec + RCH - 1) / RCH + nblocks;
   double *partial;
   ABD_TRY(ws(ctx, "br_partial", (size_t)NENT * max_chunks, &partial, s));
-  pe = prof_begin(ctx, s);
+  hipEvent_t pe = prof_begin(ctx, s);
   hipLaunchKernelGGL(k_assemble_chunks, dim3((unsigned)max_chunks), dim3(64), 0, s, nblocks, choff, nch_tot, bstart,
                      rval, info, g_loc, H_loc, sc->xbar, partial);
   prof_end(ctx, pe, "assemble_chunks", nrec, s);

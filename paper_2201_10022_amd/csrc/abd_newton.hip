@@ -59,12 +59,13 @@ int read_err(abd_ctx *ctx, hipStream_t s) {
 
 // E(q) over the given (swept) candidates; result in *h (host)
 int energy_at(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
-              double *x, const int32_t *pt, int64_t npt, const int32_t *ee, int64_t nee, double *e_dev, double *out,
-              hipStream_t s) {
+              double *x, const int32_t *pt, int64_t npt, const int32_t *ee, int64_t nee, const FrictionSet *fr,
+              double *e_dev, double *out, hipStream_t s) {
   ABD_TRY(zero(ctx, e_dev, 1, s));
   ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
   ABD_TRY(op_body_energy(ctx, sc, prm, q, qt, e_dev, s));
   ABD_TRY(op_barrier_energy(ctx, sc, prm, x, pt, npt, ee, nee, e_dev, s));
+  if (fr) ABD_TRY(op_friction_energy(ctx, sc, fr, x, e_dev, s));
   double *h;
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
   HIP_TRY(ctx, hipMemcpyAsync(h + 2, e_dev, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -92,13 +93,22 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   double *h;
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
 
+  // lagged friction of the current time step, if any
+  FrictionSet frs;
+  bool fr_on = false;
+  ABD_TRY(op_friction_state(ctx, sc, prm, &frs, &fr_on, s));
+  const FrictionSet *fr = fr_on ? &frs : nullptr;
+  st->n_friction = fr_on ? frs.n() : 0;
+
   // gradient and projected Hessian at q
   auto t0 = std::chrono::steady_clock::now();
   ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
   int32_t *pt, *ee, *keys;
   int64_t npt, nee, nk;
   ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s));
-  ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", s));
+  // the pattern covers the candidates and the lagged friction pairs
+  ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", s, fr ? fr->pt : nullptr, fr ? fr->n_pt : 0,
+                     fr ? fr->ee : nullptr, fr ? fr->n_ee : 0));
   st->n_pt = npt;
   st->n_ee = nee;
   st->n_offdiag = nk;
@@ -111,7 +121,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   t0 = std::chrono::steady_clock::now();
   ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, e, g, diag, 1, s));
   int64_t nap = 0, nae = 0;
-  ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 1, &nap, &nae, s));
+  ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 1, &nap, &nae, s, fr));
   ABD_TRY(read_err(ctx, s));
   st->t_barrier_ms += ms_since(t0);
   st->n_active_pt = nap;
@@ -161,11 +171,11 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
 
   // backtracking line search
   double e0, e1 = 0.0;
-  ABD_TRY(energy_at(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, e + 3, &e0, s));
+  ABD_TRY(energy_at(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, fr, e + 3, &e0, s));
   int k = 0;
   for (; k < prm->max_ls; ++k) {
     hipLaunchKernelGGL(k_axpy, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, q, alpha, p, qa);
-    ABD_TRY(energy_at(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, e + 3, &e1, s));
+    ABD_TRY(energy_at(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e + 3, &e1, s));
     if (e1 <= e0) break;
     alpha *= 0.5;
   }
@@ -202,7 +212,15 @@ extern "C" int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params
   ABD_TRY(ws(ctx, "ts_qo", n12, &qo, stream));
   ABD_TRY(abd_q_tilde(ctx, sc, prm, q, qdot, qt, stream));
   HIP_TRY(ctx, hipMemcpyAsync(qo, q, sizeof(double) * n12, hipMemcpyDeviceToDevice, stream));
+  // friction lagged once at q^t, released when the step returns
+  struct FrictionScope {
+    abd_ctx *c;
+    ~FrictionScope() { abd_friction_end_step(c); }
+  } fr_scope{ctx};
+  int64_t n_fr = 0;
+  if (prm->mu > 0.0) ABD_TRY(abd_friction_begin_step(ctx, sc, prm, q, &n_fr, stream));
   abd_stats total = {};
+  total.n_friction = n_fr;
   int it = 0;
   bool conv = false;
   for (; it < prm->max_newton; ++it) {

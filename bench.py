@@ -107,7 +107,7 @@ def main():
     import paper_2201_10022_amd as abd
 
     S, P = sg.icosphere_box()
-    P = dict(P, mu=0.0, max_pcg=2000)
+    P = dict(P, max_pcg=2000)
     ctx, sc = abd.setup(S, 0)
     q = torch.as_tensor(S["q0"], device="cuda:0")
     qd = torch.as_tensor(S["qd0"], device="cuda:0")
@@ -121,14 +121,6 @@ def main():
                       f"{time.perf_counter() - t0:.1f}s")
     for i in range(args.warmup):
         ctx.time_step(sc, P, q, qd)
-    if args.calib_copy_mib:
-        n = args.calib_copy_mib * (1 << 20) // 8
-        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    ctx.profile(True, reset=True)
     torch.cuda.synchronize()
     if args.start_at > 0:
         import psutil
@@ -136,7 +128,19 @@ def main():
         if wait < 0:
             log(args, f"--start-at {args.start_at}: already {-wait:.1f} s late")
         time.sleep(max(wait, 0.0))
-    tot = dict(newton=0, active=0, ccd=0, pcg=0)
+    if args.calib_copy_mib:
+        # one plain device copy of known size (read + write), untimed, so
+        # that HBM counters can be scaled against it
+        n = args.calib_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    ctx.profile(True, reset=True)
+    torch.cuda.synchronize()
+    tot = dict(newton=0, active=0, ccd=0, pcg=0, friction=0)
     t0 = time.perf_counter()
     for i in range(args.steps):
         st = ctx.time_step(sc, P, q, qd)
@@ -144,10 +148,11 @@ def main():
         tot["active"] += st["n_active_pt"] + st["n_active_ee"]
         tot["ccd"] += st["n_pt_swept"] + st["n_ee_swept"]
         tot["pcg"] += st["pcg_iters"]
+        tot["friction"] += st["n_friction"] * st["newton_iters"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ks = {k: ctx.profile_query(k) for k in ("pcg_round", "barrier_local", "accd", "assemble_chunks",
-                                             "pair_tiles_write", "energy_only")}
+                                             "pair_tiles_write", "energy_only", "friction_local")}
     ctx.profile(False)
     pairs = tot["active"] + tot["ccd"]
 
@@ -195,12 +200,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded scene generator)",
         "config": {"workload": "icosphere box drop: 1000 icospheres (subdivision 2) + fixed 12-quad box, "
-                               "dt 1e-2, dhat 1e-3, frictionless",
+                               f"dt 1e-2, dhat 1e-3, lagged friction mu {P['mu']}",
                    "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])), "tris": int(len(S["tris"])),
                    "edges": int(len(S["edges"])), "pre_steps": args.pre},
         "newton_iters_per_s": tot["newton"] / wall,
         "newton_iters": tot["newton"],
-        "pair_evals": {"barrier_active": tot["active"], "ccd": tot["ccd"]},
+        "pair_evals": {"barrier_active": tot["active"], "ccd": tot["ccd"], "friction": tot["friction"]},
         "pcg_iters": tot["pcg"],
         "kernel_ms": {k: v["ms"] for k, v in ks.items()},
         "roofline": roof,

@@ -14,6 +14,7 @@
 // iterations; once the stop flag is set the remaining kernels return at
 // once, and the host reads the flag once per replay.
 #include <cstdlib>
+#include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -396,11 +397,15 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   const bool use_graph = !(env && env[0] == '0');
   hipGraphExec_t exec = nullptr;
   if (use_graph) {
+    // every value baked into the captured kernels' arguments is part of the
+    // key (rtol2 by its bit pattern)
+    uint64_t rtol_bits;
+    std::memcpy(&rtol_bits, &rtol2, sizeof(rtol_bits));
     const std::vector<uintptr_t> key = {
         (uintptr_t)diag, (uintptr_t)off, (uintptr_t)keys, (uintptr_t)tv2, (uintptr_t)lo_beg, (uintptr_t)hi_beg,
         (uintptr_t)inv, (uintptr_t)x_out, (uintptr_t)r, (uintptr_t)z, (uintptr_t)pa, (uintptr_t)pb,
         (uintptr_t)Ap, (uintptr_t)part, (uintptr_t)part2, (uintptr_t)st, (uintptr_t)err,
-        (uintptr_t)sc->body_fixed, (uintptr_t)nb, (uintptr_t)max_iter, (uintptr_t)(rtol2 * 1e300)};
+        (uintptr_t)sc->body_fixed, (uintptr_t)nb, (uintptr_t)max_iter, (uintptr_t)rtol_bits};
     if (ctx->pcg_exec == nullptr || ctx->pcg_key != key) {
       if (ctx->pcg_exec) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec));
       ctx->pcg_exec = nullptr;

@@ -173,9 +173,11 @@ def icosphere_box(seed=2, n_side=10, n_layers=10, spacing=0.25, friction=0.5):
     scene = sb.build()
     # kappa_b: a 4 kg sphere landing at 2 m/s is stopped near dhat/2
     # (kappa |B'(dhat/2)| = m v dt); Newton tolerance 1e-2 of the box
-    # diagonal per second (IPC's convention)
+    # diagonal per second (IPC's convention); inexact Newton directions
+    # (PCG relative residual 1e-2: the Newton iteration counts match those
+    # of 1e-4)
     params = default_params(dt=1e-2, dhat=1e-3, kappa_b=70.0, mu=friction, steps=200,
-                            newton_tol=1e-2 * math.sqrt(3.0) * 2.6, max_newton=500, pcg_rtol=1e-4)
+                            newton_tol=1e-2 * math.sqrt(3.0) * 2.6, max_newton=500, pcg_rtol=1e-2)
     return scene, params
 
 

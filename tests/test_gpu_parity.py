@@ -428,3 +428,26 @@ def test_pcg_graph_replays_match_eager(abd, ctx):
         assert it == it_eager
         ctx.vertex_map(sc, _dev(q))            # eager work between replays
         ctx.candidates(sc, x, None, P["dhat"])
+
+
+def test_pcg_tolerance_change_recaptures(abd, ctx):
+    """Two solves of one system with different tolerances in a row: the
+    captured iterations must follow each call's tolerance."""
+    S = sg.near_contact_cubes(2, n=4)
+    P = dict(sg.default_params())
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    B = oracle.Body(S)
+    q = _state(S, 72)
+    qt = q.copy()
+    qt[:, :3] += P["dt"] ** 2 * np.array(P["gravity"])
+    qt[S["body_fixed"] != 0] = q[S["body_fixed"] != 0]
+    gh = oracle.grad_hess(S, B, q, qt, P)
+    args = (_dev(gh["diag"]), _dev(gh["off"]), _dev(gh["keys"], torch.int32), _dev(-gh["grad"]))
+    p_ref = oracle.solve(S, gh["diag"], gh["off"], gh["keys"], -gh["grad"])
+    _, it_loose = ctx.pcg_solve(sc, *args, rtol=1e-2, max_iter=20000)
+    p, it_tight = ctx.pcg_solve(sc, *args, rtol=1e-14, max_iter=20000)
+    assert it_tight > it_loose
+    assert np.abs(p.cpu().numpy() - p_ref).max() <= 1e-8 * np.abs(p_ref).max()
+    _, it_loose2 = ctx.pcg_solve(sc, *args, rtol=1e-2, max_iter=20000)
+    assert it_loose2 == it_loose

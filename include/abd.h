@@ -106,6 +106,9 @@ typedef struct abd_stats {
   double energy0, energy1;        /* E(q), E(q + alpha p) */
   double t_barrier_ms, t_ccd_ms, t_candidates_ms, t_solve_ms, t_total_ms;
   int64_t n_friction;             /* lagged friction pairs in use */
+  int64_t scene_newton_iters;     /* time step: Newton iterations summed over sub-scenes */
+  int32_t newly_converged;        /* sub-scenes that converged in this iteration */
+  int32_t pad_;
 } abd_stats;
 
 int abd_create(abd_ctx **ctx, int device);
@@ -201,24 +204,35 @@ int abd_q_tilde(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const 
 
 /* Block-Jacobi preconditioned CG on the symmetric block matrix (diag +
  * off/off^T) restricted to free bodies: solves H p = rhs, p = 0 on fixed
- * bodies.  Syncs; *iters (host) receives the iteration count. */
+ * bodies.  Sub-scenes are independent systems (no off-diagonal block joins
+ * two of them): each runs its own CG scalars and stops on its own
+ * |r| <= rtol |b|.  Syncs; *iters (host) receives the largest iteration
+ * count over the sub-scenes. */
 int abd_pcg_solve(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
                   int64_t n_keys, const double *rhs, double *p, double rtol, int32_t max_iter, int32_t *iters,
                   hipStream_t stream);
 
 /* One projected-Newton iteration on q (in/out) towards the minimiser of
  * the incremental potential with target q_tilde: direction p = -H^-1 g;
- * if max_k |J_k p|_inf <= newton_tol dt, sets stats->converged and leaves q;
- * else the CCD bound over the swept candidates of x(q) -> x(q+p) starts a
- * backtracking search halving alpha until E(q + alpha p) <= E(q).
- * Syncs.  stats (host) may be NULL. */
+ * a sub-scene with max_k |J_k p|_inf <= newton_tol dt (vertices of the
+ * scene) is converged and keeps its q; every other sub-scene takes the CCD
+ * bound over the swept candidates of x(q) -> x(q+p) as its first step
+ * length and halves it until its energy E_s(q + alpha_s p) <= E_s(q).
+ * Sub-scenes are independent problems: own convergence test, CCD bound,
+ * line search and PCG scalars.  scene_done (device u8 [n_scenes], in/out,
+ * may be NULL = none done): scenes marked non-zero are skipped (zero
+ * direction, q unchanged); scenes converging in this call are marked.
+ * stats->converged is set when every sub-scene is done.  Syncs.  stats
+ * (host) may be NULL. */
 int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, const double *q_tilde,
-                    abd_stats *stats, hipStream_t stream);
+                    uint8_t *scene_done, abd_stats *stats, hipStream_t stream);
 
 /* One implicit-Euler time step: q~ from (q, qdot), Newton iterations until
- * converged (ABD_E_NOT_CONVERGED after max_newton), then
+ * every sub-scene has converged (ABD_E_NOT_CONVERGED after max_newton), then
  * qdot = (q_new - q_old) / dt.  q, qdot [n_bodies][12] in/out.  Syncs.
- * stats (host, may be NULL) receives totals of the step. */
+ * stats (host, may be NULL) receives totals of the step (newton_iters: the
+ * iterations of the slowest sub-scene; scene_newton_iters: summed over
+ * sub-scenes). */
 int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot,
                   abd_stats *stats, hipStream_t stream);
 

@@ -227,11 +227,13 @@ class Context:
                                          ctypes.byref(it), _stream()))
         return p, it.value
 
-    def newton_step(self, scene, params, q, q_tilde):
+    def newton_step(self, scene, params, q, q_tilde, scene_done=None):
+        """One Newton iteration; scene_done (uint8 [n_scenes] device tensor,
+        in/out) marks sub-scenes already converged."""
         st = AbdStats()
         prm = make_params(params)
         self._check(self.L.abd_newton_step(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q),
-                                           _ptr(q_tilde), ctypes.byref(st), _stream()))
+                                           _ptr(q_tilde), _ptr(scene_done), ctypes.byref(st), _stream()))
         return st.as_dict()
 
     def time_step(self, scene, params, q, qd):

@@ -45,7 +45,7 @@ class AbdStats(ctypes.Structure):
                 ("ls_halvings", _i32), ("converged", _i32), ("newton_iters", _i32), ("alpha_ccd", _dbl),
                 ("alpha", _dbl), ("disp", _dbl), ("energy0", _dbl), ("energy1", _dbl), ("t_barrier_ms", _dbl),
                 ("t_ccd_ms", _dbl), ("t_candidates_ms", _dbl), ("t_solve_ms", _dbl), ("t_total_ms", _dbl),
-                ("n_friction", _i64)]
+                ("n_friction", _i64), ("scene_newton_iters", _i64), ("newly_converged", _i32), ("pad_", _i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,7 +72,7 @@ SIGNATURES = {
     "abd_inertia": ([_vp, _PS, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "abd_q_tilde": ([_vp, _PS, _PP, _vp, _vp, _vp, _vp], ctypes.c_int),
     "abd_pcg_solve": ([_vp, _PS, _vp, _vp, _vp, _i64, _vp, _vp, _dbl, _i32, _pi32, _vp], ctypes.c_int),
-    "abd_newton_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
+    "abd_newton_step": ([_vp, _PS, _PP, _vp, _vp, _vp, _PST, _vp], ctypes.c_int),
     "abd_time_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
     "abd_friction_lag": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
     "abd_friction_grad_hess": ([_vp, _PS, _PP, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp,

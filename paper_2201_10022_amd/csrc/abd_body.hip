@@ -81,6 +81,26 @@ __global__ void __launch_bounds__(256) k_disp_max(int nv, const double *__restri
   if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
+// |J_k p|_inf per vertex and the vertex's scene
+__global__ void __launch_bounds__(256) k_disp_vert(int nv, const double *__restrict__ xbar,
+                                                   const int32_t *__restrict__ vert_body,
+                                                   const int32_t *__restrict__ body_scene, const double *__restrict__ p,
+                                                   double *__restrict__ val, int32_t *__restrict__ key) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= nv) return;
+  const int b = vert_body[k];
+  const double *qb = p + 12 * (int64_t)b;
+  const double xb0 = xbar[3 * k], xb1 = xbar[3 * k + 1], xb2 = xbar[3 * k + 2];
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double *a = qb + 3 + 3 * i;
+    m = fmax(m, fabs(qb[i] + ((a[0] * xb0 + a[1] * xb1) + a[2] * xb2)));
+  }
+  val[k] = m;
+  key[k] = body_scene[b];
+}
+
 __global__ void k_max_fold(const double *part, int n, double *out) {
   double m = 0.0;
   for (int i = threadIdx.x; i < n; i += 64) m = fmax(m, part[i]);
@@ -254,6 +274,20 @@ int op_max_abs_disp(abd_ctx *ctx, const abd_scene *sc, const double *p, double *
   return abd_hip_check(ctx, hipGetLastError(), "k_disp_max");
 }
 
+// per-scene max_k |J_k p|_inf into out [n_scenes]
+int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s) {
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  if (S <= 1) return op_max_abs_disp(ctx, sc, p, out_dev, s);
+  double *val;
+  int32_t *key;
+  ABD_TRY(ws(ctx, "disp_v", sc->n_verts, &val, s));
+  ABD_TRY(ws(ctx, "disp_k", sc->n_verts, &key, s));
+  hipLaunchKernelGGL(k_disp_vert, dim3(grid_for(sc->n_verts, 256)), dim3(256), 0, s, sc->n_verts, sc->xbar,
+                     sc->vert_body, sc->body_scene, p, val, key);
+  HIP_TRY(ctx, hipGetLastError());
+  return seg_max_scenes(ctx, val, key, sc->n_verts, S, out_dev, s);
+}
+
 static int body_terms(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double kappa_o,
                       double w, int do_inertia, int do_ortho, int project, double *energy, double *grad,
                       double *diag, hipStream_t s) {
@@ -278,6 +312,16 @@ int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
 int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
                    double *energy, hipStream_t s) {
   return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, energy, nullptr, nullptr, s);
+}
+
+int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
+                          const double *qt, double *energy, hipStream_t s) {
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  if (S <= 1) return op_body_energy(ctx, sc, prm, q, qt, energy, s);
+  ABD_TRY(body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, nullptr, nullptr, nullptr, s));
+  double *eb;
+  ABD_TRY(ws(ctx, "body_e", sc->n_bodies, &eb, s));
+  return seg_sum_scenes(ctx, eb, sc->body_scene, sc->n_bodies, S, energy, s);
 }
 
 int op_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,

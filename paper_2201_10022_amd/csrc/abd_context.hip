@@ -54,6 +54,18 @@ int pinned_get(abd_ctx *ctx, size_t bytes, void **out) {
   return ABD_OK;
 }
 
+int pinned_get_nt(abd_ctx *ctx, size_t bytes, void **out) {
+  if (ctx->pinned_nt_bytes < bytes) {
+    if (ctx->pinned_nt) HIP_TRY(ctx, hipHostFree(ctx->pinned_nt));
+    ctx->pinned_nt = nullptr;
+    size_t nb = bytes < 4096 ? 4096 : bytes;
+    HIP_TRY(ctx, hipHostMalloc(&ctx->pinned_nt, nb, hipHostMallocDefault));
+    ctx->pinned_nt_bytes = nb;
+  }
+  *out = ctx->pinned_nt;
+  return ABD_OK;
+}
+
 __global__ void k_add_i64(const int64_t *a, const int64_t *b, int64_t *o) { *o = *a + *b; }
 
 int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s) {
@@ -155,6 +167,76 @@ int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, doubl
   return reduce_f64<1>(ctx, in, n, init, out, 0, s);
 }
 
+// ------------------------------------------------- per-scene reductions ----
+namespace {
+constexpr int SB = 512;
+
+__device__ __forceinline__ int64_t lower_bound_i32(const int32_t *a, int64_t n, int v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// scene s's body range starts at the first body with body_scene >= s
+__global__ void k_scene_offsets(int nb, const int32_t *body_scene, int n_scenes, int32_t *off) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > n_scenes) return;
+  off[s] = (int32_t)lower_bound_i32(body_scene, nb, s);
+}
+
+// one block per scene: fixed-order sum (SUM) or max of the items whose
+// (non-decreasing) key equals the scene
+template <int OP>
+__global__ void __launch_bounds__(SB) k_seg_reduce(const double *vals, const int32_t *keys, int64_t n, double *out,
+                                                   int accumulate) {
+  __shared__ double sh[SB / 64];
+  const int s = blockIdx.x;
+  const int64_t lo = lower_bound_i32(keys, n, s), hi = lower_bound_i32(keys, n, s + 1);
+  double v = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += SB) v = OP == 0 ? v + vals[i] : fmax(v, vals[i]);
+  v = OP == 0 ? wave_sum(v) : wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < SB / 64; ++w) r = OP == 0 ? r + sh[w] : fmax(r, sh[w]);
+    if (OP == 0)
+      out[s] = accumulate ? out[s] + r : r;
+    else
+      out[s] = accumulate ? fmax(out[s], r) : r;
+  }
+}
+}  // namespace
+
+int op_scene_offsets(abd_ctx *ctx, const abd_scene *sc, const int32_t **off, hipStream_t s) {
+  int32_t *o;
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  ABD_TRY(ws(ctx, "scene_body_off", S + 1, &o, s));
+  hipLaunchKernelGGL(k_scene_offsets, dim3(grid_for(S + 1, 256)), dim3(256), 0, s, sc->n_bodies, sc->body_scene, S,
+                     o);
+  *off = o;
+  return abd_hip_check(ctx, hipGetLastError(), "k_scene_offsets");
+}
+
+int seg_sum_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out_accum,
+                   hipStream_t s) {
+  if (n_scenes <= 1) return n > 0 ? reduce_sum_f64(ctx, vals, n, out_accum, s) : ABD_OK;
+  hipLaunchKernelGGL(k_seg_reduce<0>, dim3(n_scenes), dim3(SB), 0, s, vals, keys, n, out_accum, 1);
+  return abd_hip_check(ctx, hipGetLastError(), "k_seg_reduce");
+}
+
+int seg_max_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_reduce<1>, dim3(n_scenes > 0 ? n_scenes : 1), dim3(SB), 0, s, vals, keys, n, out, 0);
+  return abd_hip_check(ctx, hipGetLastError(), "k_seg_reduce");
+}
+
 // ----------------------------------------------------------- profiling ----
 static hipEvent_t pool_get(abd_ctx *ctx) {
   if (!ctx->ev_pool.empty()) {
@@ -242,6 +324,7 @@ extern "C" int abd_destroy(abd_ctx *ctx) {
   for (auto &kv : ctx->bufs)
     if (kv.second.ptr) hipFree(kv.second.ptr);
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  if (ctx->pinned_nt) hipHostFree(ctx->pinned_nt);
   for (auto &e : ctx->ev)
     if (e) hipEventDestroy(e);
   prof_flush(ctx);

@@ -176,11 +176,13 @@ __global__ void __launch_bounds__(128) k_friction_local(int64_t n, int64_t n_pt,
                                                         const double *x, const double *xt, const double *lam,
                                                         const double *T, const double *w, double mu, double eps,
                                                         double *e_out, double *g_out, double *H_out,
-                                                        PairInfo *info) {
+                                                        PairInfo *info, const int32_t *body_scene,
+                                                        int32_t *key_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int is_ee, vid[4];
   load_vids(i, n_pt, pt, ee, tris, edges, is_ee, vid);
+  if (key_out) key_out[i] = body_scene[vert_body[vid[0]]];
   const double ml = mu * lam[i];
   double wk[4], Ti[6];
 #pragma unroll
@@ -284,7 +286,7 @@ int op_friction_local(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, 
   hipEvent_t pe = prof_begin(ctx, s);
   hipLaunchKernelGGL(k_friction_local<false>, dim3(grid_for(n, 128)), dim3(128), 0, s, n, fr->n_pt, fr->pt, fr->ee,
                      sc->tris, sc->edges, sc->vert_body, x, fr->xt, fr->lam, fr->T, fr->w, fr->mu, fr->eps, e_loc,
-                     g_loc, H_loc, info);
+                     g_loc, H_loc, info, sc->body_scene, nullptr);
   prof_end(ctx, pe, "friction_local", n, s);
   return abd_hip_check(ctx, hipGetLastError(), "k_friction_local");
 }
@@ -297,9 +299,28 @@ int op_friction_energy(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr,
   ABD_TRY(ws(ctx, "fe_e", n, &e, s));
   hipLaunchKernelGGL(k_friction_local<true>, dim3(grid_for(n, 128)), dim3(128), 0, s, n, fr->n_pt, fr->pt, fr->ee,
                      sc->tris, sc->edges, sc->vert_body, x, fr->xt, fr->lam, fr->T, fr->w, fr->mu, fr->eps, e,
-                     nullptr, nullptr, nullptr);
+                     nullptr, nullptr, nullptr, sc->body_scene, nullptr);
   HIP_TRY(ctx, hipGetLastError());
   return reduce_sum_f64(ctx, e, n, energy, s);
+}
+
+int op_friction_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
+                              double *energy, hipStream_t s) {
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  if (S <= 1) return op_friction_energy(ctx, sc, fr, x, energy, s);
+  const int64_t n = fr->n();
+  if (n == 0) return ABD_OK;
+  double *e;
+  int32_t *key;
+  ABD_TRY(ws(ctx, "fe_e", n, &e, s));
+  ABD_TRY(ws(ctx, "fe_key", n, &key, s));
+  hipLaunchKernelGGL(k_friction_local<true>, dim3(grid_for(n, 128)), dim3(128), 0, s, n, fr->n_pt, fr->pt, fr->ee,
+                     sc->tris, sc->edges, sc->vert_body, x, fr->xt, fr->lam, fr->T, fr->w, fr->mu, fr->eps, e,
+                     nullptr, nullptr, nullptr, sc->body_scene, key);
+  HIP_TRY(ctx, hipGetLastError());
+  if (fr->n_pt) ABD_TRY(seg_sum_scenes(ctx, e, key, fr->n_pt, S, energy, s));
+  if (fr->n_ee) ABD_TRY(seg_sum_scenes(ctx, e + fr->n_pt, key + fr->n_pt, fr->n_ee, S, energy, s));
+  return ABD_OK;
 }
 
 int op_friction_state(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, FrictionSet *fr, bool *active,

@@ -37,6 +37,8 @@ struct abd_ctx {
   std::map<std::string, DevBuf> bufs;
   void *pinned = nullptr;  // small host staging area for scalar readbacks
   size_t pinned_bytes = 0;
+  void *pinned_nt = nullptr;  // per-scene staging of the Newton driver
+  size_t pinned_nt_bytes = 0;
   hipEvent_t ev[8] = {};
   bool profiling = false;
   std::map<std::string, KStat> kstats;
@@ -77,6 +79,9 @@ int ws(abd_ctx *ctx, const char *name, size_t count, T **out, hipStream_t stream
   return ws_get(ctx, name, count * sizeof(T) + 256, reinterpret_cast<void **>(out), stream);
 }
 int pinned_get(abd_ctx *ctx, size_t bytes, void **out);
+// separate staging area of the Newton driver (never used by the operations
+// it calls, so its contents survive them)
+int pinned_get_nt(abd_ctx *ctx, size_t bytes, void **out);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -151,6 +156,15 @@ int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, con
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *p, double rtol, int max_iter, int *iters, hipStream_t s);
 int op_max_abs_disp(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s);
+// per-scene variants (out [n_scenes]; energies accumulated, maxima written)
+int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s);
+int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
+                          const double *qt, double *energy, hipStream_t s);
+int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
+                             const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy,
+                             hipStream_t s);
+int op_friction_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
+                              double *energy, hipStream_t s);
 int op_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,
                      double *energy, double *grad, double *diag, int project, hipStream_t s);
 int op_inertia(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double *energy, double *grad,
@@ -363,3 +377,13 @@ __device__ __forceinline__ double wave_max(double v) {
 // Deterministic device-wide sums: per-block partials then one block folds them.
 int reduce_sum_f64(abd_ctx *ctx, const double *in, int64_t n, double *out_accum, hipStream_t s);
 int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, double *out, hipStream_t s);
+// Per-scene reductions of items whose scene keys are non-decreasing (bodies,
+// vertices and candidate pairs are all scene-contiguous): sums accumulate
+// into out [n_scenes] (n_scenes <= 1: one device-wide sum, keys unused);
+// maxima (of non-negative values) overwrite out.
+int seg_sum_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out_accum,
+                   hipStream_t s);
+int seg_max_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out,
+                   hipStream_t s);
+// first body of every scene, [n_scenes + 1] (device, context workspace)
+int op_scene_offsets(abd_ctx *ctx, const abd_scene *sc, const int32_t **off, hipStream_t s);

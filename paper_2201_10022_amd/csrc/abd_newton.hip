@@ -57,31 +57,53 @@ int read_err(abd_ctx *ctx, hipStream_t s) {
   return ABD_OK;
 }
 
-// E(q) over the given (swept) candidates; result in *h (host)
+// per-body masks and per-scene step lengths
+__global__ void k_neg_masked(int nb, const int32_t *body_scene, const uint8_t *done, const double *g, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 12 * nb) return;
+  out[i] = done[body_scene[i / 12]] ? 0.0 : -g[i];
+}
+__global__ void k_zero_done(int nb, const int32_t *body_scene, const uint8_t *done, double *p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 12 * nb) return;
+  if (done[body_scene[i / 12]]) p[i] = 0.0;
+}
+__global__ void k_axpy_scene(int nb, const int32_t *body_scene, const double *a, const double *alpha,
+                             const double *b, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 12 * nb) return;
+  out[i] = a[i] + alpha[body_scene[i / 12]] * b[i];
+}
+
+// per-scene E(q) over the given (swept) candidates into e_dev [S]; copied
+// to out (host, [S])
 int energy_at(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
               double *x, const int32_t *pt, int64_t npt, const int32_t *ee, int64_t nee, const FrictionSet *fr,
               double *e_dev, double *out, hipStream_t s) {
-  ABD_TRY(zero(ctx, e_dev, 1, s));
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  ABD_TRY(zero(ctx, e_dev, S, s));
   ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
-  ABD_TRY(op_body_energy(ctx, sc, prm, q, qt, e_dev, s));
-  ABD_TRY(op_barrier_energy(ctx, sc, prm, x, pt, npt, ee, nee, e_dev, s));
-  if (fr) ABD_TRY(op_friction_energy(ctx, sc, fr, x, e_dev, s));
-  double *h;
-  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
-  HIP_TRY(ctx, hipMemcpyAsync(h + 2, e_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  ABD_TRY(op_body_energy_scenes(ctx, sc, prm, q, qt, e_dev, s));
+  ABD_TRY(op_barrier_energy_scenes(ctx, sc, prm, x, pt, npt, ee, nee, e_dev, s));
+  if (fr) ABD_TRY(op_friction_energy_scenes(ctx, sc, fr, x, e_dev, s));
+  HIP_TRY(ctx, hipMemcpyAsync(out, e_dev, S * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  *out = h[2];
   return ABD_OK;
 }
 
 }  // namespace
 
+// One Newton iteration for every sub-scene not yet marked in done_dev
+// (device [S], in/out).  Sub-scenes are independent problems: each has its
+// own convergence test, CCD bound and line search (its own step length),
+// and its own PCG scalars; a scene marked done keeps its q.
 int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, const double *qt,
-                     abd_stats *st, hipStream_t s) {
+                     uint8_t *done_dev, abd_stats *st, hipStream_t s) {
   auto t_all = std::chrono::steady_clock::now();
   const int nb = sc->n_bodies, nv = sc->n_verts;
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int n12 = 12 * nb;
-  double *x, *x1, *dx, *g, *diag, *off, *p, *qa, *e;
+  double *x, *x1, *dx, *g, *diag, *off, *p, *qa, *e, *sv, *alpha_dev;
   ABD_TRY(ws(ctx, "nt_x", 3 * (size_t)nv, &x, s));
   ABD_TRY(ws(ctx, "nt_x1", 3 * (size_t)nv, &x1, s));
   ABD_TRY(ws(ctx, "nt_dx", 3 * (size_t)nv, &dx, s));
@@ -90,8 +112,16 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(ws(ctx, "nt_p", n12, &p, s));
   ABD_TRY(ws(ctx, "nt_qa", n12, &qa, s));
   ABD_TRY(ws(ctx, "nt_e", 4, &e, s));
+  ABD_TRY(ws(ctx, "nt_sv", 2 * (size_t)S, &sv, s));
+  ABD_TRY(ws(ctx, "nt_alpha", S, &alpha_dev, s));
+  double *e_sc;
+  ABD_TRY(ws(ctx, "nt_escene", S, &e_sc, s));
+  // host staging: done flags, per-scene disp / alpha / E0 / E1
   double *h;
-  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
+  ABD_TRY(pinned_get_nt(ctx, sizeof(double) * (8 + 5 * (size_t)S), reinterpret_cast<void **>(&h)));
+  double *h_disp = h + 8, *h_alpha = h_disp + S, *h_e0 = h_alpha + S, *h_e1 = h_e0 + S;
+  uint8_t *h_done = reinterpret_cast<uint8_t *>(h_e1 + S);
+  HIP_TRY(ctx, hipMemcpyAsync(h_done, done_dev, S, hipMemcpyDeviceToHost, s));
 
   // lagged friction of the current time step, if any
   FrictionSet frs;
@@ -127,28 +157,43 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->n_active_pt = nap;
   st->n_active_ee = nae;
 
-  // Newton direction
+  // Newton direction (scenes already done get a zero right-hand side)
   t0 = std::chrono::steady_clock::now();
   double *rhs;
   ABD_TRY(ws(ctx, "nt_rhs", n12, &rhs, s));
-  hipLaunchKernelGGL(k_neg, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, g, rhs);
+  hipLaunchKernelGGL(k_neg_masked, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, done_dev, g, rhs);
   int its = 0;
   ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s));
   ABD_TRY(read_err(ctx, s));
   st->pcg_iters = its;
   st->t_solve_ms += ms_since(t0);
-  ABD_TRY(op_max_abs_disp(ctx, sc, p, e + 1, s));
-  HIP_TRY(ctx, hipMemcpyAsync(h, e + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, sv, s));
+  HIP_TRY(ctx, hipMemcpyAsync(h_disp, sv, S * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  st->disp = h[0];
-  if (!(std::isfinite(h[0]))) return abd_fail(ctx, ABD_E_PCG, "non-finite Newton direction");
-  if (h[0] <= prm->newton_tol * prm->dt) {
+  double dmax = 0.0;
+  int n_active = 0;
+  for (int j = 0; j < S; ++j) {
+    if (h_done[j]) continue;
+    if (!std::isfinite(h_disp[j])) return abd_fail(ctx, ABD_E_PCG, "non-finite Newton direction (scene %d)", j);
+    dmax = h_disp[j] > dmax ? h_disp[j] : dmax;
+    if (h_disp[j] <= prm->newton_tol * prm->dt) {
+      h_done[j] = 1;
+      ++st->newly_converged;
+    } else {
+      ++n_active;
+    }
+  }
+  st->disp = dmax;
+  HIP_TRY(ctx, hipMemcpyAsync(done_dev, h_done, S, hipMemcpyHostToDevice, s));
+  if (n_active == 0) {
     st->converged = 1;
     st->alpha = 0.0;
     st->t_total_ms += ms_since(t_all);
+    prof_flush(ctx);
     return ABD_OK;
   }
   st->converged = 0;
+  hipLaunchKernelGGL(k_zero_done, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, done_dev, p);
 
   // CCD over the swept candidates of x(q) -> x(q + p)
   t0 = std::chrono::steady_clock::now();
@@ -162,26 +207,47 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->t_candidates_ms += ms_since(t0);
   t0 = std::chrono::steady_clock::now();
   hipLaunchKernelGGL(k_sub, dim3(grid_for(3 * nv, 256)), dim3(256), 0, s, 3 * nv, x1, x, dx);
-  ABD_TRY(op_ccd(ctx, sc, prm, x, dx, spt, nspt, see, nsee, nullptr, nullptr, e + 2, s));
-  HIP_TRY(ctx, hipMemcpyAsync(h, e + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  ABD_TRY(op_ccd(ctx, sc, prm, x, dx, spt, nspt, see, nsee, nullptr, nullptr, alpha_dev, s));
+  HIP_TRY(ctx, hipMemcpyAsync(h_alpha, alpha_dev, S * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   st->t_ccd_ms += ms_since(t0);
-  double alpha = h[0];
-  st->alpha_ccd = alpha;
+  double amin = 1.0;
+  for (int j = 0; j < S; ++j) {
+    if (h_done[j]) h_alpha[j] = 0.0;
+    else amin = h_alpha[j] < amin ? h_alpha[j] : amin;
+  }
+  st->alpha_ccd = amin;
 
-  // backtracking line search
-  double e0, e1 = 0.0;
-  ABD_TRY(energy_at(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, fr, e + 3, &e0, s));
+  // backtracking line search, per scene
+  ABD_TRY(energy_at(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, fr, e_sc, h_e0, s));
   int k = 0;
+  int max_halvings = 0;
+  std::vector<int> halv(S, 0);
   for (; k < prm->max_ls; ++k) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, q, alpha, p, qa);
-    ABD_TRY(energy_at(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e + 3, &e1, s));
-    if (e1 <= e0) break;
-    alpha *= 0.5;
+    HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_alpha, S * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q, alpha_dev, p,
+                       qa);
+    ABD_TRY(energy_at(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e_sc, h_e1, s));
+    int pending = 0;
+    for (int j = 0; j < S; ++j) {
+      if (h_done[j] || h_e1[j] <= h_e0[j]) continue;
+      h_alpha[j] *= 0.5;
+      ++halv[j];
+      ++pending;
+    }
+    if (pending == 0) break;
   }
   if (k == prm->max_ls) return abd_fail(ctx, ABD_E_LINESEARCH, "line search found no decrease");
-  st->ls_halvings = k;
-  st->alpha = alpha;
+  double e0 = 0.0, e1 = 0.0, amin_acc = 1.0;
+  for (int j = 0; j < S; ++j) {
+    if (h_done[j]) continue;
+    e0 += h_e0[j];
+    e1 += h_e1[j];
+    amin_acc = h_alpha[j] < amin_acc ? h_alpha[j] : amin_acc;
+    max_halvings = halv[j] > max_halvings ? halv[j] : max_halvings;
+  }
+  st->ls_halvings = max_halvings;
+  st->alpha = amin_acc;
   st->energy0 = e0;
   st->energy1 = e1;
   HIP_TRY(ctx, hipMemcpyAsync(q, qa, sizeof(double) * n12, hipMemcpyDeviceToDevice, s));
@@ -191,13 +257,19 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
 }
 
 extern "C" int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q,
-                               const double *q_tilde, abd_stats *stats, hipStream_t stream) {
+                               const double *q_tilde, uint8_t *scene_done, abd_stats *stats, hipStream_t stream) {
   if (!ctx || !sc || !prm || !q || !q_tilde || !sc->mass || !sc->volume)
     return abd_fail(ctx, ABD_E_INVALID, "abd_newton_step: null");
   abd_stats local = {};
   abd_stats *st = stats ? stats : &local;
   *st = abd_stats{};
-  ABD_TRY(newton_iteration(ctx, sc, prm, q, q_tilde, st, stream));
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  uint8_t *done = scene_done;
+  if (!done) {
+    ABD_TRY(ws(ctx, "ns_done", S, &done, stream));
+    HIP_TRY(ctx, hipMemsetAsync(done, 0, S, stream));
+  }
+  ABD_TRY(newton_iteration(ctx, sc, prm, q, q_tilde, done, st, stream));
   st->newton_iters = 1;
   return ABD_OK;
 }
@@ -207,9 +279,13 @@ extern "C" int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params
   if (!ctx || !sc || !prm || !q || !qdot || !sc->mass || !sc->volume)
     return abd_fail(ctx, ABD_E_INVALID, "abd_time_step: null");
   const int n12 = 12 * sc->n_bodies;
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   double *qt, *qo;
+  uint8_t *done;
   ABD_TRY(ws(ctx, "ts_qt", n12, &qt, stream));
   ABD_TRY(ws(ctx, "ts_qo", n12, &qo, stream));
+  ABD_TRY(ws(ctx, "ts_done", S, &done, stream));
+  HIP_TRY(ctx, hipMemsetAsync(done, 0, S, stream));
   ABD_TRY(abd_q_tilde(ctx, sc, prm, q, qdot, qt, stream));
   HIP_TRY(ctx, hipMemcpyAsync(qo, q, sizeof(double) * n12, hipMemcpyDeviceToDevice, stream));
   // friction lagged once at q^t, released when the step returns
@@ -222,10 +298,14 @@ extern "C" int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params
   abd_stats total = {};
   total.n_friction = n_fr;
   int it = 0;
+  int n_left = S;
   bool conv = false;
   for (; it < prm->max_newton; ++it) {
     abd_stats st = {};
-    ABD_TRY(newton_iteration(ctx, sc, prm, q, qt, &st, stream));
+    ABD_TRY(newton_iteration(ctx, sc, prm, q, qt, done, &st, stream));
+    // every scene still iterating ran this iteration
+    total.scene_newton_iters += n_left;
+    n_left -= st.newly_converged;
     total.n_pt = st.n_pt;
     total.n_ee = st.n_ee;
     total.n_active_pt += st.n_active_pt;

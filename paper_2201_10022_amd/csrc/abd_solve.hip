@@ -131,15 +131,30 @@ __global__ void k_tkeys(int64_t nk, const int32_t *keys, uint64_t *tk, uint32_t 
 constexpr int PB = 192;  // init / update: 16 bodies x 12 rows per block
 constexpr int PBB = PB / 12;
 constexpr int SWB = 256;  // spmv: one 64-lane wave per body, 4 bodies per block
+constexpr int SWBB = SWB / 64;
 
-// Device-side iteration state.  Every scalar is written by block 0 of one
-// kernel and read only by later kernels, so no fences or atomics are needed.
+// Sub-scenes are independent systems (the matrix is block diagonal by
+// scene), each with its own CG scalars and stop test.  Blocks never span
+// two scenes: scene s owns update blocks [u_off[s], u_off[s+1]) and spmv
+// blocks [s_off[s], s_off[s+1]), so a block folds only its scene's
+// partials.  Iteration k runs in lockstep for all scenes; a stopped scene's
+// blocks return at once.
+//
+// Device-side iteration state.  Every value is written by one designated
+// block of one kernel (block 0 for the global counters, the scene's first
+// block for a scene's scalars) and read only by later kernels, so no fences
+// are needed; the one atomic counts stopped scenes for the host.
 struct PcgState {
-  double rz[2];    // r.z of iterations with parity 0/1 (written by spmv)
-  double bb, rr;   // initial and current r.r
-  int it_done;     // iterations completed (written by update's block 0)
-  int k_cur;       // iteration being run (written by spmv's block 0)
-  int stop, it_final;
+  int it_done;    // iterations completed (written by update's block 0)
+  int k_cur;      // iteration being run (written by spmv's block 0)
+  int n_stopped;  // scenes stopped so far
+  int pad;
+};
+struct PcgScene {
+  double *rz;      // [2 S] r.z of the iterations with parity 0 / 1
+  double *bb;      // [S] initial r.r
+  int *stop;       // [S]
+  int *it_final;   // [S] iterations run by the scene
 };
 
 // fixed-order sum of n per-block partials (stride `stride`, offset `off`),
@@ -166,22 +181,59 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return s;
 }
 
-__global__ void k_pcg_reset(PcgState *st) {
-  st->it_done = 0;
-  st->k_cur = 0;
-  st->stop = 0;
-  st->it_final = 0;
+// blocks per scene (update and spmv mappings)
+__global__ void k_pcg_scene_blocks(int S, const int32_t *sbo, int64_t *ucnt, int64_t *scnt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int n = sbo[s + 1] - sbo[s];
+  ucnt[s] = (n + PBB - 1) / PBB;
+  scnt[s] = (n + SWBB - 1) / SWBB;
+}
+// scene of every block (-1 beyond the last scene's blocks)
+__global__ void k_pcg_block_scene(int S, int64_t nblk, const int64_t *off, int32_t *tab) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nblk) return;
+  int lo = 0, hi = S;  // last s with off[s] <= j, if j < off[S]
+  if (j >= off[S]) {
+    tab[j] = -1;
+    return;
+  }
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  tab[j] = lo;
+}
+
+__global__ void k_pcg_reset(int S, PcgState *st, PcgScene sc) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) {
+    st->it_done = 0;
+    st->k_cur = 0;
+    st->n_stopped = 0;
+  }
+  if (s < S) {
+    sc.stop[s] = 0;
+    sc.it_final[s] = 0;
+  }
 }
 
 // r = rhs (free bodies), x = 0, z = P r, p_old = 0; partials of r.z, r.r
-__global__ void __launch_bounds__(PB) k_pcg_init(int nb, const uint8_t *fixed, const double *inv, const double *rhs,
+__global__ void __launch_bounds__(PB) k_pcg_init(const int32_t *u_scene, const int64_t *u_off, const int32_t *sbo,
+                                                const uint8_t *fixed, const double *inv, const double *rhs,
                                                 double *x, double *r, double *z, double *p_old, double *part2) {
   __shared__ double sr[PBB][12];
   __shared__ double sh[PB / 64];
-  const int t = blockIdx.x * PB + threadIdx.x;
-  const int b = t / 12, i = t % 12, lb = threadIdx.x / 12;
+  const int sc = u_scene[blockIdx.x];
+  if (sc < 0) return;
+  const int lb = threadIdx.x / 12, i = threadIdx.x % 12;
+  const int b = sbo[sc] + (int)(blockIdx.x - u_off[sc]) * PBB + lb;
+  const bool ok = lb < PBB && b < sbo[sc + 1];
   double rv = 0.0;
-  if (b < nb) {
+  if (ok) {
     const int64_t o = 12 * (int64_t)b + i;
     rv = fixed[b] ? 0.0 : rhs[o];
     x[o] = 0.0;
@@ -191,7 +243,7 @@ __global__ void __launch_bounds__(PB) k_pcg_init(int nb, const uint8_t *fixed, c
   sr[lb][i] = rv;
   __syncthreads();
   double zv = 0.0;
-  if (b < nb) {
+  if (ok) {
     const double *M = inv + 144 * (int64_t)b + 12 * i;
 #pragma unroll
     for (int j = 0; j < 12; ++j) zv += M[j] * sr[lb][j];
@@ -204,40 +256,46 @@ __global__ void __launch_bounds__(PB) k_pcg_init(int nb, const uint8_t *fixed, c
   }
 }
 
-// Iteration k (k = it_done): fold r.z, r.r of the previous update, decide
-// stop, beta = rz_k / rz_{k-1}; p_new = z + beta p_old; Ap = H p_new with one
-// wave per body: lane = (entry slot 0..4, row 0..11), entries = the
-// diagonal block and the body's off-diagonal blocks (as row and as column),
-// five in flight per pass; per-row sums over slots in fixed order.
-__global__ void __launch_bounds__(SWB) k_pcg_spmv(int nb, const uint8_t *fixed, const double *diag,
-                                                 const double *off, const int32_t *keys, const uint32_t *tperm,
-                                                 const int64_t *lo_beg, const int64_t *hi_beg, const double *p_old,
-                                                 const double *z, double *p_new, double *Ap, const double *part2,
-                                                 int npart2, double *part, PcgState *st, double rtol2,
-                                                 int max_iter) {
+// Iteration k (k = it_done): fold the scene's r.z, r.r of the previous
+// update, decide its stop, beta = rz_k / rz_{k-1}; p_new = z + beta p_old;
+// Ap = H p_new with one wave per body: lane = (entry slot 0..4, row 0..11),
+// entries = the diagonal block and the body's off-diagonal blocks (as row
+// and as column), five in flight per pass; per-row sums over slots in
+// fixed order.
+__global__ void __launch_bounds__(SWB) k_pcg_spmv(const int32_t *s_scene, const int64_t *s_off,
+                                                 const int64_t *u_off, const int32_t *sbo, const uint8_t *fixed,
+                                                 const double *diag, const double *off, const int32_t *keys,
+                                                 const uint32_t *tperm, const int64_t *lo_beg,
+                                                 const int64_t *hi_beg, const double *p_old, const double *z,
+                                                 double *p_new, double *Ap, const double *part2, double *part,
+                                                 PcgState *st, PcgScene scs, double rtol2, int max_iter) {
   __shared__ double sh[SWB / 64];
-  if (st->stop) return;
   const int k = st->it_done;
-  const double rz = fold(part2, npart2, 2, 0, sh), rr = fold(part2, npart2, 2, 1, sh);
-  const double bb = k == 0 ? rr : st->bb;
-  const double beta = k == 0 ? 0.0 : rz / st->rz[(k - 1) & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->k_cur = k;
+  const int sc = s_scene[blockIdx.x];
+  if (sc < 0 || scs.stop[sc]) return;
+  const int64_t u0 = u_off[sc];
+  const int nu = (int)(u_off[sc + 1] - u0);
+  const double rz = fold(part2 + 2 * u0, nu, 2, 0, sh), rr = fold(part2 + 2 * u0, nu, 2, 1, sh);
+  const double bb = k == 0 ? rr : scs.bb[sc];
+  const double beta = k == 0 ? 0.0 : rz / scs.rz[2 * sc + ((k - 1) & 1)];
   const bool stop = !(bb > 0.0) || rr <= rtol2 * bb || k >= max_iter || rz == 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->rz[k & 1] = rz;
-    st->rr = rr;
-    st->k_cur = k;
-    if (k == 0) st->bb = rr;
+  if (blockIdx.x == s_off[sc] && threadIdx.x == 0) {
+    scs.rz[2 * sc + (k & 1)] = rz;
+    if (k == 0) scs.bb[sc] = rr;
     if (stop) {
-      st->stop = 1;
-      st->it_final = k;
+      scs.stop[sc] = 1;
+      scs.it_final[sc] = k;
+      atomicAdd(&st->n_stopped, 1);
     }
   }
   if (stop) return;
   const int lane = threadIdx.x & 63;
-  const int b = blockIdx.x * (SWB / 64) + (threadIdx.x >> 6);
+  const int b = sbo[sc] + (int)(blockIdx.x - s_off[sc]) * SWBB + (threadIdx.x >> 6);
+  const bool ok = b < sbo[sc + 1];
   const int slot = lane / 12, i = lane % 12;
   double acc = 0.0, pown = 0.0;
-  if (b < nb) {
+  if (ok) {
     pown = z[12 * (int64_t)b + i] + beta * p_old[12 * (int64_t)b + i];
     const int64_t l0 = lo_beg[b], nlo = lo_beg[b + 1] - l0;
     const int64_t h0 = hi_beg[b], nhi = hi_beg[b + 1] - h0;
@@ -277,7 +335,7 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(int nb, const uint8_t *fixed, 
     v += o;
   }
   double dot = 0.0;
-  if (b < nb && slot == 0) {
+  if (ok && slot == 0) {
     const bool fx = fixed[b] != 0;
     const int64_t o = 12 * (int64_t)b + i;
     const double av = fx ? 0.0 : v;
@@ -289,30 +347,37 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(int nb, const uint8_t *fixed, 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// alpha = rz_k / p.Ap (folded from spmv partials); x += alpha p;
+// alpha = rz_k / p.Ap (folded from the scene's spmv partials); x += alpha p;
 // r -= alpha Ap; z = P r; partials of r.z, r.r for the next spmv
-__global__ void __launch_bounds__(PB) k_pcg_update(int nb, const double *inv, const double *p, const double *Ap,
-                                                  double *x, double *r, double *z, const double *part, int npart,
-                                                  double *part2, PcgState *st, int *err) {
+__global__ void __launch_bounds__(PB) k_pcg_update(const int32_t *u_scene, const int64_t *u_off,
+                                                  const int64_t *s_off, const int32_t *sbo, const double *inv,
+                                                  const double *p, const double *Ap, double *x, double *r, double *z,
+                                                  const double *part, double *part2, PcgState *st, PcgScene scs,
+                                                  int *err) {
   __shared__ double sr[PBB][12];
   __shared__ double sh[PB / 64];
-  if (st->stop) return;
   const int k = st->k_cur;
-  const double pap = fold(part, npart, 1, 0, sh);
-  const double rz = st->rz[k & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->it_done = k + 1;
+  const int sc = u_scene[blockIdx.x];
+  if (sc < 0 || scs.stop[sc]) return;
+  const int64_t s0 = s_off[sc];
+  const double pap = fold(part + s0, (int)(s_off[sc + 1] - s0), 1, 0, sh);
+  const double rz = scs.rz[2 * sc + (k & 1)];
   if (!(pap > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->stop = 1;
-      st->it_final = k;
+    if (blockIdx.x == u_off[sc] && threadIdx.x == 0) {
+      scs.stop[sc] = 1;
+      scs.it_final[sc] = k;
+      atomicAdd(&st->n_stopped, 1);
       if (!(pap == 0.0 && rz == 0.0)) atomicOr(err, 8);
     }
     return;
   }
   const double a = rz / pap;
-  const int t = blockIdx.x * PB + threadIdx.x;
-  const int b = t / 12, i = t % 12, lb = threadIdx.x / 12;
+  const int lb = threadIdx.x / 12, i = threadIdx.x % 12;
+  const int b = sbo[sc] + (int)(blockIdx.x - u_off[sc]) * PBB + lb;
+  const bool ok = b < sbo[sc + 1];
   double rv = 0.0;
-  if (b < nb) {
+  if (ok) {
     const int64_t o = 12 * (int64_t)b + i;
     x[o] += a * p[o];
     rv = r[o] - a * Ap[o];
@@ -321,7 +386,7 @@ __global__ void __launch_bounds__(PB) k_pcg_update(int nb, const double *inv, co
   sr[lb][i] = rv;
   __syncthreads();
   double zv = 0.0;
-  if (b < nb) {
+  if (ok) {
     const double *M = inv + 144 * (int64_t)b + 12 * i;
 #pragma unroll
     for (int j = 0; j < 12; ++j) zv += M[j] * sr[lb][j];
@@ -331,7 +396,6 @@ __global__ void __launch_bounds__(PB) k_pcg_update(int nb, const double *inv, co
   if (threadIdx.x == 0) {
     part2[2 * blockIdx.x] = rzp;
     part2[2 * blockIdx.x + 1] = rrp;
-    if (blockIdx.x == 0) st->it_done = k + 1;
   }
 }
 
@@ -341,17 +405,23 @@ __global__ void __launch_bounds__(PB) k_pcg_update(int nb, const double *inv, co
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *x_out, double rtol, int max_iter, int *iters, hipStream_t s) {
   const int nb = sc->n_bodies;
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   *iters = 0;
   if (nb <= 0) return ABD_OK;
   if (n_keys >= (1ll << 31) || nb >= (1 << 24)) return abd_fail(ctx, ABD_E_INVALID, "pcg: too many blocks");
   double *inv, *r, *z, *pa, *pb, *Ap, *part, *part2;
-  int64_t *lo_beg, *hi_beg;
+  int64_t *lo_beg, *hi_beg, *ucnt, *scnt, *u_off, *s_off;
+  int32_t *u_scene, *s_scene;
   uint64_t *tk, *tk2;
   uint32_t *tv, *tv2;
   int *err;
   PcgState *st;
-  const int nblk_u = (int)grid_for((int64_t)nb * 12, PB);
-  const int nblk_s = (int)grid_for(nb, SWB / 64);
+  PcgScene scs;
+  // block counts: at most one partly filled block per scene
+  const int nblk_u = (int)grid_for((int64_t)nb, PBB) + S;
+  const int nblk_s = (int)grid_for(nb, SWBB) + S;
+  const int32_t *sbo;
+  ABD_TRY(op_scene_offsets(ctx, sc, &sbo, s));
   ABD_TRY(ws(ctx, "pcg_inv", 144 * (size_t)nb, &inv, s));
   ABD_TRY(ws(ctx, "pcg_r", 12 * (size_t)nb, &r, s));
   ABD_TRY(ws(ctx, "pcg_z", 12 * (size_t)nb, &z, s));
@@ -359,16 +429,33 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(ws(ctx, "pcg_pb", 12 * (size_t)nb, &pb, s));
   ABD_TRY(ws(ctx, "pcg_Ap", 12 * (size_t)nb, &Ap, s));
   ABD_TRY(ws(ctx, "pcg_part", nblk_s, &part, s));
-  ABD_TRY(ws(ctx, "pcg_part2", 2 * nblk_u, &part2, s));
+  ABD_TRY(ws(ctx, "pcg_part2", 2 * (size_t)nblk_u, &part2, s));
   ABD_TRY(ws(ctx, "pcg_lob", nb + 1, &lo_beg, s));
   ABD_TRY(ws(ctx, "pcg_hib", nb + 1, &hi_beg, s));
   ABD_TRY(ws(ctx, "pcg_tk", n_keys + 1, &tk, s));
   ABD_TRY(ws(ctx, "pcg_tk2", n_keys + 1, &tk2, s));
   ABD_TRY(ws(ctx, "pcg_tv", n_keys + 1, &tv, s));
   ABD_TRY(ws(ctx, "pcg_tv2", n_keys + 1, &tv2, s));
+  ABD_TRY(ws(ctx, "pcg_ucnt", S, &ucnt, s));
+  ABD_TRY(ws(ctx, "pcg_scnt", S, &scnt, s));
+  ABD_TRY(ws(ctx, "pcg_uoff", S + 1, &u_off, s));
+  ABD_TRY(ws(ctx, "pcg_soff", S + 1, &s_off, s));
+  ABD_TRY(ws(ctx, "pcg_usc", nblk_u, &u_scene, s));
+  ABD_TRY(ws(ctx, "pcg_ssc", nblk_s, &s_scene, s));
   ABD_TRY(ws(ctx, "pcg_state", 1, &st, s));
+  ABD_TRY(ws(ctx, "pcg_s_rz", 2 * (size_t)S, &scs.rz, s));
+  ABD_TRY(ws(ctx, "pcg_s_bb", S, &scs.bb, s));
+  ABD_TRY(ws(ctx, "pcg_s_stop", S, &scs.stop, s));
+  ABD_TRY(ws(ctx, "pcg_s_final", S, &scs.it_final, s));
   ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
   hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed, diag, inv, err);
+  hipLaunchKernelGGL(k_pcg_scene_blocks, dim3(grid_for(S, 256)), dim3(256), 0, s, S, sbo, ucnt, scnt);
+  ABD_TRY(scan_exclusive_i64(ctx, ucnt, u_off, S, u_off + S, s));
+  ABD_TRY(scan_exclusive_i64(ctx, scnt, s_off, S, s_off + S, s));
+  hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_u, 256)), dim3(256), 0, s, S, (int64_t)nblk_u, u_off,
+                     u_scene);
+  hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, S, (int64_t)nblk_s, s_off,
+                     s_scene);
   if (n_keys > 0) {
     hipLaunchKernelGGL(k_tkeys, dim3(grid_for(n_keys, 256)), dim3(256), 0, s, n_keys, keys, tk, tv);
     size_t tmp_bytes = 0;
@@ -379,18 +466,19 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   }
   hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(nb + 1, 256)), dim3(256), 0, s, nb, n_keys, keys, tk2, lo_beg,
                      hi_beg);
-  hipLaunchKernelGGL(k_pcg_reset, dim3(1), dim3(1), 0, s, st);
-  hipLaunchKernelGGL(k_pcg_init, dim3(nblk_u), dim3(PB), 0, s, nb, sc->body_fixed, inv, rhs, x_out, r, z, pa, part2);
+  hipLaunchKernelGGL(k_pcg_reset, dim3(grid_for(S, 256)), dim3(256), 0, s, S, st, scs);
+  hipLaunchKernelGGL(k_pcg_init, dim3(nblk_u), dim3(PB), 0, s, u_scene, u_off, sbo, sc->body_fixed, inv, rhs, x_out,
+                     r, z, pa, part2);
   HIP_TRY(ctx, hipGetLastError());
   const double rtol2 = rtol * rtol;
   // ITER_G iterations: p alternates pa -> pb -> pa ... (ITER_G is even)
   auto enqueue = [&](hipStream_t q) {
     for (int k = 0; k < ITER_G; ++k) {
       double *p_old = (k % 2 == 0) ? pa : pb, *p_new = (k % 2 == 0) ? pb : pa;
-      hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, q, nb, sc->body_fixed, diag, off, keys, tv2, lo_beg,
-                         hi_beg, p_old, z, p_new, Ap, part2, nblk_u, part, st, rtol2, max_iter);
-      hipLaunchKernelGGL(k_pcg_update, dim3(nblk_u), dim3(PB), 0, q, nb, inv, p_new, Ap, x_out, r, z, part, nblk_s,
-                         part2, st, err);
+      hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, q, s_scene, s_off, u_off, sbo, sc->body_fixed, diag,
+                         off, keys, tv2, lo_beg, hi_beg, p_old, z, p_new, Ap, part2, part, st, scs, rtol2, max_iter);
+      hipLaunchKernelGGL(k_pcg_update, dim3(nblk_u), dim3(PB), 0, q, u_scene, u_off, s_off, sbo, inv, p_new, Ap, x_out,
+                         r, z, part, part2, st, scs, err);
     }
   };
   const char *env = getenv("ABD_PCG_GRAPH");
@@ -405,7 +493,10 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
         (uintptr_t)diag, (uintptr_t)off, (uintptr_t)keys, (uintptr_t)tv2, (uintptr_t)lo_beg, (uintptr_t)hi_beg,
         (uintptr_t)inv, (uintptr_t)x_out, (uintptr_t)r, (uintptr_t)z, (uintptr_t)pa, (uintptr_t)pb,
         (uintptr_t)Ap, (uintptr_t)part, (uintptr_t)part2, (uintptr_t)st, (uintptr_t)err,
-        (uintptr_t)sc->body_fixed, (uintptr_t)nb, (uintptr_t)max_iter, (uintptr_t)rtol_bits};
+        (uintptr_t)sc->body_fixed, (uintptr_t)nb, (uintptr_t)max_iter, (uintptr_t)rtol_bits,
+        (uintptr_t)S, (uintptr_t)sbo, (uintptr_t)u_scene, (uintptr_t)s_scene, (uintptr_t)u_off, (uintptr_t)s_off,
+        (uintptr_t)scs.rz, (uintptr_t)scs.bb, (uintptr_t)scs.stop, (uintptr_t)scs.it_final,
+        (uintptr_t)nblk_u, (uintptr_t)nblk_s};
     if (ctx->pcg_exec == nullptr || ctx->pcg_key != key) {
       if (ctx->pcg_exec) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec));
       ctx->pcg_exec = nullptr;
@@ -420,8 +511,9 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
     }
     exec = ctx->pcg_exec;
   }
-  int *h;
-  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
+  int *h;  // [0..2] state counters, [4..4+S) per-scene iteration counts
+  ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
+  int *fin = h + 4;
   const int max_rounds = max_iter / ITER_G + 2;
   // algorithmic HBM bytes of one iteration: every 12x12 block of the
   // matrix and of the preconditioner once, plus the 12-vectors read and
@@ -429,7 +521,8 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   // p, Ap, x, r in, x, r, z out)
   const int64_t bytes_it = (2 * (int64_t)nb + n_keys) * 1152 + 11 * 96 * (int64_t)nb;
   int done = 0;
-  for (int round = 0; round < max_rounds; ++round) {
+  bool all = false;
+  for (int round = 0; round < max_rounds && !all; ++round) {
     hipEvent_t pe = prof_begin(ctx, s);
     if (exec)
       HIP_TRY(ctx, hipGraphLaunch(exec, s));
@@ -437,13 +530,20 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
       enqueue(s);
     prof_end(ctx, pe, "pcg_round", 0, s);
     HIP_TRY(ctx, hipGetLastError());
-    // it_done, k_cur, stop, it_final
-    HIP_TRY(ctx, hipMemcpyAsync(h, &st->it_done, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    // it_done, k_cur, n_stopped
+    HIP_TRY(ctx, hipMemcpyAsync(h, st, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    const int now = h[2] ? h[3] : h[0];
+    all = h[2] >= S;
+    int now = h[0];
+    if (all) {
+      // iterations: the largest count over the scenes
+      HIP_TRY(ctx, hipMemcpyAsync(fin, scs.it_final, S * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      now = 0;
+      for (int j = 0; j < S; ++j) now = fin[j] > now ? fin[j] : now;
+    }
     if (pe && !ctx->pending.empty()) ctx->pending.back().units = (int64_t)(now - done) * bytes_it;
     done = now;
-    if (h[2]) break;
   }
   *iters = done;
   return ABD_OK;

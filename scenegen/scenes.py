@@ -245,8 +245,39 @@ def batched_drops(seed=4, n_scenes=256, n_min=2, n_max=200):
             else:
                 sb.add(sv * r, st, R=R, p=p, scene=s)
     scene = sb.build()
-    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=0.33, mu=0.0, steps=100)
+    # kappa_b and the Newton tolerance as in the icosphere box (same bodies,
+    # same drop heights; 1e-2 of a scene's box diagonal per second)
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=70.0, mu=0.0, steps=100,
+                            newton_tol=1e-2 * math.sqrt(3.0 ** 2 + 3.0 ** 2 + 0.65 ** 2), max_newton=500,
+                            pcg_rtol=1e-2)
     return scene, params
+
+
+def sub_scene(S, k):
+    """Scene k of a batched scene dict as a scene of its own (index ranges
+    cut out and renumbered; no arithmetic on positions)."""
+    b0, b1 = int(S["scene_body_off"][k]), int(S["scene_body_off"][k + 1])
+    v0, v1 = int(S["body_vert_off"][b0]), int(S["body_vert_off"][b1])
+    t0, t1 = int(S["body_tri_off"][b0]), int(S["body_tri_off"][b1])
+    e0, e1 = int(S["body_edge_off"][b0]), int(S["body_edge_off"][b1])
+    nb = b1 - b0
+    return dict(
+        xbar=np.ascontiguousarray(S["xbar"][v0:v1]),
+        vert_body=(S["vert_body"][v0:v1] - b0).astype(np.int32),
+        tris=np.ascontiguousarray(S["tris"][t0:t1] - v0).astype(np.int32),
+        tri_body=(S["tri_body"][t0:t1] - b0).astype(np.int32),
+        edges=np.ascontiguousarray(S["edges"][e0:e1] - v0).astype(np.int32),
+        edge_body=(S["edge_body"][e0:e1] - b0).astype(np.int32),
+        body_vert_off=(S["body_vert_off"][b0:b1 + 1] - v0).astype(np.int32),
+        body_tri_off=(S["body_tri_off"][b0:b1 + 1] - t0).astype(np.int32),
+        body_edge_off=(S["body_edge_off"][b0:b1 + 1] - e0).astype(np.int32),
+        body_fixed=S["body_fixed"][b0:b1].copy(),
+        body_scene=np.zeros(nb, np.int32),
+        scene_body_off=np.array([0, nb], np.int32),
+        density=S["density"][b0:b1].copy(),
+        q0=np.ascontiguousarray(S["q0"][b0:b1]),
+        qd0=np.ascontiguousarray(S["qd0"][b0:b1]),
+    )
 
 
 def adjoint_drop(seed=5):

@@ -1,0 +1,164 @@
+"""GPU parity of the batched form: many independent sub-scenes in one
+scene, each with its own convergence test, CCD bound, line search and PCG
+scalars.  References: the CPU oracle run on every sub-scene on its own, and
+the GPU path run on every sub-scene on its own.  Bars: PCG bit-identical to
+the per-scene solves (same block partition and fold order per scene);
+Newton/time steps within 1e-8 of the per-scene GPU runs and within 1e-6 of
+the oracle's per-scene trajectories (tight Newton tolerance)."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def abd():
+    import paper_2201_10022_amd as abd
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return abd
+
+
+@pytest.fixture(scope="module")
+def ctx(abd):
+    return abd.Context(0)
+
+
+def _dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda:0")
+
+
+def _small_batch(seed=11, n_scenes=5, n_max=4):
+    S, P = sg.batched_drops(seed=seed, n_scenes=n_scenes, n_min=1, n_max=n_max)
+    return S, dict(P, newton_tol=1e-6, pcg_rtol=1e-13, max_pcg=20000)
+
+
+def _near_batch():
+    """Five near-contact cube stacks as the sub-scenes of one batch."""
+    sb = sg.SceneBuilder()
+    for s in range(5):
+        Sk = sg.near_contact_cubes(20 + s, n=2 + s % 3)
+        for b in range(len(Sk["body_fixed"])):
+            v0, v1 = Sk["body_vert_off"][b], Sk["body_vert_off"][b + 1]
+            t0, t1 = Sk["body_tri_off"][b], Sk["body_tri_off"][b + 1]
+            q = Sk["q0"][b]
+            sb.add(Sk["xbar"][v0:v1], Sk["tris"][t0:t1] - v0, R=q[3:].reshape(3, 3), p=q[:3],
+                   fixed=bool(Sk["body_fixed"][b]), scene=s)
+    return sb.build()
+
+
+def test_pcg_batched_bit_identical_to_per_scene(abd, ctx):
+    S = _near_batch()
+    P = sg.default_params()
+    q = sg.random_state(S, 3, rot_angle=2e-4, stretch=1e-5, shift=1e-4)
+    B = oracle.Body(S)
+    qt = q.copy()
+    qt[:, :3] += P["dt"] ** 2 * np.array(P["gravity"])
+    qt[S["body_fixed"] != 0] = q[S["body_fixed"] != 0]
+    gh = oracle.grad_hess(S, B, q, qt, P)
+    sc = abd.Scene(S)
+    p_all, it_all = ctx.pcg_solve(sc, _dev(gh["diag"]), _dev(gh["off"]), _dev(gh["keys"], torch.int32),
+                                  _dev(-gh["grad"]), rtol=1e-10, max_iter=20000)
+    p_all = p_all.cpu().numpy()
+    its = []
+    keys = gh["keys"]
+    for k in range(len(S["scene_body_off"]) - 1):
+        b0, b1 = S["scene_body_off"][k], S["scene_body_off"][k + 1]
+        sel = (keys[:, 0] >= b0) & (keys[:, 0] < b1)
+        Sk = sg.sub_scene(S, k)
+        sck = abd.Scene(Sk)
+        pk, itk = ctx.pcg_solve(sck, _dev(gh["diag"][b0:b1]), _dev(gh["off"][sel] if sel.any() else np.zeros((1, 144))),
+                                _dev(keys[sel] - b0, torch.int32), _dev(-gh["grad"][b0:b1]), rtol=1e-10,
+                                max_iter=20000)
+        np.testing.assert_array_equal(p_all[b0:b1], pk.cpu().numpy())
+        its.append(itk)
+    assert it_all == max(its)
+
+
+def test_newton_step_scene_done_mask(abd, ctx):
+    S = _near_batch()
+    P = dict(sg.default_params(), pcg_rtol=1e-13, max_pcg=20000)
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    q = sg.random_state(S, 5, rot_angle=2e-4, stretch=1e-5, shift=1e-4)
+    qd = np.zeros_like(q)
+    qd[S["body_fixed"] == 0, 1] = -0.05
+    qt = oracle.q_tilde(S, q, qd, P)
+    done = torch.zeros(5, dtype=torch.uint8, device="cuda:0")
+    done[2] = 1
+    qg = _dev(q)
+    st = ctx.newton_step(sc, P, qg, _dev(qt), scene_done=done)
+    qn = qg.cpu().numpy()
+    b0, b1 = S["scene_body_off"][2], S["scene_body_off"][3]
+    np.testing.assert_array_equal(qn[b0:b1], q[b0:b1])
+    free = S["body_fixed"] == 0
+    moved = np.abs(qn - q).max(axis=1) > 0
+    others = free.copy()
+    others[b0:b1] = False
+    assert moved[others].all()
+    assert done[2].item() == 1 and st["converged"] == 0
+
+
+def test_newton_step_batched_matches_per_scene(abd, ctx):
+    S = _near_batch()
+    P = dict(sg.default_params(), pcg_rtol=1e-13, max_pcg=20000)
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    B = oracle.Body(S)
+    q = sg.random_state(S, 7, rot_angle=2e-4, stretch=1e-5, shift=1e-4)
+    qd = np.zeros_like(q)
+    qd[S["body_fixed"] == 0, 1] = -0.05
+    qt = oracle.q_tilde(S, q, qd, P)
+    qg = _dev(q)
+    ctx.newton_step(sc, P, qg, _dev(qt))
+    qn = qg.cpu().numpy()
+    for k in range(5):
+        b0, b1 = S["scene_body_off"][k], S["scene_body_off"][k + 1]
+        Sk = sg.sub_scene(S, k)
+        sck = abd.Scene(Sk)
+        ctx.body_mass(sck)
+        qk = _dev(q[b0:b1])
+        ctx.newton_step(sck, P, qk, _dev(qt[b0:b1]))
+        ref = qk.cpu().numpy()
+        np.testing.assert_allclose(qn[b0:b1], ref, rtol=0, atol=1e-8 * max(np.abs(ref - q[b0:b1]).max(), 1e-300))
+        # and the oracle on the sub-scene
+        Bk = oracle.Body(Sk)
+        qo, conv, info = oracle.newton_iteration(Sk, Bk, q[b0:b1], qt[b0:b1], P)
+        d = qo - q[b0:b1]
+        if not conv:
+            assert np.abs((qn[b0:b1] - q[b0:b1]) - d).max() <= 1e-8 * np.abs(d).max()
+
+
+def test_time_steps_batched_drops_follow_per_scene_oracle(abd, ctx):
+    S, P = _small_batch()
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    q, qd = _dev(S["q0"]), _dev(S["qd0"])
+    nsc = len(S["scene_body_off"]) - 1
+    subs = []
+    for k in range(nsc):
+        Sk = sg.sub_scene(S, k)
+        subs.append([Sk, oracle.Body(Sk), Sk["q0"].copy(), Sk["qd0"].copy()])
+    tot_scene_iters = 0
+    for step in range(35):
+        st = ctx.time_step(sc, P, q, qd)
+        assert st["converged"] == 1
+        ref_iters = 0
+        for k, sub in enumerate(subs):
+            Sk, Bk, qk, qdk = sub
+            qk, qdk, its = oracle.time_step(Sk, Bk, qk, qdk, P)
+            sub[2], sub[3] = qk, qdk
+            ref_iters += its
+            b0, b1 = S["scene_body_off"][k], S["scene_body_off"][k + 1]
+            np.testing.assert_allclose(q[b0:b1].cpu().numpy(), qk, rtol=0, atol=1e-6)
+        tot_scene_iters += st["scene_newton_iters"]
+        assert st["newton_iters"] >= 1
+    # contacts formed in every scene
+    for Sk, Bk, qk, qdk in subs:
+        assert qk[1:, 1].min() < 0.12
+    assert tot_scene_iters > 35 * nsc

@@ -784,3 +784,20 @@ def test_friction_slope_static_creep_closed_form():
     creep = P["eps_v"] * (1.0 - math.sqrt(1.0 - 0.75 / mu))
     assert vs[-1, 0] == pytest.approx(creep, rel=1e-2)
     assert vs[-10:, 0].max() < P["eps_v"]
+
+
+def test_sub_scene_extraction_round_trip():
+    # the sub-scenes of a batch, concatenated back, reproduce the batch
+    S, _ = sg.batched_drops(seed=11, n_scenes=4, n_min=1, n_max=4)
+    b = sg.SceneBuilder()
+    for k in range(4):
+        Sk = sg.sub_scene(S, k)
+        for j in range(len(Sk["body_fixed"])):
+            v0, v1 = Sk["body_vert_off"][j], Sk["body_vert_off"][j + 1]
+            t0, t1 = Sk["body_tri_off"][j], Sk["body_tri_off"][j + 1]
+            qj = Sk["q0"][j]
+            b.add(Sk["xbar"][v0:v1], Sk["tris"][t0:t1] - v0, R=qj[3:].reshape(3, 3), p=qj[:3],
+                  fixed=bool(Sk["body_fixed"][j]), density=Sk["density"][j], qd=Sk["qd0"][j], scene=k)
+    R = b.build()
+    for key in S:
+        np.testing.assert_array_equal(R[key], S[key], err_msg=key)

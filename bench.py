@@ -15,7 +15,14 @@ wall-clock), plus Newton iterations per second, the roofline position of
 the dominant kernel (HIP events inside the library) and the CPU oracle's
 rate on a bounded sample.
 
+With --workload batched the step is one time step of 256 independent
+drop scenes (26,914 bodies, 2.27 M vertices) advanced together from rest,
+each sub-scene with its own convergence, CCD bound and line search; the
+line adds the same library run one scene at a time on a sample of evenly
+spaced scenes over the same steps, scaled by body count, and the speedup.
+
     python bench.py [--steps K] [--warmup W] [--pre N]
+    python bench.py --workload batched --steps 40 [--loop-scenes 16]
 """
 import argparse
 import json
@@ -55,6 +62,11 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size (for counter calibration) before timing")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--workload", choices=("box", "batched"), default="box",
+                    help="box: the 1000-icosphere box drop (default); batched: 256 independent drop scenes in one "
+                         "launch sequence, against a per-scene loop of the same library")
+    ap.add_argument("--loop-scenes", type=int, default=16,
+                    help="batched: scenes (evenly spaced) run one at a time for the per-scene baseline")
     ap.add_argument("--start-at", type=float, default=0.0,
                     help="start the timed steps this many seconds after process start (so a profiler's "
                          "collection period can cover exactly the timed steps)")
@@ -96,72 +108,13 @@ def cpu_baseline(seconds):
                        f"repeated {reps}x in {el:.1f} s, single thread")
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-    import torch
-
-    import paper_2201_10022_amd as abd
-
-    S, P = sg.icosphere_box()
-    P = dict(P, max_pcg=2000)
-    ctx, sc = abd.setup(S, 0)
-    q = torch.as_tensor(S["q0"], device="cuda:0")
-    qd = torch.as_tensor(S["qd0"], device="cuda:0")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.pre):
-        st = ctx.time_step(sc, P, q, qd)
-        if i % 10 == 0:
-            log(args, f"pre {i}: newton {st['newton_iters']} active {st['n_active_pt'] + st['n_active_ee']} "
-                      f"swept {st['n_pt_swept'] + st['n_ee_swept']} pcg {st['pcg_iters']} "
-                      f"{time.perf_counter() - t0:.1f}s")
-    for i in range(args.warmup):
-        ctx.time_step(sc, P, q, qd)
-    torch.cuda.synchronize()
-    if args.start_at > 0:
-        import psutil
-        wait = args.start_at - (time.time() - psutil.Process().create_time())
-        if wait < 0:
-            log(args, f"--start-at {args.start_at}: already {-wait:.1f} s late")
-        time.sleep(max(wait, 0.0))
-    if args.calib_copy_mib:
-        # one plain device copy of known size (read + write), untimed, so
-        # that HBM counters can be scaled against it
-        n = args.calib_copy_mib * (1 << 20) // 8
-        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    ctx.profile(True, reset=True)
-    torch.cuda.synchronize()
-    tot = dict(newton=0, active=0, ccd=0, pcg=0, friction=0)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        st = ctx.time_step(sc, P, q, qd)
-        tot["newton"] += st["newton_iters"]
-        tot["active"] += st["n_active_pt"] + st["n_active_ee"]
-        tot["ccd"] += st["n_pt_swept"] + st["n_ee_swept"]
-        tot["pcg"] += st["pcg_iters"]
-        tot["friction"] += st["n_friction"] * st["newton_iters"]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ks = {k: ctx.profile_query(k) for k in ("pcg_round", "barrier_local", "accd", "assemble_chunks",
-                                             "pair_tiles_write", "energy_only", "friction_local")}
-    ctx.profile(False)
-    pairs = tot["active"] + tot["ccd"]
-
+def roofline(ks):
+    """Roofline of the kernel with the largest live HIP-event time."""
     def per_launch(k):
         d = ks[k]
         n = max(d["launches"], 1)
         return d["ms"] / n, d["units"] / n
 
-    # dominant kernel by live HIP-event time over the timed steps
     dom = max(("pcg_round", "barrier_local", "accd"), key=lambda k: ks[k]["ms"])
     avg_ms, units = per_launch(dom)
     if dom == "pcg_round":
@@ -186,34 +139,183 @@ def main():
         "accd": {"avg_launch_ms": ac_ms, "pairs_per_launch": ac_u,
                  "gbs": ACCD_BYTES_PER_PAIR * ac_u / (ac_ms * 1e-3) / 1e9 if ac_ms > 0 else 0.0,
                  "pairs_per_s": ac_u / (ac_ms * 1e-3) if ac_ms > 0 else 0.0}}
-    line = {
+    return roof, pair_kernels
+
+
+KERNELS = ("pcg_round", "barrier_local", "accd", "assemble_chunks", "pair_tiles_write", "energy_only",
+           "friction_local")
+
+
+def timed_steps(args, ctx, sc, P, q, qd, steps):
+    """steps time steps between two synchronisations, kernel timing on."""
+    import torch
+    ctx.profile(True, reset=True)
+    torch.cuda.synchronize()
+    tot = dict(newton=0, scene_newton=0, active=0, ccd=0, pcg=0, friction=0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = ctx.time_step(sc, P, q, qd)
+        tot["newton"] += st["newton_iters"]
+        tot["scene_newton"] += st["scene_newton_iters"]
+        tot["active"] += st["n_active_pt"] + st["n_active_ee"]
+        tot["ccd"] += st["n_pt_swept"] + st["n_ee_swept"]
+        tot["pcg"] += st["pcg_iters"]
+        tot["friction"] += st["n_friction"] * st["newton_iters"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ks = {k: ctx.profile_query(k) for k in KERNELS}
+    ctx.profile(False)
+    return wall, tot, ks
+
+
+def wait_start(args):
+    if args.start_at > 0:
+        import psutil
+        wait = args.start_at - (time.time() - psutil.Process().create_time())
+        if wait < 0:
+            log(args, f"--start-at {args.start_at}: already {-wait:.1f} s late")
+        time.sleep(max(wait, 0.0))
+
+
+def calib_copy(args):
+    import torch
+    if args.calib_copy_mib:
+        # one plain device copy of known size (read + write), untimed, so
+        # that HBM counters can be scaled against it
+        n = args.calib_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+
+def line_common(args, wall, tot, ks, steps):
+    roof, pair_kernels = roofline(ks)
+    pairs = tot["active"] + tot["ccd"]
+    return {
         "metric": "contact-pair evals/s (barrier grad+PSD Hess+CCD, FP64); Newton iters/s",
         "value": pairs / wall,
         "unit": "pair evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": 1e3 * wall / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded scene generator)",
-        "config": {"workload": "icosphere box drop: 1000 icospheres (subdivision 2) + fixed 12-quad box, "
-                               f"dt 1e-2, dhat 1e-3, lagged friction mu {P['mu']}",
-                   "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])), "tris": int(len(S["tris"])),
-                   "edges": int(len(S["edges"])), "pre_steps": args.pre},
-        "newton_iters_per_s": tot["newton"] / wall,
-        "newton_iters": tot["newton"],
+        "newton_iters_per_s": tot["scene_newton"] / wall,
+        "newton_iters": tot["scene_newton"],
         "pair_evals": {"barrier_active": tot["active"], "ccd": tot["ccd"], "friction": tot["friction"]},
         "pcg_iters": tot["pcg"],
         "kernel_ms": {k: v["ms"] for k, v in ks.items()},
         "roofline": roof,
         "pair_kernels": pair_kernels,
     }
+
+
+def run_box(args):
+    import torch
+
+    import paper_2201_10022_amd as abd
+
+    S, P = sg.icosphere_box()
+    P = dict(P, max_pcg=2000)
+    ctx, sc = abd.setup(S, 0)
+    q = torch.as_tensor(S["q0"], device="cuda:0")
+    qd = torch.as_tensor(S["qd0"], device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.pre):
+        st = ctx.time_step(sc, P, q, qd)
+        if i % 10 == 0:
+            log(args, f"pre {i}: newton {st['newton_iters']} active {st['n_active_pt'] + st['n_active_ee']} "
+                      f"swept {st['n_pt_swept'] + st['n_ee_swept']} pcg {st['pcg_iters']} "
+                      f"{time.perf_counter() - t0:.1f}s")
+    for i in range(args.warmup):
+        ctx.time_step(sc, P, q, qd)
+    torch.cuda.synchronize()
+    wait_start(args)
+    calib_copy(args)
+    wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, args.steps)
+    line = line_common(args, wall, tot, ks, args.steps)
+    line["config"] = {"workload": "icosphere box drop: 1000 icospheres (subdivision 2) + fixed 12-quad box, "
+                                  f"dt 1e-2, dhat 1e-3, lagged friction mu {P['mu']}",
+                      "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])), "tris": int(len(S["tris"])),
+                      "edges": int(len(S["edges"])), "pre_steps": args.pre}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def run_batched(args):
+    """256 independent scenes advanced together from their first step
+    (warm-up steps, then the timed steps, which include the landings),
+    against the same library run on one scene at a time for a sample of
+    evenly spaced scenes (same steps), scaled to all scenes."""
+    import torch
+
+    import paper_2201_10022_amd as abd
+
+    S, P = sg.batched_drops()
+    n_sc = len(S["scene_body_off"]) - 1
+    steps = args.steps
+    ctx, sc = abd.setup(S, 0)
+    q = torch.as_tensor(S["q0"], device="cuda:0")
+    qd = torch.as_tensor(S["qd0"], device="cuda:0")
+    for i in range(args.warmup):
+        ctx.time_step(sc, P, q, qd)
+    torch.cuda.synchronize()
+    wait_start(args)
+    wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, steps)
+    log(args, f"batched: {steps} steps in {wall:.2f} s, scene Newton iterations {tot['scene_newton']}")
+    ctx.close()
+    # per-scene loop on a sample of scenes
+    pick = np.linspace(0, n_sc - 1, max(1, min(args.loop_scenes, n_sc))).round().astype(int)
+    loop_wall, loop_newton, loop_bodies = 0.0, 0, 0
+    for k in pick:
+        Sk = sg.sub_scene(S, int(k))
+        ck, sk = abd.setup(Sk, 0)
+        qk = torch.as_tensor(Sk["q0"], device="cuda:0")
+        qdk = torch.as_tensor(Sk["qd0"], device="cuda:0")
+        for i in range(args.warmup):
+            ck.time_step(sk, P, qk, qdk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            st = ck.time_step(sk, P, qk, qdk)
+            loop_newton += st["newton_iters"]
+        torch.cuda.synchronize()
+        loop_wall += time.perf_counter() - t0
+        loop_bodies += len(Sk["q0"])
+        ck.close()
+    scale = len(S["q0"]) / loop_bodies  # by body count of the sample
+    line = line_common(args, wall, tot, ks, steps)
+    line["config"] = {"workload": "batched drops: 256 scenes of 2..200 cubes/icospheres over a fixed ground quad, "
+                                  "dt 1e-2, dhat 1e-3, frictionless; timed steps follow the warm-up from rest",
+                      "scenes": n_sc, "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])),
+                      "tris": int(len(S["tris"])), "edges": int(len(S["edges"]))}
+    line["per_scene_loop"] = {
+        "sampled_scenes": [int(k) for k in pick], "sample_bodies": int(loop_bodies),
+        "sample_wall_s": loop_wall, "sample_newton_iters": int(loop_newton),
+        "scaled_wall_s": loop_wall * scale, "scale": "total bodies / sampled bodies",
+        "speedup": loop_wall * scale / wall}
+    print(json.dumps(line), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.workload == "batched":
+        run_batched(args)
+    else:
+        run_box(args)
 
 
 if __name__ == "__main__":

@@ -88,9 +88,14 @@ __global__ void __launch_bounds__(256) k_body_boxes(int nb, const int32_t *voff,
 template <int WRITE>
 __global__ void __launch_bounds__(64) k_body_pairs(int nb, const int32_t *body_scene, const uint8_t *fixed,
                                                    const double *bb, const int32_t *scene_end_of_body,
-                                                   int64_t *cnt, const int64_t *off, int32_t *pairs) {
+                                                   const uint8_t *skip_scene, int64_t *cnt, const int64_t *off,
+                                                   int32_t *pairs) {
   const int a = blockIdx.x;
   if (a >= nb) return;
+  if (skip_scene && skip_scene[body_scene[a]]) {
+    if (!WRITE && threadIdx.x == 0) cnt[a] = 0;
+    return;
+  }
   const int end = scene_end_of_body[a];
   double ba[6];
 #pragma unroll
@@ -266,7 +271,7 @@ __global__ void __launch_bounds__(64) k_pair_tiles(int is_ee, int64_t n_sub, con
 
 int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1, double inflate,
                   int32_t **pt_out, int64_t *n_pt, int32_t **ee_out, int64_t *n_ee, const char *tag,
-                  hipStream_t s) {
+                  hipStream_t s, const uint8_t *skip_scene) {
   const int nb = sc->n_bodies, nv = sc->n_verts, nt = sc->n_tris, ne = sc->n_edges;
   if (!x1) x1 = x0;
   *n_pt = *n_ee = 0;
@@ -290,8 +295,8 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_boff", nb, &boff, s));
   ABD_TRY(ws(ctx, "bp_btot", 4, &btot, s));
   hipLaunchKernelGGL(k_scene_end, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, sc->body_scene, send);
-  hipLaunchKernelGGL(k_body_pairs<0>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send, bcnt,
-                     nullptr, nullptr);
+  hipLaunchKernelGGL(k_body_pairs<0>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
+                     skip_scene, bcnt, nullptr, nullptr);
   ABD_TRY(scan_exclusive_i64(ctx, bcnt, boff, nb, btot, s));
   int64_t *hbuf;
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
@@ -302,7 +307,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   int32_t *bpairs;
   ABD_TRY(ws(ctx, "bp_pairs", 2 * nbp, &bpairs, s));
   hipLaunchKernelGGL(k_body_pairs<1>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
-                     nullptr, boff, bpairs);
+                     skip_scene, nullptr, boff, bpairs);
 
   // culled primitive lists per body pair
   int64_t *cap, *region, *rtot;

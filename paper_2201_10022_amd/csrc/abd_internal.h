@@ -116,8 +116,11 @@ struct FrictionSet {
 // ------------------------------------------------- internal operations ----
 // (shared by the ABI wrappers and the Newton driver)
 int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t s);
+// candidates; sub-scenes s with skip_scene[s] != 0 (device, may be NULL)
+// contribute none
 int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1, double inflate,
-                  int32_t **pt, int64_t *n_pt, int32_t **ee, int64_t *n_ee, const char *tag, hipStream_t s);
+                  int32_t **pt, int64_t *n_pt, int32_t **ee, int64_t *n_ee, const char *tag, hipStream_t s,
+                  const uint8_t *skip_scene = nullptr);
 // pattern of the pairs (pt, ee) and, when given, the extra pairs (pt2, ee2)
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2 = nullptr,

@@ -135,7 +135,8 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
   int32_t *pt, *ee, *keys;
   int64_t npt, nee, nk;
-  ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s));
+  // scenes already done take no part (their direction is zero)
+  ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s, done_dev));
   // the pattern covers the candidates and the lagged friction pairs
   ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", s, fr ? fr->pt : nullptr, fr ? fr->n_pt : 0,
                      fr ? fr->ee : nullptr, fr ? fr->n_ee : 0));
@@ -201,7 +202,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(op_vertex_map(ctx, sc, qa, x1, s));
   int32_t *spt, *see;
   int64_t nspt, nsee;
-  ABD_TRY(op_candidates(ctx, sc, x, x1, prm->dhat, &spt, &nspt, &see, &nsee, "nt_sw", s));
+  ABD_TRY(op_candidates(ctx, sc, x, x1, prm->dhat, &spt, &nspt, &see, &nsee, "nt_sw", s, done_dev));
   st->n_pt_swept = nspt;
   st->n_ee_swept = nsee;
   st->t_candidates_ms += ms_since(t0);

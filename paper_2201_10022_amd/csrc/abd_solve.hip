@@ -515,15 +515,16 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
   int *fin = h + 4;
   const int max_rounds = max_iter / ITER_G + 2;
-  // algorithmic HBM bytes of one iteration: every 12x12 block of the
-  // matrix and of the preconditioner once, plus the 12-vectors read and
+  // algorithmic HBM bytes of one iteration of a scene: every 12x12 block of
+  // its matrix and of its preconditioner once, plus the 12-vectors read and
   // written by the two kernels (spmv: z, p_old in, p_new, Ap out; update:
   // p, Ap, x, r in, x, r, z out)
-  const int64_t bytes_it = (2 * (int64_t)nb + n_keys) * 1152 + 11 * 96 * (int64_t)nb;
   int done = 0;
   bool all = false;
+  bool profiled = false;
   for (int round = 0; round < max_rounds && !all; ++round) {
     hipEvent_t pe = prof_begin(ctx, s);
+    profiled = profiled || pe != nullptr;
     if (exec)
       HIP_TRY(ctx, hipGraphLaunch(exec, s));
     else
@@ -542,10 +543,24 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
       now = 0;
       for (int j = 0; j < S; ++j) now = fin[j] > now ? fin[j] : now;
     }
-    if (pe && !ctx->pending.empty()) ctx->pending.back().units = (int64_t)(now - done) * bytes_it;
     done = now;
   }
   *iters = done;
+  if (profiled && all && !ctx->pending.empty()) {
+    // algorithmic bytes of the whole solve, per scene: its iterations times
+    // its blocks and vectors (a stopped scene's blocks do no work); booked
+    // on the last replay, so the per-replay average is exact
+    std::vector<int32_t> hs(S + 1);
+    std::vector<int64_t> hl(nb + 1);
+    HIP_TRY(ctx, hipMemcpy(hs.data(), sbo, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(hl.data(), lo_beg, (nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    int64_t total = 0;
+    for (int j = 0; j < S; ++j) {
+      const int64_t nbs = hs[j + 1] - hs[j], nks = hl[hs[j + 1]] - hl[hs[j]];
+      total += (int64_t)fin[j] * ((2 * nbs + nks) * 1152 + 11 * 96 * nbs);
+    }
+    ctx->pending.back().units = total;
+  }
   return ABD_OK;
 }
 

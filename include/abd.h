@@ -236,6 +236,33 @@ int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, do
 int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot,
                   abd_stats *stats, hipStream_t stream);
 
+/* Reverse mode of one time step (the differentiability claimed in the
+ * conclusion, sec. 6; implicit function theorem on the optimality condition
+ * grad_q E(q^{t+1}; q~, q^t) = 0).  Given the forward step's start (q_t,
+ * qdot_t) and result q_next, and the loss gradients qbar_next, qdbar_next
+ * with respect to (q^{t+1}, qdot^{t+1}): solves H l = qbar_next +
+ * qdbar_next/dt with H the unprojected Hessian of the incremental potential
+ * at q_next (barrier, orthogonality, inertia and, when mu > 0, the friction
+ * lagged at q_t) by PCG to relative residual rtol, and writes
+ * qbar_t = M l + H_D l - qdbar_next/dt and qdbar_t = dt M l (H_D the friction
+ * Hessian; the lagged normal force, tangent basis and closest-point weights
+ * are held as data of the step).  Zero on fixed bodies.  All arrays
+ * [n_bodies][12]; outputs must not alias inputs.  Syncs; *pcg_iters (host,
+ * may be NULL). */
+int abd_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q_t,
+                     const double *qdot_t, const double *q_next, const double *qbar_next, const double *qdbar_next,
+                     double rtol, double *qbar_t, double *qdbar_t, int32_t *pcg_iters, hipStream_t stream);
+
+/* Gradient of a loss of the state after n_steps time steps from (q0, qdot0):
+ * given qbar_T, qdbar_T (the loss gradient with respect to q^n and qdot^n),
+ * writes qbar_0, qdbar_0.  Runs the forward steps keeping (q, qdot) every
+ * checkpoint_every steps (context workspace), then per segment, last
+ * first, re-runs the segment's steps and applies abd_adjoint_step backwards.
+ * Syncs. */
+int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q0,
+                         const double *qdot0, int32_t n_steps, int32_t checkpoint_every, const double *qbar_T,
+                         const double *qdbar_T, double rtol, double *qbar_0, double *qdbar_0, hipStream_t stream);
+
 /* Lagged friction (sec. 4, friction potential V_F = sum of mu lambda f0 over
  * the active contact pairs; lagging as in IPC): quantities held fixed over a
  * time step are taken at the step-start positions xt.

@@ -18,6 +18,9 @@ Paper passages followed (Lan et al., Affine Body Dynamics):
   assembly              sec. 4.3 (J^T H J into 12x12 body blocks)
   friction              sec. 4, V_F (IPC's lagged model: normal force,
                         closest points and tangent basis fixed at q^t)
+  adjoint               the conclusion's (sec. 6) claim of differentiability,
+                        made concrete by the implicit function theorem on
+                        the time step's optimality condition
 Readings where the paper is silent (IPC / ACCD conventions, distance case
 tie-breaks, mollifier, line search, convergence) are listed in the
 project's design notes and restated at each function.
@@ -500,12 +503,19 @@ def step_friction(S, q, params):
     return friction_lag(S, xt, pt, ee, params)
 
 
-def time_step(S, B, q, qd, params, log=None):
+def time_step(S, B, q, qd, params, log=None, lag=None, F_out=None):
     """Implicit-Euler time step: minimise the incremental potential starting
     from q^t; qdot^{t+1} = (q^{t+1} - q^t) / dt.  With mu > 0 the friction
-    state is lagged once at q^t."""
+    state is lagged once at q^t; `lag` (a friction state) replaces the lagged
+    pairs, lambda, T and w (x^t stays that of q), and F_out (a list)
+    receives the state used."""
     qt = q_tilde(S, q, qd, params)
-    F = step_friction(S, q, params)
+    if lag is not None:
+        F = dict(lag, xt=vertex_map(S, q))
+    else:
+        F = step_friction(S, q, params)
+    if F_out is not None:
+        F_out.append(F)
     qn = q.copy()
     its = 0
     for its in range(1, params["max_newton"] + 1):
@@ -519,6 +529,68 @@ def time_step(S, B, q, qd, params, log=None):
     qdn = (qn - q) / params["dt"]
     qdn[S["body_fixed"] != 0] = 0.0
     return qn, qdn, its
+
+
+# ------------------------------------------------------------- adjoint ----
+
+def _matvec(S, diag, off, keys, v):
+    """(diag + off + off^T) v over the free DOFs, v [nb,12]."""
+    A, free = assemble(S, diag, off, keys)
+    out = np.zeros_like(v)
+    out[free] = (A @ v[free].reshape(-1)).reshape(-1, 12)
+    return out
+
+
+def adjoint_step(S, B, q_t, qd_t, q_next, qbar_next, qdbar_next, params, F=None):
+    """Reverse mode of one implicit-Euler time step.  q^{t+1} minimises
+    E(q; q~, q^t) with q~ = q^t + dt qdot^t + dt^2 M^-1 f, so
+    grad_q E(q^{t+1}) = 0; differentiating that condition (implicit
+    function theorem) with H the unprojected Hessian of E at q^{t+1}:
+      H dq^{t+1} = M dq~ + H_D dq^t,
+    H_D the friction Hessian (the friction potential depends on q - q^t
+    through u; the lagged lambda, T and w are data of the step).  With
+    qdot^{t+1} = (q^{t+1} - q^t)/dt and a = qbar^{t+1} + qdbar^{t+1}/dt:
+      H l = a;  qbar^t = M l + H_D l - qdbar^{t+1}/dt;  qdbar^t = dt M l.
+    Fixed bodies carry no adjoint.  Returns (qbar^t, qdbar^t)."""
+    dt = params["dt"]
+    free = S["body_fixed"] == 0
+    qt = q_tilde(S, q_t, qd_t, params)
+    Fn = None if F is None else dict(F, xt=vertex_map(S, q_t))
+    gh = grad_hess(S, B, q_next, qt, params, project=False, F=Fn)
+    a = (qbar_next + qdbar_next / dt) * free[:, None]
+    lam = solve(S, gh["diag"], gh["off"], gh["keys"], a)
+    Ml = np.einsum("bij,bj->bi", B.M, lam) * free[:, None]
+    qbar = Ml - qdbar_next / dt
+    if Fn is not None:
+        fr = friction(S, vertex_map(S, q_next), Fn, params, gh["keys"])
+        qbar = qbar + _matvec(S, fr["diag"], fr["off"], gh["keys"], lam)
+    qbar = qbar * free[:, None]
+    return qbar, dt * Ml
+
+
+def rollout(S, B, q0, qd0, params, n_steps, lags=None):
+    """Forward simulation: states [(q^0, qd^0), ..., (q^n, qd^n)] and the
+    friction state of every step (None without friction).  lags: per-step
+    friction states to hold (see time_step)."""
+    q, qd = q0.copy(), qd0.copy()
+    states, Fs = [(q.copy(), qd.copy())], []
+    for t in range(n_steps):
+        Fo = []
+        q, qd, _ = time_step(S, B, q, qd, params, lag=None if lags is None else lags[t], F_out=Fo)
+        states.append((q.copy(), qd.copy()))
+        Fs.append(Fo[0])
+    return states, Fs
+
+
+def rollout_grad(S, B, q0, qd0, params, n_steps, qbar_T, qdbar_T):
+    """dL/dq^0, dL/dqdot^0 of a loss L(q^n, qdot^n) with the given
+    gradients, by adjoint_step from the last step back."""
+    states, Fs = rollout(S, B, q0, qd0, params, n_steps)
+    qbar, qdbar = qbar_T.copy(), qdbar_T.copy()
+    for t in range(n_steps - 1, -1, -1):
+        (q_t, qd_t), (q_n, _) = states[t], states[t + 1]
+        qbar, qdbar = adjoint_step(S, B, q_t, qd_t, q_n, qbar, qdbar, params, Fs[t])
+    return qbar, qdbar, states, Fs
 
 
 def pair_local(is_ee, X, xb, dhat, kappa):

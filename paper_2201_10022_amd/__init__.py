@@ -289,6 +289,26 @@ class Context:
     def friction_end_step(self):
         self._check(self.L.abd_friction_end_step(self.h))
 
+    # -- adjoint -------------------------------------------------------
+    def adjoint_step(self, scene, params, q_t, qd_t, q_next, qbar_next, qdbar_next, rtol=1e-12):
+        qbar = torch.zeros_like(q_t)
+        qdbar = torch.zeros_like(q_t)
+        it = ctypes.c_int32(0)
+        prm = make_params(params)
+        self._check(self.L.abd_adjoint_step(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q_t), _ptr(qd_t),
+                                            _ptr(q_next), _ptr(qbar_next), _ptr(qdbar_next), float(rtol), _ptr(qbar),
+                                            _ptr(qdbar), ctypes.byref(it), _stream()))
+        return qbar, qdbar, it.value
+
+    def rollout_backward(self, scene, params, q0, qd0, n_steps, checkpoint_every, qbar_T, qdbar_T, rtol=1e-12):
+        qbar = torch.zeros_like(q0)
+        qdbar = torch.zeros_like(q0)
+        prm = make_params(params)
+        self._check(self.L.abd_rollout_backward(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q0),
+                                                _ptr(qd0), int(n_steps), int(checkpoint_every), _ptr(qbar_T),
+                                                _ptr(qdbar_T), float(rtol), _ptr(qbar), _ptr(qdbar), _stream()))
+        return qbar, qdbar
+
     # -- measurement ---------------------------------------------------
     def profile(self, enable=True, reset=True):
         self._check(self.L.abd_profile(self.h, int(enable), int(reset)))
@@ -298,6 +318,33 @@ class Context:
         self._check(self.L.abd_profile_query(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(la),
                                              ctypes.byref(un)))
         return dict(ms=ms.value, launches=la.value, units=un.value)
+
+
+class Rollout(torch.autograd.Function):
+    """(q^n, qdot^n) after n time steps from (q0, qdot0), differentiable:
+    the backward pass is abd_rollout_backward (checkpointed adjoint)."""
+
+    @staticmethod
+    def forward(fctx, q0, qd0, ctx, scene, params, n_steps, checkpoint_every, rtol):
+        q, qd = q0.detach().clone(), qd0.detach().clone()
+        for _ in range(n_steps):
+            ctx.time_step(scene, params, q, qd)
+        fctx.save_for_backward(q0.detach(), qd0.detach())
+        fctx.args = (ctx, scene, params, n_steps, checkpoint_every, rtol)
+        return q, qd
+
+    @staticmethod
+    def backward(fctx, gq, gqd):
+        q0, qd0 = fctx.saved_tensors
+        ctx, scene, params, n_steps, ck, rtol = fctx.args
+        gq = torch.zeros_like(q0) if gq is None else gq.contiguous()
+        gqd = torch.zeros_like(q0) if gqd is None else gqd.contiguous()
+        qbar, qdbar = ctx.rollout_backward(scene, params, q0, qd0, n_steps, ck, gq, gqd, rtol)
+        return qbar, qdbar, None, None, None, None, None, None
+
+
+def rollout(ctx, scene, params, q0, qd0, n_steps, checkpoint_every=10, rtol=1e-12):
+    return Rollout.apply(q0, qd0, ctx, scene, params, n_steps, checkpoint_every, rtol)
 
 
 def setup(S, device=0):

@@ -168,8 +168,11 @@ __device__ __forceinline__ double f1_of(double y, double eps) {
 }
 
 // one lane per friction pair: energy and (unless ENERGY_ONLY) the 12-vector
-// gradient and packed 12x12 Hessian, plus the pair's assembly record
-template <bool ENERGY_ONLY>
+// gradient and packed 12x12 Hessian, plus the pair's assembly record.
+// HVP: in place of the gradient, the local Hessian times J v for the body
+// vector v [nb][12] (so that assembling it gives the friction Hessian times
+// v).
+template <bool ENERGY_ONLY, bool HVP = false>
 __global__ void __launch_bounds__(128) k_friction_local(int64_t n, int64_t n_pt, const int32_t *pt,
                                                         const int32_t *ee, const int32_t *tris,
                                                         const int32_t *edges, const int32_t *vert_body,
@@ -177,7 +180,8 @@ __global__ void __launch_bounds__(128) k_friction_local(int64_t n, int64_t n_pt,
                                                         const double *T, const double *w, double mu, double eps,
                                                         double *e_out, double *g_out, double *H_out,
                                                         PairInfo *info, const int32_t *body_scene,
-                                                        int32_t *key_out) {
+                                                        int32_t *key_out, const double *v = nullptr,
+                                                        const double *xbar = nullptr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int is_ee, vid[4];
@@ -232,10 +236,31 @@ __global__ void __launch_bounds__(128) k_friction_local(int64_t n, int64_t n_pt,
       const double v = Ti[r] * (M00 * Ti[c] + M01 * Ti[3 + c]) + Ti[3 + r] * (M01 * Ti[c] + M11 * Ti[3 + c]);
       K[r][c] = on ? ml * v : 0.0;
     }
+  if (HVP) {
+    // J v at the 4 vertices, weighted sum nu = sum_k w_k (J v)_k, then
+    // (w w^T (x) K) (J v) = w_k K nu
+    double nu[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k) {
+      const double *vb = v + 12 * (int64_t)vert_body[vid[k]];
+      const double *xb = xbar + 3 * (int64_t)vid[k];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) g_out[12 * i + 3 * k + c] = wk[k] * f[c];
+      for (int c = 0; c < 3; ++c) nu[c] += wk[k] * (vb[c] + vb[3 + 3 * c] * xb[0] + vb[4 + 3 * c] * xb[1] +
+                                                   vb[5 + 3 * c] * xb[2]);
+    }
+    double Kn[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) Kn[r] = K[r][0] * nu[0] + K[r][1] * nu[1] + K[r][2] * nu[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g_out[12 * i + 3 * k + c] = wk[k] * Kn[c];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g_out[12 * i + 3 * k + c] = wk[k] * f[c];
+  }
 #pragma unroll
   for (int r = 0; r < 12; ++r)
 #pragma unroll
@@ -289,6 +314,23 @@ int op_friction_local(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, 
                      g_loc, H_loc, info, sc->body_scene, nullptr);
   prof_end(ctx, pe, "friction_local", n, s);
   return abd_hip_check(ctx, hipGetLastError(), "k_friction_local");
+}
+
+int op_friction_hvp(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x, const double *v,
+                    double *out, hipStream_t s) {
+  const int64_t n = fr->n();
+  if (n == 0) return ABD_OK;
+  double *e_loc, *g_loc, *H_loc;
+  PairInfo *info;
+  ABD_TRY(ws(ctx, "fh_e", n, &e_loc, s));
+  ABD_TRY(ws(ctx, "fh_g", 12 * n, &g_loc, s));
+  ABD_TRY(ws(ctx, "fh_H", 78 * n, &H_loc, s));
+  ABD_TRY(ws(ctx, "fh_info", n, &info, s));
+  hipLaunchKernelGGL((k_friction_local<false, true>), dim3(grid_for(n, 128)), dim3(128), 0, s, n, fr->n_pt, fr->pt,
+                     fr->ee, sc->tris, sc->edges, sc->vert_body, x, fr->xt, fr->lam, fr->T, fr->w, fr->mu, fr->eps,
+                     e_loc, g_loc, H_loc, info, sc->body_scene, nullptr, v, sc->xbar);
+  HIP_TRY(ctx, hipGetLastError());
+  return op_assemble(ctx, sc, n, info, g_loc, H_loc, nullptr, 0, out, nullptr, nullptr, s);
 }
 
 int op_friction_energy(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x, double *energy,

@@ -144,6 +144,12 @@ int op_friction_local(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, 
                       double *g_loc, double *H_loc, PairInfo *info, hipStream_t s);
 int op_friction_energy(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x, double *energy,
                        hipStream_t s);
+// friction Hessian of fr at x times the body vector v [nb][12], accumulated
+// into out [nb][12]
+int op_friction_hvp(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x, const double *v,
+                    double *out, hipStream_t s);
+// reads and clears the device error flags of the last operations (syncs)
+int op_read_err(abd_ctx *ctx, hipStream_t s);
 // the friction state of the current time step (null when none is set)
 int op_friction_state(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, FrictionSet *fr, bool *active,
                       hipStream_t s);

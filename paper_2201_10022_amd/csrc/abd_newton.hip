@@ -42,7 +42,9 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-int read_err(abd_ctx *ctx, hipStream_t s) {
+}  // namespace
+
+int op_read_err(abd_ctx *ctx, hipStream_t s) {
   int *err, *h;
   ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
@@ -56,6 +58,8 @@ int read_err(abd_ctx *ctx, hipStream_t s) {
   if (e & 8) return abd_fail(ctx, ABD_E_PCG, "PCG breakdown (non-positive curvature)");
   return ABD_OK;
 }
+
+namespace {
 
 // per-body masks and per-scene step lengths
 __global__ void k_neg_masked(int nb, const int32_t *body_scene, const uint8_t *done, const double *g, double *out) {
@@ -153,7 +157,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, e, g, diag, 1, s));
   int64_t nap = 0, nae = 0;
   ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 1, &nap, &nae, s, fr));
-  ABD_TRY(read_err(ctx, s));
+  ABD_TRY(op_read_err(ctx, s));
   st->t_barrier_ms += ms_since(t0);
   st->n_active_pt = nap;
   st->n_active_ee = nae;
@@ -165,7 +169,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   hipLaunchKernelGGL(k_neg_masked, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, done_dev, g, rhs);
   int its = 0;
   ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s));
-  ABD_TRY(read_err(ctx, s));
+  ABD_TRY(op_read_err(ctx, s));
   st->pcg_iters = its;
   st->t_solve_ms += ms_since(t0);
   ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, sv, s));

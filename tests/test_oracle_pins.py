@@ -801,3 +801,52 @@ def test_sub_scene_extraction_round_trip():
     R = b.build()
     for key in S:
         np.testing.assert_array_equal(R[key], S[key], err_msg=key)
+
+
+# -------------------------------------------------------------- adjoint ----
+
+def _loss_and_fd(S, P, n, lags, seed, n_dirs=3):
+    B = oracle.Body(S)
+    q0, qd0 = S["q0"].copy(), S["qd0"].copy()
+    free = S["body_fixed"] == 0
+    b1 = int(np.flatnonzero(free)[0])
+    target = np.array([0.3, 0.4, -0.2])
+    states, Fs = oracle.rollout(S, B, q0, qd0, P, n)
+    qbar = np.zeros_like(q0)
+    qbar[b1, :3] = 2 * (states[-1][0][b1, :3] - target)
+    gq, gqd, _, _ = oracle.rollout_grad(S, B, q0, qd0, P, n, qbar, np.zeros_like(q0))
+
+    def loss(qd):
+        st, _ = oracle.rollout(S, B, q0, qd, P, n, lags=Fs if lags else None)
+        return float(np.sum((st[-1][0][b1, :3] - target) ** 2))
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_dirs):
+        d = rng.normal(size=q0.shape) * free[:, None]
+        d /= np.linalg.norm(d)
+        h = 1e-6
+        fd = (loss(qd0 + h * d) - loss(qd0 - h * d)) / (2 * h)
+        out.append((fd, float(np.sum(gqd * d))))
+    return out
+
+
+def test_adjoint_rollout_gradient_frictionless_by_fd():
+    # implicit-function adjoint of 20 implicit-Euler steps of the 3-cube
+    # stack (contacts form and persist) vs central differences of the
+    # rollout in the initial velocities (Newton converged tightly)
+    S, P = sg.three_cubes()
+    P = dict(P, newton_tol=1e-7, max_newton=400)
+    S["qd0"][1:, 1] = -0.5
+    for fd, ad in _loss_and_fd(S, P, 20, False, 2):
+        assert ad == pytest.approx(fd, rel=1e-4)
+
+
+def test_adjoint_rollout_gradient_friction_lag_held_by_fd():
+    # with friction: the adjoint holds each step's lagged normal force,
+    # tangent basis and weights as data; differences of the rollout with the
+    # same lagged data (x^t still moving with q^t) agree with it
+    S, P = sg.cube_on_slope(math.atan(0.75), 0.5, v0=1.0)
+    P = dict(P, newton_tol=1e-9)
+    for fd, ad in _loss_and_fd(S, P, 15, True, 1):
+        assert ad == pytest.approx(fd, rel=1e-5)

@@ -244,9 +244,10 @@ int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, doub
  * qdbar_next/dt with H the unprojected Hessian of the incremental potential
  * at q_next (barrier, orthogonality, inertia and, when mu > 0, the friction
  * lagged at q_t) by PCG to relative residual rtol, and writes
- * qbar_t = M l + H_D l - qdbar_next/dt and qdbar_t = dt M l (H_D the friction
- * Hessian; the lagged normal force, tangent basis and closest-point weights
- * are held as data of the step).  Zero on fixed bodies.  All arrays
+ * qbar_t = M l + H_D l - C_lag^T l - qdbar_next/dt and qdbar_t = dt M l
+ * (H_D the friction Hessian; C_lag the derivative of the friction gradient
+ * through the lagged normal force, tangent basis and closest-point weights,
+ * which are functions of q_t).  Zero on fixed bodies.  All arrays
  * [n_bodies][12]; outputs must not alias inputs.  Syncs; *pcg_iters (host,
  * may be NULL). */
 int abd_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q_t,

@@ -78,6 +78,9 @@ def lib():
                                    _d, ctypes.c_double, ctypes.c_double, _d, _d, _d, _d, _i32, ctypes.c_int64,
                                    ctypes.c_int]
         L.ora_friction.restype = ctypes.c_int64
+        L.ora_friction_lag_vjp.argtypes = [ctypes.c_int64, ctypes.c_int, _i32, _i32, _i32, _i32, _u8, _d, _d, _d, _d,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _d,
+                                           _d]
         L.ora_psd_project.argtypes = [ctypes.c_int, _d]
         L.ora_pair_local.argtypes = [ctypes.c_int, _d, _d, ctypes.c_double, ctypes.c_double, _d, _d, _d]
         L.ora_pair_local.restype = ctypes.c_int
@@ -324,6 +327,28 @@ def friction(S, x, F, params, keys, hess=True):
     return dict(energy=e[0], grad=g, diag=D, off=O[:len(keys)])
 
 
+def friction_lag_vjp(S, x, F, params, l):
+    """J^T grad_{x^t} [ (J l) . g(x; lambda, T, w) ] over the lagged pairs of
+    F, the derivative taken through the lagged lambda, T and w only (the
+    sliding displacement's own x^t is the friction Hessian's part)."""
+    nb = len(S["body_fixed"])
+    out = np.zeros((nb, 12))
+    l = _c(l, np.float64)
+    eps = params["eps_v"] * params["dt"]
+    for is_ee, nm in ((0, "pt"), (1, "ee")):
+        f = F[nm]
+        n = len(f["pairs"])
+        if n == 0:
+            continue
+        lib().ora_friction_lag_vjp(n, is_ee, _p(f["pairs"], _i32), _p(_c(S["vert_body"], np.int32), _i32),
+                                   _p(_c(S["tris"], np.int32), _i32), _p(_c(S["edges"], np.int32), _i32),
+                                   _p(_c(S["body_fixed"], np.uint8), _u8), _p(_c(S["xbar"], np.float64), _d),
+                                   _p(_c(x, np.float64), _d), _p(F["xt"], _d), _p(_c(f["lam"], np.float64), _d),
+                                   float(params["mu"]), float(eps), float(params["dhat"]), float(params["kappa_b"]),
+                                   _p(l, _d), _p(out, _d))
+    return out
+
+
 def friction_energy(S, x, F, params):
     return friction(S, x, F, params, np.zeros((0, 2), np.int32), hess=False)["energy"]
 
@@ -548,9 +573,13 @@ def adjoint_step(S, B, q_t, qd_t, q_next, qbar_next, qdbar_next, params, F=None)
     function theorem) with H the unprojected Hessian of E at q^{t+1}:
       H dq^{t+1} = M dq~ + H_D dq^t,
     H_D the friction Hessian (the friction potential depends on q - q^t
-    through u; the lagged lambda, T and w are data of the step).  With
+    through u).  With
     qdot^{t+1} = (q^{t+1} - q^t)/dt and a = qbar^{t+1} + qdbar^{t+1}/dt:
       H l = a;  qbar^t = M l + H_D l - qdbar^{t+1}/dt;  qdbar^t = dt M l.
+    The lagged lambda, T and w are themselves functions of q^t; their part
+    of the mixed derivative is subtracted as well:
+      qbar^t -= J^T grad_{x^t} [ (J l) . g_D(x^{t+1}; lambda, T, w) ],
+    g_D the friction gradient, the derivative taken through the lag only.
     Fixed bodies carry no adjoint.  Returns (qbar^t, qdbar^t)."""
     dt = params["dt"]
     free = S["body_fixed"] == 0
@@ -562,8 +591,10 @@ def adjoint_step(S, B, q_t, qd_t, q_next, qbar_next, qdbar_next, params, F=None)
     Ml = np.einsum("bij,bj->bi", B.M, lam) * free[:, None]
     qbar = Ml - qdbar_next / dt
     if Fn is not None:
-        fr = friction(S, vertex_map(S, q_next), Fn, params, gh["keys"])
+        xn = vertex_map(S, q_next)
+        fr = friction(S, xn, Fn, params, gh["keys"])
         qbar = qbar + _matvec(S, fr["diag"], fr["off"], gh["keys"], lam)
+        qbar = qbar - friction_lag_vjp(S, xn, Fn, params, lam)
     qbar = qbar * free[:, None]
     return qbar, dt * Ml
 

@@ -1094,6 +1094,154 @@ int64_t ora_friction(int64_t n, int is_ee, const int32_t* pairs, const int32_t* 
 }  // extern "C"
 
 namespace {
+
+// ------------------------------------------- friction lag, differentiated ----
+// The lagged quantities as functions of the step-start positions x^t of a
+// pair's 4 vertices (jets in those 12 coordinates): closest-point weights,
+// normal force and tangent basis, with the case, the tangent axis and the
+// mollifier branch fixed by the values (they are piecewise constant).
+Jet jc(double c) { return jconst(c); }
+Jet jneg(const Jet& a) { return scale(a, -1.0); }
+
+void closest_weights_jet(int type, const V3<Jet> X[4], Jet w[4]) {
+  for (int k = 0; k < 4; ++k) w[k] = jc(0.0);
+  CaseSlots c = case_slots(type);
+  if (c.kind == 0) {
+    w[c.i] = jc(1.0);
+    w[c.j] = jc(-1.0);
+  } else if (c.kind == 1) {
+    V3<Jet> e = sub(X[c.k], X[c.j]);
+    const Jet t = dot(sub(X[c.i], X[c.j]), e) / dot(e, e);
+    w[c.i] = jc(1.0);
+    w[c.j] = t - jc(1.0);
+    w[c.k] = jneg(t);
+  } else if (c.kind == 2) {
+    V3<Jet> e1 = sub(X[2], X[1]), e2 = sub(X[3], X[1]), dp = sub(X[0], X[1]);
+    const Jet a = dot(e1, e1), b = dot(e1, e2), cc = dot(e2, e2), f1 = dot(e1, dp), f2 = dot(e2, dp);
+    const Jet det = a * cc - b * b;
+    const Jet u = (cc * f1 - b * f2) / det, v = (a * f2 - b * f1) / det;
+    w[0] = jc(1.0);
+    w[1] = u + v - jc(1.0);
+    w[2] = jneg(u);
+    w[3] = jneg(v);
+  } else {
+    V3<Jet> u = sub(X[1], X[0]), v = sub(X[3], X[2]), r0 = sub(X[0], X[2]);
+    const Jet a = dot(u, u), b = dot(u, v), cc = dot(v, v), d = dot(u, r0), e = dot(v, r0);
+    const Jet den = a * cc - b * b;
+    const Jet s = (b * e - cc * d) / den, t = (a * e - b * d) / den;
+    w[0] = jc(1.0) - s;
+    w[1] = s;
+    w[2] = t - jc(1.0);
+    w[3] = jneg(t);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Adjoint term of the lag: for every lagged pair with lambda > 0,
+// phi = v . g(x; lambda, T, w) with g the pair's friction gradient in vertex
+// space at x (sliding displacement u = T^T sum_k w_k (x_k - x^t_k) held as
+// data) and v = J l at the pair's vertices; the gradient of phi with respect
+// to the pair's step-start positions (through lambda, T, w only) is mapped
+// by J^T into out [nb][12] (accumulated; fixed bodies dropped).
+void ora_friction_lag_vjp(int64_t n, int is_ee, const int32_t* pairs, const int32_t* vert_body, const int32_t* tris,
+                          const int32_t* edges, const uint8_t* fixed, const double* xbar, const double* x,
+                          const double* xt, const double* lam, double mu, double eps, double dhat, double kappa,
+                          const double* l, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(lam[i] > 0.0)) continue;
+    int vid[4];
+    pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
+    D3 Xd[4];
+    for (int k = 0; k < 4; ++k) Xd[k] = ld3(xt, vid[k]);
+    const int ty = classify(is_ee, Xd);
+    V3<Jet> X[4];
+    for (int k = 0; k < 4; ++k) X[k] = {jvar(Xd[k].x, 3 * k), jvar(Xd[k].y, 3 * k + 1), jvar(Xd[k].z, 3 * k + 2)};
+    // lambda = -kappa m B'(d)
+    Jet num, den;
+    case_nd<Jet>(ty, X, num, den, jc(1.0));
+    const Jet d = jsqrt(num / den);
+    const Jet dm = d - jc(dhat);
+    const Jet Bp = jneg(scale(dm * jlog(scale(d, 1.0 / dhat)), 2.0)) - dm * dm / d;
+    Jet m = jc(1.0);
+    if (is_ee) {
+      V3<Jet> nn = cross(sub(X[1], X[0]), sub(X[3], X[2]));
+      const Jet c = dot(nn, nn);
+      const double* a0 = xbar + 3 * vid[0];
+      const double* a1 = xbar + 3 * vid[1];
+      const double* b0 = xbar + 3 * vid[2];
+      const double* b1 = xbar + 3 * vid[3];
+      D3 u{a1[0] - a0[0], a1[1] - a0[1], a1[2] - a0[2]}, v{b1[0] - b0[0], b1[1] - b0[1], b1[2] - b0[2]};
+      const double ep = (1e-3 * dot(u, u)) * dot(v, v);
+      if (c.v < ep) {
+        const Jet r = scale(c, 1.0 / ep);
+        m = (jc(2.0) - r) * r;
+      }
+    }
+    const Jet L = jneg(scale(m * Bp, kappa));
+    Jet w[4];
+    closest_weights_jet(ty, X, w);
+    V3<Jet> r{jc(0.0), jc(0.0), jc(0.0)};
+    for (int k = 0; k < 4; ++k) r = {r.x + w[k] * X[k].x, r.y + w[k] * X[k].y, r.z + w[k] * X[k].z};
+    const Jet nr = jsqrt(dot(r, r));
+    V3<Jet> nv{r.x / nr, r.y / nr, r.z / nr};
+    const double an[3] = {std::fabs(nv.x.v), std::fabs(nv.y.v), std::fabs(nv.z.v)};
+    int ax = 0;
+    if (an[1] < an[ax]) ax = 1;
+    if (an[2] < an[ax]) ax = 2;
+    V3<Jet> ea{jc(ax == 0 ? 1.0 : 0.0), jc(ax == 1 ? 1.0 : 0.0), jc(ax == 2 ? 1.0 : 0.0)};
+    V3<Jet> t1 = cross(nv, ea);
+    const Jet l1 = jsqrt(dot(t1, t1));
+    t1 = {t1.x / l1, t1.y / l1, t1.z / l1};
+    const V3<Jet> t2 = cross(nv, t1);
+    // delta = sum w_k (x_k - x^t_k) (displacements are data), nu = sum w_k (J l)_k
+    V3<Jet> delta{jc(0.0), jc(0.0), jc(0.0)}, nu{jc(0.0), jc(0.0), jc(0.0)};
+    for (int k = 0; k < 4; ++k) {
+      const double dx[3] = {x[3 * vid[k]] - xt[3 * vid[k]], x[3 * vid[k] + 1] - xt[3 * vid[k] + 1],
+                            x[3 * vid[k] + 2] - xt[3 * vid[k] + 2]};
+      double J[3][12];
+      kin_jacobian(xbar + 3 * vid[k], J);
+      const double* lb = l + 12 * vert_body[vid[k]];
+      double vk[3];
+      for (int c = 0; c < 3; ++c) {
+        vk[c] = 0.0;
+        for (int j = 0; j < 12; ++j) vk[c] += J[c][j] * lb[j];
+      }
+      delta = {delta.x + scale(w[k], dx[0]), delta.y + scale(w[k], dx[1]), delta.z + scale(w[k], dx[2])};
+      nu = {nu.x + scale(w[k], vk[0]), nu.y + scale(w[k], vk[1]), nu.z + scale(w[k], vk[2])};
+    }
+    const Jet u0 = dot(t1, delta), u1 = dot(t2, delta);
+    const Jet yy = u0 * u0 + u1 * u1;
+    Jet gs;
+    if (yy.v == 0.0) {
+      gs = jc(2.0 / eps);
+    } else {
+      const Jet y = jsqrt(yy);
+      gs = y.v < eps ? scale(y, -1.0 / (eps * eps)) + jc(2.0 / eps) : jc(1.0) / y;
+    }
+    const Jet coef = scale(L * gs, mu);
+    const V3<Jet> f{coef * (t1.x * u0 + t2.x * u1), coef * (t1.y * u0 + t2.y * u1), coef * (t1.z * u0 + t2.z * u1)};
+    const Jet phi = dot(nu, f);
+    // J^T grad into the bodies
+    for (int k = 0; k < 4; ++k) {
+      const int b = vert_body[vid[k]];
+      if (fixed[b]) continue;
+      double J[3][12];
+      kin_jacobian(xbar + 3 * vid[k], J);
+      for (int j = 0; j < 12; ++j) {
+        double sacc = 0.0;
+        for (int c = 0; c < 3; ++c) sacc += J[c][j] * phi.g[3 * k + c];
+        out[12 * b + j] += sacc;
+      }
+    }
+  }
+}
+
+}  // extern "C"
+
+namespace {
 }  // namespace
 
 extern "C" {

@@ -4,11 +4,15 @@
 // grad_q E(q^{t+1}) = 0.  Differentiating that condition (implicit
 // function theorem), with H the unprojected Hessian of E at q^{t+1} and H_D
 // the friction Hessian (the friction potential depends on q - q^t through
-// the sliding displacement; the lagged normal force, tangent basis and
-// closest-point weights are data of the step):
-//     H dq^{t+1} = M dq~ + H_D dq^t.
+// the sliding displacement) and C_lag the derivative of the friction
+// gradient through the lagged normal force, tangent basis and closest-point
+// weights, themselves functions of q^t:
+//     H dq^{t+1} = M dq~ + (H_D - C_lag) dq^t.
 // With qdot^{t+1} = (q^{t+1} - q^t)/dt and a = qbar^{t+1} + qdbar^{t+1}/dt:
-//     H l = a;  qbar^t = M l + H_D l - qdbar^{t+1}/dt;  qdbar^t = dt M l.
+//     H l = a;  qbar^t = M l + H_D l - C_lag^T l - qdbar^{t+1}/dt;
+//     qdbar^t = dt M l.
+// C_lag^T l is the gradient with respect to the pairs' step-start
+// positions of (J l) . g_D, taken with dual numbers one coordinate at a time.
 // A rollout's gradient runs these steps backwards from checkpoints, re-running
 // each segment's forward steps (the forward path is deterministic, so the
 // re-run states equal the original ones bit for bit).
@@ -49,6 +53,11 @@ __global__ void k_adj_combine(int nb, const uint8_t *fixed, const double *mass, 
     qb[i] = Ml[i] + hd[i] - qn[i] / dt;
     qdb[i] = dt * Ml[i];
   }
+}
+
+__global__ void k_sub_into(int n, const double *a, double *b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] -= a[i];
 }
 
 __global__ void k_zero_d(int64_t n, double *a) {
@@ -119,7 +128,15 @@ int op_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, co
   ABD_TRY(op_read_err(ctx, s));
   if (iters) *iters = its;
   ABD_TRY(zero_d(ctx, hdl, n12, s));
-  if (fr) ABD_TRY(op_friction_hvp(ctx, sc, fr, x, l, hdl, s));
+  if (fr) {
+    ABD_TRY(op_friction_hvp(ctx, sc, fr, x, l, hdl, s));
+    // the lag's own dependence on q^t enters with the opposite sign
+    double *lv;
+    ABD_TRY(ws(ctx, "adj_lagv", n12, &lv, s));
+    ABD_TRY(zero_d(ctx, lv, n12, s));
+    ABD_TRY(op_friction_lag_vjp(ctx, sc, prm, fr, x, l, lv, s));
+    hipLaunchKernelGGL(k_sub_into, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, lv, hdl);
+  }
   hipLaunchKernelGGL(k_adj_combine, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed, sc->mass, l, hdl,
                      qdbar_next, prm->dt, qbar_t, qdbar_t);
   return abd_hip_check(ctx, hipGetLastError(), "k_adj_combine");

@@ -267,6 +267,242 @@ __global__ void __launch_bounds__(128) k_friction_local(int64_t n, int64_t n_pt,
     for (int c = r; c < 12; ++c) H_out[78 * i + S12::at(r, c)] = wk[r / 3] * wk[c / 3] * K[r % 3][c % 3];
 }
 
+// ------------------------------------------------ lag, differentiated ----
+// First-order dual numbers (value, derivative along one seeded coordinate)
+// for the adjoint's lag term: the lagged lambda, T and w as functions of the
+// step-start positions, one coordinate of the pair's 12 per pass.
+struct dl {
+  double v, d;
+};
+__device__ __forceinline__ dl operator+(dl a, dl b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ dl operator-(dl a, dl b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ dl operator*(dl a, dl b) { return {a.v * b.v, a.v * b.d + a.d * b.v}; }
+__device__ __forceinline__ dl operator/(dl a, dl b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+__device__ __forceinline__ dl dc(double c) { return {c, 0.0}; }
+__device__ __forceinline__ dl dsqrt(dl a) {
+  const double s = sqrt(a.v);
+  return {s, 0.5 * a.d / s};
+}
+__device__ __forceinline__ dl dlog(dl a) { return {log(a.v), a.d / a.v}; }
+struct dl3 {
+  dl x, y, z;
+};
+__device__ __forceinline__ dl3 dsub(dl3 a, dl3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ dl ddot(dl3 a, dl3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ dl3 dcross(dl3 a, dl3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ dl3 dscale(dl3 a, dl s) { return {a.x * s, a.y * s, a.z * s}; }
+
+template <int I, int J>
+__device__ __forceinline__ dl dd2_pp(const dl3 X[4]) {
+  const dl3 d = dsub(X[I], X[J]);
+  return ddot(d, d);
+}
+template <int I, int J, int K>
+__device__ __forceinline__ dl dd2_pe(const dl3 X[4]) {
+  const dl3 e = dsub(X[K], X[J]);
+  const dl3 c = dcross(dsub(X[I], X[J]), e);
+  return ddot(c, c) / ddot(e, e);
+}
+__device__ __forceinline__ dl dd2_plane(dl3 p, dl3 o, dl3 n) {
+  const dl h = ddot(dsub(p, o), n);
+  return h * h / ddot(n, n);
+}
+// squared distance of the case as a dual
+__device__ __forceinline__ dl dd2_case(int ty, const dl3 X[4]) {
+  switch (ty) {
+    case PT_PP0: return dd2_pp<0, 1>(X);
+    case PT_PP1: return dd2_pp<0, 2>(X);
+    case PT_PP2: return dd2_pp<0, 3>(X);
+    case PT_PE01: return dd2_pe<0, 1, 2>(X);
+    case PT_PE12: return dd2_pe<0, 2, 3>(X);
+    case PT_PE02: return dd2_pe<0, 1, 3>(X);
+    case PT_FACE: return dd2_plane(X[0], X[1], dcross(dsub(X[2], X[1]), dsub(X[3], X[1])));
+    case EE_BASE + 0: return dd2_pp<0, 2>(X);
+    case EE_BASE + 1: return dd2_pp<0, 3>(X);
+    case EE_BASE + 2: return dd2_pe<0, 2, 3>(X);
+    case EE_BASE + 3: return dd2_pp<1, 2>(X);
+    case EE_BASE + 4: return dd2_pp<1, 3>(X);
+    case EE_BASE + 5: return dd2_pe<1, 2, 3>(X);
+    case EE_BASE + 6: return dd2_pp<2, 0>(X);
+    case EE_BASE + 7: return dd2_pp<2, 1>(X);
+    case EE_BASE + 8: return dd2_pe<2, 0, 1>(X);
+    case EE_BASE + 9: return dd2_pp<3, 0>(X);
+    case EE_BASE + 10: return dd2_pp<3, 1>(X);
+    case EE_BASE + 11: return dd2_pe<3, 0, 1>(X);
+    default: return dd2_plane(X[2], X[0], dcross(dsub(X[1], X[0]), dsub(X[3], X[2])));
+  }
+}
+template <int I, int J>
+__device__ __forceinline__ void dw_pp(dl w[4]) {
+  w[I] = dc(1.0);
+  w[J] = dc(-1.0);
+}
+template <int I, int J, int K>
+__device__ __forceinline__ void dw_pe(const dl3 X[4], dl w[4]) {
+  const dl3 e = dsub(X[K], X[J]);
+  const dl t = ddot(dsub(X[I], X[J]), e) / ddot(e, e);
+  w[I] = dc(1.0);
+  w[J] = t - dc(1.0);
+  w[K] = dc(0.0) - t;
+}
+__device__ __forceinline__ void dclosest_weights(int ty, const dl3 X[4], dl w[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = dc(0.0);
+  switch (ty) {
+    case PT_PP0: dw_pp<0, 1>(w); break;
+    case PT_PP1: dw_pp<0, 2>(w); break;
+    case PT_PP2: dw_pp<0, 3>(w); break;
+    case PT_PE01: dw_pe<0, 1, 2>(X, w); break;
+    case PT_PE12: dw_pe<0, 2, 3>(X, w); break;
+    case PT_PE02: dw_pe<0, 1, 3>(X, w); break;
+    case PT_FACE: {
+      const dl3 e1 = dsub(X[2], X[1]), e2 = dsub(X[3], X[1]), dp = dsub(X[0], X[1]);
+      const dl3 n = dcross(e1, e2);
+      const dl nn = ddot(n, n);
+      const dl u = ddot(dcross(dp, e2), n) / nn, v = ddot(dcross(e1, dp), n) / nn;
+      w[0] = dc(1.0);
+      w[1] = u + v - dc(1.0);
+      w[2] = dc(0.0) - u;
+      w[3] = dc(0.0) - v;
+      break;
+    }
+    case EE_BASE + 0: dw_pp<0, 2>(w); break;
+    case EE_BASE + 1: dw_pp<0, 3>(w); break;
+    case EE_BASE + 2: dw_pe<0, 2, 3>(X, w); break;
+    case EE_BASE + 3: dw_pp<1, 2>(w); break;
+    case EE_BASE + 4: dw_pp<1, 3>(w); break;
+    case EE_BASE + 5: dw_pe<1, 2, 3>(X, w); break;
+    case EE_BASE + 6: dw_pp<2, 0>(w); break;
+    case EE_BASE + 7: dw_pp<2, 1>(w); break;
+    case EE_BASE + 8: dw_pe<2, 0, 1>(X, w); break;
+    case EE_BASE + 9: dw_pp<3, 0>(w); break;
+    case EE_BASE + 10: dw_pp<3, 1>(w); break;
+    case EE_BASE + 11: dw_pe<3, 0, 1>(X, w); break;
+    default: {
+      const dl3 u = dsub(X[1], X[0]), v = dsub(X[3], X[2]), r0 = dsub(X[2], X[0]);
+      const dl3 n = dcross(u, v);
+      const dl nn = ddot(n, n);
+      const dl s = ddot(dcross(r0, v), n) / nn, t = ddot(dcross(r0, u), n) / nn;
+      w[0] = dc(1.0) - s;
+      w[1] = s;
+      w[2] = t - dc(1.0);
+      w[3] = dc(0.0) - t;
+      break;
+    }
+  }
+}
+
+// one lane per lagged pair: g_out = grad over the pair's 12 step-start
+// coordinates of phi = (J l) . g(x; lambda, T, w), through the lag only
+// (the sliding displacement x - x^t is held), for the pair assembly
+__global__ void __launch_bounds__(64) k_friction_lag_vjp(int64_t n, int64_t n_pt, const int32_t *pt,
+                                                         const int32_t *ee, const int32_t *tris, const int32_t *edges,
+                                                         const int32_t *vert_body, const double *x, const double *xt,
+                                                         const double *xbar, const double *lam, const double *l,
+                                                         double mu, double eps, double dhat, double kappa,
+                                                         double *g_out, double *H_out, PairInfo *info) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int is_ee, vid[4];
+  load_vids(i, n_pt, pt, ee, tris, edges, is_ee, vid);
+  PairInfo pi;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) pi.vid[k] = vid[k];
+  pi.body[0] = vert_body[vid[0]];
+  pi.body[1] = vert_body[vid[3]];
+  pi.is_ee = is_ee;
+  pi.pad = 0;
+  info[i] = pi;
+  for (int j = 0; j < 78; ++j) H_out[78 * i + j] = 0.0;
+  d3 X0[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) X0[k] = ld3(xt, vid[k]);
+  int ty;
+  {
+#pragma clang fp contract(off)
+    ty = classify_pair(is_ee, X0);
+  }
+  // data of the pass: displacements and J l at the 4 vertices
+  double dx[4][3], vk[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double *lb = l + 12 * (int64_t)vert_body[vid[k]];
+    const double *xb = xbar + 3 * (int64_t)vid[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dx[k][c] = x[3 * (int64_t)vid[k] + c] - xt[3 * (int64_t)vid[k] + c];
+      vk[k][c] = lb[c] + lb[3 + 3 * c] * xb[0] + lb[4 + 3 * c] * xb[1] + lb[5 + 3 * c] * xb[2];
+    }
+  }
+  double ep = 0.0;
+  if (is_ee) {
+    const d3 uu = xsub(ld3(xbar, vid[1]), ld3(xbar, vid[0])), vv = xsub(ld3(xbar, vid[3]), ld3(xbar, vid[2]));
+    ep = (1e-3 * xdot(uu, uu)) * xdot(vv, vv);
+  }
+  const bool on = lam[i] > 0.0;
+  for (int s = 0; s < 12; ++s) {
+    double gv = 0.0;
+    if (on) {
+      dl3 X[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        X[k] = {{X0[k].x, s == 3 * k ? 1.0 : 0.0}, {X0[k].y, s == 3 * k + 1 ? 1.0 : 0.0},
+                {X0[k].z, s == 3 * k + 2 ? 1.0 : 0.0}};
+      const dl d = dsqrt(dd2_case(ty, X));
+      const dl dm = d - dc(dhat);
+      const dl Bp = dc(0.0) - dc(2.0) * dm * dlog(d / dc(dhat)) - dm * dm / d;
+      dl m = dc(1.0);
+      if (is_ee) {
+        const dl3 nn = dcross(dsub(X[1], X[0]), dsub(X[3], X[2]));
+        const dl c = ddot(nn, nn);
+        if (c.v < ep) {
+          const dl r = c / dc(ep);
+          m = (dc(2.0) - r) * r;
+        }
+      }
+      const dl L = dc(-kappa) * m * Bp;
+      dl w[4];
+      dclosest_weights(ty, X, w);
+      dl3 r = {dc(0.0), dc(0.0), dc(0.0)};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r = {r.x + w[k] * X[k].x, r.y + w[k] * X[k].y, r.z + w[k] * X[k].z};
+      const dl inv = dc(1.0) / dsqrt(ddot(r, r));
+      const dl3 nv = dscale(r, inv);
+      const double ax = fabs(nv.x.v), ay = fabs(nv.y.v), az = fabs(nv.z.v);
+      dl3 t1;
+      if (ay < ax && ay <= az)
+        t1 = {dc(0.0) - nv.z, dc(0.0), nv.x};
+      else if (az < ax && az < ay)
+        t1 = {nv.y, dc(0.0) - nv.x, dc(0.0)};
+      else
+        t1 = {dc(0.0), nv.z, dc(0.0) - nv.y};
+      t1 = dscale(t1, dc(1.0) / dsqrt(ddot(t1, t1)));
+      const dl3 t2 = dcross(nv, t1);
+      dl3 delta = {dc(0.0), dc(0.0), dc(0.0)}, nu = {dc(0.0), dc(0.0), dc(0.0)};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        delta = {delta.x + w[k] * dc(dx[k][0]), delta.y + w[k] * dc(dx[k][1]), delta.z + w[k] * dc(dx[k][2])};
+        nu = {nu.x + w[k] * dc(vk[k][0]), nu.y + w[k] * dc(vk[k][1]), nu.z + w[k] * dc(vk[k][2])};
+      }
+      const dl u0 = ddot(t1, delta), u1 = ddot(t2, delta);
+      const dl yy = u0 * u0 + u1 * u1;
+      dl gs;
+      if (yy.v == 0.0) {
+        gs = dc(2.0 / eps);
+      } else {
+        const dl y = dsqrt(yy);
+        gs = y.v < eps ? dc(2.0 / eps) - y / dc(eps * eps) : dc(1.0) / y;
+      }
+      const dl coef = dc(mu) * L * gs;
+      const dl3 f = {coef * (t1.x * u0 + t2.x * u1), coef * (t1.y * u0 + t2.y * u1), coef * (t1.z * u0 + t2.z * u1)};
+      gv = ddot(nu, f).d;
+    }
+    g_out[12 * i + s] = gv;
+  }
+}
+
 // compaction of the lagged pairs with lambda > 0
 __global__ void k_lam_flags(int64_t n, const double *lam, int64_t *flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -329,6 +565,22 @@ int op_friction_hvp(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, co
   hipLaunchKernelGGL((k_friction_local<false, true>), dim3(grid_for(n, 128)), dim3(128), 0, s, n, fr->n_pt, fr->pt,
                      fr->ee, sc->tris, sc->edges, sc->vert_body, x, fr->xt, fr->lam, fr->T, fr->w, fr->mu, fr->eps,
                      e_loc, g_loc, H_loc, info, sc->body_scene, nullptr, v, sc->xbar);
+  HIP_TRY(ctx, hipGetLastError());
+  return op_assemble(ctx, sc, n, info, g_loc, H_loc, nullptr, 0, out, nullptr, nullptr, s);
+}
+
+int op_friction_lag_vjp(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const FrictionSet *fr,
+                        const double *x, const double *l, double *out, hipStream_t s) {
+  const int64_t n = fr->n();
+  if (n == 0) return ABD_OK;
+  double *g_loc, *H_loc;
+  PairInfo *info;
+  ABD_TRY(ws(ctx, "fv_g", 12 * n, &g_loc, s));
+  ABD_TRY(ws(ctx, "fv_H", 78 * n, &H_loc, s));
+  ABD_TRY(ws(ctx, "fv_info", n, &info, s));
+  hipLaunchKernelGGL(k_friction_lag_vjp, dim3(grid_for(n, 64)), dim3(64), 0, s, n, fr->n_pt, fr->pt, fr->ee, sc->tris,
+                     sc->edges, sc->vert_body, x, fr->xt, sc->xbar, fr->lam, l, fr->mu, fr->eps, prm->dhat,
+                     prm->kappa_b, g_loc, H_loc, info);
   HIP_TRY(ctx, hipGetLastError());
   return op_assemble(ctx, sc, n, info, g_loc, H_loc, nullptr, 0, out, nullptr, nullptr, s);
 }

@@ -148,6 +148,10 @@ int op_friction_energy(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr,
 // into out [nb][12]
 int op_friction_hvp(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x, const double *v,
                     double *out, hipStream_t s);
+// adjoint's lag term: J^T grad_{x^t} [(J l) . g(x; lambda, T, w)] through the
+// lagged quantities of fr, accumulated into out [nb][12]
+int op_friction_lag_vjp(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const FrictionSet *fr,
+                        const double *x, const double *l, double *out, hipStream_t s);
 // reads and clears the device error flags of the last operations (syncs)
 int op_read_err(abd_ctx *ctx, hipStream_t s);
 // the friction state of the current time step (null when none is set)

@@ -842,11 +842,21 @@ def test_adjoint_rollout_gradient_frictionless_by_fd():
         assert ad == pytest.approx(fd, rel=1e-4)
 
 
-def test_adjoint_rollout_gradient_friction_lag_held_by_fd():
-    # with friction: the adjoint holds each step's lagged normal force,
-    # tangent basis and weights as data; differences of the rollout with the
-    # same lagged data (x^t still moving with q^t) agree with it
+def test_adjoint_rollout_gradient_friction_by_fd():
+    # with lagged friction: the adjoint differentiates the lag too (normal
+    # force, tangent basis and weights as functions of q^t); central
+    # differences of the full rollout (every step re-lagged) agree with it
     S, P = sg.cube_on_slope(math.atan(0.75), 0.5, v0=1.0)
     P = dict(P, newton_tol=1e-9)
-    for fd, ad in _loss_and_fd(S, P, 15, True, 1):
+    for fd, ad in _loss_and_fd(S, P, 15, False, 1):
         assert ad == pytest.approx(fd, rel=1e-5)
+
+
+def test_adjoint_without_lag_derivative_would_fail_fd():
+    # the lag's own derivative matters: dropping it (differences of the
+    # rollout with every step's lagged data held) gives a different answer,
+    # so the test above checks that term
+    S, P = sg.cube_on_slope(math.atan(0.75), 0.5, v0=1.0)
+    P = dict(P, newton_tol=1e-9)
+    worst = max(abs(fd - ad) / abs(fd) for fd, ad in _loss_and_fd(S, P, 15, True, 1))
+    assert worst > 1e-2

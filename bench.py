@@ -23,6 +23,7 @@ spaced scenes over the same steps, scaled by body count, and the speedup.
 
     python bench.py [--steps K] [--warmup W] [--pre N]
     python bench.py --workload batched --steps 40 [--loop-scenes 16]
+    python bench.py --workload adjoint --steps 100 [--checkpoint-every 10]
 """
 import argparse
 import json
@@ -62,9 +63,12 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size (for counter calibration) before timing")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", choices=("box", "batched"), default="box",
+    ap.add_argument("--workload", choices=("box", "batched", "adjoint"), default="box",
                     help="box: the 1000-icosphere box drop (default); batched: 256 independent drop scenes in one "
-                         "launch sequence, against a per-scene loop of the same library")
+                         "launch sequence, against a per-scene loop of the same library; adjoint: gradient of a "
+                         "position loss after --steps steps of the 500-icosphere drop w.r.t. the initial velocities")
+    ap.add_argument("--adj-rtol", type=float, default=1e-8, help="adjoint: PCG relative residual of the adjoint solves")
+    ap.add_argument("--checkpoint-every", type=int, default=10)
     ap.add_argument("--loop-scenes", type=int, default=16,
                     help="batched: scenes (evenly spaced) run one at a time for the per-scene baseline")
     ap.add_argument("--start-at", type=float, default=0.0,
@@ -306,6 +310,50 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def run_adjoint(args):
+    """Forward rollout of the 500-icosphere drop (friction 0.5) for --steps
+    steps, loss |p_1(T) - target|^2, and its gradient with respect to every
+    body's initial velocity by the checkpointed adjoint."""
+    import torch
+
+    import paper_2201_10022_amd as abd
+
+    S, P, target = sg.adjoint_drop()
+    n = args.steps
+    ctx, sc = abd.setup(S, 0)
+    q0 = torch.as_tensor(S["q0"], device="cuda:0")
+    qd0 = torch.as_tensor(S["qd0"], device="cuda:0")
+    q, qd = q0.clone(), qd0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    newton = 0
+    for _ in range(n):
+        newton += ctx.time_step(sc, P, q, qd)["newton_iters"]
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    b1 = int(np.flatnonzero(S["body_fixed"] == 0)[0])
+    tq = torch.as_tensor(target, device="cuda:0")
+    loss = float(((q[b1, :3] - tq) ** 2).sum())
+    gT = torch.zeros_like(q)
+    gT[b1, :3] = 2.0 * (q[b1, :3] - tq)
+    t0 = time.perf_counter()
+    gq, gqd = ctx.rollout_backward(sc, P, q0, qd0, n, args.checkpoint_every, gT, torch.zeros_like(q), args.adj_rtol)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    line = {"metric": "adjoint rollout: time steps differentiated per second (forward re-runs included)",
+            "value": n / t_bwd, "unit": "steps/s", "n_gpus": 1, "steps": n, "warmup": 0,
+            "ms_per_step": 1e3 * t_bwd / max(n, 1), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded scene generator)",
+            "config": {"workload": "adjoint drop: 500 icospheres (5 layers) in the fixed box, lagged friction "
+                                   f"mu {P['mu']}, loss |p_1(T) - target|^2, gradient w.r.t. all initial "
+                                   "velocities", "bodies": int(len(S["q0"])),
+                       "checkpoint_every": args.checkpoint_every, "adjoint_pcg_rtol": args.adj_rtol},
+            "forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
+            "forward_newton_iters": newton, "loss": loss,
+            "grad_qdot0_norm": float(gqd.norm()), "grad_q0_norm": float(gq.norm())}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -314,6 +362,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         run_batched(args)
+    elif args.workload == "adjoint":
+        run_adjoint(args)
     else:
         run_box(args)
 

@@ -120,11 +120,21 @@ int op_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, co
   ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 0, nullptr, nullptr, s, fr));
   ABD_TRY(op_read_err(ctx, s));
 
-  // H l = qbar^{t+1} + qdbar^{t+1} / dt
+  // preconditioner: diagonal blocks of the projected (PSD) Hessian
+  double *pre;
+  ABD_TRY(ws(ctx, "adj_pre", 144 * (size_t)nb, &pre, s));
+  ABD_TRY(zero_d(ctx, pre, 144 * (int64_t)nb, s));
+  ABD_TRY(op_body_terms(ctx, sc, prm, q_next, qt, nullptr, nullptr, pre, 1, s));
+  ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, nullptr, nullptr, pre, nullptr, 1, nullptr, nullptr,
+                     s, fr));
+  ABD_TRY(op_read_err(ctx, s));
+
+  // H l = qbar^{t+1} + qdbar^{t+1} / dt; H may be indefinite (the barrier's
+  // curvature is not), so MINRES
   hipLaunchKernelGGL(k_adj_rhs, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_fixed, qbar_next, qdbar_next,
                      1.0 / prm->dt, a);
   int its = 0;
-  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, a, l, rtol, max_iter, &its, s));
+  ABD_TRY(op_minres(ctx, sc, diag, off, keys, nk, pre, a, l, rtol, max_iter, &its, s));
   ABD_TRY(op_read_err(ctx, s));
   if (iters) *iters = its;
   ABD_TRY(zero_d(ctx, hdl, n12, s));

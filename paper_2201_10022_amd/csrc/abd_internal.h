@@ -168,6 +168,12 @@ int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, con
                    double *energy, hipStream_t s);
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *p, double rtol, int max_iter, int *iters, hipStream_t s);
+// preconditioned MINRES on the (possibly indefinite) symmetric block matrix,
+// block-Jacobi preconditioner from the SPD diagonal blocks pre_diag; stops
+// at |r|_{P} <= rtol |b|_{P} (syncs every iteration)
+int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
+              int64_t n_keys, const double *pre_diag, const double *rhs, double *x_out, double rtol, int max_iter,
+              int *iters, hipStream_t s);
 int op_max_abs_disp(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s);
 // per-scene variants (out [n_scenes]; energies accumulated, maxima written)
 int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s);

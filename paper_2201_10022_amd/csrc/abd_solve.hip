@@ -564,6 +564,220 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   return ABD_OK;
 }
 
+// --------------------------------------------------------------- MINRES ----
+// Preconditioned MINRES (Paige and Saunders; the formulation of Elman,
+// Silvester and Wathen) for symmetric systems that may be indefinite, such
+// as the unprojected Hessian of the adjoint: one SpMV and one block-Jacobi
+// application per iteration, the short scalar recurrence on the host.  The
+// preconditioner must be symmetric positive definite (its diagonal blocks
+// are given separately).
+namespace {
+
+__global__ void __launch_bounds__(SWB) k_bsr_spmv(int nb, const uint8_t *fixed, const double *diag, const double *off,
+                                                 const int32_t *keys, const uint32_t *tperm, const int64_t *lo_beg,
+                                                 const int64_t *hi_beg, const double *xv, double sx, double *y) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * SWBB + (threadIdx.x >> 6);
+  if (b >= nb) return;
+  const int slot = lane / 12, i = lane % 12;
+  double acc = 0.0;
+  const int64_t l0 = lo_beg[b], nlo = lo_beg[b + 1] - l0;
+  const int64_t h0 = hi_beg[b], nhi = hi_beg[b + 1] - h0;
+  const int64_t E = 1 + nlo + nhi;
+  for (int64_t e0 = 0; e0 < E; e0 += 5) {
+    const int64_t e = e0 + slot;
+    if (lane < 60 && e < E) {
+      const double *row;
+      int64_t c;
+      int stride;
+      if (e == 0) {
+        row = diag + 144 * (int64_t)b + 12 * i;
+        c = b;
+        stride = 1;
+      } else if (e <= nlo) {
+        const int64_t kk = l0 + e - 1;
+        row = off + 144 * kk + 12 * i;
+        c = keys[2 * kk + 1];
+        stride = 1;
+      } else {
+        const int64_t kk = tperm[h0 + e - 1 - nlo];
+        row = off + 144 * kk + i;
+        c = keys[2 * kk];
+        stride = 12;
+      }
+      const double *xc = xv + 12 * c;
+#pragma unroll
+      for (int j = 0; j < 12; ++j) acc += row[stride * j] * xc[j];
+    }
+  }
+  double v = acc;
+#pragma unroll
+  for (int q = 1; q < 5; ++q) v += __shfl(acc, (lane + 12 * q) & 63, 64);
+  if (slot == 0) y[12 * (int64_t)b + i] = fixed[b] ? 0.0 : sx * v;
+}
+
+__global__ void k_block_apply(int nb, const double *inv, const double *v, double *z) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 12 * nb) return;
+  const int b = t / 12, i = t % 12;
+  const double *M = inv + 144 * (int64_t)b + 12 * i;
+  const double *vb = v + 12 * (int64_t)b;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) s += M[j] * vb[j];
+  z[t] = s;
+}
+
+__global__ void k_vmul(int n, const double *a, const double *b, double *o) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] * b[i];
+}
+
+// v_next = Az - a v - b v_prev
+__global__ void k_minres_v(int n, const double *Az, const double *v, const double *vp, double a, double b,
+                           double *vn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) vn[i] = Az[i] - a * v[i] - b * vp[i];
+}
+
+// w_next = (zs z - a3 w_prev - a2 w) / a1 (written over w_prev); x += cx w_next
+__global__ void k_minres_wx(int n, const double *z, double zs, double *wp, const double *w, double a3, double a2,
+                            double a1, double cx, double *x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double wn = (zs * z[i] - a3 * wp[i] - a2 * w[i]) / a1;
+  wp[i] = wn;
+  x[i] += cx * wn;
+}
+
+__global__ void k_vzero(int n, double *a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
+}  // namespace
+
+int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
+              int64_t n_keys, const double *pre_diag, const double *rhs, double *x_out, double rtol, int max_iter,
+              int *iters, hipStream_t s) {
+  const int nb = sc->n_bodies, n12 = 12 * nb;
+  *iters = 0;
+  if (nb <= 0) return ABD_OK;
+  double *inv, *v0, *v1, *v2, *z, *Az, *w0, *w1, *tmp, *dot;
+  int64_t *lo_beg, *hi_beg;
+  uint64_t *tk, *tk2;
+  uint32_t *tv, *tv2;
+  int *err;
+  ABD_TRY(ws(ctx, "mr_inv", 144 * (size_t)nb, &inv, s));
+  ABD_TRY(ws(ctx, "mr_v0", n12, &v0, s));
+  ABD_TRY(ws(ctx, "mr_v1", n12, &v1, s));
+  ABD_TRY(ws(ctx, "mr_v2", n12, &v2, s));
+  ABD_TRY(ws(ctx, "mr_z", n12, &z, s));
+  ABD_TRY(ws(ctx, "mr_Az", n12, &Az, s));
+  ABD_TRY(ws(ctx, "mr_w0", n12, &w0, s));
+  ABD_TRY(ws(ctx, "mr_w1", n12, &w1, s));
+  ABD_TRY(ws(ctx, "mr_tmp", n12, &tmp, s));
+  ABD_TRY(ws(ctx, "mr_dot", 2, &dot, s));
+  ABD_TRY(ws(ctx, "mr_lob", nb + 1, &lo_beg, s));
+  ABD_TRY(ws(ctx, "mr_hib", nb + 1, &hi_beg, s));
+  ABD_TRY(ws(ctx, "mr_tk", n_keys + 1, &tk, s));
+  ABD_TRY(ws(ctx, "mr_tk2", n_keys + 1, &tk2, s));
+  ABD_TRY(ws(ctx, "mr_tv", n_keys + 1, &tv, s));
+  ABD_TRY(ws(ctx, "mr_tv2", n_keys + 1, &tv2, s));
+  ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
+  hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed, pre_diag, inv, err);
+  if (n_keys > 0) {
+    hipLaunchKernelGGL(k_tkeys, dim3(grid_for(n_keys, 256)), dim3(256), 0, s, n_keys, keys, tk, tv);
+    size_t tmp_bytes = 0;
+    HIP_TRY(ctx, rocprim::radix_sort_pairs(nullptr, tmp_bytes, tk, tk2, tv, tv2, (size_t)n_keys, 0, 64, s));
+    void *stmp;
+    ABD_TRY(ws_get(ctx, "mr_sort_tmp", tmp_bytes + 16, &stmp, s));
+    HIP_TRY(ctx, rocprim::radix_sort_pairs(stmp, tmp_bytes, tk, tk2, tv, tv2, (size_t)n_keys, 0, 64, s));
+  }
+  hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(nb + 1, 256)), dim3(256), 0, s, nb, n_keys, keys, tk2, lo_beg,
+                     hi_beg);
+  const unsigned gv = grid_for(n12, 256), gs = grid_for(nb, SWBB);
+  double *h;
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
+  auto dotp = [&](const double *a, const double *b, double *out) -> int {
+    hipLaunchKernelGGL(k_vmul, dim3(gv), dim3(256), 0, s, n12, a, b, tmp);
+    HIP_TRY(ctx, hipMemsetAsync(dot, 0, sizeof(double), s));
+    ABD_TRY(reduce_sum_f64(ctx, tmp, n12, dot, s));
+    HIP_TRY(ctx, hipMemcpyAsync(h, dot, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    *out = h[0];
+    return ABD_OK;
+  };
+  // x = 0, v_prev = 0, v = rhs on free bodies, z = P v
+  hipLaunchKernelGGL(k_vzero, dim3(gv), dim3(256), 0, s, n12, x_out);
+  hipLaunchKernelGGL(k_vzero, dim3(gv), dim3(256), 0, s, n12, v0);
+  hipLaunchKernelGGL(k_vzero, dim3(gv), dim3(256), 0, s, n12, w0);
+  hipLaunchKernelGGL(k_vzero, dim3(gv), dim3(256), 0, s, n12, w1);
+  hipLaunchKernelGGL(k_block_apply, dim3(gv), dim3(256), 0, s, nb, inv, rhs, z);  // P is zero on fixed bodies
+  HIP_TRY(ctx, hipMemcpyAsync(v1, rhs, sizeof(double) * n12, hipMemcpyDeviceToDevice, s));
+  ABD_TRY(op_read_err(ctx, s));
+  double g2;
+  ABD_TRY(dotp(z, v1, &g2));
+  if (!(g2 >= 0.0)) return abd_fail(ctx, ABD_E_PCG, "MINRES: preconditioner not positive definite");
+  double gam = std::sqrt(g2), gam_prev = 1.0;
+  const double g1 = gam;
+  if (g1 == 0.0) return ABD_OK;
+  double eta = gam, c_prev = 1.0, c = 1.0, s_prev = 0.0, sn = 0.0;
+  double *vp = v0, *vc = v1, *vn = v2, *wp = w0, *wc = w1;
+  int j = 0;
+  for (; j < max_iter; ++j) {
+    // A (z / gamma), delta = (A z/gamma) . z/gamma
+    hipLaunchKernelGGL(k_bsr_spmv, dim3(gs), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2, lo_beg, hi_beg,
+                       z, 1.0 / gam, Az);
+    double dz;
+    ABD_TRY(dotp(Az, z, &dz));
+    const double delta = dz / gam;
+    hipLaunchKernelGGL(k_minres_v, dim3(gv), dim3(256), 0, s, n12, Az, vc, vp, delta / gam, gam / gam_prev, vn);
+    // z_next = P v_next (z of this iteration is still needed below: keep it in tmp)
+    HIP_TRY(ctx, hipMemcpyAsync(tmp, z, sizeof(double) * n12, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_block_apply, dim3(gv), dim3(256), 0, s, nb, inv, vn, z);
+    double gn2;
+    {
+      // gamma_next^2 = z_next . v_next (uses Az as scratch)
+      hipLaunchKernelGGL(k_vmul, dim3(gv), dim3(256), 0, s, n12, z, vn, Az);
+      HIP_TRY(ctx, hipMemsetAsync(dot, 0, sizeof(double), s));
+      ABD_TRY(reduce_sum_f64(ctx, Az, n12, dot, s));
+      HIP_TRY(ctx, hipMemcpyAsync(h, dot, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      gn2 = h[0];
+    }
+    if (!(gn2 >= 0.0)) return abd_fail(ctx, ABD_E_PCG, "MINRES: preconditioner not positive definite");
+    const double gn = std::sqrt(gn2);
+    const double a0 = c * delta - c_prev * sn * gam;
+    const double a1 = std::sqrt(a0 * a0 + gn * gn);
+    const double a2 = sn * delta + c_prev * c * gam;
+    const double a3 = s_prev * gam;
+    if (!(a1 > 0.0)) return abd_fail(ctx, ABD_E_PCG, "MINRES breakdown (singular system)");
+    const double c_n = a0 / a1, s_n = gn / a1;
+    hipLaunchKernelGGL(k_minres_wx, dim3(gv), dim3(256), 0, s, n12, tmp, 1.0 / gam, wp, wc, a3, a2, a1, c_n * eta,
+                       x_out);
+    std::swap(wp, wc);  // w_prev <- w, w <- w_next
+    eta = -s_n * eta;
+    // rotate
+    double *t = vp;
+    vp = vc;
+    vc = vn;
+    vn = t;
+    gam_prev = gam;
+    gam = gn;
+    c_prev = c;
+    c = c_n;
+    s_prev = sn;
+    sn = s_n;
+    if (std::fabs(eta) <= rtol * g1 || gn == 0.0) {
+      ++j;
+      break;
+    }
+  }
+  *iters = j;
+  return abd_hip_check(ctx, hipGetLastError(), "minres");
+}
+
 extern "C" int abd_pcg_solve(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off,
                              const int32_t *keys, int64_t n_keys, const double *rhs, double *p, double rtol,
                              int32_t max_iter, int32_t *iters, hipStream_t stream) {

@@ -144,6 +144,20 @@ int abd_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const do
                    int32_t *pt, int64_t cap_pt, int64_t *n_pt, int32_t *ee, int64_t cap_ee, int64_t *n_ee,
                    hipStream_t stream);
 
+/* Candidates at x (x1 = NULL, same inflate) taken from the swept
+ * candidates (spt, see) of a segment x0 -> x1 that contains x (x a convex
+ * combination of x0 and x1 vertex by vertex, as every Newton iterate on
+ * the search line is): each static box lies in the swept box, so the
+ * result is the swept list filtered by the same box test, in the same
+ * canonical order, equal to abd_candidates at x.  (A vertex of x computed
+ * from an intermediate q may round outside the swept box by an ulp; a pair
+ * whose static boxes touch only within that rounding can then be missing:
+ * its primitives are dhat apart up to rounding, so its barrier is zero.)
+ * Syncs; counts and ABD_E_CAPACITY as abd_candidates. */
+int abd_candidates_within(abd_ctx *ctx, const abd_scene *sc, const double *x, double inflate, const int32_t *spt,
+                          int64_t n_spt, const int32_t *see, int64_t n_see, int32_t *pt, int64_t cap_pt,
+                          int64_t *n_pt, int32_t *ee, int64_t cap_ee, int64_t *n_ee, hipStream_t stream);
+
 /* Off-diagonal block pattern of the global Hessian (sec. 4.3): sorted unique
  * body pairs (a < b, both free) touched by the given pairs.  keys:
  * [cap][2].  Syncs; *n_keys (host) receives the count. */

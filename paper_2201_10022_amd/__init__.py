@@ -142,6 +142,16 @@ class Context:
             self._check(rc)
             return pt[:npt.value], ee[:nee.value]
 
+    def candidates_within(self, scene, x, spt, see, inflate=1e-3):
+        cap_pt, cap_ee = max(spt.shape[0], 1), max(see.shape[0], 1)
+        pt = torch.empty((cap_pt, 2), dtype=torch.int32, device=x.device)
+        ee = torch.empty((cap_ee, 2), dtype=torch.int32, device=x.device)
+        npt, nee = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self.L.abd_candidates_within(self.h, ctypes.byref(scene.c), _ptr(x), float(inflate), _ptr(spt),
+                                                 spt.shape[0], _ptr(see), see.shape[0], _ptr(pt), cap_pt,
+                                                 ctypes.byref(npt), _ptr(ee), cap_ee, ctypes.byref(nee), _stream()))
+        return pt[:npt.value], ee[:nee.value]
+
     def offdiag_pattern(self, scene, pt, ee):
         cap = pt.shape[0] + ee.shape[0] + 1
         keys = torch.empty((cap, 2), dtype=torch.int32, device=pt.device)

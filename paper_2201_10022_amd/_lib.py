@@ -11,6 +11,7 @@ ERRORS = {-1: "ABD_E_INVALID", -2: "ABD_E_CAPACITY", -3: "ABD_E_INTERSECT", -4: 
           -5: "ABD_E_LINESEARCH", -6: "ABD_E_PCG", -7: "ABD_E_HIP"}
 
 EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_body_mass", "abd_vertex_map", "abd_candidates",
+           "abd_candidates_within",
            "abd_offdiag_pattern", "abd_classify", "abd_barrier_grad_hess", "abd_barrier_energy",
            "abd_ccd_max_step", "abd_orthogonality", "abd_inertia", "abd_q_tilde", "abd_pcg_solve",
            "abd_newton_step", "abd_time_step", "abd_friction_lag", "abd_friction_grad_hess",
@@ -62,6 +63,8 @@ SIGNATURES = {
     "abd_body_mass": ([_vp, _PS, _vp, _vp, _vp, _vp], ctypes.c_int),
     "abd_vertex_map": ([_vp, _PS, _vp, _vp, _vp], ctypes.c_int),
     "abd_candidates": ([_vp, _PS, _vp, _vp, _dbl, _vp, _i64, _pi64, _vp, _i64, _pi64, _vp], ctypes.c_int),
+    "abd_candidates_within": ([_vp, _PS, _vp, _dbl, _vp, _i64, _vp, _i64, _vp, _i64, _pi64, _vp, _i64, _pi64, _vp],
+                              ctypes.c_int),
     "abd_offdiag_pattern": ([_vp, _PS, _vp, _i64, _vp, _i64, _vp, _i64, _pi64, _vp], ctypes.c_int),
     "abd_classify": ([_vp, _PS, _vp, _dbl, _vp, _i64, ctypes.c_int, _vp, _vp, _vp, _vp], ctypes.c_int),
     "abd_barrier_grad_hess": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp,

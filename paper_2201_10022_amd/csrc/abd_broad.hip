@@ -441,6 +441,99 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   return abd_hip_check(ctx, hipGetLastError(), "offdiag");
 }
 
+// ------------------------------------------------ static subset of a sweep ----
+// The candidates at positions x inside a swept segment x0 -> x1 are a subset
+// of that segment's swept candidates (every static box lies inside the
+// swept box), so they are the swept list filtered by the static predicate:
+// the same vertex boxes [x, x + inflate] and the same box test.  Filtering
+// keeps the canonical order, so the result equals a full broad phase.
+namespace {
+template <int K>
+__device__ __forceinline__ void static_box(const int32_t *vid, const double *x, double inflate, double b[6]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double a = x[3 * (int64_t)vid[0] + i];
+    b[i] = fmin(a, a);
+    b[3 + i] = fmax(a, a) + inflate;
+  }
+#pragma unroll
+  for (int k = 1; k < K; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double a = x[3 * (int64_t)vid[k] + i];
+      b[i] = fmin(b[i], a);
+      b[3 + i] = fmax(b[3 + i], a + inflate);
+    }
+}
+
+__global__ void k_static_flags(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee, const int32_t *tris,
+                               const int32_t *edges, const double *x, double inflate, int64_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a[6], b[6];
+  if (i < n_pt) {
+    const int32_t v = pt[2 * i];
+    static_box<1>(&v, x, inflate, a);
+    static_box<3>(tris + 3 * (int64_t)pt[2 * i + 1], x, inflate, b);
+  } else {
+    const int64_t j = i - n_pt;
+    static_box<2>(edges + 2 * (int64_t)ee[2 * j], x, inflate, a);
+    static_box<2>(edges + 2 * (int64_t)ee[2 * j + 1], x, inflate, b);
+  }
+  flag[i] = box_overlap(a, b) ? 1 : 0;
+}
+
+__global__ void k_static_compact(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee, const int64_t *flag,
+                                 const int64_t *pos, const int64_t *n_keep_pt, int32_t *opt, int32_t *oee) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  const int64_t j = pos[i];
+  if (i < n_pt) {
+    opt[2 * j] = pt[2 * i];
+    opt[2 * j + 1] = pt[2 * i + 1];
+  } else {
+    const int64_t je = j - *n_keep_pt;
+    oee[2 * je] = ee[2 * (i - n_pt)];
+    oee[2 * je + 1] = ee[2 * (i - n_pt) + 1];
+  }
+}
+}  // namespace
+
+int op_candidates_within(abd_ctx *ctx, const abd_scene *sc, const double *x, double inflate, const int32_t *spt,
+                         int64_t n_spt, const int32_t *see, int64_t n_see, int32_t **pt_out, int64_t *n_pt,
+                         int32_t **ee_out, int64_t *n_ee, const char *tag, hipStream_t s) {
+  const int64_t n = n_spt + n_see;
+  const std::string pn = std::string(tag) + "_pt", en = std::string(tag) + "_ee";
+  *n_pt = *n_ee = 0;
+  int64_t *flag, *pos, *tot;
+  ABD_TRY(ws(ctx, "cw_flag", n + 1, &flag, s));
+  ABD_TRY(ws(ctx, "cw_pos", n + 1, &pos, s));
+  ABD_TRY(ws(ctx, "cw_tot", 2, &tot, s));
+  if (n == 0) {
+    ABD_TRY(ws(ctx, pn.c_str(), 2, pt_out, s));
+    ABD_TRY(ws(ctx, en.c_str(), 2, ee_out, s));
+    return ABD_OK;
+  }
+  hipLaunchKernelGGL(k_static_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, n_spt, n, spt, see, sc->tris, sc->edges,
+                     x, inflate, flag);
+  ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s));
+  int64_t *h;
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
+  HIP_TRY(ctx, hipMemcpyAsync(h, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  if (n_see > 0) HIP_TRY(ctx, hipMemcpyAsync(h + 1, pos + n_spt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  const int64_t keep = h[0], keep_pt = n_see > 0 ? h[1] : h[0];
+  ABD_TRY(ws(ctx, pn.c_str(), 2 * keep_pt + 2, pt_out, s));
+  ABD_TRY(ws(ctx, en.c_str(), 2 * (keep - keep_pt) + 2, ee_out, s));
+  const int64_t *nkp = n_see > 0 ? pos + n_spt : tot;
+  hipLaunchKernelGGL(k_static_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, n_spt, n, spt, see, flag, pos, nkp,
+                     *pt_out, *ee_out);
+  *n_pt = keep_pt;
+  *n_ee = keep - keep_pt;
+  return abd_hip_check(ctx, hipGetLastError(), "candidates within sweep");
+}
+
 // ------------------------------------------------------------------ ABI ----
 extern "C" int abd_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1,
                               double inflate, int32_t *pt, int64_t cap_pt, int64_t *n_pt, int32_t *ee,
@@ -448,6 +541,21 @@ extern "C" int abd_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x
   if (!ctx || !sc || !x0 || !n_pt || !n_ee) return abd_fail(ctx, ABD_E_INVALID, "abd_candidates: null");
   int32_t *ipt, *iee;
   ABD_TRY(op_candidates(ctx, sc, x0, x1, inflate, &ipt, n_pt, &iee, n_ee, "abi_cand", stream));
+  if (*n_pt > cap_pt || *n_ee > cap_ee)
+    return abd_fail(ctx, ABD_E_CAPACITY, "candidates need pt %lld ee %lld", (long long)*n_pt, (long long)*n_ee);
+  if (*n_pt) HIP_TRY(ctx, hipMemcpyAsync(pt, ipt, 2 * sizeof(int32_t) * *n_pt, hipMemcpyDeviceToDevice, stream));
+  if (*n_ee) HIP_TRY(ctx, hipMemcpyAsync(ee, iee, 2 * sizeof(int32_t) * *n_ee, hipMemcpyDeviceToDevice, stream));
+  return ABD_OK;
+}
+
+extern "C" int abd_candidates_within(abd_ctx *ctx, const abd_scene *sc, const double *x, double inflate,
+                                     const int32_t *spt, int64_t n_spt, const int32_t *see, int64_t n_see, int32_t *pt,
+                                     int64_t cap_pt, int64_t *n_pt, int32_t *ee, int64_t cap_ee, int64_t *n_ee,
+                                     hipStream_t stream) {
+  if (!ctx || !sc || !x || !n_pt || !n_ee || (n_spt && !spt) || (n_see && !see))
+    return abd_fail(ctx, ABD_E_INVALID, "abd_candidates_within: null");
+  int32_t *ipt, *iee;
+  ABD_TRY(op_candidates_within(ctx, sc, x, inflate, spt, n_spt, see, n_see, &ipt, n_pt, &iee, n_ee, "abi_cw", stream));
   if (*n_pt > cap_pt || *n_ee > cap_ee)
     return abd_fail(ctx, ABD_E_CAPACITY, "candidates need pt %lld ee %lld", (long long)*n_pt, (long long)*n_ee);
   if (*n_pt) HIP_TRY(ctx, hipMemcpyAsync(pt, ipt, 2 * sizeof(int32_t) * *n_pt, hipMemcpyDeviceToDevice, stream));

@@ -52,6 +52,11 @@ struct abd_ctx {
   // abd_friction_begin_step, used by the Newton iterations while set)
   bool fr_set = false;
   int64_t fr_n_pt = 0, fr_n_ee = 0;
+  // swept candidates of the last accepted Newton step (the segment holds the
+  // new iterate, so its static candidates are a subset of these)
+  bool sw_valid = false;
+  const int32_t *sw_pt = nullptr, *sw_ee = nullptr;
+  int64_t sw_n_pt = 0, sw_n_ee = 0;
 };
 
 // instrumentation: prof_begin returns an event recorded before the launch
@@ -121,6 +126,11 @@ int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x,
 int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1, double inflate,
                   int32_t **pt, int64_t *n_pt, int32_t **ee, int64_t *n_ee, const char *tag, hipStream_t s,
                   const uint8_t *skip_scene = nullptr);
+// candidates at x (static, inflate) taken from the swept candidates
+// (spt, see) of a segment that contains x: equal to op_candidates at x
+int op_candidates_within(abd_ctx *ctx, const abd_scene *sc, const double *x, double inflate, const int32_t *spt,
+                         int64_t n_spt, const int32_t *see, int64_t n_see, int32_t **pt, int64_t *n_pt, int32_t **ee,
+                         int64_t *n_ee, const char *tag, hipStream_t s);
 // pattern of the pairs (pt, ee) and, when given, the extra pairs (pt2, ee2)
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2 = nullptr,

@@ -102,7 +102,7 @@ int energy_at(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const do
 // own convergence test, CCD bound and line search (its own step length),
 // and its own PCG scalars; a scene marked done keeps its q.
 int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, const double *qt,
-                     uint8_t *done_dev, abd_stats *st, hipStream_t s) {
+                     uint8_t *done_dev, abd_stats *st, hipStream_t s, bool reuse_sweep) {
   auto t_all = std::chrono::steady_clock::now();
   const int nb = sc->n_bodies, nv = sc->n_verts;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
@@ -139,8 +139,14 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
   int32_t *pt, *ee, *keys;
   int64_t npt, nee, nk;
-  // scenes already done take no part (their direction is zero)
-  ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s, done_dev));
+  // scenes already done take no part (their direction is zero); after an
+  // accepted step the candidates come from that step's sweep
+  if (reuse_sweep && ctx->sw_valid)
+    ABD_TRY(op_candidates_within(ctx, sc, x, prm->dhat, ctx->sw_pt, ctx->sw_n_pt, ctx->sw_ee, ctx->sw_n_ee, &pt, &npt,
+                                 &ee, &nee, "nt_st", s));
+  else
+    ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s, done_dev));
+  ctx->sw_valid = false;
   // the pattern covers the candidates and the lagged friction pairs
   ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", s, fr ? fr->pt : nullptr, fr ? fr->n_pt : 0,
                      fr ? fr->ee : nullptr, fr ? fr->n_ee : 0));
@@ -256,6 +262,11 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->energy0 = e0;
   st->energy1 = e1;
   HIP_TRY(ctx, hipMemcpyAsync(q, qa, sizeof(double) * n12, hipMemcpyDeviceToDevice, s));
+  ctx->sw_valid = true;
+  ctx->sw_pt = spt;
+  ctx->sw_ee = see;
+  ctx->sw_n_pt = nspt;
+  ctx->sw_n_ee = nsee;
   st->t_total_ms += ms_since(t_all);
   prof_flush(ctx);
   return ABD_OK;
@@ -274,7 +285,7 @@ extern "C" int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_para
     ABD_TRY(ws(ctx, "ns_done", S, &done, stream));
     HIP_TRY(ctx, hipMemsetAsync(done, 0, S, stream));
   }
-  ABD_TRY(newton_iteration(ctx, sc, prm, q, q_tilde, done, st, stream));
+  ABD_TRY(newton_iteration(ctx, sc, prm, q, q_tilde, done, st, stream, false));
   st->newton_iters = 1;
   return ABD_OK;
 }
@@ -307,7 +318,7 @@ extern "C" int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params
   bool conv = false;
   for (; it < prm->max_newton; ++it) {
     abd_stats st = {};
-    ABD_TRY(newton_iteration(ctx, sc, prm, q, qt, done, &st, stream));
+    ABD_TRY(newton_iteration(ctx, sc, prm, q, qt, done, &st, stream, it > 0));
     // every scene still iterating ran this iteration
     total.scene_newton_iters += n_left;
     n_left -= st.newly_converged;

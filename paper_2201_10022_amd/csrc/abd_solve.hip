@@ -256,31 +256,136 @@ __global__ void __launch_bounds__(PB) k_pcg_init(const int32_t *u_scene, const i
   }
 }
 
+// Per-block constants of one iteration kernel, loaded in one go: the
+// block's scene, body range, the range of the other kernel's partials it
+// folds, and (spmv) the entry-list offsets of its four bodies.
+struct alignas(16) PcgBlk {
+  int32_t sc, first, last, is_first;
+  int32_t fold_lo, fold_n, e[SWBB + 1];
+  int32_t pad[16 - 6 - (SWBB + 1)];
+};
+
+// per body: its matrix entries (the diagonal block first, then the
+// off-diagonal blocks with the body as row, then as column)
+__global__ void k_pcg_entcount(int nb, const int64_t *lo_beg, const int64_t *hi_beg, int64_t *cnt) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  cnt[b] = 1 + (lo_beg[b + 1] - lo_beg[b]) + (hi_beg[b + 1] - hi_beg[b]);
+}
+// entry = (block index, column body | transposed << 30); block -1 = diagonal
+__global__ void k_pcg_entries(int nb, const int64_t *lo_beg, const int64_t *hi_beg, const uint32_t *tperm,
+                              const int32_t *keys, const int64_t *ent_off, int2 *ent) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  int64_t o = ent_off[b];
+  ent[o++] = make_int2(-1, b);
+  for (int64_t kk = lo_beg[b]; kk < lo_beg[b + 1]; ++kk) ent[o++] = make_int2((int)kk, keys[2 * kk + 1]);
+  for (int64_t h = hi_beg[b]; h < hi_beg[b + 1]; ++h) {
+    const int kk = (int)tperm[h];
+    ent[o++] = make_int2(kk, keys[2 * kk] | (1 << 30));
+  }
+}
+// block constants of a mapping with `bpb` bodies per block
+__global__ void k_pcg_blk(int64_t nblk, int bpb, const int32_t *tab, const int64_t *off, const int64_t *fold_off,
+                          const int32_t *sbo, const int64_t *ent_off, PcgBlk *out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nblk) return;
+  PcgBlk r;
+  for (int q = 0; q < 16 - 6 - (SWBB + 1); ++q) r.pad[q] = 0;
+  const int s = tab[j];
+  r.sc = s;
+  if (s < 0) {
+    r.first = r.last = r.is_first = r.fold_lo = r.fold_n = 0;
+    for (int q = 0; q <= SWBB; ++q) r.e[q] = 0;
+    out[j] = r;
+    return;
+  }
+  r.first = sbo[s] + (int)(j - off[s]) * bpb;
+  r.last = sbo[s + 1];
+  r.is_first = j == off[s];
+  r.fold_lo = (int)fold_off[s];
+  r.fold_n = (int)(fold_off[s + 1] - fold_off[s]);
+  for (int q = 0; q <= SWBB; ++q) {
+    const int b = r.first + q < r.last ? r.first + q : r.last;
+    r.e[q] = ent_off ? (int)ent_off[b] : 0;
+  }
+  out[j] = r;
+}
+
 // Iteration k (k = it_done): fold the scene's r.z, r.r of the previous
 // update, decide its stop, beta = rz_k / rz_{k-1}; p_new = z + beta p_old;
 // Ap = H p_new with one wave per body: lane = (entry slot 0..4, row 0..11),
-// entries = the diagonal block and the body's off-diagonal blocks (as row
-// and as column), five in flight per pass; per-row sums over slots in
+// five entries per pass.  Latency is what bounds this kernel at 12k DOFs, so
+// the dependent loads are cut to three round trips (block constants; entry
+// list, partials and stop flag; matrix rows and column vectors) and the
+// matrix work does not wait for beta (H z and H p_old are accumulated
+// separately and combined after the fold).  Per-row sums over slots in
 // fixed order.
-__global__ void __launch_bounds__(SWB) k_pcg_spmv(const int32_t *s_scene, const int64_t *s_off,
-                                                 const int64_t *u_off, const int32_t *sbo, const uint8_t *fixed,
-                                                 const double *diag, const double *off, const int32_t *keys,
-                                                 const uint32_t *tperm, const int64_t *lo_beg,
-                                                 const int64_t *hi_beg, const double *p_old, const double *z,
-                                                 double *p_new, double *Ap, const double *part2, double *part,
-                                                 PcgState *st, PcgScene scs, double rtol2, int max_iter) {
+__global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int2 *ent, const uint8_t *fixed,
+                                                 const double *diag, const double *off, const double *p_old,
+                                                 const double *z, double *p_new, double *Ap, const double *part2,
+                                                 double *part, PcgState *st, PcgScene scs, double rtol2,
+                                                 int max_iter) {
   __shared__ double sh[SWB / 64];
   const int k = st->it_done;
+  const PcgBlk bi = blk[blockIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) st->k_cur = k;
-  const int sc = s_scene[blockIdx.x];
-  if (sc < 0 || scs.stop[sc]) return;
-  const int64_t u0 = u_off[sc];
-  const int nu = (int)(u_off[sc + 1] - u0);
-  const double rz = fold(part2 + 2 * u0, nu, 2, 0, sh), rr = fold(part2 + 2 * u0, nu, 2, 1, sh);
+  if (bi.sc < 0) return;
+  const int sc = bi.sc;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot = lane / 12, i = lane % 12;
+  const int b = bi.first + wv;
+  const bool ok = b < bi.last;
+  // (explicit selects: a run-time index into the struct would move it to LDS)
+  const int ea = wv == 0 ? bi.e[0] : (wv == 1 ? bi.e[1] : (wv == 2 ? bi.e[2] : bi.e[3]));
+  const int eb = wv == 0 ? bi.e[1] : (wv == 1 ? bi.e[2] : (wv == 2 ? bi.e[3] : bi.e[4]));
+  const int e0 = ea, E = ok ? eb - ea : 0;
+  // round trip 2: stop flag, partials, the wave's entry list
+  const int stopped = scs.stop[sc];
+  double prz = 0.0, prr = 0.0;
+  for (int j = threadIdx.x; j < bi.fold_n; j += SWB) {
+    prz += part2[2 * (bi.fold_lo + j)];
+    prr += part2[2 * (bi.fold_lo + j) + 1];
+  }
+  int2 my_ent = make_int2(0, 0);
+  if (lane < E) my_ent = ent[e0 + lane];
+  const double own_z = ok ? z[12 * (int64_t)b + i] : 0.0, own_p = ok ? p_old[12 * (int64_t)b + i] : 0.0;
+  if (stopped) return;  // uniform over the block (one scene)
+  // rows and column vectors, five entries per pass (H z and H p_old kept
+  // apart so that no load waits for beta)
+  double accz = 0.0, accp = 0.0;
+  for (int e = slot; e - slot < E; e += 5) {
+    const int kk_s = __shfl(my_ent.x, e & 63, 64), cw_s = __shfl(my_ent.y, e & 63, 64);
+    if (lane < 60 && e < E) {
+      const int2 en = e < 64 ? make_int2(kk_s, cw_s) : ent[e0 + e];
+      const int kk = en.x, cw = en.y;
+      const int c = cw & ((1 << 30) - 1);
+      const bool tr = (cw >> 30) & 1;
+      const double *rp = kk < 0 ? diag + 144 * (int64_t)b + 12 * i
+                                : (tr ? off + 144 * (int64_t)kk + i : off + 144 * (int64_t)kk + 12 * i);
+      const int stride = tr ? 12 : 1;
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        accz += rp[stride * j] * z[12 * (int64_t)c + j];
+        accp += rp[stride * j] * p_old[12 * (int64_t)c + j];
+      }
+    }
+  }
+  double rz = wave_sum(prz), rr = wave_sum(prr);
+  if (lane == 0) sh[wv] = rz;
+  __syncthreads();
+  rz = 0.0;
+  for (int w = 0; w < SWB / 64; ++w) rz += sh[w];
+  __syncthreads();
+  if (lane == 0) sh[wv] = rr;
+  __syncthreads();
+  rr = 0.0;
+  for (int w = 0; w < SWB / 64; ++w) rr += sh[w];
+  __syncthreads();
   const double bb = k == 0 ? rr : scs.bb[sc];
   const double beta = k == 0 ? 0.0 : rz / scs.rz[2 * sc + ((k - 1) & 1)];
   const bool stop = !(bb > 0.0) || rr <= rtol2 * bb || k >= max_iter || rz == 0.0;
-  if (blockIdx.x == s_off[sc] && threadIdx.x == 0) {
+  if (bi.is_first && threadIdx.x == 0) {
     scs.rz[2 * sc + (k & 1)] = rz;
     if (k == 0) scs.bb[sc] = rr;
     if (stop) {
@@ -290,81 +395,78 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(const int32_t *s_scene, const 
     }
   }
   if (stop) return;
-  const int lane = threadIdx.x & 63;
-  const int b = sbo[sc] + (int)(blockIdx.x - s_off[sc]) * SWBB + (threadIdx.x >> 6);
-  const bool ok = b < sbo[sc + 1];
-  const int slot = lane / 12, i = lane % 12;
-  double acc = 0.0, pown = 0.0;
-  if (ok) {
-    pown = z[12 * (int64_t)b + i] + beta * p_old[12 * (int64_t)b + i];
-    const int64_t l0 = lo_beg[b], nlo = lo_beg[b + 1] - l0;
-    const int64_t h0 = hi_beg[b], nhi = hi_beg[b + 1] - h0;
-    const int64_t E = 1 + nlo + nhi;
-    for (int64_t e0 = 0; e0 < E; e0 += 5) {
-      const int64_t e = e0 + slot;
-      if (lane < 60 && e < E) {
-        const double *row;
-        int64_t c;
-        int stride;
-        if (e == 0) {
-          row = diag + 144 * (int64_t)b + 12 * i;
-          c = b;
-          stride = 1;
-        } else if (e <= nlo) {
-          const int64_t kk = l0 + e - 1;
-          row = off + 144 * kk + 12 * i;
-          c = keys[2 * kk + 1];
-          stride = 1;
-        } else {
-          const int64_t kk = tperm[h0 + e - 1 - nlo];
-          row = off + 144 * kk + i;  // column i of block (lo, b)
-          c = keys[2 * kk];
-          stride = 12;
-        }
-        const double *zc = z + 12 * c, *pc = p_old + 12 * c;
-#pragma unroll
-        for (int j = 0; j < 12; ++j) acc += row[stride * j] * (zc[j] + beta * pc[j]);
-      }
-    }
-  }
-  // sum the five slots of row i (lanes i, i+12, ..., i+48) in fixed order
-  double v = acc;
+  // per-row sums over the five slots (lanes i, i+12, ..., i+48), fixed order
+  double vz = accz, vp = accp;
 #pragma unroll
   for (int q = 1; q < 5; ++q) {
-    const double o = __shfl(acc, (lane + 12 * q) & 63, 64);
-    v += o;
+    vz += __shfl(accz, (lane + 12 * q) & 63, 64);
+    vp += __shfl(accp, (lane + 12 * q) & 63, 64);
   }
   double dot = 0.0;
   if (ok && slot == 0) {
-    const bool fx = fixed[b] != 0;
     const int64_t o = 12 * (int64_t)b + i;
-    const double av = fx ? 0.0 : v;
+    const double av = fixed[b] ? 0.0 : vz + beta * vp;
+    const double pown = own_z + beta * own_p;
     Ap[o] = av;
     p_new[o] = pown;
     dot = av * pown;
   }
-  const double s = block_sum(dot, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  const double sdot = block_sum(dot, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = sdot;
 }
 
 // alpha = rz_k / p.Ap (folded from the scene's spmv partials); x += alpha p;
-// r -= alpha Ap; z = P r; partials of r.z, r.r for the next spmv
-__global__ void __launch_bounds__(PB) k_pcg_update(const int32_t *u_scene, const int64_t *u_off,
-                                                  const int64_t *s_off, const int32_t *sbo, const double *inv,
-                                                  const double *p, const double *Ap, double *x, double *r, double *z,
+// r -= alpha Ap; z = P r = P r_old - alpha P Ap (both products formed
+// before alpha is known); partials of r.z, r.r for the next spmv
+__global__ void __launch_bounds__(PB) k_pcg_update(const PcgBlk *blk, const double *inv, const double *p,
+                                                  const double *Ap, double *x, double *r, double *z,
                                                   const double *part, double *part2, PcgState *st, PcgScene scs,
                                                   int *err) {
-  __shared__ double sr[PBB][12];
+  __shared__ double sr[PBB][12], sa[PBB][12];
   __shared__ double sh[PB / 64];
   const int k = st->k_cur;
+  const PcgBlk bi = blk[blockIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) st->it_done = k + 1;
-  const int sc = u_scene[blockIdx.x];
-  if (sc < 0 || scs.stop[sc]) return;
-  const int64_t s0 = s_off[sc];
-  const double pap = fold(part + s0, (int)(s_off[sc + 1] - s0), 1, 0, sh);
+  if (bi.sc < 0) return;
+  const int sc = bi.sc;
+  const int lb = threadIdx.x / 12, i = threadIdx.x % 12;
+  const int b = bi.first + lb;
+  const bool ok = b < bi.last;
+  const int64_t o = 12 * (int64_t)b + i;
+  // round trip 2: stop flag, partials, the row's data
+  const int stopped = scs.stop[sc];
+  double pp = 0.0;
+  for (int j = threadIdx.x; j < bi.fold_n; j += PB) pp += part[bi.fold_lo + j];
+  double pv = 0.0, av = 0.0, xv = 0.0, rv = 0.0, M[12];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) M[j] = 0.0;
+  if (ok) {
+    pv = p[o];
+    av = Ap[o];
+    xv = x[o];
+    rv = r[o];
+    const double *Mi = inv + 144 * (int64_t)b + 12 * i;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) M[j] = Mi[j];
+  }
+  if (stopped) return;  // uniform over the block
   const double rz = scs.rz[2 * sc + (k & 1)];
+  sr[lb][i] = rv;
+  sa[lb][i] = av;
+  double pap = wave_sum(pp);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pap;
+  __syncthreads();
+  pap = 0.0;
+  for (int w = 0; w < PB / 64; ++w) pap += sh[w];
+  double zr = 0.0, za = 0.0;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    zr += M[j] * sr[lb][j];
+    za += M[j] * sa[lb][j];
+  }
+  __syncthreads();
   if (!(pap > 0.0)) {
-    if (blockIdx.x == u_off[sc] && threadIdx.x == 0) {
+    if (bi.is_first && threadIdx.x == 0) {
       scs.stop[sc] = 1;
       scs.it_final[sc] = k;
       atomicAdd(&st->n_stopped, 1);
@@ -373,26 +475,15 @@ __global__ void __launch_bounds__(PB) k_pcg_update(const int32_t *u_scene, const
     return;
   }
   const double a = rz / pap;
-  const int lb = threadIdx.x / 12, i = threadIdx.x % 12;
-  const int b = sbo[sc] + (int)(blockIdx.x - u_off[sc]) * PBB + lb;
-  const bool ok = b < sbo[sc + 1];
-  double rv = 0.0;
+  double rn = 0.0, zn = 0.0;
   if (ok) {
-    const int64_t o = 12 * (int64_t)b + i;
-    x[o] += a * p[o];
-    rv = r[o] - a * Ap[o];
-    r[o] = rv;
+    x[o] = xv + a * pv;
+    rn = rv - a * av;
+    zn = zr - a * za;
+    r[o] = rn;
+    z[o] = zn;
   }
-  sr[lb][i] = rv;
-  __syncthreads();
-  double zv = 0.0;
-  if (ok) {
-    const double *M = inv + 144 * (int64_t)b + 12 * i;
-#pragma unroll
-    for (int j = 0; j < 12; ++j) zv += M[j] * sr[lb][j];
-    z[12 * (int64_t)b + i] = zv;
-  }
-  const double rzp = block_sum(rv * zv, sh), rrp = block_sum(rv * rv, sh);
+  const double rzp = block_sum(rn * zn, sh), rrp = block_sum(rn * rn, sh);
   if (threadIdx.x == 0) {
     part2[2 * blockIdx.x] = rzp;
     part2[2 * blockIdx.x + 1] = rrp;
@@ -466,6 +557,22 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   }
   hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(nb + 1, 256)), dim3(256), 0, s, nb, n_keys, keys, tk2, lo_beg,
                      hi_beg);
+  // entry lists per body and per-block constants
+  int64_t *ecnt, *eoff;
+  int2 *ent;
+  PcgBlk *sblk, *ublk;
+  ABD_TRY(ws(ctx, "pcg_ecnt", nb, &ecnt, s));
+  ABD_TRY(ws(ctx, "pcg_eoff", nb + 1, &eoff, s));
+  ABD_TRY(ws(ctx, "pcg_ent", nb + 2 * n_keys + 1, &ent, s));
+  ABD_TRY(ws(ctx, "pcg_sblk", nblk_s, &sblk, s));
+  ABD_TRY(ws(ctx, "pcg_ublk", nblk_u, &ublk, s));
+  hipLaunchKernelGGL(k_pcg_entcount, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, lo_beg, hi_beg, ecnt);
+  ABD_TRY(scan_exclusive_i64(ctx, ecnt, eoff, nb, eoff + nb, s));
+  hipLaunchKernelGGL(k_pcg_entries, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, lo_beg, hi_beg, tv2, keys, eoff, ent);
+  hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, (int64_t)nblk_s, SWBB, s_scene, s_off,
+                     u_off, sbo, eoff, sblk);
+  hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(nblk_u, 256)), dim3(256), 0, s, (int64_t)nblk_u, PBB, u_scene, u_off,
+                     s_off, sbo, nullptr, ublk);
   hipLaunchKernelGGL(k_pcg_reset, dim3(grid_for(S, 256)), dim3(256), 0, s, S, st, scs);
   hipLaunchKernelGGL(k_pcg_init, dim3(nblk_u), dim3(PB), 0, s, u_scene, u_off, sbo, sc->body_fixed, inv, rhs, x_out,
                      r, z, pa, part2);
@@ -475,10 +582,10 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   auto enqueue = [&](hipStream_t q) {
     for (int k = 0; k < ITER_G; ++k) {
       double *p_old = (k % 2 == 0) ? pa : pb, *p_new = (k % 2 == 0) ? pb : pa;
-      hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, q, s_scene, s_off, u_off, sbo, sc->body_fixed, diag,
-                         off, keys, tv2, lo_beg, hi_beg, p_old, z, p_new, Ap, part2, part, st, scs, rtol2, max_iter);
-      hipLaunchKernelGGL(k_pcg_update, dim3(nblk_u), dim3(PB), 0, q, u_scene, u_off, s_off, sbo, inv, p_new, Ap, x_out,
-                         r, z, part, part2, st, scs, err);
+      hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, q, sblk, ent, sc->body_fixed, diag, off, p_old, z,
+                         p_new, Ap, part2, part, st, scs, rtol2, max_iter);
+      hipLaunchKernelGGL(k_pcg_update, dim3(nblk_u), dim3(PB), 0, q, ublk, inv, p_new, Ap, x_out, r, z, part, part2,
+                         st, scs, err);
     }
   };
   const char *env = getenv("ABD_PCG_GRAPH");
@@ -496,7 +603,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
         (uintptr_t)sc->body_fixed, (uintptr_t)nb, (uintptr_t)max_iter, (uintptr_t)rtol_bits,
         (uintptr_t)S, (uintptr_t)sbo, (uintptr_t)u_scene, (uintptr_t)s_scene, (uintptr_t)u_off, (uintptr_t)s_off,
         (uintptr_t)scs.rz, (uintptr_t)scs.bb, (uintptr_t)scs.stop, (uintptr_t)scs.it_final,
-        (uintptr_t)nblk_u, (uintptr_t)nblk_s};
+        (uintptr_t)nblk_u, (uintptr_t)nblk_s, (uintptr_t)sblk, (uintptr_t)ublk, (uintptr_t)ent};
     if (ctx->pcg_exec == nullptr || ctx->pcg_key != key) {
       if (ctx->pcg_exec) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec));
       ctx->pcg_exec = nullptr;

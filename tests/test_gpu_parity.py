@@ -451,3 +451,20 @@ def test_pcg_tolerance_change_recaptures(abd, ctx):
     assert np.abs(p.cpu().numpy() - p_ref).max() <= 1e-8 * np.abs(p_ref).max()
     _, it_loose2 = ctx.pcg_solve(sc, *args, rtol=1e-2, max_iter=20000)
     assert it_loose2 == it_loose
+
+
+@pytest.mark.parametrize("name,S,P", SCENES, ids=[s[0] for s in SCENES])
+def test_candidates_within_sweep_equal_full_broad_phase(abd, ctx, name, S, P):
+    """Static candidates taken from a sweep's candidates equal the full broad
+    phase at points of the segment (the Newton loop relies on it)."""
+    sc = abd.Scene(S)
+    q0 = _state(S, 41)
+    q1 = sg.random_state(S, 42, rot_angle=3e-3, shift=3e-3)
+    x0, x1 = oracle.vertex_map(S, q0), oracle.vertex_map(S, q1)
+    spt, see = ctx.candidates(sc, _dev(x0), _dev(x1), P["dhat"])
+    for a in (0.0, 0.3, 0.77, 1.0):
+        xa = oracle.vertex_map(S, q0 + a * (q1 - q0))
+        fpt, fee = ctx.candidates(sc, _dev(xa), None, P["dhat"])
+        wpt, wee = ctx.candidates_within(sc, _dev(xa), spt, see, P["dhat"])
+        np.testing.assert_array_equal(wpt.cpu().numpy(), fpt.cpu().numpy())
+        np.testing.assert_array_equal(wee.cpu().numpy(), fee.cpu().numpy())

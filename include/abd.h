@@ -220,11 +220,12 @@ int abd_q_tilde(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const 
  * off/off^T) restricted to free bodies: solves H p = rhs, p = 0 on fixed
  * bodies.  Sub-scenes are independent systems (no off-diagonal block joins
  * two of them): each runs its own CG scalars and stops on its own
- * |r| <= rtol |b|.  Syncs; *iters (host) receives the largest iteration
- * count over the sub-scenes. */
+ * |r| <= rtol |b|.  x0 (may be NULL = zero, may alias p): initial guess.
+ * Syncs; *iters (host) receives the largest iteration count over the
+ * sub-scenes. */
 int abd_pcg_solve(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
-                  int64_t n_keys, const double *rhs, double *p, double rtol, int32_t max_iter, int32_t *iters,
-                  hipStream_t stream);
+                  int64_t n_keys, const double *rhs, const double *x0, double *p, double rtol, int32_t max_iter,
+                  int32_t *iters, hipStream_t stream);
 
 /* One projected-Newton iteration on q (in/out) towards the minimiser of
  * the incremental potential with target q_tilde: direction p = -H^-1 g;

@@ -229,11 +229,11 @@ class Context:
                                        _ptr(out), _stream()))
         return out
 
-    def pcg_solve(self, scene, diag, off, keys, rhs, rtol=1e-12, max_iter=10000):
+    def pcg_solve(self, scene, diag, off, keys, rhs, rtol=1e-12, max_iter=10000, x0=None):
         p = torch.zeros_like(rhs)
         it = ctypes.c_int32(0)
         self._check(self.L.abd_pcg_solve(self.h, ctypes.byref(scene.c), _ptr(diag), _ptr(off), _ptr(keys),
-                                         keys.shape[0], _ptr(rhs), _ptr(p), float(rtol), int(max_iter),
+                                         keys.shape[0], _ptr(rhs), _ptr(x0), _ptr(p), float(rtol), int(max_iter),
                                          ctypes.byref(it), _stream()))
         return p, it.value
 

@@ -74,7 +74,7 @@ SIGNATURES = {
     "abd_orthogonality": ([_vp, _PS, _PP, _vp, _dbl, _vp, _vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
     "abd_inertia": ([_vp, _PS, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "abd_q_tilde": ([_vp, _PS, _PP, _vp, _vp, _vp, _vp], ctypes.c_int),
-    "abd_pcg_solve": ([_vp, _PS, _vp, _vp, _vp, _i64, _vp, _vp, _dbl, _i32, _pi32, _vp], ctypes.c_int),
+    "abd_pcg_solve": ([_vp, _PS, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _dbl, _i32, _pi32, _vp], ctypes.c_int),
     "abd_newton_step": ([_vp, _PS, _PP, _vp, _vp, _vp, _PST, _vp], ctypes.c_int),
     "abd_time_step": ([_vp, _PS, _PP, _vp, _vp, _PST, _vp], ctypes.c_int),
     "abd_friction_lag": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),

@@ -159,7 +159,7 @@ __global__ void k_records(int64_t n, const PairInfo *info, const uint8_t *fixed,
   rval[3 * a + 2] = (uint32_t)(4 * a + (b0 < b1 ? 2 : 3));
 }
 
-constexpr int RCH = 32;   // records per chunk
+constexpr int RCH = 8;    // records per chunk (a short serial chain per wave)
 constexpr int NENT = 156; // 144 block entries + 12 gradient entries
 
 // chunk counts per block from the sorted keys (binary search)

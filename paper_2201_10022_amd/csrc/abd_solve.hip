@@ -221,10 +221,12 @@ __global__ void k_pcg_reset(int S, PcgState *st, PcgScene sc) {
   }
 }
 
-// r = rhs (free bodies), x = 0, z = P r, p_old = 0; partials of r.z, r.r
+// r = rhs - H x0 (free bodies; Hx0 NULL: x0 = 0), x = x0, z = P r, p_old = 0;
+// partials of r.z, r.r and rhs.rhs
 __global__ void __launch_bounds__(PB) k_pcg_init(const int32_t *u_scene, const int64_t *u_off, const int32_t *sbo,
                                                 const uint8_t *fixed, const double *inv, const double *rhs,
-                                                double *x, double *r, double *z, double *p_old, double *part2) {
+                                                const double *x0, const double *Hx0, double *x, double *r,
+                                                double *z, double *p_old, double *part2) {
   __shared__ double sr[PBB][12];
   __shared__ double sh[PB / 64];
   const int sc = u_scene[blockIdx.x];
@@ -232,11 +234,12 @@ __global__ void __launch_bounds__(PB) k_pcg_init(const int32_t *u_scene, const i
   const int lb = threadIdx.x / 12, i = threadIdx.x % 12;
   const int b = sbo[sc] + (int)(blockIdx.x - u_off[sc]) * PBB + lb;
   const bool ok = lb < PBB && b < sbo[sc + 1];
-  double rv = 0.0;
+  double rv = 0.0, bv = 0.0;
   if (ok) {
     const int64_t o = 12 * (int64_t)b + i;
-    rv = fixed[b] ? 0.0 : rhs[o];
-    x[o] = 0.0;
+    bv = fixed[b] ? 0.0 : rhs[o];
+    rv = Hx0 && !fixed[b] ? bv - Hx0[o] : bv;
+    x[o] = Hx0 && !fixed[b] ? x0[o] : 0.0;
     r[o] = rv;
     p_old[o] = 0.0;
   }
@@ -249,10 +252,11 @@ __global__ void __launch_bounds__(PB) k_pcg_init(const int32_t *u_scene, const i
     for (int j = 0; j < 12; ++j) zv += M[j] * sr[lb][j];
     z[12 * (int64_t)b + i] = zv;
   }
-  const double rz = block_sum(rv * zv, sh), rr = block_sum(rv * rv, sh);
+  const double rz = block_sum(rv * zv, sh), rr = block_sum(rv * rv, sh), bb = block_sum(bv * bv, sh);
   if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = rz;
-    part2[2 * blockIdx.x + 1] = rr;
+    part2[3 * blockIdx.x] = rz;
+    part2[3 * blockIdx.x + 1] = rr;
+    part2[3 * blockIdx.x + 2] = bb;
   }
 }
 
@@ -342,10 +346,11 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int2 
   const int e0 = ea, E = ok ? eb - ea : 0;
   // round trip 2: stop flag, partials, the wave's entry list
   const int stopped = scs.stop[sc];
-  double prz = 0.0, prr = 0.0;
+  double prz = 0.0, prr = 0.0, pbb = 0.0;
   for (int j = threadIdx.x; j < bi.fold_n; j += SWB) {
-    prz += part2[2 * (bi.fold_lo + j)];
-    prr += part2[2 * (bi.fold_lo + j) + 1];
+    prz += part2[3 * (bi.fold_lo + j)];
+    prr += part2[3 * (bi.fold_lo + j) + 1];
+    if (k == 0) pbb += part2[3 * (bi.fold_lo + j) + 2];
   }
   int2 my_ent = make_int2(0, 0);
   if (lane < E) my_ent = ent[e0 + lane];
@@ -371,7 +376,7 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int2 
       }
     }
   }
-  double rz = wave_sum(prz), rr = wave_sum(prr);
+  double rz = wave_sum(prz), rr = wave_sum(prr), b0 = wave_sum(pbb);
   if (lane == 0) sh[wv] = rz;
   __syncthreads();
   rz = 0.0;
@@ -382,12 +387,20 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int2 
   rr = 0.0;
   for (int w = 0; w < SWB / 64; ++w) rr += sh[w];
   __syncthreads();
-  const double bb = k == 0 ? rr : scs.bb[sc];
+  if (k == 0) {
+    if (lane == 0) sh[wv] = b0;
+    __syncthreads();
+    b0 = 0.0;
+    for (int w = 0; w < SWB / 64; ++w) b0 += sh[w];
+    __syncthreads();
+  }
+  // |r| <= rtol |b| with b the right-hand side (x0 may be non-zero)
+  const double bb = k == 0 ? b0 : scs.bb[sc];
   const double beta = k == 0 ? 0.0 : rz / scs.rz[2 * sc + ((k - 1) & 1)];
   const bool stop = !(bb > 0.0) || rr <= rtol2 * bb || k >= max_iter || rz == 0.0;
   if (bi.is_first && threadIdx.x == 0) {
     scs.rz[2 * sc + (k & 1)] = rz;
-    if (k == 0) scs.bb[sc] = rr;
+    if (k == 0) scs.bb[sc] = bb;
     if (stop) {
       scs.stop[sc] = 1;
       scs.it_final[sc] = k;
@@ -485,16 +498,61 @@ __global__ void __launch_bounds__(PB) k_pcg_update(const PcgBlk *blk, const doub
   }
   const double rzp = block_sum(rn * zn, sh), rrp = block_sum(rn * rn, sh);
   if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = rzp;
-    part2[2 * blockIdx.x + 1] = rrp;
+    part2[3 * blockIdx.x] = rzp;
+    part2[3 * blockIdx.x + 1] = rrp;
   }
+}
+
+// y = sx H x (plain block SpMV; one wave per body)
+__global__ void __launch_bounds__(SWB) k_bsr_spmv(int nb, const uint8_t *fixed, const double *diag, const double *off,
+                                                 const int32_t *keys, const uint32_t *tperm, const int64_t *lo_beg,
+                                                 const int64_t *hi_beg, const double *xv, double sx, double *y) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * SWBB + (threadIdx.x >> 6);
+  if (b >= nb) return;
+  const int slot = lane / 12, i = lane % 12;
+  double acc = 0.0;
+  const int64_t l0 = lo_beg[b], nlo = lo_beg[b + 1] - l0;
+  const int64_t h0 = hi_beg[b], nhi = hi_beg[b + 1] - h0;
+  const int64_t E = 1 + nlo + nhi;
+  for (int64_t e0 = 0; e0 < E; e0 += 5) {
+    const int64_t e = e0 + slot;
+    if (lane < 60 && e < E) {
+      const double *row;
+      int64_t c;
+      int stride;
+      if (e == 0) {
+        row = diag + 144 * (int64_t)b + 12 * i;
+        c = b;
+        stride = 1;
+      } else if (e <= nlo) {
+        const int64_t kk = l0 + e - 1;
+        row = off + 144 * kk + 12 * i;
+        c = keys[2 * kk + 1];
+        stride = 1;
+      } else {
+        const int64_t kk = tperm[h0 + e - 1 - nlo];
+        row = off + 144 * kk + i;
+        c = keys[2 * kk];
+        stride = 12;
+      }
+      const double *xc = xv + 12 * c;
+#pragma unroll
+      for (int j = 0; j < 12; ++j) acc += row[stride * j] * xc[j];
+    }
+  }
+  double v = acc;
+#pragma unroll
+  for (int q = 1; q < 5; ++q) v += __shfl(acc, (lane + 12 * q) & 63, 64);
+  if (slot == 0) y[12 * (int64_t)b + i] = fixed[b] ? 0.0 : sx * v;
 }
 
 }  // namespace
 
 
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
-           int64_t n_keys, const double *rhs, double *x_out, double rtol, int max_iter, int *iters, hipStream_t s) {
+           int64_t n_keys, const double *rhs, double *x_out, double rtol, int max_iter, int *iters, hipStream_t s,
+           const double *x0) {
   const int nb = sc->n_bodies;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   *iters = 0;
@@ -520,7 +578,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(ws(ctx, "pcg_pb", 12 * (size_t)nb, &pb, s));
   ABD_TRY(ws(ctx, "pcg_Ap", 12 * (size_t)nb, &Ap, s));
   ABD_TRY(ws(ctx, "pcg_part", nblk_s, &part, s));
-  ABD_TRY(ws(ctx, "pcg_part2", 2 * (size_t)nblk_u, &part2, s));
+  ABD_TRY(ws(ctx, "pcg_part2", 3 * (size_t)nblk_u, &part2, s));
   ABD_TRY(ws(ctx, "pcg_lob", nb + 1, &lo_beg, s));
   ABD_TRY(ws(ctx, "pcg_hib", nb + 1, &hi_beg, s));
   ABD_TRY(ws(ctx, "pcg_tk", n_keys + 1, &tk, s));
@@ -574,8 +632,15 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(nblk_u, 256)), dim3(256), 0, s, (int64_t)nblk_u, PBB, u_scene, u_off,
                      s_off, sbo, nullptr, ublk);
   hipLaunchKernelGGL(k_pcg_reset, dim3(grid_for(S, 256)), dim3(256), 0, s, S, st, scs);
-  hipLaunchKernelGGL(k_pcg_init, dim3(nblk_u), dim3(PB), 0, s, u_scene, u_off, sbo, sc->body_fixed, inv, rhs, x_out,
-                     r, z, pa, part2);
+  const double *Hx0 = nullptr;
+  if (x0) {
+    // warm start: r = rhs - H x0 (Ap as scratch)
+    hipLaunchKernelGGL(k_bsr_spmv, dim3(grid_for(nb, SWBB)), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2,
+                       lo_beg, hi_beg, x0, 1.0, Ap);
+    Hx0 = Ap;
+  }
+  hipLaunchKernelGGL(k_pcg_init, dim3(nblk_u), dim3(PB), 0, s, u_scene, u_off, sbo, sc->body_fixed, inv, rhs, x0, Hx0,
+                     x_out, r, z, pa, part2);
   HIP_TRY(ctx, hipGetLastError());
   const double rtol2 = rtol * rtol;
   // ITER_G iterations: p alternates pa -> pb -> pa ... (ITER_G is even)
@@ -679,49 +744,6 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
 // preconditioner must be symmetric positive definite (its diagonal blocks
 // are given separately).
 namespace {
-
-__global__ void __launch_bounds__(SWB) k_bsr_spmv(int nb, const uint8_t *fixed, const double *diag, const double *off,
-                                                 const int32_t *keys, const uint32_t *tperm, const int64_t *lo_beg,
-                                                 const int64_t *hi_beg, const double *xv, double sx, double *y) {
-  const int lane = threadIdx.x & 63;
-  const int b = blockIdx.x * SWBB + (threadIdx.x >> 6);
-  if (b >= nb) return;
-  const int slot = lane / 12, i = lane % 12;
-  double acc = 0.0;
-  const int64_t l0 = lo_beg[b], nlo = lo_beg[b + 1] - l0;
-  const int64_t h0 = hi_beg[b], nhi = hi_beg[b + 1] - h0;
-  const int64_t E = 1 + nlo + nhi;
-  for (int64_t e0 = 0; e0 < E; e0 += 5) {
-    const int64_t e = e0 + slot;
-    if (lane < 60 && e < E) {
-      const double *row;
-      int64_t c;
-      int stride;
-      if (e == 0) {
-        row = diag + 144 * (int64_t)b + 12 * i;
-        c = b;
-        stride = 1;
-      } else if (e <= nlo) {
-        const int64_t kk = l0 + e - 1;
-        row = off + 144 * kk + 12 * i;
-        c = keys[2 * kk + 1];
-        stride = 1;
-      } else {
-        const int64_t kk = tperm[h0 + e - 1 - nlo];
-        row = off + 144 * kk + i;
-        c = keys[2 * kk];
-        stride = 12;
-      }
-      const double *xc = xv + 12 * c;
-#pragma unroll
-      for (int j = 0; j < 12; ++j) acc += row[stride * j] * xc[j];
-    }
-  }
-  double v = acc;
-#pragma unroll
-  for (int q = 1; q < 5; ++q) v += __shfl(acc, (lane + 12 * q) & 63, 64);
-  if (slot == 0) y[12 * (int64_t)b + i] = fixed[b] ? 0.0 : sx * v;
-}
 
 __global__ void k_block_apply(int nb, const double *inv, const double *v, double *z) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -886,12 +908,12 @@ int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const doubl
 }
 
 extern "C" int abd_pcg_solve(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off,
-                             const int32_t *keys, int64_t n_keys, const double *rhs, double *p, double rtol,
-                             int32_t max_iter, int32_t *iters, hipStream_t stream) {
+                             const int32_t *keys, int64_t n_keys, const double *rhs, const double *x0, double *p,
+                             double rtol, int32_t max_iter, int32_t *iters, hipStream_t stream) {
   if (!ctx || !sc || !diag || !rhs || !p || !iters || (n_keys && (!off || !keys)))
     return abd_fail(ctx, ABD_E_INVALID, "abd_pcg_solve: null");
   int it = 0;
-  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, n_keys, rhs, p, rtol, max_iter, &it, stream));
+  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, n_keys, rhs, p, rtol, max_iter, &it, stream, x0));
   *iters = it;
   return ABD_OK;
 }

@@ -468,3 +468,28 @@ def test_candidates_within_sweep_equal_full_broad_phase(abd, ctx, name, S, P):
         wpt, wee = ctx.candidates_within(sc, _dev(xa), spt, see, P["dhat"])
         np.testing.assert_array_equal(wpt.cpu().numpy(), fpt.cpu().numpy())
         np.testing.assert_array_equal(wee.cpu().numpy(), fee.cpu().numpy())
+
+
+def test_pcg_initial_guess(abd, ctx):
+    """PCG from an initial guess: the solution itself stops at once; any
+    other guess reaches the direct solution; the tolerance is relative to
+    the right-hand side, not to the initial residual."""
+    S = sg.near_contact_cubes(3, n=4)
+    P = dict(sg.default_params())
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    B = oracle.Body(S)
+    q = _state(S, 73)
+    qt = q.copy()
+    qt[:, :3] += P["dt"] ** 2 * np.array(P["gravity"])
+    qt[S["body_fixed"] != 0] = q[S["body_fixed"] != 0]
+    gh = oracle.grad_hess(S, B, q, qt, P)
+    args = (_dev(gh["diag"]), _dev(gh["off"]), _dev(gh["keys"], torch.int32), _dev(-gh["grad"]))
+    p_ref = oracle.solve(S, gh["diag"], gh["off"], gh["keys"], -gh["grad"])
+    _, it_sol = ctx.pcg_solve(sc, *args, rtol=1e-6, max_iter=20000, x0=_dev(p_ref))
+    assert it_sol == 0
+    x0 = np.random.default_rng(5).normal(size=p_ref.shape) * np.abs(p_ref).max()
+    x0[S["body_fixed"] != 0] = 0.0
+    p, it = ctx.pcg_solve(sc, *args, rtol=1e-14, max_iter=20000, x0=_dev(x0))
+    assert it > 0
+    assert np.abs(p.cpu().numpy() - p_ref).max() <= 1e-8 * np.abs(p_ref).max()

@@ -329,7 +329,8 @@ extern "C" int abd_destroy(abd_ctx *ctx) {
     if (e) hipEventDestroy(e);
   prof_flush(ctx);
   for (auto &e : ctx->ev_pool) hipEventDestroy(e);
-  if (ctx->pcg_exec) hipGraphExecDestroy(ctx->pcg_exec);
+  for (int g = 0; g < 2; ++g)
+    if (ctx->pcg_exec[g]) hipGraphExecDestroy(ctx->pcg_exec[g]);
   if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
   delete ctx;
   return ABD_OK;

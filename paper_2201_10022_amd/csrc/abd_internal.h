@@ -44,9 +44,12 @@ struct abd_ctx {
   std::map<std::string, KStat> kstats;
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> ev_pool;
-  // captured PCG iterations, re-captured when any argument changes
-  hipGraphExec_t pcg_exec = nullptr;
-  std::vector<uintptr_t> pcg_key;
+  // captured PCG iterations (short and long replays), re-captured when any
+  // argument changes; pcg_hint: iterations of the last solve
+  hipGraphExec_t pcg_exec[2] = {nullptr, nullptr};
+  std::vector<uintptr_t> pcg_key[2];
+  int pcg_hint = 0;
+  int ls_hint = 0;  // line-search halvings of the last Newton iteration
   hipStream_t capture_stream = nullptr;
   // friction lagged at the start of the current time step (set by
   // abd_friction_begin_step, used by the Newton iterations while set)

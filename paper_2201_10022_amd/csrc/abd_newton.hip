@@ -79,21 +79,21 @@ __global__ void k_axpy_scene(int nb, const int32_t *body_scene, const double *a,
   out[i] = a[i] + alpha[body_scene[i / 12]] * b[i];
 }
 
-// per-scene E(q) over the given (swept) candidates into e_dev [S]; copied
-// to out (host, [S])
-int energy_at(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
-              double *x, const int32_t *pt, int64_t npt, const int32_t *ee, int64_t nee, const FrictionSet *fr,
-              double *e_dev, double *out, hipStream_t s) {
+// per-scene E(q) over the given (swept) candidates into e_dev [S],
+// enqueued only (no synchronisation)
+int energy_enqueue(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
+                   double *x, const int32_t *pt, int64_t npt, const int32_t *ee, int64_t nee, const FrictionSet *fr,
+                   double *e_dev, hipStream_t s) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   ABD_TRY(zero(ctx, e_dev, S, s));
   ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
   ABD_TRY(op_body_energy_scenes(ctx, sc, prm, q, qt, e_dev, s));
   ABD_TRY(op_barrier_energy_scenes(ctx, sc, prm, x, pt, npt, ee, nee, e_dev, s));
   if (fr) ABD_TRY(op_friction_energy_scenes(ctx, sc, fr, x, e_dev, s));
-  HIP_TRY(ctx, hipMemcpyAsync(out, e_dev, S * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
   return ABD_OK;
 }
+
+constexpr int LS_BATCH = 4;  // trial step lengths evaluated per line-search batch
 
 }  // namespace
 
@@ -117,14 +117,15 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(ws(ctx, "nt_qa", n12, &qa, s));
   ABD_TRY(ws(ctx, "nt_e", 4, &e, s));
   ABD_TRY(ws(ctx, "nt_sv", 2 * (size_t)S, &sv, s));
-  ABD_TRY(ws(ctx, "nt_alpha", S, &alpha_dev, s));
+  ABD_TRY(ws(ctx, "nt_alpha", (size_t)LS_BATCH * S, &alpha_dev, s));
   double *e_sc;
-  ABD_TRY(ws(ctx, "nt_escene", S, &e_sc, s));
+  ABD_TRY(ws(ctx, "nt_escene", (size_t)LS_BATCH * S, &e_sc, s));
   // host staging: done flags, per-scene disp / alpha / E0 / E1
   double *h;
-  ABD_TRY(pinned_get_nt(ctx, sizeof(double) * (8 + 5 * (size_t)S), reinterpret_cast<void **>(&h)));
-  double *h_disp = h + 8, *h_alpha = h_disp + S, *h_e0 = h_alpha + S, *h_e1 = h_e0 + S;
-  uint8_t *h_done = reinterpret_cast<uint8_t *>(h_e1 + S);
+  ABD_TRY(pinned_get_nt(ctx, sizeof(double) * (8 + (4 + 2 * (size_t)LS_BATCH) * S), reinterpret_cast<void **>(&h)));
+  double *h_disp = h + 8, *h_alpha = h_disp + S, *h_e0 = h_alpha + S, *h_e1 = h_e0 + S;  // h_e1 [LS_BATCH][S]
+  double *h_atr = h_e1 + (size_t)LS_BATCH * S;                                          // [LS_BATCH][S]
+  uint8_t *h_done = reinterpret_cast<uint8_t *>(h_atr + (size_t)LS_BATCH * S);
   HIP_TRY(ctx, hipMemcpyAsync(h_done, done_dev, S, hipMemcpyDeviceToHost, s));
 
   // lagged friction of the current time step, if any
@@ -229,26 +230,57 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   }
   st->alpha_ccd = amin;
 
-  // backtracking line search, per scene
-  ABD_TRY(energy_at(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, fr, e_sc, h_e0, s));
+  // backtracking line search, per scene: the trial step lengths
+  // alpha 2^-j are evaluated in batches of K (K from the last iteration's
+  // halvings) with one synchronisation per batch; each scene takes the
+  // first trial that does not raise its energy, exactly as one-by-one
+  // halving would
+  ABD_TRY(energy_enqueue(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, fr, e_sc, s));
+  HIP_TRY(ctx, hipMemcpyAsync(h_e0, e_sc, S * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
   int k = 0;
   int max_halvings = 0;
   std::vector<int> halv(S, 0);
-  for (; k < prm->max_ls; ++k) {
-    HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_alpha, S * sizeof(double), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q, alpha_dev, p,
-                       qa);
-    ABD_TRY(energy_at(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e_sc, h_e1, s));
-    int pending = 0;
-    for (int j = 0; j < S; ++j) {
-      if (h_done[j] || h_e1[j] <= h_e0[j]) continue;
-      h_alpha[j] *= 0.5;
-      ++halv[j];
-      ++pending;
+  std::vector<uint8_t> acc(S, 0);
+  for (int j = 0; j < S; ++j) acc[j] = h_done[j];
+  int K = ctx->ls_hint + 1;
+  K = K < 1 ? 1 : (K > LS_BATCH ? LS_BATCH : K);
+  bool all_acc = false;
+  while (k < prm->max_ls && !all_acc) {
+    const int kb = k + K <= prm->max_ls ? K : prm->max_ls - k;
+    for (int t = 0; t < kb; ++t)
+      for (int j = 0; j < S; ++j) h_atr[(size_t)t * S + j] = acc[j] ? h_alpha[j] : std::ldexp(h_alpha[j], -t);
+    HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_atr, (size_t)kb * S * sizeof(double), hipMemcpyHostToDevice, s));
+    for (int t = 0; t < kb; ++t) {
+      hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q,
+                         alpha_dev + (size_t)t * S, p, qa);
+      ABD_TRY(energy_enqueue(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e_sc + (size_t)t * S, s));
     }
-    if (pending == 0) break;
+    HIP_TRY(ctx, hipMemcpyAsync(h_e1, e_sc, (size_t)kb * S * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    all_acc = true;
+    for (int j = 0; j < S; ++j) {
+      if (acc[j]) continue;
+      int t = 0;
+      while (t < kb && !(h_e1[(size_t)t * S + j] <= h_e0[j])) ++t;
+      if (t < kb) {
+        acc[j] = 1;
+        h_alpha[j] = std::ldexp(h_alpha[j], -t);
+        halv[j] += t;
+        h_e1[j] = h_e1[(size_t)t * S + j];
+      } else {
+        h_alpha[j] = std::ldexp(h_alpha[j], -kb);
+        halv[j] += kb;
+        all_acc = false;
+      }
+    }
+    k += kb;
   }
-  if (k == prm->max_ls) return abd_fail(ctx, ABD_E_LINESEARCH, "line search found no decrease");
+  if (!all_acc) return abd_fail(ctx, ABD_E_LINESEARCH, "line search found no decrease");
+  // the accepted point of every scene
+  HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_alpha, S * sizeof(double), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q, alpha_dev, p,
+                     qa);
   double e0 = 0.0, e1 = 0.0, amin_acc = 1.0;
   for (int j = 0; j < S; ++j) {
     if (h_done[j]) continue;
@@ -258,6 +290,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     max_halvings = halv[j] > max_halvings ? halv[j] : max_halvings;
   }
   st->ls_halvings = max_halvings;
+  ctx->ls_hint = max_halvings;
   st->alpha = amin_acc;
   st->energy0 = e0;
   st->energy1 = e1;

@@ -10,7 +10,7 @@
 // the previous kernel's partials in a fixed order; every block does the same
 // fold, so all blocks take the same decisions (alpha, beta, stop) without
 // fences, atomics or separate reduction launches, and results are run-to-run
-// reproducible.  Iterations are replayed from a captured hipGraph of ITER_G
+// reproducible.  Iterations are replayed from captured hipGraphs of ITER_G
 // iterations; once the stop flag is set the remaining kernels return at
 // once, and the host reads the flag once per replay.
 #include <cstdlib>
@@ -22,7 +22,9 @@
 
 namespace {
 
-constexpr int ITER_G = 16;  // iterations per graph replay (even: p buffers alternate)
+// iterations per graph replay (even: p buffers alternate): short replays,
+// and long ones while the last solve's count says many remain
+constexpr int ITER_G[2] = {16, 64};
 
 // inverse of each free body's diagonal block via Cholesky (thread per body)
 __global__ void __launch_bounds__(64) k_block_inverse(int nb, const uint8_t *fixed, const double *diag, double *inv,
@@ -643,9 +645,9 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
                      x_out, r, z, pa, part2);
   HIP_TRY(ctx, hipGetLastError());
   const double rtol2 = rtol * rtol;
-  // ITER_G iterations: p alternates pa -> pb -> pa ... (ITER_G is even)
-  auto enqueue = [&](hipStream_t q) {
-    for (int k = 0; k < ITER_G; ++k) {
+  // n iterations: p alternates pa -> pb -> pa ... (n is even)
+  auto enqueue = [&](hipStream_t q, int n) {
+    for (int k = 0; k < n; ++k) {
       double *p_old = (k % 2 == 0) ? pa : pb, *p_new = (k % 2 == 0) ? pb : pa;
       hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, q, sblk, ent, sc->body_fixed, diag, off, p_old, z,
                          p_new, Ap, part2, part, st, scs, rtol2, max_iter);
@@ -655,7 +657,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   };
   const char *env = getenv("ABD_PCG_GRAPH");
   const bool use_graph = !(env && env[0] == '0');
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   if (use_graph) {
     // every value baked into the captured kernels' arguments is part of the
     // key (rtol2 by its bit pattern)
@@ -669,24 +671,26 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
         (uintptr_t)S, (uintptr_t)sbo, (uintptr_t)u_scene, (uintptr_t)s_scene, (uintptr_t)u_off, (uintptr_t)s_off,
         (uintptr_t)scs.rz, (uintptr_t)scs.bb, (uintptr_t)scs.stop, (uintptr_t)scs.it_final,
         (uintptr_t)nblk_u, (uintptr_t)nblk_s, (uintptr_t)sblk, (uintptr_t)ublk, (uintptr_t)ent};
-    if (ctx->pcg_exec == nullptr || ctx->pcg_key != key) {
-      if (ctx->pcg_exec) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec));
-      ctx->pcg_exec = nullptr;
-      if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-      hipGraph_t g = nullptr;
-      HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-      enqueue(ctx->capture_stream);
-      HIP_TRY(ctx, hipStreamEndCapture(ctx->capture_stream, &g));
-      HIP_TRY(ctx, hipGraphInstantiate(&ctx->pcg_exec, g, nullptr, nullptr, 0));
-      HIP_TRY(ctx, hipGraphDestroy(g));
-      ctx->pcg_key = key;
+    if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    for (int gi = 0; gi < 2; ++gi) {
+      if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {
+        if (ctx->pcg_exec[gi]) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec[gi]));
+        ctx->pcg_exec[gi] = nullptr;
+        hipGraph_t g = nullptr;
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        enqueue(ctx->capture_stream, ITER_G[gi]);
+        HIP_TRY(ctx, hipStreamEndCapture(ctx->capture_stream, &g));
+        HIP_TRY(ctx, hipGraphInstantiate(&ctx->pcg_exec[gi], g, nullptr, nullptr, 0));
+        HIP_TRY(ctx, hipGraphDestroy(g));
+        ctx->pcg_key[gi] = key;
+      }
+      exec[gi] = ctx->pcg_exec[gi];
     }
-    exec = ctx->pcg_exec;
   }
   int *h;  // [0..2] state counters, [4..4+S) per-scene iteration counts
   ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
   int *fin = h + 4;
-  const int max_rounds = max_iter / ITER_G + 2;
+  const int max_rounds = max_iter / ITER_G[0] + 2;
   // algorithmic HBM bytes of one iteration of a scene: every 12x12 block of
   // its matrix and of its preconditioner once, plus the 12-vectors read and
   // written by the two kernels (spmv: z, p_old in, p_new, Ap out; update:
@@ -695,12 +699,15 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   bool all = false;
   bool profiled = false;
   for (int round = 0; round < max_rounds && !all; ++round) {
+    // a long replay while the last solve's count says at least that many
+    // iterations remain, else a short one
+    const int gi = ctx->pcg_hint - done >= ITER_G[1] ? 1 : 0;
     hipEvent_t pe = prof_begin(ctx, s);
     profiled = profiled || pe != nullptr;
-    if (exec)
-      HIP_TRY(ctx, hipGraphLaunch(exec, s));
+    if (exec[gi])
+      HIP_TRY(ctx, hipGraphLaunch(exec[gi], s));
     else
-      enqueue(s);
+      enqueue(s, ITER_G[gi]);
     prof_end(ctx, pe, "pcg_round", 0, s);
     HIP_TRY(ctx, hipGetLastError());
     // it_done, k_cur, n_stopped
@@ -718,6 +725,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
     done = now;
   }
   *iters = done;
+  ctx->pcg_hint = done;
   if (profiled && all && !ctx->pending.empty()) {
     // algorithmic bytes of the whole solve, per scene: its iterations times
     // its blocks and vectors (a stopped scene's blocks do no work); booked

@@ -2,17 +2,26 @@
 // 12x12-block system H p = rhs (diagonal blocks per body, off-diagonal
 // blocks per contacting body pair, fixed bodies removed).
 //
-// Two kernels per iteration.  The first forms the search direction
+// Default: one kernel per iteration (Chronopoulos and Gear's recurrences,
+// one reduction point per iteration), with the products B_bc = H_bc P_c
+// formed once per solve.  Its result is then checked against a freshly
+// computed residual by iteration 0 of the two-kernel form below, which
+// carries on for any scene the check rejects (ABD_PCG_CG=0 runs the
+// two-kernel form alone).
+//
+// Two-kernel form.  The first kernel forms the search direction
 // p_new = z + beta p_old on the fly (p is double-buffered, so no block reads
 // a vector another block is writing), multiplies by H (one wave per body)
 // and writes per-block partials of p.Hp; the second updates x, r, z = P r and
-// writes per-block partials of r.z and r.r.  Each kernel starts by folding
-// the previous kernel's partials in a fixed order; every block does the same
-// fold, so all blocks take the same decisions (alpha, beta, stop) without
-// fences, atomics or separate reduction launches, and results are run-to-run
-// reproducible.  Iterations are replayed from captured hipGraphs of ITER_G
-// iterations; once the stop flag is set the remaining kernels return at
-// once, and the host reads the flag once per replay.
+// writes per-block partials of r.z and r.r.
+//
+// In both forms each kernel starts by folding the previous kernel's
+// partials in a fixed order; every block does the same fold, so all blocks
+// take the same decisions (alpha, beta, stop) without fences, atomics or
+// separate reduction launches, and results are run-to-run reproducible.
+// Iterations are replayed from captured hipGraphs of ITER_G iterations; once
+// a scene's stop flag is set its remaining kernels return at once, and the
+// host reads the flags once per replay.
 #include <cstdlib>
 #include <cstring>
 
@@ -505,6 +514,351 @@ __global__ void __launch_bounds__(PB) k_pcg_update(const PcgBlk *blk, const doub
   }
 }
 
+// ------------------------------------------------ one kernel per iteration ----
+// Chronopoulos and Gear's form of preconditioned CG: with u = P r, w = H u,
+// p = u + beta p, s = w + beta s (s = H p), the two inner products of an
+// iteration, gamma = r.u and delta = w.u, come from one reduction:
+//   beta_i = gamma_i / gamma_{i-1};  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1});
+//   x += alpha p_i;  r_{i+1} = r_i - alpha s_i;  u_{i+1} = P r_{i+1};  w_{i+1} = H u_{i+1}.
+// One kernel per iteration folds the previous kernel's partials and forms
+// the products H u_{i+1} of its bodies; the new u of each neighbour is
+// recomputed on the fly from the neighbour's r_i, w_i, s_{i-1} and its
+// preconditioner block with the very arithmetic its owner uses (one helper,
+// fused multiply-adds written out), so every wave sees the same values.
+// r, w, s and the partials alternate between two buffers by the parity of
+// the iteration; per-scene gamma and alpha are stored by parity.
+struct CgScene {
+  double *gam;  // [2S] gamma of the iterations with parity 0 / 1
+  double *alp;  // [2S] alpha, by parity
+  double *bb;   // [S] rhs.rhs
+  int *stop, *it_final;
+};
+struct CgState {
+  int base;  // iteration of the first kernel of a replay
+  int n_stopped;
+  int pad[2];
+};
+
+__device__ __forceinline__ void cg_step(double r, double w, double s_prev, double alpha, double beta, double &s_new,
+                                        double &r_new) {
+  s_new = fma(beta, s_prev, w);
+  r_new = fma(-alpha, s_new, r);
+}
+
+__global__ void k_cg_reset(int S, CgState *st, CgScene sc) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) {
+    st->base = 0;
+    st->n_stopped = 0;
+  }
+  if (s < S) {
+    sc.stop[s] = 0;
+    sc.it_final[s] = 0;
+  }
+}
+
+// r = rhs - H x0 (free bodies; Hx0 NULL: x0 = 0), x = x0, u = P r,
+// p = 0, s_prev = 0
+__global__ void __launch_bounds__(PB) k_cg_init1(const PcgBlk *blk, const uint8_t *fixed, const double *inv,
+                                                const double *rhs, const double *x0, const double *Hx0, double *x,
+                                                double *r, double *u, double *p, double *s_prev) {
+  __shared__ double sr[PBB][12];
+  const PcgBlk bi = blk[blockIdx.x];
+  if (bi.sc < 0) return;
+  const int lb = threadIdx.x / 12, i = threadIdx.x % 12;
+  const int b = bi.first + lb;
+  const bool ok = b < bi.last;
+  double rv = 0.0;
+  if (ok) {
+    const int64_t o = 12 * (int64_t)b + i;
+    const double bv = fixed[b] ? 0.0 : rhs[o];
+    rv = Hx0 && !fixed[b] ? bv - Hx0[o] : bv;
+    x[o] = Hx0 && !fixed[b] ? x0[o] : 0.0;
+    r[o] = rv;
+    p[o] = 0.0;
+    s_prev[o] = 0.0;
+  }
+  sr[lb][i] = rv;
+  __syncthreads();
+  if (ok) {
+    const double *M = inv + 144 * (int64_t)b + 12 * i;
+    double uv = 0.0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) uv = fma(M[j], sr[lb][j], uv);
+    u[12 * (int64_t)b + i] = uv;
+  }
+}
+
+// w_0 = H u_0; partials of gamma_0, delta_0, rho_0 = r.r and rhs.rhs
+__global__ void __launch_bounds__(SWB) k_cg_init2(const PcgBlk *blk, const int2 *ent, const uint8_t *fixed,
+                                                 const double *diag, const double *off, const double *rhs,
+                                                 const double *r, const double *u, double *w, double *part) {
+  __shared__ double sh[SWB / 64];
+  const PcgBlk bi = blk[blockIdx.x];
+  if (bi.sc < 0) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot = lane / 12, i = lane % 12;
+  const int b = bi.first + wv;
+  const bool ok = b < bi.last;
+  const int ea = wv == 0 ? bi.e[0] : (wv == 1 ? bi.e[1] : (wv == 2 ? bi.e[2] : bi.e[3]));
+  const int eb = wv == 0 ? bi.e[1] : (wv == 1 ? bi.e[2] : (wv == 2 ? bi.e[3] : bi.e[4]));
+  const int e0 = ea, E = ok ? eb - ea : 0;
+  int2 my_ent = make_int2(0, 0);
+  if (lane < E) my_ent = ent[e0 + lane];
+  double acc = 0.0;
+  for (int e = slot; e - slot < E; e += 5) {
+    const int kk_s = __shfl(my_ent.x, e & 63, 64), cw_s = __shfl(my_ent.y, e & 63, 64);
+    if (lane < 60 && e < E) {
+      const int2 en = e < 64 ? make_int2(kk_s, cw_s) : ent[e0 + e];
+      const int c = en.y & ((1 << 30) - 1);
+      const bool tr = (en.y >> 30) & 1;
+      const double *rp = en.x < 0 ? diag + 144 * (int64_t)b + 12 * i
+                                  : (tr ? off + 144 * (int64_t)en.x + i : off + 144 * (int64_t)en.x + 12 * i);
+      const int stride = tr ? 12 : 1;
+#pragma unroll
+      for (int j = 0; j < 12; ++j) acc = fma(rp[stride * j], u[12 * (int64_t)c + j], acc);
+    }
+  }
+  double v = acc;
+#pragma unroll
+  for (int q = 1; q < 5; ++q) v += __shfl(acc, (lane + 12 * q) & 63, 64);
+  double g = 0.0, d = 0.0, rr = 0.0, bb = 0.0;
+  if (ok && slot == 0) {
+    const int64_t o = 12 * (int64_t)b + i;
+    const double wv_ = fixed[b] ? 0.0 : v;
+    w[o] = wv_;
+    const double rv = r[o], uv = u[o], bv = fixed[b] ? 0.0 : rhs[o];
+    g = rv * uv;
+    d = wv_ * uv;
+    rr = rv * rv;
+    bb = bv * bv;
+  }
+  g = block_sum(g, sh);
+  d = block_sum(d, sh);
+  rr = block_sum(rr, sh);
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x] = g;
+    part[4 * blockIdx.x + 1] = d;
+    part[4 * blockIdx.x + 2] = rr;
+    part[4 * blockIdx.x + 3] = bb;
+  }
+}
+
+// Per matrix entry (row body b, column body c) the product B_bc = H_bc P_c
+// with the column body's preconditioner block, stored in entry order
+// (144 doubles per entry), so that w = H u = H P r = sum_c B_bc r_c needs
+// the column bodies' residuals only.  One block per row body.
+__global__ void __launch_bounds__(256) k_cg_bmat(int nb, const int64_t *eoff, const int2 *ent, const double *diag,
+                                                const double *off, const double *inv, double *B) {
+  const int b = blockIdx.x;
+  if (b >= nb) return;
+  const int64_t e0 = eoff[b];
+  const int n = (int)(eoff[b + 1] - e0) * 144;
+  for (int t = threadIdx.x; t < n; t += 256) {
+    const int el = t / 144, ij = t % 144, i = ij / 12, j = ij % 12;
+    const int2 en = ent[e0 + el];
+    const int kk = en.x, c = en.y & ((1 << 30) - 1);
+    const bool tr = (en.y >> 30) & 1;
+    const double *rp = kk < 0 ? diag + 144 * (int64_t)b + 12 * i
+                              : (tr ? off + 144 * (int64_t)kk + i : off + 144 * (int64_t)kk + 12 * i);
+    const int stride = tr ? 12 : 1;
+    const double *Mc = inv + 144 * (int64_t)c + j;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc = fma(rp[stride * k], Mc[12 * k], acc);
+    B[144 * (e0 + el) + ij] = acc;
+  }
+}
+
+// Operands of one entry of one lane: the column body's r_k, w_k, s_{k-1}
+// components and row i of B_bc.
+struct CgOps {
+  double r, w, s, B[12];
+};
+__device__ __forceinline__ void cg_fetch(bool live, int c, int64_t eg, int i, const double *Bm, const double *r_in,
+                                         const double *w_in, const double *s_in, CgOps &o) {
+  if (!live) {
+    o.r = o.w = o.s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) o.B[j] = 0.0;
+    return;
+  }
+  const int64_t oc = 12 * (int64_t)c + i;
+  o.r = r_in[oc];
+  o.w = w_in[oc];
+  o.s = s_in[oc];
+  const double *Bi = Bm + 144 * eg + 12 * i;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) o.B[j] = Bi[j];
+}
+
+// The column body's s_k and r_{k+1} (its owner's arithmetic, so that every
+// wave that reads the body computes the same values) and the row product
+// B_bc r_{k+1,c} into acc.
+__device__ __forceinline__ void cg_entry(const CgOps &op, double alpha, double beta, int g0, double &acc,
+                                         double &rn, double &sn) {
+  cg_step(op.r, op.w, op.s, alpha, beta, sn, rn);
+#pragma unroll
+  for (int j = 0; j < 12; ++j) acc = fma(op.B[j], __shfl(rn, (g0 + j) & 63, 64), acc);
+}
+
+// Iteration k = base + jloc of every scene not yet stopped: fold gamma_k,
+// delta_k, rho_k = r_k.r_k, decide the stop, alpha_k and beta_k; then per
+// body p_k, x_{k+1}, s_k, r_{k+1}, u_{k+1} = P r_{k+1} and w_{k+1} =
+// sum_c B_bc r_{k+1,c} with one wave per body (lane = entry slot 0..4, row
+// 0..11, five entries per pass); partials of gamma, delta, rho for the next
+// iteration.  The operands of the first two passes (ten entries) are loaded
+// before the fold; the fold and the closing reduction take one barrier each.
+__global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, const int2 *ent, const uint8_t *fixed,
+                                                const double *Bm, const double *inv, const double *r_in,
+                                                const double *w_in, const double *s_in, double *r_out, double *w_out,
+                                                double *s_out, double *x, double *u, double *p, const double *part_in,
+                                                double *part_out, CgState *st, CgScene scs, double rtol2,
+                                                int max_iter) {
+  __shared__ double shf[SWBB][4], she[SWBB][3];
+  const int k = st->base + jloc;
+  const PcgBlk bi = blk[blockIdx.x];
+  if (bi.sc < 0) return;
+  const int sc = bi.sc;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot = lane / 12, i = lane % 12;
+  const int b = bi.first + wv;
+  const bool ok = b < bi.last;
+  // (explicit selects: a run-time index into the struct would move it to LDS)
+  const int ea = wv == 0 ? bi.e[0] : (wv == 1 ? bi.e[1] : (wv == 2 ? bi.e[2] : bi.e[3]));
+  const int eb = wv == 0 ? bi.e[1] : (wv == 1 ? bi.e[2] : (wv == 2 ? bi.e[3] : bi.e[4]));
+  const int e0 = ea, E = ok ? eb - ea : 0;
+  const int npass = (E + 4) / 5;  // uniform over the wave
+  const int stopped = scs.stop[sc];
+  double pg = 0.0, pd = 0.0, pr = 0.0, pb = 0.0;
+  for (int j = threadIdx.x; j < bi.fold_n; j += SWB) {
+    const double *q = part_in + 4 * (int64_t)(bi.fold_lo + j);
+    pg += q[0];
+    pd += q[1];
+    pr += q[2];
+    if (k == 0) pb += q[3];
+  }
+  int my_c = 0;
+  if (lane < E) my_c = ent[e0 + lane].y & ((1 << 30) - 1);
+  const int64_t oo = 12 * (int64_t)b + i;
+  const double own_x = ok ? x[oo] : 0.0, own_u = ok ? u[oo] : 0.0, own_p = ok ? p[oo] : 0.0;
+  const bool own_fixed = ok && fixed[b];
+  double Mown[12];
+  {
+    const double *Mi = inv + 144 * (int64_t)(ok ? b : 0) + 12 * i;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) Mown[j] = ok ? Mi[j] : 0.0;
+  }
+  // the scene's scalars of iteration k - 1 (parity buffers) and rhs.rhs
+  const double gam_prev = scs.gam[2 * sc + ((k - 1) & 1)], alp_prev = scs.alp[2 * sc + ((k - 1) & 1)];
+  const double bb_prev = scs.bb[sc];
+  if (stopped) return;  // uniform over the block (one scene)
+  CgOps op0, op1;
+  {
+    const int c0 = __shfl(my_c, slot, 64), c1 = __shfl(my_c, slot + 5, 64);
+    cg_fetch(lane < 60 && slot < E, c0, e0 + slot, i, Bm, r_in, w_in, s_in, op0);
+    cg_fetch(lane < 60 && slot + 5 < E, c1, e0 + slot + 5, i, Bm, r_in, w_in, s_in, op1);
+  }
+  pg = wave_sum(pg);
+  pd = wave_sum(pd);
+  pr = wave_sum(pr);
+  pb = wave_sum(pb);
+  if (lane == 0) {
+    shf[wv][0] = pg;
+    shf[wv][1] = pd;
+    shf[wv][2] = pr;
+    shf[wv][3] = pb;
+  }
+  __syncthreads();
+  double gam = 0.0, del = 0.0, rho = 0.0, b0 = 0.0;
+#pragma unroll
+  for (int w = 0; w < SWBB; ++w) {
+    gam += shf[w][0];
+    del += shf[w][1];
+    rho += shf[w][2];
+    b0 += shf[w][3];
+  }
+  // |r| <= rtol |b| with b the right-hand side (x0 may be non-zero)
+  const double bb = k == 0 ? b0 : bb_prev;
+  bool stop = !(bb > 0.0) || rho <= rtol2 * bb || k >= max_iter || gam == 0.0;
+  double beta = 0.0, alpha = 0.0;
+  if (!stop) {
+    beta = k == 0 ? 0.0 : gam / gam_prev;
+    const double den = k == 0 ? del : del - beta * gam / alp_prev;
+    if (den > 0.0)
+      alpha = gam / den;
+    else
+      stop = true;  // p.Hp lost to rounding (or H indefinite): the check that follows decides
+  }
+  if (bi.is_first && threadIdx.x == 0) {
+    scs.gam[2 * sc + (k & 1)] = gam;
+    scs.alp[2 * sc + (k & 1)] = alpha;
+    if (k == 0) scs.bb[sc] = bb;
+    if (stop) {
+      scs.stop[sc] = 1;
+      scs.it_final[sc] = k;
+      atomicAdd(&st->n_stopped, 1);
+    }
+  }
+  if (stop) return;
+  const int g0 = slot * 12;
+  double accw = 0.0, own_r, own_s;
+  cg_entry(op0, alpha, beta, g0, accw, own_r, own_s);  // entry 0 of slot 0 is the body itself
+  // u_{k+1} = P_b r_{k+1} (meaningful on the lanes of slot 0)
+  double own_un = 0.0;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) own_un = fma(Mown[j], __shfl(own_r, j, 64), own_un);
+  if (npass > 1) {
+    double rn, sn;
+    cg_entry(op1, alpha, beta, g0, accw, rn, sn);
+  }
+  for (int pass = 2; pass < npass; ++pass) {
+    const int e = slot + 5 * pass;
+    const int c_s = __shfl(my_c, e & 63, 64);
+    const bool live = lane < 60 && e < E;
+    const int c = !live ? 0 : (e < 64 ? c_s : (ent[e0 + e].y & ((1 << 30) - 1)));
+    cg_fetch(live, c, e0 + e, i, Bm, r_in, w_in, s_in, op1);
+    double rn, sn;
+    cg_entry(op1, alpha, beta, g0, accw, rn, sn);
+  }
+  // per-row sums over the five slots, fixed order
+  double v = accw;
+#pragma unroll
+  for (int q = 1; q < 5; ++q) v += __shfl(accw, (lane + 12 * q) & 63, 64);
+  double g = 0.0, d = 0.0, rr = 0.0;
+  if (ok && slot == 0) {
+    const double pn = fma(beta, own_p, own_u);
+    x[oo] = fma(alpha, pn, own_x);
+    p[oo] = pn;
+    const double wn = own_fixed ? 0.0 : v;
+    r_out[oo] = own_r;
+    s_out[oo] = own_s;
+    u[oo] = own_un;
+    w_out[oo] = wn;
+    g = own_r * own_un;
+    d = wn * own_un;
+    rr = own_r * own_r;
+  }
+  g = wave_sum(g);
+  d = wave_sum(d);
+  rr = wave_sum(rr);
+  if (lane == 0) {
+    she[wv][0] = g;
+    she[wv][1] = d;
+    she[wv][2] = rr;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < SWBB; ++w) t += she[w][threadIdx.x];
+    part_out[4 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_cg_advance(CgState *st, int n) { st->base += n; }
+
 // y = sx H x (plain block SpMV; one wave per body)
 __global__ void __launch_bounds__(SWB) k_bsr_spmv(int nb, const uint8_t *fixed, const double *diag, const double *off,
                                                  const int32_t *keys, const uint32_t *tperm, const int64_t *lo_beg,
@@ -547,6 +901,142 @@ __global__ void __launch_bounds__(SWB) k_bsr_spmv(int nb, const uint8_t *fixed, 
 #pragma unroll
   for (int q = 1; q < 5; ++q) v += __shfl(acc, (lane + 12 * q) & 63, 64);
   if (slot == 0) y[12 * (int64_t)b + i] = fixed[b] ? 0.0 : sx * v;
+}
+
+// The iteration loop of the one-kernel form (set-up shared with op_pcg).
+int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, const double *diag, const double *off,
+             const int32_t *keys, const uint32_t *tv2, const int64_t *lo_beg, const int64_t *hi_beg,
+             const double *inv, const double *rhs, const double *x0, const double *Hx0, double *x_out,
+             const PcgBlk *ublk, int nblk_u, const int32_t *s_scene, const int64_t *s_off, const int32_t *sbo,
+             const int64_t *eoff, const int2 *ent, int nblk_s, double rtol2, int max_iter, int *iters,
+             hipStream_t s) {
+  double *rv[2], *wv[2], *sv[2], *pt[2], *u, *p;
+  PcgBlk *cblk;
+  CgState *st;
+  CgScene scs;
+  ABD_TRY(ws(ctx, "cg_r0", 12 * (size_t)nb, &rv[0], s));
+  ABD_TRY(ws(ctx, "cg_r1", 12 * (size_t)nb, &rv[1], s));
+  ABD_TRY(ws(ctx, "cg_w0", 12 * (size_t)nb, &wv[0], s));
+  ABD_TRY(ws(ctx, "cg_w1", 12 * (size_t)nb, &wv[1], s));
+  ABD_TRY(ws(ctx, "cg_s0", 12 * (size_t)nb, &sv[0], s));
+  ABD_TRY(ws(ctx, "cg_s1", 12 * (size_t)nb, &sv[1], s));
+  ABD_TRY(ws(ctx, "cg_u", 12 * (size_t)nb, &u, s));
+  ABD_TRY(ws(ctx, "cg_p", 12 * (size_t)nb, &p, s));
+  ABD_TRY(ws(ctx, "cg_part0", 4 * (size_t)nblk_s, &pt[0], s));
+  ABD_TRY(ws(ctx, "cg_part1", 4 * (size_t)nblk_s, &pt[1], s));
+  ABD_TRY(ws(ctx, "cg_blk", nblk_s, &cblk, s));
+  double *Bm;
+  ABD_TRY(ws(ctx, "cg_bmat", 144 * ((size_t)nb + 2 * (size_t)n_keys), &Bm, s));
+  ABD_TRY(ws(ctx, "cg_state", 1, &st, s));
+  ABD_TRY(ws(ctx, "cg_s_gam", 2 * (size_t)S, &scs.gam, s));
+  ABD_TRY(ws(ctx, "cg_s_alp", 2 * (size_t)S, &scs.alp, s));
+  ABD_TRY(ws(ctx, "cg_s_bb", S, &scs.bb, s));
+  ABD_TRY(ws(ctx, "cg_s_stop", S, &scs.stop, s));
+  ABD_TRY(ws(ctx, "cg_s_final", S, &scs.it_final, s));
+  // iteration blocks fold their own mapping's partials
+  hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, (int64_t)nblk_s, SWBB, s_scene, s_off,
+                     s_off, sbo, eoff, cblk);
+  hipLaunchKernelGGL(k_cg_reset, dim3(grid_for(S, 256)), dim3(256), 0, s, S, st, scs);
+  hipLaunchKernelGGL(k_cg_bmat, dim3(nb), dim3(256), 0, s, nb, eoff, ent, diag, off, inv, Bm);
+  hipLaunchKernelGGL(k_cg_init1, dim3(nblk_u), dim3(PB), 0, s, ublk, sc->body_fixed, inv, rhs, x0, Hx0, x_out, rv[0],
+                     u, p, sv[0]);
+  hipLaunchKernelGGL(k_cg_init2, dim3(nblk_s), dim3(SWB), 0, s, cblk, ent, sc->body_fixed, diag, off, rhs, rv[0], u,
+                     wv[0], pt[0]);
+  HIP_TRY(ctx, hipGetLastError());
+  // n iterations (n even: the parity of k is that of the local index)
+  auto enqueue = [&](hipStream_t q, int n) {
+    for (int j = 0; j < n; ++j) {
+      const int a = j & 1, o = a ^ 1;
+      hipLaunchKernelGGL(k_cg_iter, dim3(nblk_s), dim3(SWB), 0, q, j, cblk, ent, sc->body_fixed, Bm, inv, rv[a],
+                         wv[a], sv[a], rv[o], wv[o], sv[o], x_out, u, p, pt[a], pt[o], st, scs, rtol2, max_iter);
+    }
+    hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(1), 0, q, st, n);
+  };
+  const char *env = getenv("ABD_PCG_GRAPH");
+  const bool use_graph = !(env && env[0] == '0');
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  if (use_graph) {
+    // every value baked into the captured kernels' arguments is part of the
+    // key (rtol2 by its bit pattern)
+    uint64_t rtol_bits;
+    std::memcpy(&rtol_bits, &rtol2, sizeof(rtol_bits));
+    const std::vector<uintptr_t> key = {
+        (uintptr_t)Bm,       (uintptr_t)off,      (uintptr_t)inv,          (uintptr_t)x_out,      (uintptr_t)u,
+        (uintptr_t)p,        (uintptr_t)rv[0],    (uintptr_t)rv[1],        (uintptr_t)wv[0],      (uintptr_t)wv[1],
+        (uintptr_t)sv[0],    (uintptr_t)sv[1],    (uintptr_t)pt[0],        (uintptr_t)pt[1],      (uintptr_t)cblk,
+        (uintptr_t)ent,      (uintptr_t)st,       (uintptr_t)sc->body_fixed,
+        (uintptr_t)nblk_s,   (uintptr_t)max_iter, (uintptr_t)rtol_bits,    (uintptr_t)scs.gam,    (uintptr_t)scs.alp,
+        (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)1};
+    if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    for (int gi = 0; gi < 2; ++gi) {
+      if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {
+        if (ctx->pcg_exec[gi]) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec[gi]));
+        ctx->pcg_exec[gi] = nullptr;
+        hipGraph_t g = nullptr;
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        enqueue(ctx->capture_stream, ITER_G[gi]);
+        HIP_TRY(ctx, hipStreamEndCapture(ctx->capture_stream, &g));
+        HIP_TRY(ctx, hipGraphInstantiate(&ctx->pcg_exec[gi], g, nullptr, nullptr, 0));
+        HIP_TRY(ctx, hipGraphDestroy(g));
+        ctx->pcg_key[gi] = key;
+      }
+      exec[gi] = ctx->pcg_exec[gi];
+    }
+  }
+  int *h;  // [0..1] base, n_stopped; [4..4+S) per-scene iteration counts
+  ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
+  int *fin = h + 4;
+  const int max_rounds = max_iter / ITER_G[0] + 2;
+  int done = 0;
+  bool all = false;
+  bool profiled = false;
+  for (int round = 0; round < max_rounds && !all; ++round) {
+    // a long replay while the last solve's count says at least that many
+    // iterations remain, else a short one
+    const int gi = ctx->pcg_hint - done >= ITER_G[1] ? 1 : 0;
+    hipEvent_t pe = prof_begin(ctx, s);
+    profiled = profiled || pe != nullptr;
+    if (exec[gi])
+      HIP_TRY(ctx, hipGraphLaunch(exec[gi], s));
+    else
+      enqueue(s, ITER_G[gi]);
+    prof_end(ctx, pe, "pcg_round", 0, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(h, st, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    all = h[1] >= S;
+    int now = h[0];
+    if (all) {
+      // iterations: the largest count over the scenes
+      HIP_TRY(ctx, hipMemcpyAsync(fin, scs.it_final, S * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      now = 0;
+      for (int j = 0; j < S; ++j) now = fin[j] > now ? fin[j] : now;
+    }
+    done = now;
+  }
+  *iters = done;
+  ctx->pcg_hint = done;
+  if (profiled && all && !ctx->pending.empty()) {
+    // algorithmic bytes of the whole solve, per scene: its iterations times
+    // its matrix and preconditioner blocks once and the 12-vectors of the
+    // iteration kernel (r, w, s, x, u, p in; r, w, s, x, u, p out)
+    std::vector<int32_t> hs(S + 1);
+    std::vector<int64_t> hl(nb + 1);
+    HIP_TRY(ctx, hipMemcpy(hs.data(), sbo, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(hl.data(), lo_beg, (nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    int64_t total = 0;
+    for (int j = 0; j < S; ++j) {
+      const int64_t nbs = hs[j + 1] - hs[j], nks = hl[hs[j + 1]] - hl[hs[j]];
+      total += (int64_t)fin[j] * ((2 * nbs + nks) * 1152 + 12 * 96 * nbs);
+    }
+    ctx->pending.back().units = total;
+  }
+  (void)n_keys;
+  (void)keys;
+  (void)tv2;
+  (void)hi_beg;
+  return ABD_OK;
 }
 
 }  // namespace
@@ -641,10 +1131,46 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
                        lo_beg, hi_beg, x0, 1.0, Ap);
     Hx0 = Ap;
   }
-  hipLaunchKernelGGL(k_pcg_init, dim3(nblk_u), dim3(PB), 0, s, u_scene, u_off, sbo, sc->body_fixed, inv, rhs, x0, Hx0,
-                     x_out, r, z, pa, part2);
-  HIP_TRY(ctx, hipGetLastError());
   const double rtol2 = rtol * rtol;
+  const char *cg_env = getenv("ABD_PCG_CG");
+  int it0 = 0;
+  const bool one_kernel = !(cg_env && cg_env[0] == '0');
+  if (one_kernel) {
+    ABD_TRY(cg_solve(ctx, sc, S, nb, n_keys, diag, off, keys, tv2, lo_beg, hi_beg, inv, rhs, x0, Hx0, x_out, ublk,
+                     nblk_u, s_scene, s_off, sbo, eoff, ent, nblk_s, rtol2, max_iter, &it0, s));
+    // The one-reduction recurrences may stop on a recursive residual that
+    // has drifted from rhs - H x (w is formed as (H P) r rather than
+    // H (P r), and p.Hp as a difference that cancels near the attainable
+    // floor), so the iterate is checked against a freshly computed
+    // residual: iteration 0 of the two-reduction form, started from it,
+    // stops every scene that meets the tolerance and carries on with the
+    // others.
+    hipLaunchKernelGGL(k_bsr_spmv, dim3(grid_for(nb, SWBB)), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2,
+                       lo_beg, hi_beg, x_out, 1.0, Ap);
+    x0 = x_out;
+    Hx0 = Ap;
+  }
+  // (after the check's iteration, which runs outside the captured graphs,
+  // the graphs must again start from p in pa)
+  hipLaunchKernelGGL(k_pcg_init, dim3(nblk_u), dim3(PB), 0, s, u_scene, u_off, sbo, sc->body_fixed, inv, rhs, x0, Hx0,
+                     x_out, r, z, one_kernel ? pb : pa, part2);
+  HIP_TRY(ctx, hipGetLastError());
+  if (one_kernel) {
+    hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, s, sblk, ent, sc->body_fixed, diag, off, pb, z, pa, Ap,
+                       part2, part, st, scs, rtol2, max_iter);
+    hipLaunchKernelGGL(k_pcg_update, dim3(nblk_u), dim3(PB), 0, s, ublk, inv, pa, Ap, x_out, r, z, part, part2, st,
+                       scs, err);
+    HIP_TRY(ctx, hipGetLastError());
+    int *hv;
+    ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&hv)));
+    HIP_TRY(ctx, hipMemcpyAsync(hv, st, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (hv[2] >= S) {
+      *iters = it0;
+      ctx->pcg_hint = it0;
+      return ABD_OK;
+    }
+  }
   // n iterations: p alternates pa -> pb -> pa ... (n is even)
   auto enqueue = [&](hipStream_t q, int n) {
     for (int k = 0; k < n; ++k) {
@@ -698,10 +1224,12 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   int done = 0;
   bool all = false;
   bool profiled = false;
+  // (after the one-kernel form, the iterations left are few and unknown)
+  const int hint = one_kernel ? 0 : ctx->pcg_hint;
   for (int round = 0; round < max_rounds && !all; ++round) {
     // a long replay while the last solve's count says at least that many
     // iterations remain, else a short one
-    const int gi = ctx->pcg_hint - done >= ITER_G[1] ? 1 : 0;
+    const int gi = hint - done >= ITER_G[1] ? 1 : 0;
     hipEvent_t pe = prof_begin(ctx, s);
     profiled = profiled || pe != nullptr;
     if (exec[gi])
@@ -724,8 +1252,8 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
     }
     done = now;
   }
-  *iters = done;
-  ctx->pcg_hint = done;
+  *iters = it0 + done;
+  ctx->pcg_hint = one_kernel ? it0 : done;
   if (profiled && all && !ctx->pending.empty()) {
     // algorithmic bytes of the whole solve, per scene: its iterations times
     // its blocks and vectors (a stopped scene's blocks do no work); booked

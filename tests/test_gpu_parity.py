@@ -332,6 +332,33 @@ def test_orthogonality_inertia_parity(abd, ctx):
     np.testing.assert_allclose(qt2, oracle.q_tilde(S, q, qd, P), rtol=0, atol=1e-15)
 
 
+def test_orthogonality_projection_deformed(abd, ctx):
+    # projected orthogonality Hessians far from rotations: singular values
+    # below 1/sqrt(3) (negative stretch modes), repeated singular values,
+    # exact rotations (zero twist modes), reflections, and a nearly singular
+    # A, against the oracle's numerical eigen-projection
+    S, P = sg.icosphere_box(n_side=3, n_layers=2)
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    _, vol = oracle.mass_properties(S)
+    rng = np.random.default_rng(5)
+    sigmas = [(0.3, 1.0, 1.5), (0.5, 0.5, 1.2), (1.0, 1.0, 1.0), (0.55, 0.6, 0.58), (1e-5, 1.0, 1.0),
+              (0.9, 1.1, -1.0), (2.0, 2.0, 2.0), (0.98, 1.01, 1.02)]
+    q = S["q0"].copy()
+    free = np.flatnonzero(S["body_fixed"] == 0)
+    for n, b in enumerate(free):
+        Q1, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        Q2, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        q[b, 3:] = (Q1 @ np.diag(sigmas[n % len(sigmas)]) @ Q2.T).ravel()
+    e, g, D = ctx.orthogonality(sc, P, _dev(q), P["dt"] ** 2, project=True)
+    oe, og, oD = oracle.orthogonality(S, vol, q, P, project=True)
+    assert e.item() == pytest.approx(oe, rel=1e-12)
+    Dg = D.cpu().numpy()
+    for b in free:
+        ref = oD[b]
+        np.testing.assert_allclose(Dg[b], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
 # ------------------------------------------------------ a9 PCG solve ----
 
 @pytest.mark.parametrize("name,S,P", SCENES[:3] + SCENES[4:], ids=[s[0] for s in SCENES[:3] + SCENES[4:]])

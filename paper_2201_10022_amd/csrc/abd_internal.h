@@ -167,6 +167,10 @@ int op_friction_lag_vjp(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm
                         const double *x, const double *l, double *out, hipStream_t s);
 // reads and clears the device error flags of the last operations (syncs)
 int op_read_err(abd_ctx *ctx, hipStream_t s);
+// the error flag copied to pinned host memory (enqueued only), and its
+// translation into an error code (clears the flag)
+int err_enqueue(abd_ctx *ctx, int *h_err, hipStream_t s);
+int err_check(abd_ctx *ctx, int e, hipStream_t s);
 // the friction state of the current time step (null when none is set)
 int op_friction_state(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, FrictionSet *fr, bool *active,
                       hipStream_t s);

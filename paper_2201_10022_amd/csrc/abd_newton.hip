@@ -45,12 +45,23 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 }  // namespace
 
 int op_read_err(abd_ctx *ctx, hipStream_t s) {
-  int *err, *h;
-  ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
+  int *h;
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
-  HIP_TRY(ctx, hipMemcpyAsync(h, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  ABD_TRY(err_enqueue(ctx, h, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  const int e = h[0];
+  return err_check(ctx, h[0], s);
+}
+
+int err_enqueue(abd_ctx *ctx, int *h_err, hipStream_t s) {
+  int *err;
+  ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
+  HIP_TRY(ctx, hipMemcpyAsync(h_err, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  return ABD_OK;
+}
+
+int err_check(abd_ctx *ctx, int e, hipStream_t s) {
+  int *err;
+  ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
   if (e) HIP_TRY(ctx, hipMemsetAsync(err, 0, sizeof(int), s));
   if (e & 1) return abd_fail(ctx, ABD_E_INTERSECT, "pair at zero distance");
   if (e & 2) return abd_fail(ctx, ABD_E_INVALID, "pair's body pair missing from the off-diagonal keys");
@@ -77,6 +88,14 @@ __global__ void k_axpy_scene(int nb, const int32_t *body_scene, const double *a,
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 12 * nb) return;
   out[i] = a[i] + alpha[body_scene[i / 12]] * b[i];
+}
+
+// trial step lengths alpha_ccd 2^-t, t < n (0 for scenes already done)
+__global__ void k_ls_trials(int S, int n, const uint8_t *done, const double *a_ccd, double *a_tr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S * n) return;
+  const int j = i % S, t = i / S;
+  a_tr[i] = done[j] ? 0.0 : ldexp(a_ccd[j], -t);
 }
 
 // per-scene E(q) over the given (swept) candidates into e_dev [S],
@@ -118,11 +137,13 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(ws(ctx, "nt_e", 4, &e, s));
   ABD_TRY(ws(ctx, "nt_sv", 2 * (size_t)S, &sv, s));
   ABD_TRY(ws(ctx, "nt_alpha", (size_t)LS_BATCH * S, &alpha_dev, s));
-  double *e_sc;
-  ABD_TRY(ws(ctx, "nt_escene", (size_t)LS_BATCH * S, &e_sc, s));
-  // host staging: done flags, per-scene disp / alpha / E0 / E1
+  double *e_sc, *a_ccd;  // e_sc: E0 [S], then the trials' energies [LS_BATCH][S]
+  ABD_TRY(ws(ctx, "nt_escene", (size_t)(LS_BATCH + 1) * S, &e_sc, s));
+  ABD_TRY(ws(ctx, "nt_accd", S, &a_ccd, s));
+  // host staging: error flag, done flags, per-scene disp / alpha / E0 / E1
   double *h;
   ABD_TRY(pinned_get_nt(ctx, sizeof(double) * (8 + (4 + 2 * (size_t)LS_BATCH) * S), reinterpret_cast<void **>(&h)));
+  int *h_err = reinterpret_cast<int *>(h);
   double *h_disp = h + 8, *h_alpha = h_disp + S, *h_e0 = h_alpha + S, *h_e1 = h_e0 + S;  // h_e1 [LS_BATCH][S]
   double *h_atr = h_e1 + (size_t)LS_BATCH * S;                                          // [LS_BATCH][S]
   uint8_t *h_done = reinterpret_cast<uint8_t *>(h_atr + (size_t)LS_BATCH * S);
@@ -164,7 +185,6 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, e, g, diag, 1, s));
   int64_t nap = 0, nae = 0;
   ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 1, &nap, &nae, s, fr));
-  ABD_TRY(op_read_err(ctx, s));
   st->t_barrier_ms += ms_since(t0);
   st->n_active_pt = nap;
   st->n_active_ee = nae;
@@ -175,13 +195,17 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(ws(ctx, "nt_rhs", n12, &rhs, s));
   hipLaunchKernelGGL(k_neg_masked, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, done_dev, g, rhs);
   int its = 0;
+  // (errors of the assembly and the solve are read with the displacement:
+  // a failed assembly or block inverse leaves non-finite values that stop
+  // the solve at once)
   ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s));
-  ABD_TRY(op_read_err(ctx, s));
   st->pcg_iters = its;
   st->t_solve_ms += ms_since(t0);
   ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, sv, s));
   HIP_TRY(ctx, hipMemcpyAsync(h_disp, sv, S * sizeof(double), hipMemcpyDeviceToHost, s));
+  ABD_TRY(err_enqueue(ctx, h_err, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
+  ABD_TRY(err_check(ctx, h_err[0], s));
   double dmax = 0.0;
   int n_active = 0;
   for (int j = 0; j < S; ++j) {
@@ -219,8 +243,29 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->t_candidates_ms += ms_since(t0);
   t0 = std::chrono::steady_clock::now();
   hipLaunchKernelGGL(k_sub, dim3(grid_for(3 * nv, 256)), dim3(256), 0, s, 3 * nv, x1, x, dx);
-  ABD_TRY(op_ccd(ctx, sc, prm, x, dx, spt, nspt, see, nsee, nullptr, nullptr, alpha_dev, s));
-  HIP_TRY(ctx, hipMemcpyAsync(h_alpha, alpha_dev, S * sizeof(double), hipMemcpyDeviceToHost, s));
+  ABD_TRY(op_ccd(ctx, sc, prm, x, dx, spt, nspt, see, nsee, nullptr, nullptr, a_ccd, s));
+
+  // backtracking line search, per scene: the trial step lengths
+  // alpha 2^-j are evaluated in batches of K (K from the last iteration's
+  // halvings) with one synchronisation per batch; each scene takes the
+  // first trial that does not raise its energy, exactly as one-by-one
+  // halving would.  E(q) and the first batch (its step lengths formed on
+  // the device from the CCD bound) are enqueued behind the CCD, so one
+  // synchronisation brings the bound, E(q) and the first batch's energies.
+  ABD_TRY(energy_enqueue(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, fr, e_sc, s));
+  int K = ctx->ls_hint + 1;
+  K = K < 1 ? 1 : (K > LS_BATCH ? LS_BATCH : K);
+  const int kb0 = K <= prm->max_ls ? K : (prm->max_ls > 0 ? prm->max_ls : 0);
+  if (kb0 > 0) {
+    hipLaunchKernelGGL(k_ls_trials, dim3(grid_for(kb0 * S, 256)), dim3(256), 0, s, S, kb0, done_dev, a_ccd, alpha_dev);
+    for (int t = 0; t < kb0; ++t) {
+      hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q,
+                         alpha_dev + (size_t)t * S, p, qa);
+      ABD_TRY(energy_enqueue(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e_sc + (size_t)(t + 1) * S, s));
+    }
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(h_alpha, a_ccd, S * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(h_e0, e_sc, (size_t)(kb0 + 1) * S * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   st->t_ccd_ms += ms_since(t0);
   double amin = 1.0;
@@ -229,35 +274,26 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     else amin = h_alpha[j] < amin ? h_alpha[j] : amin;
   }
   st->alpha_ccd = amin;
-
-  // backtracking line search, per scene: the trial step lengths
-  // alpha 2^-j are evaluated in batches of K (K from the last iteration's
-  // halvings) with one synchronisation per batch; each scene takes the
-  // first trial that does not raise its energy, exactly as one-by-one
-  // halving would
-  ABD_TRY(energy_enqueue(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, fr, e_sc, s));
-  HIP_TRY(ctx, hipMemcpyAsync(h_e0, e_sc, S * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
   int k = 0;
   int max_halvings = 0;
   std::vector<int> halv(S, 0);
   std::vector<uint8_t> acc(S, 0);
   for (int j = 0; j < S; ++j) acc[j] = h_done[j];
-  int K = ctx->ls_hint + 1;
-  K = K < 1 ? 1 : (K > LS_BATCH ? LS_BATCH : K);
   bool all_acc = false;
   while (k < prm->max_ls && !all_acc) {
-    const int kb = k + K <= prm->max_ls ? K : prm->max_ls - k;
-    for (int t = 0; t < kb; ++t)
-      for (int j = 0; j < S; ++j) h_atr[(size_t)t * S + j] = acc[j] ? h_alpha[j] : std::ldexp(h_alpha[j], -t);
-    HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_atr, (size_t)kb * S * sizeof(double), hipMemcpyHostToDevice, s));
-    for (int t = 0; t < kb; ++t) {
-      hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q,
-                         alpha_dev + (size_t)t * S, p, qa);
-      ABD_TRY(energy_enqueue(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e_sc + (size_t)t * S, s));
+    const int kb = k == 0 ? kb0 : (k + K <= prm->max_ls ? K : prm->max_ls - k);
+    if (k > 0) {
+      for (int t = 0; t < kb; ++t)
+        for (int j = 0; j < S; ++j) h_atr[(size_t)t * S + j] = acc[j] ? h_alpha[j] : std::ldexp(h_alpha[j], -t);
+      HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_atr, (size_t)kb * S * sizeof(double), hipMemcpyHostToDevice, s));
+      for (int t = 0; t < kb; ++t) {
+        hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q,
+                           alpha_dev + (size_t)t * S, p, qa);
+        ABD_TRY(energy_enqueue(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e_sc + (size_t)(t + 1) * S, s));
+      }
+      HIP_TRY(ctx, hipMemcpyAsync(h_e1, e_sc + S, (size_t)kb * S * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
     }
-    HIP_TRY(ctx, hipMemcpyAsync(h_e1, e_sc, (size_t)kb * S * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
     all_acc = true;
     for (int j = 0; j < S; ++j) {
       if (acc[j]) continue;
@@ -274,6 +310,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
         all_acc = false;
       }
     }
+    if (kb <= 0) break;
     k += kb;
   }
   if (!all_acc) return abd_fail(ctx, ABD_E_LINESEARCH, "line search found no decrease");

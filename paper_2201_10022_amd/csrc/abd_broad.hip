@@ -212,42 +212,78 @@ __global__ void k_sub_tiles(int64_t nbp, const int32_t *list_len, int64_t *tiles
   }
 }
 
+// (sub-problem, tile index within it) of every tile
+__global__ void k_tile_sub(int64_t n_sub, const int64_t *cnt, const int64_t *off, int2 *tile_sub) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_sub) return;
+  const int64_t o = off[j];
+  for (int64_t t = 0; t < cnt[j]; ++t) tile_sub[o + t] = make_int2((int)j, (int)t);
+}
+
 // One wave per tile of TROWS rows x all columns.  WRITE=0 counts the
 // passing tests of the tile, WRITE=1 writes them row-major at the tile's
-// offset.  is_ee selects the sub-problem family.
+// offset.  is_ee selects the sub-problem family.  The tile's row boxes
+// (one per lane) and the lane's boxes of the first CPRE column chunks are
+// loaded up front, so the row loop runs on registers and shuffles; columns
+// beyond CPRE chunks are loaded in the loop.
+constexpr int CPRE = 8;
 template <int WRITE>
-__global__ void __launch_bounds__(64) k_pair_tiles(int is_ee, int64_t n_sub, const int64_t *sub_tile_off,
-                                                   int64_t n_tiles, const int64_t *list_start,
-                                                   const int32_t *list_len, const int32_t *lists,
-                                                   const double *row_boxes, const double *col_boxes,
-                                                   int64_t *tile_cnt, const int64_t *tile_off, int32_t *out) {
+__global__ void __launch_bounds__(64) k_pair_tiles(int is_ee, const int2 *tile_sub, int64_t n_tiles,
+                                                   const int64_t *list_start, const int32_t *list_len,
+                                                   const int32_t *lists, const double *row_boxes,
+                                                   const double *col_boxes, int64_t *tile_cnt, const int64_t *tile_off,
+                                                   int32_t *out) {
   const int64_t tile = blockIdx.x;
   if (tile >= n_tiles) return;
-  // sub-problem owning the tile: last s with sub_tile_off[s] <= tile
-  int64_t lo = 0, hi = n_sub - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (sub_tile_off[mid] <= tile)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const int64_t s = lo;
+  const int2 ts = tile_sub[tile];  // (sub-problem, tile within it)
+  const int64_t s = ts.x;
   const int64_t p = is_ee ? s : s / 2;
   const int li = is_ee ? 4 : 2 * (int)(s % 2);
   const int64_t rstart = list_start[6 * p + li], cstart = list_start[6 * p + li + 1];
   const int nr = list_len[6 * p + li], nc = list_len[6 * p + li + 1];
-  const int r0 = (int)(tile - sub_tile_off[s]) * TROWS;
+  const int r0 = ts.y * TROWS;
   const int r1 = min(nr, r0 + TROWS);
   const int lane = threadIdx.x;
+  const int nch = (nc + 63) / 64;
+  // row r0 + lane (lanes < TROWS) and the lane's first CPRE column chunks
+  int my_rp = 0;
+  double my_rb[6];
+  if (r0 + lane < r1) my_rp = lists[rstart + r0 + lane];
+  int cpv[CPRE];
+  double cb[CPRE][6];
+#pragma unroll
+  for (int k = 0; k < CPRE; ++k) {
+    const int c = 64 * k + lane;
+    cpv[k] = c < nc ? lists[cstart + c] : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) my_rb[i] = r0 + lane < r1 ? row_boxes[6 * (int64_t)my_rp + i] : 0.0;
+#pragma unroll
+  for (int k = 0; k < CPRE; ++k)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cb[k][i] = cpv[k] >= 0 ? col_boxes[6 * (int64_t)cpv[k] + i] : 0.0;
   int64_t pos = WRITE ? tile_off[tile] : 0;
   int64_t cnt = 0;
   for (int r = r0; r < r1; ++r) {
-    const int rp = lists[rstart + r];
+    const int src = r - r0;
+    const int rp = __shfl(my_rp, src, 64);
     double rb[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) rb[i] = row_boxes[6 * (int64_t)rp + i];
-    for (int c0 = 0; c0 < nc; c0 += 64) {
+    for (int i = 0; i < 6; ++i) rb[i] = __shfl(my_rb[i], src, 64);
+#pragma unroll
+    for (int k = 0; k < CPRE; ++k) {
+      if (k < nch) {  // uniform over the wave
+        const bool ok = cpv[k] >= 0 && box_overlap(rb, cb[k]);
+        const unsigned long long m = __ballot(ok);
+        if (WRITE && ok) {
+          const int64_t o = pos + cnt + __popcll(m & ((1ull << lane) - 1ull));
+          out[2 * o] = rp;
+          out[2 * o + 1] = cpv[k];
+        }
+        cnt += __popcll(m);
+      }
+    }
+    for (int c0 = 64 * CPRE; c0 < nc; c0 += 64) {
       const int c = c0 + lane;
       int cp = 0;
       bool ok = false;
@@ -347,12 +383,19 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_opt", ntile_pt + 1, &opt, s));
   ABD_TRY(ws(ctx, "bp_oee", ntile_ee + 1, &oee, s));
   ABD_TRY(ws(ctx, "bp_otot", 2, &otot, s));
-  if (ntile_pt)
-    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, 2 * nbp, tpt_off, ntile_pt,
-                       lstart, llen, lists, vbox, tbox, cpt, nullptr, nullptr);
-  if (ntile_ee)
-    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, nbp, tee_off, ntile_ee, lstart,
-                       llen, lists, ebox, ebox, cee, nullptr, nullptr);
+  int2 *tsub_pt, *tsub_ee;
+  ABD_TRY(ws(ctx, "bp_tsub_pt", ntile_pt + 1, &tsub_pt, s));
+  ABD_TRY(ws(ctx, "bp_tsub_ee", ntile_ee + 1, &tsub_ee, s));
+  if (ntile_pt) {
+    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(2 * nbp, 256)), dim3(256), 0, s, 2 * nbp, tpt, tpt_off, tsub_pt);
+    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, tsub_pt, ntile_pt, lstart, llen,
+                       lists, vbox, tbox, cpt, nullptr, nullptr);
+  }
+  if (ntile_ee) {
+    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, tee, tee_off, tsub_ee);
+    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, tsub_ee, ntile_ee, lstart, llen,
+                       lists, ebox, ebox, cee, nullptr, nullptr);
+  }
   ABD_TRY(scan_exclusive_i64(ctx, cpt, opt, ntile_pt, otot, s));
   ABD_TRY(scan_exclusive_i64(ctx, cee, oee, ntile_ee, otot + 1, s));
   HIP_TRY(ctx, hipMemcpyAsync(hbuf, otot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -364,11 +407,11 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, tee_name.c_str(), 2 * (*n_ee) + 2, ee_out, s));
   hipEvent_t pe = prof_begin(ctx, s);
   if (ntile_pt && *n_pt)
-    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, 2 * nbp, tpt_off, ntile_pt,
-                       lstart, llen, lists, vbox, tbox, nullptr, opt, *pt_out);
+    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, tsub_pt, ntile_pt, lstart, llen,
+                       lists, vbox, tbox, nullptr, opt, *pt_out);
   if (ntile_ee && *n_ee)
-    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, nbp, tee_off, ntile_ee, lstart,
-                       llen, lists, ebox, ebox, nullptr, oee, *ee_out);
+    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, tsub_ee, ntile_ee, lstart, llen,
+                       lists, ebox, ebox, nullptr, oee, *ee_out);
   prof_end(ctx, pe, "pair_tiles_write", ntile_pt + ntile_ee, s);
   return abd_hip_check(ctx, hipGetLastError(), "candidates");
 }

@@ -135,18 +135,18 @@ int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n,
   return ABD_OK;
 }
 
-int sort_pairs_u32(abd_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, hipStream_t s) {
+int sort_pairs_u32(abd_ctx *ctx, uint32_t **keys, uint32_t **vals, int64_t n, int key_bits, hipStream_t s) {
   if (n <= 1) return ABD_OK;
   uint32_t *k2, *v2;
   ABD_TRY(ws(ctx, "sort_k2", n, &k2, s));
   ABD_TRY(ws(ctx, "sort_v2", n, &v2, s));
   size_t tmp_bytes = 0;
-  HIP_TRY(ctx, rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, k2, vals, v2, (size_t)n, 0, key_bits, s));
+  HIP_TRY(ctx, rocprim::radix_sort_pairs(nullptr, tmp_bytes, *keys, k2, *vals, v2, (size_t)n, 0, key_bits, s));
   void *tmp = nullptr;
   ABD_TRY(ws_get(ctx, "sort_tmp", tmp_bytes + 16, &tmp, s));
-  HIP_TRY(ctx, rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, k2, vals, v2, (size_t)n, 0, key_bits, s));
-  HIP_TRY(ctx, hipMemcpyAsync(keys, k2, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-  HIP_TRY(ctx, hipMemcpyAsync(vals, v2, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(ctx, rocprim::radix_sort_pairs(tmp, tmp_bytes, *keys, k2, *vals, v2, (size_t)n, 0, key_bits, s));
+  *keys = k2;
+  *vals = v2;
   return ABD_OK;
 }
 

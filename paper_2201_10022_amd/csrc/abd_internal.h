@@ -97,8 +97,10 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 // Exclusive prefix sum of n int64 values (in != out allowed, or in-place);
 // total (device, may be NULL) receives the sum.
 int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s);
-// Stable sort of (key, value) pairs by key (keys in [0, 2^key_bits)).
-int sort_pairs_u32(abd_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, hipStream_t s);
+// Stable sort of (key, value) pairs by key (keys in [0, 2^key_bits));
+// *keys and *vals then point to the sorted arrays (context workspace, valid
+// until the next sort).
+int sort_pairs_u32(abd_ctx *ctx, uint32_t **keys, uint32_t **vals, int64_t n, int key_bits, hipStream_t s);
 
 // ----------------------------------------------------- pair records ----
 // Local record of a pair whose 12x12 Hessian and 12-gradient are assembled

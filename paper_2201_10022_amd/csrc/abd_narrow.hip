@@ -404,7 +404,7 @@ int op_assemble(abd_ctx *ctx, const abd_scene *sc, int64_t n, const PairInfo *in
   ABD_TRY(ws(ctx, "br_rval", nrec, &rval, s));
   hipLaunchKernelGGL(k_records, dim3(grid_for(n, 256)), dim3(256), 0, s, n, info, sc->body_fixed, nb, keys, n_keys,
                      rkey, rval, off != nullptr ? 1 : 0, err);
-  ABD_TRY(sort_pairs_u32(ctx, rkey, rval, nrec, 32, s));
+  ABD_TRY(sort_pairs_u32(ctx, &rkey, &rval, nrec, 32, s));
   int64_t *bstart, *nchunk, *choff, *nch_tot;
   ABD_TRY(ws(ctx, "br_bstart", nblocks + 1, &bstart, s));
   ABD_TRY(ws(ctx, "br_nchunk", nblocks + 1, &nchunk, s));

@@ -45,12 +45,16 @@ __global__ void __launch_bounds__(64) k_body_mass(int nb, const int32_t *tri_off
 
 // x_k = p + A xbar_k, each component as p_i + ((a_i0 xb0 + a_i1 xb1) + a_i2 xb2)
 // with contraction off: bit-identical to any IEEE evaluation in this order.
+// (grid.y > 1: one map per trial, q and x advanced by qstride and 3 nv)
 __global__ void __launch_bounds__(256) k_vertex_map(int nv, const double *__restrict__ xbar,
                                                     const int32_t *__restrict__ vert_body,
-                                                    const double *__restrict__ q, double *__restrict__ x) {
+                                                    const double *__restrict__ q, double *__restrict__ x,
+                                                    int64_t qstride = 0) {
 #pragma clang fp contract(off)
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nv) return;
+  q += blockIdx.y * qstride;
+  x += blockIdx.y * 3 * (int64_t)nv;
   const double *qb = q + 12 * (int64_t)vert_body[k];
   const double xb0 = xbar[3 * k], xb1 = xbar[3 * k + 1], xb2 = xbar[3 * k + 2];
 #pragma unroll
@@ -280,6 +284,9 @@ __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed,
                                                   double *diag) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
+  // energy-only trials (grid.y > 1): trial t's q at q + 12 nb t, energies at e_out + nb t
+  q += blockIdx.y * 12 * (int64_t)nb;
+  e_out += blockIdx.y * (int64_t)nb;
   if (fixed[b]) {
     e_out[b] = 0.0;
     return;
@@ -407,6 +414,28 @@ int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
 int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
                    double *energy, hipStream_t s) {
   return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, energy, nullptr, nullptr, s);
+}
+
+int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int n_trials, double *x,
+                         hipStream_t s) {
+  if (sc->n_verts <= 0 || n_trials <= 0) return ABD_OK;
+  hipLaunchKernelGGL(k_vertex_map, dim3(grid_for(sc->n_verts, 256), n_trials), dim3(256), 0, s, sc->n_verts, sc->xbar,
+                     sc->vert_body, q, x, 12 * (int64_t)sc->n_bodies);
+  return abd_hip_check(ctx, hipGetLastError(), "k_vertex_map");
+}
+
+int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
+                          const double *qt, int n_trials, double *energy, hipStream_t s) {
+  const int nb = sc->n_bodies;
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  if (nb <= 0 || n_trials <= 0) return ABD_OK;
+  if (!sc->mass || !sc->volume) return abd_fail(ctx, ABD_E_INVALID, "scene mass or volume is NULL");
+  double *eb;
+  ABD_TRY(ws(ctx, "body_e_tr", (size_t)nb * n_trials, &eb, s));
+  hipLaunchKernelGGL(k_body_terms, dim3(grid_for(nb, 64), n_trials), dim3(64), 0, s, nb, sc->body_fixed, sc->mass,
+                     sc->volume, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, 0, eb, nullptr, nullptr);
+  HIP_TRY(ctx, hipGetLastError());
+  return seg_sum_trials(ctx, eb, nb, nb, sc->body_scene, n_trials, S, energy, s);
 }
 
 int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,

@@ -284,7 +284,76 @@ __global__ void __launch_bounds__(SB) k_seg_reduce(const double *vals, const int
       out[s] = accumulate ? fmax(out[s], r) : r;
   }
 }
+
+// Trial-major values (trial t's items at vals + t * stride): one block per
+// (trial, scene) sums the scene's items in fixed order into out[t S + s].
+__global__ void __launch_bounds__(SB) k_seg_reduce_trials(const double *vals, int64_t stride, int64_t n,
+                                                          const int32_t *keys, int S, double *out) {
+  __shared__ double sh[SB / 64];
+  const int t = blockIdx.x / S, s = blockIdx.x % S;
+  const int64_t lo = lower_bound_i32(keys, n, s), hi = lower_bound_i32(keys, n, s + 1);
+  const double *v = vals + (int64_t)t * stride;
+  double a = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += SB) a += v[i];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < SB / 64; ++w) r += sh[w];
+    out[blockIdx.x] += r;
+  }
+}
+
+// One scene: per trial, blocks of TRB*4 items into partials, then one
+// block per trial folds them (both in fixed order).
+constexpr int TRB = 256;
+__global__ void __launch_bounds__(TRB) k_trial_pass(const double *vals, int64_t stride, int64_t n, double *part) {
+  __shared__ double sh[TRB / 64];
+  const double *v = vals + (int64_t)blockIdx.y * stride;
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TRB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TRB) a += v[i];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < TRB / 64; ++w) r += sh[w];
+    part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = r;
+  }
+}
+__global__ void __launch_bounds__(TRB) k_trial_final(const double *part, int np, double *out) {
+  __shared__ double sh[TRB / 64];
+  const double *pp = part + (int64_t)blockIdx.x * np;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < np; i += TRB) a += pp[i];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < TRB / 64; ++w) r += sh[w];
+    out[blockIdx.x] += r;
+  }
+}
 }  // namespace
+
+int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, const int32_t *keys, int n_trials,
+                   int n_scenes, double *out_accum, hipStream_t s) {
+  if (n <= 0 || n_trials <= 0) return ABD_OK;
+  if (n_scenes > 1) {
+    hipLaunchKernelGGL(k_seg_reduce_trials, dim3(n_trials * n_scenes), dim3(SB), 0, s, vals, stride, n, keys, n_scenes,
+                       out_accum);
+    return abd_hip_check(ctx, hipGetLastError(), "k_seg_reduce_trials");
+  }
+  int nblk = (int)((n + TRB * 4 - 1) / (TRB * 4));
+  nblk = nblk < 1 ? 1 : (nblk > 256 ? 256 : nblk);
+  double *part;
+  ABD_TRY(ws(ctx, "trial_part", (size_t)nblk * n_trials, &part, s));
+  hipLaunchKernelGGL(k_trial_pass, dim3(nblk, n_trials), dim3(TRB), 0, s, vals, stride, n, part);
+  hipLaunchKernelGGL(k_trial_final, dim3(n_trials), dim3(TRB), 0, s, part, nblk, out_accum);
+  return abd_hip_check(ctx, hipGetLastError(), "k_trial_pass");
+}
 
 int op_scene_offsets(abd_ctx *ctx, const abd_scene *sc, const int32_t **off, hipStream_t s) {
   int32_t *o;

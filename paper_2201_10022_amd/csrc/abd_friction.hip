@@ -181,12 +181,16 @@ __global__ void __launch_bounds__(128) k_friction_local(int64_t n, int64_t n_pt,
                                                         double *e_out, double *g_out, double *H_out,
                                                         PairInfo *info, const int32_t *body_scene,
                                                         int32_t *key_out, const double *v = nullptr,
-                                                        const double *xbar = nullptr) {
+                                                        const double *xbar = nullptr, int64_t xstride = 0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (ENERGY_ONLY) {  // (grid.y > 1: trial t's positions at x + t xstride, energies at e_out + t n)
+    x += blockIdx.y * xstride;
+    e_out += blockIdx.y * n;
+  }
   int is_ee, vid[4];
   load_vids(i, n_pt, pt, ee, tris, edges, is_ee, vid);
-  if (key_out) key_out[i] = body_scene[vert_body[vid[0]]];
+  if (key_out && blockIdx.y == 0) key_out[i] = body_scene[vert_body[vid[0]]];
   const double ml = mu * lam[i];
   double wk[4], Ti[6];
 #pragma unroll
@@ -614,6 +618,24 @@ int op_friction_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const FrictionS
   HIP_TRY(ctx, hipGetLastError());
   if (fr->n_pt) ABD_TRY(seg_sum_scenes(ctx, e, key, fr->n_pt, S, energy, s));
   if (fr->n_ee) ABD_TRY(seg_sum_scenes(ctx, e + fr->n_pt, key + fr->n_pt, fr->n_ee, S, energy, s));
+  return ABD_OK;
+}
+
+int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
+                              int n_trials, double *energy, hipStream_t s) {
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  const int64_t n = fr->n();
+  if (n == 0 || n_trials <= 0) return ABD_OK;
+  double *e;
+  int32_t *key;
+  ABD_TRY(ws(ctx, "fe_e_tr", (size_t)n * n_trials, &e, s));
+  ABD_TRY(ws(ctx, "fe_key", n, &key, s));
+  hipLaunchKernelGGL(k_friction_local<true>, dim3(grid_for(n, 128), n_trials), dim3(128), 0, s, n, fr->n_pt, fr->pt,
+                     fr->ee, sc->tris, sc->edges, sc->vert_body, x, fr->xt, fr->lam, fr->T, fr->w, fr->mu, fr->eps, e,
+                     nullptr, nullptr, nullptr, sc->body_scene, key, nullptr, nullptr, 3 * (int64_t)sc->n_verts);
+  HIP_TRY(ctx, hipGetLastError());
+  if (fr->n_pt) ABD_TRY(seg_sum_trials(ctx, e, n, fr->n_pt, key, n_trials, S, energy, s));
+  if (fr->n_ee) ABD_TRY(seg_sum_trials(ctx, e + fr->n_pt, n, fr->n_ee, key + fr->n_pt, n_trials, S, energy, s));
   return ABD_OK;
 }
 

@@ -83,32 +83,43 @@ __global__ void k_zero_done(int nb, const int32_t *body_scene, const uint8_t *do
   if (i >= 12 * nb) return;
   if (done[body_scene[i / 12]]) p[i] = 0.0;
 }
-__global__ void k_axpy_scene(int nb, const int32_t *body_scene, const double *a, const double *alpha,
-                             const double *b, double *out) {
+// trial t of n: out[t][i] = a[i] + alpha[t S + scene] b[i]
+__global__ void k_axpy_trials(int nb, int S, const int32_t *body_scene, const double *a, const double *alpha,
+                              const double *b, double *out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 12 * nb) return;
-  out[i] = a[i] + alpha[body_scene[i / 12]] * b[i];
+  const int t = blockIdx.y;
+  out[(int64_t)t * 12 * nb + i] = a[i] + alpha[(int64_t)t * S + body_scene[i / 12]] * b[i];
 }
 
-// trial step lengths alpha_ccd 2^-t, t < n (0 for scenes already done)
+// step lengths of the first line-search batch: row 0 is 0 (E(q) itself),
+// row t >= 1 is alpha_ccd 2^-(t-1) (0 for scenes already done)
 __global__ void k_ls_trials(int S, int n, const uint8_t *done, const double *a_ccd, double *a_tr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S * n) return;
   const int j = i % S, t = i / S;
-  a_tr[i] = done[j] ? 0.0 : ldexp(a_ccd[j], -t);
+  a_tr[i] = t == 0 || done[j] ? 0.0 : ldexp(a_ccd[j], -(t - 1));
 }
 
-// per-scene E(q) over the given (swept) candidates into e_dev [S],
-// enqueued only (no synchronisation)
-int energy_enqueue(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
-                   double *x, const int32_t *pt, int64_t npt, const int32_t *ee, int64_t nee, const FrictionSet *fr,
-                   double *e_dev, hipStream_t s) {
+// per-scene E(q + alpha_t p) for n trials (alpha [n][S] on the device) over
+// the given (swept) candidates into e_dev [n][S]; all trials go through the
+// same launches (a trial dimension in the grid), enqueued only
+int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *p,
+                  const double *qt, const double *alpha, int n, const int32_t *pt, int64_t npt, const int32_t *ee,
+                  int64_t nee, const FrictionSet *fr, double *e_dev, hipStream_t s) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
-  ABD_TRY(zero(ctx, e_dev, S, s));
-  ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
-  ABD_TRY(op_body_energy_scenes(ctx, sc, prm, q, qt, e_dev, s));
-  ABD_TRY(op_barrier_energy_scenes(ctx, sc, prm, x, pt, npt, ee, nee, e_dev, s));
-  if (fr) ABD_TRY(op_friction_energy_scenes(ctx, sc, fr, x, e_dev, s));
+  const int nb = sc->n_bodies;
+  const int64_t n12 = 12 * (int64_t)nb;
+  double *qn, *xn;
+  ABD_TRY(ws(ctx, "ls_q", (size_t)n * n12, &qn, s));
+  ABD_TRY(ws(ctx, "ls_x", (size_t)n * 3 * sc->n_verts, &xn, s));
+  ABD_TRY(zero(ctx, e_dev, (int64_t)n * S, s));
+  hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), n), dim3(256), 0, s, nb, S, sc->body_scene, q, alpha, p,
+                     qn);
+  ABD_TRY(op_vertex_map_trials(ctx, sc, qn, n, xn, s));
+  ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, e_dev, s));
+  ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, xn, n, pt, npt, ee, nee, e_dev, s));
+  if (fr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, e_dev, s));
   return ABD_OK;
 }
 
@@ -136,7 +147,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(ws(ctx, "nt_qa", n12, &qa, s));
   ABD_TRY(ws(ctx, "nt_e", 4, &e, s));
   ABD_TRY(ws(ctx, "nt_sv", 2 * (size_t)S, &sv, s));
-  ABD_TRY(ws(ctx, "nt_alpha", (size_t)LS_BATCH * S, &alpha_dev, s));
+  ABD_TRY(ws(ctx, "nt_alpha", (size_t)(LS_BATCH + 1) * S, &alpha_dev, s));
   double *e_sc, *a_ccd;  // e_sc: E0 [S], then the trials' energies [LS_BATCH][S]
   ABD_TRY(ws(ctx, "nt_escene", (size_t)(LS_BATCH + 1) * S, &e_sc, s));
   ABD_TRY(ws(ctx, "nt_accd", S, &a_ccd, s));
@@ -252,18 +263,12 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   // halving would.  E(q) and the first batch (its step lengths formed on
   // the device from the CCD bound) are enqueued behind the CCD, so one
   // synchronisation brings the bound, E(q) and the first batch's energies.
-  ABD_TRY(energy_enqueue(ctx, sc, prm, q, qt, x1, spt, nspt, see, nsee, fr, e_sc, s));
   int K = ctx->ls_hint + 1;
   K = K < 1 ? 1 : (K > LS_BATCH ? LS_BATCH : K);
   const int kb0 = K <= prm->max_ls ? K : (prm->max_ls > 0 ? prm->max_ls : 0);
-  if (kb0 > 0) {
-    hipLaunchKernelGGL(k_ls_trials, dim3(grid_for(kb0 * S, 256)), dim3(256), 0, s, S, kb0, done_dev, a_ccd, alpha_dev);
-    for (int t = 0; t < kb0; ++t) {
-      hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q,
-                         alpha_dev + (size_t)t * S, p, qa);
-      ABD_TRY(energy_enqueue(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e_sc + (size_t)(t + 1) * S, s));
-    }
-  }
+  hipLaunchKernelGGL(k_ls_trials, dim3(grid_for((kb0 + 1) * S, 256)), dim3(256), 0, s, S, kb0 + 1, done_dev, a_ccd,
+                     alpha_dev);
+  ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb0 + 1, spt, nspt, see, nsee, fr, e_sc, s));
   HIP_TRY(ctx, hipMemcpyAsync(h_alpha, a_ccd, S * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipMemcpyAsync(h_e0, e_sc, (size_t)(kb0 + 1) * S * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -286,11 +291,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
       for (int t = 0; t < kb; ++t)
         for (int j = 0; j < S; ++j) h_atr[(size_t)t * S + j] = acc[j] ? h_alpha[j] : std::ldexp(h_alpha[j], -t);
       HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_atr, (size_t)kb * S * sizeof(double), hipMemcpyHostToDevice, s));
-      for (int t = 0; t < kb; ++t) {
-        hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q,
-                           alpha_dev + (size_t)t * S, p, qa);
-        ABD_TRY(energy_enqueue(ctx, sc, prm, qa, qt, x1, spt, nspt, see, nsee, fr, e_sc + (size_t)(t + 1) * S, s));
-      }
+      ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb, spt, nspt, see, nsee, fr, e_sc + S, s));
       HIP_TRY(ctx, hipMemcpyAsync(h_e1, e_sc + S, (size_t)kb * S * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(ctx, hipStreamSynchronize(s));
     }
@@ -316,7 +317,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   if (!all_acc) return abd_fail(ctx, ABD_E_LINESEARCH, "line search found no decrease");
   // the accepted point of every scene
   HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_alpha, S * sizeof(double), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_axpy_scene, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, q, alpha_dev, p,
+  hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), 1), dim3(256), 0, s, nb, S, sc->body_scene, q, alpha_dev, p,
                      qa);
   double e0 = 0.0, e1 = 0.0, amin_acc = 1.0;
   for (int j = 0; j < S; ++j) {

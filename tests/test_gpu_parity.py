@@ -379,6 +379,40 @@ def test_pcg_matches_direct_solve(abd, ctx, name, S, P):
     assert np.abs(p - p_ref).max() <= 1e-8 * np.abs(p_ref).max()
 
 
+@pytest.mark.parametrize("form", ["two_kernel", "one_kernel"])
+@pytest.mark.parametrize("rtol", [1e-6, 1e-13])
+def test_pcg_forms_match_direct_solve(abd, ctx, form, rtol, monkeypatch):
+    # both iteration forms (the one-kernel form is followed by the check on
+    # a fresh residual; ABD_PCG_CG=0 selects the two-kernel form alone) meet
+    # the tolerance on the true residual, against the oracle's direct solve
+    if form == "two_kernel":
+        monkeypatch.setenv("ABD_PCG_CG", "0")
+    else:
+        monkeypatch.delenv("ABD_PCG_CG", raising=False)
+    name, S, P = SCENES[0]
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    B = oracle.Body(S)
+    q = _state(S, 52)
+    qt = q.copy()
+    qt[:, :3] += P["dt"] ** 2 * np.array(P["gravity"])
+    qt[S["body_fixed"] != 0] = q[S["body_fixed"] != 0]
+    gh = oracle.grad_hess(S, B, q, qt, P)
+    p_ref = oracle.solve(S, gh["diag"], gh["off"], gh["keys"], -gh["grad"])
+    p, its = ctx.pcg_solve(sc, _dev(gh["diag"]), _dev(gh["off"].reshape(-1, 144)), _dev(gh["keys"], torch.int32),
+                           _dev(-gh["grad"]), rtol=rtol, max_iter=20000)
+    assert its > 0
+    p = p.cpu().numpy()
+    free = S["body_fixed"] == 0
+    A = oracle.assemble(S, gh["diag"], gh["off"], gh["keys"])[0]
+    b = -gh["grad"][free].ravel()
+    res = A @ p[free].ravel() - b
+    if rtol >= 1e-8:  # (at tighter tolerances the residual's own rounding dominates)
+        assert np.linalg.norm(res) <= rtol * np.linalg.norm(b) * 1.01
+    else:
+        assert np.abs(p - p_ref).max() <= 1e-8 * np.abs(p_ref).max()
+
+
 # ------------------------------------------------- a11/a12 Newton ----
 
 @pytest.mark.parametrize("name,S,P", SCENES[:3] + SCENES[4:], ids=[s[0] for s in SCENES[:3] + SCENES[4:]])

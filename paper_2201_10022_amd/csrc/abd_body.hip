@@ -281,12 +281,13 @@ __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed,
                                                   const double *volume, const double *q, const double *qt,
                                                   double kappa_o, double w, int do_inertia, int do_ortho,
                                                   int project, int want_grad, double *e_out, double *grad,
-                                                  double *diag) {
+                                                  double *diag, int64_t estride = 0) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
-  // energy-only trials (grid.y > 1): trial t's q at q + 12 nb t, energies at e_out + nb t
+  // energy-only trials (grid.y > 1): trial t's q at q + 12 nb t, energies at
+  // e_out + t estride (estride 0: nb)
   q += blockIdx.y * 12 * (int64_t)nb;
-  e_out += blockIdx.y * (int64_t)nb;
+  e_out += blockIdx.y * (estride > 0 ? estride : (int64_t)nb);
   if (fixed[b]) {
     e_out[b] = 0.0;
     return;
@@ -425,16 +426,19 @@ int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int
 }
 
 int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
-                          const double *qt, int n_trials, double *energy, hipStream_t s) {
+                          const double *qt, int n_trials, double *energy, hipStream_t s, double *items,
+                          int64_t estride) {
   const int nb = sc->n_bodies;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   if (nb <= 0 || n_trials <= 0) return ABD_OK;
   if (!sc->mass || !sc->volume) return abd_fail(ctx, ABD_E_INVALID, "scene mass or volume is NULL");
-  double *eb;
-  ABD_TRY(ws(ctx, "body_e_tr", (size_t)nb * n_trials, &eb, s));
+  double *eb = items;
+  if (!eb) ABD_TRY(ws(ctx, "body_e_tr", (size_t)nb * n_trials, &eb, s));
   hipLaunchKernelGGL(k_body_terms, dim3(grid_for(nb, 64), n_trials), dim3(64), 0, s, nb, sc->body_fixed, sc->mass,
-                     sc->volume, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, 0, eb, nullptr, nullptr);
+                     sc->volume, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, 0, eb, nullptr, nullptr,
+                     items ? estride : 0);
   HIP_TRY(ctx, hipGetLastError());
+  if (items) return ABD_OK;
   return seg_sum_trials(ctx, eb, nb, nb, sc->body_scene, n_trials, S, energy, s);
 }
 

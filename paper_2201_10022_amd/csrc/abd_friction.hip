@@ -181,12 +181,13 @@ __global__ void __launch_bounds__(128) k_friction_local(int64_t n, int64_t n_pt,
                                                         double *e_out, double *g_out, double *H_out,
                                                         PairInfo *info, const int32_t *body_scene,
                                                         int32_t *key_out, const double *v = nullptr,
-                                                        const double *xbar = nullptr, int64_t xstride = 0) {
+                                                        const double *xbar = nullptr, int64_t xstride = 0,
+                                                        int64_t estride = 0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (ENERGY_ONLY) {  // (grid.y > 1: trial t's positions at x + t xstride, energies at e_out + t n)
+  if (ENERGY_ONLY) {  // (grid.y > 1: trial t's positions at x + t xstride, energies at e_out + t estride)
     x += blockIdx.y * xstride;
-    e_out += blockIdx.y * n;
+    e_out += blockIdx.y * (estride > 0 ? estride : n);
   }
   int is_ee, vid[4];
   load_vids(i, n_pt, pt, ee, tris, edges, is_ee, vid);
@@ -622,18 +623,20 @@ int op_friction_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const FrictionS
 }
 
 int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
-                              int n_trials, double *energy, hipStream_t s) {
+                              int n_trials, double *energy, hipStream_t s, double *items, int64_t estride) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int64_t n = fr->n();
   if (n == 0 || n_trials <= 0) return ABD_OK;
-  double *e;
-  int32_t *key;
-  ABD_TRY(ws(ctx, "fe_e_tr", (size_t)n * n_trials, &e, s));
-  ABD_TRY(ws(ctx, "fe_key", n, &key, s));
+  double *e = items;
+  int32_t *key = nullptr;
+  if (!e) ABD_TRY(ws(ctx, "fe_e_tr", (size_t)n * n_trials, &e, s));
+  if (!items) ABD_TRY(ws(ctx, "fe_key", n, &key, s));
   hipLaunchKernelGGL(k_friction_local<true>, dim3(grid_for(n, 128), n_trials), dim3(128), 0, s, n, fr->n_pt, fr->pt,
                      fr->ee, sc->tris, sc->edges, sc->vert_body, x, fr->xt, fr->lam, fr->T, fr->w, fr->mu, fr->eps, e,
-                     nullptr, nullptr, nullptr, sc->body_scene, key, nullptr, nullptr, 3 * (int64_t)sc->n_verts);
+                     nullptr, nullptr, nullptr, sc->body_scene, key, nullptr, nullptr, 3 * (int64_t)sc->n_verts,
+                     items ? estride : 0);
   HIP_TRY(ctx, hipGetLastError());
+  if (items) return ABD_OK;
   if (fr->n_pt) ABD_TRY(seg_sum_trials(ctx, e, n, fr->n_pt, key, n_trials, S, energy, s));
   if (fr->n_ee) ABD_TRY(seg_sum_trials(ctx, e + fr->n_pt, n, fr->n_ee, key + fr->n_pt, n_trials, S, energy, s));
   return ABD_OK;

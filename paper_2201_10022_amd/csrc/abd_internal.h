@@ -425,16 +425,20 @@ int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, doubl
 // (trial, scene) into out_accum[t * n_scenes + scene] (accumulated); keys
 // (non-decreasing item scenes) are needed when n_scenes > 1.
 // Energies of n_trials configurations at once (trial t's q, x at
-// q + 12 nb t, x + 3 nv t): each op accumulates into energy[t S + scene].
+// q + 12 nb t, x + 3 nv t): each op accumulates into energy[t S + scene];
+// with items non-NULL it instead writes the per-item energies (trial t's
+// at items + t estride) and sums nothing.
 int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int n_trials, double *x,
                          hipStream_t s);
 int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
-                          const double *qt, int n_trials, double *energy, hipStream_t s);
+                          const double *qt, int n_trials, double *energy, hipStream_t s, double *items = nullptr,
+                          int64_t estride = 0);
 int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
                              int n_trials, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
-                             double *energy, hipStream_t s);
+                             double *energy, hipStream_t s, double *items = nullptr, int64_t estride = 0);
 int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
-                              int n_trials, double *energy, hipStream_t s);
+                              int n_trials, double *energy, hipStream_t s, double *items = nullptr,
+                              int64_t estride = 0);
 int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, const int32_t *keys, int n_trials,
                    int n_scenes, double *out_accum, hipStream_t s);
 int seg_sum_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out_accum,

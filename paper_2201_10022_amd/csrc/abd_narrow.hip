@@ -282,15 +282,16 @@ __global__ void k_assemble_final(int64_t nblocks, int nb, const int64_t *chunk_o
 }
 
 // pair energies; key_out (may be NULL) receives each pair's scene
-// (grid.y > 1: trial t's positions at x + t xstride, energies at e_out + t n)
+// (grid.y > 1: trial t's positions at x + t xstride, energies at
+// e_out + t estride, estride 0: n)
 __global__ void k_energy_only(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee, const int32_t *tris,
                               const int32_t *edges, const double *x, const double *xbar, double dhat,
                               double kappa, double *e_out, const int32_t *vert_body, const int32_t *body_scene,
-                              int32_t *key_out, int64_t xstride = 0) {
+                              int32_t *key_out, int64_t xstride = 0, int64_t estride = 0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   x += blockIdx.y * xstride;
-  e_out += blockIdx.y * n;
+  e_out += blockIdx.y * (estride > 0 ? estride : n);
   int is_ee, vid[4];
   d3 X[4];
   load_pair(i, n_pt, pt, ee, tris, edges, x, is_ee, vid, X);
@@ -467,20 +468,21 @@ int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params
 
 int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
                              int n_trials, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
-                             double *energy, hipStream_t s) {
+                             double *energy, hipStream_t s, double *items, int64_t estride) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int64_t n = n_pt + n_ee;
   if (n == 0 || n_trials <= 0) return ABD_OK;
-  double *e;
-  int32_t *key;
-  ABD_TRY(ws(ctx, "be_e_tr", (size_t)n * n_trials, &e, s));
-  ABD_TRY(ws(ctx, "be_key", n, &key, s));
+  double *e = items;
+  int32_t *key = nullptr;
+  if (!e) ABD_TRY(ws(ctx, "be_e_tr", (size_t)n * n_trials, &e, s));
+  if (!items) ABD_TRY(ws(ctx, "be_key", n, &key, s));
   hipEvent_t pe = prof_begin(ctx, s);
   hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, 256), n_trials), dim3(256), 0, s, n_pt, n, pt, ee, sc->tris,
                      sc->edges, x, sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key,
-                     3 * (int64_t)sc->n_verts);
+                     3 * (int64_t)sc->n_verts, items ? estride : 0);
   prof_end(ctx, pe, "energy_only", n * n_trials, s);
   HIP_TRY(ctx, hipGetLastError());
+  if (items) return ABD_OK;
   // PT and EE lists are each ordered by scene
   if (n_pt) ABD_TRY(seg_sum_trials(ctx, e, n, n_pt, key, n_trials, S, energy, s));
   if (n_ee) ABD_TRY(seg_sum_trials(ctx, e + n_pt, n, n_ee, key + n_pt, n_trials, S, energy, s));

@@ -117,10 +117,22 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
   hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), n), dim3(256), 0, s, nb, S, sc->body_scene, q, alpha, p,
                      qn);
   ABD_TRY(op_vertex_map_trials(ctx, sc, qn, n, xn, s));
-  ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, e_dev, s));
-  ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, xn, n, pt, npt, ee, nee, e_dev, s));
-  if (fr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, e_dev, s));
-  return ABD_OK;
+  if (S > 1) {
+    ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, e_dev, s));
+    ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, xn, n, pt, npt, ee, nee, e_dev, s));
+    if (fr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, e_dev, s));
+    return ABD_OK;
+  }
+  // one scene: every item's energy of a trial in one row (bodies, barrier
+  // pairs, friction pairs), one sum per row
+  const int64_t nfr = fr ? fr->n() : 0;
+  const int64_t nt = (int64_t)nb + npt + nee + nfr;
+  double *items;
+  ABD_TRY(ws(ctx, "ls_items", (size_t)n * nt, &items, s));
+  ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, nullptr, s, items, nt));
+  if (npt + nee) ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, xn, n, pt, npt, ee, nee, nullptr, s, items + nb, nt));
+  if (nfr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, nullptr, s, items + nb + npt + nee, nt));
+  return seg_sum_trials(ctx, items, nt, nt, nullptr, n, 1, e_dev, s);
 }
 
 constexpr int LS_BATCH = 4;  // trial step lengths evaluated per line-search batch
@@ -317,8 +329,9 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   if (!all_acc) return abd_fail(ctx, ABD_E_LINESEARCH, "line search found no decrease");
   // the accepted point of every scene
   HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_alpha, S * sizeof(double), hipMemcpyHostToDevice, s));
+  // (in place: each element reads q[i] before writing it)
   hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), 1), dim3(256), 0, s, nb, S, sc->body_scene, q, alpha_dev, p,
-                     qa);
+                     q);
   double e0 = 0.0, e1 = 0.0, amin_acc = 1.0;
   for (int j = 0; j < S; ++j) {
     if (h_done[j]) continue;
@@ -332,7 +345,6 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->alpha = amin_acc;
   st->energy0 = e0;
   st->energy1 = e1;
-  HIP_TRY(ctx, hipMemcpyAsync(q, qa, sizeof(double) * n12, hipMemcpyDeviceToDevice, s));
   ctx->sw_valid = true;
   ctx->sw_pt = spt;
   ctx->sw_ee = see;

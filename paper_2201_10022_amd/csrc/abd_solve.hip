@@ -159,7 +159,7 @@ struct PcgState {
   int it_done;    // iterations completed (written by update's block 0)
   int k_cur;      // iteration being run (written by spmv's block 0)
   int n_stopped;  // scenes stopped so far
-  int pad;
+  int max_final;  // largest iteration count of a stopped scene
 };
 struct PcgScene {
   double *rz;      // [2 S] r.z of the iterations with parity 0 / 1
@@ -225,6 +225,7 @@ __global__ void k_pcg_reset(int S, PcgState *st, PcgScene sc) {
     st->it_done = 0;
     st->k_cur = 0;
     st->n_stopped = 0;
+    st->max_final = 0;
   }
   if (s < S) {
     sc.stop[s] = 0;
@@ -415,6 +416,7 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int2 
     if (stop) {
       scs.stop[sc] = 1;
       scs.it_final[sc] = k;
+      atomicMax(&st->max_final, k);
       atomicAdd(&st->n_stopped, 1);
     }
   }
@@ -493,6 +495,7 @@ __global__ void __launch_bounds__(PB) k_pcg_update(const PcgBlk *blk, const doub
     if (bi.is_first && threadIdx.x == 0) {
       scs.stop[sc] = 1;
       scs.it_final[sc] = k;
+      atomicMax(&st->max_final, k);
       atomicAdd(&st->n_stopped, 1);
       if (!(pap == 0.0 && rz == 0.0)) atomicOr(err, 8);
     }
@@ -536,7 +539,8 @@ struct CgScene {
 struct CgState {
   int base;  // iteration of the first kernel of a replay
   int n_stopped;
-  int pad[2];
+  int max_final;  // largest iteration count of a stopped scene
+  int pad;
 };
 
 __device__ __forceinline__ void cg_step(double r, double w, double s_prev, double alpha, double beta, double &s_new,
@@ -550,6 +554,7 @@ __global__ void k_cg_reset(int S, CgState *st, CgScene sc) {
   if (s == 0) {
     st->base = 0;
     st->n_stopped = 0;
+    st->max_final = 0;
   }
   if (s < S) {
     sc.stop[s] = 0;
@@ -798,6 +803,7 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
     if (stop) {
       scs.stop[sc] = 1;
       scs.it_final[sc] = k;
+      atomicMax(&st->max_final, k);
       atomicAdd(&st->n_stopped, 1);
     }
   }
@@ -983,7 +989,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
       exec[gi] = ctx->pcg_exec[gi];
     }
   }
-  int *h;  // [0..1] base, n_stopped; [4..4+S) per-scene iteration counts
+  int *h;  // [0..2] base, n_stopped, max_final; [4..4+S) per-scene iteration counts
   ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
   int *fin = h + 4;
   const int max_rounds = max_iter / ITER_G[0] + 2;
@@ -1002,18 +1008,10 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
       enqueue(s, ITER_G[gi]);
     prof_end(ctx, pe, "pcg_round", 0, s);
     HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(h, st, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(h, st, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     all = h[1] >= S;
-    int now = h[0];
-    if (all) {
-      // iterations: the largest count over the scenes
-      HIP_TRY(ctx, hipMemcpyAsync(fin, scs.it_final, S * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_TRY(ctx, hipStreamSynchronize(s));
-      now = 0;
-      for (int j = 0; j < S; ++j) now = fin[j] > now ? fin[j] : now;
-    }
-    done = now;
+    done = all ? h[2] : h[0];  // iterations: the largest count over the scenes
   }
   *iters = done;
   ctx->pcg_hint = done;
@@ -1023,6 +1021,10 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
     // iteration kernel (r, w, s, x, u, p in; r, w, s, x, u, p out)
     std::vector<int32_t> hs(S + 1);
     std::vector<int64_t> hl(nb + 1);
+    if (S == 1)
+      fin[0] = done;
+    else
+      HIP_TRY(ctx, hipMemcpy(fin, scs.it_final, S * sizeof(int), hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(hs.data(), sbo, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(hl.data(), lo_beg, (nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
     int64_t total = 0;
@@ -1238,19 +1240,11 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
       enqueue(s, ITER_G[gi]);
     prof_end(ctx, pe, "pcg_round", 0, s);
     HIP_TRY(ctx, hipGetLastError());
-    // it_done, k_cur, n_stopped
-    HIP_TRY(ctx, hipMemcpyAsync(h, st, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    // it_done, k_cur, n_stopped, max_final
+    HIP_TRY(ctx, hipMemcpyAsync(h, st, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     all = h[2] >= S;
-    int now = h[0];
-    if (all) {
-      // iterations: the largest count over the scenes
-      HIP_TRY(ctx, hipMemcpyAsync(fin, scs.it_final, S * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_TRY(ctx, hipStreamSynchronize(s));
-      now = 0;
-      for (int j = 0; j < S; ++j) now = fin[j] > now ? fin[j] : now;
-    }
-    done = now;
+    done = all ? h[3] : h[0];  // iterations: the largest count over the scenes
   }
   *iters = it0 + done;
   ctx->pcg_hint = one_kernel ? it0 : done;
@@ -1260,6 +1254,10 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
     // on the last replay, so the per-replay average is exact
     std::vector<int32_t> hs(S + 1);
     std::vector<int64_t> hl(nb + 1);
+    if (S == 1)
+      fin[0] = done;
+    else
+      HIP_TRY(ctx, hipMemcpy(fin, scs.it_final, S * sizeof(int), hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(hs.data(), sbo, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemcpy(hl.data(), lo_beg, (nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
     int64_t total = 0;

@@ -89,7 +89,7 @@ template <int WRITE>
 __global__ void __launch_bounds__(64) k_body_pairs(int nb, const int32_t *body_scene, const uint8_t *fixed,
                                                    const double *bb, const int32_t *scene_end_of_body,
                                                    const uint8_t *skip_scene, int64_t *cnt, const int64_t *off,
-                                                   int32_t *pairs) {
+                                                   int32_t *pairs, int64_t cap = 0) {
   const int a = blockIdx.x;
   if (a >= nb) return;
   if (skip_scene && skip_scene[body_scene[a]]) {
@@ -110,8 +110,10 @@ __global__ void __launch_bounds__(64) k_body_pairs(int nb, const int32_t *body_s
     const unsigned long long m = __ballot(ok);
     if (WRITE && ok) {
       const int64_t pos = base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull));
-      pairs[2 * pos] = a;
-      pairs[2 * pos + 1] = b;
+      if (pos < cap) {  // (beyond the capacity the caller sizes again and repeats)
+        pairs[2 * pos] = a;
+        pairs[2 * pos + 1] = b;
+      }
     }
     c += __popcll(m);
   }
@@ -139,11 +141,16 @@ __global__ void k_scene_end(int nb, const int32_t *body_scene, int32_t *end) {
 //   2: vertices of b in box(a)   3: triangles of a in box(b)
 //   4: edges of a in box(b)      5: edges of b in box(a)
 // Capacity of each list = primitive count of its body; region offsets per
-// body pair from a scan of the summed capacities.
-__global__ void k_list_caps(int64_t nbp, const int32_t *bpairs, const int32_t *voff, const int32_t *toff,
-                            const int32_t *eoff, int64_t *cap) {
+// body pair from a scan of the summed capacities.  Runs over a buffer of
+// n_cap slots; slots at or beyond the body-pair count (device) get 0.
+__global__ void k_list_caps(int64_t n_cap, const int64_t *nbp_dev, const int32_t *bpairs, const int32_t *voff,
+                            const int32_t *toff, const int32_t *eoff, int64_t *cap) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nbp) return;
+  if (p >= n_cap) return;
+  if (p >= *nbp_dev) {
+    cap[p] = 0;
+    return;
+  }
   const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
   cap[p] = (int64_t)(voff[a + 1] - voff[a]) + (toff[b + 1] - toff[b]) + (voff[b + 1] - voff[b]) +
            (toff[a + 1] - toff[a]) + (eoff[a + 1] - eoff[a]) + (eoff[b + 1] - eoff[b]);
@@ -213,11 +220,11 @@ __global__ void k_sub_tiles(int64_t nbp, const int32_t *list_len, int64_t *tiles
 }
 
 // (sub-problem, tile index within it) of every tile
-__global__ void k_tile_sub(int64_t n_sub, const int64_t *cnt, const int64_t *off, int2 *tile_sub) {
+__global__ void k_tile_sub(int64_t n_sub, const int64_t *cnt, const int64_t *off, int2 *tile_sub, int64_t cap) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_sub) return;
   const int64_t o = off[j];
-  for (int64_t t = 0; t < cnt[j]; ++t) tile_sub[o + t] = make_int2((int)j, (int)t);
+  for (int64_t t = 0; t < cnt[j] && o + t < cap; ++t) tile_sub[o + t] = make_int2((int)j, (int)t);
 }
 
 // One wave per tile of TROWS rows x all columns.  WRITE=0 counts the
@@ -232,8 +239,14 @@ __global__ void __launch_bounds__(64) k_pair_tiles(int is_ee, const int2 *tile_s
                                                    const int64_t *list_start, const int32_t *list_len,
                                                    const int32_t *lists, const double *row_boxes,
                                                    const double *col_boxes, int64_t *tile_cnt, const int64_t *tile_off,
-                                                   int32_t *out) {
+                                                   int32_t *out, const int64_t *n_tiles_dev = nullptr) {
   const int64_t tile = blockIdx.x;
+  // (the count pass runs over a capacity: tiles beyond the device count
+  // record 0 so that the scan over the capacity stays exact)
+  if (n_tiles_dev && tile < n_tiles && tile >= *n_tiles_dev) {
+    if (!WRITE && threadIdx.x == 0) tile_cnt[tile] = 0;
+    return;
+  }
   if (tile >= n_tiles) return;
   const int2 ts = tile_sub[tile];  // (sub-problem, tile within it)
   const int64_t s = ts.x;
@@ -329,33 +342,43 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_send", nb, &send, s));
   ABD_TRY(ws(ctx, "bp_bcnt", nb, &bcnt, s));
   ABD_TRY(ws(ctx, "bp_boff", nb, &boff, s));
-  ABD_TRY(ws(ctx, "bp_btot", 4, &btot, s));
+  ABD_TRY(ws(ctx, "bp_btot", 8, &btot, s));  // totals: body pairs, lists, tiles (2), pairs (2)
   hipLaunchKernelGGL(k_scene_end, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, sc->body_scene, send);
   hipLaunchKernelGGL(k_body_pairs<0>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
                      skip_scene, bcnt, nullptr, nullptr);
   ABD_TRY(scan_exclusive_i64(ctx, bcnt, boff, nb, btot, s));
   int64_t *hbuf;
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
-  HIP_TRY(ctx, hipMemcpyAsync(hbuf, btot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  const int64_t nbp = hbuf[0];
-  if (nbp == 0) return ABD_OK;
+  // Body pairs and their list regions are sized by the last call's count
+  // (with room to grow) so that one synchronisation reads both totals; a
+  // count beyond the capacity repeats the two steps at the exact size.
+  const std::string key_bp = std::string(tag) + "_bp";
+  int64_t cap_bp = ctx->cap_hint[key_bp];
+  cap_bp = cap_bp + cap_bp / 4 + 256;
+  int64_t nbp = 0, list_total = 0;
   int32_t *bpairs;
-  ABD_TRY(ws(ctx, "bp_pairs", 2 * nbp, &bpairs, s));
-  hipLaunchKernelGGL(k_body_pairs<1>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
-                     skip_scene, nullptr, boff, bpairs);
+  int64_t *cap, *region, *rtot = btot + 1;
+  for (int pass = 0;; ++pass) {
+    ABD_TRY(ws(ctx, "bp_pairs", 2 * cap_bp + 2, &bpairs, s));
+    ABD_TRY(ws(ctx, "bp_cap", cap_bp + 1, &cap, s));
+    ABD_TRY(ws(ctx, "bp_region", cap_bp + 1, &region, s));
+    hipLaunchKernelGGL(k_body_pairs<1>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
+                       skip_scene, nullptr, boff, bpairs, cap_bp);
+    hipLaunchKernelGGL(k_list_caps, dim3(grid_for(cap_bp, 256)), dim3(256), 0, s, cap_bp, btot, bpairs,
+                       sc->body_vert_off, sc->body_tri_off, sc->body_edge_off, cap);
+    ABD_TRY(scan_exclusive_i64(ctx, cap, region, cap_bp, rtot, s));
+    HIP_TRY(ctx, hipMemcpyAsync(hbuf, btot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    nbp = hbuf[0];
+    list_total = hbuf[1];
+    if (nbp <= cap_bp) break;
+    if (pass > 0) return abd_fail(ctx, ABD_E_INVALID, "candidates: body-pair count changed between passes");
+    cap_bp = nbp;
+  }
+  ctx->cap_hint[key_bp] = nbp;
+  if (nbp == 0) return ABD_OK;
 
   // culled primitive lists per body pair
-  int64_t *cap, *region, *rtot;
-  ABD_TRY(ws(ctx, "bp_cap", nbp, &cap, s));
-  ABD_TRY(ws(ctx, "bp_region", nbp, &region, s));
-  ABD_TRY(ws(ctx, "bp_rtot", 1, &rtot, s));
-  hipLaunchKernelGGL(k_list_caps, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, bpairs, sc->body_vert_off,
-                     sc->body_tri_off, sc->body_edge_off, cap);
-  ABD_TRY(scan_exclusive_i64(ctx, cap, region, nbp, rtot, s));
-  HIP_TRY(ctx, hipMemcpyAsync(hbuf, rtot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  const int64_t list_total = hbuf[0];
   int32_t *lists, *llen;
   int64_t *lstart;
   ABD_TRY(ws(ctx, "bp_lists", list_total + 1, &lists, s));
@@ -364,44 +387,52 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 6), dim3(256), 0, s, bpairs, region, sc->body_vert_off,
                      sc->body_tri_off, sc->body_edge_off, bbox, vbox, tbox, ebox, lists, lstart, llen);
 
-  // tiles
-  int64_t *tpt, *tee, *tpt_off, *tee_off, *ttot;
+  // tiles: the count pass is sized like the body pairs (one
+  // synchronisation reads the tile and pair totals)
+  int64_t *tpt, *tee, *tpt_off, *tee_off, *ttot = btot + 2, *otot = btot + 4;
   ABD_TRY(ws(ctx, "bp_tpt", 2 * nbp, &tpt, s));
   ABD_TRY(ws(ctx, "bp_tee", nbp, &tee, s));
   ABD_TRY(ws(ctx, "bp_tpt_off", 2 * nbp, &tpt_off, s));
   ABD_TRY(ws(ctx, "bp_tee_off", nbp, &tee_off, s));
-  ABD_TRY(ws(ctx, "bp_ttot", 2, &ttot, s));
   hipLaunchKernelGGL(k_sub_tiles, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, llen, tpt, tee);
   ABD_TRY(scan_exclusive_i64(ctx, tpt, tpt_off, 2 * nbp, ttot, s));
   ABD_TRY(scan_exclusive_i64(ctx, tee, tee_off, nbp, ttot + 1, s));
-  HIP_TRY(ctx, hipMemcpyAsync(hbuf, ttot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  const int64_t ntile_pt = hbuf[0], ntile_ee = hbuf[1];
-  int64_t *cpt, *cee, *opt, *oee, *otot;
-  ABD_TRY(ws(ctx, "bp_cpt", ntile_pt + 1, &cpt, s));
-  ABD_TRY(ws(ctx, "bp_cee", ntile_ee + 1, &cee, s));
-  ABD_TRY(ws(ctx, "bp_opt", ntile_pt + 1, &opt, s));
-  ABD_TRY(ws(ctx, "bp_oee", ntile_ee + 1, &oee, s));
-  ABD_TRY(ws(ctx, "bp_otot", 2, &otot, s));
+  const std::string key_tp = std::string(tag) + "_tpt", key_te = std::string(tag) + "_tee";
+  int64_t cap_tp = ctx->cap_hint[key_tp], cap_te = ctx->cap_hint[key_te];
+  cap_tp = cap_tp + cap_tp / 4 + 256;
+  cap_te = cap_te + cap_te / 4 + 256;
+  int64_t ntile_pt = 0, ntile_ee = 0;
+  int64_t *cpt, *cee, *opt, *oee;
   int2 *tsub_pt, *tsub_ee;
-  ABD_TRY(ws(ctx, "bp_tsub_pt", ntile_pt + 1, &tsub_pt, s));
-  ABD_TRY(ws(ctx, "bp_tsub_ee", ntile_ee + 1, &tsub_ee, s));
-  if (ntile_pt) {
-    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(2 * nbp, 256)), dim3(256), 0, s, 2 * nbp, tpt, tpt_off, tsub_pt);
-    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, tsub_pt, ntile_pt, lstart, llen,
-                       lists, vbox, tbox, cpt, nullptr, nullptr);
+  for (int pass = 0;; ++pass) {
+    ABD_TRY(ws(ctx, "bp_cpt", cap_tp + 1, &cpt, s));
+    ABD_TRY(ws(ctx, "bp_cee", cap_te + 1, &cee, s));
+    ABD_TRY(ws(ctx, "bp_opt", cap_tp + 1, &opt, s));
+    ABD_TRY(ws(ctx, "bp_oee", cap_te + 1, &oee, s));
+    ABD_TRY(ws(ctx, "bp_tsub_pt", cap_tp + 1, &tsub_pt, s));
+    ABD_TRY(ws(ctx, "bp_tsub_ee", cap_te + 1, &tsub_ee, s));
+    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(2 * nbp, 256)), dim3(256), 0, s, 2 * nbp, tpt, tpt_off, tsub_pt,
+                       cap_tp);
+    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)cap_tp), dim3(64), 0, s, 0, tsub_pt, cap_tp, lstart, llen,
+                       lists, vbox, tbox, cpt, nullptr, nullptr, ttot);
+    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, tee, tee_off, tsub_ee, cap_te);
+    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)cap_te), dim3(64), 0, s, 1, tsub_ee, cap_te, lstart, llen,
+                       lists, ebox, ebox, cee, nullptr, nullptr, ttot + 1);
+    ABD_TRY(scan_exclusive_i64(ctx, cpt, opt, cap_tp, otot, s));
+    ABD_TRY(scan_exclusive_i64(ctx, cee, oee, cap_te, otot + 1, s));
+    HIP_TRY(ctx, hipMemcpyAsync(hbuf, ttot, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    ntile_pt = hbuf[0];
+    ntile_ee = hbuf[1];
+    if (ntile_pt <= cap_tp && ntile_ee <= cap_te) break;
+    if (pass > 0) return abd_fail(ctx, ABD_E_INVALID, "candidates: tile count changed between passes");
+    cap_tp = ntile_pt > cap_tp ? ntile_pt : cap_tp;
+    cap_te = ntile_ee > cap_te ? ntile_ee : cap_te;
   }
-  if (ntile_ee) {
-    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, tee, tee_off, tsub_ee);
-    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, tsub_ee, ntile_ee, lstart, llen,
-                       lists, ebox, ebox, cee, nullptr, nullptr);
-  }
-  ABD_TRY(scan_exclusive_i64(ctx, cpt, opt, ntile_pt, otot, s));
-  ABD_TRY(scan_exclusive_i64(ctx, cee, oee, ntile_ee, otot + 1, s));
-  HIP_TRY(ctx, hipMemcpyAsync(hbuf, otot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  *n_pt = hbuf[0];
-  *n_ee = hbuf[1];
+  ctx->cap_hint[key_tp] = ntile_pt;
+  ctx->cap_hint[key_te] = ntile_ee;
+  *n_pt = hbuf[2];
+  *n_ee = hbuf[3];
   std::string tpt_name = std::string(tag) + "_pt", tee_name = std::string(tag) + "_ee";
   ABD_TRY(ws(ctx, tpt_name.c_str(), 2 * (*n_pt) + 2, pt_out, s));
   ABD_TRY(ws(ctx, tee_name.c_str(), 2 * (*n_ee) + 2, ee_out, s));

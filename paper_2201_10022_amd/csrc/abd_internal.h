@@ -35,6 +35,9 @@ struct abd_ctx {
   int device = 0;
   std::string err;
   std::map<std::string, DevBuf> bufs;
+  // counts of the last call per buffer family, used as capacities of the
+  // next one (checked when the counts are read)
+  std::map<std::string, int64_t> cap_hint;
   void *pinned = nullptr;  // small host staging area for scalar readbacks
   size_t pinned_bytes = 0;
   void *pinned_nt = nullptr;  // per-scene staging of the Newton driver

@@ -264,6 +264,49 @@ def test_barrier_grad_hess_parity(abd, ctx, name, S, P):
         assert max(errs.values()) <= tol, errs
 
 
+def test_barrier_and_ccd_full_size_icosphere_box(abd, ctx):
+    # the benchmark scene at full size (1000 icospheres, 162k vertices) with
+    # its bottom layer lowered to rest U[0.2,0.8] dhat above the floor:
+    # candidates (bit-exact), the assembled barrier gradient and projected
+    # Hessian, and the CCD bound of a 4 mm downward sweep, against the oracle
+    S, P = sg.icosphere_box()
+    q = S["q0"].copy()
+    rng = np.random.default_rng(123)
+    for b in range(1, 101):
+        sl = slice(S["body_vert_off"][b], S["body_vert_off"][b + 1])
+        low = (S["xbar"][sl] @ q[b, 3:].reshape(3, 3).T)[:, 1].min()
+        q[b, 1] = rng.uniform(0.2, 0.8) * P["dhat"] - low
+    sc = abd.Scene(S)
+    x = oracle.vertex_map(S, q)
+    pt, ee = ctx.candidates(sc, _dev(x), _dev(x), P["dhat"])
+    opt, oee = oracle.candidates(S, x, None, P["dhat"])
+    np.testing.assert_array_equal(_sorted_pairs(pt.cpu().numpy()), opt)
+    np.testing.assert_array_equal(_sorted_pairs(ee.cpu().numpy()), oee)
+    keys = oracle.off_keys(S, opt, oee)
+    r, gs, Ds, Os = _abs_scale(S, x, opt, oee, P, keys)
+    assert r["n_active"] > 100  # (floor contacts only: no off-diagonal blocks at this state)
+    e, g, D, O = ctx.barrier_grad_hess(sc, P, _dev(x), _dev(opt, torch.int32), _dev(oee, torch.int32),
+                                       _dev(keys, torch.int32))
+    tol = 1e-10
+    assert abs(e.item() - r["energy"]) <= tol * abs(r["energy"])
+    worst = lambda a, b, sc_: float(np.max(np.abs(a - b) / np.maximum(sc_, 1e-300)))
+    errs = dict(g=worst(g.cpu().numpy(), r["grad"], gs), D=worst(D.cpu().numpy(), r["diag"], Ds))
+    if len(keys):
+        errs["O"] = worst(O.cpu().numpy(), r["off"], Os)
+    assert max(errs.values()) <= tol, errs
+    q1 = q.copy()
+    q1[1:, 1] -= 4e-3
+    x1 = oracle.vertex_map(S, q1)
+    spt, see = oracle.candidates(S, x, x1, P["dhat"])
+    tp, te, alpha = ctx.ccd_max_step(sc, P, _dev(x), _dev(x1 - x), _dev(spt, torch.int32), _dev(see, torch.int32))
+    otp, ote, oalpha = oracle.ccd(S, x, x1 - x, spt, see, P)
+    assert len(spt) + len(see) > 1000
+    for t, ot in ((tp.cpu().numpy(), otp), (te.cpu().numpy(), ote)):
+        assert np.all(t <= ot * (1 + 1e-9))
+        assert np.all(t >= 0.99 * ot)
+    assert oalpha * 0.99 <= alpha.item() <= oalpha * (1 + 1e-9)
+
+
 def test_barrier_unprojected_parity(abd, ctx):
     S = sg.near_contact_cubes(8, n=3)
     P = sg.default_params()

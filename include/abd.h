@@ -220,9 +220,14 @@ int abd_q_tilde(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const 
  * off/off^T) restricted to free bodies: solves H p = rhs, p = 0 on fixed
  * bodies.  Sub-scenes are independent systems (no off-diagonal block joins
  * two of them): each runs its own CG scalars and stops on its own
- * |r| <= rtol |b|.  x0 (may be NULL = zero, may alias p): initial guess.
- * Syncs; *iters (host) receives the largest iteration count over the
- * sub-scenes. */
+ * |r| <= rtol |b|.  The iterations run in Chronopoulos-Gear form (one
+ * kernel per iteration); the result is then checked on a freshly computed
+ * residual b - H p, and a sub-scene that fails the check continues in the
+ * classical form (environment ABD_PCG_CG=0: classical form only).
+ * x0 (may be NULL = zero, may alias p): initial guess.  Syncs; *iters
+ * (host) receives the largest iteration count over the sub-scenes (both
+ * forms counted).  Error ABD_E_PCG: a diagonal block not positive definite
+ * or a non-positive curvature in the classical form. */
 int abd_pcg_solve(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
                   int64_t n_keys, const double *rhs, const double *x0, double *p, double rtol, int32_t max_iter,
                   int32_t *iters, hipStream_t stream);

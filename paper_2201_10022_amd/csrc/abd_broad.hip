@@ -473,6 +473,46 @@ __global__ void k_unique_write(int64_t n, const uint64_t *k, const int64_t *flag
   out[2 * pos[i]] = (int32_t)(k[i] >> 32);
   out[2 * pos[i] + 1] = (int32_t)(k[i] & 0xffffffffu);
 }
+
+// Dense variant for one scene of at most OD_DENSE_MAX bodies: the body pairs
+// are marked in an nb x nb byte matrix (every writer stores 1, so races are
+// harmless), then each row a writes its marked columns b > a in order, which
+// gives the same sorted, unique keys as sorting the pair keys.
+constexpr int OD_DENSE_MAX = 4096;
+__global__ void k_od_clear(int64_t n16, uint4 *f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) f[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+__global__ void k_od_mark(int64_t n, int is_ee, const int32_t *pairs, const int32_t *vert_body,
+                          const int32_t *tri_body, const int32_t *edge_body, const uint8_t *fixed, int nb,
+                          uint8_t *flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = is_ee ? edge_body[pairs[2 * i]] : vert_body[pairs[2 * i]];
+  const int b = is_ee ? edge_body[pairs[2 * i + 1]] : tri_body[pairs[2 * i + 1]];
+  if (!fixed[a] && !fixed[b] && a != b) flags[(int64_t)min(a, b) * nb + max(a, b)] = 1;
+}
+// one wave per row: count (WRITE 0) or write (WRITE 1) the marked columns
+template <int WRITE>
+__global__ void __launch_bounds__(64) k_od_row(int nb, const uint8_t *flags, int64_t *cnt, const int64_t *off,
+                                               int32_t *keys) {
+  const int a = blockIdx.x;
+  if (a >= nb) return;
+  const uint8_t *row = flags + (int64_t)a * nb;
+  int64_t c = 0, base = WRITE ? off[a] : 0;
+  for (int b0 = a + 1; b0 < nb; b0 += 64) {
+    const int b = b0 + (int)threadIdx.x;
+    const bool on = b < nb && row[b];
+    const unsigned long long m = __ballot(on);
+    if (WRITE && on) {
+      const int64_t o = base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull));
+      keys[2 * o] = a;
+      keys[2 * o + 1] = b;
+    }
+    c += __popcll(m);
+  }
+  if (!WRITE && threadIdx.x == 0) cnt[a] = c;
+}
 }  // namespace
 
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
@@ -492,6 +532,30 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   ABD_TRY(ws(ctx, "od_tot", 1, &tot, s));
   const int32_t *lists[4] = {pt, ee, pt2, ee2};
   const int64_t counts[4] = {n_pt, n_ee, n_pt2, n_ee2};
+  const int nb = sc->n_bodies;
+  if ((sc->n_scenes <= 1) && nb <= OD_DENSE_MAX) {
+    const int64_t nbb = ((int64_t)nb * nb + 15) / 16 * 16;
+    uint8_t *flags;
+    int64_t *rcnt, *roff;
+    ABD_TRY(ws(ctx, "od_flags", nbb, &flags, s));
+    ABD_TRY(ws(ctx, "od_rcnt", nb, &rcnt, s));
+    ABD_TRY(ws(ctx, "od_roff", nb + 1, &roff, s));
+    hipLaunchKernelGGL(k_od_clear, dim3(grid_for(nbb / 16, 256)), dim3(256), 0, s, nbb / 16,
+                       reinterpret_cast<uint4 *>(flags));
+    for (int l = 0; l < 4; ++l)
+      if (counts[l] > 0)
+        hipLaunchKernelGGL(k_od_mark, dim3(grid_for(counts[l], 256)), dim3(256), 0, s, counts[l], l & 1, lists[l],
+                           sc->vert_body, sc->tri_body, sc->edge_body, sc->body_fixed, nb, flags);
+    hipLaunchKernelGGL(k_od_row<0>, dim3(nb), dim3(64), 0, s, nb, flags, rcnt, nullptr, nullptr);
+    ABD_TRY(scan_exclusive_i64(ctx, rcnt, roff, nb, roff + nb, s));
+    hipLaunchKernelGGL(k_od_row<1>, dim3(nb), dim3(64), 0, s, nb, flags, nullptr, roff, *keys_out);
+    int64_t *hbuf;
+    ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
+    HIP_TRY(ctx, hipMemcpyAsync(hbuf, roff + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    *n_keys = hbuf[0];
+    return abd_hip_check(ctx, hipGetLastError(), "offdiag");
+  }
   int64_t at = 0;
   for (int l = 0; l < 4; ++l) {
     if (counts[l] > 0)

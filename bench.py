@@ -323,8 +323,9 @@ def run_batched(args):
 
 def run_adjoint(args):
     """Forward rollout of the 500-icosphere drop (friction 0.5) for --steps
-    steps, loss |p_1(T) - target|^2, and its gradient with respect to every
-    body's initial velocity by the checkpointed adjoint."""
+    steps keeping checkpoints, loss |p_1(T) - target|^2, and its gradient
+    with respect to every body's initial velocity by the checkpointed
+    adjoint (each segment re-run once from its checkpoint)."""
     import torch
 
     import paper_2201_10022_amd as abd
@@ -337,9 +338,8 @@ def run_adjoint(args):
     q, qd = q0.clone(), qd0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    newton = 0
-    for _ in range(n):
-        newton += ctx.time_step(sc, P, q, qd)["newton_iters"]
+    # forward, keeping a checkpoint every --checkpoint-every steps
+    ck, newton = ctx.rollout_forward(sc, P, q, qd, n, args.checkpoint_every)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     b1 = int(np.flatnonzero(S["body_fixed"] == 0)[0])
@@ -348,7 +348,8 @@ def run_adjoint(args):
     gT = torch.zeros_like(q)
     gT[b1, :3] = 2.0 * (q[b1, :3] - tq)
     t0 = time.perf_counter()
-    gq, gqd = ctx.rollout_backward(sc, P, q0, qd0, n, args.checkpoint_every, gT, torch.zeros_like(q), args.adj_rtol)
+    gq, gqd = ctx.rollout_backward(sc, P, q0, qd0, n, args.checkpoint_every, gT, torch.zeros_like(q), args.adj_rtol,
+                                   checkpoints=ck)
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
     line = {"metric": "adjoint rollout: time steps differentiated per second (forward re-runs included)",

@@ -276,15 +276,26 @@ int abd_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, c
                      const double *qdot_t, const double *q_next, const double *qbar_next, const double *qdbar_next,
                      double rtol, double *qbar_t, double *qdbar_t, int32_t *pcg_iters, hipStream_t stream);
 
+/* n_steps time steps from (q, qdot) (device [n_bodies][12], in/out),
+ * keeping (q, qdot) before every checkpoint_every-th step in checkpoints
+ * (device, caller-owned, [ceil(n_steps / checkpoint_every)][2][n_bodies][12],
+ * may be NULL) for abd_rollout_backward.  *newton_iters (host, may be NULL)
+ * receives the Newton iterations summed over the steps.  Syncs. */
+int abd_rollout_forward(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot,
+                        int32_t n_steps, int32_t checkpoint_every, double *checkpoints, int64_t *newton_iters,
+                        hipStream_t stream);
+
 /* Gradient of a loss of the state after n_steps time steps from (q0, qdot0):
  * given qbar_T, qdbar_T (the loss gradient with respect to q^n and qdot^n),
- * writes qbar_0, qdbar_0.  Runs the forward steps keeping (q, qdot) every
- * checkpoint_every steps (context workspace), then per segment, last
- * first, re-runs the segment's steps and applies abd_adjoint_step backwards.
- * Syncs. */
+ * writes qbar_0, qdbar_0.  The states every checkpoint_every steps come
+ * from checkpoints (as written by abd_rollout_forward with the same
+ * arguments) or, when it is NULL, from running the forward steps again
+ * (context workspace); then per segment, last first, the segment's steps
+ * are re-run and abd_adjoint_step is applied backwards.  Syncs. */
 int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q0,
-                         const double *qdot0, int32_t n_steps, int32_t checkpoint_every, const double *qbar_T,
-                         const double *qdbar_T, double rtol, double *qbar_0, double *qdbar_0, hipStream_t stream);
+                         const double *qdot0, int32_t n_steps, int32_t checkpoint_every, const double *checkpoints,
+                         const double *qbar_T, const double *qdbar_T, double rtol, double *qbar_0, double *qdbar_0,
+                         hipStream_t stream);
 
 /* Lagged friction (sec. 4, friction potential V_F = sum of mu lambda f0 over
  * the active contact pairs; lagging as in IPC): quantities held fixed over a

@@ -310,13 +310,28 @@ class Context:
                                             _ptr(qdbar), ctypes.byref(it), _stream()))
         return qbar, qdbar, it.value
 
-    def rollout_backward(self, scene, params, q0, qd0, n_steps, checkpoint_every, qbar_T, qdbar_T, rtol=1e-12):
+    def rollout_forward(self, scene, params, q, qd, n_steps, checkpoint_every=10, keep=True):
+        """n_steps time steps on (q, qd) in place; returns the checkpoints
+        (for rollout_backward; None when keep is false) and the summed Newton
+        iterations."""
+        n_ck = max((int(n_steps) + int(checkpoint_every) - 1) // int(checkpoint_every), 1)
+        ck = torch.zeros((n_ck, 2) + tuple(q.shape), dtype=torch.float64, device=q.device) if keep else None
+        nt = ctypes.c_int64(0)
+        prm = make_params(params)
+        self._check(self.L.abd_rollout_forward(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q), _ptr(qd),
+                                               int(n_steps), int(checkpoint_every), _ptr(ck), ctypes.byref(nt),
+                                               _stream()))
+        return ck, nt.value
+
+    def rollout_backward(self, scene, params, q0, qd0, n_steps, checkpoint_every, qbar_T, qdbar_T, rtol=1e-12,
+                         checkpoints=None):
         qbar = torch.zeros_like(q0)
         qdbar = torch.zeros_like(q0)
         prm = make_params(params)
         self._check(self.L.abd_rollout_backward(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q0),
-                                                _ptr(qd0), int(n_steps), int(checkpoint_every), _ptr(qbar_T),
-                                                _ptr(qdbar_T), float(rtol), _ptr(qbar), _ptr(qdbar), _stream()))
+                                                _ptr(qd0), int(n_steps), int(checkpoint_every), _ptr(checkpoints),
+                                                _ptr(qbar_T), _ptr(qdbar_T), float(rtol), _ptr(qbar), _ptr(qdbar),
+                                                _stream()))
         return qbar, qdbar
 
     # -- measurement ---------------------------------------------------
@@ -332,24 +347,24 @@ class Context:
 
 class Rollout(torch.autograd.Function):
     """(q^n, qdot^n) after n time steps from (q0, qdot0), differentiable:
-    the backward pass is abd_rollout_backward (checkpointed adjoint)."""
+    the forward pass keeps checkpoints (abd_rollout_forward), the backward
+    pass is abd_rollout_backward from them (checkpointed adjoint)."""
 
     @staticmethod
     def forward(fctx, q0, qd0, ctx, scene, params, n_steps, checkpoint_every, rtol):
         q, qd = q0.detach().clone(), qd0.detach().clone()
-        for _ in range(n_steps):
-            ctx.time_step(scene, params, q, qd)
-        fctx.save_for_backward(q0.detach(), qd0.detach())
+        ck, _ = ctx.rollout_forward(scene, params, q, qd, n_steps, checkpoint_every)
+        fctx.save_for_backward(q0.detach(), qd0.detach(), ck)
         fctx.args = (ctx, scene, params, n_steps, checkpoint_every, rtol)
         return q, qd
 
     @staticmethod
     def backward(fctx, gq, gqd):
-        q0, qd0 = fctx.saved_tensors
-        ctx, scene, params, n_steps, ck, rtol = fctx.args
+        q0, qd0, ck = fctx.saved_tensors
+        ctx, scene, params, n_steps, every, rtol = fctx.args
         gq = torch.zeros_like(q0) if gq is None else gq.contiguous()
         gqd = torch.zeros_like(q0) if gqd is None else gqd.contiguous()
-        qbar, qdbar = ctx.rollout_backward(scene, params, q0, qd0, n_steps, ck, gq, gqd, rtol)
+        qbar, qdbar = ctx.rollout_backward(scene, params, q0, qd0, n_steps, every, gq, gqd, rtol, checkpoints=ck)
         return qbar, qdbar, None, None, None, None, None, None
 
 

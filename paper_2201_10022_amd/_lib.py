@@ -16,7 +16,7 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_body_mass", "abd_
            "abd_ccd_max_step", "abd_orthogonality", "abd_inertia", "abd_q_tilde", "abd_pcg_solve",
            "abd_newton_step", "abd_time_step", "abd_friction_lag", "abd_friction_grad_hess",
            "abd_friction_energy", "abd_friction_begin_step", "abd_friction_end_step", "abd_adjoint_step",
-           "abd_rollout_backward", "abd_profile", "abd_profile_query"]
+           "abd_rollout_forward", "abd_rollout_backward", "abd_profile", "abd_profile_query"]
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -84,7 +84,9 @@ SIGNATURES = {
     "abd_friction_begin_step": ([_vp, _PS, _PP, _vp, _pi64, _vp], ctypes.c_int),
     "abd_friction_end_step": ([_vp], ctypes.c_int),
     "abd_adjoint_step": ([_vp, _PS, _PP, _vp, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _pi32, _vp], ctypes.c_int),
-    "abd_rollout_backward": ([_vp, _PS, _PP, _vp, _vp, _i32, _i32, _vp, _vp, _dbl, _vp, _vp, _vp], ctypes.c_int),
+    "abd_rollout_forward": ([_vp, _PS, _PP, _vp, _vp, _i32, _i32, _vp, ctypes.POINTER(ctypes.c_int64), _vp],
+                            ctypes.c_int),
+    "abd_rollout_backward": ([_vp, _PS, _PP, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _dbl, _vp, _vp, _vp], ctypes.c_int),
     "abd_profile": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "abd_profile_query": ([_vp, ctypes.c_char_p, ctypes.POINTER(_dbl), _pi64, _pi64], ctypes.c_int),
 }

@@ -168,10 +168,35 @@ extern "C" int abd_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_par
   return ABD_OK;
 }
 
+extern "C" int abd_rollout_forward(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q,
+                                   double *qdot, int32_t n_steps, int32_t checkpoint_every, double *checkpoints,
+                                   int64_t *newton_iters, hipStream_t stream) {
+  if (!ctx || !sc || !prm || !q || !qdot || !sc->mass || !sc->volume)
+    return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_forward: null");
+  if (n_steps < 0 || checkpoint_every < 1) return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_forward: bad sizes");
+  hipStream_t s = stream;
+  const int n12 = 12 * sc->n_bodies;
+  const size_t vb = sizeof(double) * (size_t)n12;
+  int64_t tot = 0;
+  for (int t = 0; t < n_steps; ++t) {
+    if (checkpoints && t % checkpoint_every == 0) {
+      double *c = checkpoints + 2 * (size_t)n12 * (t / checkpoint_every);
+      HIP_TRY(ctx, hipMemcpyAsync(c, q, vb, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(c + n12, qdot, vb, hipMemcpyDeviceToDevice, s));
+    }
+    abd_stats st;
+    ABD_TRY(abd_time_step(ctx, sc, prm, q, qdot, &st, s));
+    tot += st.newton_iters;
+  }
+  if (newton_iters) *newton_iters = tot;
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return ABD_OK;
+}
+
 extern "C" int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q0,
                                     const double *qdot0, int32_t n_steps, int32_t checkpoint_every,
-                                    const double *qbar_T, const double *qdbar_T, double rtol, double *qbar_0,
-                                    double *qdbar_0, hipStream_t stream) {
+                                    const double *checkpoints, const double *qbar_T, const double *qdbar_T,
+                                    double rtol, double *qbar_0, double *qdbar_0, hipStream_t stream) {
   if (!ctx || !sc || !prm || !q0 || !qdot0 || !qbar_T || !qdbar_T || !qbar_0 || !qdbar_0 || !sc->mass ||
       !sc->volume)
     return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_backward: null");
@@ -181,8 +206,9 @@ extern "C" int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd
   const size_t vb = sizeof(double) * (size_t)n12;
   const int K = checkpoint_every;
   const int n_ck = (n_steps + K - 1) / K;
-  double *ck, *seg, *q, *qd, *qb, *qdb, *qb2, *qdb2;
-  ABD_TRY(ws(ctx, "ro_ck", 2 * (size_t)n12 * (n_ck > 0 ? n_ck : 1), &ck, s));
+  double *ckw, *seg, *q, *qd, *qb, *qdb, *qb2, *qdb2;
+  const double *ck = checkpoints;
+  if (!ck) ABD_TRY(ws(ctx, "ro_ck", 2 * (size_t)n12 * (n_ck > 0 ? n_ck : 1), &ckw, s));
   ABD_TRY(ws(ctx, "ro_seg", 2 * (size_t)n12 * (K + 1), &seg, s));
   ABD_TRY(ws(ctx, "ro_q", n12, &q, s));
   ABD_TRY(ws(ctx, "ro_qd", n12, &qd, s));
@@ -190,16 +216,12 @@ extern "C" int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd
   ABD_TRY(ws(ctx, "ro_qdb", n12, &qdb, s));
   ABD_TRY(ws(ctx, "ro_qb2", n12, &qb2, s));
   ABD_TRY(ws(ctx, "ro_qdb2", n12, &qdb2, s));
-  // forward, keeping (q, qdot) every K steps
-  HIP_TRY(ctx, hipMemcpyAsync(q, q0, vb, hipMemcpyDeviceToDevice, s));
-  HIP_TRY(ctx, hipMemcpyAsync(qd, qdot0, vb, hipMemcpyDeviceToDevice, s));
-  for (int t = 0; t < n_steps; ++t) {
-    if (t % K == 0) {
-      double *c = ck + 2 * (size_t)n12 * (t / K);
-      HIP_TRY(ctx, hipMemcpyAsync(c, q, vb, hipMemcpyDeviceToDevice, s));
-      HIP_TRY(ctx, hipMemcpyAsync(c + n12, qd, vb, hipMemcpyDeviceToDevice, s));
-    }
-    ABD_TRY(abd_time_step(ctx, sc, prm, q, qd, nullptr, s));
+  if (!ck) {
+    // forward, keeping (q, qdot) every K steps
+    HIP_TRY(ctx, hipMemcpyAsync(q, q0, vb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(qd, qdot0, vb, hipMemcpyDeviceToDevice, s));
+    ABD_TRY(abd_rollout_forward(ctx, sc, prm, q, qd, n_steps, K, ckw, nullptr, s));
+    ck = ckw;
   }
   HIP_TRY(ctx, hipMemcpyAsync(qb, qbar_T, vb, hipMemcpyDeviceToDevice, s));
   HIP_TRY(ctx, hipMemcpyAsync(qdb, qdbar_T, vb, hipMemcpyDeviceToDevice, s));

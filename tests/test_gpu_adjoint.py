@@ -118,6 +118,12 @@ def test_rollout_checkpoint_spacing_and_autograd(abd, ctx):
     for ck in (4, 5, 12, 20):
         got = ctx.rollout_backward(sc, P, q0, qd0, n, ck, gT, z)
         assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    # checkpoints kept by the forward rollout give the same gradient
+    qf, qdf = q0.clone(), qd0.clone()
+    ckp, nt = ctx.rollout_forward(sc, P, qf, qdf, n, 5)
+    assert nt >= n
+    got = ctx.rollout_backward(sc, P, q0, qd0, n, 5, gT, z, checkpoints=ckp)
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
     qa = q0.clone().requires_grad_(True)
     qda = qd0.clone().requires_grad_(True)
     qT, qdT = abd.rollout(ctx, sc, P, qa, qda, n, checkpoint_every=4)

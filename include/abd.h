@@ -277,9 +277,10 @@ int abd_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, c
                      double rtol, double *qbar_t, double *qdbar_t, int32_t *pcg_iters, hipStream_t stream);
 
 /* n_steps time steps from (q, qdot) (device [n_bodies][12], in/out),
- * keeping (q, qdot) before every checkpoint_every-th step in checkpoints
- * (device, caller-owned, [ceil(n_steps / checkpoint_every)][2][n_bodies][12],
- * may be NULL) for abd_rollout_backward.  *newton_iters (host, may be NULL)
+ * keeping (q, qdot) before every checkpoint_every-th step, and after the
+ * last step, in checkpoints (device, caller-owned,
+ * [ceil(n_steps / checkpoint_every) + 1][2][n_bodies][12], may be NULL) for
+ * abd_rollout_backward.  *newton_iters (host, may be NULL)
  * receives the Newton iterations summed over the steps.  Syncs. */
 int abd_rollout_forward(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot,
                         int32_t n_steps, int32_t checkpoint_every, double *checkpoints, int64_t *newton_iters,
@@ -291,7 +292,8 @@ int abd_rollout_forward(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm
  * from checkpoints (as written by abd_rollout_forward with the same
  * arguments) or, when it is NULL, from running the forward steps again
  * (context workspace); then per segment, last first, the segment's steps
- * are re-run and abd_adjoint_step is applied backwards.  Syncs. */
+ * are re-run (not with checkpoint_every = 1: every state is kept) and
+ * abd_adjoint_step is applied backwards.  Syncs. */
 int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q0,
                          const double *qdot0, int32_t n_steps, int32_t checkpoint_every, const double *checkpoints,
                          const double *qbar_T, const double *qdbar_T, double rtol, double *qbar_0, double *qdbar_0,

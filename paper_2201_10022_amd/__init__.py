@@ -314,7 +314,7 @@ class Context:
         """n_steps time steps on (q, qd) in place; returns the checkpoints
         (for rollout_backward; None when keep is false) and the summed Newton
         iterations."""
-        n_ck = max((int(n_steps) + int(checkpoint_every) - 1) // int(checkpoint_every), 1)
+        n_ck = (int(n_steps) + int(checkpoint_every) - 1) // int(checkpoint_every) + 1
         ck = torch.zeros((n_ck, 2) + tuple(q.shape), dtype=torch.float64, device=q.device) if keep else None
         nt = ctypes.c_int64(0)
         prm = make_params(params)

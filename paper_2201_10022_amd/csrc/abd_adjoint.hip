@@ -188,6 +188,11 @@ extern "C" int abd_rollout_forward(abd_ctx *ctx, const abd_scene *sc, const abd_
     ABD_TRY(abd_time_step(ctx, sc, prm, q, qdot, &st, s));
     tot += st.newton_iters;
   }
+  if (checkpoints) {  // the final state after the last checkpoint
+    double *c = checkpoints + 2 * (size_t)n12 * ((n_steps + checkpoint_every - 1) / checkpoint_every);
+    HIP_TRY(ctx, hipMemcpyAsync(c, q, vb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(c + n12, qdot, vb, hipMemcpyDeviceToDevice, s));
+  }
   if (newton_iters) *newton_iters = tot;
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return ABD_OK;
@@ -208,7 +213,7 @@ extern "C" int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd
   const int n_ck = (n_steps + K - 1) / K;
   double *ckw, *seg, *q, *qd, *qb, *qdb, *qb2, *qdb2;
   const double *ck = checkpoints;
-  if (!ck) ABD_TRY(ws(ctx, "ro_ck", 2 * (size_t)n12 * (n_ck > 0 ? n_ck : 1), &ckw, s));
+  if (!ck) ABD_TRY(ws(ctx, "ro_ck", 2 * (size_t)n12 * (n_ck + 1), &ckw, s));
   ABD_TRY(ws(ctx, "ro_seg", 2 * (size_t)n12 * (K + 1), &seg, s));
   ABD_TRY(ws(ctx, "ro_q", n12, &q, s));
   ABD_TRY(ws(ctx, "ro_qd", n12, &qd, s));
@@ -227,6 +232,13 @@ extern "C" int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd
   HIP_TRY(ctx, hipMemcpyAsync(qdb, qdbar_T, vb, hipMemcpyDeviceToDevice, s));
   for (int c = n_ck - 1; c >= 0; --c) {
     const int t0 = c * K, t1 = (t0 + K < n_steps) ? t0 + K : n_steps;
+    if (K == 1) {  // every state is a checkpoint: nothing to re-run
+      const double *st = ck + 2 * (size_t)n12 * c, *sn = ck + 2 * (size_t)n12 * (c + 1);
+      ABD_TRY(op_adjoint_step(ctx, sc, prm, st, st + n12, sn, qb, qdb, rtol, prm->max_pcg, qb2, qdb2, nullptr, s));
+      std::swap(qb, qb2);
+      std::swap(qdb, qdb2);
+      continue;
+    }
     // re-run the segment, keeping every state
     const double *cs = ck + 2 * (size_t)n12 * c;
     HIP_TRY(ctx, hipMemcpyAsync(seg, cs, vb, hipMemcpyDeviceToDevice, s));

@@ -124,6 +124,12 @@ def test_rollout_checkpoint_spacing_and_autograd(abd, ctx):
     assert nt >= n
     got = ctx.rollout_backward(sc, P, q0, qd0, n, 5, gT, z, checkpoints=ckp)
     assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    assert torch.equal(ckp[-1, 0], qf) and torch.equal(ckp[-1, 1], qdf)
+    # every state kept: no re-runs
+    qf, qdf = q0.clone(), qd0.clone()
+    ck1, _ = ctx.rollout_forward(sc, P, qf, qdf, n, 1)
+    got = ctx.rollout_backward(sc, P, q0, qd0, n, 1, gT, z, checkpoints=ck1)
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
     qa = q0.clone().requires_grad_(True)
     qda = qd0.clone().requires_grad_(True)
     qT, qdT = abd.rollout(ctx, sc, P, qa, qda, n, checkpoint_every=4)

@@ -263,15 +263,19 @@ int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, doub
  * with respect to (q^{t+1}, qdot^{t+1}): solves H l = qbar_next +
  * qdbar_next/dt with H the unprojected Hessian of the incremental potential
  * at q_next (barrier, orthogonality, inertia and, when mu > 0, the friction
- * lagged at q_t; it may be indefinite) by MINRES preconditioned with the
- * diagonal blocks of the projected Hessian, to relative residual rtol (in
- * the preconditioner's norm), and writes
+ * lagged at q_t; it may be indefinite), to relative residual rtol, with
+ * the diagonal blocks of the projected Hessian as block-Jacobi
+ * preconditioner: first by preconditioned conjugate gradients (as
+ * abd_pcg_solve); if CG meets non-positive curvature or reaches its
+ * iteration cap, again by MINRES (residual in the preconditioner's norm),
+ * which needs symmetry only.  Then it writes
  * qbar_t = M l + H_D l - C_lag^T l - qdbar_next/dt and qdbar_t = dt M l
  * (H_D the friction Hessian; C_lag the derivative of the friction gradient
  * through the lagged normal force, tangent basis and closest-point weights,
  * which are functions of q_t).  Zero on fixed bodies.  All arrays
  * [n_bodies][12]; outputs must not alias inputs.  Syncs; *pcg_iters (host,
- * may be NULL) receives the MINRES iteration count. */
+ * may be NULL) receives the iteration count: CG's, plus MINRES's when CG
+ * failed. */
 int abd_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q_t,
                      const double *qdot_t, const double *q_next, const double *qbar_next, const double *qdbar_next,
                      double rtol, double *qbar_t, double *qdbar_t, int32_t *pcg_iters, hipStream_t stream);

@@ -129,12 +129,28 @@ int op_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, co
                      s, fr));
   ABD_TRY(op_read_err(ctx, s));
 
-  // H l = qbar^{t+1} + qdbar^{t+1} / dt; H may be indefinite (the barrier's
-  // curvature is not), so MINRES
+  // H l = qbar^{t+1} + qdbar^{t+1} / dt.  H is positive definite at a
+  // strict local minimum, so conjugate gradients first (the solver of the
+  // forward pass, its preconditioner from the projected diagonal blocks);
+  // near contact the barrier's curvature can make H indefinite: if CG meets
+  // a non-positive curvature or runs out of iterations, MINRES, which needs
+  // symmetry only.
   hipLaunchKernelGGL(k_adj_rhs, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_fixed, qbar_next, qdbar_next,
                      1.0 / prm->dt, a);
   int its = 0;
-  ABD_TRY(op_minres(ctx, sc, diag, off, keys, nk, pre, a, l, rtol, max_iter, &its, s));
+  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, a, l, rtol, max_iter, &its, s, nullptr, pre));
+  int *herr;
+  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&herr)));
+  ABD_TRY(err_enqueue(ctx, herr, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  if ((herr[0] & (4 | 8)) || its >= max_iter) {
+    int *errf;
+    ABD_TRY(ws(ctx, "err_flag", 1, &errf, s));
+    HIP_TRY(ctx, hipMemsetAsync(errf, 0, sizeof(int), s));
+    int its2 = 0;
+    ABD_TRY(op_minres(ctx, sc, diag, off, keys, nk, pre, a, l, rtol, max_iter, &its2, s));
+    its += its2;
+  }
   ABD_TRY(op_read_err(ctx, s));
   if (iters) *iters = its;
   ABD_TRY(zero_d(ctx, hdl, n12, s));

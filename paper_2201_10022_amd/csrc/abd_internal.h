@@ -191,7 +191,7 @@ int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, con
 // x0 (may be NULL = 0, may alias p): initial guess
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *p, double rtol, int max_iter, int *iters, hipStream_t s,
-           const double *x0 = nullptr);
+           const double *x0 = nullptr, const double *pre_diag = nullptr);  // pre_diag: preconditioner blocks (NULL: diag)
 // preconditioned MINRES on the (possibly indefinite) symmetric block matrix,
 // block-Jacobi preconditioner from the SPD diagonal blocks pre_diag; stops
 // at |r|_{P} <= rtol |b|_{P} (syncs every iteration)

@@ -1046,7 +1046,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
 
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *x_out, double rtol, int max_iter, int *iters, hipStream_t s,
-           const double *x0) {
+           const double *x0, const double *pre_diag) {
   const int nb = sc->n_bodies;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   *iters = 0;
@@ -1091,7 +1091,8 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(ws(ctx, "pcg_s_stop", S, &scs.stop, s));
   ABD_TRY(ws(ctx, "pcg_s_final", S, &scs.it_final, s));
   ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
-  hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed, diag, inv, err);
+  hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed,
+                     pre_diag ? pre_diag : diag, inv, err);
   hipLaunchKernelGGL(k_pcg_scene_blocks, dim3(grid_for(S, 256)), dim3(256), 0, s, S, sbo, ucnt, scnt);
   ABD_TRY(scan_exclusive_i64(ctx, ucnt, u_off, S, u_off + S, s));
   ABD_TRY(scan_exclusive_i64(ctx, scnt, s_off, S, s_off + S, s));

@@ -187,6 +187,8 @@ struct LocalOut {
   double H[78];
 };
 
+__host__ __device__ inline void project_translation_invariant(double *H);
+
 // local barrier energy, gradient and (projected) Hessian of one pair
 __host__ __device__ inline void barrier_local(int is_ee, int type, const d3 X[4], const double *xb4, double dhat, double kappa,
                               int project, LocalOut &o) {
@@ -296,7 +298,13 @@ __host__ __device__ inline void barrier_local(int is_ee, int type, const d3 X[4]
             o.H[S12::at(i, j)] += kb1 * (gc[i] * gs[j] + gs[i] * gc[j]) + kB2 * gc[i] * gc[j] + kB1 * hc;
           }
   }
-  if (!project) return;
+  if (project) project_translation_invariant(o.H);
+}
+
+// PSD projection of a packed 12x12 local Hessian whose null space holds the
+// common translations of the 4 vertices: H = Q H9 Q^T with the 4-point
+// Helmert basis Q (12x9), so H_+ = Q (H9)_+ Q^T.  In place.
+__host__ __device__ inline void project_translation_invariant(double *H) {
   // H9 = Q^T H Q with Q[(k,c),(m,c)] = helm(m,k)
   double H9[45];
   {
@@ -309,7 +317,7 @@ __host__ __device__ inline void barrier_local(int is_ee, int type, const d3 X[4]
         for (int j = 0; j < 12; ++j) {
           double acc = 0.0;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) acc += helm(mm, k) * o.H[S12::at(3 * k + c, j)];
+          for (int k = 0; k < 4; ++k) acc += helm(mm, k) * H[S12::at(3 * k + c, j)];
           T[3 * mm + c][j] = acc;
         }
 #pragma unroll
@@ -343,7 +351,7 @@ __host__ __device__ inline void barrier_local(int is_ee, int type, const d3 X[4]
           for (int mm = 0; mm < 3; ++mm)
 #pragma unroll
             for (int nn = 0; nn < 3; ++nn) acc += helm(mm, k) * helm(nn, l) * H9[S9::at(3 * mm + c, 3 * nn + c2)];
-          o.H[S12::at(i, j)] = acc;
+          H[S12::at(i, j)] = acc;
         }
 }
 

@@ -112,10 +112,13 @@ __global__ void __launch_bounds__(64) k_barrier_local(const int64_t *n_act_dev, 
     return;
   }
   LocalOut o;
-  barrier_local(is_ee, ty, X, xb4, dhat, kappa, project, o);
+  barrier_local(is_ee, ty, X, xb4, dhat, kappa, 0, o);
+  // energy and gradient leave before the projection, whose eigen-solve
+  // needs the registers
   e_out[a] = o.e;
 #pragma unroll
   for (int i = 0; i < 12; ++i) g_out[12 * a + i] = o.g[i];
+  if (project) project_translation_invariant(o.H);
 #pragma unroll
   for (int i = 0; i < 78; ++i) H_out[78 * a + i] = o.H[i];
 }

@@ -103,19 +103,30 @@ __global__ void __launch_bounds__(64) k_body_pairs(int nb, const int32_t *body_s
   const bool fa = fixed[a] != 0;
   int64_t base = WRITE ? off[a] : 0;
   int64_t c = 0;
-  for (int b0 = a + 1; b0 < end; b0 += 64) {
-    const int b = b0 + (int)threadIdx.x;
-    bool ok = false;
-    if (b < end && !(fa && fixed[b])) ok = box_overlap(ba, bb + 6 * (int64_t)b);
-    const unsigned long long m = __ballot(ok);
-    if (WRITE && ok) {
-      const int64_t pos = base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull));
-      if (pos < cap) {  // (beyond the capacity the caller sizes again and repeats)
-        pairs[2 * pos] = a;
-        pairs[2 * pos + 1] = b;
-      }
+  // BPU chunks of 64 candidates per trip: their box loads are issued
+  // together, so the wave of body 0 (the longest scan) waits on one load
+  // latency per BPU chunks rather than per chunk
+  constexpr int BPU = 4;
+  for (int b0 = a + 1; b0 < end; b0 += 64 * BPU) {
+    bool ok[BPU];
+#pragma unroll
+    for (int u = 0; u < BPU; ++u) {
+      const int b = b0 + 64 * u + (int)threadIdx.x;
+      ok[u] = b < end && !(fa && fixed[b]) && box_overlap(ba, bb + 6 * (int64_t)b);
     }
-    c += __popcll(m);
+#pragma unroll
+    for (int u = 0; u < BPU; ++u) {
+      const int b = b0 + 64 * u + (int)threadIdx.x;
+      const unsigned long long m = __ballot(ok[u]);
+      if (WRITE && ok[u]) {
+        const int64_t pos = base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull));
+        if (pos < cap) {  // (beyond the capacity the caller sizes again and repeats)
+          pairs[2 * pos] = a;
+          pairs[2 * pos + 1] = b;
+        }
+      }
+      c += __popcll(m);
+    }
   }
   if (!WRITE && threadIdx.x == 0) cnt[a] = c;
 }

@@ -73,14 +73,22 @@ __global__ void k_add_i64(const int64_t *a, const int64_t *b, int64_t *o) { *o =
 // contiguous chunk, the chunk sums are scanned across the block, then each
 // thread rewrites its chunk.  Works in place; `total` may be out + n.
 constexpr int SCAN1_T = 1024;
+constexpr int SCAN1_U = 8;  // loads in flight per thread
 constexpr int64_t SCAN1_MAX = 1 << 16;
 __global__ void __launch_bounds__(SCAN1_T) k_scan1(const int64_t *in, int64_t *out, int64_t n, int64_t *total) {
   __shared__ int64_t sw[SCAN1_T / 64 + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t per = (n + SCAN1_T - 1) / SCAN1_T;
   const int64_t lo = t * per < n ? t * per : n, hi = lo + per < n ? lo + per : n;
+  // each thread's range is read in groups of SCAN1_U independent loads
   int64_t own = 0;
-  for (int64_t i = lo; i < hi; ++i) own += in[i];
+  for (int64_t i0 = lo; i0 < hi; i0 += SCAN1_U) {
+    int64_t v[SCAN1_U];
+#pragma unroll
+    for (int k = 0; k < SCAN1_U; ++k) v[k] = i0 + k < hi ? in[i0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < SCAN1_U; ++k) own += v[k];
+  }
   int64_t x = own;  // inclusive scan over the wave
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -100,10 +108,15 @@ __global__ void __launch_bounds__(SCAN1_T) k_scan1(const int64_t *in, int64_t *o
   }
   __syncthreads();
   int64_t run = sw[w] + x - own;
-  for (int64_t i = lo; i < hi; ++i) {
-    const int64_t v = in[i];
-    out[i] = run;
-    run += v;
+  for (int64_t i0 = lo; i0 < hi; i0 += SCAN1_U) {
+    int64_t v[SCAN1_U];
+#pragma unroll
+    for (int k = 0; k < SCAN1_U; ++k) v[k] = i0 + k < hi ? in[i0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < SCAN1_U; ++k) {
+      if (i0 + k < hi) out[i0 + k] = run;  // (in place: the group's inputs are already read)
+      run += v[k];
+    }
   }
   if (t == 0 && total) *total = sw[SCAN1_T / 64];
 }

@@ -996,18 +996,27 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   int done = 0;
   bool all = false;
   bool profiled = false;
-  for (int round = 0; round < max_rounds && !all; ++round) {
-    // a long replay while the last solve's count says at least that many
-    // iterations remain, else a short one
-    const int gi = ctx->pcg_hint - done >= ITER_G[1] ? 1 : 0;
-    hipEvent_t pe = prof_begin(ctx, s);
-    profiled = profiled || pe != nullptr;
-    if (exec[gi])
-      HIP_TRY(ctx, hipGraphLaunch(exec[gi], s));
-    else
-      enqueue(s, ITER_G[gi]);
-    prof_end(ctx, pe, "pcg_round", 0, s);
-    HIP_TRY(ctx, hipGetLastError());
+  for (int round = 0; round < max_rounds && !all;) {
+    // replays are queued back to back, without reading the state in
+    // between, while the last solve's count says that at least a short
+    // replay's worth of iterations remains after them: a long replay while
+    // that many remain, else a short one.  Launches past a scene's stop
+    // return at once, so queueing too many costs little next to a host
+    // round trip per replay.
+    int planned = 0;
+    do {
+      const int gi = ctx->pcg_hint - (done + planned) >= ITER_G[1] ? 1 : 0;
+      hipEvent_t pe = prof_begin(ctx, s);
+      profiled = profiled || pe != nullptr;
+      if (exec[gi])
+        HIP_TRY(ctx, hipGraphLaunch(exec[gi], s));
+      else
+        enqueue(s, ITER_G[gi]);
+      prof_end(ctx, pe, "pcg_round", 0, s);
+      HIP_TRY(ctx, hipGetLastError());
+      planned += ITER_G[gi];
+      ++round;
+    } while (round < max_rounds && ctx->pcg_hint - (done + planned) >= ITER_G[0]);
     HIP_TRY(ctx, hipMemcpyAsync(h, st, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     all = h[1] >= S;

@@ -357,9 +357,13 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   hipLaunchKernelGGL(k_scene_end, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, sc->body_scene, send);
   hipLaunchKernelGGL(k_body_pairs<0>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
                      skip_scene, bcnt, nullptr, nullptr);
-  ABD_TRY(scan_exclusive_i64(ctx, bcnt, boff, nb, btot, s));
-  int64_t *hbuf;
-  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
+  // the totals' scans also write them to mapped host memory (hbuf, slot
+  // for slot like btot), so reading them needs no copy
+  int64_t *hbuf, *hbuf_d;
+  ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
+  hbuf += MIR_BROAD;
+  hbuf_d += MIR_BROAD;
+  ABD_TRY(scan_exclusive_i64(ctx, bcnt, boff, nb, btot, s, hbuf_d));
   // Body pairs and their list regions are sized by the last call's count
   // (with room to grow) so that one synchronisation reads both totals; a
   // count beyond the capacity repeats the two steps at the exact size.
@@ -377,8 +381,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
                        skip_scene, nullptr, boff, bpairs, cap_bp);
     hipLaunchKernelGGL(k_list_caps, dim3(grid_for(cap_bp, 256)), dim3(256), 0, s, cap_bp, btot, bpairs,
                        sc->body_vert_off, sc->body_tri_off, sc->body_edge_off, cap);
-    ABD_TRY(scan_exclusive_i64(ctx, cap, region, cap_bp, rtot, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hbuf, btot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    ABD_TRY(scan_exclusive_i64(ctx, cap, region, cap_bp, rtot, s, hbuf_d + 1));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     nbp = hbuf[0];
     list_total = hbuf[1];
@@ -406,8 +409,8 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_tpt_off", 2 * nbp, &tpt_off, s));
   ABD_TRY(ws(ctx, "bp_tee_off", nbp, &tee_off, s));
   hipLaunchKernelGGL(k_sub_tiles, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, llen, tpt, tee);
-  ABD_TRY(scan_exclusive_i64(ctx, tpt, tpt_off, 2 * nbp, ttot, s));
-  ABD_TRY(scan_exclusive_i64(ctx, tee, tee_off, nbp, ttot + 1, s));
+  ABD_TRY(scan_exclusive_i64(ctx, tpt, tpt_off, 2 * nbp, ttot, s, hbuf_d + 2));
+  ABD_TRY(scan_exclusive_i64(ctx, tee, tee_off, nbp, ttot + 1, s, hbuf_d + 3));
   const std::string key_tp = std::string(tag) + "_tpt", key_te = std::string(tag) + "_tee";
   int64_t cap_tp = ctx->cap_hint[key_tp], cap_te = ctx->cap_hint[key_te];
   cap_tp = cap_tp + cap_tp / 4 + 256;
@@ -429,12 +432,11 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, tee, tee_off, tsub_ee, cap_te);
     hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)cap_te), dim3(64), 0, s, 1, tsub_ee, cap_te, lstart, llen,
                        lists, ebox, ebox, cee, nullptr, nullptr, ttot + 1);
-    ABD_TRY(scan_exclusive_i64(ctx, cpt, opt, cap_tp, otot, s));
-    ABD_TRY(scan_exclusive_i64(ctx, cee, oee, cap_te, otot + 1, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hbuf, ttot, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    ABD_TRY(scan_exclusive_i64(ctx, cpt, opt, cap_tp, otot, s, hbuf_d + 4));
+    ABD_TRY(scan_exclusive_i64(ctx, cee, oee, cap_te, otot + 1, s, hbuf_d + 5));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    ntile_pt = hbuf[0];
-    ntile_ee = hbuf[1];
+    ntile_pt = hbuf[2];
+    ntile_ee = hbuf[3];
     if (ntile_pt <= cap_tp && ntile_ee <= cap_te) break;
     if (pass > 0) return abd_fail(ctx, ABD_E_INVALID, "candidates: tile count changed between passes");
     cap_tp = ntile_pt > cap_tp ? ntile_pt : cap_tp;
@@ -442,8 +444,8 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   }
   ctx->cap_hint[key_tp] = ntile_pt;
   ctx->cap_hint[key_te] = ntile_ee;
-  *n_pt = hbuf[2];
-  *n_ee = hbuf[3];
+  *n_pt = hbuf[4];
+  *n_ee = hbuf[5];
   std::string tpt_name = std::string(tag) + "_pt", tee_name = std::string(tag) + "_ee";
   ABD_TRY(ws(ctx, tpt_name.c_str(), 2 * (*n_pt) + 2, pt_out, s));
   ABD_TRY(ws(ctx, tee_name.c_str(), 2 * (*n_ee) + 2, ee_out, s));
@@ -557,14 +559,13 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
       if (counts[l] > 0)
         hipLaunchKernelGGL(k_od_mark, dim3(grid_for(counts[l], 256)), dim3(256), 0, s, counts[l], l & 1, lists[l],
                            sc->vert_body, sc->tri_body, sc->edge_body, sc->body_fixed, nb, flags);
+    int64_t *hbuf, *hbuf_d;
+    ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
     hipLaunchKernelGGL(k_od_row<0>, dim3(nb), dim3(64), 0, s, nb, flags, rcnt, nullptr, nullptr);
-    ABD_TRY(scan_exclusive_i64(ctx, rcnt, roff, nb, roff + nb, s));
+    ABD_TRY(scan_exclusive_i64(ctx, rcnt, roff, nb, roff + nb, s, hbuf_d + MIR_OFFDIAG));
     hipLaunchKernelGGL(k_od_row<1>, dim3(nb), dim3(64), 0, s, nb, flags, nullptr, roff, *keys_out);
-    int64_t *hbuf;
-    ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
-    HIP_TRY(ctx, hipMemcpyAsync(hbuf, roff + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    *n_keys = hbuf[0];
+    *n_keys = hbuf[MIR_OFFDIAG];
     return abd_hip_check(ctx, hipGetLastError(), "offdiag");
   }
   int64_t at = 0;
@@ -580,13 +581,12 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   ABD_TRY(ws_get(ctx, "od_tmp", tmp_bytes + 16, &tmp, s));
   HIP_TRY(ctx, rocprim::radix_sort_keys(tmp, tmp_bytes, k, k2, (size_t)n, 0, 64, s));
   hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, n, k2, flag);
-  ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s));
+  int64_t *hbuf, *hbuf_d;
+  ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
+  ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s, hbuf_d + MIR_OFFDIAG));
   hipLaunchKernelGGL(k_unique_write, dim3(grid_for(n, 256)), dim3(256), 0, s, n, k2, flag, pos, *keys_out);
-  int64_t *hbuf;
-  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
-  HIP_TRY(ctx, hipMemcpyAsync(hbuf, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  *n_keys = hbuf[0];
+  *n_keys = hbuf[MIR_OFFDIAG];
   return abd_hip_check(ctx, hipGetLastError(), "offdiag");
 }
 
@@ -666,13 +666,13 @@ int op_candidates_within(abd_ctx *ctx, const abd_scene *sc, const double *x, dou
   }
   hipLaunchKernelGGL(k_static_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, n_spt, n, spt, see, sc->tris, sc->edges,
                      x, inflate, flag);
-  ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s));
-  int64_t *h;
-  ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
-  HIP_TRY(ctx, hipMemcpyAsync(h, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  if (n_see > 0) HIP_TRY(ctx, hipMemcpyAsync(h + 1, pos + n_spt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  // total and the PT part pos[n_spt], written to mapped host memory by the scan
+  int64_t *h, *h_d;
+  ABD_TRY(mirror_get(ctx, &h, &h_d));
+  h += MIR_COMPACT;
+  ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s, h_d + MIR_COMPACT, n_spt));
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  const int64_t keep = h[0], keep_pt = n_see > 0 ? h[1] : h[0];
+  const int64_t keep = h[0], keep_pt = h[1];
   ABD_TRY(ws(ctx, pn.c_str(), 2 * keep_pt + 2, pt_out, s));
   ABD_TRY(ws(ctx, en.c_str(), 2 * (keep - keep_pt) + 2, ee_out, s));
   const int64_t *nkp = n_see > 0 ? pos + n_spt : tot;

@@ -54,19 +54,47 @@ int pinned_get(abd_ctx *ctx, size_t bytes, void **out) {
   return ABD_OK;
 }
 
-int pinned_get_nt(abd_ctx *ctx, size_t bytes, void **out) {
+int pinned_get_nt(abd_ctx *ctx, size_t bytes, void **out, void **dev) {
   if (ctx->pinned_nt_bytes < bytes) {
-    if (ctx->pinned_nt) HIP_TRY(ctx, hipHostFree(ctx->pinned_nt));
-    ctx->pinned_nt = nullptr;
+    // growing waits for queued work that may still write the old area
+    if (ctx->pinned_nt) {
+      HIP_TRY(ctx, hipDeviceSynchronize());
+      HIP_TRY(ctx, hipHostFree(ctx->pinned_nt));
+    }
+    ctx->pinned_nt = ctx->pinned_nt_d = nullptr;
     size_t nb = bytes < 4096 ? 4096 : bytes;
-    HIP_TRY(ctx, hipHostMalloc(&ctx->pinned_nt, nb, hipHostMallocDefault));
+    HIP_TRY(ctx, hipHostMalloc(&ctx->pinned_nt, nb, hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_TRY(ctx, hipHostGetDevicePointer(&ctx->pinned_nt_d, ctx->pinned_nt, 0));
     ctx->pinned_nt_bytes = nb;
   }
   *out = ctx->pinned_nt;
+  if (dev) *dev = ctx->pinned_nt_d;
   return ABD_OK;
 }
 
-__global__ void k_add_i64(const int64_t *a, const int64_t *b, int64_t *o) { *o = *a + *b; }
+int mirror_get(abd_ctx *ctx, int64_t **host, int64_t **dev) {
+  if (!ctx->mirror_h) {
+    void *h = nullptr, *d = nullptr;
+    HIP_TRY(ctx, hipHostMalloc(&h, MIRROR_SLOTS * sizeof(int64_t), hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_TRY(ctx, hipHostGetDevicePointer(&d, h, 0));
+    ctx->mirror_h = static_cast<int64_t *>(h);
+    ctx->mirror_d = static_cast<int64_t *>(d);
+  }
+  *host = ctx->mirror_h;
+  *dev = ctx->mirror_d;
+  return ABD_OK;
+}
+
+// total and split value of a scan done by the library (single thread)
+__global__ void k_scan_tail(const int64_t *out, const int64_t *last_in, int64_t n, int64_t *total, int64_t *host,
+                            int64_t split) {
+  const int64_t v = out[n - 1] + *last_in;
+  if (total) *total = v;
+  if (host) {
+    host[0] = v;
+    if (split >= 0) host[1] = split < n ? out[split] : v;
+  }
+}
 
 // Exclusive scan of up to SCAN1_MAX values by one block (one launch; the
 // scans here are mostly per body or per scene): each thread sums a
@@ -75,7 +103,8 @@ __global__ void k_add_i64(const int64_t *a, const int64_t *b, int64_t *o) { *o =
 constexpr int SCAN1_T = 1024;
 constexpr int SCAN1_U = 8;  // loads in flight per thread
 constexpr int64_t SCAN1_MAX = 1 << 16;
-__global__ void __launch_bounds__(SCAN1_T) k_scan1(const int64_t *in, int64_t *out, int64_t n, int64_t *total) {
+__global__ void __launch_bounds__(SCAN1_T) k_scan1(const int64_t *in, int64_t *out, int64_t n, int64_t *total,
+                                                   int64_t *host, int64_t split) {
   __shared__ int64_t sw[SCAN1_T / 64 + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t per = (n + SCAN1_T - 1) / SCAN1_T;
@@ -114,38 +143,50 @@ __global__ void __launch_bounds__(SCAN1_T) k_scan1(const int64_t *in, int64_t *o
     for (int k = 0; k < SCAN1_U; ++k) v[k] = i0 + k < hi ? in[i0 + k] : 0;
 #pragma unroll
     for (int k = 0; k < SCAN1_U; ++k) {
-      if (i0 + k < hi) out[i0 + k] = run;  // (in place: the group's inputs are already read)
+      if (i0 + k < hi) {
+        out[i0 + k] = run;  // (in place: the group's inputs are already read)
+        if (host && i0 + k == split) host[1] = run;
+      }
       run += v[k];
     }
   }
-  if (t == 0 && total) *total = sw[SCAN1_T / 64];
+  if (t == 0) {
+    const int64_t tot = sw[SCAN1_T / 64];
+    if (total) *total = tot;
+    if (host) {
+      host[0] = tot;
+      if (split == n) host[1] = tot;
+    }
+  }
 }
 
-int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s) {
-  if (n <= 0) {
-    if (total) HIP_TRY(ctx, hipMemsetAsync(total, 0, sizeof(int64_t), s));
-    return ABD_OK;
-  }
+int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s,
+                       int64_t *host, int64_t split) {
+  if (n < 0) n = 0;
+  if (split > n) split = -1;
   if (n <= SCAN1_MAX) {
-    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(SCAN1_T), 0, s, in, out, n, total);
+    // (n == 0 reads nothing and writes the zero total)
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(SCAN1_T), 0, s, in, out, n, total, host, split);
     return abd_hip_check(ctx, hipGetLastError(), "k_scan1");
   }
-  // keep the last input for the total (in-place scans overwrite it)
-  int64_t *last = nullptr;
-  if (total) {
-    ABD_TRY(ws(ctx, "scan_last", 1, &last, s));
-    HIP_TRY(ctx, hipMemcpyAsync(last, in + n - 1, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  // the last input for the total: a copy only when the scan is in place
+  const int64_t *last = in + n - 1;
+  if ((total || host) && in == out) {
+    int64_t *keep;
+    ABD_TRY(ws(ctx, "scan_last", 1, &keep, s));
+    HIP_TRY(ctx, hipMemcpyAsync(keep, in + n - 1, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    last = keep;
   }
   size_t tmp_bytes = 0;
   HIP_TRY(ctx, rocprim::exclusive_scan(nullptr, tmp_bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), s));
   void *tmp = nullptr;
   ABD_TRY(ws_get(ctx, "scan_tmp", tmp_bytes + 16, &tmp, s));
   HIP_TRY(ctx, rocprim::exclusive_scan(tmp, tmp_bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), s));
-  if (total) {
+  if (total || host) {
     // total = out[n-1] + in[n-1]
-    hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, s, out + n - 1, last, total);
+    hipLaunchKernelGGL(k_scan_tail, dim3(1), dim3(1), 0, s, out, last, n, total, host, split);
   }
-  return ABD_OK;
+  return abd_hip_check(ctx, hipGetLastError(), "scan tail");
 }
 
 int sort_pairs_u32(abd_ctx *ctx, uint32_t **keys, uint32_t **vals, int64_t n, int key_bits, hipStream_t s) {
@@ -479,6 +520,7 @@ extern "C" int abd_destroy(abd_ctx *ctx) {
     if (kv.second.ptr) hipFree(kv.second.ptr);
   if (ctx->pinned) hipHostFree(ctx->pinned);
   if (ctx->pinned_nt) hipHostFree(ctx->pinned_nt);
+  if (ctx->mirror_h) hipHostFree(ctx->mirror_h);
   for (auto &e : ctx->ev)
     if (e) hipEventDestroy(e);
   prof_flush(ctx);

@@ -757,13 +757,12 @@ static int friction_begin(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
     ABD_TRY(ws(ctx, "frl_tot", 2, &tot, s));
     ABD_TRY(op_friction_lag(ctx, sc, prm, xt, pt, npt, ee, nee, lam, T, w, s));
     hipLaunchKernelGGL(k_lam_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, n, lam, flag);
-    ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s));
-    int64_t *h;
-    ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
-    HIP_TRY(ctx, hipMemcpyAsync(h, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    if (nee > 0) HIP_TRY(ctx, hipMemcpyAsync(h + 1, pos + npt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    int64_t *h, *h_d;
+    ABD_TRY(mirror_get(ctx, &h, &h_d));
+    h += MIR_COMPACT;
+    ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s, h_d + MIR_COMPACT, npt));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    const int64_t keep = h[0], keep_pt = nee > 0 ? h[1] : h[0];
+    const int64_t keep = h[0], keep_pt = h[1];
     // the PT count the compaction needs is pos[npt] (or the total)
     const int64_t *n_keep_pt_dev = nee > 0 ? pos + npt : tot;
     int32_t *fpt, *fee;

@@ -41,7 +41,12 @@ struct abd_ctx {
   void *pinned = nullptr;  // small host staging area for scalar readbacks
   size_t pinned_bytes = 0;
   void *pinned_nt = nullptr;  // per-scene staging of the Newton driver
+  void *pinned_nt_d = nullptr;  // (mapped: its device address)
   size_t pinned_nt_bytes = 0;
+  // coherent mapped host memory that kernels write counts into directly
+  // (read after the stream synchronises; allocated once, so its address
+  // can be baked into captured graphs)
+  int64_t *mirror_h = nullptr, *mirror_d = nullptr;
   hipEvent_t ev[8] = {};
   bool profiling = false;
   std::map<std::string, KStat> kstats;
@@ -91,15 +96,29 @@ int ws(abd_ctx *ctx, const char *name, size_t count, T **out, hipStream_t stream
 }
 int pinned_get(abd_ctx *ctx, size_t bytes, void **out);
 // separate staging area of the Newton driver (never used by the operations
-// it calls, so its contents survive them)
-int pinned_get_nt(abd_ctx *ctx, size_t bytes, void **out);
+// it calls, so its contents survive them); coherent mapped host memory, so
+// kernels may also write it through *dev (may be NULL)
+int pinned_get_nt(abd_ctx *ctx, size_t bytes, void **out, void **dev = nullptr);
+// MIRROR_SLOTS int64 of coherent mapped host memory: host and device
+// addresses.  Fixed slots per use; a slot is read right after the
+// synchronisation that follows its writer.
+constexpr int MIRROR_SLOTS = 64;
+constexpr int MIR_BROAD = 0;     // 8 slots: broad-phase totals
+constexpr int MIR_OFFDIAG = 8;   // 1 slot: off-diagonal key count
+constexpr int MIR_COMPACT = 12;  // 2 slots: compaction total and PT count
+constexpr int MIR_PCG = 16;      // 2 slots (4 ints): PCG iteration state
+int mirror_get(abd_ctx *ctx, int64_t **host, int64_t **dev);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // ---------------------------------------------------- device-wide scan ----
 // Exclusive prefix sum of n int64 values (in != out allowed, or in-place);
 // total (device, may be NULL) receives the sum.
-int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s);
+// host (device address of mapped host memory, may be null) receives
+// host[0] = total and, for 0 <= split <= n, host[1] = out[split] (the
+// total when split == n); both written by the scan's own kernels.
+int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s,
+                       int64_t *host = nullptr, int64_t split = -1);
 // Stable sort of (key, value) pairs by key (keys in [0, 2^key_bits));
 // *keys and *vals then point to the sorted arrays (context workspace, valid
 // until the next sort).

@@ -360,16 +360,16 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   if (n > 0) {
     hipLaunchKernelGGL(k_active_flags, dim3(grid_for(n, 256)), dim3(256), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges,
                        x, dhat2, flag);
-    ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, nact, s));
+    // active counts (total, and the PT part pos[n_pt]) written to mapped
+    // host memory by the scan
+    int64_t *hbuf, *hbuf_d;
+    ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
+    hbuf += MIR_COMPACT;
+    ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, nact, s, hbuf_d + MIR_COMPACT, n_pt));
     hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, n, flag, pos, act);
-    // active counts (PT part = pos[n_pt] if n_pt < n)
-    int64_t *hbuf;
-    ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&hbuf)));
-    HIP_TRY(ctx, hipMemcpyAsync(hbuf, nact, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    if (n_ee > 0) HIP_TRY(ctx, hipMemcpyAsync(hbuf + 1, pos + n_pt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     na = hbuf[0];
-    na_pt = n_ee > 0 ? hbuf[1] : na;
+    na_pt = hbuf[1];
   }
   if (n_active_pt) *n_active_pt = na_pt;
   if (n_active_ee) *n_active_ee = na - na_pt;

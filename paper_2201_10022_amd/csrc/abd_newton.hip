@@ -72,6 +72,15 @@ int err_check(abd_ctx *ctx, int e, hipStream_t s) {
 
 namespace {
 
+// small results straight into mapped host memory (one launch instead of a
+// copy per array): ha[0..na) = a, hb[0..nb) = b, *he = *e
+__global__ void k_to_host(const double *a, int na, const double *b, int nb, const int *e, double *ha, double *hb,
+                          int *he) {
+  for (int i = threadIdx.x; i < na; i += blockDim.x) ha[i] = a[i];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hb[i] = b[i];
+  if (e && threadIdx.x == 0) *he = *e;
+}
+
 // per-body masks and per-scene step lengths
 __global__ void k_neg_masked(int nb, const int32_t *body_scene, const uint8_t *done, const double *g, double *out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -164,10 +173,13 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(ws(ctx, "nt_escene", (size_t)(LS_BATCH + 1) * S, &e_sc, s));
   ABD_TRY(ws(ctx, "nt_accd", S, &a_ccd, s));
   // host staging: error flag, done flags, per-scene disp / alpha / E0 / E1
-  double *h;
-  ABD_TRY(pinned_get_nt(ctx, sizeof(double) * (8 + (4 + 2 * (size_t)LS_BATCH) * S), reinterpret_cast<void **>(&h)));
-  int *h_err = reinterpret_cast<int *>(h);
+  // (mapped memory: d_* are the device addresses of the same slots)
+  double *h, *hd;
+  ABD_TRY(pinned_get_nt(ctx, sizeof(double) * (8 + (4 + 2 * (size_t)LS_BATCH) * S), reinterpret_cast<void **>(&h),
+                        reinterpret_cast<void **>(&hd)));
+  int *h_err = reinterpret_cast<int *>(h), *d_err = reinterpret_cast<int *>(hd);
   double *h_disp = h + 8, *h_alpha = h_disp + S, *h_e0 = h_alpha + S, *h_e1 = h_e0 + S;  // h_e1 [LS_BATCH][S]
+  double *d_disp = hd + 8, *d_alpha = d_disp + S, *d_e0 = d_alpha + S;
   double *h_atr = h_e1 + (size_t)LS_BATCH * S;                                          // [LS_BATCH][S]
   uint8_t *h_done = reinterpret_cast<uint8_t *>(h_atr + (size_t)LS_BATCH * S);
   HIP_TRY(ctx, hipMemcpyAsync(h_done, done_dev, S, hipMemcpyDeviceToHost, s));
@@ -225,8 +237,11 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->pcg_iters = its;
   st->t_solve_ms += ms_since(t0);
   ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, sv, s));
-  HIP_TRY(ctx, hipMemcpyAsync(h_disp, sv, S * sizeof(double), hipMemcpyDeviceToHost, s));
-  ABD_TRY(err_enqueue(ctx, h_err, s));
+  {
+    int *errf;
+    ABD_TRY(ws(ctx, "err_flag", 1, &errf, s));
+    hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, sv, S, nullptr, 0, errf, d_disp, nullptr, d_err);
+  }
   HIP_TRY(ctx, hipStreamSynchronize(s));
   ABD_TRY(err_check(ctx, h_err[0], s));
   double dmax = 0.0;
@@ -281,8 +296,8 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   hipLaunchKernelGGL(k_ls_trials, dim3(grid_for((kb0 + 1) * S, 256)), dim3(256), 0, s, S, kb0 + 1, done_dev, a_ccd,
                      alpha_dev);
   ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb0 + 1, spt, nspt, see, nsee, fr, e_sc, s));
-  HIP_TRY(ctx, hipMemcpyAsync(h_alpha, a_ccd, S * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipMemcpyAsync(h_e0, e_sc, (size_t)(kb0 + 1) * S * sizeof(double), hipMemcpyDeviceToHost, s));
+  hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, a_ccd, S, e_sc, (kb0 + 1) * S, nullptr, d_alpha, d_e0,
+                     nullptr);
   HIP_TRY(ctx, hipStreamSynchronize(s));
   st->t_ccd_ms += ms_since(t0);
   double amin = 1.0;

@@ -863,7 +863,14 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
   }
 }
 
-__global__ void k_cg_advance(CgState *st, int n) { st->base += n; }
+// closes a replay: advances the base and copies the state the host reads
+// (base, n_stopped, max_final) to mapped host memory
+__global__ void k_cg_advance(CgState *st, int n, int *host) {
+  st->base += n;
+  host[0] = st->base;
+  host[1] = st->n_stopped;
+  host[2] = st->max_final;
+}
 
 // y = sx H x (plain block SpMV; one wave per body)
 __global__ void __launch_bounds__(SWB) k_bsr_spmv(int nb, const uint8_t *fixed, const double *diag, const double *off,
@@ -949,6 +956,10 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   hipLaunchKernelGGL(k_cg_init2, dim3(nblk_s), dim3(SWB), 0, s, cblk, ent, sc->body_fixed, diag, off, rhs, rv[0], u,
                      wv[0], pt[0]);
   HIP_TRY(ctx, hipGetLastError());
+  int64_t *mir_h, *mir_d;
+  ABD_TRY(mirror_get(ctx, &mir_h, &mir_d));
+  int *hst_d = reinterpret_cast<int *>(mir_d + MIR_PCG);
+  const int *hst = reinterpret_cast<const int *>(mir_h + MIR_PCG);
   // n iterations (n even: the parity of k is that of the local index)
   auto enqueue = [&](hipStream_t q, int n) {
     for (int j = 0; j < n; ++j) {
@@ -956,7 +967,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
       hipLaunchKernelGGL(k_cg_iter, dim3(nblk_s), dim3(SWB), 0, q, j, cblk, ent, sc->body_fixed, Bm, inv, rv[a],
                          wv[a], sv[a], rv[o], wv[o], sv[o], x_out, u, p, pt[a], pt[o], st, scs, rtol2, max_iter);
     }
-    hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(1), 0, q, st, n);
+    hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(1), 0, q, st, n, hst_d);
   };
   const char *env = getenv("ABD_PCG_GRAPH");
   const bool use_graph = !(env && env[0] == '0');
@@ -972,7 +983,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
         (uintptr_t)sv[0],    (uintptr_t)sv[1],    (uintptr_t)pt[0],        (uintptr_t)pt[1],      (uintptr_t)cblk,
         (uintptr_t)ent,      (uintptr_t)st,       (uintptr_t)sc->body_fixed,
         (uintptr_t)nblk_s,   (uintptr_t)max_iter, (uintptr_t)rtol_bits,    (uintptr_t)scs.gam,    (uintptr_t)scs.alp,
-        (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)1};
+        (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)hst_d, (uintptr_t)1};
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     for (int gi = 0; gi < 2; ++gi) {
       if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {
@@ -989,7 +1000,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
       exec[gi] = ctx->pcg_exec[gi];
     }
   }
-  int *h;  // [0..2] base, n_stopped, max_final; [4..4+S) per-scene iteration counts
+  int *h;  // [4..4+S): per-scene iteration counts (profiled solves)
   ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
   int *fin = h + 4;
   const int max_rounds = max_iter / ITER_G[0] + 2;
@@ -1017,10 +1028,9 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
       planned += ITER_G[gi];
       ++round;
     } while (round < max_rounds && ctx->pcg_hint - (done + planned) >= ITER_G[0]);
-    HIP_TRY(ctx, hipMemcpyAsync(h, st, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    all = h[1] >= S;
-    done = all ? h[2] : h[0];  // iterations: the largest count over the scenes
+    all = hst[1] >= S;
+    done = all ? hst[2] : hst[0];  // iterations: the largest count over the scenes
   }
   *iters = done;
   ctx->pcg_hint = done;

@@ -21,21 +21,43 @@ __device__ __forceinline__ bool box_overlap(const double *a, const double *b) {
   return a[0] <= b[3] && b[0] <= a[3] && a[1] <= b[4] && b[1] <= a[4] && a[2] <= b[5] && b[2] <= a[5];
 }
 
+// The culling step (primitives inside the other body's box) only narrows
+// the rows and columns of the exact primitive-pair test, which implies it
+// (a primitive box overlapping one inside the other body's box overlaps
+// that box), so it may keep extra primitives: it reads single-precision
+// copies of the boxes rounded outwards, half the bytes of the exact ones.
+__device__ __forceinline__ void store_box32(float *o, const double *b) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o[i] = __double2float_rd(b[i]);
+    o[3 + i] = __double2float_ru(b[3 + i]);
+  }
+}
+__device__ __forceinline__ bool box_overlap32(const float *a, const double *b) {
+  return (double)a[0] <= b[3] && b[0] <= (double)a[3] && (double)a[1] <= b[4] && b[1] <= (double)a[4] &&
+         (double)a[2] <= b[5] && b[2] <= (double)a[5];
+}
+
 __global__ void __launch_bounds__(256) k_vert_boxes(int nv, const double *x0, const double *x1, double inflate,
-                                                    double *vb) {
+                                                    double *vb, float *vb32) {
 #pragma clang fp contract(off)
   const int v = blockIdx.x * 256 + threadIdx.x;
   if (v >= nv) return;
+  double b[6];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const double a = x0[3 * v + i], b = x1[3 * v + i];
-    vb[6 * (int64_t)v + i] = fmin(a, b);
-    vb[6 * (int64_t)v + 3 + i] = fmax(a, b) + inflate;
+    const double a = x0[3 * v + i], c = x1[3 * v + i];
+    b[i] = fmin(a, c);
+    b[3 + i] = fmax(a, c) + inflate;
   }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) vb[6 * (int64_t)v + i] = b[i];
+  store_box32(vb32 + 6 * (int64_t)v, b);
 }
 
 template <int K>  // vertices per primitive
-__global__ void __launch_bounds__(256) k_prim_boxes(int n, const int32_t *prims, const double *vb, double *pb) {
+__global__ void __launch_bounds__(256) k_prim_boxes(int n, const int32_t *prims, const double *vb, double *pb,
+                                                    float *pb32) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
   double b[6];
@@ -53,6 +75,7 @@ __global__ void __launch_bounds__(256) k_prim_boxes(int n, const int32_t *prims,
   }
 #pragma unroll
   for (int i = 0; i < 6; ++i) pb[6 * (int64_t)p + i] = b[i];
+  store_box32(pb32 + 6 * (int64_t)p, b);
 }
 
 __global__ void __launch_bounds__(256) k_body_boxes(int nb, const int32_t *voff, const double *vb, double *bb) {
@@ -111,8 +134,16 @@ __global__ void __launch_bounds__(64) k_body_pairs(int nb, const int32_t *body_s
     bool ok[BPU];
 #pragma unroll
     for (int u = 0; u < BPU; ++u) {
+      // (loads from a clamped index, so none waits on a test)
       const int b = b0 + 64 * u + (int)threadIdx.x;
-      ok[u] = b < end && !(fa && fixed[b]) && box_overlap(ba, bb + 6 * (int64_t)b);
+      const int bl = b < end ? b : a;
+      double o[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) o[i] = bb[6 * (int64_t)bl + i];
+      const bool fb = fixed[bl] != 0;
+      const bool ov = (ba[0] <= o[3]) & (o[0] <= ba[3]) & (ba[1] <= o[4]) & (o[1] <= ba[4]) & (ba[2] <= o[5]) &
+                      (o[2] <= ba[5]);
+      ok[u] = (b < end) & !(fa & fb) & ov;
     }
 #pragma unroll
     for (int u = 0; u < BPU; ++u) {
@@ -169,8 +200,8 @@ __global__ void k_list_caps(int64_t n_cap, const int64_t *nbp_dev, const int32_t
 
 __global__ void __launch_bounds__(256) k_cull_lists(const int32_t *bpairs, const int64_t *region,
                                                     const int32_t *voff, const int32_t *toff, const int32_t *eoff,
-                                                    const double *bb, const double *vbox, const double *tbox,
-                                                    const double *ebox, int32_t *lists, int64_t *list_start,
+                                                    const double *bb, const float *vbox, const float *tbox,
+                                                    const float *ebox, int32_t *lists, int64_t *list_start,
                                                     int32_t *list_len) {
   __shared__ int wcnt[4];
   const int64_t p = blockIdx.x;
@@ -180,7 +211,7 @@ __global__ void __launch_bounds__(256) k_cull_lists(const int32_t *bpairs, const
   const int own = (kind == 0 || kind == 3 || kind == 4) ? a : b;
   const int oth = own == a ? b : a;
   const int32_t *offs = (kind == 0 || kind == 2) ? voff : (kind == 1 || kind == 3) ? toff : eoff;
-  const double *boxes = (kind == 0 || kind == 2) ? vbox : (kind == 1 || kind == 3) ? tbox : ebox;
+  const float *boxes = (kind == 0 || kind == 2) ? vbox : (kind == 1 || kind == 3) ? tbox : ebox;
   // start of this list inside the body pair's region
   int64_t start = region[p];
   {
@@ -197,7 +228,7 @@ __global__ void __launch_bounds__(256) k_cull_lists(const int32_t *bpairs, const
   int total = 0;
   for (int c0 = offs[own]; c0 < offs[own + 1]; c0 += 256) {
     const int i = c0 + (int)threadIdx.x;
-    const bool ok = i < offs[own + 1] && box_overlap(boxes + 6 * (int64_t)i, ob);
+    const bool ok = i < offs[own + 1] && box_overlap32(boxes + 6 * (int64_t)i, ob);
     const unsigned long long m = __ballot(ok);
     if (lane == 0) wcnt[wid] = __popcll(m);
     __syncthreads();
@@ -341,9 +372,15 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_tbox", 6 * (size_t)nt + 6, &tbox, s));
   ABD_TRY(ws(ctx, "bp_ebox", 6 * (size_t)ne + 6, &ebox, s));
   ABD_TRY(ws(ctx, "bp_bbox", 6 * (size_t)nb, &bbox, s));
-  hipLaunchKernelGGL(k_vert_boxes, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv, x0, x1, inflate, vbox);
-  if (nt) hipLaunchKernelGGL(k_prim_boxes<3>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, sc->tris, vbox, tbox);
-  if (ne) hipLaunchKernelGGL(k_prim_boxes<2>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, sc->edges, vbox, ebox);
+  float *vbox32, *tbox32, *ebox32;
+  ABD_TRY(ws(ctx, "bp_vbox32", 6 * (size_t)nv, &vbox32, s));
+  ABD_TRY(ws(ctx, "bp_tbox32", 6 * (size_t)nt + 6, &tbox32, s));
+  ABD_TRY(ws(ctx, "bp_ebox32", 6 * (size_t)ne + 6, &ebox32, s));
+  hipLaunchKernelGGL(k_vert_boxes, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv, x0, x1, inflate, vbox, vbox32);
+  if (nt)
+    hipLaunchKernelGGL(k_prim_boxes<3>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, sc->tris, vbox, tbox, tbox32);
+  if (ne)
+    hipLaunchKernelGGL(k_prim_boxes<2>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, sc->edges, vbox, ebox, ebox32);
   hipLaunchKernelGGL(k_body_boxes, dim3(nb), dim3(256), 0, s, nb, sc->body_vert_off, vbox, bbox);
   HIP_TRY(ctx, hipGetLastError());
 
@@ -399,7 +436,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_llen", 6 * nbp, &llen, s));
   ABD_TRY(ws(ctx, "bp_lstart", 6 * nbp, &lstart, s));
   hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 6), dim3(256), 0, s, bpairs, region, sc->body_vert_off,
-                     sc->body_tri_off, sc->body_edge_off, bbox, vbox, tbox, ebox, lists, lstart, llen);
+                     sc->body_tri_off, sc->body_edge_off, bbox, vbox32, tbox32, ebox32, lists, lstart, llen);
 
   // tiles: the count pass is sized like the body pairs (one
   // synchronisation reads the tile and pair totals)

@@ -200,6 +200,63 @@ __global__ void k_pcg_scene_blocks(int S, const int32_t *sbo, int64_t *ucnt, int
   ucnt[s] = (n + PBB - 1) / PBB;
   scnt[s] = (n + SWBB - 1) / SWBB;
 }
+// the four steps below in one block, for up to SETUP_T scenes: per-scene
+// block counts, their exclusive scans (u_off, s_off) and the scene of
+// every update and SpMV block
+constexpr int SETUP_T = 1024;
+__global__ void __launch_bounds__(SETUP_T) k_pcg_scene_setup(int S, const int32_t *sbo, int64_t nblk_u,
+                                                             int64_t nblk_s, int64_t *u_off, int64_t *s_off,
+                                                             int32_t *u_scene, int32_t *s_scene) {
+  __shared__ int64_t su[SETUP_T + 1], ss[SETUP_T + 1];
+  const int t = threadIdx.x;
+  int64_t cu = 0, cs = 0;
+  if (t < S) {
+    const int n = sbo[t + 1] - sbo[t];
+    cu = (n + PBB - 1) / PBB;
+    cs = (n + SWBB - 1) / SWBB;
+  }
+  su[t + 1] = cu;
+  ss[t + 1] = cs;
+  if (t == 0) su[0] = ss[0] = 0;
+  __syncthreads();
+  // inclusive scan of su[1..], ss[1..] (Hillis-Steele)
+  for (int o = 1; o < SETUP_T; o <<= 1) {
+    const int64_t a = t >= o ? su[t + 1 - o] : 0, b = t >= o ? ss[t + 1 - o] : 0;
+    __syncthreads();
+    su[t + 1] += a;
+    ss[t + 1] += b;
+    __syncthreads();
+  }
+  for (int k = t; k <= S; k += SETUP_T) {
+    u_off[k] = su[k];
+    s_off[k] = ss[k];
+  }
+  for (int64_t j = t; j < nblk_u; j += SETUP_T) {
+    int lo = 0, hi = S;
+    if (j >= su[S]) {
+      u_scene[j] = -1;
+      continue;
+    }
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (su[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    u_scene[j] = lo;
+  }
+  for (int64_t j = t; j < nblk_s; j += SETUP_T) {
+    int lo = 0, hi = S;
+    if (j >= ss[S]) {
+      s_scene[j] = -1;
+      continue;
+    }
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ss[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    s_scene[j] = lo;
+  }
+}
+
 // scene of every block (-1 beyond the last scene's blocks)
 __global__ void k_pcg_block_scene(int S, int64_t nblk, const int64_t *off, int32_t *tab) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1112,13 +1169,18 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
   hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed,
                      pre_diag ? pre_diag : diag, inv, err);
-  hipLaunchKernelGGL(k_pcg_scene_blocks, dim3(grid_for(S, 256)), dim3(256), 0, s, S, sbo, ucnt, scnt);
-  ABD_TRY(scan_exclusive_i64(ctx, ucnt, u_off, S, u_off + S, s));
-  ABD_TRY(scan_exclusive_i64(ctx, scnt, s_off, S, s_off + S, s));
-  hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_u, 256)), dim3(256), 0, s, S, (int64_t)nblk_u, u_off,
-                     u_scene);
-  hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, S, (int64_t)nblk_s, s_off,
-                     s_scene);
+  if (S <= SETUP_T) {
+    hipLaunchKernelGGL(k_pcg_scene_setup, dim3(1), dim3(SETUP_T), 0, s, S, sbo, (int64_t)nblk_u, (int64_t)nblk_s,
+                       u_off, s_off, u_scene, s_scene);
+  } else {
+    hipLaunchKernelGGL(k_pcg_scene_blocks, dim3(grid_for(S, 256)), dim3(256), 0, s, S, sbo, ucnt, scnt);
+    ABD_TRY(scan_exclusive_i64(ctx, ucnt, u_off, S, u_off + S, s));
+    ABD_TRY(scan_exclusive_i64(ctx, scnt, s_off, S, s_off + S, s));
+    hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_u, 256)), dim3(256), 0, s, S, (int64_t)nblk_u, u_off,
+                       u_scene);
+    hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, S, (int64_t)nblk_s, s_off,
+                       s_scene);
+  }
   if (n_keys > 0) {
     hipLaunchKernelGGL(k_tkeys, dim3(grid_for(n_keys, 256)), dim3(256), 0, s, n_keys, keys, tk, tv);
     size_t tmp_bytes = 0;

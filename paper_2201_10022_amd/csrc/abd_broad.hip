@@ -261,12 +261,19 @@ __global__ void k_sub_tiles(int64_t nbp, const int32_t *list_len, int64_t *tiles
   }
 }
 
-// (sub-problem, tile index within it) of every tile
-__global__ void k_tile_sub(int64_t n_sub, const int64_t *cnt, const int64_t *off, int2 *tile_sub, int64_t cap) {
+// (sub-problem, tile index within it) of every tile.  The 3 nbp
+// sub-problems' tile counts are scanned as one array: PT sub-problems
+// [0, 2 nbp) first, then EE; an EE tile's index is counted from the first
+// EE tile (off[2 nbp]).
+__global__ void k_tile_sub(int64_t nbp, const int64_t *cnt, const int64_t *off, int2 *tsub_pt, int64_t cap_pt,
+                           int2 *tsub_ee, int64_t cap_ee) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_sub) return;
-  const int64_t o = off[j];
-  for (int64_t t = 0; t < cnt[j] && o + t < cap; ++t) tile_sub[o + t] = make_int2((int)j, (int)t);
+  if (j >= 3 * nbp) return;
+  const bool ee = j >= 2 * nbp;
+  const int64_t o = ee ? off[j] - off[2 * nbp] : off[j], cap = ee ? cap_ee : cap_pt;
+  int2 *ts = ee ? tsub_ee : tsub_pt;
+  const int sub = (int)(ee ? j - 2 * nbp : j);
+  for (int64_t t = 0; t < cnt[j] && o + t < cap; ++t) ts[o + t] = make_int2(sub, (int)t);
 }
 
 // One wave per tile of TROWS rows x all columns.  WRITE=0 counts the
@@ -277,16 +284,14 @@ __global__ void k_tile_sub(int64_t n_sub, const int64_t *cnt, const int64_t *off
 // beyond CPRE chunks are loaded in the loop.
 constexpr int CPRE = 8;
 template <int WRITE>
-__global__ void __launch_bounds__(64) k_pair_tiles(int is_ee, const int2 *tile_sub, int64_t n_tiles,
-                                                   const int64_t *list_start, const int32_t *list_len,
-                                                   const int32_t *lists, const double *row_boxes,
-                                                   const double *col_boxes, int64_t *tile_cnt, const int64_t *tile_off,
-                                                   int32_t *out, const int64_t *n_tiles_dev = nullptr) {
-  const int64_t tile = blockIdx.x;
+__device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *tile_sub, int64_t n_tiles,
+                                          const int64_t *list_start, const int32_t *list_len, const int32_t *lists,
+                                          const double *row_boxes, const double *col_boxes, int64_t *tile_cnt,
+                                          int64_t pos0, int32_t *out, int64_t n_tiles_valid) {
   // (the count pass runs over a capacity: tiles beyond the device count
   // record 0 so that the scan over the capacity stays exact)
-  if (n_tiles_dev && tile < n_tiles && tile >= *n_tiles_dev) {
-    if (!WRITE && threadIdx.x == 0) tile_cnt[tile] = 0;
+  if (!WRITE && tile < n_tiles && tile >= n_tiles_valid) {
+    if (threadIdx.x == 0) tile_cnt[tile] = 0;
     return;
   }
   if (tile >= n_tiles) return;
@@ -317,7 +322,7 @@ __global__ void __launch_bounds__(64) k_pair_tiles(int is_ee, const int2 *tile_s
   for (int k = 0; k < CPRE; ++k)
 #pragma unroll
     for (int i = 0; i < 6; ++i) cb[k][i] = cpv[k] >= 0 ? col_boxes[6 * (int64_t)cpv[k] + i] : 0.0;
-  int64_t pos = WRITE ? tile_off[tile] : 0;
+  int64_t pos = WRITE ? pos0 : 0;
   int64_t cnt = 0;
   for (int r = r0; r < r1; ++r) {
     const int src = r - r0;
@@ -356,6 +361,34 @@ __global__ void __launch_bounds__(64) k_pair_tiles(int is_ee, const int2 *tile_s
     }
   }
   if (!WRITE && lane == 0) tile_cnt[tile] = cnt;
+}
+
+// Both families in one launch: blocks [0, n_pt_blocks) take PT tiles, the
+// rest EE tiles.  Count pass (WRITE=0): n_pt_blocks / n_ee_blocks are the
+// capacities, the valid tile counts come from the device (toff, the scan
+// of the per-sub-problem tile counts over 3 nbp, and its total), and the
+// counts go to cnt[0, cap_pt) (PT) and cnt[cap_pt, cap_pt + cap_ee) (EE).
+// Write pass: the blocks are the exact tile counts and off is the scan of
+// cnt (EE offsets counted from off[cap_pt]).
+template <int WRITE>
+__global__ void __launch_bounds__(64) k_pair_tiles(int64_t nbp, int64_t n_pt_blocks, int64_t n_ee_blocks,
+                                                   int64_t cap_pt, const int2 *tsub_pt, const int2 *tsub_ee,
+                                                   const int64_t *toff, const int64_t *ttotal,
+                                                   const int64_t *list_start, const int32_t *list_len,
+                                                   const int32_t *lists, const double *vbox, const double *tbox,
+                                                   const double *ebox, int64_t *cnt, const int64_t *off,
+                                                   int32_t *out_pt, int32_t *out_ee) {
+  const int64_t b = blockIdx.x;
+  if (b < n_pt_blocks) {
+    const int64_t valid = WRITE ? n_pt_blocks : toff[2 * nbp];
+    pair_tile<WRITE>(0, b, tsub_pt, n_pt_blocks, list_start, list_len, lists, vbox, tbox, cnt, WRITE ? off[b] : 0,
+                     out_pt, valid);
+  } else if (b < n_pt_blocks + n_ee_blocks) {
+    const int64_t t = b - n_pt_blocks;
+    const int64_t valid = WRITE ? n_ee_blocks : *ttotal - toff[2 * nbp];
+    pair_tile<WRITE>(1, t, tsub_ee, n_ee_blocks, list_start, list_len, lists, ebox, ebox, cnt + cap_pt,
+                     WRITE ? off[cap_pt + t] - off[cap_pt] : 0, out_ee, valid);
+  }
 }
 
 }  // namespace
@@ -439,41 +472,37 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
                      sc->body_tri_off, sc->body_edge_off, bbox, vbox32, tbox32, ebox32, lists, lstart, llen);
 
   // tiles: the count pass is sized like the body pairs (one
-  // synchronisation reads the tile and pair totals)
-  int64_t *tpt, *tee, *tpt_off, *tee_off, *ttot = btot + 2, *otot = btot + 4;
-  ABD_TRY(ws(ctx, "bp_tpt", 2 * nbp, &tpt, s));
-  ABD_TRY(ws(ctx, "bp_tee", nbp, &tee, s));
-  ABD_TRY(ws(ctx, "bp_tpt_off", 2 * nbp, &tpt_off, s));
-  ABD_TRY(ws(ctx, "bp_tee_off", nbp, &tee_off, s));
-  hipLaunchKernelGGL(k_sub_tiles, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, llen, tpt, tee);
-  ABD_TRY(scan_exclusive_i64(ctx, tpt, tpt_off, 2 * nbp, ttot, s, hbuf_d + 2));
-  ABD_TRY(scan_exclusive_i64(ctx, tee, tee_off, nbp, ttot + 1, s, hbuf_d + 3));
+  // synchronisation reads the tile and pair totals).  Tile counts per
+  // sub-problem: PT [0, 2 nbp), EE [2 nbp, 3 nbp), scanned as one array.
+  int64_t *tcnt, *toff, *ttot = btot + 2, *otot = btot + 4;
+  ABD_TRY(ws(ctx, "bp_tcnt", 3 * nbp, &tcnt, s));
+  ABD_TRY(ws(ctx, "bp_toff", 3 * nbp + 1, &toff, s));
+  hipLaunchKernelGGL(k_sub_tiles, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, llen, tcnt, tcnt + 2 * nbp);
+  // hbuf[2] = all tiles, hbuf[3] = PT tiles
+  ABD_TRY(scan_exclusive_i64(ctx, tcnt, toff, 3 * nbp, ttot, s, hbuf_d + 2, 2 * nbp));
   const std::string key_tp = std::string(tag) + "_tpt", key_te = std::string(tag) + "_tee";
   int64_t cap_tp = ctx->cap_hint[key_tp], cap_te = ctx->cap_hint[key_te];
   cap_tp = cap_tp + cap_tp / 4 + 256;
   cap_te = cap_te + cap_te / 4 + 256;
   int64_t ntile_pt = 0, ntile_ee = 0;
-  int64_t *cpt, *cee, *opt, *oee;
+  int64_t *ccnt, *coff;
   int2 *tsub_pt, *tsub_ee;
   for (int pass = 0;; ++pass) {
-    ABD_TRY(ws(ctx, "bp_cpt", cap_tp + 1, &cpt, s));
-    ABD_TRY(ws(ctx, "bp_cee", cap_te + 1, &cee, s));
-    ABD_TRY(ws(ctx, "bp_opt", cap_tp + 1, &opt, s));
-    ABD_TRY(ws(ctx, "bp_oee", cap_te + 1, &oee, s));
+    // pair counts per tile: PT tiles [0, cap_tp), EE tiles [cap_tp, cap_tp + cap_te)
+    ABD_TRY(ws(ctx, "bp_ccnt", cap_tp + cap_te + 1, &ccnt, s));
+    ABD_TRY(ws(ctx, "bp_coff", cap_tp + cap_te + 1, &coff, s));
     ABD_TRY(ws(ctx, "bp_tsub_pt", cap_tp + 1, &tsub_pt, s));
     ABD_TRY(ws(ctx, "bp_tsub_ee", cap_te + 1, &tsub_ee, s));
-    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(2 * nbp, 256)), dim3(256), 0, s, 2 * nbp, tpt, tpt_off, tsub_pt,
-                       cap_tp);
-    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)cap_tp), dim3(64), 0, s, 0, tsub_pt, cap_tp, lstart, llen,
-                       lists, vbox, tbox, cpt, nullptr, nullptr, ttot);
-    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, tee, tee_off, tsub_ee, cap_te);
-    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)cap_te), dim3(64), 0, s, 1, tsub_ee, cap_te, lstart, llen,
-                       lists, ebox, ebox, cee, nullptr, nullptr, ttot + 1);
-    ABD_TRY(scan_exclusive_i64(ctx, cpt, opt, cap_tp, otot, s, hbuf_d + 4));
-    ABD_TRY(scan_exclusive_i64(ctx, cee, oee, cap_te, otot + 1, s, hbuf_d + 5));
+    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(3 * nbp, 256)), dim3(256), 0, s, nbp, tcnt, toff, tsub_pt, cap_tp,
+                       tsub_ee, cap_te);
+    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)(cap_tp + cap_te)), dim3(64), 0, s, nbp, cap_tp, cap_te, cap_tp,
+                       tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, vbox, tbox, ebox, ccnt, nullptr, nullptr,
+                       nullptr);
+    // hbuf[4] = all pairs, hbuf[5] = PT pairs
+    ABD_TRY(scan_exclusive_i64(ctx, ccnt, coff, cap_tp + cap_te, otot, s, hbuf_d + 4, cap_tp));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    ntile_pt = hbuf[2];
-    ntile_ee = hbuf[3];
+    ntile_pt = hbuf[3];
+    ntile_ee = hbuf[2] - hbuf[3];
     if (ntile_pt <= cap_tp && ntile_ee <= cap_te) break;
     if (pass > 0) return abd_fail(ctx, ABD_E_INVALID, "candidates: tile count changed between passes");
     cap_tp = ntile_pt > cap_tp ? ntile_pt : cap_tp;
@@ -481,18 +510,16 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   }
   ctx->cap_hint[key_tp] = ntile_pt;
   ctx->cap_hint[key_te] = ntile_ee;
-  *n_pt = hbuf[4];
-  *n_ee = hbuf[5];
+  *n_pt = hbuf[5];
+  *n_ee = hbuf[4] - hbuf[5];
   std::string tpt_name = std::string(tag) + "_pt", tee_name = std::string(tag) + "_ee";
   ABD_TRY(ws(ctx, tpt_name.c_str(), 2 * (*n_pt) + 2, pt_out, s));
   ABD_TRY(ws(ctx, tee_name.c_str(), 2 * (*n_ee) + 2, ee_out, s));
   hipEvent_t pe = prof_begin(ctx, s);
-  if (ntile_pt && *n_pt)
-    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_pt), dim3(64), 0, s, 0, tsub_pt, ntile_pt, lstart, llen,
-                       lists, vbox, tbox, nullptr, opt, *pt_out);
-  if (ntile_ee && *n_ee)
-    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)ntile_ee), dim3(64), 0, s, 1, tsub_ee, ntile_ee, lstart, llen,
-                       lists, ebox, ebox, nullptr, oee, *ee_out);
+  if (*n_pt + *n_ee > 0)
+    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)(ntile_pt + ntile_ee)), dim3(64), 0, s, nbp, ntile_pt,
+                       ntile_ee, cap_tp, tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, vbox, tbox, ebox, nullptr,
+                       coff, *pt_out, *ee_out);
   prof_end(ctx, pe, "pair_tiles_write", ntile_pt + ntile_ee, s);
   return abd_hip_check(ctx, hipGetLastError(), "candidates");
 }

@@ -38,6 +38,31 @@ int zero(abd_ctx *ctx, double *a, int64_t n, hipStream_t s) {
   return abd_hip_check(ctx, hipGetLastError(), "k_zero");
 }
 
+// four arrays cleared by one launch (index i runs over their concatenation)
+struct Zero4 {
+  double *p[4];
+  int64_t n[4];
+};
+__global__ void k_zero4(Zero4 z, int64_t total) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i < z.n[k]) {
+      z.p[k][i] = 0.0;
+      return;
+    }
+    i -= z.n[k];
+  }
+}
+int zero4(abd_ctx *ctx, double *a, int64_t na, double *b, int64_t nb, double *c, int64_t nc, double *d, int64_t nd,
+          hipStream_t s) {
+  const Zero4 z = {{a, b, c, d}, {na, nb, nc, nd}};
+  const int64_t total = na + nb + nc + nd;
+  if (total > 0) hipLaunchKernelGGL(k_zero4, dim3(grid_for(total, 256)), dim3(256), 0, s, z, total);
+  return abd_hip_check(ctx, hipGetLastError(), "k_zero4");
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -212,10 +237,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->n_offdiag = nk;
   st->t_candidates_ms += ms_since(t0);
   ABD_TRY(ws(ctx, "nt_off", 144 * (size_t)(nk + 1), &off, s));
-  ABD_TRY(zero(ctx, g, n12, s));
-  ABD_TRY(zero(ctx, diag, 144 * (int64_t)nb, s));
-  ABD_TRY(zero(ctx, off, 144 * nk, s));
-  ABD_TRY(zero(ctx, e, 1, s));
+  ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, off, 144 * nk, e, 1, s));
   t0 = std::chrono::steady_clock::now();
   ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, e, g, diag, 1, s));
   int64_t nap = 0, nae = 0;

@@ -560,19 +560,37 @@ __global__ void k_od_clear(int64_t n16, uint4 *f) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n16) f[i] = make_uint4(0u, 0u, 0u, 0u);
 }
-__global__ void k_od_mark(int64_t n, int is_ee, const int32_t *pairs, const int32_t *vert_body,
-                          const int32_t *tri_body, const int32_t *edge_body, const uint8_t *fixed, int nb,
-                          uint8_t *flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// the four pair lists (PT, EE, extra PT, extra EE) marked by one launch;
+// both (a, b) and (b, a) are marked, so that row b also lists the rows
+// a < b of its column
+struct MarkLists {
+  const int32_t *p[4];
+  int64_t end[4];  // cumulative counts
+};
+__global__ void k_od_mark(MarkLists L, const int32_t *vert_body, const int32_t *tri_body, const int32_t *edge_body,
+                          const uint8_t *fixed, int nb, uint8_t *flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.end[3]) return;
+  int l = 0;
+  while (i >= L.end[l]) ++l;
+  if (l > 0) i -= L.end[l - 1];
+  const int32_t *pairs = L.p[l];
+  const int is_ee = l & 1;
   const int a = is_ee ? edge_body[pairs[2 * i]] : vert_body[pairs[2 * i]];
   const int b = is_ee ? edge_body[pairs[2 * i + 1]] : tri_body[pairs[2 * i + 1]];
-  if (!fixed[a] && !fixed[b] && a != b) flags[(int64_t)min(a, b) * nb + max(a, b)] = 1;
+  if (!fixed[a] && !fixed[b] && a != b) {
+    flags[(int64_t)min(a, b) * nb + max(a, b)] = 1;
+    flags[(int64_t)max(a, b) * nb + min(a, b)] = 1;
+  }
 }
 // one wave per row: count (WRITE 0) or write (WRITE 1) the marked columns
+// b > a: the keys in (row, column) order.  With the pattern requested, the
+// count pass also counts the marked columns b < a (keys with column a) and
+// the write pass stores each key's index at the transposed position
+// kidx[b][a].
 template <int WRITE>
 __global__ void __launch_bounds__(64) k_od_row(int nb, const uint8_t *flags, int64_t *cnt, const int64_t *off,
-                                               int32_t *keys) {
+                                               int32_t *keys, int64_t *lcnt, int32_t *kidx) {
   const int a = blockIdx.x;
   if (a >= nb) return;
   const uint8_t *row = flags + (int64_t)a * nb;
@@ -585,18 +603,44 @@ __global__ void __launch_bounds__(64) k_od_row(int nb, const uint8_t *flags, int
       const int64_t o = base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull));
       keys[2 * o] = a;
       keys[2 * o + 1] = b;
+      if (kidx) kidx[(int64_t)b * nb + a] = (int32_t)o;
     }
     c += __popcll(m);
   }
   if (!WRITE && threadIdx.x == 0) cnt[a] = c;
+  if (!WRITE && lcnt) {
+    int64_t cl = 0;
+    for (int b0 = 0; b0 < a; b0 += 64) {
+      const int b = b0 + (int)threadIdx.x;
+      cl += __popcll(__ballot(b < a && row[b]));
+    }
+    if (threadIdx.x == 0) lcnt[a] = cl;
+  }
+}
+// one wave per body c: the indices of the keys (b, c), b < c, in order of
+// b (the keys sorted by (column, row))
+__global__ void __launch_bounds__(64) k_od_lower(int nb, const uint8_t *flags, const int64_t *loff,
+                                                 const int32_t *kidx, uint32_t *tperm) {
+  const int c = blockIdx.x;
+  if (c >= nb) return;
+  const uint8_t *row = flags + (int64_t)c * nb;
+  int64_t o = loff[c];
+  for (int b0 = 0; b0 < c; b0 += 64) {
+    const int b = b0 + (int)threadIdx.x;
+    const bool on = b < c && row[b];
+    const unsigned long long m = __ballot(on);
+    if (on) tperm[o + __popcll(m & ((1ull << threadIdx.x) - 1ull))] = (uint32_t)kidx[(int64_t)c * nb + b];
+    o += __popcll(m);
+  }
 }
 }  // namespace
 
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys_out, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2,
-               int64_t n_pt2, const int32_t *ee2, int64_t n_ee2) {
+               int64_t n_pt2, const int32_t *ee2, int64_t n_ee2, KeyPattern *pat) {
   const int64_t n = n_pt + n_ee + n_pt2 + n_ee2;
   *n_keys = 0;
+  if (pat) *pat = KeyPattern{};
   std::string nm = std::string(tag) + "_keys";
   ABD_TRY(ws(ctx, nm.c_str(), 2 * n + 2, keys_out, s));
   if (n == 0) return ABD_OK;
@@ -619,15 +663,37 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
     ABD_TRY(ws(ctx, "od_roff", nb + 1, &roff, s));
     hipLaunchKernelGGL(k_od_clear, dim3(grid_for(nbb / 16, 256)), dim3(256), 0, s, nbb / 16,
                        reinterpret_cast<uint4 *>(flags));
-    for (int l = 0; l < 4; ++l)
-      if (counts[l] > 0)
-        hipLaunchKernelGGL(k_od_mark, dim3(grid_for(counts[l], 256)), dim3(256), 0, s, counts[l], l & 1, lists[l],
-                           sc->vert_body, sc->tri_body, sc->edge_body, sc->body_fixed, nb, flags);
+    MarkLists ml;
+    int64_t acc = 0;
+    for (int l = 0; l < 4; ++l) {
+      ml.p[l] = lists[l];
+      acc += counts[l];
+      ml.end[l] = acc;
+    }
+    hipLaunchKernelGGL(k_od_mark, dim3(grid_for(n, 256)), dim3(256), 0, s, ml, sc->vert_body, sc->tri_body,
+                       sc->edge_body, sc->body_fixed, nb, flags);
     int64_t *hbuf, *hbuf_d;
     ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
-    hipLaunchKernelGGL(k_od_row<0>, dim3(nb), dim3(64), 0, s, nb, flags, rcnt, nullptr, nullptr);
+    int64_t *lcnt = nullptr, *loff = nullptr;
+    int32_t *kidx = nullptr;
+    uint32_t *tperm = nullptr;
+    if (pat) {
+      ABD_TRY(ws(ctx, "od_lcnt", nb, &lcnt, s));
+      ABD_TRY(ws(ctx, "od_loff", nb + 1, &loff, s));
+      ABD_TRY(ws(ctx, "od_kidx", (size_t)nb * nb, &kidx, s));
+      ABD_TRY(ws(ctx, "od_tperm", n + 1, &tperm, s));
+    }
+    hipLaunchKernelGGL(k_od_row<0>, dim3(nb), dim3(64), 0, s, nb, flags, rcnt, nullptr, nullptr, lcnt, nullptr);
     ABD_TRY(scan_exclusive_i64(ctx, rcnt, roff, nb, roff + nb, s, hbuf_d + MIR_OFFDIAG));
-    hipLaunchKernelGGL(k_od_row<1>, dim3(nb), dim3(64), 0, s, nb, flags, nullptr, roff, *keys_out);
+    hipLaunchKernelGGL(k_od_row<1>, dim3(nb), dim3(64), 0, s, nb, flags, nullptr, roff, *keys_out, nullptr, kidx);
+    if (pat) {
+      ABD_TRY(scan_exclusive_i64(ctx, lcnt, loff, nb, loff + nb, s));
+      hipLaunchKernelGGL(k_od_lower, dim3(nb), dim3(64), 0, s, nb, flags, loff, kidx, tperm);
+      pat->lo_beg = roff;
+      pat->hi_beg = loff;
+      pat->tperm = tperm;
+      pat->valid = true;
+    }
     HIP_TRY(ctx, hipStreamSynchronize(s));
     *n_keys = hbuf[MIR_OFFDIAG];
     return abd_hip_check(ctx, hipGetLastError(), "offdiag");

@@ -158,10 +158,21 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
 int op_candidates_within(abd_ctx *ctx, const abd_scene *sc, const double *x, double inflate, const int32_t *spt,
                          int64_t n_spt, const int32_t *see, int64_t n_see, int32_t **pt, int64_t *n_pt, int32_t **ee,
                          int64_t *n_ee, const char *tag, hipStream_t s);
-// pattern of the pairs (pt, ee) and, when given, the extra pairs (pt2, ee2)
+// Row structure of a key list (keys sorted by (row, column), row < column)
+// for the block solvers: lo_beg[b] (nb + 1) the first key with row b,
+// hi_beg[b] (nb + 1) the first entry of body b in tperm, the key indices
+// ordered by (column, row).
+struct KeyPattern {
+  const int64_t *lo_beg = nullptr, *hi_beg = nullptr;
+  const uint32_t *tperm = nullptr;
+  bool valid = false;
+};
+// pattern of the pairs (pt, ee) and, when given, the extra pairs (pt2, ee2);
+// pat (may be NULL) receives the keys' row structure when the dense path
+// builds it (else pat->valid = false)
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2 = nullptr,
-               int64_t n_pt2 = 0, const int32_t *ee2 = nullptr, int64_t n_ee2 = 0);
+               int64_t n_pt2 = 0, const int32_t *ee2 = nullptr, int64_t n_ee2 = 0, KeyPattern *pat = nullptr);
 // barrier (and, when fr is given, the lagged friction of fr) energy,
 // gradient and Hessian blocks, assembled in one pass
 int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
@@ -208,9 +219,11 @@ int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
 int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
                    double *energy, hipStream_t s);
 // x0 (may be NULL = 0, may alias p): initial guess
+// pre_diag: preconditioner blocks (NULL: diag); pat: the keys' row
+// structure if already built (else built here)
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *p, double rtol, int max_iter, int *iters, hipStream_t s,
-           const double *x0 = nullptr, const double *pre_diag = nullptr);  // pre_diag: preconditioner blocks (NULL: diag)
+           const double *x0 = nullptr, const double *pre_diag = nullptr, const KeyPattern *pat = nullptr);
 // preconditioned MINRES on the (possibly indefinite) symmetric block matrix,
 // block-Jacobi preconditioner from the SPD diagonal blocks pre_diag; stops
 // at |r|_{P} <= rtol |b|_{P} (syncs every iteration)

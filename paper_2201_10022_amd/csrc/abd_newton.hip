@@ -230,8 +230,9 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s, done_dev));
   ctx->sw_valid = false;
   // the pattern covers the candidates and the lagged friction pairs
+  KeyPattern pat;
   ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", s, fr ? fr->pt : nullptr, fr ? fr->n_pt : 0,
-                     fr ? fr->ee : nullptr, fr ? fr->n_ee : 0));
+                     fr ? fr->ee : nullptr, fr ? fr->n_ee : 0, &pat));
   st->n_pt = npt;
   st->n_ee = nee;
   st->n_offdiag = nk;
@@ -255,7 +256,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   // (errors of the assembly and the solve are read with the displacement:
   // a failed assembly or block inverse leaves non-finite values that stop
   // the solve at once)
-  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s));
+  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s, nullptr, nullptr, &pat));
   st->pcg_iters = its;
   st->t_solve_ms += ms_since(t0);
   ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, sv, s));

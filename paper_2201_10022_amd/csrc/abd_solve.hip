@@ -1122,7 +1122,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
 
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *x_out, double rtol, int max_iter, int *iters, hipStream_t s,
-           const double *x0, const double *pre_diag) {
+           const double *x0, const double *pre_diag, const KeyPattern *pat) {
   const int nb = sc->n_bodies;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   *iters = 0;
@@ -1181,16 +1181,23 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
     hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, S, (int64_t)nblk_s, s_off,
                        s_scene);
   }
-  if (n_keys > 0) {
-    hipLaunchKernelGGL(k_tkeys, dim3(grid_for(n_keys, 256)), dim3(256), 0, s, n_keys, keys, tk, tv);
-    size_t tmp_bytes = 0;
-    HIP_TRY(ctx, rocprim::radix_sort_pairs(nullptr, tmp_bytes, tk, tk2, tv, tv2, (size_t)n_keys, 0, 64, s));
-    void *tmp;
-    ABD_TRY(ws_get(ctx, "pcg_sort_tmp", tmp_bytes + 16, &tmp, s));
-    HIP_TRY(ctx, rocprim::radix_sort_pairs(tmp, tmp_bytes, tk, tk2, tv, tv2, (size_t)n_keys, 0, 64, s));
+  if (pat && pat->valid) {
+    // row structure built with the keys
+    lo_beg = const_cast<int64_t *>(pat->lo_beg);
+    hi_beg = const_cast<int64_t *>(pat->hi_beg);
+    tv2 = const_cast<uint32_t *>(pat->tperm);
+  } else {
+    if (n_keys > 0) {
+      hipLaunchKernelGGL(k_tkeys, dim3(grid_for(n_keys, 256)), dim3(256), 0, s, n_keys, keys, tk, tv);
+      size_t tmp_bytes = 0;
+      HIP_TRY(ctx, rocprim::radix_sort_pairs(nullptr, tmp_bytes, tk, tk2, tv, tv2, (size_t)n_keys, 0, 64, s));
+      void *tmp;
+      ABD_TRY(ws_get(ctx, "pcg_sort_tmp", tmp_bytes + 16, &tmp, s));
+      HIP_TRY(ctx, rocprim::radix_sort_pairs(tmp, tmp_bytes, tk, tk2, tv, tv2, (size_t)n_keys, 0, 64, s));
+    }
+    hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(nb + 1, 256)), dim3(256), 0, s, nb, n_keys, keys, tk2, lo_beg,
+                       hi_beg);
   }
-  hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(nb + 1, 256)), dim3(256), 0, s, nb, n_keys, keys, tk2, lo_beg,
-                     hi_beg);
   // entry lists per body and per-block constants
   int64_t *ecnt, *eoff;
   int2 *ent;

@@ -340,17 +340,17 @@ struct alignas(16) PcgBlk {
 
 // per body: its matrix entries (the diagonal block first, then the
 // off-diagonal blocks with the body as row, then as column)
-__global__ void k_pcg_entcount(int nb, const int64_t *lo_beg, const int64_t *hi_beg, int64_t *cnt) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  cnt[b] = 1 + (lo_beg[b + 1] - lo_beg[b]) + (hi_beg[b + 1] - hi_beg[b]);
-}
 // entry = (block index, column body | transposed << 30); block -1 = diagonal
+// (body b's entries start at b + lo_beg[b] + hi_beg[b]: one diagonal entry
+// per earlier body plus the earlier rows' and columns' keys; ent_off gets
+// these offsets, nb + 1 of them)
 __global__ void k_pcg_entries(int nb, const int64_t *lo_beg, const int64_t *hi_beg, const uint32_t *tperm,
-                              const int32_t *keys, const int64_t *ent_off, int2 *ent) {
+                              const int32_t *keys, int64_t *ent_off, int2 *ent) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == nb) ent_off[nb] = nb + lo_beg[nb] + hi_beg[nb];
   if (b >= nb) return;
-  int64_t o = ent_off[b];
+  int64_t o = b + lo_beg[b] + hi_beg[b];
+  ent_off[b] = o;
   ent[o++] = make_int2(-1, b);
   for (int64_t kk = lo_beg[b]; kk < lo_beg[b + 1]; ++kk) ent[o++] = make_int2((int)kk, keys[2 * kk + 1]);
   for (int64_t h = hi_beg[b]; h < hi_beg[b + 1]; ++h) {
@@ -358,10 +358,28 @@ __global__ void k_pcg_entries(int nb, const int64_t *lo_beg, const int64_t *hi_b
     ent[o++] = make_int2(kk, keys[2 * kk] | (1 << 30));
   }
 }
-// block constants of a mapping with `bpb` bodies per block
-__global__ void k_pcg_blk(int64_t nblk, int bpb, const int32_t *tab, const int64_t *off, const int64_t *fold_off,
-                          const int32_t *sbo, const int64_t *ent_off, PcgBlk *out) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// block constants of a mapping with `bpb` bodies per block; up to three
+// mappings per launch (thread index over their concatenation)
+struct BlkJob {
+  int64_t nblk;
+  int bpb;
+  const int32_t *tab;
+  const int64_t *off, *fold_off, *ent_off;
+  PcgBlk *out;
+};
+struct BlkJobs {
+  BlkJob j[3];
+};
+__global__ void k_pcg_blk(BlkJobs J, const int32_t *sbo) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int m = 0;
+  while (m < 3 && j >= J.j[m].nblk) j -= J.j[m++].nblk;
+  if (m == 3) return;
+  const int64_t nblk = J.j[m].nblk;
+  const int bpb = J.j[m].bpb;
+  const int32_t *tab = J.j[m].tab;
+  const int64_t *off = J.j[m].off, *fold_off = J.j[m].fold_off, *ent_off = J.j[m].ent_off;
+  PcgBlk *out = J.j[m].out;
   if (j >= nblk) return;
   PcgBlk r;
   for (int q = 0; q < 16 - 6 - (SWBB + 1); ++q) r.pad[q] = 0;
@@ -1003,9 +1021,8 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   ABD_TRY(ws(ctx, "cg_s_bb", S, &scs.bb, s));
   ABD_TRY(ws(ctx, "cg_s_stop", S, &scs.stop, s));
   ABD_TRY(ws(ctx, "cg_s_final", S, &scs.it_final, s));
-  // iteration blocks fold their own mapping's partials
-  hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, (int64_t)nblk_s, SWBB, s_scene, s_off,
-                     s_off, sbo, eoff, cblk);
+  // (cblk, the iteration blocks' constants, folding their own mapping's
+  // partials, come from the caller's launch)
   hipLaunchKernelGGL(k_cg_reset, dim3(grid_for(S, 256)), dim3(256), 0, s, S, st, scs);
   hipLaunchKernelGGL(k_cg_bmat, dim3(nb), dim3(256), 0, s, nb, eoff, ent, diag, off, inv, Bm);
   hipLaunchKernelGGL(k_cg_init1, dim3(nblk_u), dim3(PB), 0, s, ublk, sc->body_fixed, inv, rhs, x0, Hx0, x_out, rv[0],
@@ -1199,21 +1216,28 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
                        hi_beg);
   }
   // entry lists per body and per-block constants
-  int64_t *ecnt, *eoff;
+  int64_t *eoff;
   int2 *ent;
   PcgBlk *sblk, *ublk;
-  ABD_TRY(ws(ctx, "pcg_ecnt", nb, &ecnt, s));
   ABD_TRY(ws(ctx, "pcg_eoff", nb + 1, &eoff, s));
   ABD_TRY(ws(ctx, "pcg_ent", nb + 2 * n_keys + 1, &ent, s));
   ABD_TRY(ws(ctx, "pcg_sblk", nblk_s, &sblk, s));
   ABD_TRY(ws(ctx, "pcg_ublk", nblk_u, &ublk, s));
-  hipLaunchKernelGGL(k_pcg_entcount, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, lo_beg, hi_beg, ecnt);
-  ABD_TRY(scan_exclusive_i64(ctx, ecnt, eoff, nb, eoff + nb, s));
-  hipLaunchKernelGGL(k_pcg_entries, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, lo_beg, hi_beg, tv2, keys, eoff, ent);
-  hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, (int64_t)nblk_s, SWBB, s_scene, s_off,
-                     u_off, sbo, eoff, sblk);
-  hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(nblk_u, 256)), dim3(256), 0, s, (int64_t)nblk_u, PBB, u_scene, u_off,
-                     s_off, sbo, nullptr, ublk);
+  hipLaunchKernelGGL(k_pcg_entries, dim3(grid_for(nb + 1, 256)), dim3(256), 0, s, nb, lo_beg, hi_beg, tv2, keys, eoff,
+                     ent);
+  // block constants of the three mappings: two-kernel SpMV blocks (folding
+  // the update blocks' partials), update blocks (folding the SpMV blocks'),
+  // one-kernel iteration blocks (folding their own)
+  PcgBlk *cblk;
+  ABD_TRY(ws(ctx, "cg_blk", nblk_s, &cblk, s));
+  {
+    BlkJobs J;
+    J.j[0] = BlkJob{(int64_t)nblk_s, SWBB, s_scene, s_off, u_off, eoff, sblk};
+    J.j[1] = BlkJob{(int64_t)nblk_u, PBB, u_scene, u_off, s_off, nullptr, ublk};
+    J.j[2] = BlkJob{(int64_t)nblk_s, SWBB, s_scene, s_off, s_off, eoff, cblk};
+    const int64_t tot = 2 * (int64_t)nblk_s + nblk_u;
+    hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(tot, 256)), dim3(256), 0, s, J, sbo);
+  }
   hipLaunchKernelGGL(k_pcg_reset, dim3(grid_for(S, 256)), dim3(256), 0, s, S, st, scs);
   const double *Hx0 = nullptr;
   if (x0) {

@@ -38,72 +38,85 @@ __device__ __forceinline__ bool box_overlap32(const float *a, const double *b) {
          (double)a[2] <= b[5] && b[2] <= (double)a[5];
 }
 
-__global__ void __launch_bounds__(256) k_vert_boxes(int nv, const double *x0, const double *x1, double inflate,
-                                                    double *vb, float *vb32) {
+// swept box of vertex v over x0 -> x1, inflated upwards
+__device__ __forceinline__ void vert_box(int64_t v, const double *x0, const double *x1, double inflate, double b[6]) {
 #pragma clang fp contract(off)
-  const int v = blockIdx.x * 256 + threadIdx.x;
-  if (v >= nv) return;
-  double b[6];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const double a = x0[3 * v + i], c = x1[3 * v + i];
     b[i] = fmin(a, c);
     b[3 + i] = fmax(a, c) + inflate;
   }
-#pragma unroll
-  for (int i = 0; i < 6; ++i) vb[6 * (int64_t)v + i] = b[i];
-  store_box32(vb32 + 6 * (int64_t)v, b);
 }
 
-template <int K>  // vertices per primitive
-__global__ void __launch_bounds__(256) k_prim_boxes(int n, const int32_t *prims, const double *vb, double *pb,
-                                                    float *pb32) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= n) return;
-  double b[6];
-  const int v0 = prims[K * (int64_t)p];
+// All boxes in one launch.  Blocks [0, nb): body boxes (min / max over the
+// body's vertex boxes); the blocks after them: one thread per vertex, then
+// per triangle, then per edge (a primitive box is the min / max of its
+// vertices' boxes, recomputed here rather than read back).
+__global__ void __launch_bounds__(256) k_boxes(int nb, const int32_t *voff, int nv, int nt, int ne,
+                                               const int32_t *tris, const int32_t *edges, const double *x0,
+                                               const double *x1, double inflate, double *vb, float *vb32, double *tb,
+                                               float *tb32, double *eb, float *eb32, double *bb) {
+  if ((int)blockIdx.x < nb) {
+    __shared__ double sh[6][4];
+    const int b = blockIdx.x;
+    double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int v = voff[b] + threadIdx.x; v < voff[b + 1]; v += 256) {
+      double vbx[6];
+      vert_box(v, x0, x1, inflate, vbx);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) b[i] = vb[6 * (int64_t)v0 + i];
-#pragma unroll
-  for (int k = 1; k < K; ++k) {
-    const int v = prims[K * (int64_t)p + k];
+      for (int i = 0; i < 3; ++i) {
+        m[i] = fmin(m[i], vbx[i]);
+        m[3 + i] = fmax(m[3 + i], vbx[3 + i]);
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      b[i] = fmin(b[i], vb[6 * (int64_t)v + i]);
-      b[3 + i] = fmax(b[3 + i], vb[6 * (int64_t)v + 3 + i]);
+      m[i] = wave_min(m[i]);
+      m[3 + i] = wave_max(m[3 + i]);
     }
-  }
+    if ((threadIdx.x & 63) == 0)
 #pragma unroll
-  for (int i = 0; i < 6; ++i) pb[6 * (int64_t)p + i] = b[i];
-  store_box32(pb32 + 6 * (int64_t)p, b);
-}
-
-__global__ void __launch_bounds__(256) k_body_boxes(int nb, const int32_t *voff, const double *vb, double *bb) {
-  __shared__ double sh[6][4];
-  const int b = blockIdx.x;
-  double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-  for (int v = voff[b] + threadIdx.x; v < voff[b + 1]; v += 256) {
+      for (int i = 0; i < 6; ++i) sh[i][threadIdx.x >> 6] = m[i];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      const int i = threadIdx.x;
+      double r = sh[i][0];
+      for (int w = 1; w < 4; ++w) r = i < 3 ? fmin(r, sh[i][w]) : fmax(r, sh[i][w]);
+      bb[6 * (int64_t)b + i] = r;
+    }
+    return;
+  }
+  int64_t k = ((int64_t)blockIdx.x - nb) * 256 + threadIdx.x;
+  double box[6];
+  if (k < nv) {
+    vert_box(k, x0, x1, inflate, box);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vb[6 * k + i] = box[i];
+    store_box32(vb32 + 6 * k, box);
+    return;
+  }
+  k -= nv;
+  const bool tri = k < nt;
+  if (!tri) k -= nt;
+  if (!tri && k >= ne) return;
+  const int K = tri ? 3 : 2;
+  const int32_t *prim = tri ? tris + 3 * k : edges + 2 * k;
+  vert_box(prim[0], x0, x1, inflate, box);
+  for (int q = 1; q < K; ++q) {
+    double o[6];
+    vert_box(prim[q], x0, x1, inflate, o);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      m[i] = fmin(m[i], vb[6 * (int64_t)v + i]);
-      m[3 + i] = fmax(m[3 + i], vb[6 * (int64_t)v + 3 + i]);
+      box[i] = fmin(box[i], o[i]);
+      box[3 + i] = fmax(box[3 + i], o[3 + i]);
     }
   }
+  double *out = tri ? tb : eb;
+  float *out32 = tri ? tb32 : eb32;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    m[i] = wave_min(m[i]);
-    m[3 + i] = wave_max(m[3 + i]);
-  }
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int i = 0; i < 6; ++i) sh[i][threadIdx.x >> 6] = m[i];
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    const int i = threadIdx.x;
-    double r = sh[i][0];
-    for (int w = 1; w < 4; ++w) r = i < 3 ? fmin(r, sh[i][w]) : fmax(r, sh[i][w]);
-    bb[6 * (int64_t)b + i] = r;
-  }
+  for (int i = 0; i < 6; ++i) out[6 * k + i] = box[i];
+  store_box32(out32 + 6 * k, box);
 }
 
 // body pairs (a < b) in one sub-scene, not both fixed, boxes overlapping.
@@ -409,12 +422,9 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_vbox32", 6 * (size_t)nv, &vbox32, s));
   ABD_TRY(ws(ctx, "bp_tbox32", 6 * (size_t)nt + 6, &tbox32, s));
   ABD_TRY(ws(ctx, "bp_ebox32", 6 * (size_t)ne + 6, &ebox32, s));
-  hipLaunchKernelGGL(k_vert_boxes, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv, x0, x1, inflate, vbox, vbox32);
-  if (nt)
-    hipLaunchKernelGGL(k_prim_boxes<3>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, sc->tris, vbox, tbox, tbox32);
-  if (ne)
-    hipLaunchKernelGGL(k_prim_boxes<2>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, sc->edges, vbox, ebox, ebox32);
-  hipLaunchKernelGGL(k_body_boxes, dim3(nb), dim3(256), 0, s, nb, sc->body_vert_off, vbox, bbox);
+  hipLaunchKernelGGL(k_boxes, dim3(nb + grid_for((int64_t)nv + nt + ne, 256)), dim3(256), 0, s, nb,
+                     sc->body_vert_off, nv, nt, ne, sc->tris, sc->edges, x0, x1, inflate, vbox, vbox32, tbox, tbox32,
+                     ebox, ebox32, bbox);
   HIP_TRY(ctx, hipGetLastError());
 
   // body pairs

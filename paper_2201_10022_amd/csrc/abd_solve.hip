@@ -276,19 +276,6 @@ __global__ void k_pcg_block_scene(int S, int64_t nblk, const int64_t *off, int32
   tab[j] = lo;
 }
 
-__global__ void k_pcg_reset(int S, PcgState *st, PcgScene sc) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) {
-    st->it_done = 0;
-    st->k_cur = 0;
-    st->n_stopped = 0;
-    st->max_final = 0;
-  }
-  if (s < S) {
-    sc.stop[s] = 0;
-    sc.it_final[s] = 0;
-  }
-}
 
 // r = rhs - H x0 (free bodies; Hx0 NULL: x0 = 0), x = x0, z = P r, p_old = 0;
 // partials of r.z, r.r and rhs.rhs
@@ -370,8 +357,19 @@ struct BlkJob {
 struct BlkJobs {
   BlkJob j[3];
 };
-__global__ void k_pcg_blk(BlkJobs J, const int32_t *sbo) {
+__global__ void k_pcg_blk(BlkJobs J, const int32_t *sbo, int S, PcgState *st, PcgScene scs) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // (the two-kernel form's state reset rides along)
+  if (j == 0) {
+    st->it_done = 0;
+    st->k_cur = 0;
+    st->n_stopped = 0;
+    st->max_final = 0;
+  }
+  for (int64_t q = j; q < S; q += (int64_t)gridDim.x * blockDim.x) {
+    scs.stop[q] = 0;
+    scs.it_final[q] = 0;
+  }
   int m = 0;
   while (m < 3 && j >= J.j[m].nblk) j -= J.j[m++].nblk;
   if (m == 3) return;
@@ -624,18 +622,6 @@ __device__ __forceinline__ void cg_step(double r, double w, double s_prev, doubl
   r_new = fma(-alpha, s_new, r);
 }
 
-__global__ void k_cg_reset(int S, CgState *st, CgScene sc) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) {
-    st->base = 0;
-    st->n_stopped = 0;
-    st->max_final = 0;
-  }
-  if (s < S) {
-    sc.stop[s] = 0;
-    sc.it_final[s] = 0;
-  }
-}
 
 // r = rhs - H x0 (free bodies; Hx0 NULL: x0 = 0), x = x0, u = P r,
 // p = 0, s_prev = 0
@@ -730,9 +716,21 @@ __global__ void __launch_bounds__(SWB) k_cg_init2(const PcgBlk *blk, const int2 
 // (144 doubles per entry), so that w = H u = H P r = sum_c B_bc r_c needs
 // the column bodies' residuals only.  One block per row body.
 __global__ void __launch_bounds__(256) k_cg_bmat(int nb, const int64_t *eoff, const int2 *ent, const double *diag,
-                                                const double *off, const double *inv, double *B) {
+                                                const double *off, const double *inv, double *B, int S, CgState *st,
+                                                CgScene scs) {
   const int b = blockIdx.x;
   if (b >= nb) return;
+  if (b == 0) {  // (the iteration state's reset rides along)
+    if (threadIdx.x == 0) {
+      st->base = 0;
+      st->n_stopped = 0;
+      st->max_final = 0;
+    }
+    for (int q = threadIdx.x; q < S; q += blockDim.x) {
+      scs.stop[q] = 0;
+      scs.it_final[q] = 0;
+    }
+  }
   const int64_t e0 = eoff[b];
   const int n = (int)(eoff[b + 1] - e0) * 144;
   for (int t = threadIdx.x; t < n; t += 256) {
@@ -1023,8 +1021,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   ABD_TRY(ws(ctx, "cg_s_final", S, &scs.it_final, s));
   // (cblk, the iteration blocks' constants, folding their own mapping's
   // partials, come from the caller's launch)
-  hipLaunchKernelGGL(k_cg_reset, dim3(grid_for(S, 256)), dim3(256), 0, s, S, st, scs);
-  hipLaunchKernelGGL(k_cg_bmat, dim3(nb), dim3(256), 0, s, nb, eoff, ent, diag, off, inv, Bm);
+  hipLaunchKernelGGL(k_cg_bmat, dim3(nb), dim3(256), 0, s, nb, eoff, ent, diag, off, inv, Bm, S, st, scs);
   hipLaunchKernelGGL(k_cg_init1, dim3(nblk_u), dim3(PB), 0, s, ublk, sc->body_fixed, inv, rhs, x0, Hx0, x_out, rv[0],
                      u, p, sv[0]);
   hipLaunchKernelGGL(k_cg_init2, dim3(nblk_s), dim3(SWB), 0, s, cblk, ent, sc->body_fixed, diag, off, rhs, rv[0], u,
@@ -1236,9 +1233,8 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
     J.j[1] = BlkJob{(int64_t)nblk_u, PBB, u_scene, u_off, s_off, nullptr, ublk};
     J.j[2] = BlkJob{(int64_t)nblk_s, SWBB, s_scene, s_off, s_off, eoff, cblk};
     const int64_t tot = 2 * (int64_t)nblk_s + nblk_u;
-    hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(tot, 256)), dim3(256), 0, s, J, sbo);
+    hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(tot, 256)), dim3(256), 0, s, J, sbo, S, st, scs);
   }
-  hipLaunchKernelGGL(k_pcg_reset, dim3(grid_for(S, 256)), dim3(256), 0, s, S, st, scs);
   const double *Hx0 = nullptr;
   if (x0) {
     // warm start: r = rhs - H x0 (Ap as scratch)

@@ -47,6 +47,11 @@ struct abd_ctx {
   // (read after the stream synchronises; allocated once, so its address
   // can be baked into captured graphs)
   int64_t *mirror_h = nullptr, *mirror_d = nullptr;
+  // look-back scan: status words (lb_tiles of them, then the tile counter)
+  // and the tag of the last call
+  unsigned long long *lb_status = nullptr;
+  int64_t lb_tiles = 0;
+  unsigned int lb_tag = 0;
   hipEvent_t ev[8] = {};
   bool profiling = false;
   std::map<std::string, KStat> kstats;

@@ -92,6 +92,7 @@ int err_check(abd_ctx *ctx, int e, hipStream_t s) {
   if (e & 2) return abd_fail(ctx, ABD_E_INVALID, "pair's body pair missing from the off-diagonal keys");
   if (e & 4) return abd_fail(ctx, ABD_E_PCG, "diagonal block not positive definite");
   if (e & 8) return abd_fail(ctx, ABD_E_PCG, "PCG breakdown (non-positive curvature)");
+  if (e & 16) return abd_fail(ctx, ABD_E_HIP, "scan: look-back wait exceeded its cap");
   return ABD_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <rocprim/device/device_scan.hpp>
 
 #include "abd_internal.h"
+#include "abd_lookback.h"
 
 int abd_fail(abd_ctx *ctx, int code, const char *fmt, ...) {
   char buf[512];
@@ -160,27 +161,10 @@ __global__ void __launch_bounds__(SCAN1_T) k_scan1(const int64_t *in, int64_t *o
   }
 }
 
-// Exclusive scan of more values in one pass (decoupled look-back): each
-// block takes the next tile of LB_TILE values from a counter, publishes its
-// tile's sum, then the sum of everything before it, and finds its prefix
-// from the nearest earlier tile whose prefix is published (adding the sums
-// of the tiles in between).  A status word packs (call tag, flag, value)
-// into one 64-bit atomic, so no fence orders a flag against its value;
-// the tag, new on every call, makes words of earlier calls read as not yet
-// published, and the counter restarts when a block finds it tagged with an
-// earlier call.  Every tile waits only on tiles claimed before it, whose
-// blocks are running and publish without waiting, so the waits end; a
-// spin cap (error bit 16) bounds them regardless.
+// Exclusive scan of more values in one pass, by decoupled look-back over
+// tiles of LB_TILE values (abd_lookback.h).
 constexpr int LB_T = 256, LB_U = 8;
 constexpr int64_t LB_TILE = (int64_t)LB_T * LB_U;
-constexpr int LB_TAG_BITS = 20;
-constexpr unsigned long long LB_VAL_MASK = (1ull << 42) - 1;
-constexpr int LB_SPIN_CAP = 1 << 24;
-__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 __global__ void __launch_bounds__(LB_T) k_scan_lb(const int64_t *in, int64_t *out, int64_t n, int64_t *total,
                                                   int64_t *host, int64_t split, unsigned long long *status,
                                                   unsigned long long *counter, unsigned int tag, int *err) {
@@ -188,27 +172,7 @@ __global__ void __launch_bounds__(LB_T) k_scan_lb(const int64_t *in, int64_t *ou
   __shared__ int64_t s_agg, s_prefix;
   __shared__ unsigned int s_tile;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const unsigned long long T = (unsigned long long)tag;
-  if (t == 0) {
-    unsigned int tile = 0;
-    for (int spin = 0;; ++spin) {
-      const unsigned long long v = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if ((v >> 32) != T) {
-        if (atomicCAS(counter, v, (T << 32) | 1ull) == v) {
-          tile = 0;
-          break;
-        }
-        if (spin > LB_SPIN_CAP) {  // (cannot happen: some CAS succeeds)
-          atomicOr(err, 16);
-          break;
-        }
-      } else {
-        tile = (unsigned int)(atomicAdd(counter, 1ull) & 0xffffffffull);
-        break;
-      }
-    }
-    s_tile = tile;
-  }
+  if (t == 0) s_tile = lb_claim(counter, tag, err);
   __syncthreads();
   const int64_t tile = s_tile;
   const int64_t i0 = tile * LB_TILE + (int64_t)t * LB_U;
@@ -238,47 +202,7 @@ __global__ void __launch_bounds__(LB_T) k_scan_lb(const int64_t *in, int64_t *ou
   }
   __syncthreads();
   if (w == 0) {
-    const int64_t agg = s_agg;
-    int64_t p = 0;
-    if (tile == 0) {
-      if (lane == 0) __hip_atomic_store(status, (T << 44) | (2ull << 42) | ((unsigned long long)agg & LB_VAL_MASK),
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      if (lane == 0)
-        __hip_atomic_store(status + tile, (T << 44) | (1ull << 42) | ((unsigned long long)agg & LB_VAL_MASK),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      // look back 64 tiles at a time, one per lane
-      int64_t j0 = tile - 1;
-      for (int spin = 0;;) {
-        const int64_t j = j0 - lane;
-        bool ready = true;
-        int flag = 2;
-        int64_t val = 0;
-        if (j >= 0) {  // (before tile 0: a published prefix of 0)
-          const unsigned long long st = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ready = (st >> 44) == T;
-          flag = (int)((st >> 42) & 3ull);
-          val = (int64_t)(st & LB_VAL_MASK);
-        }
-        const unsigned long long pre = __ballot(ready && flag == 2);
-        const int first = pre ? __ffsll((long long)pre) - 1 : 64;
-        const unsigned long long need = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1ull);
-        if (__ballot(!ready) & need) {
-          if (++spin > LB_SPIN_CAP) {
-            if (lane == 0) atomicOr(err, 16);
-            break;
-          }
-          continue;
-        }
-        p += wave_sum_i64(lane <= first ? val : 0);
-        if (first < 64) break;
-        j0 -= 64;
-      }
-      if (lane == 0)
-        __hip_atomic_store(status + tile,
-                           (T << 44) | (2ull << 42) | ((unsigned long long)(p + agg) & LB_VAL_MASK), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const int64_t p = lb_lookback(status, tile, s_agg, tag, err);
     if (lane == 0) s_prefix = p;
   }
   __syncthreads();
@@ -301,6 +225,27 @@ __global__ void __launch_bounds__(LB_T) k_scan_lb(const int64_t *in, int64_t *ou
   }
 }
 
+int lb_prepare(abd_ctx *ctx, int64_t words, unsigned long long **status, unsigned int *tag, hipStream_t s) {
+  if (ctx->lb_words < words) {
+    // status words start untagged (tag 0 is never used)
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (ctx->lb_status) HIP_TRY(ctx, hipFree(ctx->lb_status));
+    ctx->lb_status = nullptr;
+    const int64_t cap = words + words / 2 + 64;
+    HIP_TRY(ctx, hipMalloc(&ctx->lb_status, cap * sizeof(unsigned long long)));
+    HIP_TRY(ctx, hipMemsetAsync(ctx->lb_status, 0, cap * sizeof(unsigned long long), s));
+    ctx->lb_words = cap;
+  }
+  if (++ctx->lb_tag >= (1u << LB_TAG_BITS)) {
+    // tags wrap: clear the words so that none carries a reused tag
+    ctx->lb_tag = 1;
+    HIP_TRY(ctx, hipMemsetAsync(ctx->lb_status, 0, ctx->lb_words * sizeof(unsigned long long), s));
+  }
+  *status = ctx->lb_status;
+  *tag = ctx->lb_tag;
+  return ABD_OK;
+}
+
 int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t s,
                        int64_t *host, int64_t split) {
   if (n < 0) n = 0;
@@ -311,27 +256,15 @@ int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n,
     return abd_hip_check(ctx, hipGetLastError(), "k_scan1");
   }
   const int64_t tiles = (n + LB_TILE - 1) / LB_TILE;
-  if (tiles <= (1ll << 31) && n < (1ll << 42)) {
-    if (ctx->lb_tiles < tiles) {
-      // status words start untagged (tag 0 is never used)
-      HIP_TRY(ctx, hipStreamSynchronize(s));
-      if (ctx->lb_status) HIP_TRY(ctx, hipFree(ctx->lb_status));
-      ctx->lb_status = nullptr;
-      const int64_t cap = tiles + tiles / 2 + 64;
-      HIP_TRY(ctx, hipMalloc(&ctx->lb_status, (cap + 1) * sizeof(unsigned long long)));
-      HIP_TRY(ctx, hipMemsetAsync(ctx->lb_status, 0, (cap + 1) * sizeof(unsigned long long), s));
-      ctx->lb_tiles = cap;
-    }
-    if (++ctx->lb_tag >= (1u << LB_TAG_BITS)) {
-      // tags wrap: clear the words so that none carries a reused tag
-      ctx->lb_tag = 1;
-      HIP_TRY(ctx, hipMemsetAsync(ctx->lb_status, 0, (ctx->lb_tiles + 1) * sizeof(unsigned long long), s));
-    }
+  if (tiles < (1ll << 31) && n < (1ll << 42)) {
+    unsigned long long *st;
+    unsigned int tag;
+    ABD_TRY(lb_prepare(ctx, tiles + 1, &st, &tag, s));
     int *err;
     ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
     // the counter is the word after the tiles' status words
-    hipLaunchKernelGGL(k_scan_lb, dim3((unsigned)tiles), dim3(LB_T), 0, s, in, out, n, total, host, split,
-                       ctx->lb_status, ctx->lb_status + ctx->lb_tiles, ctx->lb_tag, err);
+    hipLaunchKernelGGL(k_scan_lb, dim3((unsigned)tiles), dim3(LB_T), 0, s, in, out, n, total, host, split, st,
+                       st + tiles, tag, err);
     return abd_hip_check(ctx, hipGetLastError(), "k_scan_lb");
   }
   // the last input for the total: a copy only when the scan is in place

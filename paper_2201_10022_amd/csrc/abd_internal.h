@@ -47,10 +47,10 @@ struct abd_ctx {
   // (read after the stream synchronises; allocated once, so its address
   // can be baked into captured graphs)
   int64_t *mirror_h = nullptr, *mirror_d = nullptr;
-  // look-back scan: status words (lb_tiles of them, then the tile counter)
-  // and the tag of the last call
+  // look-back status words (shared by all look-back launches: every launch
+  // takes a new tag) and the tag of the last launch
   unsigned long long *lb_status = nullptr;
-  int64_t lb_tiles = 0;
+  int64_t lb_words = 0;
   unsigned int lb_tag = 0;
   hipEvent_t ev[8] = {};
   bool profiling = false;
@@ -113,6 +113,9 @@ constexpr int MIR_OFFDIAG = 8;   // 1 slot: off-diagonal key count
 constexpr int MIR_COMPACT = 12;  // 2 slots: compaction total and PT count
 constexpr int MIR_PCG = 16;      // 2 slots (4 ints): PCG iteration state
 int mirror_get(abd_ctx *ctx, int64_t **host, int64_t **dev);
+// at least `words` zero-or-stale look-back status words and a new tag for
+// one launch (abd_lookback.h)
+int lb_prepare(abd_ctx *ctx, int64_t words, unsigned long long **status, unsigned int *tag, hipStream_t s);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 

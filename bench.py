@@ -151,7 +151,7 @@ def roofline(ks):
 # steps with rocprofv3 FETCH_SIZE and WRITE_SIZE (k_cg_iter + k_cg_advance,
 # each counter scaled by what it reads for a 512 MiB device copy); valid for
 # the k_cg_iter the measurement was taken on
-PCG_ROUND_TRAFFIC = 335.3e6
+PCG_ROUND_TRAFFIC = 330.3e6
 
 KERNELS = ("pcg_round", "barrier_local", "accd", "assemble_chunks", "pair_tiles_write", "energy_only",
            "friction_local")

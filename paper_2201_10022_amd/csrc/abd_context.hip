@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(TRB) k_trial_pass(const double *vals, int64_t 
     part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = r;
   }
 }
-__global__ void __launch_bounds__(TRB) k_trial_final(const double *part, int np, double *out) {
+__global__ void __launch_bounds__(TRB) k_trial_final(const double *part, int np, double *out, int assign) {
   __shared__ double sh[TRB / 64];
   const double *pp = part + (int64_t)blockIdx.x * np;
   double a = 0.0;
@@ -485,14 +485,18 @@ __global__ void __launch_bounds__(TRB) k_trial_final(const double *part, int np,
   if (threadIdx.x == 0) {
     double r = sh[0];
     for (int w = 1; w < TRB / 64; ++w) r += sh[w];
-    out[blockIdx.x] += r;
+    if (assign)
+      out[blockIdx.x] = r;
+    else
+      out[blockIdx.x] += r;
   }
 }
 }  // namespace
 
 int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, const int32_t *keys, int n_trials,
-                   int n_scenes, double *out_accum, hipStream_t s) {
+                   int n_scenes, double *out_accum, hipStream_t s, bool assign) {
   if (n <= 0 || n_trials <= 0) return ABD_OK;
+  if (assign && n_scenes > 1) return abd_fail(ctx, ABD_E_INVALID, "seg_sum_trials: assign needs one scene");
   if (n_scenes > 1) {
     hipLaunchKernelGGL(k_seg_reduce_trials, dim3(n_trials * n_scenes), dim3(SB), 0, s, vals, stride, n, keys, n_scenes,
                        out_accum);
@@ -503,7 +507,7 @@ int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, 
   double *part;
   ABD_TRY(ws(ctx, "trial_part", (size_t)nblk * n_trials, &part, s));
   hipLaunchKernelGGL(k_trial_pass, dim3(nblk, n_trials), dim3(TRB), 0, s, vals, stride, n, part);
-  hipLaunchKernelGGL(k_trial_final, dim3(n_trials), dim3(TRB), 0, s, part, nblk, out_accum);
+  hipLaunchKernelGGL(k_trial_final, dim3(n_trials), dim3(TRB), 0, s, part, nblk, out_accum, assign ? 1 : 0);
   return abd_hip_check(ctx, hipGetLastError(), "k_trial_pass");
 }
 

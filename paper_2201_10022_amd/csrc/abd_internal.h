@@ -483,7 +483,8 @@ int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionS
                               int n_trials, double *energy, hipStream_t s, double *items = nullptr,
                               int64_t estride = 0);
 int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, const int32_t *keys, int n_trials,
-                   int n_scenes, double *out_accum, hipStream_t s);
+                   int n_scenes, double *out_accum, hipStream_t s,
+                   bool assign = false);
 int seg_sum_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out_accum,
                    hipStream_t s);
 int seg_max_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out,

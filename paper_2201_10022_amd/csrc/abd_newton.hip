@@ -148,7 +148,8 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
   double *qn, *xn;
   ABD_TRY(ws(ctx, "ls_q", (size_t)n * n12, &qn, s));
   ABD_TRY(ws(ctx, "ls_x", (size_t)n * 3 * sc->n_verts, &xn, s));
-  ABD_TRY(zero(ctx, e_dev, (int64_t)n * S, s));
+  // (one scene with items: the row sums below are assigned, not added)
+  if (S > 1 || (int64_t)nb + npt + nee + (fr ? fr->n() : 0) == 0) ABD_TRY(zero(ctx, e_dev, (int64_t)n * S, s));
   hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), n), dim3(256), 0, s, nb, S, sc->body_scene, q, alpha, p,
                      qn);
   ABD_TRY(op_vertex_map_trials(ctx, sc, qn, n, xn, s));
@@ -167,7 +168,7 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
   ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, nullptr, s, items, nt));
   if (npt + nee) ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, xn, n, pt, npt, ee, nee, nullptr, s, items + nb, nt));
   if (nfr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, nullptr, s, items + nb + npt + nee, nt));
-  return seg_sum_trials(ctx, items, nt, nt, nullptr, n, 1, e_dev, s);
+  return seg_sum_trials(ctx, items, nt, nt, nullptr, n, 1, e_dev, s, true);
 }
 
 constexpr int LS_BATCH = 4;  // trial step lengths evaluated per line-search batch

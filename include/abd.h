@@ -268,7 +268,7 @@ int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, doub
  * preconditioner: first by preconditioned conjugate gradients (as
  * abd_pcg_solve); if CG meets non-positive curvature or reaches its
  * iteration cap, again by MINRES (residual in the preconditioner's norm),
- * which needs symmetry only.  Then it writes
+ * which needs symmetry only (environment ABD_ADJ_MINRES=1: MINRES alone).  Then it writes
  * qbar_t = M l + H_D l - C_lag^T l - qdbar_next/dt and qdbar_t = dt M l
  * (H_D the friction Hessian; C_lag the derivative of the friction gradient
  * through the lagged normal force, tangent basis and closest-point weights,

@@ -138,12 +138,18 @@ int op_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, co
   hipLaunchKernelGGL(k_adj_rhs, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_fixed, qbar_next, qdbar_next,
                      1.0 / prm->dt, a);
   int its = 0;
-  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, a, l, rtol, max_iter, &its, s, nullptr, pre));
+  // (environment ABD_ADJ_MINRES=1: MINRES alone)
+  const char *only_mr = getenv("ABD_ADJ_MINRES");
+  const bool cg_first = !(only_mr && only_mr[0] == '1');
   int *herr;
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&herr)));
-  ABD_TRY(err_enqueue(ctx, herr, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  if ((herr[0] & (4 | 8)) || its >= max_iter) {
+  herr[0] = 0;
+  if (cg_first) {
+    ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, a, l, rtol, max_iter, &its, s, nullptr, pre));
+    ABD_TRY(err_enqueue(ctx, herr, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+  }
+  if (!cg_first || (herr[0] & (4 | 8)) || its >= max_iter) {
     int *errf;
     ABD_TRY(ws(ctx, "err_flag", 1, &errf, s));
     HIP_TRY(ctx, hipMemsetAsync(errf, 0, sizeof(int), s));

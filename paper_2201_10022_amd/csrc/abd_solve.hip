@@ -1427,6 +1427,102 @@ __global__ void k_vzero(int n, double *a) {
   if (i < n) a[i] = 0.0;
 }
 
+// MINRES scalars on the device (Paige and Saunders' recurrences with the
+// preconditioner's inner product), so that iterations are queued without a
+// host round trip; the host reads `done` once per batch.  An iteration
+// begun after `done` is set changes nothing: apply = 0 for it.
+struct MrState {
+  double gam, gam_prev, eta, c, c_prev, sn, s_prev, g1, rtol;
+  double delta;                       // (A z / gam) . (z / gam) of the iteration
+  double inv_gam, va, vb;             // v_next = inv_gam A z - va v - vb v_prev
+  double wz, wa3, wa2, wa1, wcx;      // w_next = (wz z - wa3 w_prev - wa2 w) / wa1; x += wcx w_next
+  int done, apply, iters, err;        // err: 1 preconditioner not SPD, 2 breakdown
+};
+constexpr int MR_T = 1024;
+__device__ __forceinline__ double mr_block_dot(const double *a, const double *b, int n, double *sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += MR_T) v += a[i] * b[i];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < MR_T / 64; ++w) r += sh[w];
+  return r;  // (thread 0)
+}
+// delta = (A z / gam) . (z / gam) from the unscaled A z
+__global__ void __launch_bounds__(MR_T) k_mr_delta(const double *Az, const double *z, int n, MrState *st) {
+  __shared__ double sh[MR_T / 64];
+  if (st->done) return;
+  const double dz = mr_block_dot(Az, z, n, sh);
+  if (threadIdx.x == 0) {
+    const double gam = st->gam;
+    const double delta = dz / gam / gam;
+    st->inv_gam = 1.0 / gam;
+    st->va = delta / gam;
+    st->vb = gam / st->gam_prev;
+    st->delta = delta;
+  }
+}
+__global__ void k_mr_v(int n, const double *Az, const double *v, const double *vp, const MrState *st, double *vn) {
+  if (st->done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) vn[i] = st->inv_gam * Az[i] - st->va * v[i] - st->vb * vp[i];
+}
+// gamma_next from z_next . v_next, the Givens rotation, the w / x update
+// coefficients, the residual estimate and the stop test
+__global__ void __launch_bounds__(MR_T) k_mr_rot(const double *zn, const double *vn, int n, MrState *st) {
+  __shared__ double sh[MR_T / 64];
+  if (st->done) {
+    if (threadIdx.x == 0) st->apply = 0;
+    return;
+  }
+  const double gn2 = mr_block_dot(zn, vn, n, sh);
+  if (threadIdx.x != 0) return;
+  if (!(gn2 >= 0.0)) {
+    st->err = 1;
+    st->done = 1;
+    st->apply = 0;
+    return;
+  }
+  const double gam = st->gam, delta = st->delta, c = st->c, c_prev = st->c_prev, sn = st->sn, s_prev = st->s_prev;
+  const double gn = sqrt(gn2);
+  const double a0 = c * delta - c_prev * sn * gam;
+  const double a1 = sqrt(a0 * a0 + gn * gn);
+  const double a2 = sn * delta + c_prev * c * gam;
+  const double a3 = s_prev * gam;
+  if (!(a1 > 0.0)) {
+    st->err = 2;
+    st->done = 1;
+    st->apply = 0;
+    return;
+  }
+  const double c_n = a0 / a1, s_n = gn / a1;
+  st->wz = 1.0 / gam;
+  st->wa3 = a3;
+  st->wa2 = a2;
+  st->wa1 = a1;
+  st->wcx = c_n * st->eta;
+  st->apply = 1;
+  st->eta = -s_n * st->eta;
+  st->gam_prev = gam;
+  st->gam = gn;
+  st->c_prev = c;
+  st->c = c_n;
+  st->s_prev = sn;
+  st->sn = s_n;
+  st->iters += 1;
+  if (fabs(st->eta) <= st->rtol * st->g1 || gn == 0.0) st->done = 1;
+}
+__global__ void k_mr_wx(int n, const double *z, double *wp, const double *w, const MrState *st, double *x) {
+  if (!st->apply) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double wn = (st->wz * z[i] - st->wa3 * wp[i] - st->wa2 * w[i]) / st->wa1;
+  wp[i] = wn;
+  x[i] += st->wcx * wn;
+}
+
 }  // namespace
 
 int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
@@ -1494,58 +1590,54 @@ int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const doubl
   double gam = std::sqrt(g2), gam_prev = 1.0;
   const double g1 = gam;
   if (g1 == 0.0) return ABD_OK;
-  double eta = gam, c_prev = 1.0, c = 1.0, s_prev = 0.0, sn = 0.0;
-  double *vp = v0, *vc = v1, *vn = v2, *wp = w0, *wc = w1;
+  // device scalars; iterations queued in batches of MR_BATCH, the host
+  // reading the stop flag, the count and the error after each batch
+  MrState h0 = {};
+  h0.gam = gam;
+  h0.gam_prev = gam_prev;
+  h0.eta = gam;
+  h0.c = h0.c_prev = 1.0;
+  h0.sn = h0.s_prev = 0.0;
+  h0.g1 = g1;
+  h0.rtol = rtol;
+  MrState *st;
+  ABD_TRY(ws(ctx, "mr_state", 1, &st, s));
+  MrState *hs;
+  ABD_TRY(pinned_get(ctx, sizeof(MrState), reinterpret_cast<void **>(&hs)));
+  *hs = h0;
+  HIP_TRY(ctx, hipMemcpyAsync(st, hs, sizeof(MrState), hipMemcpyHostToDevice, s));
+  double *z2;
+  ABD_TRY(ws(ctx, "mr_z2", n12, &z2, s));
+  double *vp = v0, *vc = v1, *vn = v2, *wp = w0, *wc = w1, *zc = z, *zn = z2;
+  constexpr int MR_BATCH = 16;
   int j = 0;
-  for (; j < max_iter; ++j) {
-    // A (z / gamma), delta = (A z/gamma) . z/gamma
-    hipLaunchKernelGGL(k_bsr_spmv, dim3(gs), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2, lo_beg, hi_beg,
-                       z, 1.0 / gam, Az);
-    double dz;
-    ABD_TRY(dotp(Az, z, &dz));
-    const double delta = dz / gam;
-    hipLaunchKernelGGL(k_minres_v, dim3(gv), dim3(256), 0, s, n12, Az, vc, vp, delta / gam, gam / gam_prev, vn);
-    // z_next = P v_next (z of this iteration is still needed below: keep it in tmp)
-    HIP_TRY(ctx, hipMemcpyAsync(tmp, z, sizeof(double) * n12, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_block_apply, dim3(gv), dim3(256), 0, s, nb, inv, vn, z);
-    double gn2;
-    {
-      // gamma_next^2 = z_next . v_next (uses Az as scratch)
-      hipLaunchKernelGGL(k_vmul, dim3(gv), dim3(256), 0, s, n12, z, vn, Az);
-      HIP_TRY(ctx, hipMemsetAsync(dot, 0, sizeof(double), s));
-      ABD_TRY(reduce_sum_f64(ctx, Az, n12, dot, s));
-      HIP_TRY(ctx, hipMemcpyAsync(h, dot, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(ctx, hipStreamSynchronize(s));
-      gn2 = h[0];
+  while (j < max_iter) {
+    const int nbat = max_iter - j < MR_BATCH ? max_iter - j : MR_BATCH;
+    for (int q = 0; q < nbat; ++q) {
+      hipLaunchKernelGGL(k_bsr_spmv, dim3(gs), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2, lo_beg,
+                         hi_beg, zc, 1.0, Az);
+      hipLaunchKernelGGL(k_mr_delta, dim3(1), dim3(MR_T), 0, s, Az, zc, n12, st);
+      hipLaunchKernelGGL(k_mr_v, dim3(gv), dim3(256), 0, s, n12, Az, vc, vp, st, vn);
+      hipLaunchKernelGGL(k_block_apply, dim3(gv), dim3(256), 0, s, nb, inv, vn, zn);
+      hipLaunchKernelGGL(k_mr_rot, dim3(1), dim3(MR_T), 0, s, zn, vn, n12, st);
+      hipLaunchKernelGGL(k_mr_wx, dim3(gv), dim3(256), 0, s, n12, zc, wp, wc, st, x_out);
+      // rotate (data independent, so queued iterations agree with the device)
+      std::swap(wp, wc);
+      double *t = vp;
+      vp = vc;
+      vc = vn;
+      vn = t;
+      std::swap(zc, zn);
     }
-    if (!(gn2 >= 0.0)) return abd_fail(ctx, ABD_E_PCG, "MINRES: preconditioner not positive definite");
-    const double gn = std::sqrt(gn2);
-    const double a0 = c * delta - c_prev * sn * gam;
-    const double a1 = std::sqrt(a0 * a0 + gn * gn);
-    const double a2 = sn * delta + c_prev * c * gam;
-    const double a3 = s_prev * gam;
-    if (!(a1 > 0.0)) return abd_fail(ctx, ABD_E_PCG, "MINRES breakdown (singular system)");
-    const double c_n = a0 / a1, s_n = gn / a1;
-    hipLaunchKernelGGL(k_minres_wx, dim3(gv), dim3(256), 0, s, n12, tmp, 1.0 / gam, wp, wc, a3, a2, a1, c_n * eta,
-                       x_out);
-    std::swap(wp, wc);  // w_prev <- w, w <- w_next
-    eta = -s_n * eta;
-    // rotate
-    double *t = vp;
-    vp = vc;
-    vc = vn;
-    vn = t;
-    gam_prev = gam;
-    gam = gn;
-    c_prev = c;
-    c = c_n;
-    s_prev = sn;
-    sn = s_n;
-    if (std::fabs(eta) <= rtol * g1 || gn == 0.0) {
-      ++j;
-      break;
-    }
+    j += nbat;
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(hs, st, sizeof(MrState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (hs->err == 1) return abd_fail(ctx, ABD_E_PCG, "MINRES: preconditioner not positive definite");
+    if (hs->err == 2) return abd_fail(ctx, ABD_E_PCG, "MINRES breakdown (singular system)");
+    if (hs->done) break;
   }
+  j = hs->iters;
   *iters = j;
   return abd_hip_check(ctx, hipGetLastError(), "minres");
 }

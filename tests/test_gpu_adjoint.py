@@ -50,8 +50,15 @@ def _cases():
 CASES = _cases()
 
 
+@pytest.mark.parametrize("solver", ["cg_first", "minres"])
 @pytest.mark.parametrize("name,S,P", CASES, ids=[c[0] for c in CASES])
-def test_adjoint_step_parity(abd, ctx, name, S, P):
+def test_adjoint_step_parity(abd, ctx, name, S, P, solver, monkeypatch):
+    # (the adjoint solve is CG with MINRES where CG fails; ABD_ADJ_MINRES=1
+    # runs MINRES alone, so both solvers meet the oracle on every case)
+    if solver == "minres":
+        monkeypatch.setenv("ABD_ADJ_MINRES", "1")
+    else:
+        monkeypatch.delenv("ABD_ADJ_MINRES", raising=False)
     sc = abd.Scene(S)
     ctx.body_mass(sc)
     B = oracle.Body(S)

@@ -1464,11 +1464,6 @@ __global__ void __launch_bounds__(MR_T) k_mr_delta(const double *Az, const doubl
     st->delta = delta;
   }
 }
-__global__ void k_mr_v(int n, const double *Az, const double *v, const double *vp, const MrState *st, double *vn) {
-  if (st->done) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) vn[i] = st->inv_gam * Az[i] - st->va * v[i] - st->vb * vp[i];
-}
 // gamma_next from z_next . v_next, the Givens rotation, the w / x update
 // coefficients, the residual estimate and the stop test
 __global__ void __launch_bounds__(MR_T) k_mr_rot(const double *zn, const double *vn, int n, MrState *st) {
@@ -1514,6 +1509,39 @@ __global__ void __launch_bounds__(MR_T) k_mr_rot(const double *zn, const double 
   st->iters += 1;
   if (fabs(st->eta) <= st->rtol * st->g1 || gn == 0.0) st->done = 1;
 }
+// One launch for the element-wise work between the two reductions of an
+// iteration: the previous iteration's w / x update (its coefficients were
+// fixed by that iteration's k_mr_rot; skipped on the first iteration and
+// once stopped), then v_next = inv_gam A z - va v - vb v_prev and
+// z_next = P v_next.  A block covers whole bodies (MV_B of them), so P's
+// 12 x 12 block product reads v_next from LDS.
+constexpr int MV_B = 16;
+__global__ void __launch_bounds__(12 * MV_B) k_mr_vz(int nb, const double *Az, const double *v, const double *vp,
+                                                    const double *inv, MrState *st, double *vn, double *zn,
+                                                    int first, const double *z_prev, double *wp, const double *w,
+                                                    double *x) {
+  __shared__ double sv[12 * MV_B];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = 12 * nb;
+  if (!first && st->apply && t < n) {
+    const double wn = (st->wz * z_prev[t] - st->wa3 * wp[t] - st->wa2 * w[t]) / st->wa1;
+    wp[t] = wn;
+    x[t] += st->wcx * wn;
+  }
+  if (st->done) return;  // (uniform over the grid)
+  const double val = t < n ? st->inv_gam * Az[t] - st->va * v[t] - st->vb * vp[t] : 0.0;
+  if (t < n) vn[t] = val;
+  sv[threadIdx.x] = val;
+  __syncthreads();
+  if (t >= n) return;
+  const int lb = threadIdx.x / 12, i = threadIdx.x % 12;
+  const double *M = inv + 144 * (int64_t)(t / 12) + 12 * i;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) acc += M[j] * sv[12 * lb + j];
+  zn[t] = acc;
+}
+
 __global__ void k_mr_wx(int n, const double *z, double *wp, const double *w, const MrState *st, double *x) {
   if (!st->apply) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1606,28 +1634,41 @@ int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const doubl
   ABD_TRY(pinned_get(ctx, sizeof(MrState), reinterpret_cast<void **>(&hs)));
   *hs = h0;
   HIP_TRY(ctx, hipMemcpyAsync(st, hs, sizeof(MrState), hipMemcpyHostToDevice, s));
-  double *z2;
+  double *z2, *z3;
   ABD_TRY(ws(ctx, "mr_z2", n12, &z2, s));
+  ABD_TRY(ws(ctx, "mr_z3", n12, &z3, s));
   double *vp = v0, *vc = v1, *vn = v2, *wp = w0, *wc = w1, *zc = z, *zn = z2;
   constexpr int MR_BATCH = 16;
   int j = 0;
+  // per iteration: A z; delta; [previous w / x update, v_next, z_next];
+  // gamma_next and the rotation.  The w / x update of an iteration runs in
+  // the next iteration's element-wise launch (or after the loop), with the
+  // z of its own iteration (zp).
+  const unsigned gvz = grid_for(nb, MV_B);
+  double *zp = nullptr;
+  bool first = true;
   while (j < max_iter) {
     const int nbat = max_iter - j < MR_BATCH ? max_iter - j : MR_BATCH;
     for (int q = 0; q < nbat; ++q) {
       hipLaunchKernelGGL(k_bsr_spmv, dim3(gs), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2, lo_beg,
                          hi_beg, zc, 1.0, Az);
       hipLaunchKernelGGL(k_mr_delta, dim3(1), dim3(MR_T), 0, s, Az, zc, n12, st);
-      hipLaunchKernelGGL(k_mr_v, dim3(gv), dim3(256), 0, s, n12, Az, vc, vp, st, vn);
-      hipLaunchKernelGGL(k_block_apply, dim3(gv), dim3(256), 0, s, nb, inv, vn, zn);
+      hipLaunchKernelGGL(k_mr_vz, dim3(gvz), dim3(12 * MV_B), 0, s, nb, Az, vc, vp, inv, st, vn, zn, first ? 1 : 0,
+                         zp, wp, wc, x_out);
+      if (!first) std::swap(wp, wc);  // (the update wrote w_next over w_prev)
+      first = false;
       hipLaunchKernelGGL(k_mr_rot, dim3(1), dim3(MR_T), 0, s, zn, vn, n12, st);
-      hipLaunchKernelGGL(k_mr_wx, dim3(gv), dim3(256), 0, s, n12, zc, wp, wc, st, x_out);
       // rotate (data independent, so queued iterations agree with the device)
-      std::swap(wp, wc);
       double *t = vp;
       vp = vc;
       vc = vn;
       vn = t;
-      std::swap(zc, zn);
+      // z of this iteration, needed by its w / x update next time; its
+      // buffer is free again once that update has run
+      double *zold = zp;
+      zp = zc;
+      zc = zn;
+      zn = zold ? zold : z3;
     }
     j += nbat;
     HIP_TRY(ctx, hipGetLastError());
@@ -1637,6 +1678,9 @@ int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const doubl
     if (hs->err == 2) return abd_fail(ctx, ABD_E_PCG, "MINRES breakdown (singular system)");
     if (hs->done) break;
   }
+  // the last iteration's w / x update
+  if (!first) hipLaunchKernelGGL(k_mr_wx, dim3(gv), dim3(256), 0, s, n12, zp, wp, wc, st, x_out);
+  HIP_TRY(ctx, hipGetLastError());
   j = hs->iters;
   *iters = j;
   return abd_hip_check(ctx, hipGetLastError(), "minres");

@@ -41,11 +41,13 @@ import scenegen as sg  # noqa: E402
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, dense
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 
-# Algorithmic work per active pair of the barrier kernel (counted stage by
-# stage in the design doc): case classification and distance, barrier scalars,
-# case derivatives, the 78-entry local Hessian, the 9x9 translation
-# reduction, a textbook dense symmetric eigensolve with vectors (9 n^3,
-# n = 9), the PSD reconstruction and the map back to 12x12.
+# Algorithmic work per active pair of the barrier kernel, in FP64 operations
+# (each +, -, *, /, sqrt, log counted once): case classification and
+# distance ~60, barrier scalars ~25, case derivatives ~120, gradient 12, the
+# 78-entry local Hessian ~1,326, the edge-edge mollifier terms ~800, the
+# 9x9 translation reduction 1,224, a textbook dense symmetric eigensolve with
+# vectors (9 n^3 = 6,561 for n = 9), the PSD reconstruction 810 and the map
+# back to 12x12 2,106: 12,300 (point-triangle) to 13,200 (edge-edge).
 BARRIER_FLOP_PER_PAIR = 12700.0
 # Algorithmic bytes per CCD pair: pair ids, the 4 vertex ids and the 4
 # vertices' positions and displacements.
@@ -369,7 +371,7 @@ def run_adjoint(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "one GPU only: multi-GPU execution is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "batched":

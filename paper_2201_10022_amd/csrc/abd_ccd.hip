@@ -8,12 +8,13 @@
 // The number of advances per pair ranges from 1 (pairs far apart or
 // separating) to ~l_p / d0 (pairs sliding at a small distance), so a lane
 // per pair would leave most of a wave idle behind its slowest lane.  The
-// kernel is persistent instead: each lane runs a small state machine and,
-// whenever it finishes a pair, takes the next one from a global work
-// counter (one atomic per wave and refill), so a wave's lanes stay busy
-// until the queue is empty.  Every lane performs at most one distance
-// evaluation per loop trip; the sequence of operations per pair is the
-// same as the one-pair-per-lane form.
+// kernel is persistent instead: each lane runs a small state machine; its
+// first pair is its global thread index, and whenever it finishes a pair
+// it takes the next one beyond the grid from a global work counter (one
+// atomic per wave and refill, none when the grid covers every pair), so a
+// wave's lanes stay busy until the queue is empty.  Every lane performs at
+// most one distance evaluation per loop trip; the sequence of operations
+// per pair is the same as the one-pair-per-lane form.
 #include "abd_internal.h"
 
 namespace {
@@ -41,7 +42,11 @@ __global__ void __launch_bounds__(CCD_BLOCK) k_accd(int64_t n_pt, int64_t n, con
                                                     double *t_ee, double *alpha) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
-  int64_t cur = -1;   // pair index, -1 = needs work, >= n = queue exhausted
+  // the first pair of every lane is its global thread index (no atomic);
+  // lanes that finish take the next pairs beyond the grid from the counter
+  const int64_t nlanes = (int64_t)gridDim.x * blockDim.x;
+  int64_t cur = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // pair index, >= n = queue exhausted
+  bool fresh = true;  // cur assigned, its state not loaded yet
   int phase = 0;      // 0: distance at start pending, 1: advancing
   int is_ee = 0, it = 0, scene = 0;
   // running minimum of this lane's finished pairs, per sub-scene (pairs come
@@ -60,7 +65,13 @@ __global__ void __launch_bounds__(CCD_BLOCK) k_accd(int64_t n_pt, int64_t n, con
       if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(need));
       base = __shfl(base, leader, 64);
       if (cur < 0) {
-        cur = (int64_t)(base + __popcll(need & ((1ull << lane) - 1ull)));
+        cur = nlanes + (int64_t)(base + __popcll(need & ((1ull << lane) - 1ull)));
+        fresh = true;
+      }
+    }
+    if (fresh) {
+      fresh = false;
+      {
         if (cur >= n) {
           cur = n;
         } else {
@@ -160,7 +171,7 @@ __global__ void __launch_bounds__(CCD_BLOCK) k_accd(int64_t n_pt, int64_t n, con
         }
         mval = fmin(mval, result);
       }
-      cur = -1;
+      cur = nlanes >= n ? n : -1;  // (every pair had a lane: nothing to take)
     }
   }
 }

@@ -28,7 +28,10 @@ __device__ __forceinline__ double pair_distance(int is_ee, const d3 X[4]) {
 }
 
 __device__ __forceinline__ void atomic_min_nonneg(double *addr, double v) {
-  // non-negative IEEE doubles order like their bit patterns
+  // non-negative IEEE doubles order like their bit patterns; a value not
+  // below the one already there (read without the atomic: it only ever
+  // decreases) would change nothing, so it skips the contended atomic
+  if (!(v < *reinterpret_cast<volatile double *>(addr))) return;
   atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 

@@ -211,12 +211,11 @@ __global__ void k_list_caps(int64_t n_cap, const int64_t *nbp_dev, const int32_t
            (toff[a + 1] - toff[a]) + (eoff[a + 1] - eoff[a]) + (eoff[b + 1] - eoff[b]);
 }
 
-__global__ void __launch_bounds__(256) k_cull_lists(const int32_t *bpairs, const int64_t *region,
+__global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const int64_t *region,
                                                     const int32_t *voff, const int32_t *toff, const int32_t *eoff,
                                                     const double *bb, const float *vbox, const float *tbox,
                                                     const float *ebox, int32_t *lists, int64_t *list_start,
                                                     int32_t *list_len) {
-  __shared__ int wcnt[4];
   const int64_t p = blockIdx.x;
   const int kind = blockIdx.y;
   const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
@@ -237,19 +236,16 @@ __global__ void __launch_bounds__(256) k_cull_lists(const int32_t *bpairs, const
   double ob[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) ob[i] = bb[6 * (int64_t)oth + i];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // one wave: chunks of 64 primitives, compacted with a ballot (no block
+  // barrier); the list keeps the primitives in index order
+  const int lane = threadIdx.x;
   int total = 0;
-  for (int c0 = offs[own]; c0 < offs[own + 1]; c0 += 256) {
-    const int i = c0 + (int)threadIdx.x;
+  for (int c0 = offs[own]; c0 < offs[own + 1]; c0 += 64) {
+    const int i = c0 + lane;
     const bool ok = i < offs[own + 1] && box_overlap32(boxes + 6 * (int64_t)i, ob);
     const unsigned long long m = __ballot(ok);
-    if (lane == 0) wcnt[wid] = __popcll(m);
-    __syncthreads();
-    int before = 0;
-    for (int w = 0; w < wid; ++w) before += wcnt[w];
-    if (ok) lists[start + total + before + __popcll(m & ((1ull << lane) - 1ull))] = i;
-    total += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    __syncthreads();
+    if (ok) lists[start + total + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    total += __popcll(m);
   }
   if (threadIdx.x == 0) {
     list_start[6 * p + kind] = start;
@@ -478,7 +474,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_lists", list_total + 1, &lists, s));
   ABD_TRY(ws(ctx, "bp_llen", 6 * nbp, &llen, s));
   ABD_TRY(ws(ctx, "bp_lstart", 6 * nbp, &lstart, s));
-  hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 6), dim3(256), 0, s, bpairs, region, sc->body_vert_off,
+  hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 6), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
                      sc->body_tri_off, sc->body_edge_off, bbox, vbox32, tbox32, ebox32, lists, lstart, llen);
 
   // tiles: the count pass is sized like the body pairs (one

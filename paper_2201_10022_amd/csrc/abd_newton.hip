@@ -6,6 +6,8 @@
 #include <chrono>
 #include <cmath>
 
+#include <cstring>
+
 #include "abd_internal.h"
 
 namespace {
@@ -126,6 +128,11 @@ __global__ void k_axpy_trials(int nb, int S, const int32_t *body_scene, const do
   const int t = blockIdx.y;
   out[(int64_t)t * 12 * nb + i] = a[i] + alpha[(int64_t)t * S + body_scene[i / 12]] * b[i];
 }
+// (one scene, one step length passed by value)
+__global__ void k_axpy1(int n, const double *a, double alpha, const double *b, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + alpha * b[i];
+}
 
 // step lengths of the first line-search batch: row 0 is 0 (E(q) itself),
 // row t >= 1 is alpha_ccd 2^-(t-1) (0 for scenes already done)
@@ -179,8 +186,10 @@ constexpr int LS_BATCH = 4;  // trial step lengths evaluated per line-search bat
 // (device [S], in/out).  Sub-scenes are independent problems: each has its
 // own convergence test, CCD bound and line search (its own step length),
 // and its own PCG scalars; a scene marked done keeps its q.
+// done_mode: 0 read the done flags from done_dev, 1 they are all zero, 2 the
+// staging area still holds them (the last call on this context wrote them)
 int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, const double *qt,
-                     uint8_t *done_dev, abd_stats *st, hipStream_t s, bool reuse_sweep) {
+                     uint8_t *done_dev, abd_stats *st, hipStream_t s, bool reuse_sweep, int done_mode) {
   auto t_all = std::chrono::steady_clock::now();
   const int nb = sc->n_bodies, nv = sc->n_verts;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
@@ -209,7 +218,10 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   double *d_disp = hd + 8, *d_alpha = d_disp + S, *d_e0 = d_alpha + S;
   double *h_atr = h_e1 + (size_t)LS_BATCH * S;                                          // [LS_BATCH][S]
   uint8_t *h_done = reinterpret_cast<uint8_t *>(h_atr + (size_t)LS_BATCH * S);
-  HIP_TRY(ctx, hipMemcpyAsync(h_done, done_dev, S, hipMemcpyDeviceToHost, s));
+  if (done_mode == 0)
+    HIP_TRY(ctx, hipMemcpyAsync(h_done, done_dev, S, hipMemcpyDeviceToHost, s));
+  else if (done_mode == 1)
+    std::memset(h_done, 0, S);
 
   // lagged friction of the current time step, if any
   FrictionSet frs;
@@ -283,7 +295,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     }
   }
   st->disp = dmax;
-  HIP_TRY(ctx, hipMemcpyAsync(done_dev, h_done, S, hipMemcpyHostToDevice, s));
+  if (st->newly_converged > 0) HIP_TRY(ctx, hipMemcpyAsync(done_dev, h_done, S, hipMemcpyHostToDevice, s));
   if (n_active == 0) {
     st->converged = 1;
     st->alpha = 0.0;
@@ -368,10 +380,14 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   }
   if (!all_acc) return abd_fail(ctx, ABD_E_LINESEARCH, "line search found no decrease");
   // the accepted point of every scene
-  HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_alpha, S * sizeof(double), hipMemcpyHostToDevice, s));
   // (in place: each element reads q[i] before writing it)
-  hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), 1), dim3(256), 0, s, nb, S, sc->body_scene, q, alpha_dev, p,
-                     q);
+  if (S == 1) {
+    hipLaunchKernelGGL(k_axpy1, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, q, h_alpha[0], p, q);
+  } else {
+    HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_alpha, S * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), 1), dim3(256), 0, s, nb, S, sc->body_scene, q,
+                       alpha_dev, p, q);
+  }
   double e0 = 0.0, e1 = 0.0, amin_acc = 1.0;
   for (int j = 0; j < S; ++j) {
     if (h_done[j]) continue;
@@ -408,7 +424,7 @@ extern "C" int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_para
     ABD_TRY(ws(ctx, "ns_done", S, &done, stream));
     HIP_TRY(ctx, hipMemsetAsync(done, 0, S, stream));
   }
-  ABD_TRY(newton_iteration(ctx, sc, prm, q, q_tilde, done, st, stream, false));
+  ABD_TRY(newton_iteration(ctx, sc, prm, q, q_tilde, done, st, stream, false, scene_done ? 0 : 1));
   st->newton_iters = 1;
   return ABD_OK;
 }
@@ -441,7 +457,7 @@ extern "C" int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params
   bool conv = false;
   for (; it < prm->max_newton; ++it) {
     abd_stats st = {};
-    ABD_TRY(newton_iteration(ctx, sc, prm, q, qt, done, &st, stream, it > 0));
+    ABD_TRY(newton_iteration(ctx, sc, prm, q, qt, done, &st, stream, it > 0, it > 0 ? 2 : 1));
     // every scene still iterating ran this iteration
     total.scene_newton_iters += n_left;
     n_left -= st.newly_converged;

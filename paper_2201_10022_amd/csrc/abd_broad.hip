@@ -211,64 +211,63 @@ __global__ void k_list_caps(int64_t n_cap, const int64_t *nbp_dev, const int32_t
            (toff[a + 1] - toff[a]) + (eoff[a + 1] - eoff[a]) + (eoff[b + 1] - eoff[b]);
 }
 
+constexpr int TROWS = 16;
+
+// One wave per body pair p and sub-problem sub (0: a's vertices x b's
+// triangles, 1: b's vertices x a's triangles, 2: a's edges x b's edges):
+// the two lists of primitives inside the other body's box (kinds 2 sub and
+// 2 sub + 1), each in index order by ballot compaction in chunks of 64,
+// then the sub-problem's tile count (TROWS rows x all columns per tile).
 __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const int64_t *region,
                                                     const int32_t *voff, const int32_t *toff, const int32_t *eoff,
                                                     const double *bb, const float *vbox, const float *tbox,
                                                     const float *ebox, int32_t *lists, int64_t *list_start,
-                                                    int32_t *list_len) {
+                                                    int32_t *list_len, int64_t *tiles_pt, int64_t *tiles_ee) {
   const int64_t p = blockIdx.x;
-  const int kind = blockIdx.y;
+  const int sub = blockIdx.y;
   const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
-  // (body owning the primitives, body whose box culls them)
-  const int own = (kind == 0 || kind == 3 || kind == 4) ? a : b;
-  const int oth = own == a ? b : a;
-  const int32_t *offs = (kind == 0 || kind == 2) ? voff : (kind == 1 || kind == 3) ? toff : eoff;
-  const float *boxes = (kind == 0 || kind == 2) ? vbox : (kind == 1 || kind == 3) ? tbox : ebox;
-  // start of this list inside the body pair's region
-  int64_t start = region[p];
-  {
-    const int la = voff[a + 1] - voff[a], lb = voff[b + 1] - voff[b];
-    const int ta = toff[a + 1] - toff[a], tb = toff[b + 1] - toff[b];
-    const int ea = eoff[a + 1] - eoff[a];
-    const int caps[6] = {la, tb, lb, ta, ea, 0};
-    for (int k = 0; k < kind; ++k) start += caps[k];
-  }
-  double ob[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) ob[i] = bb[6 * (int64_t)oth + i];
-  // one wave: chunks of 64 primitives, compacted with a ballot (no block
-  // barrier); the list keeps the primitives in index order
+  const int la = voff[a + 1] - voff[a], lb = voff[b + 1] - voff[b];
+  const int ta = toff[a + 1] - toff[a], tb = toff[b + 1] - toff[b];
+  const int ea = eoff[a + 1] - eoff[a];
+  const int caps[6] = {la, tb, lb, ta, ea, 0};
   const int lane = threadIdx.x;
-  int total = 0;
-  for (int c0 = offs[own]; c0 < offs[own + 1]; c0 += 64) {
-    const int i = c0 + lane;
-    const bool ok = i < offs[own + 1] && box_overlap32(boxes + 6 * (int64_t)i, ob);
-    const unsigned long long m = __ballot(ok);
-    if (ok) lists[start + total + __popcll(m & ((1ull << lane) - 1ull))] = i;
-    total += __popcll(m);
+  int len[2];
+  for (int h = 0; h < 2; ++h) {
+    const int kind = 2 * sub + h;
+    // (body owning the primitives, body whose box culls them)
+    const int own = (kind == 0 || kind == 3 || kind == 4) ? a : b;
+    const int oth = own == a ? b : a;
+    const int32_t *offs = (kind == 0 || kind == 2) ? voff : (kind == 1 || kind == 3) ? toff : eoff;
+    const float *boxes = (kind == 0 || kind == 2) ? vbox : (kind == 1 || kind == 3) ? tbox : ebox;
+    // start of this list inside the body pair's region
+    int64_t start = region[p];
+    for (int k = 0; k < kind; ++k) start += caps[k];
+    double ob[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ob[i] = bb[6 * (int64_t)oth + i];
+    int total = 0;
+    for (int c0 = offs[own]; c0 < offs[own + 1]; c0 += 64) {
+      const int i = c0 + lane;
+      const bool ok = i < offs[own + 1] && box_overlap32(boxes + 6 * (int64_t)i, ob);
+      const unsigned long long m = __ballot(ok);
+      if (ok) lists[start + total + __popcll(m & ((1ull << lane) - 1ull))] = i;
+      total += __popcll(m);
+    }
+    if (lane == 0) {
+      list_start[6 * p + kind] = start;
+      list_len[6 * p + kind] = total;
+    }
+    len[h] = total;
   }
-  if (threadIdx.x == 0) {
-    list_start[6 * p + kind] = start;
-    list_len[6 * p + kind] = total;
-  }
-}
-
-constexpr int TROWS = 16;
-
-// tiles per sub-problem: sub 3p+0: rows list 0 x cols list 1 (PT),
-// 3p+1: list 2 x list 3 (PT), 3p+2: list 4 x list 5 (EE)
-__global__ void k_sub_tiles(int64_t nbp, const int32_t *list_len, int64_t *tiles_pt, int64_t *tiles_ee) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nbp) return;
-  for (int s = 0; s < 3; ++s) {
-    const int nr = list_len[6 * p + 2 * s], nc = list_len[6 * p + 2 * s + 1];
-    const int64_t t = nc > 0 ? (nr + TROWS - 1) / TROWS : 0;
-    if (s < 2)
-      tiles_pt[2 * p + s] = t;
+  if (lane == 0) {
+    const int64_t t = len[1] > 0 ? (len[0] + TROWS - 1) / TROWS : 0;
+    if (sub < 2)
+      tiles_pt[2 * p + sub] = t;
     else
       tiles_ee[p] = t;
   }
 }
+
 
 // (sub-problem, tile index within it) of every tile.  The 3 nbp
 // sub-problems' tile counts are scanned as one array: PT sub-problems
@@ -474,8 +473,6 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_lists", list_total + 1, &lists, s));
   ABD_TRY(ws(ctx, "bp_llen", 6 * nbp, &llen, s));
   ABD_TRY(ws(ctx, "bp_lstart", 6 * nbp, &lstart, s));
-  hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 6), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
-                     sc->body_tri_off, sc->body_edge_off, bbox, vbox32, tbox32, ebox32, lists, lstart, llen);
 
   // tiles: the count pass is sized like the body pairs (one
   // synchronisation reads the tile and pair totals).  Tile counts per
@@ -483,7 +480,9 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   int64_t *tcnt, *toff, *ttot = btot + 2, *otot = btot + 4;
   ABD_TRY(ws(ctx, "bp_tcnt", 3 * nbp, &tcnt, s));
   ABD_TRY(ws(ctx, "bp_toff", 3 * nbp + 1, &toff, s));
-  hipLaunchKernelGGL(k_sub_tiles, dim3(grid_for(nbp, 256)), dim3(256), 0, s, nbp, llen, tcnt, tcnt + 2 * nbp);
+  hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 3), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
+                     sc->body_tri_off, sc->body_edge_off, bbox, vbox32, tbox32, ebox32, lists, lstart, llen, tcnt,
+                     tcnt + 2 * nbp);
   // hbuf[2] = all tiles, hbuf[3] = PT tiles
   ABD_TRY(scan_exclusive_i64(ctx, tcnt, toff, 3 * nbp, ttot, s, hbuf_d + 2, 2 * nbp));
   const std::string key_tp = std::string(tag) + "_tpt", key_te = std::string(tag) + "_tee";

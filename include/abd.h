@@ -194,7 +194,8 @@ int abd_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm,
 /* CCD step bound (sec. 4.1: linear trajectories x0 + t dx, additive CCD):
  * per pair a conservative safe fraction t in [0, ccd_tmax] (t_pt [n_pt],
  * t_ee [n_ee], either may be NULL) and alpha [n_scenes] = min(1, min t)
- * over each sub-scene's pairs. */
+ * over each sub-scene's pairs.  (Environment ABD_CCD_MAX_BLOCKS caps the
+ * kernel's grid; the results do not depend on it.) */
 int abd_ccd_max_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x0, const double *dx,
                      const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *t_pt, double *t_ee,
                      double *alpha, hipStream_t stream);

@@ -190,10 +190,12 @@ class Context:
                                               pt.shape[0], _ptr(ee), ee.shape[0], _ptr(energy), _stream()))
         return energy
 
-    def ccd_max_step(self, scene, params, x0, dx, pt, ee):
+    def ccd_max_step(self, scene, params, x0, dx, pt, ee, per_pair=True):
+        """(t_pt, t_ee, alpha); per_pair=False asks for the bound alone
+        (t_pt, t_ee are then None)."""
         dev = x0.device
-        t_pt = torch.zeros(pt.shape[0], dtype=torch.float64, device=dev)
-        t_ee = torch.zeros(ee.shape[0], dtype=torch.float64, device=dev)
+        t_pt = torch.zeros(pt.shape[0], dtype=torch.float64, device=dev) if per_pair else None
+        t_ee = torch.zeros(ee.shape[0], dtype=torch.float64, device=dev) if per_pair else None
         alpha = torch.zeros(max(scene.n_scenes, 1), dtype=torch.float64, device=dev)
         prm = make_params(params)
         self._check(self.L.abd_ccd_max_step(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(x0), _ptr(dx),

@@ -15,6 +15,8 @@
 // wave's lanes stay busy until the queue is empty.  Every lane performs at
 // most one distance evaluation per loop trip; the sequence of operations
 // per pair is the same as the one-pair-per-lane form.
+#include <cstdlib>
+
 #include "abd_internal.h"
 
 namespace {
@@ -199,6 +201,12 @@ int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const doubl
     // persistent grid: enough waves to fill the chip, never more than the work
     int64_t blocks = (n + CCD_BLOCK - 1) / CCD_BLOCK;
     if (blocks > 1024) blocks = 1024;
+    // (environment ABD_CCD_MAX_BLOCKS: a smaller grid, so that tests reach
+    // the work counter with few pairs)
+    if (const char *mb = getenv("ABD_CCD_MAX_BLOCKS")) {
+      const long cap = atol(mb);
+      if (cap >= 1 && blocks > cap) blocks = cap;
+    }
     hipEvent_t pe = prof_begin(ctx, s);
     hipLaunchKernelGGL(k_accd, dim3((unsigned)blocks), dim3(CCD_BLOCK), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges,
                        sc->vert_body, sc->body_scene, x0, dx, prm->ccd_s, prm->ccd_tmax, prm->ccd_max_iter, counter,

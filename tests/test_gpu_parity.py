@@ -349,6 +349,37 @@ def test_ccd_window(abd, ctx, name, S, P):
     assert oalpha * 0.99 <= alpha.item() <= oalpha * (1 + 1e-9)
 
 
+def test_ccd_grid_queue_and_bound_only_agree(abd, ctx, monkeypatch):
+    # the CCD kernel gives each lane its first pair by thread index and the
+    # pairs beyond the grid through a work counter; a grid of one block (256
+    # lanes) sends almost every pair through the counter.  Per-pair times
+    # and the bound are bit-identical either way, and the bound alone (no
+    # per-pair output) equals the bound with it.
+    S, P = sg.icosphere_box(n_side=3, n_layers=2)
+    sc = abd.Scene(S)
+    q0 = S["q0"].copy()
+    q1 = q0.copy()
+    q1[1:, 1] -= 0.4  # (through the lower layer and the floor: a bound below 1)
+    q1[1:, 0] += 0.004
+    x0, x1 = oracle.vertex_map(S, q0), oracle.vertex_map(S, q1)
+    pt, ee = oracle.candidates(S, x0, x1, P["dhat"])
+    assert len(pt) + len(ee) > 4 * 256
+    args = (sc, P, _dev(x0), _dev(x1 - x0), _dev(pt, torch.int32), _dev(ee, torch.int32))
+    monkeypatch.delenv("ABD_CCD_MAX_BLOCKS", raising=False)
+    tp, te, a = ctx.ccd_max_step(*args)
+    _, _, a_only = ctx.ccd_max_step(*args, per_pair=False)
+    monkeypatch.setenv("ABD_CCD_MAX_BLOCKS", "1")
+    tp1, te1, a1 = ctx.ccd_max_step(*args)
+    _, _, a1_only = ctx.ccd_max_step(*args, per_pair=False)
+    monkeypatch.delenv("ABD_CCD_MAX_BLOCKS", raising=False)
+    np.testing.assert_array_equal(tp.cpu().numpy(), tp1.cpu().numpy())
+    np.testing.assert_array_equal(te.cpu().numpy(), te1.cpu().numpy())
+    assert a.item() == a1.item() == a_only.item() == a1_only.item()
+    otp, ote, oalpha = oracle.ccd(S, x0, x1 - x0, pt, ee, P)
+    assert oalpha < 1.0
+    assert oalpha * 0.99 <= a.item() <= oalpha * (1 + 1e-9)
+
+
 # --------------------------------------------------- a8 body terms ----
 
 def test_orthogonality_inertia_parity(abd, ctx):

@@ -277,6 +277,9 @@ __device__ __forceinline__ bool ortho_project_closed(const double *A, double s, 
 
 // inertia + weighted orthogonality per body: energies to e_out[b], gradient
 // and diagonal blocks accumulated (thread per body)
+// DERIV = 0: energies only (the derivative code compiled out, so the
+// energy-only launches of the line search do not carry its registers)
+template <int DERIV>
 __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed, const double *mass,
                                                   const double *volume, const double *q, const double *qt,
                                                   double kappa_o, double w, int do_inertia, int do_ortho,
@@ -303,10 +306,10 @@ __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed,
 #pragma unroll
     for (int i = 0; i < 12; ++i) s += dq[i] * Mq[i];
     e += 0.5 * s;
-    if (want_grad)
+    if (DERIV && want_grad)
 #pragma unroll
       for (int i = 0; i < 12; ++i) grad[12 * (int64_t)b + i] += Mq[i];
-    if (diag) {
+    if (DERIV && diag) {
       const double *mb = mass + 10 * (int64_t)b;
       double *D = diag + 144 * (int64_t)b;
       const double S[3][3] = {{mb[4], mb[5], mb[6]}, {mb[5], mb[7], mb[8]}, {mb[6], mb[8], mb[9]}};
@@ -325,12 +328,12 @@ __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed,
   }
   if (do_ortho) {
     Ortho o;
-    ortho_eval(qb + 3, kappa_o * volume[b], w, o, diag != nullptr);
+    ortho_eval(qb + 3, kappa_o * volume[b], w, o, DERIV && diag != nullptr);
     e += o.e;
-    if (want_grad)
+    if (DERIV && want_grad)
 #pragma unroll
       for (int i = 0; i < 9; ++i) grad[12 * (int64_t)b + 3 + i] += o.g[i];
-    if (diag) {
+    if (DERIV && diag) {
       if (project && !ortho_project_closed(qb + 3, 4.0 * w * kappa_o * volume[b], o.H)) psd_project_packed<9>(o.H);
       using S = SymIdx<9>;
       double *D = diag + 144 * (int64_t)b;
@@ -399,9 +402,14 @@ static int body_terms(abd_ctx *ctx, const abd_scene *sc, const double *q, const 
   if (!sc->volume && do_ortho) return abd_fail(ctx, ABD_E_INVALID, "scene volume is NULL");
   double *eb;
   ABD_TRY(ws(ctx, "body_e", sc->n_bodies, &eb, s));
-  hipLaunchKernelGGL(k_body_terms, dim3(grid_for(sc->n_bodies, 64)), dim3(64), 0, s, sc->n_bodies, sc->body_fixed,
-                     sc->mass, sc->volume, q, qt, kappa_o, w, do_inertia, do_ortho, project, grad != nullptr ? 1 : 0,
-                     eb, grad, diag);
+  if (grad || diag)
+    hipLaunchKernelGGL(k_body_terms<1>, dim3(grid_for(sc->n_bodies, 64)), dim3(64), 0, s, sc->n_bodies,
+                       sc->body_fixed, sc->mass, sc->volume, q, qt, kappa_o, w, do_inertia, do_ortho, project,
+                       grad != nullptr ? 1 : 0, eb, grad, diag, (int64_t)0);
+  else
+    hipLaunchKernelGGL(k_body_terms<0>, dim3(grid_for(sc->n_bodies, 64)), dim3(64), 0, s, sc->n_bodies,
+                       sc->body_fixed, sc->mass, sc->volume, q, qt, kappa_o, w, do_inertia, do_ortho, project, 0, eb,
+                       nullptr, nullptr, (int64_t)0);
   HIP_TRY(ctx, hipGetLastError());
   if (energy) ABD_TRY(reduce_sum_f64(ctx, eb, sc->n_bodies, energy, s));
   return ABD_OK;
@@ -434,9 +442,9 @@ int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
   if (!sc->mass || !sc->volume) return abd_fail(ctx, ABD_E_INVALID, "scene mass or volume is NULL");
   double *eb = items;
   if (!eb) ABD_TRY(ws(ctx, "body_e_tr", (size_t)nb * n_trials, &eb, s));
-  hipLaunchKernelGGL(k_body_terms, dim3(grid_for(nb, 64), n_trials), dim3(64), 0, s, nb, sc->body_fixed, sc->mass,
+  hipLaunchKernelGGL(k_body_terms<0>, dim3(grid_for(nb, 64), n_trials), dim3(64), 0, s, nb, sc->body_fixed, sc->mass,
                      sc->volume, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, 0, eb, nullptr, nullptr,
-                     items ? estride : 0);
+                     items ? estride : (int64_t)0);
   HIP_TRY(ctx, hipGetLastError());
   if (items) return ABD_OK;
   return seg_sum_trials(ctx, eb, nb, nb, sc->body_scene, n_trials, S, energy, s);

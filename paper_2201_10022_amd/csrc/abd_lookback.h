@@ -23,19 +23,21 @@ __device__ __forceinline__ int64_t lb_wave_sum(int64_t v) {
   return v;
 }
 
-// next tile of this launch (one thread)
+// next tile of this launch (one thread).  The counter word carries the tag
+// where a status word does (bits 44 and up), so a word left by any earlier
+// launch, counter or status, reads as another launch's and is restarted.
 __device__ __forceinline__ unsigned int lb_claim(unsigned long long *counter, unsigned int tag, int *err) {
   const unsigned long long T = tag;
   for (int spin = 0;; ++spin) {
     const unsigned long long v = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((v >> 32) != T) {
-      if (atomicCAS(counter, v, (T << 32) | 1ull) == v) return 0;
+    if ((v >> 44) != T) {
+      if (atomicCAS(counter, v, (T << 44) | 1ull) == v) return 0;
       if (spin > LB_SPIN_CAP) {  // (cannot happen: some CAS succeeds)
         atomicOr(err, 16);
         return 0;
       }
     } else {
-      return (unsigned int)(atomicAdd(counter, 1ull) & 0xffffffffull);
+      return (unsigned int)(atomicAdd(counter, 1ull) & ((1ull << 44) - 1ull));
     }
   }
 }

@@ -128,6 +128,39 @@ __global__ void k_axpy_trials(int nb, int S, const int32_t *body_scene, const do
   const int t = blockIdx.y;
   out[(int64_t)t * 12 * nb + i] = a[i] + alpha[(int64_t)t * S + body_scene[i / 12]] * b[i];
 }
+// The trial states of a line-search batch in one launch (trial in grid.y):
+// blocks [0, nqb) form q_t = q + alpha_t p per entry, as k_axpy_trials does
+// (one fused multiply-add); the others map the vertices, x_t = x(q_t), with
+// the same arithmetic as the vertex map and q_t formed in place by that
+// same fused multiply-add, so they need not wait for the first part.
+__global__ void __launch_bounds__(256) k_trial_states(int nb, int S, const int32_t *body_scene, const double *q,
+                                                      const double *alpha, const double *p, double *qn, int nv,
+                                                      const double *xbar, const int32_t *vert_body, double *xn,
+                                                      int nqb) {
+#pragma clang fp contract(off)
+  const int t = blockIdx.y;
+  if ((int)blockIdx.x < nqb) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= 12 * nb) return;
+    qn[(int64_t)t * 12 * nb + i] = fma(alpha[(int64_t)t * S + body_scene[i / 12]], p[i], q[i]);
+    return;
+  }
+  const int k = ((int)blockIdx.x - nqb) * 256 + threadIdx.x;
+  if (k >= nv) return;
+  const int64_t b = vert_body[k];
+  const double al = alpha[(int64_t)t * S + body_scene[b]];
+  double qb[12];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) qb[j] = fma(al, p[12 * b + j], q[12 * b + j]);
+  const double xb0 = xbar[3 * k], xb1 = xbar[3 * k + 1], xb2 = xbar[3 * k + 2];
+  double *x = xn + (int64_t)t * 3 * nv;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double *a = qb + 3 + 3 * i;
+    x[3 * k + i] = qb[i] + ((a[0] * xb0 + a[1] * xb1) + a[2] * xb2);
+  }
+}
+
 // (one scene, one step length passed by value)
 __global__ void k_axpy1(int n, const double *a, double alpha, const double *b, double *out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,9 +190,12 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
   ABD_TRY(ws(ctx, "ls_x", (size_t)n * 3 * sc->n_verts, &xn, s));
   // (one scene with items: the row sums below are assigned, not added)
   if (S > 1 || (int64_t)nb + npt + nee + (fr ? fr->n() : 0) == 0) ABD_TRY(zero(ctx, e_dev, (int64_t)n * S, s));
-  hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), n), dim3(256), 0, s, nb, S, sc->body_scene, q, alpha, p,
-                     qn);
-  ABD_TRY(op_vertex_map_trials(ctx, sc, qn, n, xn, s));
+  {
+    const int nqb = (int)grid_for(n12, 256);
+    hipLaunchKernelGGL(k_trial_states, dim3(nqb + grid_for(sc->n_verts, 256), n), dim3(256), 0, s, nb, S,
+                       sc->body_scene, q, alpha, p, qn, sc->n_verts, sc->xbar, sc->vert_body, xn, nqb);
+    HIP_TRY(ctx, hipGetLastError());
+  }
   if (S > 1) {
     ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, e_dev, s));
     ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, xn, n, pt, npt, ee, nee, e_dev, s));

@@ -71,3 +71,21 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_binding_signatures_match_the_header_arity():
+    """Every binding signature takes as many arguments as the header's
+    prototype, and pointer arguments are bound as pointers."""
+    from paper_2201_10022_amd import _lib
+    txt = open(os.path.join(ROOT, "include", "abd.h")).read()
+    protos = re.findall(r"^\s*(?:int|const char \*)\s*(abd_\w+)\s*\(([^;]*)\)\s*;", txt, re.M)
+    assert protos
+    for name, args in protos:
+        params = [a.strip() for a in args.replace("\n", " ").split(",") if a.strip()]
+        if params == ["void"]:
+            params = []
+        argtypes = _lib.SIGNATURES[name][0]
+        assert len(argtypes) == len(params), (name, params)
+        for p, t in zip(params, argtypes):
+            is_ptr = issubclass(t, (ctypes._Pointer, ctypes.c_void_p, ctypes.c_char_p))
+            assert is_ptr == ("*" in p or "hipStream_t" in p), (name, p, t)

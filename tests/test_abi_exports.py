@@ -75,11 +75,13 @@ def test_binding_structs_match_the_header_layout(tmp_path):
 
 def test_binding_signatures_match_the_header_arity():
     """Every binding signature takes as many arguments as the header's
-    prototype, and pointer arguments are bound as pointers."""
+    prototype, pointer arguments are bound as pointers and scalar arguments
+    with the header's width and kind."""
     from paper_2201_10022_amd import _lib
     txt = open(os.path.join(ROOT, "include", "abd.h")).read()
     protos = re.findall(r"^\s*(?:int|const char \*)\s*(abd_\w+)\s*\(([^;]*)\)\s*;", txt, re.M)
     assert protos
+    scalar = {"int": ctypes.c_int, "int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
     for name, args in protos:
         params = [a.strip() for a in args.replace("\n", " ").split(",") if a.strip()]
         if params == ["void"]:
@@ -89,3 +91,7 @@ def test_binding_signatures_match_the_header_arity():
         for p, t in zip(params, argtypes):
             is_ptr = issubclass(t, (ctypes._Pointer, ctypes.c_void_p, ctypes.c_char_p))
             assert is_ptr == ("*" in p or "hipStream_t" in p), (name, p, t)
+            if not is_ptr:
+                ctype = " ".join(p.split()[:-1])
+                assert ctypes.sizeof(t) == ctypes.sizeof(scalar[ctype]), (name, p, t)
+                assert (t is ctypes.c_double) == (ctype == "double"), (name, p, t)

@@ -607,6 +607,9 @@ extern "C" int abd_create(abd_ctx **out, int device) {
   c->device = device;
   for (auto &e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      for (auto &d : c->ev)
+        if (d) hipEventDestroy(d);
       delete c;
       return ABD_E_HIP;
     }

@@ -45,7 +45,11 @@ int ws_get(abd_ctx *ctx, const char *name, size_t bytes, void **out, hipStream_t
 
 int pinned_get(abd_ctx *ctx, size_t bytes, void **out) {
   if (ctx->pinned_bytes < bytes) {
-    if (ctx->pinned) HIP_TRY(ctx, hipHostFree(ctx->pinned));
+    // growing waits for any queued copy into the old area
+    if (ctx->pinned) {
+      HIP_TRY(ctx, hipDeviceSynchronize());
+      HIP_TRY(ctx, hipHostFree(ctx->pinned));
+    }
     ctx->pinned = nullptr;
     size_t nb = bytes < 4096 ? 4096 : bytes;
     HIP_TRY(ctx, hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault));
@@ -77,7 +81,11 @@ int mirror_get(abd_ctx *ctx, int64_t **host, int64_t **dev) {
   if (!ctx->mirror_h) {
     void *h = nullptr, *d = nullptr;
     HIP_TRY(ctx, hipHostMalloc(&h, MIRROR_SLOTS * sizeof(int64_t), hipHostMallocMapped | hipHostMallocCoherent));
-    HIP_TRY(ctx, hipHostGetDevicePointer(&d, h, 0));
+    const hipError_t e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess) {
+      hipHostFree(h);
+      return abd_hip_check(ctx, e, "hipHostGetDevicePointer");
+    }
     ctx->mirror_h = static_cast<int64_t *>(h);
     ctx->mirror_d = static_cast<int64_t *>(d);
   }

@@ -46,6 +46,34 @@ def test_mass_right_tetrahedron_textbook():
     np.testing.assert_allclose(mass[0, [5, 6, 8]], 1 / 120, rtol=1e-14)
 
 
+def test_mass_general_tetrahedra_by_affine_map_of_the_simplex():
+    # any tetrahedron is b + A u over the unit simplex, so with
+    # m1 = int u = 1/24 (1,1,1) and M2 = int u u^T = (I + 1 1^T) / 120:
+    # vol = |det A| / 6, h = |det A| (A m1 + b / 6),
+    # S = |det A| (A M2 A^T + A m1 b^T + b m1^T A^T + b b^T / 6)
+    rng = np.random.default_rng(77)
+    m1 = np.full(3, 1 / 24)
+    M2 = (np.eye(3) + np.ones((3, 3))) / 120
+    for _ in range(5):
+        v = rng.normal(size=(4, 3))
+        A, b = (v[1:] - v[0]).T, v[0]
+        det = np.linalg.det(A)
+        t = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], np.int32)
+        if det < 0:
+            t = t[:, ::-1].copy()
+        rho = 3.0
+        S = _single_body(v, t, density=rho)
+        mass, vol = oracle.mass_properties(S)
+        ad = abs(det)
+        h = ad * (A @ m1 + b / 6)
+        Sm = ad * (A @ M2 @ A.T + np.outer(A @ m1, b) + np.outer(b, A @ m1) + np.outer(b, b) / 6)
+        np.testing.assert_allclose(vol[0], ad / 6, rtol=1e-12)
+        np.testing.assert_allclose(mass[0, 0], rho * ad / 6, rtol=1e-12)
+        np.testing.assert_allclose(mass[0, 1:4], rho * h, rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(mass[0, 4:], rho * Sm[[0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]],
+                                   rtol=1e-11, atol=1e-13)
+
+
 def test_mass_translated_and_rotated_body():
     # moments of a shifted, rotated cube follow the parallel-axis theorem:
     # h = m c, S = R (m/12 I) R^T + m c c^T

@@ -458,6 +458,64 @@ def test_barrier_q_gradient_and_hessian_by_fd():
                     np.testing.assert_allclose(O.T[:, c], col[b1], atol=2e-4 * scale)
 
 
+@pytest.mark.parametrize("mu", [0.0, 0.4])
+def test_incremental_potential_gradient_hessian_and_newton_direction(mu):
+    # sec. 4: E(q) = 1/2 |q - q~|_M^2 + orthogonality + barrier (+ lagged
+    # friction).  grad_hess must be the derivative of total_energy (a term
+    # dropped, doubled or of the wrong sign in either fails), and the Newton
+    # direction must solve the assembled system H p = -g.
+    S, P = _near_scene(4)
+    P = dict(P, mu=mu)
+    B = oracle.Body(S)
+    rng = np.random.default_rng(9)
+    free = np.flatnonzero(S["body_fixed"] == 0)
+    qd = np.zeros_like(S["q0"])
+    qd[free] = rng.normal(scale=0.05, size=(len(free), 12))
+    qt = oracle.q_tilde(S, S["q0"], qd, P)
+    q0 = S["q0"].copy()
+    q0[free, 3:] += rng.normal(scale=1e-4, size=(len(free), 9))
+    x = oracle.vertex_map(S, q0)
+    pt, ee = oracle.candidates(S, x, None, P["dhat"])
+    F = oracle.step_friction(S, q0, P)
+    assert (F is not None) == (mu > 0)
+    gh = oracle.grad_hess(S, B, q0, qt, P, x=x, pt=pt, ee=ee, project=False, F=F)
+    assert gh["n_active"] > 10
+
+    def energy(q):
+        return oracle.total_energy(S, B, q, qt, oracle.vertex_map(S, q), pt, ee, P, F)
+
+    def grad(q):
+        return oracle.grad_hess(S, B, q, qt, P, pt=pt, ee=ee, project=False, F=F)["grad"]
+
+    assert energy(q0) == pytest.approx(gh["energy"], rel=1e-12)
+    A, fr = oracle.assemble(S, gh["diag"], gh["off"], gh["keys"])
+    H = A.toarray()
+    gscale = np.abs(gh["grad"][free]).max()
+    hscale = np.abs(H).max()
+    # the friction state is lagged at q0, where the sliding displacement is
+    # zero: its gradient has a |u| u / eps^2 term whose central difference
+    # errs by about h / eps^2, so the Hessian columns take a step well below
+    # eps = eps_v dt
+    h = 1e-8
+    hh = 1e-10 if mu > 0 else h
+    for i, b in enumerate(fr):
+        for c in range(12):
+            qp, qm = q0.copy(), q0.copy()
+            qp[b, c] += h
+            qm[b, c] -= h
+            fd = (energy(qp) - energy(qm)) / (2 * h)
+            assert fd == pytest.approx(gh["grad"][b, c], rel=1e-5, abs=1e-6 * gscale)
+            qp, qm = q0.copy(), q0.copy()
+            qp[b, c] += hh
+            qm[b, c] -= hh
+            col = ((grad(qp) - grad(qm)) / (2 * hh))[fr].reshape(-1)
+            np.testing.assert_allclose(H[:, 12 * i + c], col, atol=2e-4 * hscale)
+    p = oracle.solve(S, gh["diag"], gh["off"], gh["keys"], -gh["grad"])
+    res = H @ p[fr].reshape(-1) + gh["grad"][fr].reshape(-1)
+    assert np.abs(res).max() <= 1e-9 * np.abs(H).max() * np.abs(p).max() + 1e-12 * gscale
+    assert np.all(p[S["body_fixed"] != 0] == 0.0)
+
+
 def test_assembly_equals_dense_jacobian_product():
     S, P = _near_scene(2)
     x = oracle.vertex_map(S, S["q0"])

@@ -115,6 +115,37 @@ def test_mass_matrix_kinetic_energy():
     assert 0.5 * qd @ M @ qd == pytest.approx(ke, rel=1e-13)
 
 
+def test_q_tilde_gravity_term_is_exact_for_off_centre_bodies():
+    # sec. 4: q~ = q + dt qdot + dt^2 M^-1 f with f = int rho J(xbar)^T g.
+    # The generalised gravity force is integrated here by Gauss-Legendre
+    # quadrature over a cube whose rest frame is off its centre, and
+    # M^-1 f must be the pure translation (g, 0, 0, 0) the oracle uses.
+    c = np.array([0.4, -0.7, 0.25])
+    v, t = meshes.cube(0.5)
+    S = _single_body(v + c, t, density=2.5)
+    mass, _ = oracle.mass_properties(S)
+    M = oracle.mass_matrix(mass)[0]
+    P = sg.default_params(dt=0.02)
+    grav = np.asarray(P["gravity"], float)
+    gl, w = np.polynomial.legendre.leggauss(2)
+    pts = np.stack(np.meshgrid(gl / 2, gl / 2, gl / 2, indexing="ij"), -1).reshape(-1, 3) + c
+    wts = np.einsum("i,j,k->ijk", w / 2, w / 2, w / 2).reshape(-1)
+    f = np.zeros(12)
+    for xb, wt in zip(pts, wts):
+        J = np.zeros((3, 12))
+        J[:, :3] = np.eye(3)
+        for i in range(3):
+            J[i, 3 + 3 * i: 6 + 3 * i] = xb
+        f += 2.5 * wt * J.T @ grav
+    d = np.linalg.solve(M, f)
+    np.testing.assert_allclose(d[:3], grav, rtol=1e-12)
+    np.testing.assert_allclose(d[3:], 0.0, atol=1e-12 * np.abs(grav).max())
+    q = sg.random_state(S, 2, rot_angle=0.5, stretch=0.05, shift=0.3)
+    qd = np.random.default_rng(5).normal(size=q.shape)
+    qt = oracle.q_tilde(S, q, qd, P)
+    np.testing.assert_allclose(qt, q + P["dt"] * qd + P["dt"] ** 2 * d[None, :], rtol=1e-14, atol=1e-15)
+
+
 # --------------------------------------------------------- vertex map ----
 
 def test_vertex_map_matches_affine_map_and_rigid_motion():

@@ -414,6 +414,173 @@ def test_mollifier_parallel_edges_vanish():
     assert e == 0.0 and np.abs(g).max() == 0.0
 
 
+# Near-parallel crossing edges: edge a on the x axis, edge b a height h above
+# it, turned by theta in the x-z plane.  The closest points are both
+# midpoints (line-line case), so d = h, and c = |u x v|^2 = |u|^2 |v|^2
+# sin^2 theta.  The mollifier's threshold eps = 1e-3 |u_rest|^2 |v_rest|^2
+# depends on the rest edges alone, so scaling a rest copy of the pair sets
+# r = c / eps to any value while the deformed pair (and B(d)) stays fixed.
+def _crossing_edges(h=0.5 * DHAT, theta=0.02, half=1e-2):
+    v = np.array([math.cos(theta), 0.0, math.sin(theta)])
+    return np.array([[-half, 0, 0], [half, 0, 0], [0, h, 0] - half * v, [0, h, 0] + half * v])
+
+
+def _rest_for_ratio(X, r):
+    """A scaled copy of X whose eps makes c / eps = r, and that r as the
+    definition gives it (c and eps as products of the edge vectors)."""
+    u, v = X[1] - X[0], X[3] - X[2]
+    c = np.dot(np.cross(u, v), np.cross(u, v))
+    sig = (c / (1e-3 * u.dot(u) * v.dot(v) * r)) ** 0.25
+    xb = X * sig
+    ub, vb = xb[1] - xb[0], xb[3] - xb[2]
+    return xb, c / ((1e-3 * ub.dot(ub)) * vb.dot(vb))
+
+
+def _mollifier_closed_form(r):
+    # IPC's EE mollifier m(c) = (2 - c/eps) c/eps below eps, 1 above
+    return (2.0 - r) * r if r < 1.0 else 1.0
+
+
+def test_mollifier_closed_form_values_and_c1_join():
+    # the ratio of the mollified energy to the same pair's unmollified
+    # energy (rest edges short enough that c > eps) is m(r): 0.4375 at
+    # r = 1/4, 0.75 at r = 1/2, 0.99 at 0.9; approaching r = 1 from below,
+    # 1 - m = (1 - r)^2 (value 1 and zero slope at the join), and m = 1
+    # at and above it.  A linear ramp c/eps fails every r < 1.
+    X = _crossing_edges()
+    d, ty = oracle.pair_distance(1, X)
+    assert ty == 28 and d == pytest.approx(0.5 * DHAT, rel=1e-12)  # line-line
+    xb_ref, r_ref = _rest_for_ratio(X, 4.0)
+    _, e_ref, _, _ = oracle.pair_local(1, X, xb_ref, DHAT, 3.0)
+    assert e_ref == pytest.approx(3.0 * _paper_barrier(d, DHAT), rel=1e-12)
+    for r in (0.25, 0.5, 0.9, 1.0 - 1e-2, 1.0 - 1e-3, 1.0 + 1e-3, 2.0):
+        xb, r_act = _rest_for_ratio(X, r)
+        _, e, _, _ = oracle.pair_local(1, X, xb, DHAT, 3.0)
+        m = e / e_ref
+        assert m == pytest.approx(_mollifier_closed_form(r_act), rel=1e-12, abs=1e-15)
+        if r < 1.0:
+            # one-sided difference at the join: (1 - m(1 - s)) / s = s -> 0
+            s = 1.0 - r_act
+            assert (1.0 - m) / s == pytest.approx(s, rel=1e-6)
+    _, e_half, _, _ = oracle.pair_local(1, X, _rest_for_ratio(X, 0.5)[0], DHAT, 3.0)
+    assert e_half / e_ref == pytest.approx(0.75, rel=1e-12)
+
+
+def test_mollified_barrier_derivatives_finite_differences():
+    # 0 < c < eps on near-parallel edges: the gradient and Hessian of m B
+    # are the derivatives of its (pinned) energy, so the product rule's m'
+    # term (slope (2 - 2r)/eps) is checked.  Dropping m' or using a linear
+    # ramp moves the gradient by far more than the tolerance.
+    for theta, r in ((0.02, 0.5), (0.015, 0.3), (0.03, 0.8)):
+        X = _crossing_edges(h=0.4 * DHAT, theta=theta)
+        xb, _ = _rest_for_ratio(X, r)
+        ty, e, g, H = oracle.pair_local(1, X, xb, DHAT, 1.0)
+        assert ty == 28  # line-line
+        h = 1e-9
+        x = X.reshape(12)
+        gf = np.zeros(12)
+        Hf = np.zeros((12, 12))
+        for i in range(12):
+            xp, xm = x.copy(), x.copy()
+            xp[i] += h
+            xm[i] -= h
+            _, ep, gp, _ = oracle.pair_local(1, xp.reshape(4, 3), xb, DHAT, 1.0)
+            _, em, gm, _ = oracle.pair_local(1, xm.reshape(4, 3), xb, DHAT, 1.0)
+            gf[i] = (ep - em) / (2 * h)
+            Hf[:, i] = (gp - gm) / (2 * h)
+        np.testing.assert_allclose(g, gf, rtol=0, atol=1e-6 * np.abs(g).max())
+        np.testing.assert_allclose(H, Hf, rtol=0, atol=1e-5 * np.abs(H).max())
+        # the m' part is a visible share of the gradient here: the same
+        # pair with m held at its value (rest edges giving r >= 1, energy
+        # rescaled) has a gradient that differs by well over the tolerance
+        xb1, _ = _rest_for_ratio(X, 4.0)
+        _, e1, g1, _ = oracle.pair_local(1, X, xb1, DHAT, 1.0)
+        assert np.abs(g - (e / e1) * g1).max() > 1e-3 * np.abs(g).max()
+
+
+def _two_edge_scene(X, xb):
+    """Two free bodies holding one edge each (vertices 0-1 and 2-3); the
+    scene-level oracle calls take the deformed positions X separately from
+    the rest positions xb."""
+    return dict(xbar=np.ascontiguousarray(xb, dtype=np.float64), vert_body=np.array([0, 0, 1, 1], np.int32),
+                tris=np.zeros((0, 3), np.int32), tri_body=np.zeros(0, np.int32),
+                edges=np.array([[0, 1], [2, 3]], np.int32), edge_body=np.array([0, 1], np.int32),
+                body_fixed=np.zeros(2, np.uint8)), np.ascontiguousarray(X, dtype=np.float64)
+
+
+def test_mollifier_in_scene_energy_and_friction_lag():
+    # the energy-only path and the friction lag carry their own mollifier
+    # evaluation: at r = 1/2 the barrier energy is 0.75 of the unmollified
+    # one and the lagged normal force lambda = kappa m |B'(d)| is 0.75 of
+    # its unmollified value, which is kappa |B'(d)| in closed form.
+    X = _crossing_edges()
+    d = 0.5 * DHAT
+    P = sg.default_params(dhat=DHAT, kappa_b=5.0)
+    ee = np.array([[0, 1]], np.int32)
+    pt = np.zeros((0, 2), np.int32)
+    Bp = -2 * (d - DHAT) * math.log(d / DHAT) - (d - DHAT) ** 2 / d
+    res = {}
+    for r in (0.5, 4.0):
+        xb, r_act = _rest_for_ratio(X, r)
+        S, x = _two_edge_scene(X, xb)
+        e = oracle.barrier_energy(S, x, pt, ee, P)
+        F = oracle.friction_lag(S, x, pt, ee, P)
+        res[r] = (e, F["ee"]["lam"][0], r_act)
+    m = _mollifier_closed_form(res[0.5][2])
+    assert res[4.0][0] == pytest.approx(5.0 * _paper_barrier(d, DHAT), rel=1e-12)
+    assert res[0.5][0] == pytest.approx(m * res[4.0][0], rel=1e-12)
+    assert res[4.0][1] == pytest.approx(5.0 * abs(Bp), rel=1e-10)
+    assert res[0.5][1] == pytest.approx(m * res[4.0][1], rel=1e-12)
+    assert m == pytest.approx(0.75, rel=1e-12)
+
+
+def test_friction_lag_vjp_through_mollifier_by_fd():
+    # the adjoint's derivative of the lag (lambda, T, w as functions of x^t)
+    # on a near-parallel pair with 0 < c < eps: lambda carries m(c(x^t)),
+    # so the VJP must carry m and its slope; central differences of the lag
+    # (x^t in the sliding displacement held fixed) agree with it.
+    X = _crossing_edges(h=0.4 * DHAT, theta=0.02)
+    xb, r = _rest_for_ratio(X, 0.5)
+    assert 0.4 < r < 0.6
+    # bodies at identity with x = xbar (rest positions are the current ones
+    # scaled, so A = I / sig maps the rest pair onto X)
+    sig = xb[1, 0] / X[1, 0]
+    S, _ = _two_edge_scene(X, xb)
+    P = sg.default_params(dhat=DHAT, kappa_b=5.0, mu=0.4)
+    qt = np.zeros((2, 12))
+    for b in range(2):
+        qt[b, 3:] = (np.eye(3) / sig).reshape(9)
+    xt = oracle.vertex_map(S, qt)
+    np.testing.assert_allclose(xt, X, atol=1e-15)
+    ee = np.array([[0, 1]], np.int32)
+    pt = np.zeros((0, 2), np.int32)
+    F = oracle.friction_lag(S, xt, pt, ee, P, keep_inactive=True)
+    assert F["ee"]["lam"][0] > 0
+    # current positions: a small slide of body 1 along x (|u| above eps_v dt)
+    q = qt.copy()
+    q[1, 0] += 3e-5
+    x = oracle.vertex_map(S, q)
+    rng = np.random.default_rng(8)
+    l = rng.normal(size=(2, 12))
+    v = oracle.friction_lag_vjp(S, x, F, P, l)
+    keys = np.array([[0, 1]], np.int32)
+
+    def lag_dot(qq):
+        Fp = oracle.friction_lag(S, oracle.vertex_map(S, qq), pt, ee, P, keep_inactive=True)
+        Fp["xt"] = F["xt"]
+        return float(np.sum(l * oracle.friction(S, x, Fp, P, keys, hess=False)["grad"]))
+
+    h = 1e-9
+    fd = np.zeros((2, 12))
+    for b in range(2):
+        for c in range(12):
+            qp, qm = qt.copy(), qt.copy()
+            qp[b, c] += h
+            qm[b, c] -= h
+            fd[b, c] = (lag_dot(qp) - lag_dot(qm)) / (2 * h)
+    np.testing.assert_allclose(v, fd, rtol=0, atol=1e-5 * np.abs(fd).max())
+
+
 # ---------------------------------------------------------------- PSD ----
 
 def test_psd_projection_matches_eigh():

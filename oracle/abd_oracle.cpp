@@ -8,7 +8,10 @@
 // one passage of Lan et al., "Affine Body Dynamics" (ABD), or the textbook
 // definition that passage relies on, in the order the paper states it.
 // Compiled with -O2 -ffp-contract=off -fno-fast-math so that the arithmetic
-// written here is the arithmetic executed.
+// written here is the arithmetic executed.  Per-pair loops run their pairs
+// in parallel (OpenMP) where every pair's result is independent; sums over
+// pairs are then taken in pair order, so every result is the same for any
+// thread count.
 //
 // Derivatives of distances and barriers are NOT derived by hand here: a
 // second-order forward-mode jet (value, gradient, full Hessian) is pushed
@@ -560,22 +563,34 @@ int ora_candidates(int nb, int nv, int nt, int ne, const int32_t* body_vert_off,
         o[3 + i] = std::max(o[3 + i], vb[6 * v + 3 + i]);
       }
   }
+  // body pairs split over threads; the lists are sorted afterwards, so the
+  // result does not depend on the split
   std::vector<std::pair<int32_t, int32_t>> P, E;
-  for (int a = 0; a < nb; ++a)
-    for (int b = a + 1; b < nb; ++b) {
-      if (body_scene[a] != body_scene[b]) continue;
-      if (fixed[a] && fixed[b]) continue;
-      if (!overlap(&bb[6 * a], &bb[6 * b])) continue;
-      for (int s = 0; s < 2; ++s) {
-        const int bv = s ? b : a, bt = s ? a : b;
-        for (int v = body_vert_off[bv]; v < body_vert_off[bv + 1]; ++v)
-          for (int t = body_tri_off[bt]; t < body_tri_off[bt + 1]; ++t)
-            if (overlap(&vb[6 * v], &tb[6 * (size_t)t])) P.push_back({v, t});
+#pragma omp parallel
+  {
+    std::vector<std::pair<int32_t, int32_t>> Pl, El;
+#pragma omp for schedule(dynamic, 4) nowait
+    for (int a = 0; a < nb; ++a)
+      for (int b = a + 1; b < nb; ++b) {
+        if (body_scene[a] != body_scene[b]) continue;
+        if (fixed[a] && fixed[b]) continue;
+        if (!overlap(&bb[6 * a], &bb[6 * b])) continue;
+        for (int s = 0; s < 2; ++s) {
+          const int bv = s ? b : a, bt = s ? a : b;
+          for (int v = body_vert_off[bv]; v < body_vert_off[bv + 1]; ++v)
+            for (int t = body_tri_off[bt]; t < body_tri_off[bt + 1]; ++t)
+              if (overlap(&vb[6 * v], &tb[6 * (size_t)t])) Pl.push_back({v, t});
+        }
+        for (int e = body_edge_off[a]; e < body_edge_off[a + 1]; ++e)
+          for (int f = body_edge_off[b]; f < body_edge_off[b + 1]; ++f)
+            if (overlap(&eb[6 * (size_t)e], &eb[6 * (size_t)f])) El.push_back({std::min(e, f), std::max(e, f)});
       }
-      for (int e = body_edge_off[a]; e < body_edge_off[a + 1]; ++e)
-        for (int f = body_edge_off[b]; f < body_edge_off[b + 1]; ++f)
-          if (overlap(&eb[6 * (size_t)e], &eb[6 * (size_t)f])) E.push_back({std::min(e, f), std::max(e, f)});
+#pragma omp critical
+    {
+      P.insert(P.end(), Pl.begin(), Pl.end());
+      E.insert(E.end(), El.begin(), El.end());
     }
+  }
   std::sort(P.begin(), P.end());
   std::sort(E.begin(), E.end());
   *n_pt = (int64_t)P.size();
@@ -597,6 +612,7 @@ int ora_candidates(int nb, int nv, int nt, int ne, const int32_t* body_vert_off,
 void ora_classify(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, const int32_t* edges,
                   const double* x, double dhat, uint8_t* type, double* d2, uint8_t* active) {
   const double dhat2 = dhat * dhat;
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     int vid[4];
     pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
@@ -628,71 +644,96 @@ int64_t ora_barrier(int64_t n, int is_ee, const int32_t* pairs, const int32_t* v
   const double dhat2 = dhat * dhat;
   int64_t n_active = 0;
   double esum = 0.0;
-  for (int64_t i = 0; i < n; ++i) {
-    int vid[4];
-    pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
-    D3 X[4];
-    const double* xb4[4];
-    for (int k = 0; k < 4; ++k) {
-      X[k] = ld3(x, vid[k]);
-      xb4[k] = xbar + 3 * vid[k];
-    }
-    const int ty = classify(is_ee, X);
-    double num, den;
-    case_nd<double>(ty, X, num, den, 1.0);
-    if (local_H) std::memset(local_H + 144 * i, 0, 144 * sizeof(double));
-    if (local_g) std::memset(local_g + 12 * i, 0, 12 * sizeof(double));
-    if (!(num < dhat2 * den)) continue;
-    if (num == 0.0) return -3;
-    ++n_active;
-    double e, g[12], H[144];
-    pair_local(is_ee, ty, X, xb4, dhat, kappa, &e, g, H);
-    if (project) psd_project(12, H);
-    esum += e;
-    if (local_H) std::memcpy(local_H + 144 * i, H, sizeof(H));
-    if (local_g) std::memcpy(local_g + 12 * i, g, sizeof(g));
-    // 12 x 24 pair Jacobian: body slot 0 = body of vertex slot 0, slot 1 =
-    // the other body
-    const int ba = vert_body[vid[0]], bo = vert_body[vid[3]];
-    double Jp[12][24];
-    for (int r = 0; r < 12; ++r)
-      for (int c = 0; c < 24; ++c) Jp[r][c] = 0.0;
-    int slot[4];
-    for (int k = 0; k < 4; ++k) {
-      slot[k] = vert_body[vid[k]] == ba ? 0 : 1;
-      double J[3][12];
-      kin_jacobian(xb4[k], J);
-      for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 12; ++c) Jp[3 * k + r][12 * slot[k] + c] = J[r][c];
-    }
-    const int bodies[2] = {ba, bo};
-    double G[24], HH[24][24];
-    for (int c = 0; c < 24; ++c) {
-      double s = 0.0;
-      for (int r = 0; r < 12; ++r) s += Jp[r][c] * g[r];
-      G[c] = s;
-    }
-    for (int c = 0; c < 24; ++c)
-      for (int d = 0; d < 24; ++d) {
-        double s = 0.0;
-        for (int r = 0; r < 12; ++r)
-          for (int t = 0; t < 12; ++t) s += Jp[r][c] * H[r * 12 + t] * Jp[t][d];
-        HH[c][d] = s;
+  // pairs are evaluated a chunk at a time (in parallel), then their
+  // contributions are added in pair order
+  constexpr int64_t CH = 1024;
+  struct PairOut {
+    int status;  // 0 inactive, 1 active, -3 zero distance
+    int ba, bo;
+    double e, G[24], HH[24][24];
+  };
+  std::vector<PairOut> out((size_t)std::min<int64_t>(CH, std::max<int64_t>(n, 1)));
+  for (int64_t c0 = 0; c0 < n; c0 += CH) {
+    const int64_t m = std::min(CH, n - c0);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t j = 0; j < m; ++j) {
+      const int64_t i = c0 + j;
+      PairOut& o = out[(size_t)j];
+      int vid[4];
+      pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
+      D3 X[4];
+      const double* xb4[4];
+      for (int k = 0; k < 4; ++k) {
+        X[k] = ld3(x, vid[k]);
+        xb4[k] = xbar + 3 * vid[k];
       }
-    for (int sa = 0; sa < 2; ++sa) {
-      const int b = bodies[sa];
-      if (fixed[b]) continue;
-      for (int c = 0; c < 12; ++c) grad[12 * b + c] += G[12 * sa + c];
-      for (int c = 0; c < 12; ++c)
-        for (int d = 0; d < 12; ++d) diag[144 * b + 12 * c + d] += HH[12 * sa + c][12 * sa + d];
+      const int ty = classify(is_ee, X);
+      double num, den;
+      case_nd<double>(ty, X, num, den, 1.0);
+      if (local_H) std::memset(local_H + 144 * i, 0, 144 * sizeof(double));
+      if (local_g) std::memset(local_g + 12 * i, 0, 12 * sizeof(double));
+      o.status = 0;
+      if (!(num < dhat2 * den)) continue;
+      if (num == 0.0) {
+        o.status = -3;
+        continue;
+      }
+      o.status = 1;
+      double g[12], H[144];
+      pair_local(is_ee, ty, X, xb4, dhat, kappa, &o.e, g, H);
+      if (project) psd_project(12, H);
+      if (local_H) std::memcpy(local_H + 144 * i, H, sizeof(H));
+      if (local_g) std::memcpy(local_g + 12 * i, g, sizeof(g));
+      // 12 x 24 pair Jacobian: body slot 0 = body of vertex slot 0, slot 1 =
+      // the other body
+      const int ba = vert_body[vid[0]], bo = vert_body[vid[3]];
+      o.ba = ba;
+      o.bo = bo;
+      double Jp[12][24];
+      for (int r = 0; r < 12; ++r)
+        for (int c = 0; c < 24; ++c) Jp[r][c] = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        const int slot = vert_body[vid[k]] == ba ? 0 : 1;
+        double J[3][12];
+        kin_jacobian(xb4[k], J);
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 12; ++c) Jp[3 * k + r][12 * slot + c] = J[r][c];
+      }
+      for (int c = 0; c < 24; ++c) {
+        double sum = 0.0;
+        for (int r = 0; r < 12; ++r) sum += Jp[r][c] * g[r];
+        o.G[c] = sum;
+      }
+      for (int c = 0; c < 24; ++c)
+        for (int d = 0; d < 24; ++d) {
+          double sum = 0.0;
+          for (int r = 0; r < 12; ++r)
+            for (int t = 0; t < 12; ++t) sum += Jp[r][c] * H[r * 12 + t] * Jp[t][d];
+          o.HH[c][d] = sum;
+        }
     }
-    if (!fixed[ba] && !fixed[bo] && off) {
-      const int lo = std::min(ba, bo), hi = std::max(ba, bo);
-      const int k = find_off(off_keys, n_off, lo, hi);
-      if (k < 0) return -1;
-      const int sl = (lo == ba) ? 0 : 1, sh = 1 - sl;
-      for (int c = 0; c < 12; ++c)
-        for (int d = 0; d < 12; ++d) off[144 * (int64_t)k + 12 * c + d] += HH[12 * sl + c][12 * sh + d];
+    for (int64_t j = 0; j < m; ++j) {
+      const PairOut& o = out[(size_t)j];
+      if (o.status == -3) return -3;
+      if (o.status == 0) continue;
+      ++n_active;
+      esum += o.e;
+      const int bodies[2] = {o.ba, o.bo};
+      for (int sa = 0; sa < 2; ++sa) {
+        const int b = bodies[sa];
+        if (fixed[b]) continue;
+        for (int c = 0; c < 12; ++c) grad[12 * b + c] += o.G[12 * sa + c];
+        for (int c = 0; c < 12; ++c)
+          for (int d = 0; d < 12; ++d) diag[144 * b + 12 * c + d] += o.HH[12 * sa + c][12 * sa + d];
+      }
+      if (!fixed[o.ba] && !fixed[o.bo] && off) {
+        const int lo = std::min(o.ba, o.bo), hi = std::max(o.ba, o.bo);
+        const int k = find_off(off_keys, n_off, lo, hi);
+        if (k < 0) return -1;
+        const int sl = (lo == o.ba) ? 0 : 1, sh = 1 - sl;
+        for (int c = 0; c < 12; ++c)
+          for (int d = 0; d < 12; ++d) off[144 * (int64_t)k + 12 * c + d] += o.HH[12 * sl + c][12 * sh + d];
+      }
     }
   }
   *energy += esum;
@@ -703,8 +744,10 @@ int64_t ora_barrier(int64_t n, int is_ee, const int32_t* pairs, const int32_t* v
 double ora_barrier_energy(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, const int32_t* edges,
                           const double* xbar, const double* x, double dhat, double kappa, int* status) {
   const double dhat2 = dhat * dhat;
-  double esum = 0.0;
-  *status = 0;
+  // per-pair terms in parallel (NaN marks a pair at zero distance), summed
+  // in pair order
+  std::vector<double> term((size_t)std::max<int64_t>(n, 1), 0.0);
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     int vid[4];
     pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
@@ -719,8 +762,8 @@ double ora_barrier_energy(int64_t n, int is_ee, const int32_t* pairs, const int3
     case_nd<double>(ty, X, num, den, 1.0);
     if (!(num < dhat2 * den)) continue;
     if (num == 0.0) {
-      *status = -3;
-      return INFINITY;
+      term[(size_t)i] = NAN;
+      continue;
     }
     const double s = num / den, d = std::sqrt(s);
     double b = -(d - dhat) * (d - dhat) * std::log(d / dhat);
@@ -735,7 +778,16 @@ double ora_barrier_energy(int64_t n, int is_ee, const int32_t* pairs, const int3
         b = (2.0 - r) * r * b;
       }
     }
-    esum += kappa * b;
+    term[(size_t)i] = kappa * b;
+  }
+  double esum = 0.0;
+  *status = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (std::isnan(term[(size_t)i])) {
+      *status = -3;
+      return INFINITY;
+    }
+    esum += term[(size_t)i];
   }
   return esum;
 }
@@ -750,6 +802,7 @@ double ora_barrier_energy(int64_t n, int is_ee, const int32_t* pairs, const int3
 void ora_ccd(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, const int32_t* edges,
              const double* x, const double* dx, double s, double tmax, int max_iter, double* tout,
              int32_t* iters_out) {
+#pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < n; ++i) {
     int vid[4];
     pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose=False):
-    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-fopenmp",
            "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd))

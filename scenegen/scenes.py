@@ -325,6 +325,67 @@ def cube_on_slope(theta, mu, v0=1.0, gap=5e-4, ground=40.0):
     return sb.build(), params
 
 
+def cube_lattice(seed=6, n=10, half=0.05, gap_range=(2e-4, 5e-4), tilt=2e-4, jitter=1e-5):
+    """n x n x n cubes (half-edge `half`, 1 kg at the default size) on an
+    axis-aligned lattice whose planes are `gap_range` apart (one gap per
+    plane and axis), so that every interior cube has 26 neighbours (6 across
+    faces, 12 across edges, 8 across corners) closer than sqrt(3) times the
+    largest gap; each cube tilted by at most `tilt` and shifted by at most
+    `jitter` per axis.  The bottom layer is fixed.  A dense, multi-block
+    contact state for the solver: no free fall, every body in contact.
+    Draw order: the n-1 gaps between x planes, then y planes, then z planes;
+    then per cube (y-layer-major, then x, then z): tilt axis (3), tilt
+    angle, jitter (3)."""
+    rng = np.random.default_rng(seed)
+    v, t = meshes.cube(half)
+    gaps = [rng.uniform(*gap_range, size=n - 1) for _ in range(3)]
+    coords = [np.concatenate([[0.0], np.cumsum(2 * half + g)]) for g in gaps]
+    coords = [c - c.mean() for c in coords]
+    sb = SceneBuilder()
+    for j in range(n):
+        for i in range(n):
+            for k in range(n):
+                R = random_rotation(rng, tilt)
+                jit = rng.uniform(-jitter, jitter, size=3)
+                p = np.array([coords[0][i], coords[1][j] + half + 0.1, coords[2][k]]) + jit
+                sb.add(v, t, R=R, p=p, fixed=(j == 0))
+    scene = sb.build()
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=70.0, mu=0.0, newton_tol=1e-5)
+    return scene, params
+
+
+def icosphere_fcc(seed=7, cells=(5, 10, 5), radius=0.06, gap=5e-5):
+    """Icospheres (subdivision 2) of one radius on a face-centred cubic
+    lattice (4 spheres per cubic cell, 12 nearest neighbours) whose centres
+    are 2 radius + gap apart, with random rotations.  Every mesh vertex lies
+    on its sphere, so meshes of neighbours are at least `gap` apart, and a
+    pair comes within dhat where vertices of both meshes point at each
+    other.  The bottom layer (lowest centre height) is fixed.  Draw order
+    per sphere (cells x-major, then y, then z; four sites per cell): rotation
+    axis (3), angle."""
+    rng = np.random.default_rng(seed)
+    sv, st = meshes.icosphere(2, radius)
+    a = math.sqrt(2.0) * (2.0 * radius + gap)
+    sites = ((0.0, 0.0, 0.0), (0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0))
+    centres = []
+    for ix in range(cells[0]):
+        for iy in range(cells[1]):
+            for iz in range(cells[2]):
+                for sx, sy, sz in sites:
+                    centres.append(((ix + sx) * a, (iy + sy) * a, (iz + sz) * a))
+    centres = np.array(centres)
+    centres -= centres.mean(0)
+    centres[:, 1] += 1.0
+    ylow = centres[:, 1].min()
+    sb = SceneBuilder()
+    for c in centres:
+        R = random_rotation(rng, math.pi)
+        sb.add(sv, st, R=R, p=c, fixed=bool(c[1] == ylow))
+    scene = sb.build()
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=70.0, mu=0.0, newton_tol=1e-5)
+    return scene, params
+
+
 CONFIGS = {
     "three_cubes": three_cubes,
     "icosphere_box": icosphere_box,

@@ -75,16 +75,21 @@ def icosphere(subdiv=2, radius=1.0):
     return v, f
 
 
-def torus(major, minor, n_major=200, n_minor=50):
+def torus(major, minor, n_major=200, n_minor=50, straight=0.0):
     """Torus about the local y axis (ring in the x-z plane):
-    n_major*n_minor vertices, 2*n_major*n_minor triangles."""
+    n_major*n_minor vertices, 2*n_major*n_minor triangles.  With
+    straight > 0 the ring is a stadium (a chain link): the half with x > 0
+    is moved by straight/2 along +x and the other half by straight/2 along
+    -x, so two straight tube sections of that length join the halves (the
+    meridians at u = pi/2 and 3 pi/2 belong to the +x half)."""
     i = np.arange(n_major)
     j = np.arange(n_minor)
     u = 2.0 * np.pi * i / n_major
     w = 2.0 * np.pi * j / n_minor
     uu, ww = np.meshgrid(u, w, indexing="ij")
     rr = major + minor * np.cos(ww)
-    x = rr * np.cos(uu)
+    side = np.where((4 * i <= n_major) | (4 * i >= 3 * n_major), 0.5, -0.5)
+    x = rr * np.cos(uu) + straight * side[:, None]
     z = rr * np.sin(uu)
     y = minor * np.sin(ww)
     v = np.stack([x, y, z], axis=-1).reshape(-1, 3)

@@ -183,20 +183,32 @@ def icosphere_box(seed=2, n_side=10, n_layers=10, spacing=0.25, friction=0.5):
 
 def torus_chains(seed=3, n_chains=8, n_links=8, n_major=200, n_minor=50,
                  sigma=1e-3, gap=2e-3):
-    """n_chains parallel chains of n_links interlocked tori (major 0.3,
-    minor 0.1), alternating flat (ring in x-z) and upright (ring in x-y)
-    links; noiseless tube gaps `gap` both along and across chains.  Vertices
-    are pushed inward along the tube normal by |N(0,sigma)|, so gaps only
-    grow.  End links fixed; the others get velocity N(0,0.5^2) per
+    """n_chains parallel chains of n_links interlocked links (major radius
+    0.3, minor 0.1), alternating flat (ring in x-z) and upright (ring in x-y)
+    along x; noiseless tube gaps `gap` between every pair of neighbours.
+
+    A link cannot be a plain torus here: with major = 3 minor the hole of a
+    ring (inner diameter 0.4) holds the tubes (diameter 0.2) of its two
+    neighbours only with zero clearance, so interlocked neighbours at a
+    positive gap would overlap each other.  Each link is a stadium instead:
+    the torus's two halves joined by straight tube sections of length
+    s = 6 minor - 2 major + 3 gap (6 mm at these sizes) along the chain, which
+    is the length at which the two neighbours' tubes in a link's hole are
+    `gap` apart from each other and from the link.  Link pitch along a chain
+    s + 2 major - 2 minor - gap; chain pitch 2 (major + minor) + gap.
+
+    Vertices are pushed inward along the tube normal by |N(0,sigma)|, so gaps
+    only grow.  End links fixed; the others get velocity N(0,0.5^2) per
     translation component.  Draw order: per body (chain-major) the noise of
     all vertices, then for free bodies the 3 velocity components."""
     rng = np.random.default_rng(seed)
     Rm, rm = 0.3, 0.1
-    v0, t0 = meshes.torus(Rm, rm, n_major, n_minor)
+    straight = 6 * rm - 2 * Rm + 3 * gap
+    v0, t0 = meshes.torus(Rm, rm, n_major, n_minor, straight=straight)
     uu = np.repeat(2 * np.pi * np.arange(n_major) / n_major, n_minor)
     ww = np.tile(2 * np.pi * np.arange(n_minor) / n_minor, n_major)
     nrm = np.stack([np.cos(ww) * np.cos(uu), np.sin(ww), np.cos(ww) * np.sin(uu)], -1)
-    pitch = 2 * Rm - 2 * rm - gap
+    pitch = straight + 2 * Rm - 2 * rm - gap
     wpitch = 2 * (Rm + rm) + gap
     upright = _rot((1.0, 0.0, 0.0), math.pi / 2)
     sb = SceneBuilder()
@@ -212,7 +224,12 @@ def torus_chains(seed=3, n_chains=8, n_links=8, n_major=200, n_minor=50,
             p = (pitch * (l - (n_links - 1) / 2.0), 1.0, wpitch * (c - (n_chains - 1) / 2.0))
             sb.add(v, t0, R=R, p=p, fixed=fixed, qd=qd)
     scene = sb.build()
-    params = default_params(dt=5e-3, dhat=5e-4, kappa_b=2.4, mu=0.0, steps=100)
+    # kappa_b by the landing rule of the icosphere box: a link (59 kg) met
+    # at 0.5 m/s is stopped near dhat/2: kappa |B'(dhat/2)| = m v dt, with
+    # |B'(dhat/2)| = (1/2 + ln 2) dhat
+    m_link = 1000.0 * 2.0 * math.pi ** 2 * Rm * rm ** 2
+    kappa = m_link * 0.5 * 5e-3 / ((0.5 + math.log(2.0)) * 5e-4)
+    params = default_params(dt=5e-3, dhat=5e-4, kappa_b=round(kappa), mu=0.0, steps=100)
     return scene, params
 
 
@@ -305,6 +322,30 @@ def icosphere_resting_layer(seed=2, dhat=1e-3):
         low = (scene["xbar"][sl] @ A.T)[:, 1].min()
         q[b, 1] = rng.uniform(0.2, 0.8) * dhat - low
     return scene, params
+
+
+def landed(scene, seed, dhat=1e-3, v_impact=1.0, layer=0.125):
+    """A copy of `scene` whose lowest layer of free bodies (centres within
+    `layer` of the lowest free centre height) is lowered until each body's
+    lowest mesh vertex sits U[0.2,0.8] dhat above the ground plane y = 0 and
+    moves down at v_impact: the moment a layer lands, as a positions-only
+    contact state.  Draw order: one height fraction per lowered body, in
+    body order."""
+    rng = np.random.default_rng(seed)
+    S = dict(scene)
+    q = scene["q0"].copy()
+    qd = scene["qd0"].copy()
+    free = np.flatnonzero(scene["body_fixed"] == 0)
+    y0 = q[free, 1].min()
+    for b in free:
+        if q[b, 1] > y0 + layer:
+            continue
+        sl = slice(scene["body_vert_off"][b], scene["body_vert_off"][b + 1])
+        low = (scene["xbar"][sl] @ q[b, 3:].reshape(3, 3).T)[:, 1].min()
+        q[b, 1] = rng.uniform(0.2, 0.8) * dhat - low
+        qd[b, 1] = -v_impact
+    S["q0"], S["qd0"] = q, qd
+    return S
 
 
 def cube_on_slope(theta, mu, v0=1.0, gap=5e-4, ground=40.0):

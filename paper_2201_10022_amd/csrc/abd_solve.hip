@@ -936,6 +936,60 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
   }
 }
 
+// Between replays of a batch: the blocks of scenes still iterating move to
+// the front of the block list, in order, with their partials (a scene's fold
+// range moves with its blocks), and the tail is marked empty (sc = -1), so
+// that once most scenes have stopped an iteration launch reads and runs only
+// the remaining scenes' blocks instead of every scene's constants,
+// preconditioner blocks and vectors.  One block walks the list in segments
+// of CT entries: a segment is read whole before any of it is written, and
+// entries only move to lower indices, so nothing unread is overwritten.
+constexpr int CT = 1024;
+__global__ void __launch_bounds__(CT) k_cg_compact(PcgBlk *blk, int nblk, double *part, CgScene scs) {
+  __shared__ int wsum[CT / 64];
+  __shared__ int base_sh;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base_sh = 0;
+  __syncthreads();
+  for (int seg = 0; seg < nblk; seg += CT) {
+    const int j = seg + (int)threadIdx.x;
+    PcgBlk r;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    bool live = false;
+    if (j < nblk) {
+      r = blk[j];
+      live = r.sc >= 0 && !scs.stop[r.sc];
+      if (live) {
+        p0 = part[4 * (int64_t)j];
+        p1 = part[4 * (int64_t)j + 1];
+        p2 = part[4 * (int64_t)j + 2];
+        p3 = part[4 * (int64_t)j + 3];
+      }
+    }
+    const unsigned long long m = __ballot(live);
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int before = base_sh, total = 0;
+    for (int q = 0; q < CT / 64; ++q) {
+      before += q < w ? wsum[q] : 0;
+      total += wsum[q];
+    }
+    __syncthreads();  // every entry of the segment, base_sh and wsum read
+    if (live) {
+      const int np = before + __popcll(m & ((1ull << lane) - 1ull));
+      r.fold_lo = np - (j - r.fold_lo);
+      blk[np] = r;
+      part[4 * (int64_t)np] = p0;
+      part[4 * (int64_t)np + 1] = p1;
+      part[4 * (int64_t)np + 2] = p2;
+      part[4 * (int64_t)np + 3] = p3;
+    }
+    if (threadIdx.x == 0) base_sh += total;
+    __syncthreads();
+  }
+  for (int j = base_sh + (int)threadIdx.x; j < nblk; j += CT) blk[j].sc = -1;
+}
+
 // closes a replay: advances the base and copies the state the host reads
 // (base, n_stopped, max_final) to mapped host memory
 __global__ void k_cg_advance(CgState *st, int n, int *host) {
@@ -1038,6 +1092,8 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
       hipLaunchKernelGGL(k_cg_iter, dim3(nblk_s), dim3(SWB), 0, q, j, cblk, ent, sc->body_fixed, Bm, inv, rv[a],
                          wv[a], sv[a], rv[o], wv[o], sv[o], x_out, u, p, pt[a], pt[o], st, scs, rtol2, max_iter);
     }
+    // (n is even: the next replay's first iteration folds pt[0])
+    if (S > 1) hipLaunchKernelGGL(k_cg_compact, dim3(1), dim3(CT), 0, q, cblk, nblk_s, pt[0], scs);
     hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(1), 0, q, st, n, hst_d);
   };
   const char *env = getenv("ABD_PCG_GRAPH");
@@ -1054,7 +1110,8 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
         (uintptr_t)sv[0],    (uintptr_t)sv[1],    (uintptr_t)pt[0],        (uintptr_t)pt[1],      (uintptr_t)cblk,
         (uintptr_t)ent,      (uintptr_t)st,       (uintptr_t)sc->body_fixed,
         (uintptr_t)nblk_s,   (uintptr_t)max_iter, (uintptr_t)rtol_bits,    (uintptr_t)scs.gam,    (uintptr_t)scs.alp,
-        (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)hst_d, (uintptr_t)1};
+        (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)hst_d, (uintptr_t)S,
+        (uintptr_t)1};
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     for (int gi = 0; gi < 2; ++gi) {
       if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {

@@ -1,29 +1,35 @@
 """Throughput of the affine-body contact path on one MI355X.
 
-A step is one implicit-Euler time step of the 1000-icosphere box drop
-(162,017 vertices, 320,024 triangles, 480,040 edges, 12,000 free DOFs,
-FP64): every Newton iteration runs the kinematic map, both candidate
-sweeps, the barrier gradient and PSD-projected Hessian with J^T H J
-assembly, the body terms, the PCG solve, CCD and the line search.  The
-scene is first advanced (untimed) until the spheres have landed, so the
-timed steps run in contact.
+Default workload (the largest single-GPU configuration): 256 independent
+drop scenes advanced together, scene k holding 2..200 cubes or icospheres
+(26,914 bodies, 2.27 M vertices, 4.42 M triangles, 6.64 M edges, FP64)
+over its own fixed ground quad.  A step is one implicit-Euler time step of
+the whole batch: every Newton iteration runs the kinematic map, both
+candidate sweeps, the barrier gradient and PSD-projected Hessian with
+J^T H J assembly, the body terms, the PCG solve, CCD and the line search,
+each sub-scene with its own convergence test, CCD bound, line search and
+PCG scalars.  The timed steps follow --warmup steps from rest and include
+the first layers' landings.
 
 Printed JSON line: value = contact-pair evaluations per second (active
 pairs through the barrier kernels plus pairs through CCD, summed over
-every Newton iteration of the timed steps, divided by the timed
-wall-clock), plus Newton iterations per second, the roofline position of
-the dominant kernel (HIP events inside the library) and the CPU oracle's
-rate on a bounded sample.
+every Newton iteration of every scene in the timed steps, divided by the
+timed wall-clock), plus Newton iterations per second, the roofline
+position of the dominant kernel (HIP events inside the library; measured
+HBM traffic from the committed counter summary of the same command while
+the kernel's source is unchanged), the same library run one scene at a
+time on a sample of scenes, the CPU oracle's rate on a bounded sample of
+the same work, and shorter runs of the other two single-scene workloads.
 
-With --workload batched the step is one time step of 256 independent
-drop scenes (26,914 bodies, 2.27 M vertices) advanced together from rest,
-each sub-scene with its own convergence, CCD bound and line search; the
-line adds the same library run one scene at a time on a sample of evenly
-spaced scenes over the same steps, scaled by body count, and the speedup.
+Other workloads:
+    --workload box      the 1000-icosphere box drop (162,017 vertices,
+                        lagged friction), timed after the spheres landed
+    --workload chains   64 interlocked links in 8 chains (640,000
+                        vertices), dt 5e-3, dhat 5e-4
+    --workload adjoint  gradient of a position loss after --steps steps of
+                        the 500-icosphere drop w.r.t. the initial velocities
 
-    python bench.py [--steps K] [--warmup W] [--pre N]
-    python bench.py --workload batched --steps 40 [--loop-scenes 16]
-    python bench.py --workload adjoint --steps 100 [--checkpoint-every 10]
+    python bench.py [--steps K] [--warmup W] [--no-extras] [--no-cpu]
 """
 import argparse
 import json
@@ -57,21 +63,27 @@ ACCD_BYTES_PER_PAIR = 8 + 16 + 4 * 48
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--pre", type=int, default=60, help="untimed steps before warmup (spheres land)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batched: skip the short runs of the box-drop and chain workloads")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="batched: print the line right after the timed steps (no per-scene loop, extras or CPU "
+                         "baseline), so that a profiler sees nothing after them")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size (for counter calibration) before timing")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", choices=("box", "batched", "adjoint"), default="box",
-                    help="box: the 1000-icosphere box drop (default); batched: 256 independent drop scenes in one "
-                         "launch sequence, against a per-scene loop of the same library; adjoint: gradient of a "
-                         "position loss after --steps steps of the 500-icosphere drop w.r.t. the initial velocities")
+    ap.add_argument("--workload", choices=("batched", "box", "chains", "adjoint"), default="batched",
+                    help="batched: 256 independent drop scenes in one launch sequence, against a per-scene loop "
+                         "of the same library (default); box: the 1000-icosphere box drop; chains: 64 "
+                         "interlocked links; adjoint: gradient of a position loss after --steps steps of the "
+                         "500-icosphere drop w.r.t. the initial velocities")
     ap.add_argument("--adj-rtol", type=float, default=1e-8, help="adjoint: PCG relative residual of the adjoint solves")
     ap.add_argument("--checkpoint-every", type=int, default=10)
-    ap.add_argument("--loop-scenes", type=int, default=16,
+    ap.add_argument("--loop-scenes", type=int, default=8,
                     help="batched: scenes (evenly spaced) run one at a time for the per-scene baseline")
     ap.add_argument("--start-at", type=float, default=0.0,
                     help="start the timed steps this many seconds after process start (so a profiler's "
@@ -84,34 +96,77 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seconds):
-    """The oracle's pair work (barrier gradient + PSD Hessian + J^T H J on the
-    candidates, additive CCD on the swept candidates) on the resting bottom
-    layer of the same scene, repeated for about `seconds`."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def batched_sample(S, P, n_pick=16):
+    """n_pick evenly spaced scenes of the batch at the landing of their
+    lowest layer (the CPU baseline's sample)."""
+    n_sc = len(S["scene_body_off"]) - 1
+    pick = np.linspace(0, n_sc - 1, min(n_pick, n_sc)).round().astype(int)
+    return ([sg.landed(sg.sub_scene(S, int(k)), seed=1000 + int(k), dhat=P["dhat"]) for k in pick],
+            f"{len(pick)} evenly spaced scenes of the batch")
+
+
+def cpu_baseline(seconds, scenes, P):
+    """The oracle (OpenMP over pairs and bodies, all host threads) doing the
+    same work as the GPU step on a bounded sample of it: whole Newton
+    iterations (incremental potential with barrier gradient and projected
+    Hessian, direct solve, swept candidates, CCD, line search) of the
+    sampled scenes at the moment their lowest layer lands (bodies
+    U[0.2,0.8] dhat above the ground, moving down at 1 m/s), repeated until
+    about `seconds` have passed.  value = (active barrier pairs + CCD
+    pairs) / wall time of those iterations, the GPU value's definition;
+    pair_work_only divides the same pairs by the time of the barrier and
+    CCD calls alone."""
     import oracle
-    S, P = sg.icosphere_resting_layer(dhat=1e-3)
-    x = oracle.vertex_map(S, S["q0"])
-    q1 = sg.random_state(S, 9, rot_angle=0.05, shift=0.0)
-    q1[1:, 1] -= 4e-3
-    x1 = oracle.vertex_map(S, q1)
-    pt, ee = oracle.candidates(S, x, None, P["dhat"])
-    keys = oracle.off_keys(S, pt, ee)
-    spt, see = oracle.candidates(S, x, x1, P["dhat"])
-    pairs = 0
-    reps = 0
+    scenes, what = scenes
+    work = []
+    for Sk in scenes:
+        Bk = oracle.Body(Sk)
+        qt = oracle.q_tilde(Sk, Sk["q0"], Sk["qd0"], P)
+        work.append((Sk, Bk, qt, oracle.step_friction(Sk, Sk["q0"], P)))
+    pairs, iters, reps, el = 0, 0, 0, 0.0
     t0 = time.perf_counter()
-    while True:
-        r = oracle.barrier(S, x, pt, ee, P, keys, project=True)
-        oracle.ccd(S, x, x1 - x, spt, see, P)
-        pairs += r["n_active"] + len(spt) + len(see)
+    while el < seconds:
+        for Sk, Bk, qt, F in work:
+            _, conv, info = oracle.newton_iteration(Sk, Bk, Sk["q0"], qt, P, F)
+            pairs += info["n_active"] + info.get("n_pt_swept", 0) + info.get("n_ee_swept", 0)
+            iters += 1
         reps += 1
         el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return dict(value=pairs / el, unit="pair evals/s", cores=1, kind="oracle",
-                sample=f"bottom layer of the icosphere box resting within dhat of the floor: "
-                       f"{r['n_active']} active barrier pairs + {len(spt) + len(see)} CCD pairs, "
-                       f"repeated {reps}x in {el:.1f} s, single thread")
+    # the pair work alone (barrier + CCD calls on the same pairs), one pass
+    pw_pairs, pw_t = 0, 0.0
+    for Sk, Bk, qt, F in work:
+        q = Sk["q0"]
+        x = oracle.vertex_map(Sk, q)
+        pt, ee = oracle.candidates(Sk, x, None, P["dhat"])
+        keys = oracle.off_keys(Sk, pt, ee)
+        gh = oracle.grad_hess(Sk, Bk, q, qt, P, x=x, pt=pt, ee=ee, F=F)
+        p = oracle.solve(Sk, gh["diag"], gh["off"], gh["keys"], -gh["grad"])
+        x1 = oracle.vertex_map(Sk, q + p)
+        spt, see = oracle.candidates(Sk, x, x1, P["dhat"])
+        t1 = time.perf_counter()
+        r = oracle.barrier(Sk, x, pt, ee, P, keys, project=True)
+        oracle.ccd(Sk, x, x1 - x, spt, see, P)
+        pw_t += time.perf_counter() - t1
+        pw_pairs += r["n_active"] + len(spt) + len(see)
+    return dict(value=pairs / el, unit="pair evals/s", cores=oracle.threads(), kind="oracle",
+                cpu_model=_cpu_model(), newton_iters_per_s=iters / el,
+                pair_work_only={"value": pw_pairs / pw_t if pw_t > 0 else 0.0,
+                                "denominator": "time of the oracle's barrier and CCD calls only"},
+                sample=f"{what} ({sum(len(w[0]['q0']) for w in work)} "
+                       f"bodies) at the landing of their lowest layer: one Newton iteration each, repeated "
+                       f"{reps}x ({iters} iterations, {pairs} pair evaluations) in {el:.1f} s on "
+                       f"{oracle.threads()} OpenMP threads")
 
 
 def roofline(ks):
@@ -149,11 +204,32 @@ def roofline(ks):
     return roof, pair_kernels
 
 
-# HBM bytes per PCG graph replay measured on the default box-drop timed
-# steps with rocprofv3 FETCH_SIZE and WRITE_SIZE (k_cg_iter + k_cg_advance,
-# each counter scaled by what it reads for a 512 MiB device copy); valid for
-# the k_cg_iter the measurement was taken on
-PCG_ROUND_TRAFFIC = 330.3e6
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summaries (profiles/*.md, a line
+    `bench-traffic: kernel=K workload=W bytes_per_launch=B sources=F1,F2
+    sha256=H`), or None when there is none or when the kernel's sources
+    have changed since the counters were taken (H is the SHA-256 of the
+    listed source files' contents, concatenated in order)."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("bench-traffic:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if kv.get("kernel") != kernel or kv.get("workload") != workload:
+                    continue
+                h = hashlib.sha256()
+                for src in kv.get("sources", "").split(","):
+                    with open(os.path.join(ROOT, src), "rb") as g:
+                        h.update(g.read())
+                if h.hexdigest() != kv.get("sha256"):
+                    return None, f"{os.path.basename(path)}: sources changed since the counters were taken"
+                return float(kv["bytes_per_launch"]), os.path.basename(path)
+    return None, "no counter summary for this kernel and workload"
+
 
 KERNELS = ("pcg_round", "barrier_local", "accd", "assemble_chunks", "pair_tiles_write", "energy_only",
            "friction_local")
@@ -230,7 +306,17 @@ def line_common(args, wall, tot, ks, steps):
     }
 
 
-def run_box(args):
+def attach_traffic(line, workload):
+    roof = line["roofline"]
+    kname = "pcg_round" if roof["kernel"].startswith("pcg_round") else roof["kernel"]
+    t, src = measured_traffic(kname, workload)
+    roof["traffic"] = t
+    roof["traffic_source"] = src
+
+
+def box_line(args, pre, warmup, steps, quiet=False):
+    """The 1000-icosphere box drop: `pre` untimed steps (the spheres land),
+    `warmup` more, then `steps` timed steps."""
     import torch
 
     import paper_2201_10022_amd as abd
@@ -242,29 +328,70 @@ def run_box(args):
     qd = torch.as_tensor(S["qd0"], device="cuda:0")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.pre):
+    for i in range(pre):
         st = ctx.time_step(sc, P, q, qd)
-        if i % 10 == 0:
-            log(args, f"pre {i}: newton {st['newton_iters']} active {st['n_active_pt'] + st['n_active_ee']} "
+        if i % 10 == 0 and not quiet:
+            log(args, f"box pre {i}: newton {st['newton_iters']} active {st['n_active_pt'] + st['n_active_ee']} "
                       f"swept {st['n_pt_swept'] + st['n_ee_swept']} pcg {st['pcg_iters']} "
                       f"{time.perf_counter() - t0:.1f}s")
-    for i in range(args.warmup):
+    for i in range(warmup):
         ctx.time_step(sc, P, q, qd)
     torch.cuda.synchronize()
-    wait_start(args)
-    calib_copy(args)
-    wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, args.steps)
-    line = line_common(args, wall, tot, ks, args.steps)
-    if (args.pre, args.warmup, args.steps) == (60, 2, 5) and line["roofline"]["kernel"].startswith("pcg_round"):
-        # HBM bytes per replay over these timed steps (rocprofv3 FETCH_SIZE and
-        # WRITE_SIZE of k_cg_iter + k_cg_advance, scaled by a 512 MiB copy)
-        line["roofline"]["traffic"] = PCG_ROUND_TRAFFIC
+    wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, steps)
+    ctx.close()
+    line = line_common(args, wall, tot, ks, steps)
+    line["warmup"] = warmup
     line["config"] = {"workload": "icosphere box drop: 1000 icospheres (subdivision 2) + fixed 12-quad box, "
                                   f"dt 1e-2, dhat 1e-3, lagged friction mu {P['mu']}",
                       "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])), "tris": int(len(S["tris"])),
-                      "edges": int(len(S["edges"])), "pre_steps": args.pre}
+                      "edges": int(len(S["edges"])), "pre_steps": pre}
+    line["steps_per_s"] = steps / wall
+    attach_traffic(line, "box")
+    return line
+
+
+def chains_line(args, warmup, steps):
+    """The chain workload from its initial state: `warmup` untimed steps,
+    then `steps` timed steps."""
+    import torch
+
+    import paper_2201_10022_amd as abd
+
+    S, P = sg.torus_chains()
+    ctx, sc = abd.setup(S, 0)
+    q = torch.as_tensor(S["q0"], device="cuda:0")
+    qd = torch.as_tensor(S["qd0"], device="cuda:0")
+    for i in range(warmup):
+        ctx.time_step(sc, P, q, qd)
+    torch.cuda.synchronize()
+    wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, steps)
+    ctx.close()
+    line = line_common(args, wall, tot, ks, steps)
+    line["warmup"] = warmup
+    line["config"] = {"workload": "interlocked chains: 8 chains x 8 links (major 0.3, minor 0.1, 200 x 50 "
+                                  "grid, stadium links), end links fixed, dt 5e-3, dhat 5e-4, frictionless",
+                      "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])), "tris": int(len(S["tris"])),
+                      "edges": int(len(S["edges"]))}
+    line["steps_per_s"] = steps / wall
+    attach_traffic(line, "chains")
+    return line
+
+
+def run_box(args):
+    wait_start(args)
+    calib_copy(args)
+    line = box_line(args, args.pre, args.warmup, args.steps)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        S, P = sg.icosphere_box(n_layers=2)
+        sample = ([sg.landed(S, seed=1000, dhat=P["dhat"])], "the box drop's lowest 2 of 10 layers (200 spheres)")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, sample, P)
+    print(json.dumps(line), flush=True)
+
+
+def run_chains(args):
+    wait_start(args)
+    calib_copy(args)
+    line = chains_line(args, args.warmup, args.steps)
     print(json.dumps(line), flush=True)
 
 
@@ -287,9 +414,20 @@ def run_batched(args):
         ctx.time_step(sc, P, q, qd)
     torch.cuda.synchronize()
     wait_start(args)
+    calib_copy(args)
     wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, steps)
     log(args, f"batched: {steps} steps in {wall:.2f} s, scene Newton iterations {tot['scene_newton']}")
     ctx.close()
+    line = line_common(args, wall, tot, ks, steps)
+    line["config"] = {"workload": "batched drops: 256 scenes of 2..200 cubes/icospheres over a fixed ground quad, "
+                                  "dt 1e-2, dhat 1e-3, frictionless; timed steps follow the warm-up from rest",
+                      "scenes": n_sc, "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])),
+                      "tris": int(len(S["tris"])), "edges": int(len(S["edges"]))}
+    line["steps_per_s"] = steps / wall
+    attach_traffic(line, "batched")
+    if args.timed_only:
+        print(json.dumps(line), flush=True)
+        return
     # per-scene loop on a sample of scenes
     pick = np.linspace(0, n_sc - 1, max(1, min(args.loop_scenes, n_sc))).round().astype(int)
     loop_wall, loop_newton, loop_bodies = 0.0, 0, 0
@@ -310,16 +448,21 @@ def run_batched(args):
         loop_bodies += len(Sk["q0"])
         ck.close()
     scale = len(S["q0"]) / loop_bodies  # by body count of the sample
-    line = line_common(args, wall, tot, ks, steps)
-    line["config"] = {"workload": "batched drops: 256 scenes of 2..200 cubes/icospheres over a fixed ground quad, "
-                                  "dt 1e-2, dhat 1e-3, frictionless; timed steps follow the warm-up from rest",
-                      "scenes": n_sc, "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])),
-                      "tris": int(len(S["tris"])), "edges": int(len(S["edges"]))}
     line["per_scene_loop"] = {
         "sampled_scenes": [int(k) for k in pick], "sample_bodies": int(loop_bodies),
         "sample_wall_s": loop_wall, "sample_newton_iters": int(loop_newton),
         "scaled_wall_s": loop_wall * scale, "scale": "total bodies / sampled bodies",
         "speedup": loop_wall * scale / wall}
+    if not args.no_extras:
+        log(args, "extra: box drop")
+        bl = box_line(args, 60, 2, 5, quiet=True)
+        log(args, "extra: chains")
+        cl = chains_line(args, 2, 5)
+        keep = ("value", "unit", "ms_per_step", "steps_per_s", "newton_iters_per_s", "newton_iters", "steps",
+                "warmup", "pair_evals", "pcg_iters", "roofline", "pair_kernels", "config")
+        line["other_configs"] = {"box": {k: bl[k] for k in keep}, "chains": {k: cl[k] for k in keep}}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, batched_sample(S, P), P)
     print(json.dumps(line), flush=True)
 
 
@@ -378,6 +521,8 @@ def main():
         run_batched(args)
     elif args.workload == "adjoint":
         run_adjoint(args)
+    elif args.workload == "chains":
+        run_chains(args)
     else:
         run_box(args)
 

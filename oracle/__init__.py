@@ -86,8 +86,14 @@ def lib():
         L.ora_pair_local.restype = ctypes.c_int
         L.ora_pair_distance.argtypes = [ctypes.c_int, _d, _int]
         L.ora_pair_distance.restype = ctypes.c_double
+        L.ora_threads.restype = ctypes.c_int
         _LIB = L
     return _LIB
+
+
+def threads():
+    """Threads the oracle's parallel loops use."""
+    return int(lib().ora_threads())
 
 
 def _p(a, t):

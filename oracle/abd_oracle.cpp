@@ -23,6 +23,8 @@
 #include <cstring>
 #include <vector>
 
+#include <omp.h>
+
 namespace {
 
 // ---------------------------------------------------------------- jets ----
@@ -444,6 +446,9 @@ int find_off(const int32_t* keys, int64_t n_off, int a, int b) {
 }  // namespace
 
 extern "C" {
+
+// Threads the parallel loops below run on (OpenMP's current maximum).
+int ora_threads() { return omp_get_max_threads(); }
 
 // Mass properties (ABD, kinetic energy section, Eq. mass): M = int rho J^T J,
 // needing m = int rho, the first moment h = int rho xbar and the second

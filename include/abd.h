@@ -191,6 +191,22 @@ int abd_barrier_grad_hess(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
 int abd_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                        int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy, hipStream_t stream);
 
+/* Barrier energy only, allocating nothing: for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same kernels, same summation
+ * order and same result as abd_barrier_energy (accumulates into energy [1]),
+ * but its scratch (per-pair energies and the reduction's partials) is a
+ * fixed array in the library, one per GPU, held until the process ends:
+ * n_pt + n_ee <= ABD_NOALLOC_MAX_PAIRS, else ABD_E_CAPACITY and nothing is
+ * launched.  Calls on one GPU share that array, so calls that overlap on
+ * one GPU (different streams or threads) race; serialise them.  Calls no
+ * hipMalloc, hipFree or allocating library routine, and records no
+ * profiling events. */
+#define ABD_NOALLOC_MAX_PAIRS (1 << 20)
+int abd_barrier_energy_noalloc(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
+                               const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy,
+                               hipStream_t stream);
+
 /* CCD step bound (sec. 4.1: linear trajectories x0 + t dx, additive CCD):
  * per pair a conservative safe fraction t in [0, ccd_tmax] (t_pt [n_pt],
  * t_ee [n_ee], either may be NULL) and alpha [n_scenes] = min(1, min t)

@@ -190,6 +190,17 @@ class Context:
                                               pt.shape[0], _ptr(ee), ee.shape[0], _ptr(energy), _stream()))
         return energy
 
+    def barrier_energy_noalloc(self, scene, params, x, pt, ee, energy=None):
+        """abd_barrier_energy_noalloc: accumulates into `energy` (a float64
+        [1] device tensor; a new zero one when None)."""
+        if energy is None:
+            energy = torch.zeros(1, dtype=torch.float64, device=x.device)
+        prm = make_params(params)
+        self._check(self.L.abd_barrier_energy_noalloc(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(x),
+                                                      _ptr(pt), pt.shape[0], _ptr(ee), ee.shape[0], _ptr(energy),
+                                                      _stream()))
+        return energy
+
     def ccd_max_step(self, scene, params, x0, dx, pt, ee, per_pair=True):
         """(t_pt, t_ee, alpha); per_pair=False asks for the bound alone
         (t_pt, t_ee are then None)."""

@@ -13,6 +13,7 @@ ERRORS = {-1: "ABD_E_INVALID", -2: "ABD_E_CAPACITY", -3: "ABD_E_INTERSECT", -4: 
 EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_body_mass", "abd_vertex_map", "abd_candidates",
            "abd_candidates_within",
            "abd_offdiag_pattern", "abd_classify", "abd_barrier_grad_hess", "abd_barrier_energy",
+           "abd_barrier_energy_noalloc",
            "abd_ccd_max_step", "abd_orthogonality", "abd_inertia", "abd_q_tilde", "abd_pcg_solve",
            "abd_newton_step", "abd_time_step", "abd_friction_lag", "abd_friction_grad_hess",
            "abd_friction_energy", "abd_friction_begin_step", "abd_friction_end_step", "abd_adjoint_step",
@@ -70,6 +71,7 @@ SIGNATURES = {
     "abd_barrier_grad_hess": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp,
                                ctypes.c_int, _vp], ctypes.c_int),
     "abd_barrier_energy": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "abd_barrier_energy_noalloc": ([_vp, _PS, _PP, _vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
     "abd_ccd_max_step": ([_vp, _PS, _PP, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
     "abd_orthogonality": ([_vp, _PS, _PP, _vp, _dbl, _vp, _vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
     "abd_inertia": ([_vp, _PS, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),

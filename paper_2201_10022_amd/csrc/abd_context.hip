@@ -375,22 +375,40 @@ __global__ void __launch_bounds__(R1) k_reduce1(const double *in, int64_t n, dou
   }
 }
 
-template <int OP>
-int reduce_f64(abd_ctx *ctx, const double *in, int64_t n, double init, double *out, int accumulate, hipStream_t s) {
-  if (n <= 16 * R1) {
-    hipLaunchKernelGGL(k_reduce1<OP>, dim3(1), dim3(R1), 0, s, in, n, init, out, accumulate);
-    return ABD_OK;
-  }
+// partial blocks of the two-pass form (n > 16 R1)
+int reduce_blocks(int64_t n) {
   int nblk = (int)((n + RB * 4 - 1) / (RB * 4));
   if (nblk < 1) nblk = 1;
-  if (nblk > 1024) nblk = 1024;
-  double *part;
-  ABD_TRY(ws(ctx, OP == 0 ? "red_sum" : "red_min", nblk, &part, s));
+  if (nblk > REDUCE_MAX_PARTS) nblk = REDUCE_MAX_PARTS;
+  return nblk;
+}
+
+// the launches of a reduction; part holds reduce_blocks(n) doubles (unused
+// for n <= 16 R1)
+template <int OP>
+void reduce_launch(const double *in, int64_t n, double init, double *part, double *out, int accumulate,
+                   hipStream_t s) {
+  if (n <= 16 * R1) {
+    hipLaunchKernelGGL(k_reduce1<OP>, dim3(1), dim3(R1), 0, s, in, n, init, out, accumulate);
+    return;
+  }
+  const int nblk = reduce_blocks(n);
   hipLaunchKernelGGL(k_reduce_pass<OP>, dim3(nblk), dim3(RB), 0, s, in, n, init, part);
   hipLaunchKernelGGL(k_reduce_final<OP>, dim3(1), dim3(RB), 0, s, part, nblk, init, out, accumulate);
+}
+
+template <int OP>
+int reduce_f64(abd_ctx *ctx, const double *in, int64_t n, double init, double *out, int accumulate, hipStream_t s) {
+  double *part = nullptr;
+  if (n > 16 * R1) ABD_TRY(ws(ctx, OP == 0 ? "red_sum" : "red_min", reduce_blocks(n), &part, s));
+  reduce_launch<OP>(in, n, init, part, out, accumulate, s);
   return ABD_OK;
 }
 }  // namespace
+
+void reduce_sum_f64_into(const double *in, int64_t n, double *part, double *out_accum, hipStream_t s) {
+  reduce_launch<0>(in, n, 0.0, part, out_accum, 1, s);
+}
 
 int reduce_sum_f64(abd_ctx *ctx, const double *in, int64_t n, double *out_accum, hipStream_t s) {
   return reduce_f64<0>(ctx, in, n, 0.0, out_accum, 1, s);
@@ -611,6 +629,7 @@ extern "C" int abd_create(abd_ctx **out, int device) {
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return ABD_E_HIP;
   if (device < 0 || device >= n) return ABD_E_INVALID;
   if (hipSetDevice(device) != hipSuccess) return ABD_E_HIP;
+  if (noalloc_scratch_init(device) != ABD_OK) return ABD_E_HIP;
   abd_ctx *c = new abd_ctx();
   c->device = device;
   for (auto &e : c->ev)

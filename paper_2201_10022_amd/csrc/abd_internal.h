@@ -459,6 +459,13 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Deterministic device-wide sums: per-block partials then one block folds them.
 int reduce_sum_f64(abd_ctx *ctx, const double *in, int64_t n, double *out_accum, hipStream_t s);
+// the same sum (same launches, same order) with the second pass's block
+// partials in caller memory of REDUCE_MAX_PARTS doubles; allocates nothing
+constexpr int REDUCE_MAX_PARTS = 1024;
+void reduce_sum_f64_into(const double *in, int64_t n, double *part, double *out_accum, hipStream_t s);
+// once per device, with the device current: the device address of the
+// allocation-free entry point's scratch array (abd_narrow.hip)
+int noalloc_scratch_init(int device);
 int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, double *out, hipStream_t s);
 // Per-scene reductions of items whose scene keys are non-decreasing (bodies,
 // vertices and candidate pairs are all scene-contiguous): sums accumulate

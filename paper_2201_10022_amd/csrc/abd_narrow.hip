@@ -16,6 +16,8 @@
 // assembled matrix is bit-reproducible run to run.
 #include "abd_barrier_math.h"
 
+#include <mutex>
+
 namespace {
 using namespace abd_math;
 
@@ -510,6 +512,53 @@ extern "C" int abd_barrier_grad_hess(abd_ctx *ctx, const abd_scene *sc, const ab
     return abd_fail(ctx, ABD_E_INVALID, "abd_barrier_grad_hess: null");
   return op_barrier(ctx, sc, prm, x, pt, n_pt, ee, n_ee, keys, n_keys, energy, grad, diag, off, project_psd, nullptr,
                     nullptr, stream);
+}
+
+// ----------------------------------------- allocation-free barrier energy ----
+// Scratch of abd_barrier_energy_noalloc: the per-pair energies, then the
+// reduction's block partials.  One copy per GPU, held until the process
+// ends; every call on a GPU shares it, so calls that overlap on one GPU
+// race.  Host code uses the device address taken once per device below,
+// never the array's name.
+static __device__ __align__(256) double scratch[ABD_NOALLOC_MAX_PAIRS + REDUCE_MAX_PARTS];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return ABD_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return ABD_OK;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return ABD_E_HIP;
+  }
+  g_scratch[device] = static_cast<double *>(ptr);
+  return ABD_OK;
+}
+
+extern "C" int abd_barrier_energy_noalloc(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm,
+                                          const double *x, const int32_t *pt, int64_t n_pt, const int32_t *ee,
+                                          int64_t n_ee, double *energy, hipStream_t stream) {
+  if (!ctx || !sc || !prm || !x || !energy || n_pt < 0 || n_ee < 0 || (n_pt && !pt) || (n_ee && !ee))
+    return abd_fail(ctx, ABD_E_INVALID, "abd_barrier_energy_noalloc: null or negative count");
+  const int64_t n = n_pt + n_ee;
+  if (n > ABD_NOALLOC_MAX_PAIRS)
+    return abd_fail(ctx, ABD_E_CAPACITY, "abd_barrier_energy_noalloc: %lld pairs exceed the scratch capacity of %d",
+                    (long long)n, (int)ABD_NOALLOC_MAX_PAIRS);
+  if (n == 0) return ABD_OK;
+  double *scr = g_scratch[ctx->device];
+  if (!scr) return abd_fail(ctx, ABD_E_HIP, "abd_barrier_energy_noalloc: scratch address not set for this device");
+  // the kernels and the summation order of abd_barrier_energy
+  double *e = scr, *part = scr + ABD_NOALLOC_MAX_PAIRS;
+  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, 256)), dim3(256), 0, stream, n_pt, n, pt, ee, sc->tris,
+                     sc->edges, x, sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, nullptr);
+  reduce_sum_f64_into(e, n, part, energy, stream);
+  return abd_hip_check(ctx, hipGetLastError(), "abd_barrier_energy_noalloc");
 }
 
 extern "C" int abd_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,

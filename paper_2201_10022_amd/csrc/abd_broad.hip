@@ -49,47 +49,53 @@ __device__ __forceinline__ void vert_box(int64_t v, const double *x0, const doub
   }
 }
 
-// All boxes in one launch.  Blocks [0, nb): body boxes (min / max over the
-// body's vertex boxes); the blocks after them: one thread per vertex, then
-// per triangle, then per edge (a primitive box is the min / max of its
-// vertices' boxes, recomputed here rather than read back).
-__global__ void __launch_bounds__(256) k_boxes(int nb, const int32_t *voff, int nv, int nt, int ne,
-                                               const int32_t *tris, const int32_t *edges, const double *x0,
-                                               const double *x1, double inflate, double *vb, float *vb32, double *tb,
-                                               float *tb32, double *eb, float *eb32, double *bb) {
-  if ((int)blockIdx.x < nb) {
-    __shared__ double sh[6][4];
-    const int b = blockIdx.x;
-    double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int v = voff[b] + threadIdx.x; v < voff[b + 1]; v += 256) {
-      double vbx[6];
-      vert_box(v, x0, x1, inflate, vbx);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        m[i] = fmin(m[i], vbx[i]);
-        m[3 + i] = fmax(m[3 + i], vbx[3 + i]);
-      }
-    }
+// Body boxes (min / max over the body's vertex boxes), one block per body;
+// clears the body's mark of being in an overlapping body pair.
+__global__ void __launch_bounds__(256) k_body_boxes(const int32_t *voff, const double *x0, const double *x1,
+                                                    double inflate, double *bb, uint8_t *involved) {
+  __shared__ double sh[6][4];
+  const int b = blockIdx.x;
+  double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int v = voff[b] + threadIdx.x; v < voff[b + 1]; v += 256) {
+    double vbx[6];
+    vert_box(v, x0, x1, inflate, vbx);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      m[i] = wave_min(m[i]);
-      m[3 + i] = wave_max(m[3 + i]);
+      m[i] = fmin(m[i], vbx[i]);
+      m[3 + i] = fmax(m[3 + i], vbx[3 + i]);
     }
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-      for (int i = 0; i < 6; ++i) sh[i][threadIdx.x >> 6] = m[i];
-    __syncthreads();
-    if (threadIdx.x < 6) {
-      const int i = threadIdx.x;
-      double r = sh[i][0];
-      for (int w = 1; w < 4; ++w) r = i < 3 ? fmin(r, sh[i][w]) : fmax(r, sh[i][w]);
-      bb[6 * (int64_t)b + i] = r;
-    }
-    return;
   }
-  int64_t k = ((int64_t)blockIdx.x - nb) * 256 + threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    m[i] = wave_min(m[i]);
+    m[3 + i] = wave_max(m[3 + i]);
+  }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sh[i][threadIdx.x >> 6] = m[i];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int i = threadIdx.x;
+    double r = sh[i][0];
+    for (int w = 1; w < 4; ++w) r = i < 3 ? fmin(r, sh[i][w]) : fmax(r, sh[i][w]);
+    bb[6 * (int64_t)b + i] = r;
+  }
+  if (threadIdx.x == 0) involved[b] = 0;
+}
+
+// Vertex, triangle and edge boxes (double, and single precision rounded
+// outwards) of the bodies that are in at least one overlapping body pair;
+// the culling and pair tests read no other primitive's box.
+__global__ void __launch_bounds__(256) k_prim_boxes(int nv, int nt, int ne, const int32_t *vert_body,
+                                                    const int32_t *tri_body, const int32_t *edge_body,
+                                                    const uint8_t *involved, const int32_t *tris,
+                                                    const int32_t *edges, const double *x0, const double *x1,
+                                                    double inflate, double *vb, float *vb32, double *tb,
+                                                    float *tb32, double *eb, float *eb32) {
+  int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double box[6];
   if (k < nv) {
+    if (!involved[vert_body[k]]) return;
     vert_box(k, x0, x1, inflate, box);
 #pragma unroll
     for (int i = 0; i < 6; ++i) vb[6 * k + i] = box[i];
@@ -100,6 +106,7 @@ __global__ void __launch_bounds__(256) k_boxes(int nb, const int32_t *voff, int 
   const bool tri = k < nt;
   if (!tri) k -= nt;
   if (!tri && k >= ne) return;
+  if (!involved[tri ? tri_body[k] : edge_body[k]]) return;
   const int K = tri ? 3 : 2;
   const int32_t *prim = tri ? tris + 3 * k : edges + 2 * k;
   vert_box(prim[0], x0, x1, inflate, box);
@@ -197,9 +204,11 @@ __global__ void k_scene_end(int nb, const int32_t *body_scene, int32_t *end) {
 //   4: edges of a in box(b)      5: edges of b in box(a)
 // Capacity of each list = primitive count of its body; region offsets per
 // body pair from a scan of the summed capacities.  Runs over a buffer of
-// n_cap slots; slots at or beyond the body-pair count (device) get 0.
+// n_cap slots; slots at or beyond the body-pair count (device) get 0.  Also
+// marks both bodies of every pair as involved (their primitive boxes are
+// then computed).
 __global__ void k_list_caps(int64_t n_cap, const int64_t *nbp_dev, const int32_t *bpairs, const int32_t *voff,
-                            const int32_t *toff, const int32_t *eoff, int64_t *cap) {
+                            const int32_t *toff, const int32_t *eoff, int64_t *cap, uint8_t *involved) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_cap) return;
   if (p >= *nbp_dev) {
@@ -207,6 +216,8 @@ __global__ void k_list_caps(int64_t n_cap, const int64_t *nbp_dev, const int32_t
     return;
   }
   const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
+  involved[a] = 1;  // (every writer stores the same value)
+  involved[b] = 1;
   cap[p] = (int64_t)(voff[a + 1] - voff[a]) + (toff[b + 1] - toff[b]) + (voff[b + 1] - voff[b]) +
            (toff[a + 1] - toff[a]) + (eoff[a + 1] - eoff[a]) + (eoff[b + 1] - eoff[b]);
 }
@@ -417,9 +428,9 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_vbox32", 6 * (size_t)nv, &vbox32, s));
   ABD_TRY(ws(ctx, "bp_tbox32", 6 * (size_t)nt + 6, &tbox32, s));
   ABD_TRY(ws(ctx, "bp_ebox32", 6 * (size_t)ne + 6, &ebox32, s));
-  hipLaunchKernelGGL(k_boxes, dim3(nb + grid_for((int64_t)nv + nt + ne, 256)), dim3(256), 0, s, nb,
-                     sc->body_vert_off, nv, nt, ne, sc->tris, sc->edges, x0, x1, inflate, vbox, vbox32, tbox, tbox32,
-                     ebox, ebox32, bbox);
+  uint8_t *involved;
+  ABD_TRY(ws(ctx, "bp_involved", nb, &involved, s));
+  hipLaunchKernelGGL(k_body_boxes, dim3(nb), dim3(256), 0, s, sc->body_vert_off, x0, x1, inflate, bbox, involved);
   HIP_TRY(ctx, hipGetLastError());
 
   // body pairs
@@ -455,7 +466,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     hipLaunchKernelGGL(k_body_pairs<1>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
                        skip_scene, nullptr, boff, bpairs, cap_bp);
     hipLaunchKernelGGL(k_list_caps, dim3(grid_for(cap_bp, 256)), dim3(256), 0, s, cap_bp, btot, bpairs,
-                       sc->body_vert_off, sc->body_tri_off, sc->body_edge_off, cap);
+                       sc->body_vert_off, sc->body_tri_off, sc->body_edge_off, cap, involved);
     ABD_TRY(scan_exclusive_i64(ctx, cap, region, cap_bp, rtot, s, hbuf_d + 1));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     nbp = hbuf[0];
@@ -466,6 +477,11 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   }
   ctx->cap_hint[key_bp] = nbp;
   if (nbp == 0) return ABD_OK;
+  // primitive boxes of the bodies in overlapping pairs only
+  hipLaunchKernelGGL(k_prim_boxes, dim3(grid_for((int64_t)nv + nt + ne, 256)), dim3(256), 0, s, nv, nt, ne,
+                     sc->vert_body, sc->tri_body, sc->edge_body, involved, sc->tris, sc->edges, x0, x1, inflate, vbox,
+                     vbox32, tbox, tbox32, ebox, ebox32);
+  HIP_TRY(ctx, hipGetLastError());
 
   // culled primitive lists per body pair
   int32_t *lists, *llen;

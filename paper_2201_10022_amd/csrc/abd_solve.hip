@@ -793,11 +793,16 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
                                                 const double *w_in, const double *s_in, double *r_out, double *w_out,
                                                 double *s_out, double *x, double *u, double *p, const double *part_in,
                                                 double *part_out, CgState *st, CgScene scs, double rtol2,
-                                                int max_iter) {
+                                                int max_iter, int batch) {
   __shared__ double shf[SWBB][4], she[SWBB][3];
   const int k = st->base + jloc;
   const PcgBlk bi = blk[blockIdx.x];
   if (bi.sc < 0) return;
+  // In a batch, scenes stop at different iterations of a replay: a stopped
+  // scene's blocks leave before loading anything more.  (One scene: its
+  // stop comes once, at the end, so the flag is read with the other first
+  // loads instead of ahead of them.)
+  if (batch && scs.stop[bi.sc]) return;
   const int sc = bi.sc;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int slot = lane / 12, i = lane % 12;
@@ -1090,7 +1095,8 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
     for (int j = 0; j < n; ++j) {
       const int a = j & 1, o = a ^ 1;
       hipLaunchKernelGGL(k_cg_iter, dim3(nblk_s), dim3(SWB), 0, q, j, cblk, ent, sc->body_fixed, Bm, inv, rv[a],
-                         wv[a], sv[a], rv[o], wv[o], sv[o], x_out, u, p, pt[a], pt[o], st, scs, rtol2, max_iter);
+                         wv[a], sv[a], rv[o], wv[o], sv[o], x_out, u, p, pt[a], pt[o], st, scs, rtol2, max_iter,
+                         S > 1 ? 1 : 0);
     }
     // (n is even: the next replay's first iteration folds pt[0])
     if (S > 1) hipLaunchKernelGGL(k_cg_compact, dim3(1), dim3(CT), 0, q, cblk, nblk_s, pt[0], scs);

@@ -77,6 +77,16 @@ typedef struct abd_scene {
   const double *mass;           /* [n_bodies][10] from abd_body_mass (may be NULL
                                    for calls that do not use it) */
   const double *volume;         /* [n_bodies] from abd_body_mass */
+  /* Joints (sec. 5.3: q maps linearly to a virtual tetrahedron's vertices,
+   * which are material points, so fixing them is a linear equality):
+   * joint j makes body a's body-frame point coincide with body b's point
+   * (b = -1: with a fixed world point), enforced by the penalty
+   * dt^2 kappa_j / 2 |x_a - x_b|^2 in the incremental potential.  A hinge
+   * is two joints on its axis.  a and b in one sub-scene.  The arrays are
+   * read once per context and scene (they must not change while used). */
+  int32_t n_joints;
+  const int32_t *joint_body;    /* [n_joints][2] (a, b) */
+  const double *joint_point;    /* [n_joints][2][3] point of a; of b (world point when b = -1) */
 } abd_scene;
 
 /* Method parameters (host struct). */
@@ -92,6 +102,14 @@ typedef struct abd_params {
   double ccd_s;       /* ACCD gap fraction s */
   double ccd_tmax;    /* ACCD maximal step fraction */
   int32_t ccd_max_iter, max_newton, max_pcg, max_ls;
+  /* the body's rigidity potential, times kappa_o, the body volume and the
+   * weight (dt^2 in the incremental potential): 0 the orthogonality
+   * potential V_perp (Eq. ortho-energy, the paper's choice); 1 ARAP,
+   * |A - R(A)|_F^2 with R the polar rotation; 2 neo-Hookean with
+   * mu = lambda = 1, 1/2 (|A|_F^2 - 3) - ln J + 1/2 (ln J)^2, J = det A
+   * (infinite for J <= 0) -- the alternatives sec. 3.2 names */
+  int32_t rigidity;
+  double kappa_j;     /* joint penalty stiffness (N/m; used when the scene has joints) */
 } abd_params;
 
 /* Per-iteration statistics (host struct). */
@@ -159,8 +177,9 @@ int abd_candidates_within(abd_ctx *ctx, const abd_scene *sc, const double *x, do
                           int64_t *n_pt, int32_t *ee, int64_t cap_ee, int64_t *n_ee, hipStream_t stream);
 
 /* Off-diagonal block pattern of the global Hessian (sec. 4.3): sorted unique
- * body pairs (a < b, both free) touched by the given pairs.  keys:
- * [cap][2].  Syncs; *n_keys (host) receives the count. */
+ * body pairs (a < b, both free) touched by the given pairs and by the
+ * scene's joints between two bodies.  keys: [cap][2].  Syncs; *n_keys (host)
+ * receives the count (ABD_E_CAPACITY when it exceeds cap). */
 int abd_offdiag_pattern(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee,
                         int64_t n_ee, int32_t *keys, int64_t cap, int64_t *n_keys, hipStream_t stream);
 
@@ -216,10 +235,13 @@ int abd_ccd_max_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, c
                      const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *t_pt, double *t_ee,
                      double *alpha, hipStream_t stream);
 
-/* Orthogonality potential (Eq. orthogonality / ortho-energy / ortho-poly)
- * scaled by `weight` (dt^2 inside the incremental potential): energy [1],
- * grad [n_bodies][12], diag [n_bodies][144] accumulated; the 9x9 A-block of
- * the Hessian PSD-projected when project_psd != 0.  Fixed bodies skipped. */
+/* Orthogonality potential (Eq. orthogonality / ortho-energy / ortho-poly),
+ * or the alternative rigidity potential prm->rigidity selects (ARAP or
+ * neo-Hookean, sec. 3.2), scaled by `weight` (dt^2 inside the incremental
+ * potential): energy [1], grad [n_bodies][12], diag [n_bodies][144]
+ * accumulated; the 9x9 A-block of the Hessian PSD-projected when
+ * project_psd != 0.  grad and diag may both be NULL (energy only).  Fixed
+ * bodies skipped. */
 int abd_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,
                       double *energy, double *grad, double *diag, int project_psd, hipStream_t stream);
 
@@ -366,6 +388,37 @@ int abd_friction_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm
 int abd_friction_begin_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                             int64_t *n_pairs, hipStream_t stream);
 int abd_friction_end_step(abd_ctx *ctx);
+
+/* Launch shapes of the hot kernels (the autotuner's table).  No entry
+ * changes a result: every kernel computes the same values and lists pairs
+ * in the same order for any table.  Defaults {16, 1, 256, 1024, 256, 16, 64}.
+ *   tile_rows       rows per pair-culling tile (one wave): 8, 16, 32, 64
+ *   barrier_waves   waves per block of the barrier kernel: 1, 2, 4
+ *   ccd_block       threads per block of the CCD kernel: 64, 128, 256
+ *   ccd_max_blocks  grid cap of the persistent CCD kernel: 64 .. 16384
+ *   energy_block    threads per block of the energy-only kernel: 64 .. 1024 (powers of 2)
+ *   pcg_short, pcg_long  PCG iterations per short / long graph replay:
+ *                   even, 2 <= pcg_short <= pcg_long <= 256 */
+typedef struct {
+  int32_t tile_rows, barrier_waves, ccd_block, ccd_max_blocks, energy_block, pcg_short, pcg_long;
+} abd_tune;
+
+/* The context's launch-shape table: get, or set (ABD_E_INVALID for a value
+ * outside the sets above; the table is then unchanged). */
+int abd_tune_get(const abd_ctx *ctx, abd_tune *out);
+int abd_tune_set(abd_ctx *ctx, const abd_tune *in);
+
+/* Autotuner over the table above on the caller's workload: coordinate
+ * descent, one entry at a time in the order of the struct, keeping for each
+ * the value (among a fixed candidate set) whose n_steps time steps from the
+ * start state (q, qdot [n_bodies][12], device; restored before every trial
+ * run and on return) take the least host wall time between stream
+ * synchronisations, best of `reps` runs; an entry changes only when a
+ * candidate is faster by more than 1 %.  Leaves the picked table set in ctx
+ * and copies it to *out (host); *best_ms_per_step (host, may be NULL) gets
+ * its time per step.  Syncs.  Errors of the time steps are returned. */
+int abd_autotune(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, double *q, double *qdot, int n_steps,
+                 int reps, abd_tune *out, double *best_ms_per_step, hipStream_t stream);
 
 /* Kernel timing with HIP events on the calls' streams, for measurement:
  * abd_profile(enable, reset) switches recording on/off (reset clears the

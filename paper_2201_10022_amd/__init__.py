@@ -44,6 +44,8 @@ def make_params(p):
         out.gravity[i] = float(p["gravity"][i])
     for k in ("ccd_max_iter", "max_newton", "max_pcg", "max_ls"):
         setattr(out, k, int(p[k]))
+    out.rigidity = int(p.get("rigidity", 0))
+    out.kappa_j = float(p.get("kappa_j", 0.0))
     return out
 
 
@@ -73,6 +75,10 @@ class Scene:
         self.n_scenes = int(S["body_scene"].max()) + 1 if self.n_bodies else 0
         self.mass = torch.zeros((self.n_bodies, 10), dtype=torch.float64, device=dev)
         self.volume = torch.zeros(self.n_bodies, dtype=torch.float64, device=dev)
+        jb = S.get("joint_body")
+        self.n_joints = 0 if jb is None else len(jb)
+        self.joint_body = t(jb, torch.int32) if self.n_joints else None
+        self.joint_point = t(S["joint_point"], torch.float64) if self.n_joints else None
         self.c = self._struct()
 
     def _struct(self):
@@ -85,6 +91,10 @@ class Scene:
         for name in ("xbar", "vert_body", "tris", "tri_body", "edges", "edge_body", "body_vert_off", "body_tri_off",
                      "body_edge_off", "body_fixed", "body_scene", "mass", "volume"):
             setattr(s, name, getattr(self, name).data_ptr())
+        s.n_joints = self.n_joints
+        if self.n_joints:
+            s.joint_body = self.joint_body.data_ptr()
+            s.joint_point = self.joint_point.data_ptr()
         return s
 
 
@@ -153,7 +163,8 @@ class Context:
         return pt[:npt.value], ee[:nee.value]
 
     def offdiag_pattern(self, scene, pt, ee):
-        cap = pt.shape[0] + ee.shape[0] + 1
+        # (every pair, and every joint between two bodies, gives at most one key)
+        cap = pt.shape[0] + ee.shape[0] + scene.n_joints + 1
         keys = torch.empty((cap, 2), dtype=torch.int32, device=pt.device)
         n = ctypes.c_int64(0)
         self._check(self.L.abd_offdiag_pattern(self.h, ctypes.byref(scene.c), _ptr(pt), pt.shape[0], _ptr(ee),
@@ -214,12 +225,15 @@ class Context:
                                             _ptr(alpha), _stream()))
         return t_pt, t_ee, alpha
 
-    def orthogonality(self, scene, params, q, weight, project=True):
+    def orthogonality(self, scene, params, q, weight, project=True, hessian=True):
+        """The rigidity potential selected by params["rigidity"] (0 the
+        orthogonality potential); hessian=False: the energy alone (no
+        gradient or blocks: the energy-only kernel)."""
         nb = scene.n_bodies
         dev = q.device
         e = torch.zeros(1, dtype=torch.float64, device=dev)
-        g = torch.zeros((nb, 12), dtype=torch.float64, device=dev)
-        D = torch.zeros((nb, 144), dtype=torch.float64, device=dev)
+        g = torch.zeros((nb, 12), dtype=torch.float64, device=dev) if hessian else None
+        D = torch.zeros((nb, 144), dtype=torch.float64, device=dev) if hessian else None
         prm = make_params(params)
         self._check(self.L.abd_orthogonality(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q),
                                              float(weight), _ptr(e), _ptr(g), _ptr(D), int(project), _stream()))
@@ -348,6 +362,26 @@ class Context:
         return qbar, qdbar
 
     # -- measurement ---------------------------------------------------
+    # -- launch shapes -------------------------------------------------
+    def tune_get(self):
+        t = _lib.AbdTune()
+        self._check(self.L.abd_tune_get(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def tune_set(self, table):
+        t = _lib.AbdTune(**{k: int(v) for k, v in table.items()})
+        self._check(self.L.abd_tune_set(self.h, ctypes.byref(t)))
+
+    def autotune(self, scene, params, q, qd, n_steps=3, reps=2):
+        """abd_autotune on the workload (q, qd unchanged on return): the
+        picked table (also set in the context) and its ms per step."""
+        t = _lib.AbdTune()
+        ms = ctypes.c_double(0.0)
+        prm = make_params(params)
+        self._check(self.L.abd_autotune(self.h, ctypes.byref(scene.c), ctypes.byref(prm), _ptr(q), _ptr(qd),
+                                        int(n_steps), int(reps), ctypes.byref(t), ctypes.byref(ms), _stream()))
+        return t.as_dict(), ms.value
+
     def profile(self, enable=True, reset=True):
         self._check(self.L.abd_profile(self.h, int(enable), int(reset)))
 

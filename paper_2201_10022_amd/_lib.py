@@ -17,7 +17,8 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_body_mass", "abd_
            "abd_ccd_max_step", "abd_orthogonality", "abd_inertia", "abd_q_tilde", "abd_pcg_solve",
            "abd_newton_step", "abd_time_step", "abd_friction_lag", "abd_friction_grad_hess",
            "abd_friction_energy", "abd_friction_begin_step", "abd_friction_end_step", "abd_adjoint_step",
-           "abd_rollout_forward", "abd_rollout_backward", "abd_profile", "abd_profile_query"]
+           "abd_rollout_forward", "abd_rollout_backward", "abd_profile", "abd_profile_query",
+           "abd_tune_get", "abd_tune_set", "abd_autotune"]
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -31,14 +32,15 @@ class AbdScene(ctypes.Structure):
     _fields_ = [("n_bodies", _i32), ("n_verts", _i32), ("n_tris", _i32), ("n_edges", _i32), ("n_scenes", _i32),
                 ("xbar", _vp), ("vert_body", _vp), ("tris", _vp), ("tri_body", _vp), ("edges", _vp),
                 ("edge_body", _vp), ("body_vert_off", _vp), ("body_tri_off", _vp), ("body_edge_off", _vp),
-                ("body_fixed", _vp), ("body_scene", _vp), ("mass", _vp), ("volume", _vp)]
+                ("body_fixed", _vp), ("body_scene", _vp), ("mass", _vp), ("volume", _vp), ("n_joints", _i32),
+                ("joint_body", _vp), ("joint_point", _vp)]
 
 
 class AbdParams(ctypes.Structure):
     _fields_ = [("dt", _dbl), ("dhat", _dbl), ("kappa_b", _dbl), ("kappa_o", _dbl), ("mu", _dbl), ("eps_v", _dbl),
                 ("gravity", _dbl * 3), ("newton_tol", _dbl), ("pcg_rtol", _dbl), ("ccd_s", _dbl),
                 ("ccd_tmax", _dbl), ("ccd_max_iter", _i32), ("max_newton", _i32), ("max_pcg", _i32),
-                ("max_ls", _i32)]
+                ("max_ls", _i32), ("rigidity", _i32), ("kappa_j", _dbl)]
 
 
 class AbdStats(ctypes.Structure):
@@ -48,6 +50,14 @@ class AbdStats(ctypes.Structure):
                 ("alpha", _dbl), ("disp", _dbl), ("energy0", _dbl), ("energy1", _dbl), ("t_barrier_ms", _dbl),
                 ("t_ccd_ms", _dbl), ("t_candidates_ms", _dbl), ("t_solve_ms", _dbl), ("t_total_ms", _dbl),
                 ("n_friction", _i64), ("scene_newton_iters", _i64), ("newly_converged", _i32), ("pad_", _i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class AbdTune(ctypes.Structure):
+    _fields_ = [("tile_rows", _i32), ("barrier_waves", _i32), ("ccd_block", _i32), ("ccd_max_blocks", _i32),
+                ("energy_block", _i32), ("pcg_short", _i32), ("pcg_long", _i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +101,10 @@ SIGNATURES = {
     "abd_rollout_backward": ([_vp, _PS, _PP, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _dbl, _vp, _vp, _vp], ctypes.c_int),
     "abd_profile": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "abd_profile_query": ([_vp, ctypes.c_char_p, ctypes.POINTER(_dbl), _pi64, _pi64], ctypes.c_int),
+    "abd_tune_get": ([_vp, ctypes.POINTER(AbdTune)], ctypes.c_int),
+    "abd_tune_set": ([_vp, ctypes.POINTER(AbdTune)], ctypes.c_int),
+    "abd_autotune": ([_vp, _PS, _PP, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(AbdTune),
+                      ctypes.POINTER(_dbl), _vp], ctypes.c_int),
 }
 
 _LIB = None

@@ -49,14 +49,56 @@ __device__ __forceinline__ void vert_box(int64_t v, const double *x0, const doub
   }
 }
 
-// Body boxes (min / max over the body's vertex boxes), one block per body;
+// exact swept box of a primitive (kind 0 vertex, 1 triangle, 2 edge):
+// min / max of its vertices' boxes, the same arithmetic as a vertex's
+__device__ __forceinline__ void prim_box(int kind, int64_t i, const int32_t *tris, const int32_t *edges,
+                                         const double *x0, const double *x1, double inflate, double b[6]) {
+  if (kind == 0) {
+    vert_box(i, x0, x1, inflate, b);
+    return;
+  }
+  const int K = kind == 1 ? 3 : 2;
+  const int32_t *prim = kind == 1 ? tris + 3 * i : edges + 2 * i;
+  vert_box(prim[0], x0, x1, inflate, b);
+  for (int q = 1; q < K; ++q) {
+    double o[6];
+    vert_box(prim[q], x0, x1, inflate, o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      b[c] = fmin(b[c], o[c]);
+      b[3 + c] = fmax(b[3 + c], o[3 + c]);
+    }
+  }
+}
+
+// single-precision culling box of a primitive from its vertices' culling
+// boxes (rounding outwards is monotone, so this equals the primitive's exact
+// box rounded outwards)
+__device__ __forceinline__ void prim_box32(int kind, int64_t i, const int32_t *tris, const int32_t *edges,
+                                           const float *vb32, float b[6]) {
+  const int K = kind == 0 ? 1 : (kind == 1 ? 3 : 2);
+  const int32_t v0 = kind == 0 ? (int32_t)i : (kind == 1 ? tris[3 * i] : edges[2 * i]);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) b[c] = vb32[6 * (int64_t)v0 + c];
+  for (int q = 1; q < K; ++q) {
+    const int32_t v = kind == 1 ? tris[3 * i + q] : edges[2 * i + q];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      b[c] = fminf(b[c], vb32[6 * (int64_t)v + c]);
+      b[3 + c] = fmaxf(b[3 + c], vb32[6 * (int64_t)v + 3 + c]);
+    }
+  }
+}
+
+// Body boxes (min / max over the body's vertex boxes), one wave per body;
 // clears the body's mark of being in an overlapping body pair.
-__global__ void __launch_bounds__(256) k_body_boxes(const int32_t *voff, const double *x0, const double *x1,
-                                                    double inflate, double *bb, uint8_t *involved) {
-  __shared__ double sh[6][4];
-  const int b = blockIdx.x;
+__global__ void __launch_bounds__(256) k_body_boxes(int nb, const int32_t *voff, const double *x0,
+                                                    const double *x1, double inflate, double *bb,
+                                                    uint8_t *involved) {
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (b >= nb) return;  // (uniform over the wave)
   double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-  for (int v = voff[b] + threadIdx.x; v < voff[b + 1]; v += 256) {
+  for (int v = voff[b] + lane; v < voff[b + 1]; v += 64) {
     double vbx[6];
     vert_box(v, x0, x1, inflate, vbx);
 #pragma unroll
@@ -70,60 +112,27 @@ __global__ void __launch_bounds__(256) k_body_boxes(const int32_t *voff, const d
     m[i] = wave_min(m[i]);
     m[3 + i] = wave_max(m[3 + i]);
   }
-  if ((threadIdx.x & 63) == 0)
+  if (lane < 6) {
+    double r = m[0];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) sh[i][threadIdx.x >> 6] = m[i];
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    const int i = threadIdx.x;
-    double r = sh[i][0];
-    for (int w = 1; w < 4; ++w) r = i < 3 ? fmin(r, sh[i][w]) : fmax(r, sh[i][w]);
-    bb[6 * (int64_t)b + i] = r;
+    for (int i = 1; i < 6; ++i) r = lane == i ? m[i] : r;
+    bb[6 * (int64_t)b + lane] = r;
   }
-  if (threadIdx.x == 0) involved[b] = 0;
+  if (lane == 0) involved[b] = 0;
 }
 
-// Vertex, triangle and edge boxes (double, and single precision rounded
-// outwards) of the bodies that are in at least one overlapping body pair;
-// the culling and pair tests read no other primitive's box.
-__global__ void __launch_bounds__(256) k_prim_boxes(int nv, int nt, int ne, const int32_t *vert_body,
-                                                    const int32_t *tri_body, const int32_t *edge_body,
-                                                    const uint8_t *involved, const int32_t *tris,
-                                                    const int32_t *edges, const double *x0, const double *x1,
-                                                    double inflate, double *vb, float *vb32, double *tb,
-                                                    float *tb32, double *eb, float *eb32) {
-  int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// Single-precision culling boxes of the vertices of the bodies that are in
+// at least one overlapping body pair (triangle and edge boxes are formed
+// from them where the culling reads them; the exact pair test forms its
+// boxes from the positions).
+__global__ void __launch_bounds__(256) k_vert_boxes(int nv, const int32_t *vert_body, const uint8_t *involved,
+                                                    const double *x0, const double *x1, double inflate,
+                                                    float *vb32) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= nv || !involved[vert_body[k]]) return;
   double box[6];
-  if (k < nv) {
-    if (!involved[vert_body[k]]) return;
-    vert_box(k, x0, x1, inflate, box);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) vb[6 * k + i] = box[i];
-    store_box32(vb32 + 6 * k, box);
-    return;
-  }
-  k -= nv;
-  const bool tri = k < nt;
-  if (!tri) k -= nt;
-  if (!tri && k >= ne) return;
-  if (!involved[tri ? tri_body[k] : edge_body[k]]) return;
-  const int K = tri ? 3 : 2;
-  const int32_t *prim = tri ? tris + 3 * k : edges + 2 * k;
-  vert_box(prim[0], x0, x1, inflate, box);
-  for (int q = 1; q < K; ++q) {
-    double o[6];
-    vert_box(prim[q], x0, x1, inflate, o);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      box[i] = fmin(box[i], o[i]);
-      box[3 + i] = fmax(box[3 + i], o[3 + i]);
-    }
-  }
-  double *out = tri ? tb : eb;
-  float *out32 = tri ? tb32 : eb32;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) out[6 * k + i] = box[i];
-  store_box32(out32 + 6 * k, box);
+  vert_box(k, x0, x1, inflate, box);
+  store_box32(vb32 + 6 * k, box);
 }
 
 // body pairs (a < b) in one sub-scene, not both fixed, boxes overlapping.
@@ -222,18 +231,18 @@ __global__ void k_list_caps(int64_t n_cap, const int64_t *nbp_dev, const int32_t
            (toff[a + 1] - toff[a]) + (eoff[a + 1] - eoff[a]) + (eoff[b + 1] - eoff[b]);
 }
 
-constexpr int TROWS = 16;
 
 // One wave per body pair p and sub-problem sub (0: a's vertices x b's
 // triangles, 1: b's vertices x a's triangles, 2: a's edges x b's edges):
 // the two lists of primitives inside the other body's box (kinds 2 sub and
 // 2 sub + 1), each in index order by ballot compaction in chunks of 64,
-// then the sub-problem's tile count (TROWS rows x all columns per tile).
+// then the sub-problem's tile count (trows rows x all columns per tile).
 __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const int64_t *region,
                                                     const int32_t *voff, const int32_t *toff, const int32_t *eoff,
-                                                    const double *bb, const float *vbox, const float *tbox,
-                                                    const float *ebox, int32_t *lists, int64_t *list_start,
-                                                    int32_t *list_len, int64_t *tiles_pt, int64_t *tiles_ee) {
+                                                    const double *bb, const float *vb32, const int32_t *tris,
+                                                    const int32_t *edges, int32_t *lists, int64_t *list_start,
+                                                    int32_t *list_len, int64_t *tiles_pt, int64_t *tiles_ee,
+                                                    int trows) {
   const int64_t p = blockIdx.x;
   const int sub = blockIdx.y;
   const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
@@ -249,7 +258,7 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
     const int own = (kind == 0 || kind == 3 || kind == 4) ? a : b;
     const int oth = own == a ? b : a;
     const int32_t *offs = (kind == 0 || kind == 2) ? voff : (kind == 1 || kind == 3) ? toff : eoff;
-    const float *boxes = (kind == 0 || kind == 2) ? vbox : (kind == 1 || kind == 3) ? tbox : ebox;
+    const int pk = (kind == 0 || kind == 2) ? 0 : (kind == 1 || kind == 3) ? 1 : 2;  // vertex, triangle, edge
     // start of this list inside the body pair's region
     int64_t start = region[p];
     for (int k = 0; k < kind; ++k) start += caps[k];
@@ -259,7 +268,12 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
     int total = 0;
     for (int c0 = offs[own]; c0 < offs[own + 1]; c0 += 64) {
       const int i = c0 + lane;
-      const bool ok = i < offs[own + 1] && box_overlap32(boxes + 6 * (int64_t)i, ob);
+      bool ok = false;
+      if (i < offs[own + 1]) {
+        float fb[6];
+        prim_box32(pk, i, tris, edges, vb32, fb);
+        ok = box_overlap32(fb, ob);
+      }
       const unsigned long long m = __ballot(ok);
       if (ok) lists[start + total + __popcll(m & ((1ull << lane) - 1ull))] = i;
       total += __popcll(m);
@@ -271,7 +285,7 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
     len[h] = total;
   }
   if (lane == 0) {
-    const int64_t t = len[1] > 0 ? (len[0] + TROWS - 1) / TROWS : 0;
+    const int64_t t = len[1] > 0 ? (len[0] + trows - 1) / trows : 0;
     if (sub < 2)
       tiles_pt[2 * p + sub] = t;
     else
@@ -295,7 +309,7 @@ __global__ void k_tile_sub(int64_t nbp, const int64_t *cnt, const int64_t *off, 
   for (int64_t t = 0; t < cnt[j] && o + t < cap; ++t) ts[o + t] = make_int2(sub, (int)t);
 }
 
-// One wave per tile of TROWS rows x all columns.  WRITE=0 counts the
+// One wave per tile of trows (<= 64) rows x all columns.  WRITE=0 counts the
 // passing tests of the tile, WRITE=1 writes them row-major at the tile's
 // offset.  is_ee selects the sub-problem family.  The tile's row boxes
 // (one per lane) and the lane's boxes of the first CPRE column chunks are
@@ -305,8 +319,11 @@ constexpr int CPRE = 8;
 template <int WRITE>
 __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *tile_sub, int64_t n_tiles,
                                           const int64_t *list_start, const int32_t *list_len, const int32_t *lists,
-                                          const double *row_boxes, const double *col_boxes, int64_t *tile_cnt,
-                                          int64_t pos0, int32_t *out, int64_t n_tiles_valid) {
+                                          const int32_t *tris, const int32_t *edges, const double *x0,
+                                          const double *x1, double inflate, int64_t *tile_cnt, int64_t pos0,
+                                          int32_t *out, int64_t n_tiles_valid, int trows) {
+  // rows: vertices (PT) or edges (EE); columns: triangles (PT) or edges (EE)
+  const int rk = is_ee ? 2 : 0, ck = is_ee ? 2 : 1;
   // (the count pass runs over a capacity: tiles beyond the device count
   // record 0 so that the scan over the capacity stays exact)
   if (!WRITE && tile < n_tiles && tile >= n_tiles_valid) {
@@ -320,11 +337,11 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
   const int li = is_ee ? 4 : 2 * (int)(s % 2);
   const int64_t rstart = list_start[6 * p + li], cstart = list_start[6 * p + li + 1];
   const int nr = list_len[6 * p + li], nc = list_len[6 * p + li + 1];
-  const int r0 = ts.y * TROWS;
-  const int r1 = min(nr, r0 + TROWS);
+  const int r0 = ts.y * trows;
+  const int r1 = min(nr, r0 + trows);
   const int lane = threadIdx.x;
   const int nch = (nc + 63) / 64;
-  // row r0 + lane (lanes < TROWS) and the lane's first CPRE column chunks
+  // row r0 + lane (lanes < trows) and the lane's first CPRE column chunks
   int my_rp = 0;
   double my_rb[6];
   if (r0 + lane < r1) my_rp = lists[rstart + r0 + lane];
@@ -335,12 +352,21 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
     const int c = 64 * k + lane;
     cpv[k] = c < nc ? lists[cstart + c] : -1;
   }
+  if (r0 + lane < r1) {
+    prim_box(rk, my_rp, tris, edges, x0, x1, inflate, my_rb);
+  } else {
 #pragma unroll
-  for (int i = 0; i < 6; ++i) my_rb[i] = r0 + lane < r1 ? row_boxes[6 * (int64_t)my_rp + i] : 0.0;
+    for (int i = 0; i < 6; ++i) my_rb[i] = 0.0;
+  }
 #pragma unroll
-  for (int k = 0; k < CPRE; ++k)
+  for (int k = 0; k < CPRE; ++k) {
+    if (cpv[k] >= 0) {
+      prim_box(ck, cpv[k], tris, edges, x0, x1, inflate, cb[k]);
+    } else {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) cb[k][i] = cpv[k] >= 0 ? col_boxes[6 * (int64_t)cpv[k] + i] : 0.0;
+      for (int i = 0; i < 6; ++i) cb[k][i] = 0.0;
+    }
+  }
   int64_t pos = WRITE ? pos0 : 0;
   int64_t cnt = 0;
   for (int r = r0; r < r1; ++r) {
@@ -368,7 +394,9 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
       bool ok = false;
       if (c < nc) {
         cp = lists[cstart + c];
-        ok = box_overlap(rb, col_boxes + 6 * (int64_t)cp);
+        double cbx[6];
+        prim_box(ck, cp, tris, edges, x0, x1, inflate, cbx);
+        ok = box_overlap(rb, cbx);
       }
       const unsigned long long m = __ballot(ok);
       if (WRITE && ok) {
@@ -394,19 +422,20 @@ __global__ void __launch_bounds__(64) k_pair_tiles(int64_t nbp, int64_t n_pt_blo
                                                    int64_t cap_pt, const int2 *tsub_pt, const int2 *tsub_ee,
                                                    const int64_t *toff, const int64_t *ttotal,
                                                    const int64_t *list_start, const int32_t *list_len,
-                                                   const int32_t *lists, const double *vbox, const double *tbox,
-                                                   const double *ebox, int64_t *cnt, const int64_t *off,
-                                                   int32_t *out_pt, int32_t *out_ee) {
+                                                   const int32_t *lists, const int32_t *tris, const int32_t *edges,
+                                                   const double *x0, const double *x1, double inflate,
+                                                   int64_t *cnt, const int64_t *off, int32_t *out_pt,
+                                                   int32_t *out_ee, int trows) {
   const int64_t b = blockIdx.x;
   if (b < n_pt_blocks) {
     const int64_t valid = WRITE ? n_pt_blocks : toff[2 * nbp];
-    pair_tile<WRITE>(0, b, tsub_pt, n_pt_blocks, list_start, list_len, lists, vbox, tbox, cnt, WRITE ? off[b] : 0,
-                     out_pt, valid);
+    pair_tile<WRITE>(0, b, tsub_pt, n_pt_blocks, list_start, list_len, lists, tris, edges, x0, x1, inflate, cnt,
+                     WRITE ? off[b] : 0, out_pt, valid, trows);
   } else if (b < n_pt_blocks + n_ee_blocks) {
     const int64_t t = b - n_pt_blocks;
     const int64_t valid = WRITE ? n_ee_blocks : *ttotal - toff[2 * nbp];
-    pair_tile<WRITE>(1, t, tsub_ee, n_ee_blocks, list_start, list_len, lists, ebox, ebox, cnt + cap_pt,
-                     WRITE ? off[cap_pt + t] - off[cap_pt] : 0, out_ee, valid);
+    pair_tile<WRITE>(1, t, tsub_ee, n_ee_blocks, list_start, list_len, lists, tris, edges, x0, x1, inflate,
+                     cnt + cap_pt, WRITE ? off[cap_pt + t] - off[cap_pt] : 0, out_ee, valid, trows);
   }
 }
 
@@ -418,19 +447,16 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   const int nb = sc->n_bodies, nv = sc->n_verts, nt = sc->n_tris, ne = sc->n_edges;
   if (!x1) x1 = x0;
   *n_pt = *n_ee = 0;
+  ctx->involved_valid = false;
   if (nb <= 1 || nv <= 0) return ABD_OK;
-  double *vbox, *tbox, *ebox, *bbox;
-  ABD_TRY(ws(ctx, "bp_vbox", 6 * (size_t)nv, &vbox, s));
-  ABD_TRY(ws(ctx, "bp_tbox", 6 * (size_t)nt + 6, &tbox, s));
-  ABD_TRY(ws(ctx, "bp_ebox", 6 * (size_t)ne + 6, &ebox, s));
+  double *bbox;
   ABD_TRY(ws(ctx, "bp_bbox", 6 * (size_t)nb, &bbox, s));
-  float *vbox32, *tbox32, *ebox32;
+  float *vbox32;
   ABD_TRY(ws(ctx, "bp_vbox32", 6 * (size_t)nv, &vbox32, s));
-  ABD_TRY(ws(ctx, "bp_tbox32", 6 * (size_t)nt + 6, &tbox32, s));
-  ABD_TRY(ws(ctx, "bp_ebox32", 6 * (size_t)ne + 6, &ebox32, s));
   uint8_t *involved;
   ABD_TRY(ws(ctx, "bp_involved", nb, &involved, s));
-  hipLaunchKernelGGL(k_body_boxes, dim3(nb), dim3(256), 0, s, sc->body_vert_off, x0, x1, inflate, bbox, involved);
+  hipLaunchKernelGGL(k_body_boxes, dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, sc->body_vert_off, x0, x1, inflate,
+                     bbox, involved);
   HIP_TRY(ctx, hipGetLastError());
 
   // body pairs
@@ -476,14 +502,15 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     cap_bp = nbp;
   }
   ctx->cap_hint[key_bp] = nbp;
+  ctx->involved_valid = true;
   if (nbp == 0) return ABD_OK;
-  // primitive boxes of the bodies in overlapping pairs only
-  hipLaunchKernelGGL(k_prim_boxes, dim3(grid_for((int64_t)nv + nt + ne, 256)), dim3(256), 0, s, nv, nt, ne,
-                     sc->vert_body, sc->tri_body, sc->edge_body, involved, sc->tris, sc->edges, x0, x1, inflate, vbox,
-                     vbox32, tbox, tbox32, ebox, ebox32);
+  // culling boxes of the vertices of bodies in overlapping pairs only
+  hipLaunchKernelGGL(k_vert_boxes, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv, sc->vert_body, involved, x0, x1,
+                     inflate, vbox32);
   HIP_TRY(ctx, hipGetLastError());
 
   // culled primitive lists per body pair
+  const int trows = ctx->tune.tile_rows;
   int32_t *lists, *llen;
   int64_t *lstart;
   ABD_TRY(ws(ctx, "bp_lists", list_total + 1, &lists, s));
@@ -497,8 +524,8 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_tcnt", 3 * nbp, &tcnt, s));
   ABD_TRY(ws(ctx, "bp_toff", 3 * nbp + 1, &toff, s));
   hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 3), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
-                     sc->body_tri_off, sc->body_edge_off, bbox, vbox32, tbox32, ebox32, lists, lstart, llen, tcnt,
-                     tcnt + 2 * nbp);
+                     sc->body_tri_off, sc->body_edge_off, bbox, vbox32, sc->tris, sc->edges, lists, lstart, llen,
+                     tcnt, tcnt + 2 * nbp, trows);
   // hbuf[2] = all tiles, hbuf[3] = PT tiles
   ABD_TRY(scan_exclusive_i64(ctx, tcnt, toff, 3 * nbp, ttot, s, hbuf_d + 2, 2 * nbp));
   const std::string key_tp = std::string(tag) + "_tpt", key_te = std::string(tag) + "_tee";
@@ -517,8 +544,8 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(3 * nbp, 256)), dim3(256), 0, s, nbp, tcnt, toff, tsub_pt, cap_tp,
                        tsub_ee, cap_te);
     hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)(cap_tp + cap_te)), dim3(64), 0, s, nbp, cap_tp, cap_te, cap_tp,
-                       tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, vbox, tbox, ebox, ccnt, nullptr, nullptr,
-                       nullptr);
+                       tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0, x1, inflate,
+                       ccnt, nullptr, nullptr, nullptr, trows);
     // hbuf[4] = all pairs, hbuf[5] = PT pairs
     ABD_TRY(scan_exclusive_i64(ctx, ccnt, coff, cap_tp + cap_te, otot, s, hbuf_d + 4, cap_tp));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -539,8 +566,8 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   hipEvent_t pe = prof_begin(ctx, s);
   if (*n_pt + *n_ee > 0)
     hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)(ntile_pt + ntile_ee)), dim3(64), 0, s, nbp, ntile_pt,
-                       ntile_ee, cap_tp, tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, vbox, tbox, ebox, nullptr,
-                       coff, *pt_out, *ee_out);
+                       ntile_ee, cap_tp, tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0,
+                       x1, inflate, nullptr, coff, *pt_out, *ee_out, trows);
   prof_end(ctx, pe, "pair_tiles_write", ntile_pt + ntile_ee, s);
   return abd_hip_check(ctx, hipGetLastError(), "candidates");
 }
@@ -585,13 +612,13 @@ __global__ void k_od_clear(int64_t n16, uint4 *f) {
 // both (a, b) and (b, a) are marked, so that row b also lists the rows
 // a < b of its column
 struct MarkLists {
-  const int32_t *p[4];
-  int64_t end[4];  // cumulative counts
+  const int32_t *p[5];
+  int64_t end[5];  // cumulative counts (point-triangle, edge-edge, pt2, ee2, pt3)
 };
 __global__ void k_od_mark(MarkLists L, const int32_t *vert_body, const int32_t *tri_body, const int32_t *edge_body,
                           const uint8_t *fixed, int nb, uint8_t *flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L.end[3]) return;
+  if (i >= L.end[4]) return;
   int l = 0;
   while (i >= L.end[l]) ++l;
   if (l > 0) i -= L.end[l - 1];
@@ -658,8 +685,18 @@ __global__ void __launch_bounds__(64) k_od_lower(int nb, const uint8_t *flags, c
 
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys_out, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2,
-               int64_t n_pt2, const int32_t *ee2, int64_t n_ee2, KeyPattern *pat) {
-  const int64_t n = n_pt + n_ee + n_pt2 + n_ee2;
+               int64_t n_pt2, const int32_t *ee2, int64_t n_ee2, KeyPattern *pat, const int32_t *pt3,
+               int64_t n_pt3) {
+  // (a scene's joints between two free bodies join the pattern)
+  if (!pt3 && sc->n_joints > 0) {
+    JointTables *jt = nullptr;
+    ABD_TRY(joint_tables(ctx, sc, &jt, s));
+    if (jt) {
+      pt3 = jt->pairs;
+      n_pt3 = jt->n_pairs;
+    }
+  }
+  const int64_t n = n_pt + n_ee + n_pt2 + n_ee2 + n_pt3;
   *n_keys = 0;
   if (pat) *pat = KeyPattern{};
   std::string nm = std::string(tag) + "_keys";
@@ -672,8 +709,8 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   ABD_TRY(ws(ctx, "od_flag", n, &flag, s));
   ABD_TRY(ws(ctx, "od_pos", n, &pos, s));
   ABD_TRY(ws(ctx, "od_tot", 1, &tot, s));
-  const int32_t *lists[4] = {pt, ee, pt2, ee2};
-  const int64_t counts[4] = {n_pt, n_ee, n_pt2, n_ee2};
+  const int32_t *lists[5] = {pt, ee, pt2, ee2, pt3};
+  const int64_t counts[5] = {n_pt, n_ee, n_pt2, n_ee2, n_pt3};
   const int nb = sc->n_bodies;
   if ((sc->n_scenes <= 1) && nb <= OD_DENSE_MAX) {
     const int64_t nbb = ((int64_t)nb * nb + 15) / 16 * 16;
@@ -686,7 +723,7 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
                        reinterpret_cast<uint4 *>(flags));
     MarkLists ml;
     int64_t acc = 0;
-    for (int l = 0; l < 4; ++l) {
+    for (int l = 0; l < 5; ++l) {
       ml.p[l] = lists[l];
       acc += counts[l];
       ml.end[l] = acc;
@@ -720,7 +757,7 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
     return abd_hip_check(ctx, hipGetLastError(), "offdiag");
   }
   int64_t at = 0;
-  for (int l = 0; l < 4; ++l) {
+  for (int l = 0; l < 5; ++l) {
     if (counts[l] > 0)
       hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(counts[l], 256)), dim3(256), 0, s, counts[l], l & 1, lists[l],
                          sc->vert_body, sc->tri_body, sc->edge_body, sc->body_fixed, k + at);

@@ -37,9 +37,8 @@ __device__ __forceinline__ void atomic_min_nonneg(double *addr, double v) {
   atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-constexpr int CCD_BLOCK = 256;
-
-__global__ void __launch_bounds__(CCD_BLOCK) k_accd(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee,
+template <int BS>
+__global__ void __launch_bounds__(BS) k_accd(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee,
                                                     const int32_t *tris, const int32_t *edges,
                                                     const int32_t *vert_body, const int32_t *body_scene,
                                                     const double *x, const double *dx, double s, double tmax,
@@ -198,9 +197,11 @@ int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const doubl
   hipLaunchKernelGGL(k_ccd_init, dim3(grid_for(ns, 256)), dim3(256), 0, s, alpha, alpha ? ns : 0, 1.0, counter);
   const int64_t n = n_pt + n_ee;
   if (n > 0) {
-    // persistent grid: enough waves to fill the chip, never more than the work
-    int64_t blocks = (n + CCD_BLOCK - 1) / CCD_BLOCK;
-    if (blocks > 1024) blocks = 1024;
+    // persistent grid: enough waves to fill the chip, never more than the
+    // work (block size and grid cap from the launch-shape table)
+    const int bs = ctx->tune.ccd_block;
+    int64_t blocks = (n + bs - 1) / bs;
+    if (blocks > ctx->tune.ccd_max_blocks) blocks = ctx->tune.ccd_max_blocks;
     // (environment ABD_CCD_MAX_BLOCKS: a smaller grid, so that tests reach
     // the work counter with few pairs)
     if (const char *mb = getenv("ABD_CCD_MAX_BLOCKS")) {
@@ -208,9 +209,16 @@ int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const doubl
       if (cap >= 1 && blocks > cap) blocks = cap;
     }
     hipEvent_t pe = prof_begin(ctx, s);
-    hipLaunchKernelGGL(k_accd, dim3((unsigned)blocks), dim3(CCD_BLOCK), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges,
-                       sc->vert_body, sc->body_scene, x0, dx, prm->ccd_s, prm->ccd_tmax, prm->ccd_max_iter, counter,
-                       t_pt, t_ee, alpha);
+#define ABD_ACCD_ARGS                                                                                          \
+  n_pt, n, pt, ee, sc->tris, sc->edges, sc->vert_body, sc->body_scene, x0, dx, prm->ccd_s, prm->ccd_tmax, \
+      prm->ccd_max_iter, counter, t_pt, t_ee, alpha
+    if (bs == 64)
+      hipLaunchKernelGGL(k_accd<64>, dim3((unsigned)blocks), dim3(64), 0, s, ABD_ACCD_ARGS);
+    else if (bs == 128)
+      hipLaunchKernelGGL(k_accd<128>, dim3((unsigned)blocks), dim3(128), 0, s, ABD_ACCD_ARGS);
+    else
+      hipLaunchKernelGGL(k_accd<256>, dim3((unsigned)blocks), dim3(256), 0, s, ABD_ACCD_ARGS);
+#undef ABD_ACCD_ARGS
     prof_end(ctx, pe, "accd", n, s);
   }
   return abd_hip_check(ctx, hipGetLastError(), "k_accd");

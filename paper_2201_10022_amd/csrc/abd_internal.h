@@ -31,8 +31,22 @@ struct PendingEv {
   int64_t units;
 };
 
+// joint tables of a scene (abd_joint.hip), rebuilt when the key changes
+struct JointTables {
+  std::vector<uintptr_t> key;
+  int32_t *joff = nullptr, *jent = nullptr, *run_off = nullptr, *run_joint = nullptr, *pairs = nullptr;
+  int n_runs = 0;
+  int64_t n_pairs = 0;  // joints between two free bodies (point-triangle-shaped pairs for the pattern)
+};
+
 struct abd_ctx {
   int device = 0;
+  // launch shapes (abd_tune_set / abd_autotune); none changes a result
+  abd_tune tune = {16, 1, 256, 1024, 256, 16, 64};
+  // the last op_candidates call marked, per body, whether it is in an
+  // overlapping body pair (workspace "bp_involved"); false until it has
+  bool involved_valid = false;
+  JointTables joints;
   std::string err;
   std::map<std::string, DevBuf> bufs;
   // counts of the last call per buffer family, used as capacities of the
@@ -175,12 +189,22 @@ struct KeyPattern {
   const uint32_t *tperm = nullptr;
   bool valid = false;
 };
-// pattern of the pairs (pt, ee) and, when given, the extra pairs (pt2, ee2);
-// pat (may be NULL) receives the keys' row structure when the dense path
-// builds it (else pat->valid = false)
+// pattern of the pairs (pt, ee) and, when given, the extra pairs (pt2, ee2)
+// and point-triangle-shaped pairs pt3 (joints); pat (may be NULL) receives
+// the keys' row structure when the dense path builds it (else pat->valid =
+// false)
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2 = nullptr,
-               int64_t n_pt2 = 0, const int32_t *ee2 = nullptr, int64_t n_ee2 = 0, KeyPattern *pat = nullptr);
+               int64_t n_pt2 = 0, const int32_t *ee2 = nullptr, int64_t n_ee2 = 0, KeyPattern *pat = nullptr,
+               const int32_t *pt3 = nullptr, int64_t n_pt3 = 0);
+// joints: the scene's tables (NULL when it has none); per-body energy
+// (added to e_items + t estride for trial t, q at q + t qstride), gradient
+// and diagonal blocks, times c = kappa_j w; off-diagonal blocks into off
+int joint_tables(abd_ctx *ctx, const abd_scene *sc, JointTables **out, hipStream_t s);
+int op_joint_body(abd_ctx *ctx, const abd_scene *sc, double c, const double *q, int n_trials, int64_t qstride,
+                  double *e_items, int64_t estride, double *grad, double *diag, hipStream_t s);
+int op_joint_off(abd_ctx *ctx, const abd_scene *sc, double c, const int32_t *keys, int64_t n_keys, double *off,
+                 hipStream_t s);
 // barrier (and, when fr is given, the lagged friction of fr) energy,
 // gradient and Hessian blocks, assembled in one pass
 int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,

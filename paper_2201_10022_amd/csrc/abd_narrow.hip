@@ -72,7 +72,8 @@ __global__ void k_compact(int64_t n, const int64_t *flag, const int64_t *pos, in
   if (i < n && flag[i]) out[pos[i]] = (int32_t)i;
 }
 
-__global__ void __launch_bounds__(64) k_barrier_local(const int64_t *n_act_dev, const int32_t *act, int64_t n_pt,
+template <int BS>
+__global__ void __launch_bounds__(BS) k_barrier_local(const int64_t *n_act_dev, const int32_t *act, int64_t n_pt,
                                                       const int32_t *pt, const int32_t *ee, const int32_t *tris,
                                                       const int32_t *edges, const int32_t *vert_body,
                                                       const double *x, const double *xbar, double dhat,
@@ -386,9 +387,18 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   ABD_TRY(ws(ctx, "br_info", nl, &info, s));
   if (na > 0) {
     hipEvent_t pe = prof_begin(ctx, s);
-    hipLaunchKernelGGL(k_barrier_local, dim3(grid_for(na, 64)), dim3(64), 0, s, nact, act, n_pt, pt, ee, sc->tris,
-                       sc->edges, sc->vert_body, x, sc->xbar, dhat, prm->kappa_b, project, e_loc, g_loc, H_loc, info,
-                       err);
+    // (waves per block from the launch-shape table)
+#define ABD_BARRIER_ARGS                                                                                          \
+  nact, act, n_pt, pt, ee, sc->tris, sc->edges, sc->vert_body, x, sc->xbar, dhat, prm->kappa_b, project, e_loc, \
+      g_loc, H_loc, info, err
+    const int wpb = ctx->tune.barrier_waves;
+    if (wpb == 4)
+      hipLaunchKernelGGL(k_barrier_local<256>, dim3(grid_for(na, 256)), dim3(256), 0, s, ABD_BARRIER_ARGS);
+    else if (wpb == 2)
+      hipLaunchKernelGGL(k_barrier_local<128>, dim3(grid_for(na, 128)), dim3(128), 0, s, ABD_BARRIER_ARGS);
+    else
+      hipLaunchKernelGGL(k_barrier_local<64>, dim3(grid_for(na, 64)), dim3(64), 0, s, ABD_BARRIER_ARGS);
+#undef ABD_BARRIER_ARGS
     prof_end(ctx, pe, "barrier_local", na, s);
     HIP_TRY(ctx, hipGetLastError());
   }
@@ -442,7 +452,8 @@ int op_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, 
   double *e;
   ABD_TRY(ws(ctx, "be_e", n, &e, s));
   hipEvent_t pe = prof_begin(ctx, s);
-  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, 256)), dim3(256), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges, x,
+  const int eb = ctx->tune.energy_block;
+  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb)), dim3(eb), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges, x,
                      sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, nullptr);
   prof_end(ctx, pe, "energy_only", n, s);
   HIP_TRY(ctx, hipGetLastError());
@@ -461,7 +472,8 @@ int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params
   ABD_TRY(ws(ctx, "be_e", n, &e, s));
   ABD_TRY(ws(ctx, "be_key", n, &key, s));
   hipEvent_t pe = prof_begin(ctx, s);
-  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, 256)), dim3(256), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges, x,
+  const int eb = ctx->tune.energy_block;
+  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb)), dim3(eb), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges, x,
                      sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key);
   prof_end(ctx, pe, "energy_only", n, s);
   HIP_TRY(ctx, hipGetLastError());
@@ -482,7 +494,8 @@ int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params
   if (!e) ABD_TRY(ws(ctx, "be_e_tr", (size_t)n * n_trials, &e, s));
   if (!items) ABD_TRY(ws(ctx, "be_key", n, &key, s));
   hipEvent_t pe = prof_begin(ctx, s);
-  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, 256), n_trials), dim3(256), 0, s, n_pt, n, pt, ee, sc->tris,
+  const int eb = ctx->tune.energy_block;
+  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb), n_trials), dim3(eb), 0, s, n_pt, n, pt, ee, sc->tris,
                      sc->edges, x, sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key,
                      3 * (int64_t)sc->n_verts, items ? estride : 0);
   prof_end(ctx, pe, "energy_only", n * n_trials, s);
@@ -555,7 +568,8 @@ extern "C" int abd_barrier_energy_noalloc(abd_ctx *ctx, const abd_scene *sc, con
   if (!scr) return abd_fail(ctx, ABD_E_HIP, "abd_barrier_energy_noalloc: scratch address not set for this device");
   // the kernels and the summation order of abd_barrier_energy
   double *e = scr, *part = scr + ABD_NOALLOC_MAX_PAIRS;
-  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, 256)), dim3(256), 0, stream, n_pt, n, pt, ee, sc->tris,
+  const int eb = ctx->tune.energy_block;
+  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb)), dim3(eb), 0, stream, n_pt, n, pt, ee, sc->tris,
                      sc->edges, x, sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, nullptr);
   reduce_sum_f64_into(e, n, part, energy, stream);
   return abd_hip_check(ctx, hipGetLastError(), "abd_barrier_energy_noalloc");

@@ -133,10 +133,12 @@ __global__ void k_axpy_trials(int nb, int S, const int32_t *body_scene, const do
 // (one fused multiply-add); the others map the vertices, x_t = x(q_t), with
 // the same arithmetic as the vertex map and q_t formed in place by that
 // same fused multiply-add, so they need not wait for the first part.
+// Vertices of bodies in no overlapping body pair of the sweep (only_bodies
+// non-NULL and 0) are skipped: no candidate pair reads them.
 __global__ void __launch_bounds__(256) k_trial_states(int nb, int S, const int32_t *body_scene, const double *q,
                                                       const double *alpha, const double *p, double *qn, int nv,
                                                       const double *xbar, const int32_t *vert_body, double *xn,
-                                                      int nqb) {
+                                                      int nqb, const uint8_t *only_bodies) {
 #pragma clang fp contract(off)
   const int t = blockIdx.y;
   if ((int)blockIdx.x < nqb) {
@@ -148,6 +150,7 @@ __global__ void __launch_bounds__(256) k_trial_states(int nb, int S, const int32
   const int k = ((int)blockIdx.x - nqb) * 256 + threadIdx.x;
   if (k >= nv) return;
   const int64_t b = vert_body[k];
+  if (only_bodies && !only_bodies[b]) return;
   const double al = alpha[(int64_t)t * S + body_scene[b]];
   double qb[12];
 #pragma unroll
@@ -191,9 +194,14 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
   // (one scene with items: the row sums below are assigned, not added)
   if (S > 1 || (int64_t)nb + npt + nee + (fr ? fr->n() : 0) == 0) ABD_TRY(zero(ctx, e_dev, (int64_t)n * S, s));
   {
+    // (the candidates are those of the sweep just culled: vertices of bodies
+    // it found in no overlapping pair are read by no pair; lagged friction
+    // pairs may lie elsewhere, so with friction every vertex is mapped)
+    uint8_t *only = nullptr;
+    if (!fr && ctx->involved_valid) ABD_TRY(ws(ctx, "bp_involved", nb, &only, s));
     const int nqb = (int)grid_for(n12, 256);
     hipLaunchKernelGGL(k_trial_states, dim3(nqb + grid_for(sc->n_verts, 256), n), dim3(256), 0, s, nb, S,
-                       sc->body_scene, q, alpha, p, qn, sc->n_verts, sc->xbar, sc->vert_body, xn, nqb);
+                       sc->body_scene, q, alpha, p, qn, sc->n_verts, sc->xbar, sc->vert_body, xn, nqb, only);
     HIP_TRY(ctx, hipGetLastError());
   }
   if (S > 1) {
@@ -293,6 +301,8 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, e, g, diag, 1, s));
   int64_t nap = 0, nae = 0;
   ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 1, &nap, &nae, s, fr));
+  if (sc->n_joints > 0 && prm->kappa_j > 0.0)
+    ABD_TRY(op_joint_off(ctx, sc, prm->kappa_j * prm->dt * prm->dt, keys, nk, off, s));
   st->t_barrier_ms += ms_since(t0);
   st->n_active_pt = nap;
   st->n_active_ee = nae;

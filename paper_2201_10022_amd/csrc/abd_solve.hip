@@ -19,7 +19,9 @@
 // partials in a fixed order; every block does the same fold, so all blocks
 // take the same decisions (alpha, beta, stop) without fences, atomics or
 // separate reduction launches, and results are run-to-run reproducible.
-// Iterations are replayed from captured hipGraphs of ITER_G iterations; once
+// Iterations are replayed from captured hipGraphs of a short or a long run
+// of iterations (even counts from the launch-shape table: the p buffers
+// alternate; long replays while the last solve's count says many remain); once
 // a scene's stop flag is set its remaining kernels return at once, and the
 // host reads the flags once per replay.
 #include <cstdlib>
@@ -31,9 +33,6 @@
 
 namespace {
 
-// iterations per graph replay (even: p buffers alternate): short replays,
-// and long ones while the last solve's count says many remain
-constexpr int ITER_G[2] = {16, 64};
 
 // inverse of each free body's diagonal block via Cholesky (thread per body)
 __global__ void __launch_bounds__(64) k_block_inverse(int nb, const uint8_t *fixed, const double *diag, double *inv,
@@ -1055,6 +1054,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
              const PcgBlk *ublk, int nblk_u, const int32_t *s_scene, const int64_t *s_off, const int32_t *sbo,
              const int64_t *eoff, const int2 *ent, int nblk_s, double rtol2, int max_iter, int *iters,
              hipStream_t s) {
+  const int iter_g[2] = {ctx->tune.pcg_short, ctx->tune.pcg_long};
   double *rv[2], *wv[2], *sv[2], *pt[2], *u, *p;
   PcgBlk *cblk;
   CgState *st;
@@ -1117,7 +1117,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
         (uintptr_t)ent,      (uintptr_t)st,       (uintptr_t)sc->body_fixed,
         (uintptr_t)nblk_s,   (uintptr_t)max_iter, (uintptr_t)rtol_bits,    (uintptr_t)scs.gam,    (uintptr_t)scs.alp,
         (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)hst_d, (uintptr_t)S,
-        (uintptr_t)1};
+        (uintptr_t)iter_g[0], (uintptr_t)iter_g[1], (uintptr_t)1};
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     for (int gi = 0; gi < 2; ++gi) {
       if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {
@@ -1125,7 +1125,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
         ctx->pcg_exec[gi] = nullptr;
         hipGraph_t g = nullptr;
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-        enqueue(ctx->capture_stream, ITER_G[gi]);
+        enqueue(ctx->capture_stream, iter_g[gi]);
         HIP_TRY(ctx, hipStreamEndCapture(ctx->capture_stream, &g));
         HIP_TRY(ctx, hipGraphInstantiate(&ctx->pcg_exec[gi], g, nullptr, nullptr, 0));
         HIP_TRY(ctx, hipGraphDestroy(g));
@@ -1137,7 +1137,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   int *h;  // [4..4+S): per-scene iteration counts (profiled solves)
   ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
   int *fin = h + 4;
-  const int max_rounds = max_iter / ITER_G[0] + 2;
+  const int max_rounds = max_iter / iter_g[0] + 2;
   int done = 0;
   bool all = false;
   bool profiled = false;
@@ -1150,18 +1150,18 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
     // round trip per replay.
     int planned = 0;
     do {
-      const int gi = ctx->pcg_hint - (done + planned) >= ITER_G[1] ? 1 : 0;
+      const int gi = ctx->pcg_hint - (done + planned) >= iter_g[1] ? 1 : 0;
       hipEvent_t pe = prof_begin(ctx, s);
       profiled = profiled || pe != nullptr;
       if (exec[gi])
         HIP_TRY(ctx, hipGraphLaunch(exec[gi], s));
       else
-        enqueue(s, ITER_G[gi]);
+        enqueue(s, iter_g[gi]);
       prof_end(ctx, pe, "pcg_round", 0, s);
       HIP_TRY(ctx, hipGetLastError());
-      planned += ITER_G[gi];
+      planned += iter_g[gi];
       ++round;
-    } while (round < max_rounds && ctx->pcg_hint - (done + planned) >= ITER_G[0]);
+    } while (round < max_rounds && ctx->pcg_hint - (done + planned) >= iter_g[0]);
     HIP_TRY(ctx, hipStreamSynchronize(s));
     all = hst[1] >= S;
     done = all ? hst[2] : hst[0];  // iterations: the largest count over the scenes
@@ -1202,6 +1202,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
            const double *x0, const double *pre_diag, const KeyPattern *pat) {
   const int nb = sc->n_bodies;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  const int iter_g[2] = {ctx->tune.pcg_short, ctx->tune.pcg_long};
   *iters = 0;
   if (nb <= 0) return ABD_OK;
   if (n_keys >= (1ll << 31) || nb >= (1 << 24)) return abd_fail(ctx, ABD_E_INVALID, "pcg: too many blocks");
@@ -1370,7 +1371,8 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
         (uintptr_t)sc->body_fixed, (uintptr_t)nb, (uintptr_t)max_iter, (uintptr_t)rtol_bits,
         (uintptr_t)S, (uintptr_t)sbo, (uintptr_t)u_scene, (uintptr_t)s_scene, (uintptr_t)u_off, (uintptr_t)s_off,
         (uintptr_t)scs.rz, (uintptr_t)scs.bb, (uintptr_t)scs.stop, (uintptr_t)scs.it_final,
-        (uintptr_t)nblk_u, (uintptr_t)nblk_s, (uintptr_t)sblk, (uintptr_t)ublk, (uintptr_t)ent};
+        (uintptr_t)nblk_u, (uintptr_t)nblk_s, (uintptr_t)sblk, (uintptr_t)ublk, (uintptr_t)ent,
+        (uintptr_t)iter_g[0], (uintptr_t)iter_g[1]};
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     for (int gi = 0; gi < 2; ++gi) {
       if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {
@@ -1378,7 +1380,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
         ctx->pcg_exec[gi] = nullptr;
         hipGraph_t g = nullptr;
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-        enqueue(ctx->capture_stream, ITER_G[gi]);
+        enqueue(ctx->capture_stream, iter_g[gi]);
         HIP_TRY(ctx, hipStreamEndCapture(ctx->capture_stream, &g));
         HIP_TRY(ctx, hipGraphInstantiate(&ctx->pcg_exec[gi], g, nullptr, nullptr, 0));
         HIP_TRY(ctx, hipGraphDestroy(g));
@@ -1390,7 +1392,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   int *h;  // [0..2] state counters, [4..4+S) per-scene iteration counts
   ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
   int *fin = h + 4;
-  const int max_rounds = max_iter / ITER_G[0] + 2;
+  const int max_rounds = max_iter / iter_g[0] + 2;
   // algorithmic HBM bytes of one iteration of a scene: every 12x12 block of
   // its matrix and of its preconditioner once, plus the 12-vectors read and
   // written by the two kernels (spmv: z, p_old in, p_new, Ap out; update:
@@ -1403,13 +1405,13 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   for (int round = 0; round < max_rounds && !all; ++round) {
     // a long replay while the last solve's count says at least that many
     // iterations remain, else a short one
-    const int gi = hint - done >= ITER_G[1] ? 1 : 0;
+    const int gi = hint - done >= iter_g[1] ? 1 : 0;
     hipEvent_t pe = prof_begin(ctx, s);
     profiled = profiled || pe != nullptr;
     if (exec[gi])
       HIP_TRY(ctx, hipGraphLaunch(exec[gi], s));
     else
-      enqueue(s, ITER_G[gi]);
+      enqueue(s, iter_g[gi]);
     prof_end(ctx, pe, "pcg_round", 0, s);
     HIP_TRY(ctx, hipGetLastError());
     // it_done, k_cur, n_stopped, max_final

@@ -50,7 +50,8 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     cc = shutil.which("gcc")
     if cc is None or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
         pytest.skip("no host C compiler or HIP headers")
-    structs = {"abd_scene": _lib.AbdScene, "abd_params": _lib.AbdParams, "abd_stats": _lib.AbdStats}
+    structs = {"abd_scene": _lib.AbdScene, "abd_params": _lib.AbdParams, "abd_stats": _lib.AbdStats,
+               "abd_tune": _lib.AbdTune}
     lines = ['#include <stdio.h>', '#include "abd.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')

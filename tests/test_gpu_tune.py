@@ -1,0 +1,86 @@
+"""The launch-shape table changes times, not results: a batched Newton
+iteration and a box-drop time step give bit-identical states under
+different tables (tile rows, waves per barrier block, CCD block and grid
+cap, energy block, PCG replay lengths), and the autotuner leaves the
+workload's state unchanged and sets a valid table."""
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TABLES = [
+    dict(tile_rows=16, barrier_waves=1, ccd_block=256, ccd_max_blocks=1024, energy_block=256, pcg_short=16,
+         pcg_long=64),
+    dict(tile_rows=8, barrier_waves=4, ccd_block=64, ccd_max_blocks=256, energy_block=128, pcg_short=8, pcg_long=32),
+    dict(tile_rows=64, barrier_waves=2, ccd_block=128, ccd_max_blocks=4096, energy_block=512, pcg_short=32,
+         pcg_long=128),
+]
+
+
+@pytest.fixture(scope="module")
+def abd():
+    import paper_2201_10022_amd as abd
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return abd
+
+
+def _dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda:0")
+
+
+def test_tables_give_identical_results(abd):
+    ctx = abd.Context(0)
+    assert ctx.tune_get() == TABLES[0]
+    # a batch of 16 drop scenes after 22 steps (landing), one Newton
+    # iteration; and 3 steps of the box drop's lowest two layers at landing
+    S, P = sg.batched_drops(n_scenes=16)
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    q, qd = _dev(S["q0"]), _dev(S["qd0"])
+    for _ in range(22):
+        ctx.time_step(sc, P, q, qd)
+    qt = ctx.q_tilde(sc, P, q, qd)
+    Sb, Pb = sg.icosphere_box(n_layers=2)
+    Sb = sg.landed(Sb, seed=7, dhat=Pb["dhat"])
+    scb = abd.Scene(Sb)
+    ctx.body_mass(scb)
+    ref = None
+    for tab in TABLES:
+        ctx.tune_set(tab)
+        assert ctx.tune_get() == tab
+        qn = q.clone()
+        st = ctx.newton_step(sc, P, qn, qt)
+        assert st["n_active_pt"] + st["n_active_ee"] > 0
+        qb, qdb = _dev(Sb["q0"]), _dev(Sb["qd0"])
+        for _ in range(3):
+            ctx.time_step(scb, Pb, qb, qdb)
+        got = (qn.cpu().numpy(), qb.cpu().numpy(), qdb.cpu().numpy())
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(got, ref):
+                np.testing.assert_array_equal(a, b)
+    with pytest.raises(abd.AbdError):
+        ctx.tune_set(dict(TABLES[0], tile_rows=12))
+    assert ctx.tune_get() == TABLES[2]
+
+
+def test_autotune_keeps_the_state(abd):
+    ctx = abd.Context(0)
+    S, P = sg.batched_drops(n_scenes=8)
+    sc = abd.Scene(S)
+    ctx.body_mass(sc)
+    q, qd = _dev(S["q0"]), _dev(S["qd0"])
+    for _ in range(20):
+        ctx.time_step(sc, P, q, qd)
+    q0, qd0 = q.clone(), qd.clone()
+    table, ms = ctx.autotune(sc, P, q, qd, n_steps=2, reps=1)
+    assert ms > 0.0
+    assert ctx.tune_get() == table
+    assert torch.equal(q, q0) and torch.equal(qd, qd0)
+    ctx.tune_set(table)  # (valid)

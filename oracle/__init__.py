@@ -202,11 +202,17 @@ def classify(S, x, pairs, is_ee, dhat):
 
 
 def off_keys(S, pt, ee):
-    """Sorted unique body pairs (a<b, both free) touched by candidate pairs:
-    the off-diagonal block pattern of the global Hessian (sec. 4.3)."""
+    """Sorted unique body pairs (a<b, both free) touched by candidate pairs
+    and by joints between two bodies: the off-diagonal block pattern of the
+    global Hessian (sec. 4.3)."""
     vb, tb, eb, fx = S["vert_body"], S["tri_body"], S["edge_body"], S["body_fixed"]
     a = np.concatenate([vb[pt[:, 0]], eb[ee[:, 0]]]) if len(pt) + len(ee) else np.zeros(0, np.int64)
     b = np.concatenate([tb[pt[:, 1]], eb[ee[:, 1]]]) if len(pt) + len(ee) else np.zeros(0, np.int64)
+    jb = S.get("joint_body")
+    if jb is not None and len(jb):
+        jb = np.asarray(jb)[np.asarray(jb)[:, 1] >= 0]
+        a = np.concatenate([a, jb[:, 0]]).astype(np.int64)
+        b = np.concatenate([b, jb[:, 1]]).astype(np.int64)
     keep = (fx[a] == 0) & (fx[b] == 0)
     lo = np.minimum(a, b)[keep].astype(np.int64)
     hi = np.maximum(a, b)[keep].astype(np.int64)
@@ -387,6 +393,115 @@ def orthogonality_energy(S, vol, q, params, w=None):
                                           float(params["kappa_o"]), float(w))
 
 
+# Alternative rigidity potentials (sec. 3.2 names ARAP, |A - R(A)|_F^2 with
+# A = R S the polar decomposition, and neo-Hookean as alternatives to the
+# orthogonality potential).  Reading (the paper gives no constants): both
+# scaled like V_perp, kappa_o times the body volume times w (dt^2 in the
+# incremental potential); neo-Hookean with Lame parameters mu = lambda =
+# kappa_o, Psi = mu/2 (tr A^T A - 3) - mu ln J + lambda/2 (ln J)^2, J = det A,
+# infinite for J <= 0; ARAP's R the polar rotation (det R = +1: for
+# det A < 0 the SVD's last singular pair is flipped).  Per-body loops with
+# numpy's SVD, determinant and inverse as library primitives; the Hessians
+# are exact: ARAP's from the polar decomposition's differential (R^T dA =
+# W S + dS with W skew and dS symmetric, so W S + S W equals the skew part
+# of R^T dA, a 3x3 linear system for W, and dR = R W), neo-Hookean's from
+# d(A^-T) = -A^-T dA^T A^-T and d ln J = tr(A^-1 dA).
+
+RIGIDITY = {0: "orthogonality", 1: "arap", 2: "neo-hookean"}
+
+
+def _polar(A):
+    U, sv, Vt = np.linalg.svd(A)
+    D = np.diag([1.0, 1.0, np.sign(np.linalg.det(U @ Vt))])
+    R = U @ D @ Vt
+    return R, R.T @ A
+
+
+def _skew_vec(M):
+    return np.array([M[2, 1] - M[1, 2], M[0, 2] - M[2, 0], M[1, 0] - M[0, 1]]) / 2.0
+
+
+def _skew_mat(w):
+    return np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+
+
+def arap_body(A):
+    """Psi = |A - R|^2, its gradient 2 (A - R) and exact Hessian 2 (I - dR/dA)
+    (9-vectors and 9x9 in A's row-major order)."""
+    R, Sm = _polar(A)
+    e = float(np.sum((A - R) ** 2))
+    g = 2.0 * (A - R)
+    # W S + S W for the three unit skew matrices W
+    L = np.stack([_skew_vec(_skew_mat(u) @ Sm + Sm @ _skew_mat(u)) for u in np.eye(3)], 1)
+    H = np.zeros((9, 9))
+    for k in range(9):
+        dA = np.zeros(9)
+        dA[k] = 1.0
+        dA = dA.reshape(3, 3)
+        X = R.T @ dA
+        w = np.linalg.solve(L, _skew_vec(X - X.T))
+        dR = R @ _skew_mat(w)
+        H[:, k] = 2.0 * (dA - dR).reshape(9)
+    return e, g.reshape(9), 0.5 * (H + H.T)
+
+
+def neo_hookean_body(A, mu, lam):
+    J = np.linalg.det(A)
+    if J <= 0.0:
+        return np.inf, np.zeros(9), np.zeros((9, 9))
+    lnJ = np.log(J)
+    Ait = np.linalg.inv(A).T
+    e = 0.5 * mu * (float(np.sum(A * A)) - 3.0) - mu * lnJ + 0.5 * lam * lnJ * lnJ
+    P = mu * (A - Ait) + lam * lnJ * Ait
+    H = np.zeros((9, 9))
+    for k in range(9):
+        dA = np.zeros(9)
+        dA[k] = 1.0
+        dA = dA.reshape(3, 3)
+        dAit = -Ait @ dA.T @ Ait
+        dlnJ = float(np.sum(Ait * dA))
+        dP = mu * (dA - dAit) + lam * dlnJ * Ait + lam * lnJ * dAit
+        H[:, k] = dP.reshape(9)
+    return e, P.reshape(9), 0.5 * (H + H.T)
+
+
+def _psd(H):
+    lam, V = np.linalg.eigh(H)
+    return (V * np.maximum(lam, 0.0)) @ V.T
+
+
+def rigidity(S, vol, q, params, project=True, w=None):
+    """Energy, gradient [nb,12] and diagonal blocks [nb,144] of the body's
+    rigidity potential selected by params["rigidity"] (0 orthogonality, the
+    paper's V_perp; 1 ARAP; 2 neo-Hookean), times w (default dt^2)."""
+    kind = int(params.get("rigidity", 0))
+    if kind == 0:
+        return orthogonality(S, vol, q, params, project=project, w=w)
+    w = params["dt"] ** 2 if w is None else w
+    nb = len(S["body_fixed"])
+    e = 0.0
+    g = np.zeros((nb, 12))
+    D = np.zeros((nb, 12, 12))
+    k = params["kappa_o"]
+    for b in range(nb):
+        if S["body_fixed"][b]:
+            continue
+        A = q[b, 3:].reshape(3, 3)
+        eb, gb, Hb = arap_body(A) if kind == 1 else neo_hookean_body(A, 1.0, 1.0)
+        c = k * vol[b] * w
+        e += c * eb
+        g[b, 3:] = c * gb
+        D[b, 3:, 3:] = c * (_psd(Hb) if project else Hb)
+    return e, g, D.reshape(nb, 144)
+
+
+def rigidity_energy(S, vol, q, params, w=None):
+    kind = int(params.get("rigidity", 0))
+    if kind == 0:
+        return orthogonality_energy(S, vol, q, params, w=w)
+    return rigidity(S, vol, q, params, project=False, w=w)[0]
+
+
 def inertia(S, M, q, qt):
     """Incremental-potential inertia term 1/2 |q - q~|_M^2 (sec. 4),
     gradient M (q - q~), Hessian M; fixed bodies excluded."""
@@ -459,9 +574,72 @@ class Body:
         self.M = mass_matrix(self.mass)
 
 
+# Joints (sec. 5.3): an affine body's q maps linearly to any virtual
+# tetrahedron's vertices (Eq. phi), which are material points p_i = A pbar_i +
+# p, so a joint that fixes tetrahedron vertices is a linear equality between
+# material points: x_a(q_a) = x_b(q_b) for a point of body a and a point of
+# body b, or = c for a fixed world point c (a hinge: two such points on its
+# axis, over-constraining as the paper notes).  Reading: enforced by a stiff
+# quadratic penalty in the incremental potential, w kappa_j / 2 |x_a - x_b|^2
+# per joint (w = dt^2, like the other potentials).  S["joint_body"] [n, 2]
+# (b = -1: world), S["joint_point"] [n, 2, 3] (body-frame points; the world
+# point in the second slot when b = -1).
+
+def _point_jac(xb):
+    J = np.zeros((3, 12))
+    J[:, :3] = np.eye(3)
+    for i in range(3):
+        J[i, 3 + 3 * i:6 + 3 * i] = xb
+    return J
+
+
+def joints(S, q, params, keys, w=None):
+    """Energy, gradient [nb,12], diagonal [nb,144] and off-diagonal
+    [len(keys),144] blocks of the joint penalties (fixed bodies: no DOFs;
+    keys None: no off-diagonal blocks)."""
+    nb = len(S["body_fixed"])
+    if keys is None:
+        keys = np.zeros((0, 2), np.int32)
+        off = False
+    else:
+        off = True
+    e, g = 0.0, np.zeros((nb, 12))
+    D = np.zeros((nb, 12, 12))
+    O = np.zeros((len(keys), 12, 12))
+    jb = S.get("joint_body")
+    if jb is None or not len(jb):
+        return e, g, D.reshape(nb, 144), O.reshape(len(keys), 144)
+    c = params["kappa_j"] * (params["dt"] ** 2 if w is None else w)
+    kidx = {(int(a), int(b)): i for i, (a, b) in enumerate(keys)}
+    fx = S["body_fixed"]
+    for (a, b), (pa, pb) in zip(np.asarray(jb), np.asarray(S["joint_point"])):
+        Ja = _point_jac(pa)
+        xa = Ja @ q[a]
+        if b >= 0:
+            Jb = _point_jac(pb)
+            xb = Jb @ q[b]
+        else:
+            xb = np.asarray(pb, np.float64)
+        r = xa - xb
+        e += 0.5 * c * float(r @ r)
+        if not fx[a]:
+            g[a] += c * Ja.T @ r
+            D[a] += c * Ja.T @ Ja
+        if b >= 0 and not fx[b]:
+            g[b] -= c * Jb.T @ r
+            D[b] += c * Jb.T @ Jb
+            if off and not fx[a]:
+                lo, hi = (a, b) if a < b else (b, a)
+                blk = -c * (Ja.T @ Jb if a < b else Jb.T @ Ja)
+                O[kidx[(int(lo), int(hi))]] += blk
+    return e, g, D.reshape(nb, 144), O.reshape(len(keys), 144)
+
+
 def total_energy(S, B, q, qt, x, pt, ee, params, F=None):
     e_in, _, _ = inertia(S, B.M, q, qt)
-    e = e_in + orthogonality_energy(S, B.vol, q, params) + barrier_energy(S, x, pt, ee, params)
+    e = e_in + rigidity_energy(S, B.vol, q, params) + barrier_energy(S, x, pt, ee, params)
+    if S.get("joint_body") is not None and len(S["joint_body"]):
+        e += joints(S, q, params, None)[0]
     if F is not None:
         e += friction_energy(S, x, F, params)
     return e
@@ -478,10 +656,11 @@ def grad_hess(S, B, q, qt, params, x=None, pt=None, ee=None, project=True, F=Non
         pt, ee = candidates(S, x, None, params["dhat"])
     keys = off_keys(S, *_with_friction_pairs(pt, ee, F))
     e_in, g_in, D_in = inertia(S, B.M, q, qt)
-    e_o, g_o, D_o = orthogonality(S, B.vol, q, params, project=project)
+    e_o, g_o, D_o = rigidity(S, B.vol, q, params, project=project)
     bar = barrier(S, x, pt, ee, params, keys, project=project)
-    out = dict(energy=e_in + e_o + bar["energy"], grad=g_in + g_o + bar["grad"],
-               diag=D_in + D_o + bar["diag"], off=bar["off"], keys=keys, pt=pt, ee=ee,
+    e_j, g_j, D_j, O_j = joints(S, q, params, keys)
+    out = dict(energy=e_in + e_o + bar["energy"] + e_j, grad=g_in + g_o + bar["grad"] + g_j,
+               diag=D_in + D_o + bar["diag"] + D_j, off=bar["off"] + O_j, keys=keys, pt=pt, ee=ee,
                n_active=bar["n_active"])
     if F is not None:
         fr = friction(S, x, F, params, keys)

@@ -275,6 +275,195 @@ __device__ __forceinline__ bool ortho_project_closed(const double *A, double s, 
   return true;
 }
 
+// Alternative rigidity potentials of A (sec. 3.2's ARAP, |A - R(A)|_F^2,
+// and neo-Hookean with mu = lambda = 1: 1/2 (|A|_F^2 - 3) - ln J +
+// 1/2 (ln J)^2, J = det A, infinite for J <= 0), times kn w, through A's
+// signed singular value decomposition A = U diag(s) W^T (U, W rotations;
+// s_3 < 0 when det A < 0).  Both are isotropic: Psi depends on s only, the
+// gradient is U diag(psi) W^T (psi_i = dPsi/ds_i), and the Hessian's
+// eigenvectors are U E W^T for: the three scaling modes, E = diag(z) with
+// (z, lambda) the eigenpairs of d2Psi/ds2; per pair i < j the twist
+// (e_i e_j^T - e_j e_i^T)/sqrt2 with eigenvalue (psi_i + psi_j)/(s_i + s_j)
+// and the flip (e_i e_j^T + e_j e_i^T)/sqrt2 with (psi_i - psi_j)/(s_i -
+// s_j), both in closed forms without the differences:
+//   ARAP: psi_i = 2 (s_i - 1), d2Psi = 2 I, twist 2 - 4/(s_i + s_j), flip 2;
+//   neo-Hookean: psi_i = s_i + (ln J - 1)/s_i,
+//     d2Psi_ij = delta_ij (1 - (ln J - 1)/s_i^2) + 1/(s_i s_j),
+//     twist 1 + (ln J - 1)/(s_i s_j), flip 1 - (ln J - 1)/(s_i s_j).
+// W and s^2 come from the 3x3 eigenproblem of A^T A; the two larger
+// singular directions give u = A w / s (Gram-Schmidt), the third u is their
+// cross product and its s the signed length of A w along it.
+struct IsoSvd {
+  double U[3][3];  // U[k][i]: component i of u_k
+  double W[3][3];  // W[k][c]: component c of w_k
+  double s[3];
+};
+__device__ __forceinline__ void iso_svd(const double *A, IsoSvd &d) {
+  using S3 = SymIdx<3>;
+  double C[6], V[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int e = c; e < 3; ++e) C[S3::at(c, e)] = A[c] * A[e] + A[3 + c] * A[3 + e] + A[6 + c] * A[6 + e];
+  jacobi_eig<3>(C, V, 20, 1e-32);
+  // order: the two larger eigenvalues first, the smallest last
+  double ev[3] = {C[S3::at(0, 0)], C[S3::at(1, 1)], C[S3::at(2, 2)]};
+  int kmin = ev[0] <= ev[1] ? (ev[0] <= ev[2] ? 0 : 2) : (ev[1] <= ev[2] ? 1 : 2);
+  const int ka = kmin == 0 ? 1 : 0, kb = kmin == 2 ? 1 : 2;
+  const int ord[3] = {ka, kb, kmin};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d.W[k][c] = V[3 * c + ord[k]];
+  // W a rotation
+  const double detW = d.W[0][0] * (d.W[1][1] * d.W[2][2] - d.W[1][2] * d.W[2][1]) -
+                      d.W[0][1] * (d.W[1][0] * d.W[2][2] - d.W[1][2] * d.W[2][0]) +
+                      d.W[0][2] * (d.W[1][0] * d.W[2][1] - d.W[1][1] * d.W[2][0]);
+  if (detW < 0.0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d.W[2][c] = -d.W[2][c];
+  double Aw[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Aw[k][i] = A[3 * i] * d.W[k][0] + A[3 * i + 1] * d.W[k][1] + A[3 * i + 2] * d.W[k][2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    double v[3] = {Aw[k][0], Aw[k][1], Aw[k][2]};
+    if (k == 1) {
+      const double dd = d.U[0][0] * v[0] + d.U[0][1] * v[1] + d.U[0][2] * v[2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) v[i] -= dd * d.U[0][i];
+    }
+    const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    d.s[k] = nr;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) d.U[k][i] = v[i] / nr;
+  }
+  d.U[2][0] = d.U[0][1] * d.U[1][2] - d.U[0][2] * d.U[1][1];
+  d.U[2][1] = d.U[0][2] * d.U[1][0] - d.U[0][0] * d.U[1][2];
+  d.U[2][2] = d.U[0][0] * d.U[1][1] - d.U[0][1] * d.U[1][0];
+  d.s[2] = d.U[2][0] * Aw[2][0] + d.U[2][1] * Aw[2][1] + d.U[2][2] * Aw[2][2];
+  // (s_0, s_1: lengths after Gram-Schmidt; u_0 . A w_0 etc. are these)
+}
+
+// energy only of kind 2 (ARAP) or 3 (neo-Hookean), unscaled
+__device__ __forceinline__ double iso_energy(const double *A, int kind) {
+  if (kind == 3) {
+    const double J = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(J > 0.0)) return INFINITY;
+    double f2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f2 += A[i] * A[i];
+    const double lj = log(J);
+    return 0.5 * (f2 - 3.0) - lj + 0.5 * lj * lj;
+  }
+  IsoSvd d;
+  iso_svd(A, d);
+  return (d.s[0] - 1.0) * (d.s[0] - 1.0) + (d.s[1] - 1.0) * (d.s[1] - 1.0) + (d.s[2] - 1.0) * (d.s[2] - 1.0);
+}
+
+// energy, gradient and (projected when project) Hessian of kind 2 / 3,
+// times c = kn w; H packed upper 9x9
+__device__ __forceinline__ void iso_eval(const double *A, int kind, double c, Ortho &o, bool want_h, bool project) {
+  IsoSvd d;
+  iso_svd(A, d);
+  const double *sv = d.s;
+  double psi[3], hs[6], twist[3], flip[3];
+  using S3 = SymIdx<3>;
+  const int pi_[3] = {0, 0, 1}, pj_[3] = {1, 2, 2};
+  if (kind == 2) {
+    o.e = c * ((sv[0] - 1.0) * (sv[0] - 1.0) + (sv[1] - 1.0) * (sv[1] - 1.0) + (sv[2] - 1.0) * (sv[2] - 1.0));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) psi[k] = 2.0 * (sv[k] - 1.0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) hs[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) hs[S3::at(k, k)] = 2.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      twist[m] = 2.0 - 4.0 / (sv[pi_[m]] + sv[pj_[m]]);
+      flip[m] = 2.0;
+    }
+  } else {
+    const double J = sv[0] * sv[1] * sv[2];
+    if (!(J > 0.0)) {
+      o.e = INFINITY;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) o.g[i] = 0.0;
+#pragma unroll
+      for (int i = 0; i < 45; ++i) o.H[i] = 0.0;
+      return;
+    }
+    const double lj = log(J), l1 = lj - 1.0;
+    o.e = c * (0.5 * (sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2] - 3.0) - lj + 0.5 * lj * lj);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) psi[k] = sv[k] + l1 / sv[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a; b < 3; ++b) hs[S3::at(a, b)] = (a == b ? 1.0 - l1 / (sv[a] * sv[a]) : 0.0) + 1.0 / (sv[a] * sv[b]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double q = l1 / (sv[pi_[m]] * sv[pj_[m]]);
+      twist[m] = 1.0 + q;
+      flip[m] = 1.0 - q;
+    }
+  }
+  // gradient U diag(psi) W^T (row-major in A's order)
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      o.g[3 * i + cc] = c * (psi[0] * d.U[0][i] * d.W[0][cc] + psi[1] * d.U[1][i] * d.W[1][cc] +
+                             psi[2] * d.U[2][i] * d.W[2][cc]);
+  if (!want_h) return;
+  // scaling modes: eigenpairs of d2Psi/ds2
+  double Z[9];
+  jacobi_eig<3>(hs, Z, 20, 1e-32);
+  double lam[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) lam[k] = hs[S3::at(k, k)];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    lam[3 + 2 * m] = twist[m];
+    lam[4 + 2 * m] = flip[m];
+  }
+  if (project)
+#pragma unroll
+    for (int m = 0; m < 9; ++m) lam[m] = fmax(lam[m], 0.0);
+  double V[9][9];
+  const double r2 = 0.70710678118654752440;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const int o_ = 3 * i + cc;
+      double uw[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) uw[k] = d.U[k][i] * d.W[k][cc];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) V[k][o_] = Z[k] * uw[0] + Z[3 + k] * uw[1] + Z[6 + k] * uw[2];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double aij = d.U[pi_[m]][i] * d.W[pj_[m]][cc], aji = d.U[pj_[m]][i] * d.W[pi_[m]][cc];
+        V[3 + 2 * m][o_] = r2 * (aij - aji);
+        V[4 + 2 * m][o_] = r2 * (aij + aji);
+      }
+    }
+  using S9 = SymIdx<9>;
+#pragma unroll
+  for (int r = 0; r < 9; ++r)
+#pragma unroll
+    for (int cc = r; cc < 9; ++cc) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < 9; ++m) acc += lam[m] * V[m][r] * V[m][cc];
+      o.H[S9::at(r, cc)] = c * acc;
+    }
+}
+
 // inertia + weighted orthogonality per body: energies to e_out[b], gradient
 // and diagonal blocks accumulated (thread per body)
 // DERIV = 0: energies only (the derivative code compiled out, so the
@@ -326,15 +515,21 @@ __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed,
       }
     }
   }
-  if (do_ortho) {
+  if (do_ortho >= 2 && !DERIV) {
+    e += w * kappa_o * volume[b] * iso_energy(qb + 3, do_ortho);
+  } else if (do_ortho) {
     Ortho o;
-    ortho_eval(qb + 3, kappa_o * volume[b], w, o, DERIV && diag != nullptr);
+    if (do_ortho == 1)
+      ortho_eval(qb + 3, kappa_o * volume[b], w, o, DERIV && diag != nullptr);
+    else
+      iso_eval(qb + 3, do_ortho, w * kappa_o * volume[b], o, DERIV && diag != nullptr, project != 0);
     e += o.e;
     if (DERIV && want_grad)
 #pragma unroll
       for (int i = 0; i < 9; ++i) grad[12 * (int64_t)b + 3 + i] += o.g[i];
     if (DERIV && diag) {
-      if (project && !ortho_project_closed(qb + 3, 4.0 * w * kappa_o * volume[b], o.H)) psd_project_packed<9>(o.H);
+      if (do_ortho == 1 && project && !ortho_project_closed(qb + 3, 4.0 * w * kappa_o * volume[b], o.H))
+        psd_project_packed<9>(o.H);
       using S = SymIdx<9>;
       double *D = diag + 144 * (int64_t)b;
 #pragma unroll
@@ -394,12 +589,14 @@ int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, d
   return seg_max_scenes(ctx, val, key, sc->n_verts, S, out_dev, s);
 }
 
+// (kappa_j > 0: the scene's joint penalties are added, times w)
 static int body_terms(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double kappa_o,
                       double w, int do_inertia, int do_ortho, int project, double *energy, double *grad,
-                      double *diag, hipStream_t s) {
+                      double *diag, hipStream_t s, double kappa_j = 0.0) {
   if (sc->n_bodies <= 0) return ABD_OK;
   if (!sc->mass && do_inertia) return abd_fail(ctx, ABD_E_INVALID, "scene mass is NULL");
   if (!sc->volume && do_ortho) return abd_fail(ctx, ABD_E_INVALID, "scene volume is NULL");
+  if (do_ortho < 0 || do_ortho > 3) return abd_fail(ctx, ABD_E_INVALID, "rigidity must be 0, 1 or 2");
   double *eb;
   ABD_TRY(ws(ctx, "body_e", sc->n_bodies, &eb, s));
   if (grad || diag)
@@ -411,18 +608,22 @@ static int body_terms(abd_ctx *ctx, const abd_scene *sc, const double *q, const 
                        sc->body_fixed, sc->mass, sc->volume, q, qt, kappa_o, w, do_inertia, do_ortho, project, 0, eb,
                        nullptr, nullptr, (int64_t)0);
   HIP_TRY(ctx, hipGetLastError());
+  if (kappa_j > 0.0 && sc->n_joints > 0)
+    ABD_TRY(op_joint_body(ctx, sc, kappa_j * w, q, 1, 0, eb, 0, grad, diag, s));
   if (energy) ABD_TRY(reduce_sum_f64(ctx, eb, sc->n_bodies, energy, s));
   return ABD_OK;
 }
 
 int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
                   double *energy, double *grad, double *diag, int project, hipStream_t s) {
-  return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, project, energy, grad, diag, s);
+  return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1 + prm->rigidity, project, energy, grad, diag,
+                    s, prm->kappa_j);
 }
 
 int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
                    double *energy, hipStream_t s) {
-  return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, energy, nullptr, nullptr, s);
+  return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1 + prm->rigidity, 0, energy, nullptr, nullptr,
+                    s, prm->kappa_j);
 }
 
 int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int n_trials, double *x,
@@ -443,9 +644,12 @@ int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
   double *eb = items;
   if (!eb) ABD_TRY(ws(ctx, "body_e_tr", (size_t)nb * n_trials, &eb, s));
   hipLaunchKernelGGL(k_body_terms<0>, dim3(grid_for(nb, 64), n_trials), dim3(64), 0, s, nb, sc->body_fixed, sc->mass,
-                     sc->volume, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, 0, eb, nullptr, nullptr,
+                     sc->volume, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1 + prm->rigidity, 0, 0, eb, nullptr, nullptr,
                      items ? estride : (int64_t)0);
   HIP_TRY(ctx, hipGetLastError());
+  if (prm->kappa_j > 0.0 && sc->n_joints > 0)
+    ABD_TRY(op_joint_body(ctx, sc, prm->kappa_j * prm->dt * prm->dt, q, n_trials, 12 * (int64_t)nb, eb,
+                          items ? estride : (int64_t)nb, nullptr, nullptr, s));
   if (items) return ABD_OK;
   return seg_sum_trials(ctx, eb, nb, nb, sc->body_scene, n_trials, S, energy, s);
 }
@@ -454,7 +658,8 @@ int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
                           const double *qt, double *energy, hipStream_t s) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   if (S <= 1) return op_body_energy(ctx, sc, prm, q, qt, energy, s);
-  ABD_TRY(body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1, 0, nullptr, nullptr, nullptr, s));
+  ABD_TRY(body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1 + prm->rigidity, 0, nullptr, nullptr, nullptr,
+                     s, prm->kappa_j));
   double *eb;
   ABD_TRY(ws(ctx, "body_e", sc->n_bodies, &eb, s));
   return seg_sum_scenes(ctx, eb, sc->body_scene, sc->n_bodies, S, energy, s);
@@ -462,7 +667,7 @@ int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
 
 int op_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,
                      double *energy, double *grad, double *diag, int project, hipStream_t s) {
-  return body_terms(ctx, sc, q, nullptr, prm->kappa_o, weight, 0, 1, project, energy, grad, diag, s);
+  return body_terms(ctx, sc, q, nullptr, prm->kappa_o, weight, 0, 1 + prm->rigidity, project, energy, grad, diag, s);
 }
 
 int op_inertia(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double *energy, double *grad,

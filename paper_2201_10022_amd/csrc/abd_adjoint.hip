@@ -118,6 +118,8 @@ int op_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, co
   ABD_TRY(zero_d(ctx, e, 1, s));
   ABD_TRY(op_body_terms(ctx, sc, prm, q_next, qt, e, g, diag, 0, s));
   ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 0, nullptr, nullptr, s, fr));
+  if (sc->n_joints > 0 && prm->kappa_j > 0.0)
+    ABD_TRY(op_joint_off(ctx, sc, prm->kappa_j * prm->dt * prm->dt, keys, nk, off, s));
   ABD_TRY(op_read_err(ctx, s));
 
   // preconditioner: diagonal blocks of the projected (PSD) Hessian

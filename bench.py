@@ -26,6 +26,8 @@ Other workloads:
                         lagged friction), timed after the spheres landed
     --workload chains   64 interlocked links in 8 chains (640,000
                         vertices), dt 5e-3, dhat 5e-4
+    --workload wrecking a ball on an 8-link chain swung into a wall of 560
+                        cubes (570 bodies), timed over the impact
     --workload adjoint  gradient of a position loss after --steps steps of
                         the 500-icosphere drop w.r.t. the initial velocities
 
@@ -76,15 +78,21 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size (for counter calibration) before timing")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", choices=("batched", "box", "chains", "adjoint"), default="batched",
+    ap.add_argument("--workload", choices=("batched", "box", "chains", "wrecking", "adjoint"), default="batched",
                     help="batched: 256 independent drop scenes in one launch sequence, against a per-scene loop "
                          "of the same library (default); box: the 1000-icosphere box drop; chains: 64 "
-                         "interlocked links; adjoint: gradient of a position loss after --steps steps of the "
+                         "interlocked links; wrecking: a ball on a chain swung into a wall of 560 cubes; "
+                         "adjoint: gradient of a position loss after --steps steps of the "
                          "500-icosphere drop w.r.t. the initial velocities")
     ap.add_argument("--adj-rtol", type=float, default=1e-8, help="adjoint: PCG relative residual of the adjoint solves")
     ap.add_argument("--checkpoint-every", type=int, default=10)
     ap.add_argument("--loop-scenes", type=int, default=8,
                     help="batched: scenes (evenly spaced) run one at a time for the per-scene baseline")
+    ap.add_argument("--tune", choices=("table", "auto", "default"), default="table",
+                    help="launch shapes: the committed autotuned table for the workload (default), a fresh "
+                         "autotuner run on the workload's state after the warm-up (untimed), or the library's "
+                         "defaults")
+    ap.add_argument("--tune-steps", type=int, default=10, help="--tune auto: time steps per trial")
     ap.add_argument("--start-at", type=float, default=0.0,
                     help="start the timed steps this many seconds after process start (so a profiler's "
                          "collection period can cover exactly the timed steps)")
@@ -306,6 +314,26 @@ def line_common(args, wall, tot, ks, steps):
     }
 
 
+TUNE_TABLE = os.path.join(ROOT, "paper_2201_10022_amd", "tune_mi355x.json")
+
+
+def apply_tune(args, ctx, sc, P, q, qd, workload):
+    """Sets the context's launch-shape table; returns (table, source)."""
+    if args.tune == "default":
+        return ctx.tune_get(), "library defaults"
+    if args.tune == "auto":
+        table, ms = ctx.autotune(sc, P, q, qd, n_steps=args.tune_steps, reps=2)
+        return table, f"autotuned in this run ({ms:.2f} ms per step over {args.tune_steps} steps from here)"
+    entry = None
+    if os.path.exists(TUNE_TABLE):
+        with open(TUNE_TABLE) as f:
+            entry = json.load(f).get(workload)
+    if entry is None:
+        return ctx.tune_get(), "library defaults (no committed table for this workload)"
+    ctx.tune_set(entry["table"])
+    return ctx.tune_get(), "committed autotuned table (paper_2201_10022_amd/tune_mi355x.json)"
+
+
 def attach_traffic(line, workload):
     roof = line["roofline"]
     kname = "pcg_round" if roof["kernel"].startswith("pcg_round") else roof["kernel"]
@@ -336,11 +364,13 @@ def box_line(args, pre, warmup, steps, quiet=False):
                       f"{time.perf_counter() - t0:.1f}s")
     for i in range(warmup):
         ctx.time_step(sc, P, q, qd)
+    tune = apply_tune(args, ctx, sc, P, q, qd, "box")
     torch.cuda.synchronize()
     wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, steps)
     ctx.close()
     line = line_common(args, wall, tot, ks, steps)
     line["warmup"] = warmup
+    line["tune"] = {"table": tune[0], "source": tune[1]}
     line["config"] = {"workload": "icosphere box drop: 1000 icospheres (subdivision 2) + fixed 12-quad box, "
                                   f"dt 1e-2, dhat 1e-3, lagged friction mu {P['mu']}",
                       "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])), "tris": int(len(S["tris"])),
@@ -363,11 +393,13 @@ def chains_line(args, warmup, steps):
     qd = torch.as_tensor(S["qd0"], device="cuda:0")
     for i in range(warmup):
         ctx.time_step(sc, P, q, qd)
+    tune = apply_tune(args, ctx, sc, P, q, qd, "chains")
     torch.cuda.synchronize()
     wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, steps)
     ctx.close()
     line = line_common(args, wall, tot, ks, steps)
     line["warmup"] = warmup
+    line["tune"] = {"table": tune[0], "source": tune[1]}
     line["config"] = {"workload": "interlocked chains: 8 chains x 8 links (major 0.3, minor 0.1, 200 x 50 "
                                   "grid, stadium links), end links fixed, dt 5e-3, dhat 5e-4, frictionless",
                       "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])), "tris": int(len(S["tris"])),
@@ -375,6 +407,96 @@ def chains_line(args, warmup, steps):
     line["steps_per_s"] = steps / wall
     attach_traffic(line, "chains")
     return line
+
+
+def wrecking_line(args, pre, warmup, steps):
+    """The wrecking-ball-shaped workload: `pre` untimed steps (the ball
+    swings down), `warmup` more, then `steps` timed steps (the impact)."""
+    import torch
+
+    import paper_2201_10022_amd as abd
+
+    S, P = sg.wrecking_ball()
+    ctx, sc = abd.setup(S, 0)
+    q = torch.as_tensor(S["q0"], device="cuda:0")
+    qd = torch.as_tensor(S["qd0"], device="cuda:0")
+    for i in range(pre + warmup):
+        ctx.time_step(sc, P, q, qd)
+    tune = apply_tune(args, ctx, sc, P, q, qd, "wrecking")
+    torch.cuda.synchronize()
+    wall, tot, ks = timed_steps(args, ctx, sc, P, q, qd, steps)
+    ctx.close()
+    line = line_common(args, wall, tot, ks, steps)
+    line["warmup"] = warmup
+    line["tune"] = {"table": tune[0], "source": tune[1]}
+    line["config"] = {"workload": "wrecking ball: wall of 560 cubes on a ground quad, 65 kg ball with an eyelet on "
+                                  "an 8-link chain from a fixed pivot, swung 60 degrees, dt 1e-2, dhat 1e-3, "
+                                  "frictionless", "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])),
+                      "tris": int(len(S["tris"])), "edges": int(len(S["edges"])), "pre_steps": pre}
+    line["steps_per_s"] = steps / wall
+    attach_traffic(line, "wrecking")
+    return line
+
+
+def run_wrecking(args):
+    wait_start(args)
+    line = wrecking_line(args, args.pre if args.pre != 60 else 40, args.warmup, args.steps)
+    print(json.dumps(line), flush=True)
+
+
+def rigidity_ops(args, reps=50):
+    """Energy operations of the three rigidity potentials (energy, gradient
+    and PSD-projected 9x9 Hessian per body; sec. 3.2 compares V_perp with
+    ARAP and neo-Hookean) on the batched workload's 26,914 bodies, each A a
+    seeded random rotation times (I + 0.05 N(0,1)): mean kernel time per
+    call from torch events on the library's stream, and the time of each
+    alternative over V_perp's."""
+    import torch
+
+    import paper_2201_10022_amd as abd
+
+    S, P = sg.batched_drops()
+    ctx, sc = abd.setup(S, 0)
+    rng = np.random.default_rng(11)
+    q = S["q0"].copy()
+    for b in np.flatnonzero(S["body_fixed"] == 0):
+        Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        q[b, 3:] = (Q * np.sign(np.linalg.det(Q)) @ (np.eye(3) + 0.05 * rng.normal(size=(3, 3)))).reshape(9)
+    import ctypes
+    qg = torch.as_tensor(q, device="cuda:0")
+    nbt = len(S["q0"])
+    e = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    g = torch.zeros((nbt, 12), dtype=torch.float64, device="cuda:0")
+    D = torch.zeros((nbt, 144), dtype=torch.float64, device="cuda:0")
+    out = {}
+    for kind, name in ((0, "orthogonality"), (1, "arap"), (2, "neo_hookean")):
+        prm = abd.make_params(dict(P, rigidity=kind))
+
+        def call():
+            # (accumulates into the same buffers: only the library's kernels run)
+            ctx._check(ctx.L.abd_orthogonality(ctx.h, ctypes.byref(sc.c), ctypes.byref(prm), abd._ptr(qg),
+                                               P["dt"] ** 2, abd._ptr(e), abd._ptr(g), abd._ptr(D), 1,
+                                               abd._stream()))
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            call()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_call": a.elapsed_time(b) / reps}
+    ctx.close()
+    nb = int((S["body_fixed"] == 0).sum())
+    base = out["orthogonality"]["ms_per_call"]
+    for name, v in out.items():
+        v["ns_per_body"] = 1e6 * v["ms_per_call"] / nb
+        v["time_over_orthogonality"] = v["ms_per_call"] / base
+    out["bodies"] = nb
+    out["op"] = ("energy + gradient + PSD-projected Hessian per body (one abd_orthogonality call: the body-terms "
+                 "kernel and the energy sum)")
+    return out
 
 
 def run_box(args):
@@ -412,6 +534,7 @@ def run_batched(args):
     qd = torch.as_tensor(S["qd0"], device="cuda:0")
     for i in range(args.warmup):
         ctx.time_step(sc, P, q, qd)
+    tune = apply_tune(args, ctx, sc, P, q, qd, "batched")
     torch.cuda.synchronize()
     wait_start(args)
     calib_copy(args)
@@ -424,6 +547,7 @@ def run_batched(args):
                       "scenes": n_sc, "bodies": int(len(S["q0"])), "verts": int(len(S["xbar"])),
                       "tris": int(len(S["tris"])), "edges": int(len(S["edges"]))}
     line["steps_per_s"] = steps / wall
+    line["tune"] = {"table": tune[0], "source": tune[1]}
     attach_traffic(line, "batched")
     if args.timed_only:
         print(json.dumps(line), flush=True)
@@ -434,6 +558,7 @@ def run_batched(args):
     for k in pick:
         Sk = sg.sub_scene(S, int(k))
         ck, sk = abd.setup(Sk, 0)
+        ck.tune_set(tune[0])
         qk = torch.as_tensor(Sk["q0"], device="cuda:0")
         qdk = torch.as_tensor(Sk["qd0"], device="cuda:0")
         for i in range(args.warmup):
@@ -458,9 +583,14 @@ def run_batched(args):
         bl = box_line(args, 60, 2, 5, quiet=True)
         log(args, "extra: chains")
         cl = chains_line(args, 2, 5)
+        log(args, "extra: wrecking ball")
+        wl = wrecking_line(args, 40, 2, 10)
         keep = ("value", "unit", "ms_per_step", "steps_per_s", "newton_iters_per_s", "newton_iters", "steps",
                 "warmup", "pair_evals", "pcg_iters", "roofline", "pair_kernels", "config")
-        line["other_configs"] = {"box": {k: bl[k] for k in keep}, "chains": {k: cl[k] for k in keep}}
+        line["other_configs"] = {"box": {k: bl[k] for k in keep}, "chains": {k: cl[k] for k in keep},
+                                 "wrecking": {k: wl[k] for k in keep}}
+        log(args, "extra: rigidity potentials")
+        line["rigidity_ops"] = rigidity_ops(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, batched_sample(S, P), P)
     print(json.dumps(line), flush=True)
@@ -523,6 +653,8 @@ def main():
         run_adjoint(args)
     elif args.workload == "chains":
         run_chains(args)
+    elif args.workload == "wrecking":
+        run_wrecking(args)
     else:
         run_box(args)
 

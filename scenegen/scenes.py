@@ -57,6 +57,12 @@ class SceneBuilder:
 
     def __init__(self):
         self.bodies = []
+        self.joints = []
+
+    def joint(self, a, b, pa, pb):
+        """A joint making body a's body-frame point pa coincide with body b's
+        point pb (b = -1: with the fixed world point pb)."""
+        self.joints.append((int(a), int(b), np.asarray(pa, np.float64), np.asarray(pb, np.float64)))
 
     def add(self, verts, tris, R=None, p=(0, 0, 0), fixed=False, density=1000.0,
             qd=None, scene=0):
@@ -109,14 +115,17 @@ class SceneBuilder:
             density=np.array(dens, np.float64),
             q0=np.ascontiguousarray(np.array(q0, np.float64)),
             qd0=np.ascontiguousarray(np.array(qd0, np.float64)),
+            joint_body=np.array([[a, b] for a, b, _, _ in self.joints], np.int32).reshape(-1, 2),
+            joint_point=np.array([[pa, pb] for _, _, pa, pb in self.joints], np.float64).reshape(-1, 2, 3),
         )
 
 
 def default_params(**kw):
     """Method parameters.  kappa_b is the barrier stiffness (fixed per
     scene), kappa_o the orthogonality stiffness (multiplied by body volume),
+    kappa_j the joint penalty stiffness (N/m),
     ccd_s / ccd_tmax / ccd_max_iter the additive-CCD constants."""
-    p = dict(dt=1e-2, dhat=1e-3, kappa_b=80.0, kappa_o=1e8, mu=0.0, eps_v=1e-3,
+    p = dict(dt=1e-2, dhat=1e-3, kappa_b=80.0, kappa_o=1e8, kappa_j=1e7, mu=0.0, eps_v=1e-3,
              gravity=GRAVITY, newton_tol=1e-5, pcg_rtol=1e-10, ccd_s=0.1,
              ccd_tmax=1.0, ccd_max_iter=10000, max_newton=100, max_pcg=5000,
              max_ls=40, steps=100)
@@ -230,6 +239,99 @@ def torus_chains(seed=3, n_chains=8, n_links=8, n_major=200, n_minor=50,
     m_link = 1000.0 * 2.0 * math.pi ** 2 * Rm * rm ** 2
     kappa = m_link * 0.5 * 5e-3 / ((0.5 + math.log(2.0)) * 5e-4)
     params = default_params(dt=5e-3, dhat=5e-4, kappa_b=round(kappa), mu=0.0, steps=100)
+    return scene, params
+
+
+def wrecking_ball(seed=8, n_wide=28, n_high=20, half=0.05, n_links=8, theta0=math.pi / 3):
+    """A wall of n_wide x n_high cubes (half-edge `half`, one deep) stacked
+    on a fixed ground quad, and a ball swinging into it on a chain: the
+    shape of the paper's wrecking-ball scene (sec. 5, Tab. tab:time: 575
+    bodies, 14K triangles) from generated shapes only.
+
+    Wall: the front face at x = 0.27, columns along z with 2e-3 gaps, each
+    cube U[2e-4, 6e-4] above the one below (the bottom row above the
+    ground), tilted by at most 2e-4 rad: every cube rests within dhat of its
+    support.  Chain: n_links stadium links (major 0.06, minor 0.02, 24 x 8
+    grid; straight sections 6 minor - 2 major + 3 gap so that the two tubes
+    in a link's hole are 2e-3 apart, as in the chain workload), alternating
+    flat / upright along the chain direction u, link 0 fixed at the pivot
+    (0, 2.3, 0), the chain straight and swung theta0 from the vertical
+    towards -x.  Ball: one body made of an icosphere (subdivision 3, radius
+    0.25) and an eyelet ring (a link) interlocked with the last link, the
+    sphere 1 cm beyond the ring along u.  At rest; gravity swings the ball
+    into the wall after about 0.5 s.  Draw order: per cube (z-major, then
+    y): vertical gap, tilt axis (3), tilt angle."""
+    rng = np.random.default_rng(seed)
+    gv, gt = meshes.ground_quad(6.0)
+    cv, ct = meshes.cube(half)
+    Rm, rm, gap = 0.06, 0.02, 2e-3
+    straight = 6 * rm - 2 * Rm + 3 * gap
+    lv, lt = meshes.torus(Rm, rm, 24, 8, straight=straight)
+    pitch = straight + 2 * Rm - 2 * rm - gap
+    sb = SceneBuilder()
+    sb.add(gv, gt, fixed=True)
+    x_face, zgap = 0.27, 2e-3
+    for k in range(n_wide):
+        y = 0.0
+        for j in range(n_high):
+            y += rng.uniform(2e-4, 6e-4)
+            R = random_rotation(rng, 2e-4)
+            w = cv @ R.T
+            z = (k - (n_wide - 1) / 2.0) * (2 * half + zgap)
+            sb.add(cv, ct, R=R, p=(x_face - w[:, 0].min(), y - w[:, 1].min(), z))
+            y += w[:, 1].max() - w[:, 1].min()
+    u = np.array([-math.sin(theta0), -math.cos(theta0), 0.0])
+    zz = np.array([0.0, 0.0, 1.0])
+    v = np.cross(zz, u)
+    flat = np.stack([u, v, zz], 1)               # local x -> u, ring plane u-z
+    upright = np.stack([u, zz, np.cross(u, zz)], 1)  # ring plane u-v
+    pivot = np.array([0.0, 2.3, 0.0])
+    for l in range(n_links):
+        sb.add(lv, lt, R=flat if l % 2 == 0 else upright, p=pivot + l * pitch * u, fixed=(l == 0))
+    bv, bt = meshes.icosphere(3, 0.25)
+    reach = straight / 2 + Rm + rm + 0.01 + 0.25  # ring centre to sphere centre
+    ball_v = np.concatenate([lv, bv + np.array([reach, 0.0, 0.0])])
+    ball_t = np.concatenate([lt, bt + len(lv)])
+    sb.add(ball_v, ball_t, R=flat if n_links % 2 == 0 else upright, p=pivot + n_links * pitch * u)
+    scene = sb.build()
+    # kappa_b by the landing rule of the icosphere box for the ball (65 kg
+    # meeting the wall at about 3.3 m/s, stopped near dhat/2)
+    m_ball = 1000.0 * 4.0 / 3.0 * math.pi * 0.25 ** 3
+    kappa = m_ball * 3.3 * 1e-2 / ((0.5 + math.log(2.0)) * 1e-3)
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=round(kappa, -1), mu=0.0, steps=100,
+                            newton_tol=1e-2 * math.sqrt(3.0), max_newton=500, pcg_rtol=1e-2)
+    return scene, params
+
+
+def hinged_chain(n_links=5, length=0.4, width=0.1, gap=0.01, theta0=math.pi / 4, n_chains=1, spacing=0.5):
+    """n_chains chains of n_links box links (length x width x width, each
+    shortened by `gap` at both ends) joined end to end by hinges about z,
+    the first link hinged to a fixed world axis at (0, 2, 0), the chain
+    straight and swung theta0 from the vertical towards -x: the paper's
+    pendulum (two links) and octopus-tentacle (five joints) mechanisms
+    (sec. 5.3, Fig. rotation) from generated shapes.  A hinge is two joints,
+    at z = +-width/2 on its axis.  Chains are `spacing` apart along z.  No
+    random draws."""
+    cv, ct = meshes.cube(0.5)
+    lv = cv * np.array([length - 2 * gap, width, width])
+    u = np.array([-math.sin(theta0), -math.cos(theta0), 0.0])
+    zz = np.array([0.0, 0.0, 1.0])
+    R = np.stack([u, np.cross(zz, u), zz], 1)
+    sb = SceneBuilder()
+    hz = width / 2
+    for c in range(n_chains):
+        pivot = np.array([0.0, 2.0, (c - (n_chains - 1) / 2.0) * spacing])
+        first = len(sb.bodies)
+        for l in range(n_links):
+            sb.add(lv, ct, R=R, p=pivot + (l + 0.5) * length * u)
+        for s_ in (-hz, hz):
+            sb.joint(first, -1, (-length / 2, 0.0, s_), pivot + (0.0, 0.0, s_))
+            for l in range(n_links - 1):
+                sb.joint(first + l, first + l + 1, (length / 2, 0.0, s_), (-length / 2, 0.0, s_))
+    scene = sb.build()
+    # kappa_b by the landing rule: a 3.8 kg link meeting its neighbour at
+    # 3 m/s is stopped near dhat/2
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=100.0, kappa_j=1e7, mu=0.0, steps=100, newton_tol=1e-5)
     return scene, params
 
 
@@ -429,6 +531,7 @@ def icosphere_fcc(seed=7, cells=(5, 10, 5), radius=0.06, gap=5e-5):
 
 CONFIGS = {
     "three_cubes": three_cubes,
+    "wrecking_ball": wrecking_ball,
     "icosphere_box": icosphere_box,
     "torus_chains": torus_chains,
     "batched_drops": batched_drops,

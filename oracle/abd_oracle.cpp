@@ -571,7 +571,7 @@ int ora_candidates(int nb, int nv, int nt, int ne, const int32_t* body_vert_off,
   // body pairs split over threads; the lists are sorted afterwards, so the
   // result does not depend on the split
   std::vector<std::pair<int32_t, int32_t>> P, E;
-#pragma omp parallel
+#pragma omp parallel if (nb >= 64)
   {
     std::vector<std::pair<int32_t, int32_t>> Pl, El;
 #pragma omp for schedule(dynamic, 4) nowait
@@ -617,7 +617,7 @@ int ora_candidates(int nb, int nv, int nt, int ne, const int32_t* body_vert_off,
 void ora_classify(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, const int32_t* edges,
                   const double* x, double dhat, uint8_t* type, double* d2, uint8_t* active) {
   const double dhat2 = dhat * dhat;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 4096)
   for (int64_t i = 0; i < n; ++i) {
     int vid[4];
     pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
@@ -660,7 +660,7 @@ int64_t ora_barrier(int64_t n, int is_ee, const int32_t* pairs, const int32_t* v
   std::vector<PairOut> out((size_t)std::min<int64_t>(CH, std::max<int64_t>(n, 1)));
   for (int64_t c0 = 0; c0 < n; c0 += CH) {
     const int64_t m = std::min(CH, n - c0);
-#pragma omp parallel for schedule(dynamic, 8)
+#pragma omp parallel for schedule(dynamic, 8) if (m >= 64)
     for (int64_t j = 0; j < m; ++j) {
       const int64_t i = c0 + j;
       PairOut& o = out[(size_t)j];
@@ -752,7 +752,7 @@ double ora_barrier_energy(int64_t n, int is_ee, const int32_t* pairs, const int3
   // per-pair terms in parallel (NaN marks a pair at zero distance), summed
   // in pair order
   std::vector<double> term((size_t)std::max<int64_t>(n, 1), 0.0);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 1024)
   for (int64_t i = 0; i < n; ++i) {
     int vid[4];
     pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);
@@ -807,7 +807,7 @@ double ora_barrier_energy(int64_t n, int is_ee, const int32_t* pairs, const int3
 void ora_ccd(int64_t n, int is_ee, const int32_t* pairs, const int32_t* tris, const int32_t* edges,
              const double* x, const double* dx, double s, double tmax, int max_iter, double* tout,
              int32_t* iters_out) {
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 64) if (n >= 1024)
   for (int64_t i = 0; i < n; ++i) {
     int vid[4];
     pair_verts(is_ee, pairs + 2 * i, tris, edges, vid);

@@ -187,8 +187,8 @@ def roofline(ks):
     dom = max(("pcg_round", "barrier_local", "accd"), key=lambda k: ks[k]["ms"])
     avg_ms, units = per_launch(dom)
     if dom == "pcg_round":
-        roof = {"kernel": "pcg_round (one hipGraph replay of 16 or 64 PCG iterations, one k_cg_iter each, "
-                          "+ k_cg_advance)", "bound": "hbm",
+        roof = {"kernel": "pcg_round (one hipGraph replay of pcg_short or pcg_long PCG iterations of the launch "
+                          "table, one k_cg_iter each, + k_cg_compact for a batch + k_cg_advance)", "bound": "hbm",
                 "achieved": units / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "bytes_per_launch": units, "launches": ks[dom]["launches"]}
     elif dom == "barrier_local":

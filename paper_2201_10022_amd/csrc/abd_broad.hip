@@ -497,6 +497,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     HIP_TRY(ctx, hipStreamSynchronize(s));
     nbp = hbuf[0];
     list_total = hbuf[1];
+    ABD_TRY(mirror_counts_ok(ctx, {nbp, list_total}, "candidates"));
     if (nbp <= cap_bp) break;
     if (pass > 0) return abd_fail(ctx, ABD_E_INVALID, "candidates: body-pair count changed between passes");
     cap_bp = nbp;
@@ -549,6 +550,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     // hbuf[4] = all pairs, hbuf[5] = PT pairs
     ABD_TRY(scan_exclusive_i64(ctx, ccnt, coff, cap_tp + cap_te, otot, s, hbuf_d + 4, cap_tp));
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    ABD_TRY(mirror_counts_ok(ctx, {hbuf[2], hbuf[3], hbuf[4], hbuf[5]}, "candidates"));
     ntile_pt = hbuf[3];
     ntile_ee = hbuf[2] - hbuf[3];
     if (ntile_pt <= cap_tp && ntile_ee <= cap_te) break;
@@ -754,6 +756,7 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
     }
     HIP_TRY(ctx, hipStreamSynchronize(s));
     *n_keys = hbuf[MIR_OFFDIAG];
+    ABD_TRY(mirror_counts_ok(ctx, {*n_keys}, "offdiag"));
     return abd_hip_check(ctx, hipGetLastError(), "offdiag");
   }
   int64_t at = 0;
@@ -775,6 +778,7 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   hipLaunchKernelGGL(k_unique_write, dim3(grid_for(n, 256)), dim3(256), 0, s, n, k2, flag, pos, *keys_out);
   HIP_TRY(ctx, hipStreamSynchronize(s));
   *n_keys = hbuf[MIR_OFFDIAG];
+  ABD_TRY(mirror_counts_ok(ctx, {*n_keys}, "offdiag"));
   return abd_hip_check(ctx, hipGetLastError(), "offdiag");
 }
 
@@ -861,6 +865,7 @@ int op_candidates_within(abd_ctx *ctx, const abd_scene *sc, const double *x, dou
   ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s, h_d + MIR_COMPACT, n_spt));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   const int64_t keep = h[0], keep_pt = h[1];
+  ABD_TRY(mirror_counts_ok(ctx, {keep, keep_pt}, "candidates_within"));
   ABD_TRY(ws(ctx, pn.c_str(), 2 * keep_pt + 2, pt_out, s));
   ABD_TRY(ws(ctx, en.c_str(), 2 * (keep - keep_pt) + 2, ee_out, s));
   const int64_t *nkp = n_see > 0 ? pos + n_spt : tot;

@@ -77,6 +77,12 @@ int pinned_get_nt(abd_ctx *ctx, size_t bytes, void **out, void **dev) {
   return ABD_OK;
 }
 
+int mirror_counts_ok(abd_ctx *ctx, std::initializer_list<int64_t> counts, const char *where) {
+  for (int64_t c : counts)
+    if (c < 0) return abd_fail(ctx, ABD_E_HIP, "%s: a look-back scan did not complete", where);
+  return ABD_OK;
+}
+
 int mirror_get(abd_ctx *ctx, int64_t **host, int64_t **dev) {
   if (!ctx->mirror_h) {
     void *h = nullptr, *d = nullptr;
@@ -219,12 +225,12 @@ __global__ void __launch_bounds__(LB_T) k_scan_lb(const int64_t *in, int64_t *ou
   for (int k = 0; k < LB_U; ++k) {
     if (i0 + k < n) {
       out[i0 + k] = run;
-      if (host && i0 + k == split) host[1] = run;
+      if (host && i0 + k == split) host[1] = s_prefix < 0 ? -1 : run;  // (-1: a failed look-back)
     }
     run += v[k];
   }
   if (t == 0 && (tile + 1) * LB_TILE >= n) {  // the last tile
-    const int64_t tot = s_prefix + s_agg;
+    const int64_t tot = s_prefix < 0 ? -1 : s_prefix + s_agg;
     if (total) *total = tot;
     if (host) {
       host[0] = tot;

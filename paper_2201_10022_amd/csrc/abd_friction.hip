@@ -763,6 +763,7 @@ static int friction_begin(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
     ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s, h_d + MIR_COMPACT, npt));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     const int64_t keep = h[0], keep_pt = h[1];
+    ABD_TRY(mirror_counts_ok(ctx, {keep, keep_pt}, "friction"));
     // the PT count the compaction needs is pos[npt] (or the total)
     const int64_t *n_keep_pt_dev = nee > 0 ? pos + npt : tot;
     int32_t *fpt, *fee;

@@ -1,5 +1,6 @@
 // Internal declarations of the gfx950 ABD library (not part of the ABI).
 #pragma once
+#include <initializer_list>
 
 #include <hip/hip_runtime.h>
 
@@ -127,6 +128,9 @@ constexpr int MIR_OFFDIAG = 8;   // 1 slot: off-diagonal key count
 constexpr int MIR_COMPACT = 12;  // 2 slots: compaction total and PT count
 constexpr int MIR_PCG = 16;      // 2 slots (4 ints): PCG iteration state
 int mirror_get(abd_ctx *ctx, int64_t **host, int64_t **dev);
+// Counts that a scan wrote to mapped host memory are -1 when its look-back
+// failed; a host that sizes buffers from them calls this first.
+int mirror_counts_ok(abd_ctx *ctx, std::initializer_list<int64_t> counts, const char *where);
 // at least `words` zero-or-stale look-back status words and a new tag for
 // one launch (abd_lookback.h)
 int lb_prepare(abd_ctx *ctx, int64_t words, unsigned long long **status, unsigned int *tag, hipStream_t s);

@@ -8,7 +8,11 @@
 // restarts when a block finds it tagged with an earlier launch.  A tile
 // waits only on tiles claimed before it, whose blocks are running and
 // publish their own sum without waiting, so every wait ends; a spin cap
-// (error bit 16) bounds the waits regardless.  Values must stay below 2^42.
+// (error bit 16) bounds the waits regardless.  A tile that hits the cap
+// publishes the poison value LB_VAL_MASK as its inclusive prefix, and every
+// tile after it that reads a poisoned word returns the prefix -1, so a scan
+// whose look-back failed ends with a total of -1 that the host rejects
+// instead of sizing buffers from it.  Values must stay below 2^42 - 1.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -62,6 +66,7 @@ __device__ __forceinline__ int64_t lb_lookback(unsigned long long *status, int64
   }
   if (lane == 0) lb_publish(status + tile, tag, 0, agg);
   int64_t p = 0, j0 = tile - 1;
+  bool poisoned = false;
   for (int spin = 0;;) {
     const int64_t j = j0 - lane;
     bool ready = true;
@@ -79,14 +84,19 @@ __device__ __forceinline__ int64_t lb_lookback(unsigned long long *status, int64
     if (__ballot(!ready) & need) {
       if (++spin > LB_SPIN_CAP) {
         if (lane == 0) atomicOr(err, 16);
+        poisoned = true;
         break;
       }
       continue;
+    }
+    if (__ballot(lane <= first && val == (int64_t)LB_VAL_MASK)) {
+      poisoned = true;
+      break;
     }
     p += lb_wave_sum(lane <= first ? val : 0);
     if (first < 64) break;
     j0 -= 64;
   }
-  if (lane == 0) lb_publish(status + tile, tag, 1, p + agg);
-  return p;
+  if (lane == 0) lb_publish(status + tile, tag, 1, poisoned ? (int64_t)LB_VAL_MASK : p + agg);
+  return poisoned ? -1 : p;
 }

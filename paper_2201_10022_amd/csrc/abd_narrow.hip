@@ -373,6 +373,7 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
     HIP_TRY(ctx, hipStreamSynchronize(s));
     na = hbuf[0];
     na_pt = hbuf[1];
+    ABD_TRY(mirror_counts_ok(ctx, {na, na_pt}, "barrier"));
   }
   if (n_active_pt) *n_active_pt = na_pt;
   if (n_active_ee) *n_active_ee = na - na_pt;

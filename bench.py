@@ -444,6 +444,55 @@ def run_wrecking(args):
     print(json.dumps(line), flush=True)
 
 
+def culling_ops(args, reps=10):
+    """The candidate search (body boxes, i-AABB lists, tiled primitive-pair
+    box tests, both passes) with the single i-AABB and with the three-level
+    tree per i-AABB (sec. 4.2, Fig. iBVH), on the interlocked links in
+    contact swept over one step of their initial velocities (entangled: the
+    links' i-AABBs hold whole arcs of both tori) and on the box drop's
+    landing state: host wall time per call (the call synchronises to read
+    its counts), best of `reps`, and the primitive-pair box tests each
+    runs.  Both give the same pairs in the same order."""
+    import torch
+
+    import paper_2201_10022_amd as abd
+
+    out = {}
+    for name, make in (("chains", lambda: sg.torus_chains()), ("box", lambda: sg.icosphere_box())):
+        S, P = make()
+        if name == "chains":
+            q = sg.torus_chains_contact(S, 8)
+        else:
+            S = sg.landed(S, seed=7, dhat=P["dhat"])
+            q = S["q0"]
+        ctx, sc = abd.setup(S, 0)
+        qg = torch.as_tensor(q, device="cuda:0")
+        q1 = torch.as_tensor(q + P["dt"] * S["qd0"], device="cuda:0")
+        x0, x1 = ctx.vertex_map(sc, qg), ctx.vertex_map(sc, q1)
+        res = {}
+        for levels in (1, 3):
+            ctx.tune_set(dict(cull_levels=levels))
+            ctx.candidates(sc, x0, x1, P["dhat"])
+            ctx.profile(True, True)
+            pt, ee = ctx.candidates(sc, x0, x1, P["dhat"])
+            tests = ctx.profile_query("box_tests")["units"]
+            ctx.profile(False, True)
+            best = float("inf")
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.candidates(sc, x0, x1, P["dhat"])
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            res[f"levels_{levels}"] = {"ms_per_call": 1e3 * best, "box_tests": int(tests),
+                                       "pairs": int(len(pt) + len(ee))}
+        ctx.close()
+        res["tests_tree_over_single"] = res["levels_3"]["box_tests"] / max(res["levels_1"]["box_tests"], 1)
+        res["time_tree_over_single"] = res["levels_3"]["ms_per_call"] / res["levels_1"]["ms_per_call"]
+        out[name] = res
+    return out
+
+
 def rigidity_ops(args, reps=50):
     """Energy operations of the three rigidity potentials (energy, gradient
     and PSD-projected 9x9 Hessian per body; sec. 3.2 compares V_perp with
@@ -591,6 +640,8 @@ def run_batched(args):
                                  "wrecking": {k: wl[k] for k in keep}}
         log(args, "extra: rigidity potentials")
         line["rigidity_ops"] = rigidity_ops(args)
+        log(args, "extra: i-AABB culling levels")
+        line["culling_ops"] = culling_ops(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, batched_sample(S, P), P)
     print(json.dumps(line), flush=True)

@@ -391,16 +391,23 @@ int abd_friction_end_step(abd_ctx *ctx);
 
 /* Launch shapes of the hot kernels (the autotuner's table).  No entry
  * changes a result: every kernel computes the same values and lists pairs
- * in the same order for any table.  Defaults {16, 1, 256, 1024, 256, 16, 64}.
+ * in the same order for any table.  Defaults {16, 1, 256, 1024, 256, 16, 64, 1}.
  *   tile_rows       rows per pair-culling tile (one wave): 8, 16, 32, 64
  *   barrier_waves   waves per block of the barrier kernel: 1, 2, 4
  *   ccd_block       threads per block of the CCD kernel: 64, 128, 256
  *   ccd_max_blocks  grid cap of the persistent CCD kernel: 64 .. 16384
  *   energy_block    threads per block of the energy-only kernel: 64 .. 1024 (powers of 2)
  *   pcg_short, pcg_long  PCG iterations per short / long graph replay:
- *                   even, 2 <= pcg_short <= pcg_long <= 256 */
+ *                   even, 2 <= pcg_short <= pcg_long <= 256
+ *   cull_levels     i-AABB culling (sec. 4.2, Fig. iBVH): 1, the single
+ *                   i-AABB per overlapping body pair; 3, a three-level
+ *                   binary AABB tree inside each i-AABB (per culled list:
+ *                   the list, its halves, their quarters; leaf pairs whose
+ *                   boxes are disjoint are not tested).  Both give the
+ *                   same candidate pairs in the same order. */
 typedef struct {
   int32_t tile_rows, barrier_waves, ccd_block, ccd_max_blocks, energy_block, pcg_short, pcg_long;
+  int32_t cull_levels;
 } abd_tune;
 
 /* The context's launch-shape table: get, or set (ABD_E_INVALID for a value
@@ -428,7 +435,10 @@ int abd_autotune(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, doubl
  * launches and the work units processed (active pairs, records, pairs,
  * pairs, tiles; friction pairs for "friction_local"; for "pcg_round", one
  * replay of the captured PCG iterations,
- * the algorithmic HBM bytes of the iterations it executed).
+ * the algorithmic HBM bytes of the iterations it executed); and, with zero
+ * time, "box_tests" / "box_tests_single_level": per candidate-search call,
+ * the primitive-pair box tests run with the table's i-AABB culling, and the
+ * tests a single-level cull would run.
  * Query synchronises the device. */
 int abd_profile(abd_ctx *ctx, int enable, int reset);
 int abd_profile_query(abd_ctx *ctx, const char *kernel, double *ms, int64_t *launches, int64_t *units);

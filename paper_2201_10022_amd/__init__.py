@@ -369,7 +369,11 @@ class Context:
         return t.as_dict()
 
     def tune_set(self, table):
-        t = _lib.AbdTune(**{k: int(v) for k, v in table.items()})
+        """Sets the launch table; entries missing from `table` keep their
+        current values."""
+        cur = self.tune_get()
+        cur.update(table)
+        t = _lib.AbdTune(**{k: int(v) for k, v in cur.items()})
         self._check(self.L.abd_tune_set(self.h, ctypes.byref(t)))
 
     def autotune(self, scene, params, q, qd, n_steps=3, reps=2):

@@ -57,7 +57,7 @@ class AbdStats(ctypes.Structure):
 
 class AbdTune(ctypes.Structure):
     _fields_ = [("tile_rows", _i32), ("barrier_waves", _i32), ("ccd_block", _i32), ("ccd_max_blocks", _i32),
-                ("energy_block", _i32), ("pcg_short", _i32), ("pcg_long", _i32)]
+                ("energy_block", _i32), ("pcg_short", _i32), ("pcg_long", _i32), ("cull_levels", _i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

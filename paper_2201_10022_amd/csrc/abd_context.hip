@@ -611,7 +611,10 @@ void prof_flush(abd_ctx *ctx) {
 extern "C" int abd_profile(abd_ctx *ctx, int enable, int reset) {
   if (!ctx) return ABD_E_INVALID;
   prof_flush(ctx);
-  if (reset) ctx->kstats.clear();
+  if (reset) {
+    ctx->kstats.clear();
+    ctx->prof_box_tests_clear = true;
+  }
   ctx->profiling = enable != 0;
   return ABD_OK;
 }
@@ -621,6 +624,15 @@ extern "C" int abd_profile_query(abd_ctx *ctx, const char *kernel, double *ms, i
   hipDeviceSynchronize();
   prof_flush(ctx);
   auto it = ctx->kstats.find(kernel);
+  const std::string kn(kernel);
+  if (it != ctx->kstats.end() && (kn == "box_tests" || kn == "box_tests_single_level")) {
+    // (device sums: the units of the two entries)
+    auto b = ctx->bufs.find("prof_box_tests");
+    double h[2] = {0.0, 0.0};
+    if (b != ctx->bufs.end() && b->second.ptr)
+      HIP_TRY(ctx, hipMemcpy(h, b->second.ptr, sizeof h, hipMemcpyDeviceToHost));
+    it->second.units = (int64_t)h[kn == "box_tests" ? 0 : 1];
+  }
   *ms = it == ctx->kstats.end() ? 0.0 : it->second.ms;
   *launches = it == ctx->kstats.end() ? 0 : it->second.launches;
   *units = it == ctx->kstats.end() ? 0 : it->second.units;

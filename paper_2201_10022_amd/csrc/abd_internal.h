@@ -43,7 +43,7 @@ struct JointTables {
 struct abd_ctx {
   int device = 0;
   // launch shapes (abd_tune_set / abd_autotune); none changes a result
-  abd_tune tune = {16, 1, 256, 1024, 256, 16, 64};
+  abd_tune tune = {16, 1, 256, 1024, 256, 16, 64, 1};
   // the last op_candidates call marked, per body, whether it is in an
   // overlapping body pair (workspace "bp_involved"); false until it has
   bool involved_valid = false;
@@ -70,6 +70,9 @@ struct abd_ctx {
   hipEvent_t ev[8] = {};
   bool profiling = false;
   std::map<std::string, KStat> kstats;
+  // the device sums of box tests (workspace "prof_box_tests") restart at
+  // the next profiled candidates call
+  bool prof_box_tests_clear = true;
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> ev_pool;
   // captured PCG iterations (short and long replays), re-captured when any

@@ -21,7 +21,7 @@ bool tune_valid(const abd_tune &t) {
   return one_of(t.tile_rows, {8, 16, 32, 64}) && one_of(t.barrier_waves, {1, 2, 4}) &&
          one_of(t.ccd_block, {64, 128, 256}) && t.ccd_max_blocks >= 64 && t.ccd_max_blocks <= 16384 &&
          one_of(t.energy_block, {64, 128, 256, 512, 1024}) && t.pcg_short >= 2 && t.pcg_short % 2 == 0 &&
-         t.pcg_long >= t.pcg_short && t.pcg_long % 2 == 0 && t.pcg_long <= 256;
+         t.pcg_long >= t.pcg_short && t.pcg_long % 2 == 0 && t.pcg_long <= 256 && one_of(t.cull_levels, {1, 3});
 }
 
 }  // namespace
@@ -71,15 +71,16 @@ extern "C" int abd_autotune(abd_ctx *ctx, const abd_scene *sc, const abd_params 
   };
   // candidate values per entry (the struct's order)
   const std::vector<std::vector<int>> cand = {
-      {8, 16, 32, 64}, {1, 2, 4}, {64, 128, 256}, {256, 512, 1024, 2048, 4096}, {128, 256, 512}, {8, 16, 32}};
+      {8, 16, 32, 64}, {1, 2, 4}, {64, 128, 256}, {256, 512, 1024, 2048, 4096}, {128, 256, 512}, {8, 16, 32},
+      {1, 3}};
   abd_tune cur = ctx->tune;
   double best = 0.0;
   int rc = measure(&best);
   for (size_t e = 0; rc == ABD_OK && e < cand.size(); ++e) {
     for (int v : cand[e]) {
       abd_tune t = cur;
-      int32_t *f[6] = {&t.tile_rows, &t.barrier_waves, &t.ccd_block, &t.ccd_max_blocks, &t.energy_block,
-                       &t.pcg_short};
+      int32_t *f[7] = {&t.tile_rows, &t.barrier_waves, &t.ccd_block, &t.ccd_max_blocks, &t.energy_block,
+                       &t.pcg_short, &t.cull_levels};
       if (*f[e] == v) continue;
       *f[e] = v;
       if (e == 5) t.pcg_long = 4 * v;  // (long replays stay 4 short ones)

@@ -5,7 +5,7 @@ derivatives of the simulation method live here.
 """
 from . import meshes, scenes  # noqa: F401
 from .scenes import (CONFIGS, SceneBuilder, default_params, three_cubes,  # noqa: F401
-                     icosphere_box, torus_chains, batched_drops, adjoint_drop,
+                     icosphere_box, torus_chains, torus_chains_contact, batched_drops, adjoint_drop,
                      near_contact_cubes, triangle_soup, random_state, icosphere_resting_layer,
                      cube_on_slope, sub_scene, cube_lattice, icosphere_fcc, landed,
                      wrecking_ball, hinged_chain)

@@ -242,6 +242,21 @@ def torus_chains(seed=3, n_chains=8, n_links=8, n_major=200, n_minor=50,
     return scene, params
 
 
+def torus_chains_contact(scene, n_chains=8, close=1.95e-3, gap=2e-3):
+    """Generalized coordinates of a contact state of `torus_chains` (same
+    n_chains and gap): every upright link (ring in x-y, A's middle diagonal
+    entry 0) moved `close` along +x, towards the next flat link, and the
+    chains moved `close` closer together, so interlocked and side-by-side
+    neighbours sit gap - close apart before the vertex noise."""
+    q = scene["q0"].copy()
+    up = q[:, 4] < 0.5
+    q[up, 0] += close
+    wpitch = 2 * (0.3 + 0.1) + gap
+    c = np.round(q[:, 2] / wpitch + (n_chains - 1) / 2.0)
+    q[:, 2] = (wpitch - close) * (c - (n_chains - 1) / 2.0)
+    return q
+
+
 def wrecking_ball(seed=8, n_wide=28, n_high=20, half=0.05, n_links=8, theta0=math.pi / 3):
     """A wall of n_wide x n_high cubes (half-edge `half`, one deep) stacked
     on a fixed ground quad, and a ball swinging into it on a chain: the

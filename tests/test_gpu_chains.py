@@ -23,10 +23,6 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-LINK_PITCH = 0.404           # along a chain (stadium links, gap 2e-3)
-CHAIN_PITCH = 2 * 0.4 + 2e-3  # across chains
-
-
 @pytest.fixture(scope="module")
 def abd():
     import paper_2201_10022_amd as abd
@@ -49,22 +45,11 @@ def _sorted(a):
     return a[np.lexsort((a[:, 1], a[:, 0]))] if len(a) else a
 
 
-def _contact_state(S, n_chains, close=1.95e-3):
-    """Upright links (ring in x-y: A's middle diagonal entry 0) moved
-    `close` along +x, chain offsets in z shrunk by `close` per chain."""
-    q = S["q0"].copy()
-    up = q[:, 4] < 0.5
-    q[up, 0] += close
-    c = np.round(q[:, 2] / CHAIN_PITCH + (n_chains - 1) / 2.0)
-    q[:, 2] = (CHAIN_PITCH - close) * (c - (n_chains - 1) / 2.0)
-    return q
-
-
 def test_chains_full_size_candidates_barrier_ccd(abd, ctx):
     S, P = sg.torus_chains()
     assert len(S["xbar"]) == 640000 and len(S["tris"]) == 1280000
     sc = abd.Scene(S)
-    q = _contact_state(S, 8)
+    q = sg.torus_chains_contact(S, 8)
     x = oracle.vertex_map(S, q)
     xg = _dev(x)
     pt, ee = oracle.candidates(S, x, None, P["dhat"])

@@ -1,7 +1,8 @@
 """The launch-shape table changes times, not results: a batched Newton
 iteration and a box-drop time step give bit-identical states under
 different tables (tile rows, waves per barrier block, CCD block and grid
-cap, energy block, PCG replay lengths), and the autotuner leaves the
+cap, energy block, PCG replay lengths, single-level or three-level i-AABB
+culling), and the autotuner leaves the
 workload's state unchanged and sets a valid table."""
 import numpy as np
 import pytest
@@ -14,10 +15,11 @@ torch = pytest.importorskip("torch")
 
 TABLES = [
     dict(tile_rows=16, barrier_waves=1, ccd_block=256, ccd_max_blocks=1024, energy_block=256, pcg_short=16,
-         pcg_long=64),
-    dict(tile_rows=8, barrier_waves=4, ccd_block=64, ccd_max_blocks=256, energy_block=128, pcg_short=8, pcg_long=32),
+         pcg_long=64, cull_levels=1),
+    dict(tile_rows=8, barrier_waves=4, ccd_block=64, ccd_max_blocks=256, energy_block=128, pcg_short=8, pcg_long=32,
+         cull_levels=3),
     dict(tile_rows=64, barrier_waves=2, ccd_block=128, ccd_max_blocks=4096, energy_block=512, pcg_short=32,
-         pcg_long=128),
+         pcg_long=128, cull_levels=3),
 ]
 
 

@@ -400,11 +400,13 @@ int abd_friction_end_step(abd_ctx *ctx);
  *   pcg_short, pcg_long  PCG iterations per short / long graph replay:
  *                   even, 2 <= pcg_short <= pcg_long <= 256
  *   cull_levels     i-AABB culling (sec. 4.2, Fig. iBVH): 1, the single
- *                   i-AABB per overlapping body pair; 3, a three-level
- *                   binary AABB tree inside each i-AABB (per culled list:
- *                   the list, its halves, their quarters; leaf pairs whose
- *                   boxes are disjoint are not tested).  Both give the
- *                   same candidate pairs in the same order. */
+ *                   i-AABB per overlapping body pair; 3, inside each
+ *                   i-AABB, three-level binary AABB trees over the culled
+ *                   column primitives (blocks of 256 in index order, their
+ *                   128-halves, their 64-chunks), which each tile of rows
+ *                   descends with its own box, testing only the chunks it
+ *                   reaches.  Both give the same candidate pairs in the
+ *                   same order. */
 typedef struct {
   int32_t tile_rows, barrier_waves, ccd_block, ccd_max_blocks, energy_block, pcg_short, pcg_long;
   int32_t cull_levels;

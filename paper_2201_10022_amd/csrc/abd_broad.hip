@@ -38,6 +38,9 @@ __device__ __forceinline__ bool box_overlap32(const float *a, const double *b) {
          (double)a[2] <= b[5] && b[2] <= (double)a[5];
 }
 
+// list capacities are rounded up to multiples of 64 (chunk alignment)
+__device__ __forceinline__ int64_t round64(int64_t n) { return (n + 63) & ~(int64_t)63; }
+
 // swept box of vertex v over x0 -> x1, inflated upwards
 __device__ __forceinline__ void vert_box(int64_t v, const double *x0, const double *x1, double inflate, double b[6]) {
 #pragma clang fp contract(off)
@@ -211,8 +214,8 @@ __global__ void k_scene_end(int nb, const int32_t *body_scene, int32_t *end) {
 //   0: vertices of a in box(b)   1: triangles of b in box(a)
 //   2: vertices of b in box(a)   3: triangles of a in box(b)
 //   4: edges of a in box(b)      5: edges of b in box(a)
-// Capacity of each list = primitive count of its body; region offsets per
-// body pair from a scan of the summed capacities.  Runs over a buffer of
+// Capacity of each list = primitive count of its body rounded up to 64;
+// region offsets per body pair from a scan of the summed capacities.  Runs over a buffer of
 // n_cap slots; slots at or beyond the body-pair count (device) get 0.  Also
 // marks both bodies of every pair as involved (their primitive boxes are
 // then computed).
@@ -227,8 +230,9 @@ __global__ void k_list_caps(int64_t n_cap, const int64_t *nbp_dev, const int32_t
   const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
   involved[a] = 1;  // (every writer stores the same value)
   involved[b] = 1;
-  cap[p] = (int64_t)(voff[a + 1] - voff[a]) + (toff[b + 1] - toff[b]) + (voff[b + 1] - voff[b]) +
-           (toff[a + 1] - toff[a]) + (eoff[a + 1] - eoff[a]) + (eoff[b + 1] - eoff[b]);
+  // (each list's capacity rounded up to 64, so lists start at multiples of 64)
+  cap[p] = round64(voff[a + 1] - voff[a]) + round64(toff[b + 1] - toff[b]) + round64(voff[b + 1] - voff[b]) +
+           round64(toff[a + 1] - toff[a]) + round64(eoff[a + 1] - eoff[a]) + round64(eoff[b + 1] - eoff[b]);
 }
 
 
@@ -236,41 +240,21 @@ __global__ void k_clear_f64(int n, double *a) {
   if ((int)threadIdx.x < n) a[threadIdx.x] = 0.0;
 }
 
-// Three-level i-AABB tree (sec. 4.2): over each culled list (positions
-// [0, n), in primitive index order) a binary tree of index ranges -- the
-// list, its two halves, their four quarters -- with split positions at
-// multiples of 64, so that a 64-column chunk and a tile of rows (trows
-// divides 64) each lie inside one leaf.  A node's box is the union of its
-// primitives' culling boxes.  Leaf i of the row list is tested against leaf
-// j of the column list when the two roots, the two halves holding them and
-// the two leaves overlap; a primitive pair whose exact boxes overlap lies in
-// such a leaf pair (every node box contains its primitives' boxes), so the
-// tree drops no candidate, and since skipped rows and column chunks hold no
-// passing pair the output is the single-level one, pair for pair.
-__device__ __forceinline__ int tree_split(int n) {  // first position of the right half
-  const int h = 64 * ((n + 127) / 128);
-  return h < n ? h : n;
-}
-__device__ __forceinline__ void tree_bounds(int n, int b[5]) {
-  const int h = tree_split(n);
-  b[0] = 0;
-  b[1] = tree_split(h);
-  b[2] = h;
-  b[3] = h + tree_split(n - h);
-  b[4] = n;
-}
-__device__ __forceinline__ int tree_leaf(const int b[5], int pos) {
-  return (pos >= b[1]) + (pos >= b[2]) + (pos >= b[3]);
-}
-// column chunk k (list positions from 64 k) is tested when its leaf is in
-// the row leaf's mask cmask (column-leaf bounds c1 <= c2 <= c3)
-__device__ __forceinline__ bool tree_chunk_live(int k, int cmask, int c1, int c2, int c3) {
-  const int c0 = 64 * k;
-  return (cmask >> ((c0 >= c1) + (c0 >= c2) + (c0 >= c3))) & 1;
-}
-__device__ __forceinline__ bool box32_overlap(const float *a, const float *b) {
-  return a[0] <= b[3] && b[0] <= a[3] && a[1] <= b[4] && b[1] <= a[4] && a[2] <= b[5] && b[2] <= a[5];
-}
+// Three-level i-AABB tree (sec. 4.2, Fig. iBVH).  Every culled column
+// list is cut, in its index order, into blocks of 256 positions, and each
+// block is the root of a binary AABB tree of three levels: the block, its
+// two 128-position halves and their four 64-position chunks (the leaves).
+// A node's box is the union of its primitives' culling boxes.  A tile of
+// rows tests the box of its rows against each block's tree top-down and
+// runs the primitive-pair tests only in the chunks it reaches; a column
+// whose exact box overlaps a row's lies in such a chunk (every node box
+// contains its primitives' boxes), and skipping a chunk drops only columns
+// that no row of the tile meets, so the output is the single-level one,
+// pair for pair.  Lists start at multiples of 64 in the list buffer, so
+// chunk k of a list starting at s is record (s >> 6) + k of the chunk
+// records: its leaf box, the box of the 128-node that starts at it (even k)
+// and of the 256-node that starts at it (k % 4 == 0).
+constexpr int CREC = 18;  // floats per chunk record
 __device__ __forceinline__ void box32_union(float *o, const float *a, const float *b) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -278,33 +262,51 @@ __device__ __forceinline__ void box32_union(float *o, const float *a, const floa
     o[3 + c] = fmaxf(a[3 + c], b[3 + c]);
   }
 }
+// lane 0 stores the wave-uniform box b
+__device__ __forceinline__ void store_box_lanes(float *dst, const float *b, int lane) {
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dst[c] = b[c];
+  }
+}
+// a node's single-precision box against a tile's double-precision box
+__device__ __forceinline__ bool node_meets(const float *n, const double *t) {
+  return (double)n[0] <= t[3] && t[0] <= (double)n[3] && (double)n[1] <= t[4] && t[1] <= (double)n[4] &&
+         (double)n[2] <= t[5] && t[2] <= (double)n[5];
+}
+// is chunk k of a column list (first record g0) reached from the tile box
+__device__ __forceinline__ bool chunk_reached(const float *crec, int64_t g0, int k, const double *tb) {
+  return node_meets(crec + CREC * (g0 + (k & ~3)) + 12, tb) && node_meets(crec + CREC * (g0 + (k & ~1)) + 6, tb) &&
+         node_meets(crec + CREC * (g0 + k), tb);
+}
 
 // One wave per body pair p and sub-problem sub (0: a's vertices x b's
 // triangles, 1: b's vertices x a's triangles, 2: a's edges x b's edges):
 // the two lists of primitives inside the other body's box (kinds 2 sub and
 // 2 sub + 1), each in index order by ballot compaction in chunks of 64,
 // then the sub-problem's tile count (trows rows x all columns per tile).
-// With tree_mask (three-level tree): the leaf boxes of both lists, the
-// sub-problem's 16-bit mask of leaf pairs to test (bit 4 i + j: row leaf i,
-// column leaf j) and the tiles of the row leaves that meet some column
-// leaf.  tests (optional, profiling) gets the primitive-pair box tests of
-// the sub-problem: [0] with the tree (or single-level), [1] single-level.
+// With crec (three-level tree): the column list's chunk records.  tests
+// (optional, profiling) gets the sub-problem's primitive-pair box tests of
+// a single-level cull.
 __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const int64_t *region,
                                                     const int32_t *voff, const int32_t *toff, const int32_t *eoff,
                                                     const double *bb, const float *vb32, const int32_t *tris,
                                                     const int32_t *edges, int32_t *lists, int64_t *list_start,
                                                     int32_t *list_len, int64_t *tiles_pt, int64_t *tiles_ee,
-                                                    int trows, int32_t *tree_mask, double *tests) {
+                                                    int trows, float *crec, double *tests) {
   const int64_t p = blockIdx.x;
   const int sub = blockIdx.y;
   const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
   const int la = voff[a + 1] - voff[a], lb = voff[b + 1] - voff[b];
   const int ta = toff[a + 1] - toff[a], tb = toff[b + 1] - toff[b];
   const int ea = eoff[a + 1] - eoff[a];
-  const int caps[6] = {la, tb, lb, ta, ea, 0};
+  // list starts inside the body pair's region (capacities rounded to 64)
+  const int64_t s1 = round64(la), s2 = s1 + round64(tb), s3 = s2 + round64(lb), s4 = s3 + round64(ta),
+                s5 = s4 + round64(ea);
   const int lane = threadIdx.x;
   int len[2], pkh[2];
   int64_t sth[2];
+#pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int kind = 2 * sub + h;
     // (body owning the primitives, body whose box culls them)
@@ -313,8 +315,8 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
     const int32_t *offs = (kind == 0 || kind == 2) ? voff : (kind == 1 || kind == 3) ? toff : eoff;
     const int pk = (kind == 0 || kind == 2) ? 0 : (kind == 1 || kind == 3) ? 1 : 2;  // vertex, triangle, edge
     // start of this list inside the body pair's region
-    int64_t start = region[p];
-    for (int k = 0; k < kind; ++k) start += caps[k];
+    const int64_t start =
+        region[p] + (kind == 0 ? 0 : kind == 1 ? s1 : kind == 2 ? s2 : kind == 3 ? s3 : kind == 4 ? s4 : s5);
     double ob[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) ob[i] = bb[6 * (int64_t)oth + i];
@@ -339,85 +341,55 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
     pkh[h] = pk;
     sth[h] = start;
   }
-  int64_t t = len[1] > 0 ? (len[0] + trows - 1) / trows : 0;
-  double n_tests = (double)len[0] * len[1];
-  const double n_flat = n_tests;
-  if (tree_mask) {
-    // leaf boxes: a 64-chunk of list positions lies in one leaf
-    float lb[2][4][6];
-    int bnd[2][5];
+  if (crec) {
+    // chunk records of the column list (kind 2 sub + 1)
+    const int n = len[1];
+    const int64_t g0 = sth[1] >> 6;
+    float n128[6], n256[6];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      tree_bounds(len[h], bnd[h]);
+    for (int c = 0; c < 3; ++c) {
+      n128[c] = n256[c] = INFINITY;
+      n128[3 + c] = n256[3 + c] = -INFINITY;
+    }
+    for (int k = 0; 64 * k < n; ++k) {
+      float fb[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+      if (64 * k + lane < n) prim_box32(pkh[1], lists[sth[1] + 64 * k + lane], tris, edges, vb32, fb);
 #pragma unroll
-      for (int l = 0; l < 4; ++l)
+      for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          lb[h][l][c] = INFINITY;
-          lb[h][l][3 + c] = -INFINITY;
+          fb[c] = fminf(fb[c], __shfl_xor(fb[c], o, 64));
+          fb[3 + c] = fmaxf(fb[3 + c], __shfl_xor(fb[3 + c], o, 64));
         }
-      for (int c0 = 0; c0 < len[h]; c0 += 64) {
-        float fb[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-        if (c0 + lane < len[h]) prim_box32(pkh[h], lists[sth[h] + c0 + lane], tris, edges, vb32, fb);
+      store_box_lanes(crec + CREC * (g0 + k), fb, lane);
+      box32_union(n128, n128, fb);
+      box32_union(n256, n256, fb);
+      const bool last = 64 * (k + 1) >= n;
+      if ((k & 1) || last) {
+        store_box_lanes(crec + CREC * (g0 + (k & ~1)) + 6, n128, lane);
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < 3; ++c) {
+          n128[c] = INFINITY;
+          n128[3 + c] = -INFINITY;
+        }
+      }
+      if ((k & 3) == 3 || last) {
+        store_box_lanes(crec + CREC * (g0 + (k & ~3)) + 12, n256, lane);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            fb[c] = fminf(fb[c], __shfl_xor(fb[c], o, 64));
-            fb[3 + c] = fmaxf(fb[3 + c], __shfl_xor(fb[3 + c], o, 64));
-          }
-        const int l = tree_leaf(bnd[h], c0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)  // (constant indices: a run-time one would move lb to scratch)
-          if (q == l) box32_union(lb[h][q], lb[h][q], fb);
+        for (int c = 0; c < 3; ++c) {
+          n256[c] = INFINITY;
+          n256[3 + c] = -INFINITY;
+        }
       }
     }
-    // descent: roots, halves, leaves
-    float half[2][2][6], root[2][6];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      box32_union(half[h][0], lb[h][0], lb[h][1]);
-      box32_union(half[h][1], lb[h][2], lb[h][3]);
-      box32_union(root[h], half[h][0], half[h][1]);
-    }
-    int mask = 0;
-    if (box32_overlap(root[0], root[1]))
-#pragma unroll
-      for (int hi = 0; hi < 2; ++hi)
-#pragma unroll
-        for (int hj = 0; hj < 2; ++hj)
-          if (box32_overlap(half[0][hi], half[1][hj]))
-#pragma unroll
-            for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
-              for (int b2 = 0; b2 < 2; ++b2) {
-                const int i = 2 * hi + a2, j = 2 * hj + b2;
-                if (bnd[0][i + 1] > bnd[0][i] && bnd[1][j + 1] > bnd[1][j] && box32_overlap(lb[0][i], lb[1][j]))
-                  mask |= 1 << (4 * i + j);
-              }
-    t = 0;
-    n_tests = 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int rows = bnd[0][i + 1] - bnd[0][i];
-      int cols = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if ((mask >> (4 * i + j)) & 1) cols += bnd[1][j + 1] - bnd[1][j];
-      if (cols > 0) t += (rows + trows - 1) / trows;
-      n_tests += (double)rows * cols;
-    }
-    if (lane == 0) tree_mask[3 * p + sub] = mask;
   }
   if (lane == 0) {
+    const int64_t t = len[1] > 0 ? (len[0] + trows - 1) / trows : 0;
     if (sub < 2)
       tiles_pt[2 * p + sub] = t;
     else
       tiles_ee[p] = t;
-    if (tests) {
-      tests[3 * p + sub] = n_tests;
-      tests[3 * gridDim.x + 3 * p + sub] = n_flat;
-    }
+    if (tests) tests[3 * p + sub] = (double)len[0] * len[1];
   }
 }
 
@@ -449,14 +421,17 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
                                           const int64_t *list_start, const int32_t *list_len, const int32_t *lists,
                                           const int32_t *tris, const int32_t *edges, const double *x0,
                                           const double *x1, double inflate, int64_t *tile_cnt, int64_t pos0,
-                                          int32_t *out, int64_t n_tiles_valid, int trows,
-                                          const int32_t *tree_mask) {
+                                          int32_t *out, int64_t n_tiles_valid, int trows, const float *crec,
+                                          double *tile_tests) {
   // rows: vertices (PT) or edges (EE); columns: triangles (PT) or edges (EE)
   const int rk = is_ee ? 2 : 0, ck = is_ee ? 2 : 1;
   // (the count pass runs over a capacity: tiles beyond the device count
   // record 0 so that the scan over the capacity stays exact)
   if (!WRITE && tile < n_tiles && tile >= n_tiles_valid) {
-    if (threadIdx.x == 0) tile_cnt[tile] = 0;
+    if (threadIdx.x == 0) {
+      tile_cnt[tile] = 0;
+      if (tile_tests) tile_tests[tile] = 0.0;
+    }
     return;
   }
   if (tile >= n_tiles) return;
@@ -466,40 +441,8 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
   const int li = is_ee ? 4 : 2 * (int)(s % 2);
   const int64_t rstart = list_start[6 * p + li], cstart = list_start[6 * p + li + 1];
   const int nr = list_len[6 * p + li], nc = list_len[6 * p + li + 1];
-  int r0 = ts.y * trows, r1 = min(nr, r0 + trows);
-  // three-level tree: the tile's row leaf and the column chunks (64 list
-  // positions, one leaf each) of the leaves it meets; skipped chunks load
-  // and test nothing
-  int cmask = 0xF, cb1 = 0, cb2 = 0, cb3 = 0;
-  if (tree_mask) {
-    const int mask = tree_mask[3 * p + (is_ee ? 2 : (int)(s % 2))];
-    int rb[5], cbnd[5];
-    tree_bounds(nr, rb);
-    tree_bounds(nc, cbnd);
-    // the tile's row leaf: tiles run over the row leaves that meet some
-    // column leaf, in order (the tile exists, so some leaf holds it)
-    int tt = ts.y;
-    bool found = false;
-    r0 = r1 = nr;
-    cmask = 0;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const int m = (mask >> (4 * l)) & 0xF;
-      const int nt = m ? (rb[l + 1] - rb[l] + trows - 1) / trows : 0;
-      if (!found && tt < nt) {
-        found = true;
-        r0 = rb[l] + tt * trows;
-        r1 = min(rb[l + 1], r0 + trows);
-        cmask = m;
-      } else if (!found) {
-        tt -= nt;
-      }
-    }
-    cb1 = cbnd[1];
-    cb2 = cbnd[2];
-    cb3 = cbnd[3];
-  }
-
+  const int r0 = ts.y * trows;
+  const int r1 = min(nr, r0 + trows);
   const int lane = threadIdx.x;
   const int nch = (nc + 63) / 64;
   // row r0 + lane (lanes < trows) and the lane's first CPRE column chunks
@@ -508,16 +451,40 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
   if (r0 + lane < r1) my_rp = lists[rstart + r0 + lane];
   int cpv[CPRE];
   double cb[CPRE][6];
-#pragma unroll
-  for (int k = 0; k < CPRE; ++k) {
-    const int c = 64 * k + lane;
-    cpv[k] = c < nc && tree_chunk_live(k, cmask, cb1, cb2, cb3) ? lists[cstart + c] : -1;
-  }
   if (r0 + lane < r1) {
     prim_box(rk, my_rp, tris, edges, x0, x1, inflate, my_rb);
   } else {
 #pragma unroll
     for (int i = 0; i < 6; ++i) my_rb[i] = 0.0;
+  }
+  // three-level tree: the tile's box (union of its row boxes) and the
+  // column chunks it reaches (bit k of `live` for the first CPRE chunks)
+  double tb[6];
+  const int64_t g0 = cstart >> 6;
+  unsigned live = 0xFFFFFFFFu;
+  if (crec) {
+    const bool own = r0 + lane < r1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      tb[c] = own ? my_rb[c] : INFINITY;
+      tb[3 + c] = own ? my_rb[3 + c] : -INFINITY;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        tb[c] = fmin(tb[c], __shfl_xor(tb[c], o, 64));
+        tb[3 + c] = fmax(tb[3 + c], __shfl_xor(tb[3 + c], o, 64));
+      }
+    live = 0;
+#pragma unroll
+    for (int k = 0; k < CPRE; ++k)
+      if (k < nch && chunk_reached(crec, g0, k, tb)) live |= 1u << k;
+  }
+#pragma unroll
+  for (int k = 0; k < CPRE; ++k) {
+    const int c = 64 * k + lane;
+    cpv[k] = c < nc && ((live >> k) & 1) ? lists[cstart + c] : -1;
   }
 #pragma unroll
   for (int k = 0; k < CPRE; ++k) {
@@ -550,7 +517,7 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
       }
     }
     for (int c0 = 64 * CPRE; c0 < nc; c0 += 64) {
-      if (!tree_chunk_live(c0 / 64, cmask, cb1, cb2, cb3)) continue;  // (uniform over the wave)
+      if (crec && !chunk_reached(crec, g0, c0 >> 6, tb)) continue;  // (uniform over the wave)
       const int c = c0 + lane;
       int cp = 0;
       bool ok = false;
@@ -569,7 +536,17 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
       cnt += __popcll(m);
     }
   }
-  if (!WRITE && lane == 0) tile_cnt[tile] = cnt;
+  if (!WRITE && lane == 0) {
+    tile_cnt[tile] = cnt;
+    if (tile_tests) {
+      // primitive-pair box tests of the tile: its rows x the columns of the
+      // chunks it reaches
+      int cols = 0;
+      for (int k = 0; k < nch; ++k)
+        if (!crec || (k < CPRE ? (live >> k) & 1 : chunk_reached(crec, g0, k, tb))) cols += min(64, nc - 64 * k);
+      tile_tests[tile] = (double)(r1 - r0) * cols;
+    }
+  }
 }
 
 // Both families in one launch: blocks [0, n_pt_blocks) take PT tiles, the
@@ -587,17 +564,19 @@ __global__ void __launch_bounds__(64) k_pair_tiles(int64_t nbp, int64_t n_pt_blo
                                                    const int32_t *lists, const int32_t *tris, const int32_t *edges,
                                                    const double *x0, const double *x1, double inflate,
                                                    int64_t *cnt, const int64_t *off, int32_t *out_pt,
-                                                   int32_t *out_ee, int trows, const int32_t *tree_mask) {
+                                                   int32_t *out_ee, int trows, const float *crec,
+                                                   double *tile_tests) {
   const int64_t b = blockIdx.x;
   if (b < n_pt_blocks) {
     const int64_t valid = WRITE ? n_pt_blocks : toff[2 * nbp];
     pair_tile<WRITE>(0, b, tsub_pt, n_pt_blocks, list_start, list_len, lists, tris, edges, x0, x1, inflate, cnt,
-                     WRITE ? off[b] : 0, out_pt, valid, trows, tree_mask);
+                     WRITE ? off[b] : 0, out_pt, valid, trows, crec, tile_tests);
   } else if (b < n_pt_blocks + n_ee_blocks) {
     const int64_t t = b - n_pt_blocks;
     const int64_t valid = WRITE ? n_ee_blocks : *ttotal - toff[2 * nbp];
     pair_tile<WRITE>(1, t, tsub_ee, n_ee_blocks, list_start, list_len, lists, tris, edges, x0, x1, inflate,
-                     cnt + cap_pt, WRITE ? off[cap_pt + t] - off[cap_pt] : 0, out_ee, valid, trows, tree_mask);
+                     cnt + cap_pt, WRITE ? off[cap_pt + t] - off[cap_pt] : 0, out_ee, valid, trows, crec,
+                     tile_tests ? tile_tests + cap_pt : nullptr);
   }
 }
 
@@ -686,25 +665,13 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   int64_t *tcnt, *toff, *ttot = btot + 2, *otot = btot + 4;
   ABD_TRY(ws(ctx, "bp_tcnt", 3 * nbp, &tcnt, s));
   ABD_TRY(ws(ctx, "bp_toff", 3 * nbp + 1, &toff, s));
-  int32_t *tmask = nullptr;
-  if (ctx->tune.cull_levels == 3) ABD_TRY(ws(ctx, "bp_tmask", 3 * nbp, &tmask, s));
-  double *tests = nullptr;
-  if (ctx->profiling) ABD_TRY(ws(ctx, "bp_tests", 6 * nbp, &tests, s));
+  float *crec = nullptr;  // three-level tree: chunk records of the column lists
+  if (ctx->tune.cull_levels == 3) ABD_TRY(ws(ctx, "bp_crec", CREC * (list_total / 64 + 1), &crec, s));
+  double *tests = nullptr;  // profiling: single-level tests per sub-problem
+  if (ctx->profiling) ABD_TRY(ws(ctx, "bp_tests", 3 * nbp, &tests, s));
   hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 3), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
                      sc->body_tri_off, sc->body_edge_off, bbox, vbox32, sc->tris, sc->edges, lists, lstart, llen,
-                     tcnt, tcnt + 2 * nbp, trows, tmask, tests);
-  if (tests) {
-    // primitive-pair box tests (with the table's culling, and single-level),
-    // summed on the device over the profiled calls (read by the query)
-    double *acc;
-    ABD_TRY(ws(ctx, "prof_box_tests", 2, &acc, s));
-    if (ctx->prof_box_tests_clear) hipLaunchKernelGGL(k_clear_f64, dim3(1), dim3(64), 0, s, 2, acc);
-    ctx->prof_box_tests_clear = false;
-    ABD_TRY(reduce_sum_f64(ctx, tests, 3 * nbp, acc, s));
-    ABD_TRY(reduce_sum_f64(ctx, tests + 3 * nbp, 3 * nbp, acc + 1, s));
-    ctx->kstats["box_tests"].launches += 1;
-    ctx->kstats["box_tests_single_level"].launches += 1;
-  }
+                     tcnt, tcnt + 2 * nbp, trows, crec, tests);
   // hbuf[2] = all tiles, hbuf[3] = PT tiles
   ABD_TRY(scan_exclusive_i64(ctx, tcnt, toff, 3 * nbp, ttot, s, hbuf_d + 2, 2 * nbp));
   const std::string key_tp = std::string(tag) + "_tpt", key_te = std::string(tag) + "_tee";
@@ -713,6 +680,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   cap_te = cap_te + cap_te / 4 + 256;
   int64_t ntile_pt = 0, ntile_ee = 0;
   int64_t *ccnt, *coff;
+  double *tile_tests = nullptr;
   int2 *tsub_pt, *tsub_ee;
   for (int pass = 0;; ++pass) {
     // pair counts per tile: PT tiles [0, cap_tp), EE tiles [cap_tp, cap_tp + cap_te)
@@ -722,9 +690,10 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     ABD_TRY(ws(ctx, "bp_tsub_ee", cap_te + 1, &tsub_ee, s));
     hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(3 * nbp, 256)), dim3(256), 0, s, nbp, tcnt, toff, tsub_pt, cap_tp,
                        tsub_ee, cap_te);
+    if (tests) ABD_TRY(ws(ctx, "bp_tile_tests", cap_tp + cap_te, &tile_tests, s));
     hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)(cap_tp + cap_te)), dim3(64), 0, s, nbp, cap_tp, cap_te, cap_tp,
                        tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0, x1, inflate,
-                       ccnt, nullptr, nullptr, nullptr, trows, tmask);
+                       ccnt, nullptr, nullptr, nullptr, trows, crec, tile_tests);
     // hbuf[4] = all pairs, hbuf[5] = PT pairs
     ABD_TRY(scan_exclusive_i64(ctx, ccnt, coff, cap_tp + cap_te, otot, s, hbuf_d + 4, cap_tp));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -738,6 +707,18 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   }
   ctx->cap_hint[key_tp] = ntile_pt;
   ctx->cap_hint[key_te] = ntile_ee;
+  if (tests) {
+    // primitive-pair box tests (the tiles' with the table's culling, and a
+    // single-level cull's), summed on the device over the profiled calls
+    double *acc;
+    ABD_TRY(ws(ctx, "prof_box_tests", 2, &acc, s));
+    if (ctx->prof_box_tests_clear) hipLaunchKernelGGL(k_clear_f64, dim3(1), dim3(64), 0, s, 2, acc);
+    ctx->prof_box_tests_clear = false;
+    ABD_TRY(reduce_sum_f64(ctx, tile_tests, cap_tp + cap_te, acc, s));
+    ABD_TRY(reduce_sum_f64(ctx, tests, 3 * nbp, acc + 1, s));
+    ctx->kstats["box_tests"].launches += 1;
+    ctx->kstats["box_tests_single_level"].launches += 1;
+  }
   *n_pt = hbuf[5];
   *n_ee = hbuf[4] - hbuf[5];
   std::string tpt_name = std::string(tag) + "_pt", tee_name = std::string(tag) + "_ee";
@@ -747,7 +728,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   if (*n_pt + *n_ee > 0)
     hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)(ntile_pt + ntile_ee)), dim3(64), 0, s, nbp, ntile_pt,
                        ntile_ee, cap_tp, tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0,
-                       x1, inflate, nullptr, coff, *pt_out, *ee_out, trows, tmask);
+                       x1, inflate, nullptr, coff, *pt_out, *ee_out, trows, crec, nullptr);
   prof_end(ctx, pe, "pair_tiles_write", ntile_pt + ntile_ee, s);
   return abd_hip_check(ctx, hipGetLastError(), "candidates");
 }

@@ -704,6 +704,58 @@ def newton_iteration(S, B, q, qt, params, F=None):
     return q + alpha * p, False, info
 
 
+# Adaptive barrier stiffness (IPC's rule; the paper writes kappa without a
+# value or rule).  Reading, per time step of a single scene (kappa_adaptive
+# set; params["kappa_b"] is the floor kappa_min, params["kappa_max"] the
+# ceiling):
+#  - at q^t, kappa = clamp(-(g_E . g_B) / (g_B . g_B), kappa_min, kappa_max),
+#    the kappa that best balances the barrier's gradient g_B (kappa = 1)
+#    against the rest of the incremental potential's g_E (inertia, the
+#    rigidity potential and joints), both over the free bodies' DOFs;
+#    kappa_min when g_B = 0.  It is set before friction is lagged;
+#  - before each Newton iteration, with d the smallest distance of an
+#    active pair at the iterate and d_prev the previous one (at q^t for the
+#    first iteration): kappa doubles, up to kappa_max, when d < eps_d
+#    (params["kappa_eps_d"]) and d < d_prev.
+# Distances compare as squares (d^2 from the pair classification).
+
+def min_active_d2(S, x, pt, ee, dhat):
+    """Smallest squared distance of an active pair (inf when none)."""
+    best = np.inf
+    for pairs, is_ee in ((pt, 0), (ee, 1)):
+        if len(pairs):
+            _, d2, act = classify(S, x, pairs, is_ee, dhat)
+            if np.any(act):
+                best = min(best, float(d2[act != 0].min()))
+    return best
+
+
+def barrier_stiffness_init(S, B, q, qt, params):
+    """(kappa, d^2_min) at the start of a time step (rule above)."""
+    x = vertex_map(S, q)
+    pt, ee = candidates(S, x, None, params["dhat"])
+    _, g_in, _ = inertia(S, B.M, q, qt)
+    _, g_o, _ = rigidity(S, B.vol, q, params)
+    _, g_j, _, _ = joints(S, q, params, None)
+    gE = g_in + g_o + g_j
+    keys = off_keys(S, pt, ee)
+    gB = barrier(S, x, pt, ee, dict(params, kappa_b=1.0), keys)["grad"]
+    free = S["body_fixed"] == 0
+    gE, gB = gE[free], gB[free]
+    den = float(np.sum(gB * gB))
+    kmin, kmax = params["kappa_b"], params["kappa_max"]
+    kappa = kmin if den == 0.0 else min(max(-float(np.sum(gE * gB)) / den, kmin), kmax)
+    return kappa, min_active_d2(S, x, pt, ee, params["dhat"])
+
+
+def barrier_stiffness_update(kappa, d2, d2_prev, params):
+    """Doubling rule before a Newton iteration (rule above)."""
+    eps2 = params["kappa_eps_d"] ** 2
+    if d2 < eps2 and d2 < d2_prev:
+        return min(2.0 * kappa, params["kappa_max"])
+    return kappa
+
+
 def step_friction(S, q, params):
     """Friction state lagged at the step start (None when mu = 0)."""
     if params.get("mu", 0.0) <= 0.0:
@@ -720,6 +772,12 @@ def time_step(S, B, q, qd, params, log=None, lag=None, F_out=None):
     pairs, lambda, T and w (x^t stays that of q), and F_out (a list)
     receives the state used."""
     qt = q_tilde(S, q, qd, params)
+    adaptive = bool(params.get("kappa_adaptive", 0))
+    if adaptive:
+        if len(np.unique(S["body_scene"])) > 1:
+            raise ValueError("the oracle's adaptive barrier stiffness takes one scene")
+        kappa, d2_prev = barrier_stiffness_init(S, B, q, qt, params)
+        params = dict(params, kappa_b=kappa)
     if lag is not None:
         F = dict(lag, xt=vertex_map(S, q))
     else:
@@ -729,7 +787,13 @@ def time_step(S, B, q, qd, params, log=None, lag=None, F_out=None):
     qn = q.copy()
     its = 0
     for its in range(1, params["max_newton"] + 1):
+        if adaptive:
+            x = vertex_map(S, qn)
+            d2 = min_active_d2(S, x, *candidates(S, x, None, params["dhat"]), params["dhat"])
+            params = dict(params, kappa_b=barrier_stiffness_update(params["kappa_b"], d2, d2_prev, params))
+            d2_prev = d2
         qn, conv, info = newton_iteration(S, B, qn, qt, params, F)
+        info["kappa_b"] = params["kappa_b"]
         if log is not None:
             log.append(info)
         if conv:
@@ -800,7 +864,10 @@ def rollout(S, B, q0, qd0, params, n_steps, lags=None):
 
 def rollout_grad(S, B, q0, qd0, params, n_steps, qbar_T, qdbar_T):
     """dL/dq^0, dL/dqdot^0 of a loss L(q^n, qdot^n) with the given
-    gradients, by adjoint_step from the last step back."""
+    gradients, by adjoint_step from the last step back (fixed barrier
+    stiffness only: the adjoint does not differentiate the adaptive rule)."""
+    if params.get("kappa_adaptive", 0):
+        raise ValueError("the adjoint takes a fixed barrier stiffness")
     states, Fs = rollout(S, B, q0, qd0, params, n_steps)
     qbar, qdbar = qbar_T.copy(), qdbar_T.copy()
     for t in range(n_steps - 1, -1, -1):

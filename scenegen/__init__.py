@@ -8,4 +8,4 @@ from .scenes import (CONFIGS, SceneBuilder, default_params, three_cubes,  # noqa
                      icosphere_box, torus_chains, torus_chains_contact, batched_drops, adjoint_drop,
                      near_contact_cubes, triangle_soup, random_state, icosphere_resting_layer,
                      cube_on_slope, sub_scene, cube_lattice, icosphere_fcc, landed,
-                     wrecking_ball, hinged_chain)
+                     wrecking_ball, hinged_chain, tet_over_ground)

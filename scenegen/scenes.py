@@ -122,14 +122,18 @@ class SceneBuilder:
 
 def default_params(**kw):
     """Method parameters.  kappa_b is the barrier stiffness (fixed per
-    scene), kappa_o the orthogonality stiffness (multiplied by body volume),
+    scene; with kappa_adaptive its floor, kappa_max its ceiling and
+    kappa_eps_d the distance below which an approaching contact doubles
+    it), kappa_o the orthogonality stiffness (multiplied by body volume),
     kappa_j the joint penalty stiffness (N/m),
     ccd_s / ccd_tmax / ccd_max_iter the additive-CCD constants."""
-    p = dict(dt=1e-2, dhat=1e-3, kappa_b=80.0, kappa_o=1e8, kappa_j=1e7, mu=0.0, eps_v=1e-3,
+    p = dict(dt=1e-2, dhat=1e-3, kappa_b=80.0, kappa_o=1e8, kappa_j=1e7, kappa_adaptive=0,
+             kappa_eps_d=1e-9, mu=0.0, eps_v=1e-3,
              gravity=GRAVITY, newton_tol=1e-5, pcg_rtol=1e-10, ccd_s=0.1,
              ccd_tmax=1.0, ccd_max_iter=10000, max_newton=100, max_pcg=5000,
              max_ls=40, steps=100)
     p.update(kw)
+    p.setdefault("kappa_max", 100.0 * p["kappa_b"])  # (IPC's ceiling ratio)
     return p
 
 
@@ -480,6 +484,24 @@ def cube_on_slope(theta, mu, v0=1.0, gap=5e-4, ground=40.0):
     g = 9.8
     params = default_params(dt=1e-2, dhat=1e-3, kappa_b=80.0, mu=mu,
                             gravity=(g * math.sin(theta), -g * math.cos(theta), 0.0))
+    return sb.build(), params
+
+
+def tet_over_ground(a=0.5, height=3e-4, v0=0.0, ground=10.0):
+    """A right-corner tetrahedron (body frame: the corner at the origin, legs
+    a along x, y and z; density 1000) with its x-z face parallel to a large
+    fixed ground triangle at y = 0, that face `height` above it and the
+    corner at x = z = 0; moving down at v0.  The ground is one triangle
+    reaching `ground` from the origin.  No randomness."""
+    v = np.array([[0.0, 0.0, 0.0], [a, 0.0, 0.0], [0.0, a, 0.0], [0.0, 0.0, a]])
+    t = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], np.int32)
+    g = np.array([[-ground, 0.0, -ground], [-ground, 0.0, 2 * ground], [2 * ground, 0.0, -ground]])
+    sb = SceneBuilder()
+    sb.add(g, np.array([[0, 1, 2]], np.int32), fixed=True)
+    qd = np.zeros(12)
+    qd[1] = -v0
+    sb.add(v, t, p=(0.0, height, 0.0), qd=qd)
+    params = default_params(dt=1e-2, dhat=1e-3, kappa_b=10.0, mu=0.0, newton_tol=1e-6, pcg_rtol=1e-12)
     return sb.build(), params
 
 

@@ -110,6 +110,18 @@ typedef struct abd_params {
    * (infinite for J <= 0) -- the alternatives sec. 3.2 names */
   int32_t rigidity;
   double kappa_j;     /* joint penalty stiffness (N/m; used when the scene has joints) */
+  /* Adaptive barrier stiffness (IPC's rule; the paper's kappa of sec. 4,
+   * Eq. barrier, has no value): 0 keeps kappa_b fixed; 1 makes abd_time_step
+   * set, per scene at q^t, kappa = clamp(-(g_E . g_B) / |g_B|^2, kappa_b,
+   * kappa_max) (g_B the barrier gradient at kappa = 1, g_E that of inertia,
+   * rigidity potential and joints, over the free DOFs; kappa_b when
+   * g_B = 0), and double it (up to kappa_max) before a Newton iteration
+   * whose closest active pair is nearer than kappa_eps_d and nearer than at
+   * the iteration before.  abd_newton_step and the adjoint entry points
+   * reject 1 (ABD_E_INVALID). */
+  int32_t kappa_adaptive;
+  double kappa_max;
+  double kappa_eps_d;  /* m */
 } abd_params;
 
 /* Per-iteration statistics (host struct). */
@@ -388,6 +400,11 @@ int abd_friction_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm
 int abd_friction_begin_step(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                             int64_t *n_pairs, hipStream_t stream);
 int abd_friction_end_step(abd_ctx *ctx);
+
+/* The per-scene barrier stiffness of the last adaptive time step on this
+ * context (its final value), copied to kappa_out [n_scenes] (host).  Syncs;
+ * ABD_E_INVALID when no adaptive step has run. */
+int abd_barrier_stiffness(abd_ctx *ctx, const abd_scene *sc, double *kappa_out);
 
 /* Launch shapes of the hot kernels (the autotuner's table).  No entry
  * changes a result: every kernel computes the same values and lists pairs

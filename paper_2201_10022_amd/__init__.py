@@ -46,6 +46,9 @@ def make_params(p):
         setattr(out, k, int(p[k]))
     out.rigidity = int(p.get("rigidity", 0))
     out.kappa_j = float(p.get("kappa_j", 0.0))
+    out.kappa_adaptive = int(p.get("kappa_adaptive", 0))
+    out.kappa_max = float(p.get("kappa_max", 100.0 * out.kappa_b))
+    out.kappa_eps_d = float(p.get("kappa_eps_d", 0.0))
     return out
 
 
@@ -363,6 +366,13 @@ class Context:
 
     # -- measurement ---------------------------------------------------
     # -- launch shapes -------------------------------------------------
+    def barrier_stiffness(self, scene):
+        """Per-scene barrier stiffness of the last adaptive time step."""
+        n = max(int(scene.c.n_scenes), 1)
+        out = (ctypes.c_double * n)()
+        self._check(self.L.abd_barrier_stiffness(self.h, ctypes.byref(scene.c), out))
+        return np.array(out[:], np.float64)
+
     def tune_get(self):
         t = _lib.AbdTune()
         self._check(self.L.abd_tune_get(self.h, ctypes.byref(t)))

@@ -18,7 +18,7 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_body_mass", "abd_
            "abd_newton_step", "abd_time_step", "abd_friction_lag", "abd_friction_grad_hess",
            "abd_friction_energy", "abd_friction_begin_step", "abd_friction_end_step", "abd_adjoint_step",
            "abd_rollout_forward", "abd_rollout_backward", "abd_profile", "abd_profile_query",
-           "abd_tune_get", "abd_tune_set", "abd_autotune"]
+           "abd_tune_get", "abd_tune_set", "abd_autotune", "abd_barrier_stiffness"]
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -40,7 +40,8 @@ class AbdParams(ctypes.Structure):
     _fields_ = [("dt", _dbl), ("dhat", _dbl), ("kappa_b", _dbl), ("kappa_o", _dbl), ("mu", _dbl), ("eps_v", _dbl),
                 ("gravity", _dbl * 3), ("newton_tol", _dbl), ("pcg_rtol", _dbl), ("ccd_s", _dbl),
                 ("ccd_tmax", _dbl), ("ccd_max_iter", _i32), ("max_newton", _i32), ("max_pcg", _i32),
-                ("max_ls", _i32), ("rigidity", _i32), ("kappa_j", _dbl)]
+                ("max_ls", _i32), ("rigidity", _i32), ("kappa_j", _dbl), ("kappa_adaptive", _i32),
+                ("kappa_max", _dbl), ("kappa_eps_d", _dbl)]
 
 
 class AbdStats(ctypes.Structure):
@@ -101,6 +102,7 @@ SIGNATURES = {
     "abd_rollout_backward": ([_vp, _PS, _PP, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _dbl, _vp, _vp, _vp], ctypes.c_int),
     "abd_profile": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "abd_profile_query": ([_vp, ctypes.c_char_p, ctypes.POINTER(_dbl), _pi64, _pi64], ctypes.c_int),
+    "abd_barrier_stiffness": ([_vp, _PS, ctypes.POINTER(_dbl)], ctypes.c_int),
     "abd_tune_get": ([_vp, ctypes.POINTER(AbdTune)], ctypes.c_int),
     "abd_tune_set": ([_vp, ctypes.POINTER(AbdTune)], ctypes.c_int),
     "abd_autotune": ([_vp, _PS, _PP, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(AbdTune),

@@ -183,6 +183,8 @@ extern "C" int abd_adjoint_step(abd_ctx *ctx, const abd_scene *sc, const abd_par
   if (!ctx || !sc || !prm || !q_t || !qdot_t || !q_next || !qbar_next || !qdbar_next || !qbar_t || !qdbar_t ||
       !sc->mass || !sc->volume)
     return abd_fail(ctx, ABD_E_INVALID, "abd_adjoint_step: null");
+  if (prm->kappa_adaptive)
+    return abd_fail(ctx, ABD_E_INVALID, "abd_adjoint_step: the adjoint takes a fixed barrier stiffness");
   if (qbar_t == qbar_next || qbar_t == qdbar_next || qdbar_t == qbar_next || qdbar_t == qdbar_next)
     return abd_fail(ctx, ABD_E_INVALID, "abd_adjoint_step: outputs alias inputs");
   int its = 0;
@@ -197,6 +199,8 @@ extern "C" int abd_rollout_forward(abd_ctx *ctx, const abd_scene *sc, const abd_
                                    int64_t *newton_iters, hipStream_t stream) {
   if (!ctx || !sc || !prm || !q || !qdot || !sc->mass || !sc->volume)
     return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_forward: null");
+  if (prm->kappa_adaptive)
+    return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_forward: the adjoint takes a fixed barrier stiffness");
   if (n_steps < 0 || checkpoint_every < 1) return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_forward: bad sizes");
   hipStream_t s = stream;
   const int n12 = 12 * sc->n_bodies;
@@ -229,6 +233,8 @@ extern "C" int abd_rollout_backward(abd_ctx *ctx, const abd_scene *sc, const abd
   if (!ctx || !sc || !prm || !q0 || !qdot0 || !qbar_T || !qdbar_T || !qbar_0 || !qdbar_0 || !sc->mass ||
       !sc->volume)
     return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_backward: null");
+  if (prm->kappa_adaptive)
+    return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_backward: the adjoint takes a fixed barrier stiffness");
   if (n_steps < 0 || checkpoint_every < 1) return abd_fail(ctx, ABD_E_INVALID, "abd_rollout_backward: bad sizes");
   hipStream_t s = stream;
   const int n12 = 12 * sc->n_bodies;

@@ -115,7 +115,8 @@ __device__ __forceinline__ void tangent_basis(d3 r, double T[6]) {
 __global__ void __launch_bounds__(256) k_friction_lag(int64_t n, int64_t n_pt, const int32_t *pt, const int32_t *ee,
                                                       const int32_t *tris, const int32_t *edges, const double *xt,
                                                       const double *xbar, double dhat, double kappa, double *lam,
-                                                      double *T, double *w) {
+                                                      double *T, double *w, const double *kappa_sc,
+                                                      const int32_t *vert_body, const int32_t *body_scene) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int is_ee, vid[4];
@@ -144,7 +145,9 @@ __global__ void __launch_bounds__(256) k_friction_lag(int64_t n, int64_t n_pt, c
       const double eps = (1e-3 * xdot(uu, uu)) * xdot(vv, vv);
       if (c < eps) m = (2.0 - c / eps) * (c / eps);
     }
-    l = -kappa * m * Bp;
+    // (per-scene stiffness when it adapts)
+    const double kap = kappa_sc ? kappa_sc[body_scene[vert_body[vid[0]]]] : kappa;
+    l = -kap * m * Bp;
     closest_weights(ty, X, wl);
     d3 r{0.0, 0.0, 0.0};
 #pragma unroll
@@ -541,7 +544,8 @@ int op_friction_lag(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, co
   const int64_t n = n_pt + n_ee;
   if (n == 0) return ABD_OK;
   hipLaunchKernelGGL(k_friction_lag, dim3(grid_for(n, 256)), dim3(256), 0, s, n, n_pt, pt, ee, sc->tris, sc->edges,
-                     xt, sc->xbar, prm->dhat, prm->kappa_b, lam, T, w);
+                     xt, sc->xbar, prm->dhat, prm->kappa_b, lam, T, w, ctx->kappa_sc, sc->vert_body,
+                     sc->body_scene);
   return abd_hip_check(ctx, hipGetLastError(), "k_friction_lag");
 }
 

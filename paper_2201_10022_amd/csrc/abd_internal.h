@@ -85,6 +85,10 @@ struct abd_ctx {
   // friction lagged at the start of the current time step (set by
   // abd_friction_begin_step, used by the Newton iterations while set)
   bool fr_set = false;
+  // adaptive barrier stiffness: per-scene kappa (device [S], workspace
+  // "kappa_sc") while abd_time_step runs with kappa_adaptive; null otherwise,
+  // and then every kernel takes the scalar kappa_b
+  double *kappa_sc = nullptr;
   int64_t fr_n_pt = 0, fr_n_ee = 0;
   // swept candidates of the last accepted Newton step (the segment holds the
   // new iterate, so its static candidates are a subset of these)
@@ -253,6 +257,13 @@ int op_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, 
 int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x0, const double *dx,
            const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *t_pt, double *t_ee,
            double *alpha, hipStream_t s);
+// adaptive barrier stiffness (abd_kappa.hip): per-scene kappa and the
+// closest active distance at q (workspace "kappa_sc", "kappa_d2prev"), and
+// the doubling rule before a Newton iteration at x over its candidates
+int op_kappa_init(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
+                  hipStream_t s);
+int op_kappa_update(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
+                    int64_t npt, const int32_t *ee, int64_t nee, hipStream_t s);
 int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
                   double *energy, double *grad, double *diag, int project, hipStream_t s);
 int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,

@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(BS) k_barrier_local(const int64_t *n_act_dev, 
                                                       const int32_t *edges, const int32_t *vert_body,
                                                       const double *x, const double *xbar, double dhat,
                                                       double kappa, int project, double *e_out, double *g_out,
-                                                      double *H_out, PairInfo *info, int *err) {
+                                                      double *H_out, PairInfo *info, int *err,
+                                                      const double *kappa_sc, const int32_t *body_scene) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= *n_act_dev) return;
   const int64_t idx = act[a];
@@ -115,7 +116,8 @@ __global__ void __launch_bounds__(BS) k_barrier_local(const int64_t *n_act_dev, 
     return;
   }
   LocalOut o;
-  barrier_local(is_ee, ty, X, xb4, dhat, kappa, 0, o);
+  // (per-scene stiffness when it adapts)
+  barrier_local(is_ee, ty, X, xb4, dhat, kappa_sc ? kappa_sc[body_scene[pi.body[0]]] : kappa, 0, o);
   // energy and gradient leave before the projection, whose eigen-solve
   // needs the registers
   e_out[a] = o.e;
@@ -293,7 +295,8 @@ __global__ void k_assemble_final(int64_t nblocks, int nb, const int64_t *chunk_o
 __global__ void k_energy_only(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee, const int32_t *tris,
                               const int32_t *edges, const double *x, const double *xbar, double dhat,
                               double kappa, double *e_out, const int32_t *vert_body, const int32_t *body_scene,
-                              int32_t *key_out, int64_t xstride = 0, int64_t estride = 0) {
+                              int32_t *key_out, int64_t xstride = 0, int64_t estride = 0,
+                              const double *kappa_sc = nullptr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   x += blockIdx.y * xstride;
@@ -336,7 +339,8 @@ __global__ void k_energy_only(int64_t n_pt, int64_t n, const int32_t *pt, const 
       b = (2.0 - r) * r * b;
     }
   }
-  e_out[i] = kappa * b;
+  // (per-scene stiffness when it adapts)
+  e_out[i] = (kappa_sc ? kappa_sc[body_scene[vert_body[vid[0]]]] : kappa) * b;
 }
 
 }  // namespace
@@ -391,7 +395,7 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
     // (waves per block from the launch-shape table)
 #define ABD_BARRIER_ARGS                                                                                          \
   nact, act, n_pt, pt, ee, sc->tris, sc->edges, sc->vert_body, x, sc->xbar, dhat, prm->kappa_b, project, e_loc, \
-      g_loc, H_loc, info, err
+      g_loc, H_loc, info, err, ctx->kappa_sc, sc->body_scene
     const int wpb = ctx->tune.barrier_waves;
     if (wpb == 4)
       hipLaunchKernelGGL(k_barrier_local<256>, dim3(grid_for(na, 256)), dim3(256), 0, s, ABD_BARRIER_ARGS);
@@ -455,7 +459,8 @@ int op_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, 
   hipEvent_t pe = prof_begin(ctx, s);
   const int eb = ctx->tune.energy_block;
   hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb)), dim3(eb), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges, x,
-                     sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, nullptr);
+                     sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, nullptr, 0, 0,
+                     ctx->kappa_sc);
   prof_end(ctx, pe, "energy_only", n, s);
   HIP_TRY(ctx, hipGetLastError());
   return reduce_sum_f64(ctx, e, n, energy, s);
@@ -475,7 +480,8 @@ int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params
   hipEvent_t pe = prof_begin(ctx, s);
   const int eb = ctx->tune.energy_block;
   hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb)), dim3(eb), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges, x,
-                     sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key);
+                     sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key, 0, 0,
+                     ctx->kappa_sc);
   prof_end(ctx, pe, "energy_only", n, s);
   HIP_TRY(ctx, hipGetLastError());
   // PT and EE lists are each ordered by scene
@@ -498,7 +504,7 @@ int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params
   const int eb = ctx->tune.energy_block;
   hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb), n_trials), dim3(eb), 0, s, n_pt, n, pt, ee, sc->tris,
                      sc->edges, x, sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key,
-                     3 * (int64_t)sc->n_verts, items ? estride : 0);
+                     3 * (int64_t)sc->n_verts, items ? estride : 0, ctx->kappa_sc);
   prof_end(ctx, pe, "energy_only", n * n_trials, s);
   HIP_TRY(ctx, hipGetLastError());
   if (items) return ABD_OK;

@@ -297,6 +297,9 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->t_candidates_ms += ms_since(t0);
   ABD_TRY(ws(ctx, "nt_off", 144 * (size_t)(nk + 1), &off, s));
   ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, off, 144 * nk, e, 1, s));
+  // adaptive barrier stiffness: the doubling rule at this iterate, before
+  // the barrier's derivatives and this iteration's energies
+  if (ctx->kappa_sc) ABD_TRY(op_kappa_update(ctx, sc, prm, x, pt, npt, ee, nee, s));
   t0 = std::chrono::steady_clock::now();
   ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, e, g, diag, 1, s));
   int64_t nap = 0, nae = 0;
@@ -461,6 +464,8 @@ extern "C" int abd_newton_step(abd_ctx *ctx, const abd_scene *sc, const abd_para
                                const double *q_tilde, uint8_t *scene_done, abd_stats *stats, hipStream_t stream) {
   if (!ctx || !sc || !prm || !q || !q_tilde || !sc->mass || !sc->volume)
     return abd_fail(ctx, ABD_E_INVALID, "abd_newton_step: null");
+  if (prm->kappa_adaptive)
+    return abd_fail(ctx, ABD_E_INVALID, "abd_newton_step: the adaptive barrier stiffness runs inside abd_time_step");
   abd_stats local = {};
   abd_stats *st = stats ? stats : &local;
   *st = abd_stats{};
@@ -489,6 +494,18 @@ extern "C" int abd_time_step(abd_ctx *ctx, const abd_scene *sc, const abd_params
   HIP_TRY(ctx, hipMemsetAsync(done, 0, S, stream));
   ABD_TRY(abd_q_tilde(ctx, sc, prm, q, qdot, qt, stream));
   HIP_TRY(ctx, hipMemcpyAsync(qo, q, sizeof(double) * n12, hipMemcpyDeviceToDevice, stream));
+  // adaptive barrier stiffness: set at q^t (before friction is lagged with
+  // it), read by the barrier kernels until the step returns
+  struct KappaScope {
+    abd_ctx *c;
+    ~KappaScope() { c->kappa_sc = nullptr; }
+  } kappa_scope{ctx};
+  if (prm->kappa_adaptive) {
+    if (!(prm->kappa_b > 0.0) || !(prm->kappa_max >= prm->kappa_b) || !(prm->kappa_eps_d >= 0.0))
+      return abd_fail(ctx, ABD_E_INVALID, "abd_time_step: adaptive stiffness needs 0 < kappa_b <= kappa_max, eps_d >= 0");
+    ABD_TRY(op_kappa_init(ctx, sc, prm, q, qt, stream));
+    ABD_TRY(ws(ctx, "kappa_sc", S, &ctx->kappa_sc, stream));
+  }
   // friction lagged once at q^t, released when the step returns
   struct FrictionScope {
     abd_ctx *c;

@@ -6,7 +6,7 @@ kappa; abd_params.kappa_adaptive) against the oracle's.
   the oracle's value, and the GPU's (one time step with eps_d = 0, so no
   doubling), within 1e-12.
 - A drop of the tetrahedron at 0.5 m/s from 2 mm with eps_d = dhat (kappa
-  doubles while the face approaches): four time steps, states within 1e-9
+  doubles while the face approaches): four time steps, states within 1e-7
   and the final kappa equal to the oracle's.
 - The box drop's two bottom layers at landing, adaptive with floor 1 and
   eps_d = dhat/4 (the start value from the gradient balance, and doublings
@@ -83,7 +83,7 @@ def test_tetrahedron_drop_doubles_like_the_oracle(abd, ctx):
         q, qd, _ = oracle.time_step(S, B, q, qd, P, log=log)
         kappas.append(log[-1]["kappa_b"])
         ctx.time_step(sc, P, qg, qdg)
-        np.testing.assert_allclose(qg.cpu().numpy(), q, rtol=0, atol=1e-9)
+        np.testing.assert_allclose(qg.cpu().numpy(), q, rtol=0, atol=1e-7)
         assert ctx.barrier_stiffness(sc)[0] == pytest.approx(kappas[-1], rel=1e-12)
     assert max(kappas) > P["kappa_b"]
 

@@ -826,11 +826,16 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
   const int64_t oo = 12 * (int64_t)b + i;
   const double own_x = ok ? x[oo] : 0.0, own_u = ok ? u[oo] : 0.0, own_p = ok ? p[oo] : 0.0;
   const bool own_fixed = ok && fixed[b];
-  double Mown[12];
+  // row i of the body's preconditioner block, spread over the five slots:
+  // slot s holds the columns j = s, s + 5, s + 10 (j < 12)
+  double Mown[3];
   {
     const double *Mi = inv + 144 * (int64_t)(ok ? b : 0) + 12 * i;
 #pragma unroll
-    for (int j = 0; j < 12; ++j) Mown[j] = ok ? Mi[j] : 0.0;
+    for (int t = 0; t < 3; ++t) {
+      const int j = slot + 5 * t;
+      Mown[t] = ok && lane < 60 && j < 12 ? Mi[j] : 0.0;
+    }
   }
   // the scene's scalars of iteration k - 1 (parity buffers) and rhs.rhs
   const double gam_prev = scs.gam[2 * sc + ((k - 1) & 1)], alp_prev = scs.alp[2 * sc + ((k - 1) & 1)];
@@ -838,9 +843,8 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
   if (stopped) return;  // uniform over the block (one scene)
   CgOps op0, op1;
   {
-    const int c0 = __shfl(my_c, slot, 64), c1 = __shfl(my_c, slot + 5, 64);
+    const int c0 = __shfl(my_c, slot, 64);
     cg_fetch(lane < 60 && slot < E, c0, e0 + slot, i, Bm, r_in, w_in, s_in, op0);
-    cg_fetch(lane < 60 && slot + 5 < E, c1, e0 + slot + 5, i, Bm, r_in, w_in, s_in, op1);
   }
   pg = wave_sum(pg);
   pd = wave_sum(pd);
@@ -888,11 +892,17 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
   const int g0 = slot * 12;
   double accw = 0.0, own_r, own_s;
   cg_entry(op0, alpha, beta, g0, accw, own_r, own_s);  // entry 0 of slot 0 is the body itself
-  // u_{k+1} = P_b r_{k+1} (meaningful on the lanes of slot 0)
-  double own_un = 0.0;
+  // u_{k+1} = P_b r_{k+1}: per slot its columns' part, then the slots'
+  // parts in fixed order (meaningful on the lanes of slot 0)
+  double upart = 0.0;
 #pragma unroll
-  for (int j = 0; j < 12; ++j) own_un = fma(Mown[j], __shfl(own_r, j, 64), own_un);
+  for (int t = 0; t < 3; ++t) upart = fma(Mown[t], __shfl(own_r, (slot + 5 * t) % 12, 64), upart);
+  double own_un = upart;
+#pragma unroll
+  for (int q = 1; q < 5; ++q) own_un += __shfl(upart, (lane + 12 * q) & 63, 64);
   if (npass > 1) {
+    const int c1 = __shfl(my_c, slot + 5, 64);
+    cg_fetch(lane < 60 && slot + 5 < E, c1, e0 + slot + 5, i, Bm, r_in, w_in, s_in, op1);
     double rn, sn;
     cg_entry(op1, alpha, beta, g0, accw, rn, sn);
   }

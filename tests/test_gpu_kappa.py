@@ -13,8 +13,9 @@ kappa; abd_params.kappa_adaptive) against the oracle's.
   as spheres approach): three steps within 1e-6 of the oracle's trajectory
   and the same kappa.
 - A batch of 16 drop scenes at landing: per-scene kappa in one batch equal,
-  state (1e-7) and stiffness (1e-6 relative), to each scene run on its own,
-  and different between scenes.
+  state (vertices within twice the Newton stopping distance) and stiffness
+  (1e-6 relative), to each scene run on its own, and different between
+  scenes.
 - abd_newton_step and the rollouts reject the adaptive flag."""
 import math
 
@@ -141,9 +142,11 @@ def test_batched_kappa_per_scene(abd, ctx):
         ref = qk.cpu().numpy()
         # (a one-scene run sums a trial's energies in one row, a batch per
         # scene: the line searches compare energies rounded differently, so
-        # over two steps the states part by about 1e-8, far below the
-        # Newton tolerance)
-        assert np.abs(qb[b0:b1] - ref).max() <= 1e-7, k
+        # the two runs may stop Newton at different iterates; each is within
+        # about tol_v dt of the minimiser, so vertices agree to twice that)
+        bar = 2.0 * (1.0 + P["pcg_rtol"]) * P["newton_tol"] * P["dt"]
+        dx = np.abs(oracle.vertex_map(Sk, qb[b0:b1]) - oracle.vertex_map(Sk, ref)).max()
+        assert dx <= bar, (k, dx, bar)
         assert ctx.barrier_stiffness(sck)[0] == pytest.approx(kb[k], rel=1e-6)
 
 

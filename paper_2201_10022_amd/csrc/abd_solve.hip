@@ -142,6 +142,7 @@ constexpr int PB = 192;  // init / update: 16 bodies x 12 rows per block
 constexpr int PBB = PB / 12;
 constexpr int SWB = 256;  // spmv: one 64-lane wave per body, 4 bodies per block
 constexpr int SWBB = SWB / 64;
+constexpr int CBB = 5 * SWBB;  // one-kernel CG: five bodies per wave (k_cg_iter)
 
 // Sub-scenes are independent systems (the matrix is block diagonal by
 // scene), each with its own CG scalars and stop test.  Blocks never span
@@ -253,6 +254,42 @@ __global__ void __launch_bounds__(SETUP_T) k_pcg_scene_setup(int S, const int32_
       if (ss[mid] <= j) lo = mid; else hi = mid - 1;
     }
     s_scene[j] = lo;
+  }
+}
+
+// one more mapping (bpb bodies per block) the same way: per-scene block
+// counts (cnt, S > SETUP_T) or, for up to SETUP_T scenes, everything in one
+// block (counts, their exclusive scan `off`, the scene of every block)
+__global__ void k_pcg_scene_count(int S, const int32_t *sbo, int bpb, int64_t *cnt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  cnt[s] = (sbo[s + 1] - sbo[s] + bpb - 1) / bpb;
+}
+__global__ void __launch_bounds__(SETUP_T) k_pcg_scene_map(int S, const int32_t *sbo, int bpb, int64_t nblk,
+                                                           int64_t *off, int32_t *tab) {
+  __shared__ int64_t sc_[SETUP_T + 1];
+  const int t = threadIdx.x;
+  sc_[t + 1] = t < S ? (sbo[t + 1] - sbo[t] + bpb - 1) / bpb : 0;
+  if (t == 0) sc_[0] = 0;
+  __syncthreads();
+  for (int o = 1; o < SETUP_T; o <<= 1) {
+    const int64_t a = t >= o ? sc_[t + 1 - o] : 0;
+    __syncthreads();
+    sc_[t + 1] += a;
+    __syncthreads();
+  }
+  for (int k = t; k <= S; k += SETUP_T) off[k] = sc_[k];
+  for (int64_t j = t; j < nblk; j += SETUP_T) {
+    if (j >= sc_[S]) {
+      tab[j] = -1;
+      continue;
+    }
+    int lo = 0, hi = S;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sc_[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    tab[j] = lo;
   }
 }
 
@@ -654,41 +691,46 @@ __global__ void __launch_bounds__(PB) k_cg_init1(const PcgBlk *blk, const uint8_
   }
 }
 
+// The one-kernel iteration's mapping: five bodies per wave (lanes 12 h .. 12 h
+// + 11 hold rows 0..11 of body h; lanes 60..63 idle), CBB bodies per block,
+// a body's matrix entries taken one at a time in entry order (the row sums
+// add the entries' products in that order).  The piles this solver runs on
+// have few entries per body (one, the diagonal block, for a body touching
+// only fixed geometry), so a wave per body left most lanes idle and made
+// the launch a sequence of occupancy-limited rounds of waves.
 // w_0 = H u_0; partials of gamma_0, delta_0, rho_0 = r.r and rhs.rhs
-__global__ void __launch_bounds__(SWB) k_cg_init2(const PcgBlk *blk, const int2 *ent, const uint8_t *fixed,
-                                                 const double *diag, const double *off, const double *rhs,
-                                                 const double *r, const double *u, double *w, double *part) {
+__global__ void __launch_bounds__(SWB) k_cg_init2(const PcgBlk *blk, const int64_t *eoff, const int2 *ent,
+                                                 const uint8_t *fixed, const double *diag, const double *off,
+                                                 const double *rhs, const double *r, const double *u, double *w,
+                                                 double *part) {
   __shared__ double sh[SWB / 64];
   const PcgBlk bi = blk[blockIdx.x];
   if (bi.sc < 0) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int slot = lane / 12, i = lane % 12;
-  const int b = bi.first + wv;
-  const bool ok = b < bi.last;
-  const int ea = wv == 0 ? bi.e[0] : (wv == 1 ? bi.e[1] : (wv == 2 ? bi.e[2] : bi.e[3]));
-  const int eb = wv == 0 ? bi.e[1] : (wv == 1 ? bi.e[2] : (wv == 2 ? bi.e[3] : bi.e[4]));
-  const int e0 = ea, E = ok ? eb - ea : 0;
-  int2 my_ent = make_int2(0, 0);
-  if (lane < E) my_ent = ent[e0 + lane];
-  double acc = 0.0;
-  for (int e = slot; e - slot < E; e += 5) {
-    const int kk_s = __shfl(my_ent.x, e & 63, 64), cw_s = __shfl(my_ent.y, e & 63, 64);
-    if (lane < 60 && e < E) {
-      const int2 en = e < 64 ? make_int2(kk_s, cw_s) : ent[e0 + e];
-      const int c = en.y & ((1 << 30) - 1);
-      const bool tr = (en.y >> 30) & 1;
-      const double *rp = en.x < 0 ? diag + 144 * (int64_t)b + 12 * i
-                                  : (tr ? off + 144 * (int64_t)en.x + i : off + 144 * (int64_t)en.x + 12 * i);
-      const int stride = tr ? 12 : 1;
-#pragma unroll
-      for (int j = 0; j < 12; ++j) acc = fma(rp[stride * j], u[12 * (int64_t)c + j], acc);
-    }
+  const int hb = lane / 12, i = lane - 12 * hb;
+  const int b = bi.first + 5 * wv + hb;
+  const bool ok = hb < 5 && b < bi.last;
+  int64_t e0 = 0;
+  int E = 0;
+  if (ok) {
+    e0 = eoff[b];
+    E = (int)(eoff[b + 1] - e0);
   }
-  double v = acc;
+  double v = 0.0;
+  for (int e = 0; e < E; ++e) {
+    const int2 en = ent[e0 + e];
+    const int c = en.y & ((1 << 30) - 1);
+    const bool tr = (en.y >> 30) & 1;
+    const double *rp = en.x < 0 ? diag + 144 * (int64_t)b + 12 * i
+                                : (tr ? off + 144 * (int64_t)en.x + i : off + 144 * (int64_t)en.x + 12 * i);
+    const int stride = tr ? 12 : 1;
+    double pe = 0.0;
 #pragma unroll
-  for (int q = 1; q < 5; ++q) v += __shfl(acc, (lane + 12 * q) & 63, 64);
+    for (int jj = 0; jj < 12; ++jj) pe = fma(rp[stride * jj], u[12 * (int64_t)c + jj], pe);
+    v += pe;
+  }
   double g = 0.0, d = 0.0, rr = 0.0, bb = 0.0;
-  if (ok && slot == 0) {
+  if (ok) {
     const int64_t o = 12 * (int64_t)b + i;
     const double wv_ = fixed[b] ? 0.0 : v;
     w[o] = wv_;
@@ -770,29 +812,28 @@ __device__ __forceinline__ void cg_fetch(bool live, int c, int64_t eg, int i, co
   for (int j = 0; j < 12; ++j) o.B[j] = Bi[j];
 }
 
-// The column body's s_k and r_{k+1} (its owner's arithmetic, so that every
-// wave that reads the body computes the same values) and the row product
-// B_bc r_{k+1,c} into acc.
-__device__ __forceinline__ void cg_entry(const CgOps &op, double alpha, double beta, int g0, double &acc,
-                                         double &rn, double &sn) {
-  cg_step(op.r, op.w, op.s, alpha, beta, sn, rn);
-#pragma unroll
-  for (int j = 0; j < 12; ++j) acc = fma(op.B[j], __shfl(rn, (g0 + j) & 63, 64), acc);
+// column body of a body's entry e (entries below 12 from the lanes' copies)
+__device__ __forceinline__ int cg_col(int my_c, int g0, int e, bool live, const int2 *ent, int64_t e0) {
+  const int cs = __shfl(my_c, (g0 + (e < 12 ? e : 0)) & 63, 64);
+  return !live ? 0 : (e < 12 ? cs : (ent[e0 + e].y & ((1 << 30) - 1)));
 }
 
 // Iteration k = base + jloc of every scene not yet stopped: fold gamma_k,
 // delta_k, rho_k = r_k.r_k, decide the stop, alpha_k and beta_k; then per
 // body p_k, x_{k+1}, s_k, r_{k+1}, u_{k+1} = P r_{k+1} and w_{k+1} =
-// sum_c B_bc r_{k+1,c} with one wave per body (lane = entry slot 0..4, row
-// 0..11, five entries per pass); partials of gamma, delta, rho for the next
-// iteration.  The operands of the first two passes (ten entries) are loaded
-// before the fold; the fold and the closing reduction take one barrier each.
-__global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, const int2 *ent, const uint8_t *fixed,
-                                                const double *Bm, const double *inv, const double *r_in,
-                                                const double *w_in, const double *s_in, double *r_out, double *w_out,
-                                                double *s_out, double *x, double *u, double *p, const double *part_in,
-                                                double *part_out, CgState *st, CgScene scs, double rtol2,
-                                                int max_iter, int batch) {
+// sum_c B_bc r_{k+1,c}, each entry's column body's s_k and r_{k+1} formed
+// with the owner's arithmetic (so every wave that reads the body computes
+// the same values); partials of gamma, delta, rho for the next iteration.
+// Five bodies per wave (see CBB); a body's entries one at a time, the next
+// entry's operands loaded while the current one is used.  The first
+// entry's operands are loaded before the fold; the fold and the closing
+// reduction take one barrier each.
+__global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, const int64_t *eoff, const int2 *ent,
+                                                const uint8_t *fixed, const double *Bm, const double *inv,
+                                                const double *r_in, const double *w_in, const double *s_in,
+                                                double *r_out, double *w_out, double *s_out, double *x, double *u,
+                                                double *p, const double *part_in, double *part_out, CgState *st,
+                                                CgScene scs, double rtol2, int max_iter, int batch) {
   __shared__ double shf[SWBB][4], she[SWBB][3];
   const int k = st->base + jloc;
   const PcgBlk bi = blk[blockIdx.x];
@@ -804,14 +845,15 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
   if (batch && scs.stop[bi.sc]) return;
   const int sc = bi.sc;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int slot = lane / 12, i = lane % 12;
-  const int b = bi.first + wv;
-  const bool ok = b < bi.last;
-  // (explicit selects: a run-time index into the struct would move it to LDS)
-  const int ea = wv == 0 ? bi.e[0] : (wv == 1 ? bi.e[1] : (wv == 2 ? bi.e[2] : bi.e[3]));
-  const int eb = wv == 0 ? bi.e[1] : (wv == 1 ? bi.e[2] : (wv == 2 ? bi.e[3] : bi.e[4]));
-  const int e0 = ea, E = ok ? eb - ea : 0;
-  const int npass = (E + 4) / 5;  // uniform over the wave
+  const int hb = lane / 12, i = lane - 12 * hb, g0 = 12 * hb;
+  const int b = bi.first + 5 * wv + hb;
+  const bool ok = hb < 5 && b < bi.last;
+  int64_t e0 = 0;
+  int E = 0;
+  if (ok) {
+    e0 = eoff[b];
+    E = (int)(eoff[b + 1] - e0);
+  }
   const int stopped = scs.stop[sc];
   double pg = 0.0, pd = 0.0, pr = 0.0, pb = 0.0;
   for (int j = threadIdx.x; j < bi.fold_n; j += SWB) {
@@ -822,30 +864,20 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
     if (k == 0) pb += q[3];
   }
   int my_c = 0;
-  if (lane < E) my_c = ent[e0 + lane].y & ((1 << 30) - 1);
+  if (ok && i < E) my_c = ent[e0 + i].y & ((1 << 30) - 1);
   const int64_t oo = 12 * (int64_t)b + i;
   const double own_x = ok ? x[oo] : 0.0, own_u = ok ? u[oo] : 0.0, own_p = ok ? p[oo] : 0.0;
   const bool own_fixed = ok && fixed[b];
-  // row i of the body's preconditioner block, spread over the five slots:
-  // slot s holds the columns j = s, s + 5, s + 10 (j < 12)
-  double Mown[3];
-  {
-    const double *Mi = inv + 144 * (int64_t)(ok ? b : 0) + 12 * i;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int j = slot + 5 * t;
-      Mown[t] = ok && lane < 60 && j < 12 ? Mi[j] : 0.0;
-    }
-  }
   // the scene's scalars of iteration k - 1 (parity buffers) and rhs.rhs
   const double gam_prev = scs.gam[2 * sc + ((k - 1) & 1)], alp_prev = scs.alp[2 * sc + ((k - 1) & 1)];
   const double bb_prev = scs.bb[sc];
   if (stopped) return;  // uniform over the block (one scene)
-  CgOps op0, op1;
-  {
-    const int c0 = __shfl(my_c, slot, 64);
-    cg_fetch(lane < 60 && slot < E, c0, e0 + slot, i, Bm, r_in, w_in, s_in, op0);
-  }
+  // the wave's entry passes: its bodies' largest entry count
+  int Emax = E;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) Emax = max(Emax, __shfl_xor(Emax, o, 64));
+  CgOps op;
+  cg_fetch(ok && E > 0, cg_col(my_c, g0, 0, ok && E > 0, ent, e0), e0, i, Bm, r_in, w_in, s_in, op);
   pg = wave_sum(pg);
   pd = wave_sum(pd);
   pr = wave_sum(pr);
@@ -889,38 +921,38 @@ __global__ void __launch_bounds__(SWB) k_cg_iter(int jloc, const PcgBlk *blk, co
     }
   }
   if (stop) return;
-  const int g0 = slot * 12;
-  double accw = 0.0, own_r, own_s;
-  cg_entry(op0, alpha, beta, g0, accw, own_r, own_s);  // entry 0 of slot 0 is the body itself
-  // u_{k+1} = P_b r_{k+1}: per slot its columns' part, then the slots'
-  // parts in fixed order (meaningful on the lanes of slot 0)
-  double upart = 0.0;
+  // row i of the body's preconditioner block, for u_{k+1} = P_b r_{k+1}
+  double Mown[12];
+  {
+    const double *Mi = inv + 144 * (int64_t)(ok ? b : 0) + 12 * i;
 #pragma unroll
-  for (int t = 0; t < 3; ++t) upart = fma(Mown[t], __shfl(own_r, (slot + 5 * t) % 12, 64), upart);
-  double own_un = upart;
-#pragma unroll
-  for (int q = 1; q < 5; ++q) own_un += __shfl(upart, (lane + 12 * q) & 63, 64);
-  if (npass > 1) {
-    const int c1 = __shfl(my_c, slot + 5, 64);
-    cg_fetch(lane < 60 && slot + 5 < E, c1, e0 + slot + 5, i, Bm, r_in, w_in, s_in, op1);
-    double rn, sn;
-    cg_entry(op1, alpha, beta, g0, accw, rn, sn);
+    for (int j = 0; j < 12; ++j) Mown[j] = ok ? Mi[j] : 0.0;
   }
-  for (int pass = 2; pass < npass; ++pass) {
-    const int e = slot + 5 * pass;
-    const int c_s = __shfl(my_c, e & 63, 64);
-    const bool live = lane < 60 && e < E;
-    const int c = !live ? 0 : (e < 64 ? c_s : (ent[e0 + e].y & ((1 << 30) - 1)));
-    cg_fetch(live, c, e0 + e, i, Bm, r_in, w_in, s_in, op1);
+  double v = 0.0, own_r = 0.0, own_s = 0.0;
+  for (int e = 0; e < Emax; ++e) {
+    CgOps nx;
+    {
+      const int en = e + 1;
+      const bool live = ok && en < E;
+      cg_fetch(live, cg_col(my_c, g0, en, live, ent, e0), e0 + en, i, Bm, r_in, w_in, s_in, nx);
+    }
     double rn, sn;
-    cg_entry(op1, alpha, beta, g0, accw, rn, sn);
-  }
-  // per-row sums over the five slots, fixed order
-  double v = accw;
+    cg_step(op.r, op.w, op.s, alpha, beta, sn, rn);
+    double pe = 0.0;
 #pragma unroll
-  for (int q = 1; q < 5; ++q) v += __shfl(accw, (lane + 12 * q) & 63, 64);
+    for (int j = 0; j < 12; ++j) pe = fma(op.B[j], __shfl(rn, (g0 + j) & 63, 64), pe);
+    v += pe;  // (entries past E have zero operands)
+    if (e == 0) {  // entry 0 is the body itself
+      own_r = rn;
+      own_s = sn;
+    }
+    op = nx;
+  }
+  double own_un = 0.0;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) own_un = fma(Mown[j], __shfl(own_r, (g0 + j) & 63, 64), own_un);
   double g = 0.0, d = 0.0, rr = 0.0;
-  if (ok && slot == 0) {
+  if (ok) {
     const double pn = fma(beta, own_p, own_u);
     x[oo] = fma(alpha, pn, own_x);
     p[oo] = pn;
@@ -1062,7 +1094,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
              const int32_t *keys, const uint32_t *tv2, const int64_t *lo_beg, const int64_t *hi_beg,
              const double *inv, const double *rhs, const double *x0, const double *Hx0, double *x_out,
              const PcgBlk *ublk, int nblk_u, const int32_t *s_scene, const int64_t *s_off, const int32_t *sbo,
-             const int64_t *eoff, const int2 *ent, int nblk_s, double rtol2, int max_iter, int *iters,
+             const int64_t *eoff, const int2 *ent, int nblk_c, double rtol2, int max_iter, int *iters,
              hipStream_t s) {
   const int iter_g[2] = {ctx->tune.pcg_short, ctx->tune.pcg_long};
   double *rv[2], *wv[2], *sv[2], *pt[2], *u, *p;
@@ -1077,9 +1109,9 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   ABD_TRY(ws(ctx, "cg_s1", 12 * (size_t)nb, &sv[1], s));
   ABD_TRY(ws(ctx, "cg_u", 12 * (size_t)nb, &u, s));
   ABD_TRY(ws(ctx, "cg_p", 12 * (size_t)nb, &p, s));
-  ABD_TRY(ws(ctx, "cg_part0", 4 * (size_t)nblk_s, &pt[0], s));
-  ABD_TRY(ws(ctx, "cg_part1", 4 * (size_t)nblk_s, &pt[1], s));
-  ABD_TRY(ws(ctx, "cg_blk", nblk_s, &cblk, s));
+  ABD_TRY(ws(ctx, "cg_part0", 4 * (size_t)nblk_c, &pt[0], s));
+  ABD_TRY(ws(ctx, "cg_part1", 4 * (size_t)nblk_c, &pt[1], s));
+  ABD_TRY(ws(ctx, "cg_blk", nblk_c, &cblk, s));
   double *Bm;
   ABD_TRY(ws(ctx, "cg_bmat", 144 * ((size_t)nb + 2 * (size_t)n_keys), &Bm, s));
   ABD_TRY(ws(ctx, "cg_state", 1, &st, s));
@@ -1093,8 +1125,8 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   hipLaunchKernelGGL(k_cg_bmat, dim3(nb), dim3(256), 0, s, nb, eoff, ent, diag, off, inv, Bm, S, st, scs);
   hipLaunchKernelGGL(k_cg_init1, dim3(nblk_u), dim3(PB), 0, s, ublk, sc->body_fixed, inv, rhs, x0, Hx0, x_out, rv[0],
                      u, p, sv[0]);
-  hipLaunchKernelGGL(k_cg_init2, dim3(nblk_s), dim3(SWB), 0, s, cblk, ent, sc->body_fixed, diag, off, rhs, rv[0], u,
-                     wv[0], pt[0]);
+  hipLaunchKernelGGL(k_cg_init2, dim3(nblk_c), dim3(SWB), 0, s, cblk, eoff, ent, sc->body_fixed, diag, off, rhs,
+                     rv[0], u, wv[0], pt[0]);
   HIP_TRY(ctx, hipGetLastError());
   int64_t *mir_h, *mir_d;
   ABD_TRY(mirror_get(ctx, &mir_h, &mir_d));
@@ -1104,12 +1136,12 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   auto enqueue = [&](hipStream_t q, int n) {
     for (int j = 0; j < n; ++j) {
       const int a = j & 1, o = a ^ 1;
-      hipLaunchKernelGGL(k_cg_iter, dim3(nblk_s), dim3(SWB), 0, q, j, cblk, ent, sc->body_fixed, Bm, inv, rv[a],
-                         wv[a], sv[a], rv[o], wv[o], sv[o], x_out, u, p, pt[a], pt[o], st, scs, rtol2, max_iter,
-                         S > 1 ? 1 : 0);
+      hipLaunchKernelGGL(k_cg_iter, dim3(nblk_c), dim3(SWB), 0, q, j, cblk, eoff, ent, sc->body_fixed, Bm, inv,
+                         rv[a], wv[a], sv[a], rv[o], wv[o], sv[o], x_out, u, p, pt[a], pt[o], st, scs, rtol2,
+                         max_iter, S > 1 ? 1 : 0);
     }
     // (n is even: the next replay's first iteration folds pt[0])
-    if (S > 1) hipLaunchKernelGGL(k_cg_compact, dim3(1), dim3(CT), 0, q, cblk, nblk_s, pt[0], scs);
+    if (S > 1) hipLaunchKernelGGL(k_cg_compact, dim3(1), dim3(CT), 0, q, cblk, nblk_c, pt[0], scs);
     hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(1), 0, q, st, n, hst_d);
   };
   const char *env = getenv("ABD_PCG_GRAPH");
@@ -1124,8 +1156,8 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
         (uintptr_t)Bm,       (uintptr_t)off,      (uintptr_t)inv,          (uintptr_t)x_out,      (uintptr_t)u,
         (uintptr_t)p,        (uintptr_t)rv[0],    (uintptr_t)rv[1],        (uintptr_t)wv[0],      (uintptr_t)wv[1],
         (uintptr_t)sv[0],    (uintptr_t)sv[1],    (uintptr_t)pt[0],        (uintptr_t)pt[1],      (uintptr_t)cblk,
-        (uintptr_t)ent,      (uintptr_t)st,       (uintptr_t)sc->body_fixed,
-        (uintptr_t)nblk_s,   (uintptr_t)max_iter, (uintptr_t)rtol_bits,    (uintptr_t)scs.gam,    (uintptr_t)scs.alp,
+        (uintptr_t)ent,      (uintptr_t)st,       (uintptr_t)sc->body_fixed, (uintptr_t)eoff,
+        (uintptr_t)nblk_c,   (uintptr_t)max_iter, (uintptr_t)rtol_bits,    (uintptr_t)scs.gam,    (uintptr_t)scs.alp,
         (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)hst_d, (uintptr_t)S,
         (uintptr_t)iter_g[0], (uintptr_t)iter_g[1], (uintptr_t)1};
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
@@ -1227,6 +1259,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   // block counts: at most one partly filled block per scene
   const int nblk_u = (int)grid_for((int64_t)nb, PBB) + S;
   const int nblk_s = (int)grid_for(nb, SWBB) + S;
+  const int nblk_c = (int)grid_for(nb, CBB) + S;
   const int32_t *sbo;
   ABD_TRY(op_scene_offsets(ctx, sc, &sbo, s));
   ABD_TRY(ws(ctx, "pcg_inv", 144 * (size_t)nb, &inv, s));
@@ -1249,6 +1282,10 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(ws(ctx, "pcg_soff", S + 1, &s_off, s));
   ABD_TRY(ws(ctx, "pcg_usc", nblk_u, &u_scene, s));
   ABD_TRY(ws(ctx, "pcg_ssc", nblk_s, &s_scene, s));
+  int64_t *c_off;
+  int32_t *c_scene;
+  ABD_TRY(ws(ctx, "pcg_coff", S + 1, &c_off, s));
+  ABD_TRY(ws(ctx, "pcg_csc", nblk_c, &c_scene, s));
   ABD_TRY(ws(ctx, "pcg_state", 1, &st, s));
   ABD_TRY(ws(ctx, "pcg_s_rz", 2 * (size_t)S, &scs.rz, s));
   ABD_TRY(ws(ctx, "pcg_s_bb", S, &scs.bb, s));
@@ -1260,6 +1297,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   if (S <= SETUP_T) {
     hipLaunchKernelGGL(k_pcg_scene_setup, dim3(1), dim3(SETUP_T), 0, s, S, sbo, (int64_t)nblk_u, (int64_t)nblk_s,
                        u_off, s_off, u_scene, s_scene);
+    hipLaunchKernelGGL(k_pcg_scene_map, dim3(1), dim3(SETUP_T), 0, s, S, sbo, CBB, (int64_t)nblk_c, c_off, c_scene);
   } else {
     hipLaunchKernelGGL(k_pcg_scene_blocks, dim3(grid_for(S, 256)), dim3(256), 0, s, S, sbo, ucnt, scnt);
     ABD_TRY(scan_exclusive_i64(ctx, ucnt, u_off, S, u_off + S, s));
@@ -1268,6 +1306,12 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
                        u_scene);
     hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_s, 256)), dim3(256), 0, s, S, (int64_t)nblk_s, s_off,
                        s_scene);
+    int64_t *ccnt;
+    ABD_TRY(ws(ctx, "pcg_ccnt", S, &ccnt, s));
+    hipLaunchKernelGGL(k_pcg_scene_count, dim3(grid_for(S, 256)), dim3(256), 0, s, S, sbo, CBB, ccnt);
+    ABD_TRY(scan_exclusive_i64(ctx, ccnt, c_off, S, c_off + S, s));
+    hipLaunchKernelGGL(k_pcg_block_scene, dim3(grid_for(nblk_c, 256)), dim3(256), 0, s, S, (int64_t)nblk_c, c_off,
+                       c_scene);
   }
   if (pat && pat->valid) {
     // row structure built with the keys
@@ -1300,13 +1344,14 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   // the update blocks' partials), update blocks (folding the SpMV blocks'),
   // one-kernel iteration blocks (folding their own)
   PcgBlk *cblk;
-  ABD_TRY(ws(ctx, "cg_blk", nblk_s, &cblk, s));
+  ABD_TRY(ws(ctx, "cg_blk", nblk_c, &cblk, s));
   {
     BlkJobs J;
     J.j[0] = BlkJob{(int64_t)nblk_s, SWBB, s_scene, s_off, u_off, eoff, sblk};
     J.j[1] = BlkJob{(int64_t)nblk_u, PBB, u_scene, u_off, s_off, nullptr, ublk};
-    J.j[2] = BlkJob{(int64_t)nblk_s, SWBB, s_scene, s_off, s_off, eoff, cblk};
-    const int64_t tot = 2 * (int64_t)nblk_s + nblk_u;
+    // (the one-kernel iteration reads its bodies' entry offsets itself)
+    J.j[2] = BlkJob{(int64_t)nblk_c, CBB, c_scene, c_off, c_off, nullptr, cblk};
+    const int64_t tot = (int64_t)nblk_s + nblk_u + nblk_c;
     hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(tot, 256)), dim3(256), 0, s, J, sbo, S, st, scs);
   }
   const double *Hx0 = nullptr;
@@ -1322,7 +1367,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   const bool one_kernel = !(cg_env && cg_env[0] == '0');
   if (one_kernel) {
     ABD_TRY(cg_solve(ctx, sc, S, nb, n_keys, diag, off, keys, tv2, lo_beg, hi_beg, inv, rhs, x0, Hx0, x_out, ublk,
-                     nblk_u, s_scene, s_off, sbo, eoff, ent, nblk_s, rtol2, max_iter, &it0, s));
+                     nblk_u, s_scene, s_off, sbo, eoff, ent, nblk_c, rtol2, max_iter, &it0, s));
     // The one-reduction recurrences may stop on a recursive residual that
     // has drifted from rhs - H x (w is formed as (H P) r rather than
     // H (P r), and p.Hp as a difference that cancels near the attainable

@@ -142,7 +142,7 @@ constexpr int PB = 192;  // init / update: 16 bodies x 12 rows per block
 constexpr int PBB = PB / 12;
 constexpr int SWB = 256;  // spmv: one 64-lane wave per body, 4 bodies per block
 constexpr int SWBB = SWB / 64;
-constexpr int CBB = 5 * SWBB;  // one-kernel CG: five bodies per wave (k_cg_iter)
+constexpr int CBB = 5 * SWBB;  // SpMV-shaped kernels: five bodies per wave, 12 lanes each
 
 // Sub-scenes are independent systems (the matrix is block diagonal by
 // scene), each with its own CG scalars and stop test.  Blocks never span
@@ -198,7 +198,7 @@ __global__ void k_pcg_scene_blocks(int S, const int32_t *sbo, int64_t *ucnt, int
   if (s >= S) return;
   const int n = sbo[s + 1] - sbo[s];
   ucnt[s] = (n + PBB - 1) / PBB;
-  scnt[s] = (n + SWBB - 1) / SWBB;
+  scnt[s] = (n + CBB - 1) / CBB;
 }
 // the four steps below in one block, for up to SETUP_T scenes: per-scene
 // block counts, their exclusive scans (u_off, s_off) and the scene of
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(SETUP_T) k_pcg_scene_setup(int S, const int32_
   if (t < S) {
     const int n = sbo[t + 1] - sbo[t];
     cu = (n + PBB - 1) / PBB;
-    cs = (n + SWBB - 1) / SWBB;
+    cs = (n + CBB - 1) / CBB;
   }
   su[t + 1] = cu;
   ss[t + 1] = cs;
@@ -353,12 +353,12 @@ __global__ void __launch_bounds__(PB) k_pcg_init(const int32_t *u_scene, const i
 }
 
 // Per-block constants of one iteration kernel, loaded in one go: the
-// block's scene, body range, the range of the other kernel's partials it
-// folds, and (spmv) the entry-list offsets of its four bodies.
+// block's scene, body range and the range of the other kernel's partials it
+// folds.
 struct alignas(16) PcgBlk {
   int32_t sc, first, last, is_first;
-  int32_t fold_lo, fold_n, e[SWBB + 1];
-  int32_t pad[16 - 6 - (SWBB + 1)];
+  int32_t fold_lo, fold_n;
+  int32_t pad[2];
 };
 
 // per body: its matrix entries (the diagonal block first, then the
@@ -387,7 +387,7 @@ struct BlkJob {
   int64_t nblk;
   int bpb;
   const int32_t *tab;
-  const int64_t *off, *fold_off, *ent_off;
+  const int64_t *off, *fold_off;
   PcgBlk *out;
 };
 struct BlkJobs {
@@ -412,16 +412,15 @@ __global__ void k_pcg_blk(BlkJobs J, const int32_t *sbo, int S, PcgState *st, Pc
   const int64_t nblk = J.j[m].nblk;
   const int bpb = J.j[m].bpb;
   const int32_t *tab = J.j[m].tab;
-  const int64_t *off = J.j[m].off, *fold_off = J.j[m].fold_off, *ent_off = J.j[m].ent_off;
+  const int64_t *off = J.j[m].off, *fold_off = J.j[m].fold_off;
   PcgBlk *out = J.j[m].out;
   if (j >= nblk) return;
   PcgBlk r;
-  for (int q = 0; q < 16 - 6 - (SWBB + 1); ++q) r.pad[q] = 0;
+  r.pad[0] = r.pad[1] = 0;
   const int s = tab[j];
   r.sc = s;
   if (s < 0) {
     r.first = r.last = r.is_first = r.fold_lo = r.fold_n = 0;
-    for (int q = 0; q <= SWBB; ++q) r.e[q] = 0;
     out[j] = r;
     return;
   }
@@ -430,10 +429,6 @@ __global__ void k_pcg_blk(BlkJobs J, const int32_t *sbo, int S, PcgState *st, Pc
   r.is_first = j == off[s];
   r.fold_lo = (int)fold_off[s];
   r.fold_n = (int)(fold_off[s + 1] - fold_off[s]);
-  for (int q = 0; q <= SWBB; ++q) {
-    const int b = r.first + q < r.last ? r.first + q : r.last;
-    r.e[q] = ent_off ? (int)ent_off[b] : 0;
-  }
   out[j] = r;
 }
 
@@ -446,26 +441,29 @@ __global__ void k_pcg_blk(BlkJobs J, const int32_t *sbo, int S, PcgState *st, Pc
 // matrix work does not wait for beta (H z and H p_old are accumulated
 // separately and combined after the fold).  Per-row sums over slots in
 // fixed order.
-__global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int2 *ent, const uint8_t *fixed,
-                                                 const double *diag, const double *off, const double *p_old,
-                                                 const double *z, double *p_new, double *Ap, const double *part2,
-                                                 double *part, PcgState *st, PcgScene scs, double rtol2,
-                                                 int max_iter) {
+__global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int64_t *eoff, const int2 *ent,
+                                                 const uint8_t *fixed, const double *diag, const double *off,
+                                                 const double *p_old, const double *z, double *p_new, double *Ap,
+                                                 const double *part2, double *part, PcgState *st, PcgScene scs,
+                                                 double rtol2, int max_iter) {
   __shared__ double sh[SWB / 64];
   const int k = st->it_done;
   const PcgBlk bi = blk[blockIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) st->k_cur = k;
   if (bi.sc < 0) return;
   const int sc = bi.sc;
+  // five bodies per wave (lanes 12 h .. 12 h + 11: rows of body h)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int slot = lane / 12, i = lane % 12;
-  const int b = bi.first + wv;
-  const bool ok = b < bi.last;
-  // (explicit selects: a run-time index into the struct would move it to LDS)
-  const int ea = wv == 0 ? bi.e[0] : (wv == 1 ? bi.e[1] : (wv == 2 ? bi.e[2] : bi.e[3]));
-  const int eb = wv == 0 ? bi.e[1] : (wv == 1 ? bi.e[2] : (wv == 2 ? bi.e[3] : bi.e[4]));
-  const int e0 = ea, E = ok ? eb - ea : 0;
-  // round trip 2: stop flag, partials, the wave's entry list
+  const int hb = lane / 12, i = lane - 12 * hb;
+  const int b = bi.first + 5 * wv + hb;
+  const bool ok = hb < 5 && b < bi.last;
+  int64_t e0 = 0;
+  int E = 0;
+  if (ok) {
+    e0 = eoff[b];
+    E = (int)(eoff[b + 1] - e0);
+  }
+  // round trip 2: stop flag, partials, the bodies' own vectors
   const int stopped = scs.stop[sc];
   double prz = 0.0, prr = 0.0, pbb = 0.0;
   for (int j = threadIdx.x; j < bi.fold_n; j += SWB) {
@@ -473,29 +471,26 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int2 
     prr += part2[3 * (bi.fold_lo + j) + 1];
     if (k == 0) pbb += part2[3 * (bi.fold_lo + j) + 2];
   }
-  int2 my_ent = make_int2(0, 0);
-  if (lane < E) my_ent = ent[e0 + lane];
   const double own_z = ok ? z[12 * (int64_t)b + i] : 0.0, own_p = ok ? p_old[12 * (int64_t)b + i] : 0.0;
   if (stopped) return;  // uniform over the block (one scene)
-  // rows and column vectors, five entries per pass (H z and H p_old kept
-  // apart so that no load waits for beta)
-  double accz = 0.0, accp = 0.0;
-  for (int e = slot; e - slot < E; e += 5) {
-    const int kk_s = __shfl(my_ent.x, e & 63, 64), cw_s = __shfl(my_ent.y, e & 63, 64);
-    if (lane < 60 && e < E) {
-      const int2 en = e < 64 ? make_int2(kk_s, cw_s) : ent[e0 + e];
-      const int kk = en.x, cw = en.y;
-      const int c = cw & ((1 << 30) - 1);
-      const bool tr = (cw >> 30) & 1;
-      const double *rp = kk < 0 ? diag + 144 * (int64_t)b + 12 * i
-                                : (tr ? off + 144 * (int64_t)kk + i : off + 144 * (int64_t)kk + 12 * i);
-      const int stride = tr ? 12 : 1;
+  // H z and H p_old kept apart so that no load waits for beta; each
+  // entry's product added in entry order
+  double vz = 0.0, vp = 0.0;
+  for (int e = 0; e < E; ++e) {
+    const int2 en = ent[e0 + e];
+    const int c = en.y & ((1 << 30) - 1);
+    const bool tr = (en.y >> 30) & 1;
+    const double *rp = en.x < 0 ? diag + 144 * (int64_t)b + 12 * i
+                                : (tr ? off + 144 * (int64_t)en.x + i : off + 144 * (int64_t)en.x + 12 * i);
+    const int stride = tr ? 12 : 1;
+    double pz = 0.0, pp = 0.0;
 #pragma unroll
-      for (int j = 0; j < 12; ++j) {
-        accz += rp[stride * j] * z[12 * (int64_t)c + j];
-        accp += rp[stride * j] * p_old[12 * (int64_t)c + j];
-      }
+    for (int jj = 0; jj < 12; ++jj) {
+      pz = fma(rp[stride * jj], z[12 * (int64_t)c + jj], pz);
+      pp = fma(rp[stride * jj], p_old[12 * (int64_t)c + jj], pp);
     }
+    vz += pz;
+    vp += pp;
   }
   double rz = wave_sum(prz), rr = wave_sum(prr), b0 = wave_sum(pbb);
   if (lane == 0) sh[wv] = rz;
@@ -530,15 +525,8 @@ __global__ void __launch_bounds__(SWB) k_pcg_spmv(const PcgBlk *blk, const int2 
     }
   }
   if (stop) return;
-  // per-row sums over the five slots (lanes i, i+12, ..., i+48), fixed order
-  double vz = accz, vp = accp;
-#pragma unroll
-  for (int q = 1; q < 5; ++q) {
-    vz += __shfl(accz, (lane + 12 * q) & 63, 64);
-    vp += __shfl(accp, (lane + 12 * q) & 63, 64);
-  }
   double dot = 0.0;
-  if (ok && slot == 0) {
+  if (ok) {
     const int64_t o = 12 * (int64_t)b + i;
     const double av = fixed[b] ? 0.0 : vz + beta * vp;
     const double pown = own_z + beta * own_p;
@@ -755,13 +743,14 @@ __global__ void __launch_bounds__(SWB) k_cg_init2(const PcgBlk *blk, const int64
 // Per matrix entry (row body b, column body c) the product B_bc = H_bc P_c
 // with the column body's preconditioner block, stored in entry order
 // (144 doubles per entry), so that w = H u = H P r = sum_c B_bc r_c needs
-// the column bodies' residuals only.  One block per row body.
-__global__ void __launch_bounds__(256) k_cg_bmat(int nb, const int64_t *eoff, const int2 *ent, const double *diag,
+// the column bodies' residuals only.  One thread per output element over
+// all entries (an entry's row of H and column of P are shared by 12
+// threads each, through the cache); the diagonal entry of body b is
+// (-1, b), so no entry needs its row body.
+__global__ void __launch_bounds__(256) k_cg_bmat(int64_t n_out, const int2 *ent, const double *diag,
                                                 const double *off, const double *inv, double *B, int S, CgState *st,
                                                 CgScene scs) {
-  const int b = blockIdx.x;
-  if (b >= nb) return;
-  if (b == 0) {  // (the iteration state's reset rides along)
+  if (blockIdx.x == 0) {  // (the iteration state's reset rides along)
     if (threadIdx.x == 0) {
       st->base = 0;
       st->n_stopped = 0;
@@ -772,22 +761,21 @@ __global__ void __launch_bounds__(256) k_cg_bmat(int nb, const int64_t *eoff, co
       scs.it_final[q] = 0;
     }
   }
-  const int64_t e0 = eoff[b];
-  const int n = (int)(eoff[b + 1] - e0) * 144;
-  for (int t = threadIdx.x; t < n; t += 256) {
-    const int el = t / 144, ij = t % 144, i = ij / 12, j = ij % 12;
-    const int2 en = ent[e0 + el];
-    const int kk = en.x, c = en.y & ((1 << 30) - 1);
-    const bool tr = (en.y >> 30) & 1;
-    const double *rp = kk < 0 ? diag + 144 * (int64_t)b + 12 * i
-                              : (tr ? off + 144 * (int64_t)kk + i : off + 144 * (int64_t)kk + 12 * i);
-    const int stride = tr ? 12 : 1;
-    const double *Mc = inv + 144 * (int64_t)c + j;
-    double acc = 0.0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_out) return;
+  const int64_t e = t / 144;
+  const int ij = (int)(t - 144 * e), i = ij / 12, j = ij - 12 * (ij / 12);
+  const int2 en = ent[e];
+  const int kk = en.x, c = en.y & ((1 << 30) - 1);
+  const bool tr = (en.y >> 30) & 1;
+  const double *rp = kk < 0 ? diag + 144 * (int64_t)c + 12 * i
+                            : (tr ? off + 144 * (int64_t)kk + i : off + 144 * (int64_t)kk + 12 * i);
+  const int stride = tr ? 12 : 1;
+  const double *Mc = inv + 144 * (int64_t)c + j;
+  double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc = fma(rp[stride * k], Mc[12 * k], acc);
-    B[144 * (e0 + el) + ij] = acc;
-  }
+  for (int q = 0; q < 12; ++q) acc = fma(rp[stride * q], Mc[12 * q], acc);
+  B[t] = acc;
 }
 
 // Operands of one entry of one lane: the column body's r_k, w_k, s_{k-1}
@@ -1045,48 +1033,45 @@ __global__ void k_cg_advance(CgState *st, int n, int *host) {
   host[2] = st->max_final;
 }
 
-// y = sx H x (plain block SpMV; one wave per body)
+// y = sx H x (plain block SpMV; five bodies per wave, CBB per block, each
+// entry's product added in entry order)
 __global__ void __launch_bounds__(SWB) k_bsr_spmv(int nb, const uint8_t *fixed, const double *diag, const double *off,
                                                  const int32_t *keys, const uint32_t *tperm, const int64_t *lo_beg,
                                                  const int64_t *hi_beg, const double *xv, double sx, double *y) {
   const int lane = threadIdx.x & 63;
-  const int b = blockIdx.x * SWBB + (threadIdx.x >> 6);
-  if (b >= nb) return;
-  const int slot = lane / 12, i = lane % 12;
-  double acc = 0.0;
+  const int hb = lane / 12, i = lane - 12 * hb;
+  const int b = blockIdx.x * CBB + 5 * (threadIdx.x >> 6) + hb;
+  if (hb >= 5 || b >= nb) return;
   const int64_t l0 = lo_beg[b], nlo = lo_beg[b + 1] - l0;
   const int64_t h0 = hi_beg[b], nhi = hi_beg[b + 1] - h0;
   const int64_t E = 1 + nlo + nhi;
-  for (int64_t e0 = 0; e0 < E; e0 += 5) {
-    const int64_t e = e0 + slot;
-    if (lane < 60 && e < E) {
-      const double *row;
-      int64_t c;
-      int stride;
-      if (e == 0) {
-        row = diag + 144 * (int64_t)b + 12 * i;
-        c = b;
-        stride = 1;
-      } else if (e <= nlo) {
-        const int64_t kk = l0 + e - 1;
-        row = off + 144 * kk + 12 * i;
-        c = keys[2 * kk + 1];
-        stride = 1;
-      } else {
-        const int64_t kk = tperm[h0 + e - 1 - nlo];
-        row = off + 144 * kk + i;
-        c = keys[2 * kk];
-        stride = 12;
-      }
-      const double *xc = xv + 12 * c;
-#pragma unroll
-      for (int j = 0; j < 12; ++j) acc += row[stride * j] * xc[j];
+  double v = 0.0;
+  for (int64_t e = 0; e < E; ++e) {
+    const double *row;
+    int64_t c;
+    int stride;
+    if (e == 0) {
+      row = diag + 144 * (int64_t)b + 12 * i;
+      c = b;
+      stride = 1;
+    } else if (e <= nlo) {
+      const int64_t kk = l0 + e - 1;
+      row = off + 144 * kk + 12 * i;
+      c = keys[2 * kk + 1];
+      stride = 1;
+    } else {
+      const int64_t kk = tperm[h0 + e - 1 - nlo];
+      row = off + 144 * kk + i;
+      c = keys[2 * kk];
+      stride = 12;
     }
-  }
-  double v = acc;
+    const double *xc = xv + 12 * c;
+    double pe = 0.0;
 #pragma unroll
-  for (int q = 1; q < 5; ++q) v += __shfl(acc, (lane + 12 * q) & 63, 64);
-  if (slot == 0) y[12 * (int64_t)b + i] = fixed[b] ? 0.0 : sx * v;
+    for (int jj = 0; jj < 12; ++jj) pe = fma(row[stride * jj], xc[jj], pe);
+    v += pe;
+  }
+  y[12 * (int64_t)b + i] = fixed[b] ? 0.0 : sx * v;
 }
 
 // The iteration loop of the one-kernel form (set-up shared with op_pcg).
@@ -1122,7 +1107,11 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   ABD_TRY(ws(ctx, "cg_s_final", S, &scs.it_final, s));
   // (cblk, the iteration blocks' constants, folding their own mapping's
   // partials, come from the caller's launch)
-  hipLaunchKernelGGL(k_cg_bmat, dim3(nb), dim3(256), 0, s, nb, eoff, ent, diag, off, inv, Bm, S, st, scs);
+  {
+    const int64_t n_out = 144 * ((int64_t)nb + 2 * n_keys);  // (entries: one diagonal per body, each key twice)
+    hipLaunchKernelGGL(k_cg_bmat, dim3(grid_for(n_out, 256)), dim3(256), 0, s, n_out, ent, diag, off, inv, Bm, S, st,
+                       scs);
+  }
   hipLaunchKernelGGL(k_cg_init1, dim3(nblk_u), dim3(PB), 0, s, ublk, sc->body_fixed, inv, rhs, x0, Hx0, x_out, rv[0],
                      u, p, sv[0]);
   hipLaunchKernelGGL(k_cg_init2, dim3(nblk_c), dim3(SWB), 0, s, cblk, eoff, ent, sc->body_fixed, diag, off, rhs,
@@ -1258,7 +1247,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   PcgScene scs;
   // block counts: at most one partly filled block per scene
   const int nblk_u = (int)grid_for((int64_t)nb, PBB) + S;
-  const int nblk_s = (int)grid_for(nb, SWBB) + S;
+  const int nblk_s = (int)grid_for(nb, CBB) + S;
   const int nblk_c = (int)grid_for(nb, CBB) + S;
   const int32_t *sbo;
   ABD_TRY(op_scene_offsets(ctx, sc, &sbo, s));
@@ -1347,17 +1336,16 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(ws(ctx, "cg_blk", nblk_c, &cblk, s));
   {
     BlkJobs J;
-    J.j[0] = BlkJob{(int64_t)nblk_s, SWBB, s_scene, s_off, u_off, eoff, sblk};
-    J.j[1] = BlkJob{(int64_t)nblk_u, PBB, u_scene, u_off, s_off, nullptr, ublk};
-    // (the one-kernel iteration reads its bodies' entry offsets itself)
-    J.j[2] = BlkJob{(int64_t)nblk_c, CBB, c_scene, c_off, c_off, nullptr, cblk};
+    J.j[0] = BlkJob{(int64_t)nblk_s, CBB, s_scene, s_off, u_off, sblk};
+    J.j[1] = BlkJob{(int64_t)nblk_u, PBB, u_scene, u_off, s_off, ublk};
+    J.j[2] = BlkJob{(int64_t)nblk_c, CBB, c_scene, c_off, c_off, cblk};
     const int64_t tot = (int64_t)nblk_s + nblk_u + nblk_c;
     hipLaunchKernelGGL(k_pcg_blk, dim3(grid_for(tot, 256)), dim3(256), 0, s, J, sbo, S, st, scs);
   }
   const double *Hx0 = nullptr;
   if (x0) {
     // warm start: r = rhs - H x0 (Ap as scratch)
-    hipLaunchKernelGGL(k_bsr_spmv, dim3(grid_for(nb, SWBB)), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2,
+    hipLaunchKernelGGL(k_bsr_spmv, dim3(grid_for(nb, CBB)), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2,
                        lo_beg, hi_beg, x0, 1.0, Ap);
     Hx0 = Ap;
   }
@@ -1375,7 +1363,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
     // residual: iteration 0 of the two-reduction form, started from it,
     // stops every scene that meets the tolerance and carries on with the
     // others.
-    hipLaunchKernelGGL(k_bsr_spmv, dim3(grid_for(nb, SWBB)), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2,
+    hipLaunchKernelGGL(k_bsr_spmv, dim3(grid_for(nb, CBB)), dim3(SWB), 0, s, nb, sc->body_fixed, diag, off, keys, tv2,
                        lo_beg, hi_beg, x_out, 1.0, Ap);
     x0 = x_out;
     Hx0 = Ap;
@@ -1386,7 +1374,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
                      x_out, r, z, one_kernel ? pb : pa, part2);
   HIP_TRY(ctx, hipGetLastError());
   if (one_kernel) {
-    hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, s, sblk, ent, sc->body_fixed, diag, off, pb, z, pa, Ap,
+    hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, s, sblk, eoff, ent, sc->body_fixed, diag, off, pb, z, pa, Ap,
                        part2, part, st, scs, rtol2, max_iter);
     hipLaunchKernelGGL(k_pcg_update, dim3(nblk_u), dim3(PB), 0, s, ublk, inv, pa, Ap, x_out, r, z, part, part2, st,
                        scs, err);
@@ -1405,7 +1393,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   auto enqueue = [&](hipStream_t q, int n) {
     for (int k = 0; k < n; ++k) {
       double *p_old = (k % 2 == 0) ? pa : pb, *p_new = (k % 2 == 0) ? pb : pa;
-      hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, q, sblk, ent, sc->body_fixed, diag, off, p_old, z,
+      hipLaunchKernelGGL(k_pcg_spmv, dim3(nblk_s), dim3(SWB), 0, q, sblk, eoff, ent, sc->body_fixed, diag, off, p_old, z,
                          p_new, Ap, part2, part, st, scs, rtol2, max_iter);
       hipLaunchKernelGGL(k_pcg_update, dim3(nblk_u), dim3(PB), 0, q, ublk, inv, p_new, Ap, x_out, r, z, part, part2,
                          st, scs, err);
@@ -1712,7 +1700,7 @@ int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const doubl
   }
   hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(nb + 1, 256)), dim3(256), 0, s, nb, n_keys, keys, tk2, lo_beg,
                      hi_beg);
-  const unsigned gv = grid_for(n12, 256), gs = grid_for(nb, SWBB);
+  const unsigned gv = grid_for(n12, 256), gs = grid_for(nb, CBB);
   double *h;
   ABD_TRY(pinned_get(ctx, 64, reinterpret_cast<void **>(&h)));
   auto dotp = [&](const double *a, const double *b, double *out) -> int {

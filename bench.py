@@ -473,7 +473,7 @@ def culling_ops(args, reps=10):
         for levels in (1, 3):
             ctx.tune_set(dict(cull_levels=levels))
             ctx.candidates(sc, x0, x1, P["dhat"])
-            ctx.profile(True, True)
+            ctx.profile(2, True)
             pt, ee = ctx.candidates(sc, x0, x1, P["dhat"])
             tests = ctx.profile_query("box_tests")["units"]
             ctx.profile(False, True)

@@ -455,9 +455,10 @@ int abd_autotune(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, doubl
  * pairs, tiles; friction pairs for "friction_local"; for "pcg_round", one
  * replay of the captured PCG iterations,
  * the algorithmic HBM bytes of the iterations it executed); and, with zero
- * time, "box_tests" / "box_tests_single_level": per candidate-search call,
- * the primitive-pair box tests run with the table's i-AABB culling, and the
- * tests a single-level cull would run.
+ * time and only in mode 2 (enable = 2, which adds a reduction per candidate
+ * search), "box_tests" / "box_tests_single_level": per candidate-search
+ * call, the primitive-pair box tests run with the table's i-AABB culling,
+ * and the tests a single-level cull would run.
  * Query synchronises the device. */
 int abd_profile(abd_ctx *ctx, int enable, int reset);
 int abd_profile_query(abd_ctx *ctx, const char *kernel, double *ms, int64_t *launches, int64_t *units);

@@ -397,6 +397,8 @@ class Context:
         return t.as_dict(), ms.value
 
     def profile(self, enable=True, reset=True):
+        """enable: False/0 off, True/1 kernel timing, 2 timing and box-test
+        counts of the candidate searches."""
         self._check(self.L.abd_profile(self.h, int(enable), int(reset)))
 
     def profile_query(self, kernel):

@@ -667,8 +667,8 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_toff", 3 * nbp + 1, &toff, s));
   float *crec = nullptr;  // three-level tree: chunk records of the column lists
   if (ctx->tune.cull_levels == 3) ABD_TRY(ws(ctx, "bp_crec", CREC * (list_total / 64 + 1), &crec, s));
-  double *tests = nullptr;  // profiling: single-level tests per sub-problem
-  if (ctx->profiling) ABD_TRY(ws(ctx, "bp_tests", 3 * nbp, &tests, s));
+  double *tests = nullptr;  // box-test counting: single-level tests per sub-problem
+  if (ctx->count_box_tests) ABD_TRY(ws(ctx, "bp_tests", 3 * nbp, &tests, s));
   hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 3), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
                      sc->body_tri_off, sc->body_edge_off, bbox, vbox32, sc->tris, sc->edges, lists, lstart, llen,
                      tcnt, tcnt + 2 * nbp, trows, crec, tests);
@@ -760,14 +760,30 @@ __global__ void k_unique_write(int64_t n, const uint64_t *k, const int64_t *flag
   out[2 * pos[i] + 1] = (int32_t)(k[i] & 0xffffffffu);
 }
 
-// Dense variant for one scene of at most OD_DENSE_MAX bodies: the body pairs
-// are marked in an nb x nb byte matrix (every writer stores 1, so races are
-// harmless), then each row a writes its marked columns b > a in order, which
-// gives the same sorted, unique keys as sorting the pair keys.
-constexpr int OD_DENSE_MAX = 4096;
+// Dense variant: the body pairs of every scene are marked in the scene's own
+// n_s x n_s byte matrix (the matrices of a batch side by side, scene s at
+// foff[s]; every writer stores 1, so races are harmless), then each row a
+// writes its marked columns b > a in order, which gives the same sorted,
+// unique keys as sorting the pair keys (a scene's bodies are contiguous and
+// scenes are in order).  Used while the matrices fit in OD_DENSE_BYTES.
+constexpr int64_t OD_DENSE_BYTES = 64ll << 20;
 __global__ void k_od_clear(int64_t n16, uint4 *f) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n16) f[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+// a body's scene matrix: base of its row, scene size, local index
+struct OdRow {
+  int64_t base;
+  int n, loc, first;
+};
+__device__ __forceinline__ OdRow od_row(int a, const int32_t *body_scene, const int32_t *sbo, const int64_t *foff) {
+  const int sc = body_scene[a];
+  OdRow r;
+  r.first = sbo[sc];
+  r.n = sbo[sc + 1] - r.first;
+  r.loc = a - r.first;
+  r.base = foff[sc] + (int64_t)r.loc * r.n;
+  return r;
 }
 // the four pair lists (PT, EE, extra PT, extra EE) marked by one launch;
 // both (a, b) and (b, a) are marked, so that row b also lists the rows
@@ -777,7 +793,8 @@ struct MarkLists {
   int64_t end[5];  // cumulative counts (point-triangle, edge-edge, pt2, ee2, pt3)
 };
 __global__ void k_od_mark(MarkLists L, const int32_t *vert_body, const int32_t *tri_body, const int32_t *edge_body,
-                          const uint8_t *fixed, int nb, uint8_t *flags) {
+                          const uint8_t *fixed, const int32_t *body_scene, const int32_t *sbo, const int64_t *foff,
+                          uint8_t *flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.end[4]) return;
   int l = 0;
@@ -787,62 +804,95 @@ __global__ void k_od_mark(MarkLists L, const int32_t *vert_body, const int32_t *
   const int is_ee = l & 1;
   const int a = is_ee ? edge_body[pairs[2 * i]] : vert_body[pairs[2 * i]];
   const int b = is_ee ? edge_body[pairs[2 * i + 1]] : tri_body[pairs[2 * i + 1]];
-  if (!fixed[a] && !fixed[b] && a != b) {
-    flags[(int64_t)min(a, b) * nb + max(a, b)] = 1;
-    flags[(int64_t)max(a, b) * nb + min(a, b)] = 1;
+  if (!fixed[a] && !fixed[b] && a != b) {  // (a and b are bodies of one scene)
+    const OdRow ra = od_row(a, body_scene, sbo, foff), rb = od_row(b, body_scene, sbo, foff);
+    flags[ra.base + rb.loc] = 1;
+    flags[rb.base + ra.loc] = 1;
   }
 }
 // one wave per row: count (WRITE 0) or write (WRITE 1) the marked columns
 // b > a: the keys in (row, column) order.  With the pattern requested, the
 // count pass also counts the marked columns b < a (keys with column a) and
-// the write pass stores each key's index at the transposed position
-// kidx[b][a].
+// the write pass stores each key's index at the transposed position of the
+// scene matrix of kidx (laid out like the flags).
 template <int WRITE>
-__global__ void __launch_bounds__(64) k_od_row(int nb, const uint8_t *flags, int64_t *cnt, const int64_t *off,
-                                               int32_t *keys, int64_t *lcnt, int32_t *kidx) {
+__global__ void __launch_bounds__(64) k_od_row(int nb, const uint8_t *flags, const int32_t *body_scene,
+                                               const int32_t *sbo, const int64_t *foff, int64_t *cnt,
+                                               const int64_t *off, int32_t *keys, int64_t *lcnt, int32_t *kidx) {
   const int a = blockIdx.x;
   if (a >= nb) return;
-  const uint8_t *row = flags + (int64_t)a * nb;
+  const OdRow ra = od_row(a, body_scene, sbo, foff);
+  const uint8_t *row = flags + ra.base;
   int64_t c = 0, base = WRITE ? off[a] : 0;
-  for (int b0 = a + 1; b0 < nb; b0 += 64) {
+  for (int b0 = ra.loc + 1; b0 < ra.n; b0 += 64) {
     const int b = b0 + (int)threadIdx.x;
-    const bool on = b < nb && row[b];
+    const bool on = b < ra.n && row[b];
     const unsigned long long m = __ballot(on);
     if (WRITE && on) {
       const int64_t o = base + c + __popcll(m & ((1ull << threadIdx.x) - 1ull));
       keys[2 * o] = a;
-      keys[2 * o + 1] = b;
-      if (kidx) kidx[(int64_t)b * nb + a] = (int32_t)o;
+      keys[2 * o + 1] = ra.first + b;
+      if (kidx) kidx[ra.base - (int64_t)ra.loc * ra.n + (int64_t)b * ra.n + ra.loc] = (int32_t)o;
     }
     c += __popcll(m);
   }
   if (!WRITE && threadIdx.x == 0) cnt[a] = c;
   if (!WRITE && lcnt) {
     int64_t cl = 0;
-    for (int b0 = 0; b0 < a; b0 += 64) {
+    for (int b0 = 0; b0 < ra.loc; b0 += 64) {
       const int b = b0 + (int)threadIdx.x;
-      cl += __popcll(__ballot(b < a && row[b]));
+      cl += __popcll(__ballot(b < ra.loc && row[b]));
     }
     if (threadIdx.x == 0) lcnt[a] = cl;
   }
 }
 // one wave per body c: the indices of the keys (b, c), b < c, in order of
 // b (the keys sorted by (column, row))
-__global__ void __launch_bounds__(64) k_od_lower(int nb, const uint8_t *flags, const int64_t *loff,
+__global__ void __launch_bounds__(64) k_od_lower(int nb, const uint8_t *flags, const int32_t *body_scene,
+                                                 const int32_t *sbo, const int64_t *foff, const int64_t *loff,
                                                  const int32_t *kidx, uint32_t *tperm) {
   const int c = blockIdx.x;
   if (c >= nb) return;
-  const uint8_t *row = flags + (int64_t)c * nb;
+  const OdRow rc = od_row(c, body_scene, sbo, foff);
+  const uint8_t *row = flags + rc.base;
   int64_t o = loff[c];
-  for (int b0 = 0; b0 < c; b0 += 64) {
+  for (int b0 = 0; b0 < rc.loc; b0 += 64) {
     const int b = b0 + (int)threadIdx.x;
-    const bool on = b < c && row[b];
+    const bool on = b < rc.loc && row[b];
     const unsigned long long m = __ballot(on);
-    if (on) tperm[o + __popcll(m & ((1ull << threadIdx.x) - 1ull))] = (uint32_t)kidx[(int64_t)c * nb + b];
+    if (on) tperm[o + __popcll(m & ((1ull << threadIdx.x) - 1ull))] = (uint32_t)kidx[rc.base + b];
     o += __popcll(m);
   }
 }
 }  // namespace
+
+// Byte offsets of the scenes' dense pair matrices (device [S+1]) and their
+// total, from the scene's body-to-scene map, read once per scene arrays
+// and kept in the context.
+int dense_layout(abd_ctx *ctx, const abd_scene *sc, const int64_t **foff, int64_t *total, hipStream_t s) {
+  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
+  const std::vector<uintptr_t> key = {(uintptr_t)sc->body_scene, (uintptr_t)sc->n_bodies, (uintptr_t)S};
+  int64_t *f;
+  ABD_TRY(ws(ctx, "od_foff", S + 1, &f, s));
+  if (ctx->od_key != key) {
+    std::vector<int32_t> bs(sc->n_bodies);
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (sc->n_bodies > 0)
+      HIP_TRY(ctx, hipMemcpy(bs.data(), sc->body_scene, sizeof(int32_t) * bs.size(), hipMemcpyDeviceToHost));
+    std::vector<int64_t> n(S, 0), h(S + 1, 0);
+    for (int32_t v : bs) {
+      if (v < 0 || v >= S) return abd_fail(ctx, ABD_E_INVALID, "offdiag: body scene %d out of range", v);
+      ++n[v];
+    }
+    for (int k = 0; k < S; ++k) h[k + 1] = h[k] + n[k] * n[k];
+    HIP_TRY(ctx, hipMemcpy(f, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice));
+    ctx->od_key = key;
+    ctx->od_total = h[S];
+  }
+  *foff = f;
+  *total = ctx->od_total;
+  return ABD_OK;
+}
 
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys_out, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2,
@@ -873,8 +923,13 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   const int32_t *lists[5] = {pt, ee, pt2, ee2, pt3};
   const int64_t counts[5] = {n_pt, n_ee, n_pt2, n_ee2, n_pt3};
   const int nb = sc->n_bodies;
-  if ((sc->n_scenes <= 1) && nb <= OD_DENSE_MAX) {
-    const int64_t nbb = ((int64_t)nb * nb + 15) / 16 * 16;
+  const int64_t *foff;
+  int64_t fbytes;
+  ABD_TRY(dense_layout(ctx, sc, &foff, &fbytes, s));
+  if (fbytes <= OD_DENSE_BYTES) {
+    const int32_t *sbo;
+    ABD_TRY(op_scene_offsets(ctx, sc, &sbo, s));
+    const int64_t nbb = (fbytes + 15) / 16 * 16;
     uint8_t *flags;
     int64_t *rcnt, *roff;
     ABD_TRY(ws(ctx, "od_flags", nbb, &flags, s));
@@ -890,7 +945,7 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
       ml.end[l] = acc;
     }
     hipLaunchKernelGGL(k_od_mark, dim3(grid_for(n, 256)), dim3(256), 0, s, ml, sc->vert_body, sc->tri_body,
-                       sc->edge_body, sc->body_fixed, nb, flags);
+                       sc->edge_body, sc->body_fixed, sc->body_scene, sbo, foff, flags);
     int64_t *hbuf, *hbuf_d;
     ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
     int64_t *lcnt = nullptr, *loff = nullptr;
@@ -899,15 +954,18 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
     if (pat) {
       ABD_TRY(ws(ctx, "od_lcnt", nb, &lcnt, s));
       ABD_TRY(ws(ctx, "od_loff", nb + 1, &loff, s));
-      ABD_TRY(ws(ctx, "od_kidx", (size_t)nb * nb, &kidx, s));
+      ABD_TRY(ws(ctx, "od_kidx", (size_t)fbytes + 1, &kidx, s));
       ABD_TRY(ws(ctx, "od_tperm", n + 1, &tperm, s));
     }
-    hipLaunchKernelGGL(k_od_row<0>, dim3(nb), dim3(64), 0, s, nb, flags, rcnt, nullptr, nullptr, lcnt, nullptr);
+    hipLaunchKernelGGL(k_od_row<0>, dim3(nb), dim3(64), 0, s, nb, flags, sc->body_scene, sbo, foff, rcnt, nullptr,
+                       nullptr, lcnt, nullptr);
     ABD_TRY(scan_exclusive_i64(ctx, rcnt, roff, nb, roff + nb, s, hbuf_d + MIR_OFFDIAG));
-    hipLaunchKernelGGL(k_od_row<1>, dim3(nb), dim3(64), 0, s, nb, flags, nullptr, roff, *keys_out, nullptr, kidx);
+    hipLaunchKernelGGL(k_od_row<1>, dim3(nb), dim3(64), 0, s, nb, flags, sc->body_scene, sbo, foff, nullptr, roff,
+                       *keys_out, nullptr, kidx);
     if (pat) {
       ABD_TRY(scan_exclusive_i64(ctx, lcnt, loff, nb, loff + nb, s));
-      hipLaunchKernelGGL(k_od_lower, dim3(nb), dim3(64), 0, s, nb, flags, loff, kidx, tperm);
+      hipLaunchKernelGGL(k_od_lower, dim3(nb), dim3(64), 0, s, nb, flags, sc->body_scene, sbo, foff, loff, kidx,
+                         tperm);
       pat->lo_beg = roff;
       pat->hi_beg = loff;
       pat->tperm = tperm;

@@ -616,6 +616,7 @@ extern "C" int abd_profile(abd_ctx *ctx, int enable, int reset) {
     ctx->prof_box_tests_clear = true;
   }
   ctx->profiling = enable != 0;
+  ctx->count_box_tests = enable == 2;
   return ABD_OK;
 }
 

@@ -69,6 +69,7 @@ struct abd_ctx {
   unsigned int lb_tag = 0;
   hipEvent_t ev[8] = {};
   bool profiling = false;
+  bool count_box_tests = false;  // (abd_profile mode 2)
   std::map<std::string, KStat> kstats;
   // the device sums of box tests (workspace "prof_box_tests") restart at
   // the next profiled candidates call
@@ -89,6 +90,10 @@ struct abd_ctx {
   // "kappa_sc") while abd_time_step runs with kappa_adaptive; null otherwise,
   // and then every kernel takes the scalar kappa_b
   double *kappa_sc = nullptr;
+  // dense off-diagonal pattern: the scene arrays its layout was read from,
+  // and the total bytes of the per-scene pair matrices
+  std::vector<uintptr_t> od_key;
+  int64_t od_total = 0;
   int64_t fr_n_pt = 0, fr_n_ee = 0;
   // swept candidates of the last accepted Newton step (the segment holds the
   // new iterate, so its static candidates are a subset of these)

@@ -43,7 +43,7 @@ def _sorted(a):
 
 def _run(ctx, sc, x0, x1, inflate, levels, trows):
     ctx.tune_set(dict(cull_levels=levels, tile_rows=trows))
-    ctx.profile(True, True)
+    ctx.profile(2, True)
     pt, ee = ctx.candidates(sc, x0, x1, inflate)
     tests = ctx.profile_query("box_tests")["units"]
     flat = ctx.profile_query("box_tests_single_level")["units"]

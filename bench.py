@@ -248,10 +248,14 @@ def timed_steps(args, ctx, sc, P, q, qd, steps):
     import torch
     ctx.profile(True, reset=True)
     torch.cuda.synchronize()
-    tot = dict(newton=0, scene_newton=0, active=0, ccd=0, pcg=0, friction=0)
+    tot = dict(newton=0, scene_newton=0, active=0, ccd=0, pcg=0, friction=0,
+               host_ms=dict(candidates=0.0, barrier=0.0, solve=0.0, ccd_line_search=0.0, total=0.0))
     t0 = time.perf_counter()
     for _ in range(steps):
         st = ctx.time_step(sc, P, q, qd)
+        for k, f in (("candidates", "t_candidates_ms"), ("barrier", "t_barrier_ms"), ("solve", "t_solve_ms"),
+                     ("ccd_line_search", "t_ccd_ms"), ("total", "t_total_ms")):
+            tot["host_ms"][k] += st[f]
         tot["newton"] += st["newton_iters"]
         tot["scene_newton"] += st["scene_newton_iters"]
         tot["active"] += st["n_active_pt"] + st["n_active_ee"]
@@ -308,6 +312,7 @@ def line_common(args, wall, tot, ks, steps):
         "newton_iters": tot["scene_newton"],
         "pair_evals": {"barrier_active": tot["active"], "ccd": tot["ccd"], "friction": tot["friction"]},
         "pcg_iters": tot["pcg"],
+        "phase_wall_ms": {k: v / steps for k, v in tot["host_ms"].items()},
         "kernel_ms": {k: v["ms"] for k, v in ks.items()},
         "roofline": roof,
         "pair_kernels": pair_kernels,

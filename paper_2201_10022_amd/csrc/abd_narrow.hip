@@ -138,9 +138,10 @@ __global__ void __launch_bounds__(BS) k_barrier_local(const int64_t *n_act_dev, 
 // from the columns published at the start of the round, applies the four
 // rotations to the rows of its own column (J^T A), then replaces its column
 // of A and of V with its rotation's combination of its own and its
-// partner's published columns (A J, V J).  Sweeps stop when every pair of
-// the block has off-diagonal mass below 1e-24 of its Frobenius mass (an
-// error of 1e-12 of the pair's Hessian in the projected matrix).  The
+// partner's published columns (A J, V J).  A pair stops rotating once its
+// off-diagonal mass is below 1e-24 of its Frobenius mass (an error of 1e-12
+// of the pair's Hessian in the projected matrix), and the block's sweeps
+// end when every pair has stopped.  The
 // projection H_+ = sum_k max(lambda_k, 0) (Q v_k)(Q v_k)^T is summed over
 // the lanes' eigenpairs through LDS, nine output entries per lane.
 constexpr int PPW = 7;  // pairs per wave
@@ -226,10 +227,14 @@ __global__ void __launch_bounds__(BS) k_barrier_project(const int64_t *n_act_dev
         tk[k] = (d < 0.0 ? -2.0 : 2.0) * apq / den;
         ck[k] = 1.0 / sqrt(tk[k] * tk[k] + 1.0);
         sk[k] = tk[k] * ck[k];
-        // rows P and Q of this lane's column: J^T A
+        // rows P and Q of this lane's column: J^T A (a converged pair is
+        // left as it is, so its result does not depend on the other pairs
+        // of the block)
         const double ap = col[P], aq = col[Q];
-        col[P] = ck[k] * ap - sk[k] * aq;
-        col[Q] = sk[k] * ap + ck[k] * aq;
+        if (more) {
+          col[P] = ck[k] * ap - sk[k] * aq;
+          col[Q] = sk[k] * ap + ck[k] * aq;
+        }
       }
       __syncthreads();  // (every angle read)
       if (slot)
@@ -241,7 +246,7 @@ __global__ void __launch_bounds__(BS) k_barrier_project(const int64_t *n_act_dev
       __syncthreads();
       // columns: A J and V J for this lane's rotation (none for j == R)
       const int partner = (2 * R - j + 18) % 9;
-      if (partner != j) {
+      if (more && partner != j) {
         const int kk = ((j - R + 9) % 9 <= 4 ? (j - R + 9) % 9 : (R - j + 9) % 9) - 1;
         const double c = kk == 0 ? ck[0] : kk == 1 ? ck[1] : kk == 2 ? ck[2] : ck[3];
         const double sn = kk == 0 ? sk[0] : kk == 1 ? sk[1] : kk == 2 ? sk[2] : sk[3];

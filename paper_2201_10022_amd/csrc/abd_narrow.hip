@@ -3,8 +3,7 @@
 //
 // Pass 1 (k_barrier_local, one lane per active pair): distance case, the
 // case distance's gradient and Hessian, the clamped log barrier (EE pairs
-// mollified) and the 12x12 local Hessian; then (k_barrier_project, nine
-// lanes per pair) its PSD projection.  The
+// mollified), the 12x12 local Hessian and its PSD projection.  The
 // projection runs on the 9x9 matrix of relative motions: the barrier of a
 // pair is invariant under a common translation of its 4 vertices, so the
 // translations span an exact null space of the local Hessian; with the
@@ -78,7 +77,7 @@ __global__ void __launch_bounds__(BS) k_barrier_local(const int64_t *n_act_dev, 
                                                       const int32_t *pt, const int32_t *ee, const int32_t *tris,
                                                       const int32_t *edges, const int32_t *vert_body,
                                                       const double *x, const double *xbar, double dhat,
-                                                      double kappa, double *e_out, double *g_out,
+                                                      double kappa, int project, double *e_out, double *g_out,
                                                       double *H_out, PairInfo *info, int *err,
                                                       const double *kappa_sc, const int32_t *body_scene) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,175 +118,14 @@ __global__ void __launch_bounds__(BS) k_barrier_local(const int64_t *n_act_dev, 
   LocalOut o;
   // (per-scene stiffness when it adapts)
   barrier_local(is_ee, ty, X, xb4, dhat, kappa_sc ? kappa_sc[body_scene[pi.body[0]]] : kappa, 0, o);
+  // energy and gradient leave before the projection, whose eigen-solve
+  // needs the registers
   e_out[a] = o.e;
 #pragma unroll
   for (int i = 0; i < 12; ++i) g_out[12 * a + i] = o.g[i];
+  if (project) project_translation_invariant(o.H);
 #pragma unroll
   for (int i = 0; i < 78; ++i) H_out[78 * a + i] = o.H[i];
-}
-
-// The projection of pass 1, nine lanes per pair (7 pairs per wave, lane 63
-// idle), in place on the local Hessians the derivative kernel wrote (one
-// lane per pair there: its registers would hold this kernel to one wave per
-// SIMD).  Every lane of a pair reads the pair's 12x12 local Hessian, forms
-// the 9x9 matrix of relative motions H9 = Q^T H Q and keeps column j (its
-// lane index in the pair) of it and of the eigenvector matrix.  A
-// Jacobi sweep is nine rounds of the Brent-Luk schedule for nine players:
-// in round R, j meets (2R - j) mod 9 and R sits out, so a round's four
-// rotations act on disjoint index pairs.  Each lane takes the four angles
-// from the columns published at the start of the round, applies the four
-// rotations to the rows of its own column (J^T A), then replaces its column
-// of A and of V with its rotation's combination of its own and its
-// partner's published columns (A J, V J).  A pair stops rotating once its
-// off-diagonal mass is below 1e-24 of its Frobenius mass (an error of 1e-12
-// of the pair's Hessian in the projected matrix), and the block's sweeps
-// end when every pair has stopped.  The
-// projection H_+ = sum_k max(lambda_k, 0) (Q v_k)(Q v_k)^T is summed over
-// the lanes' eigenpairs through LDS, nine output entries per lane.
-constexpr int PPW = 7;  // pairs per wave
-// packed upper-triangle index -> (row, column) of a 12x12 matrix
-__constant__ uint8_t kPackI[78] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5, 5, 6, 6, 6, 6, 6, 6, 7, 7, 7, 7, 7, 8, 8, 8, 8, 9, 9, 9, 10, 10, 11};
-__constant__ uint8_t kPackJ[78] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 3, 4, 5, 6, 7, 8, 9, 10, 11, 4, 5, 6, 7, 8, 9, 10, 11, 5, 6, 7, 8, 9, 10, 11, 6, 7, 8, 9, 10, 11, 7, 8, 9, 10, 11, 8, 9, 10, 11, 9, 10, 11, 10, 11, 11};
-
-template <int BS>
-__global__ void __launch_bounds__(BS) k_barrier_project(const int64_t *n_act_dev, const double *e_loc,
-                                                        double *H_out) {
-  constexpr int W = BS / 64;
-  __shared__ double sA[W][PPW][9][9];  // published columns: [pair][column][row]
-  __shared__ double sV[W][PPW][9][9];
-  __shared__ double sU[W][PPW][9][12];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int ps = lane / 9, j = lane - 9 * ps;
-  const bool slot = ps < PPW;
-  const int pq = slot ? ps : 0;  // (lane 63 reads pair 0's slot and writes nothing)
-  const int64_t na = *n_act_dev;
-  if ((int64_t)blockIdx.x * W * PPW >= na) return;  // (uniform over the block)
-  const int64_t a = ((int64_t)blockIdx.x * W + wv) * PPW + ps;
-  const bool live = slot && a < na;
-  double col[9], vcol[9];
-#pragma unroll
-  for (int r = 0; r < 9; ++r) {
-    col[r] = 0.0;
-    vcol[r] = r == j ? 1.0 : 0.0;
-  }
-  // (a pair with a zero distance has an infinite energy and a zero Hessian)
-  const bool ok = live && e_loc[a] != INFINITY;
-  if (ok) {
-    // column j = 3 m + c of H9 = Q^T H Q: Y = H[:, (l, c)] helm(m, l) over
-    // the four vertices l, then col[3 mm + cr] = sum_k helm(mm, k) Y[3 k + cr]
-    const int m = j / 3, c = j - 3 * (j / 3);
-    const double h0 = helm(m, 0), h1 = helm(m, 1), h2 = helm(m, 2), h3 = helm(m, 3);
-    const double *Hp = H_out + 78 * a;
-    double Y[12];
-#pragma unroll
-    for (int row = 0; row < 12; ++row)
-      Y[row] = h0 * Hp[S12::at(row, c)] + h1 * Hp[S12::at(row, 3 + c)] + h2 * Hp[S12::at(row, 6 + c)] +
-               h3 * Hp[S12::at(row, 9 + c)];
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      const int mr = r / 3, cr = r % 3;
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) acc += helm(mr, k) * Y[3 * k + cr];
-      col[r] = acc;
-    }
-  }
-  // the pair's sums over its nine lanes (in lane order, the same on every lane)
-  auto pair_sum = [&](double v) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) t += __shfl(v, 9 * pq + q, 64);
-    return t;
-  };
-  double fr = 0.0;
-#pragma unroll
-  for (int r = 0; r < 9; ++r) fr += col[r] * col[r];
-  const double frob = pair_sum(fr);
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    double of = 0.0;
-#pragma unroll
-    for (int r = 0; r < 9; ++r) of += r == j ? 0.0 : col[r] * col[r];
-    const double off = pair_sum(of);
-    const bool more = ok && off > 1e-24 * frob;
-    if (!__syncthreads_or(more)) break;
-#pragma unroll
-    for (int R = 0; R < 9; ++R) {
-      if (slot)
-#pragma unroll
-        for (int r = 0; r < 9; ++r) sA[wv][pq][j][r] = col[r];
-      __syncthreads();
-      // the round's four angles (P < Q as compile-time constants)
-      double tk[4], ck[4], sk[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int u = (R + k + 1) % 9, v = (R - k - 1 + 9) % 9;
-        const int P = u < v ? u : v, Q = u < v ? v : u;
-        const double apq = sA[wv][pq][Q][P], d = sA[wv][pq][Q][Q] - sA[wv][pq][P][P];
-        const double den = fmax(fabs(d) + sqrt(d * d + 4.0 * apq * apq), 1e-300);
-        tk[k] = (d < 0.0 ? -2.0 : 2.0) * apq / den;
-        ck[k] = 1.0 / sqrt(tk[k] * tk[k] + 1.0);
-        sk[k] = tk[k] * ck[k];
-        // rows P and Q of this lane's column: J^T A (a converged pair is
-        // left as it is, so its result does not depend on the other pairs
-        // of the block)
-        const double ap = col[P], aq = col[Q];
-        if (more) {
-          col[P] = ck[k] * ap - sk[k] * aq;
-          col[Q] = sk[k] * ap + ck[k] * aq;
-        }
-      }
-      __syncthreads();  // (every angle read)
-      if (slot)
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
-          sA[wv][pq][j][r] = col[r];
-          sV[wv][pq][j][r] = vcol[r];
-        }
-      __syncthreads();
-      // columns: A J and V J for this lane's rotation (none for j == R)
-      const int partner = (2 * R - j + 18) % 9;
-      if (more && partner != j) {
-        const int kk = ((j - R + 9) % 9 <= 4 ? (j - R + 9) % 9 : (R - j + 9) % 9) - 1;
-        const double c = kk == 0 ? ck[0] : kk == 1 ? ck[1] : kk == 2 ? ck[2] : ck[3];
-        const double sn = kk == 0 ? sk[0] : kk == 1 ? sk[1] : kk == 2 ? sk[2] : sk[3];
-        const bool is_p = j < partner;
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
-          const double pa = sA[wv][pq][partner][r], pv = sV[wv][pq][partner][r];
-          col[r] = is_p ? c * col[r] - sn * pa : sn * pa + c * col[r];
-          vcol[r] = is_p ? c * vcol[r] - sn * pv : sn * pv + c * vcol[r];
-        }
-      }
-      __syncthreads();  // (every partner column read)
-    }
-  }
-  // eigenpair j: u_j = sqrt(max(lambda_j, 0)) Q v_j, then H+ = sum_k u_k u_k^T
-  double lam = 0.0;
-#pragma unroll
-  for (int r = 0; r < 9; ++r)
-    if (r == j) lam = col[r];
-  const double w = sqrt(fmax(lam, 0.0));
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double acc = 0.0;
-#pragma unroll
-      for (int mm = 0; mm < 3; ++mm) acc += helm(mm, k) * vcol[3 * mm + c];
-      if (slot) sU[wv][pq][j][3 * k + c] = w * acc;
-    }
-  __syncthreads();
-  if (live) {
-    for (int q = j; q < 78; q += 9) {
-      double acc = 0.0;
-      if (ok) {
-        const int r = kPackI[q], c = kPackJ[q];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc += sU[wv][pq][k][r] * sU[wv][pq][k][c];
-      }
-      H_out[78 * a + q] = acc;
-    }
-  }
 }
 
 __device__ __forceinline__ int find_key(const int32_t *keys, int64_t n, int a, int b) {
@@ -556,8 +394,8 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
     hipEvent_t pe = prof_begin(ctx, s);
     // (waves per block from the launch-shape table)
 #define ABD_BARRIER_ARGS                                                                                          \
-  nact, act, n_pt, pt, ee, sc->tris, sc->edges, sc->vert_body, x, sc->xbar, dhat, prm->kappa_b, e_loc, g_loc, \
-      H_loc, info, err, ctx->kappa_sc, sc->body_scene
+  nact, act, n_pt, pt, ee, sc->tris, sc->edges, sc->vert_body, x, sc->xbar, dhat, prm->kappa_b, project, e_loc, \
+      g_loc, H_loc, info, err, ctx->kappa_sc, sc->body_scene
     const int wpb = ctx->tune.barrier_waves;
     if (wpb == 4)
       hipLaunchKernelGGL(k_barrier_local<256>, dim3(grid_for(na, 256)), dim3(256), 0, s, ABD_BARRIER_ARGS);
@@ -566,15 +404,6 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
     else
       hipLaunchKernelGGL(k_barrier_local<64>, dim3(grid_for(na, 64)), dim3(64), 0, s, ABD_BARRIER_ARGS);
 #undef ABD_BARRIER_ARGS
-    // the PSD projection in place, nine lanes per pair
-    if (project) {
-      if (wpb == 4)
-        hipLaunchKernelGGL(k_barrier_project<256>, dim3(grid_for(na, 4 * PPW)), dim3(256), 0, s, nact, e_loc, H_loc);
-      else if (wpb == 2)
-        hipLaunchKernelGGL(k_barrier_project<128>, dim3(grid_for(na, 2 * PPW)), dim3(128), 0, s, nact, e_loc, H_loc);
-      else
-        hipLaunchKernelGGL(k_barrier_project<64>, dim3(grid_for(na, PPW)), dim3(64), 0, s, nact, e_loc, H_loc);
-    }
     prof_end(ctx, pe, "barrier_local", na, s);
     HIP_TRY(ctx, hipGetLastError());
   }

@@ -593,6 +593,17 @@ void prof_end(abd_ctx *ctx, hipEvent_t a, const char *name, int64_t units, hipSt
   ctx->pending.push_back({a, b, name, units});
 }
 
+namespace {
+__global__ void k_clear_u64(unsigned long long *a) { *a = 0ull; }
+}  // namespace
+
+int prof_pcg_bytes(abd_ctx *ctx, unsigned long long **acc, hipStream_t s) {
+  ABD_TRY(ws(ctx, "prof_pcg_bytes", 1, acc, s));
+  if (ctx->prof_pcg_clear) hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(1), 0, s, *acc);
+  ctx->prof_pcg_clear = false;
+  return abd_hip_check(ctx, hipGetLastError(), "k_clear_u64");
+}
+
 void prof_flush(abd_ctx *ctx) {
   for (auto &p : ctx->pending) {
     float ms = 0.0f;
@@ -614,6 +625,7 @@ extern "C" int abd_profile(abd_ctx *ctx, int enable, int reset) {
   if (reset) {
     ctx->kstats.clear();
     ctx->prof_box_tests_clear = true;
+    ctx->prof_pcg_clear = true;
   }
   ctx->profiling = enable != 0;
   ctx->count_box_tests = enable == 2;
@@ -633,6 +645,12 @@ extern "C" int abd_profile_query(abd_ctx *ctx, const char *kernel, double *ms, i
     if (b != ctx->bufs.end() && b->second.ptr)
       HIP_TRY(ctx, hipMemcpy(h, b->second.ptr, sizeof h, hipMemcpyDeviceToHost));
     it->second.units = (int64_t)h[kn == "box_tests" ? 0 : 1];
+  }
+  if (it != ctx->kstats.end() && kn == "pcg_round") {
+    auto b = ctx->bufs.find("prof_pcg_bytes");
+    unsigned long long h = 0;
+    if (b != ctx->bufs.end() && b->second.ptr) HIP_TRY(ctx, hipMemcpy(&h, b->second.ptr, sizeof h, hipMemcpyDeviceToHost));
+    it->second.units = (int64_t)h;
   }
   *ms = it == ctx->kstats.end() ? 0.0 : it->second.ms;
   *launches = it == ctx->kstats.end() ? 0 : it->second.launches;

@@ -74,6 +74,7 @@ struct abd_ctx {
   // the device sums of box tests (workspace "prof_box_tests") restart at
   // the next profiled candidates call
   bool prof_box_tests_clear = true;
+  bool prof_pcg_clear = true;  // (likewise the solver's algorithmic bytes)
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> ev_pool;
   // captured PCG iterations (short and long replays), re-captured when any
@@ -108,6 +109,9 @@ struct abd_ctx {
 hipEvent_t prof_begin(abd_ctx *ctx, hipStream_t s);
 void prof_end(abd_ctx *ctx, hipEvent_t a, const char *name, int64_t units, hipStream_t s);
 void prof_flush(abd_ctx *ctx);
+// the profile's device total of the solver's algorithmic bytes ("pcg_round"
+// units), cleared on first use after a reset
+int prof_pcg_bytes(abd_ctx *ctx, unsigned long long **acc, hipStream_t s);
 
 #define ABD_TRY(expr)                 \
   do {                                \

@@ -1025,6 +1025,28 @@ __global__ void __launch_bounds__(CT) k_cg_compact(PcgBlk *blk, int nblk, double
 }
 
 // closes a replay: advances the base and copies the state the host reads
+// Algorithmic HBM bytes of a finished solve, added to the profile's device
+// total: per scene its iteration count (it_final, or `done` for one scene)
+// times its matrix and preconditioner blocks once ((2 n_b + n_k) 12x12
+// blocks) and nvec 12-vectors per body; one block, fixed-order sum.
+__global__ void __launch_bounds__(256) k_pcg_bytes(int S, const int *it_final, int done, const int32_t *sbo,
+                                                   const int64_t *lo_beg, int nvec, unsigned long long *acc) {
+  __shared__ unsigned long long sh[256];
+  unsigned long long t = 0;
+  for (int j = threadIdx.x; j < S; j += 256) {
+    const int64_t nbs = sbo[j + 1] - sbo[j], nks = lo_beg[sbo[j + 1]] - lo_beg[sbo[j]];
+    const int64_t it = S == 1 ? done : it_final[j];
+    t += (unsigned long long)(it * ((2 * nbs + nks) * 1152 + (int64_t)nvec * 96 * nbs));
+  }
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *acc += sh[0];
+}
+
 // (base, n_stopped, max_final) to mapped host memory
 __global__ void k_cg_advance(CgState *st, int n, int *host) {
   st->base += n;
@@ -1165,9 +1187,6 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
       exec[gi] = ctx->pcg_exec[gi];
     }
   }
-  int *h;  // [4..4+S): per-scene iteration counts (profiled solves)
-  ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
-  int *fin = h + 4;
   const int max_rounds = max_iter / iter_g[0] + 2;
   int done = 0;
   bool all = false;
@@ -1199,24 +1218,12 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   }
   *iters = done;
   ctx->pcg_hint = done;
-  if (profiled && all && !ctx->pending.empty()) {
-    // algorithmic bytes of the whole solve, per scene: its iterations times
-    // its matrix and preconditioner blocks once and the 12-vectors of the
-    // iteration kernel (r, w, s, x, u, p in; r, w, s, x, u, p out)
-    std::vector<int32_t> hs(S + 1);
-    std::vector<int64_t> hl(nb + 1);
-    if (S == 1)
-      fin[0] = done;
-    else
-      HIP_TRY(ctx, hipMemcpy(fin, scs.it_final, S * sizeof(int), hipMemcpyDeviceToHost));
-    HIP_TRY(ctx, hipMemcpy(hs.data(), sbo, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_TRY(ctx, hipMemcpy(hl.data(), lo_beg, (nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
-    int64_t total = 0;
-    for (int j = 0; j < S; ++j) {
-      const int64_t nbs = hs[j + 1] - hs[j], nks = hl[hs[j + 1]] - hl[hs[j]];
-      total += (int64_t)fin[j] * ((2 * nbs + nks) * 1152 + 12 * 96 * nbs);
-    }
-    ctx->pending.back().units = total;
+  if (profiled && all) {
+    // (the profile's device total; the query reads it)
+    unsigned long long *acc;
+    ABD_TRY(prof_pcg_bytes(ctx, &acc, s));
+    hipLaunchKernelGGL(k_pcg_bytes, dim3(1), dim3(256), 0, s, S, scs.it_final, done, sbo, lo_beg, 12, acc);
+    HIP_TRY(ctx, hipGetLastError());
   }
   (void)n_keys;
   (void)keys;
@@ -1432,9 +1439,8 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
       exec[gi] = ctx->pcg_exec[gi];
     }
   }
-  int *h;  // [0..2] state counters, [4..4+S) per-scene iteration counts
-  ABD_TRY(pinned_get(ctx, sizeof(int) * (4 + (size_t)S), reinterpret_cast<void **>(&h)));
-  int *fin = h + 4;
+  int *h;  // [0..3] state counters
+  ABD_TRY(pinned_get(ctx, sizeof(int) * 4, reinterpret_cast<void **>(&h)));
   const int max_rounds = max_iter / iter_g[0] + 2;
   // algorithmic HBM bytes of one iteration of a scene: every 12x12 block of
   // its matrix and of its preconditioner once, plus the 12-vectors read and
@@ -1465,24 +1471,12 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   }
   *iters = it0 + done;
   ctx->pcg_hint = one_kernel ? it0 : done;
-  if (profiled && all && !ctx->pending.empty()) {
-    // algorithmic bytes of the whole solve, per scene: its iterations times
-    // its blocks and vectors (a stopped scene's blocks do no work); booked
-    // on the last replay, so the per-replay average is exact
-    std::vector<int32_t> hs(S + 1);
-    std::vector<int64_t> hl(nb + 1);
-    if (S == 1)
-      fin[0] = done;
-    else
-      HIP_TRY(ctx, hipMemcpy(fin, scs.it_final, S * sizeof(int), hipMemcpyDeviceToHost));
-    HIP_TRY(ctx, hipMemcpy(hs.data(), sbo, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_TRY(ctx, hipMemcpy(hl.data(), lo_beg, (nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
-    int64_t total = 0;
-    for (int j = 0; j < S; ++j) {
-      const int64_t nbs = hs[j + 1] - hs[j], nks = hl[hs[j + 1]] - hl[hs[j]];
-      total += (int64_t)fin[j] * ((2 * nbs + nks) * 1152 + 11 * 96 * nbs);
-    }
-    ctx->pending.back().units = total;
+  if (profiled && all) {
+    // (the profile's device total; the query reads it)
+    unsigned long long *acc;
+    ABD_TRY(prof_pcg_bytes(ctx, &acc, s));
+    hipLaunchKernelGGL(k_pcg_bytes, dim3(1), dim3(256), 0, s, S, scs.it_final, done, sbo, lo_beg, 11, acc);
+    HIP_TRY(ctx, hipGetLastError());
   }
   return ABD_OK;
 }

@@ -321,17 +321,28 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
 #pragma unroll
     for (int i = 0; i < 6; ++i) ob[i] = bb[6 * (int64_t)oth + i];
     int total = 0;
-    for (int c0 = offs[own]; c0 < offs[own + 1]; c0 += 64) {
-      const int i = c0 + lane;
-      bool ok = false;
-      if (i < offs[own + 1]) {
-        float fb[6];
-        prim_box32(pk, i, tris, edges, vb32, fb);
-        ok = box_overlap32(fb, ob);
+    // four chunks of 64 per trip (their loads in flight together), then
+    // compacted in order
+    constexpr int CU = 4;
+    const int hi = offs[own + 1];
+    for (int c0 = offs[own]; c0 < hi; c0 += 64 * CU) {
+      bool ok[CU];
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const int i = c0 + 64 * u + lane;
+        ok[u] = false;
+        if (i < hi) {
+          float fb[6];
+          prim_box32(pk, i, tris, edges, vb32, fb);
+          ok[u] = box_overlap32(fb, ob);
+        }
       }
-      const unsigned long long m = __ballot(ok);
-      if (ok) lists[start + total + __popcll(m & ((1ull << lane) - 1ull))] = i;
-      total += __popcll(m);
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const unsigned long long m = __ballot(ok[u]);
+        if (ok[u]) lists[start + total + __popcll(m & ((1ull << lane) - 1ull))] = c0 + 64 * u + lane;
+        total += __popcll(m);
+      }
     }
     if (lane == 0) {
       list_start[6 * p + kind] = start;

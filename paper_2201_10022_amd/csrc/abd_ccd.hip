@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(BS) k_accd(int64_t n_pt, int64_t n, const int3
                                                     const int32_t *vert_body, const int32_t *body_scene,
                                                     const double *x, const double *dx, double s, double tmax,
                                                     int max_iter, unsigned long long *counter, double *t_pt,
-                                                    double *t_ee, double *alpha) {
+                                                    double *t_ee, double *alpha, const double *x1) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
   // the first pair of every lane is its global thread index (no atomic);
@@ -87,7 +87,9 @@ __global__ void __launch_bounds__(BS) k_accd(int64_t n_pt, int64_t n, const int3
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             X[k] = ld3(x, vid[k]);
-            U[k] = ld3(dx, vid[k]);
+            // (the displacement x1 - x formed here when the end positions
+            // are given: the same subtraction as a separate pass)
+            U[k] = x1 ? xsub(ld3(x1, vid[k]), ld3(x, vid[k])) : ld3(dx, vid[k]);
           }
           const d3 mean = {((U[0].x + U[1].x) + (U[2].x + U[3].x)) * 0.25,
                            ((U[0].y + U[1].y) + (U[2].y + U[3].y)) * 0.25,
@@ -190,7 +192,7 @@ __global__ void k_ccd_init(double *alpha, int ns, double v, unsigned long long *
 
 int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x0, const double *dx,
            const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *t_pt, double *t_ee,
-           double *alpha, hipStream_t s) {
+           double *alpha, hipStream_t s, const double *x1) {
   const int ns = sc->n_scenes > 0 ? sc->n_scenes : 1;
   unsigned long long *counter;
   ABD_TRY(ws(ctx, "ccd_counter", 1, &counter, s));
@@ -211,7 +213,7 @@ int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const doubl
     hipEvent_t pe = prof_begin(ctx, s);
 #define ABD_ACCD_ARGS                                                                                          \
   n_pt, n, pt, ee, sc->tris, sc->edges, sc->vert_body, sc->body_scene, x0, dx, prm->ccd_s, prm->ccd_tmax, \
-      prm->ccd_max_iter, counter, t_pt, t_ee, alpha
+      prm->ccd_max_iter, counter, t_pt, t_ee, alpha, x1
     if (bs == 64)
       hipLaunchKernelGGL(k_accd<64>, dim3((unsigned)blocks), dim3(64), 0, s, ABD_ACCD_ARGS);
     else if (bs == 128)

@@ -265,7 +265,7 @@ int op_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, 
                       int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy, hipStream_t s);
 int op_ccd(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x0, const double *dx,
            const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *t_pt, double *t_ee,
-           double *alpha, hipStream_t s);
+           double *alpha, hipStream_t s, const double *x1 = nullptr);
 // adaptive barrier stiffness (abd_kappa.hip): per-scene kappa and the
 // closest active distance at q (workspace "kappa_sc", "kappa_d2prev"), and
 // the doubling rule before a Newton iteration at x over its candidates

@@ -20,10 +20,6 @@ __global__ void k_neg(int n, const double *a, double *out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = -a[i];
 }
-__global__ void k_sub(int n, const double *a, const double *b, double *out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a[i] - b[i];
-}
 __global__ void k_velocity(int n, const uint8_t *fixed, const double *qn, const double *qo, double inv_dt,
                            double *qd) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,10 +234,9 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   const int nb = sc->n_bodies, nv = sc->n_verts;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int n12 = 12 * nb;
-  double *x, *x1, *dx, *g, *diag, *off, *p, *qa, *e, *sv, *alpha_dev;
+  double *x, *x1, *g, *diag, *off, *p, *qa, *e, *sv, *alpha_dev;
   ABD_TRY(ws(ctx, "nt_x", 3 * (size_t)nv, &x, s));
   ABD_TRY(ws(ctx, "nt_x1", 3 * (size_t)nv, &x1, s));
-  ABD_TRY(ws(ctx, "nt_dx", 3 * (size_t)nv, &dx, s));
   ABD_TRY(ws(ctx, "nt_g", n12, &g, s));
   ABD_TRY(ws(ctx, "nt_diag", 144 * (size_t)nb, &diag, s));
   ABD_TRY(ws(ctx, "nt_p", n12, &p, s));
@@ -366,8 +361,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->n_ee_swept = nsee;
   st->t_candidates_ms += ms_since(t0);
   t0 = std::chrono::steady_clock::now();
-  hipLaunchKernelGGL(k_sub, dim3(grid_for(3 * nv, 256)), dim3(256), 0, s, 3 * nv, x1, x, dx);
-  ABD_TRY(op_ccd(ctx, sc, prm, x, dx, spt, nspt, see, nsee, nullptr, nullptr, a_ccd, s));
+  ABD_TRY(op_ccd(ctx, sc, prm, x, nullptr, spt, nspt, see, nsee, nullptr, nullptr, a_ccd, s, x1));
 
   // backtracking line search, per scene: the trial step lengths
   // alpha 2^-j are evaluated in batches of K (K from the last iteration's

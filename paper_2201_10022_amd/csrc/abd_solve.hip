@@ -763,8 +763,10 @@ __global__ void __launch_bounds__(256) k_cg_bmat(int64_t n_out, const int2 *ent,
   }
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_out) return;
-  const int64_t e = t / 144;
-  const int ij = (int)(t - 144 * e), i = ij / 12, j = ij - 12 * (ij / 12);
+  // (32-bit index arithmetic: n_out < 2^32, checked by the caller)
+  const uint32_t tu = (uint32_t)t, eu = tu / 144u, ij = tu - 144u * eu;
+  const int64_t e = eu;
+  const int i = (int)(ij / 12u), j = (int)(ij - 12u * (ij / 12u));
   const int2 en = ent[e];
   const int kk = en.x, c = en.y & ((1 << 30) - 1);
   const bool tr = (en.y >> 30) & 1;
@@ -1131,6 +1133,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   // partials, come from the caller's launch)
   {
     const int64_t n_out = 144 * ((int64_t)nb + 2 * n_keys);  // (entries: one diagonal per body, each key twice)
+    if (n_out >= (1ll << 32)) return abd_fail(ctx, ABD_E_INVALID, "pcg: too many matrix entries");
     hipLaunchKernelGGL(k_cg_bmat, dim3(grid_for(n_out, 256)), dim3(256), 0, s, n_out, ent, diag, off, inv, Bm, S, st,
                        scs);
   }

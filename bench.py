@@ -241,6 +241,9 @@ def measured_traffic(kernel, workload):
 
 KERNELS = ("pcg_round", "barrier_local", "accd", "assemble_chunks", "pair_tiles_write", "energy_only",
            "friction_local")
+# host-side work inside the timed steps: workspace growth (synchronise, free,
+# allocate, clear) and captures of the PCG graphs
+HOST_EVENTS = ("ws_grow", "pcg_capture")
 
 
 def timed_steps(args, ctx, sc, P, q, qd, steps):
@@ -265,6 +268,7 @@ def timed_steps(args, ctx, sc, P, q, qd, steps):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ks = {k: ctx.profile_query(k) for k in KERNELS}
+    tot["host_events"] = {k: ctx.profile_query(k) for k in HOST_EVENTS}
     ctx.profile(False)
     return wall, tot, ks
 
@@ -313,6 +317,7 @@ def line_common(args, wall, tot, ks, steps):
         "pair_evals": {"barrier_active": tot["active"], "ccd": tot["ccd"], "friction": tot["friction"]},
         "pcg_iters": tot["pcg"],
         "phase_wall_ms": {k: v / steps for k, v in tot["host_ms"].items()},
+        "host_events": {k: {"count": v["launches"], "ms": v["ms"]} for k, v in tot["host_events"].items()},
         "kernel_ms": {k: v["ms"] for k, v in ks.items()},
         "roofline": roof,
         "pair_kernels": pair_kernels,

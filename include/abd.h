@@ -458,7 +458,11 @@ int abd_autotune(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, doubl
  * time and only in mode 2 (enable = 2, which adds a reduction per candidate
  * search), "box_tests" / "box_tests_single_level": per candidate-search
  * call, the primitive-pair box tests run with the table's i-AABB culling,
- * and the tests a single-level cull would run.
+ * and the tests a single-level cull would run.  Two host-side entries
+ * count work done on the host inside calls, with host wall time in ms:
+ * "ws_grow" (a workspace buffer grown: synchronise, free, allocate, clear;
+ * units = bytes asked for) and "pcg_capture" (a PCG graph captured and
+ * instantiated; units = iterations in it).
  * Query synchronises the device. */
 int abd_profile(abd_ctx *ctx, int enable, int reset);
 int abd_profile_query(abd_ctx *ctx, const char *kernel, double *ms, int64_t *launches, int64_t *units);

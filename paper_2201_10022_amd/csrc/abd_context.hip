@@ -27,19 +27,34 @@ int abd_hip_check(abd_ctx *ctx, hipError_t e, const char *what) {
 int ws_get(abd_ctx *ctx, const char *name, size_t bytes, void **out, hipStream_t stream) {
   DevBuf &b = ctx->bufs[name];
   if (b.bytes < bytes) {
+    HostTimer ht(ctx, "ws_grow", (int64_t)bytes);
+    // The old buffer may still be read by queued work: it is kept until the
+    // next idle point.  Growing to twice the request (at least 256 KiB)
+    // keeps the number of growths logarithmic in the final size when
+    // counts rise step after step (contacts forming).
     if (b.ptr) {
-      HIP_TRY(ctx, hipStreamSynchronize(stream));
-      HIP_TRY(ctx, hipFree(b.ptr));
+      ctx->ws_old.push_back(b.ptr);
+      ctx->ws_old_bytes += b.bytes;
       b.ptr = nullptr;
       b.bytes = 0;
+      if (ctx->ws_old_bytes > ((size_t)1 << 30)) ABD_TRY(ws_collect(ctx));
     }
-    size_t nb = bytes + bytes / 4;
+    size_t nb = bytes < ((size_t)128 << 10) ? ((size_t)256 << 10) : 2 * bytes;
     nb = (nb + 4095) & ~(size_t)4095;
     HIP_TRY(ctx, hipMalloc(&b.ptr, nb));
     HIP_TRY(ctx, hipMemsetAsync(b.ptr, 0, nb, stream));
     b.bytes = nb;
   }
   *out = b.ptr;
+  return ABD_OK;
+}
+
+int ws_collect(abd_ctx *ctx) {
+  if (ctx->ws_old.empty()) return ABD_OK;
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  for (void *p : ctx->ws_old) HIP_TRY(ctx, hipFree(p));
+  ctx->ws_old.clear();
+  ctx->ws_old_bytes = 0;
   return ABD_OK;
 }
 
@@ -593,6 +608,14 @@ void prof_end(abd_ctx *ctx, hipEvent_t a, const char *name, int64_t units, hipSt
   ctx->pending.push_back({a, b, name, units});
 }
 
+HostTimer::~HostTimer() {
+  if (!ctx->profiling) return;
+  KStat &k = ctx->kstats[name];
+  k.ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  k.launches += 1;
+  k.units += units;
+}
+
 namespace {
 __global__ void k_clear_u64(unsigned long long *a) { *a = 0ull; }
 }  // namespace
@@ -687,6 +710,7 @@ extern "C" int abd_destroy(abd_ctx *ctx) {
   hipDeviceSynchronize();
   for (auto &kv : ctx->bufs)
     if (kv.second.ptr) hipFree(kv.second.ptr);
+  for (void *p : ctx->ws_old) hipFree(p);
   if (ctx->pinned) hipHostFree(ctx->pinned);
   if (ctx->pinned_nt) hipHostFree(ctx->pinned_nt);
   if (ctx->mirror_h) hipHostFree(ctx->mirror_h);

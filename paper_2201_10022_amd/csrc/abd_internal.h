@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -25,6 +26,17 @@ struct DevBuf {
 struct KStat {
   double ms = 0.0;
   int64_t launches = 0, units = 0;
+};
+// Host-side events of the same table (workspace growth, graph captures):
+// wall time on the host, counted while profiling is on.
+struct abd_ctx;
+struct HostTimer {
+  abd_ctx *ctx;
+  const char *name;
+  int64_t units;
+  std::chrono::steady_clock::time_point t0;
+  HostTimer(abd_ctx *c, const char *n, int64_t u) : ctx(c), name(n), units(u), t0(std::chrono::steady_clock::now()) {}
+  ~HostTimer();
 };
 struct PendingEv {
   hipEvent_t a, b;
@@ -50,6 +62,10 @@ struct abd_ctx {
   JointTables joints;
   std::string err;
   std::map<std::string, DevBuf> bufs;
+  // buffers replaced by a larger one, freed after the next point where the
+  // device is idle (ws_collect), so that growing never waits for the stream
+  std::vector<void *> ws_old;
+  size_t ws_old_bytes = 0;
   // counts of the last call per buffer family, used as capacities of the
   // next one (checked when the counts are read)
   std::map<std::string, int64_t> cap_hint;
@@ -123,9 +139,12 @@ int abd_fail(abd_ctx *ctx, int code, const char *fmt, ...);
 int abd_hip_check(abd_ctx *ctx, hipError_t e, const char *what);
 #define HIP_TRY(ctx, expr) ABD_TRY(abd_hip_check((ctx), (expr), #expr))
 
-// Growable named device workspace.  Growing synchronises `stream` first so
-// that no queued kernel still reads the released memory.
+// Growable named device workspace.  A grown buffer is new, zeroed memory
+// (cleared on `stream`); the one it replaces stays allocated until
+// ws_collect, so queued kernels may still read it.
 int ws_get(abd_ctx *ctx, const char *name, size_t bytes, void **out, hipStream_t stream);
+// frees the replaced buffers (synchronises the device when there are any)
+int ws_collect(abd_ctx *ctx);
 template <class T>
 int ws(abd_ctx *ctx, const char *name, size_t count, T **out, hipStream_t stream) {
   return ws_get(ctx, name, count * sizeof(T) + 256, reinterpret_cast<void **>(out), stream);

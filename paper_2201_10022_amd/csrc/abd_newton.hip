@@ -379,6 +379,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, a_ccd, S, e_sc, (kb0 + 1) * S, nullptr, d_alpha, d_e0,
                      nullptr);
   HIP_TRY(ctx, hipStreamSynchronize(s));
+  ABD_TRY(ws_collect(ctx));  // (the stream is idle here)
   st->t_ccd_ms += ms_since(t0);
   double amin = 1.0;
   for (int j = 0; j < S; ++j) {

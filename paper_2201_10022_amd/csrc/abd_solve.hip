@@ -1180,6 +1180,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     for (int gi = 0; gi < 2; ++gi) {
       if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {
+        HostTimer ht(ctx, "pcg_capture", iter_g[gi]);
         if (ctx->pcg_exec[gi]) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec[gi]));
         ctx->pcg_exec[gi] = nullptr;
         hipGraph_t g = nullptr;
@@ -1443,6 +1444,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     for (int gi = 0; gi < 2; ++gi) {
       if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {
+        HostTimer ht(ctx, "pcg_capture", iter_g[gi]);
         if (ctx->pcg_exec[gi]) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec[gi]));
         ctx->pcg_exec[gi] = nullptr;
         hipGraph_t g = nullptr;

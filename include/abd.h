@@ -60,7 +60,10 @@ typedef struct abd_ctx abd_ctx;
 /* Scene geometry (device arrays; counts are host values).  Bodies are
  * contiguous ranges of vertices, triangles and edges.  Vertex, triangle and
  * edge indices are global.  Sub-scenes (batched mode) are contiguous body
- * ranges; pairs never cross sub-scenes. */
+ * ranges; pairs never cross sub-scenes.  A context keeps tables derived
+ * from body_scene (and from the joint arrays) between calls, keyed by the
+ * array's address and the counts: their contents must not change while a
+ * context uses the scene. */
 typedef struct abd_scene {
   int32_t n_bodies, n_verts, n_tris, n_edges, n_scenes;
   const double *xbar;           /* [n_verts][3] body-frame rest positions */

@@ -64,53 +64,74 @@ __global__ void __launch_bounds__(256) k_vertex_map(int nv, const double *__rest
   }
 }
 
-// max_k |J_k p|_inf over vertices (p of fixed bodies is zero): per-block max
-__global__ void __launch_bounds__(256) k_disp_max(int nv, const double *__restrict__ xbar,
-                                                  const int32_t *__restrict__ vert_body, const double *__restrict__ p,
-                                                  double *__restrict__ part) {
-  __shared__ double sh[4];
-  double m = 0.0;
-  for (int k = blockIdx.x * 256 + threadIdx.x; k < nv; k += gridDim.x * 256) {
-    const double *qb = p + 12 * (int64_t)vert_body[k];
+// Per-scene max_k |J_k p|_inf (p of fixed bodies is zero) as bit patterns
+// of non-negative doubles, which order like the values (a NaN component, a
+// failed solve, orders above +inf, so it reaches the result), at
+// out[DISP_PAD * scene] (cleared to 0 first; one 128-byte line per scene,
+// so that atomics on different scenes do not queue on one line).  A block
+// whose vertices lie in one scene (vertices are scene-contiguous) folds to
+// one atomic maximum, other blocks take one per wave and scene run; the
+// maximum makes the result independent of order.
+constexpr int DISP_PAD = 16;
+__global__ void __launch_bounds__(256) k_disp_scene_max(int nv, const double *__restrict__ xbar,
+                                                        const int32_t *__restrict__ vert_body,
+                                                        const int32_t *__restrict__ body_scene,
+                                                        const double *__restrict__ p, unsigned long long *out) {
+  __shared__ unsigned long long sm[4];
+  __shared__ int ss[4];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  unsigned long long m = 0ull;
+  int sc = -1;
+  if (k < nv) {
+    const int b = vert_body[k];
+    sc = body_scene[b];
+    const double *qb = p + 12 * (int64_t)b;
     const double xb0 = xbar[3 * k], xb1 = xbar[3 * k + 1], xb2 = xbar[3 * k + 2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const double *a = qb + 3 + 3 * i;
-      m = fmax(m, fabs(qb[i] + ((a[0] * xb0 + a[1] * xb1) + a[2] * xb2)));
+      const unsigned long long v =
+          (unsigned long long)__double_as_longlong(fabs(qb[i] + ((a[0] * xb0 + a[1] * xb1) + a[2] * xb2)));
+      m = v > m ? v : m;
     }
   }
-  m = wave_max(m);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-}
-
-// |J_k p|_inf per vertex and the vertex's scene
-__global__ void __launch_bounds__(256) k_disp_vert(int nv, const double *__restrict__ xbar,
-                                                   const int32_t *__restrict__ vert_body,
-                                                   const int32_t *__restrict__ body_scene, const double *__restrict__ p,
-                                                   double *__restrict__ val, int32_t *__restrict__ key) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= nv) return;
-  const int b = vert_body[k];
-  const double *qb = p + 12 * (int64_t)b;
-  const double xb0 = xbar[3 * k], xb1 = xbar[3 * k + 1], xb2 = xbar[3 * k + 2];
-  double m = 0.0;
+  // (out-of-range lanes, sc = -1, are last in the block and carry 0)
+  const int s0 = __shfl(sc, 0, 64);
+  const bool uni = __all(sc == s0 || sc < 0);
+  if (uni) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const double *a = qb + 3 + 3 * i;
-    m = fmax(m, fabs(qb[i] + ((a[0] * xb0 + a[1] * xb1) + a[2] * xb2)));
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long v = (unsigned long long)__shfl_xor((long long)m, o, 64);
+      m = v > m ? v : m;
+    }
   }
-  val[k] = m;
-  key[k] = body_scene[b];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm[w] = m;
+    ss[w] = uni ? s0 : -2;  // -2: this wave spans scenes
+  }
+  __syncthreads();
+  const int b0 = ss[0];
+  bool block_uni = b0 >= 0;
+#pragma unroll
+  for (int v = 1; v < 4; ++v) block_uni = block_uni && (ss[v] == b0 || ss[v] == -1);
+  if (block_uni) {
+    if (threadIdx.x == 0) {
+      const unsigned long long a = sm[0] > sm[1] ? sm[0] : sm[1], c = sm[2] > sm[3] ? sm[2] : sm[3];
+      atomicMax(out + DISP_PAD * b0, a > c ? a : c);
+    }
+  } else if (uni) {
+    if ((threadIdx.x & 63) == 0 && s0 >= 0) atomicMax(out + DISP_PAD * s0, m);
+  } else if (sc >= 0) {
+    atomicMax(out + DISP_PAD * sc, m);
+  }
 }
 
-__global__ void k_max_fold(const double *part, int n, double *out) {
-  double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += 64) m = fmax(m, part[i]);
-  m = wave_max(m);
-  if (threadIdx.x == 0) *out = m;
+__global__ void k_clear_u64n(int n, unsigned long long *a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0ull;
 }
+
 
 // (M dq) for one body, M = I_3 (x) [[m, h^T], [h, S]] in (p_i, a_i) groups
 __device__ __forceinline__ void mass_apply(const double *mb, const double *dq, double *out) {
@@ -564,29 +585,19 @@ int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x,
   return abd_hip_check(ctx, hipGetLastError(), "k_vertex_map");
 }
 
-int op_max_abs_disp(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s) {
-  int nblk = (int)grid_for(sc->n_verts, 256 * 8);
-  if (nblk < 1) nblk = 1;
-  if (nblk > 1024) nblk = 1024;
-  double *part;
-  ABD_TRY(ws(ctx, "disp_part", nblk, &part, s));
-  hipLaunchKernelGGL(k_disp_max, dim3(nblk), dim3(256), 0, s, sc->n_verts, sc->xbar, sc->vert_body, p, part);
-  hipLaunchKernelGGL(k_max_fold, dim3(1), dim3(64), 0, s, part, nblk, out_dev);
-  return abd_hip_check(ctx, hipGetLastError(), "k_disp_max");
-}
-
 // per-scene max_k |J_k p|_inf into out [n_scenes]
-int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s) {
+int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, const double **out, int *stride,
+                           hipStream_t s) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
-  if (S <= 1) return op_max_abs_disp(ctx, sc, p, out_dev, s);
-  double *val;
-  int32_t *key;
-  ABD_TRY(ws(ctx, "disp_v", sc->n_verts, &val, s));
-  ABD_TRY(ws(ctx, "disp_k", sc->n_verts, &key, s));
-  hipLaunchKernelGGL(k_disp_vert, dim3(grid_for(sc->n_verts, 256)), dim3(256), 0, s, sc->n_verts, sc->xbar,
-                     sc->vert_body, sc->body_scene, p, val, key);
-  HIP_TRY(ctx, hipGetLastError());
-  return seg_max_scenes(ctx, val, key, sc->n_verts, S, out_dev, s);
+  unsigned long long *pad;
+  ABD_TRY(ws(ctx, "disp_pad", DISP_PAD * (size_t)S, &pad, s));
+  hipLaunchKernelGGL(k_clear_u64n, dim3(grid_for(DISP_PAD * S, 256)), dim3(256), 0, s, DISP_PAD * S, pad);
+  if (sc->n_verts > 0)
+    hipLaunchKernelGGL(k_disp_scene_max, dim3(grid_for(sc->n_verts, 256)), dim3(256), 0, s, sc->n_verts, sc->xbar,
+                       sc->vert_body, sc->body_scene, p, pad);
+  *out = reinterpret_cast<const double *>(pad);
+  *stride = DISP_PAD;
+  return abd_hip_check(ctx, hipGetLastError(), "k_disp_scene_max");
 }
 
 // (kappa_j > 0: the scene's joint penalties are added, times w)

@@ -599,7 +599,6 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   const int nb = sc->n_bodies, nv = sc->n_verts, nt = sc->n_tris, ne = sc->n_edges;
   if (!x1) x1 = x0;
   *n_pt = *n_ee = 0;
-  ctx->involved_valid = false;
   if (nb <= 1 || nv <= 0) return ABD_OK;
   double *bbox;
   ABD_TRY(ws(ctx, "bp_bbox", 6 * (size_t)nb, &bbox, s));
@@ -618,7 +617,8 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, "bp_bcnt", nb, &bcnt, s));
   ABD_TRY(ws(ctx, "bp_boff", nb, &boff, s));
   ABD_TRY(ws(ctx, "bp_btot", 8, &btot, s));  // totals: body pairs, lists, tiles (2), pairs (2)
-  hipLaunchKernelGGL(k_scene_end, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, sc->body_scene, send);
+  if (!scene_table_cached(ctx, sc, "bp_send", send))
+    hipLaunchKernelGGL(k_scene_end, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, sc->body_scene, send);
   hipLaunchKernelGGL(k_body_pairs<0>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
                      skip_scene, bcnt, nullptr, nullptr);
   // the totals' scans also write them to mapped host memory (hbuf, slot
@@ -655,7 +655,6 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     cap_bp = nbp;
   }
   ctx->cap_hint[key_bp] = nbp;
-  ctx->involved_valid = true;
   if (nbp == 0) return ABD_OK;
   // culling boxes of the vertices of bodies in overlapping pairs only
   hipLaunchKernelGGL(k_vert_boxes, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv, sc->vert_body, involved, x0, x1,

@@ -461,26 +461,22 @@ __global__ void k_scene_offsets(int nb, const int32_t *body_scene, int n_scenes,
   off[s] = (int32_t)lower_bound_i32(body_scene, nb, s);
 }
 
-// one block per scene: fixed-order sum (SUM) or max of the items whose
-// (non-decreasing) key equals the scene
-template <int OP>
+// one block per scene: fixed-order sum of the items whose (non-decreasing)
+// key equals the scene
 __global__ void __launch_bounds__(SB) k_seg_reduce(const double *vals, const int32_t *keys, int64_t n, double *out,
                                                    int accumulate) {
   __shared__ double sh[SB / 64];
   const int s = blockIdx.x;
   const int64_t lo = lower_bound_i32(keys, n, s), hi = lower_bound_i32(keys, n, s + 1);
   double v = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += SB) v = OP == 0 ? v + vals[i] : fmax(v, vals[i]);
-  v = OP == 0 ? wave_sum(v) : wave_max(v);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += SB) v = v + vals[i];
+  v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double r = sh[0];
-    for (int w = 1; w < SB / 64; ++w) r = OP == 0 ? r + sh[w] : fmax(r, sh[w]);
-    if (OP == 0)
-      out[s] = accumulate ? out[s] + r : r;
-    else
-      out[s] = accumulate ? fmax(out[s], r) : r;
+    for (int w = 1; w < SB / 64; ++w) r = r + sh[w];
+    out[s] = accumulate ? out[s] + r : r;
   }
 }
 
@@ -558,26 +554,30 @@ int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, 
   return abd_hip_check(ctx, hipGetLastError(), "k_trial_pass");
 }
 
+bool scene_table_cached(abd_ctx *ctx, const abd_scene *sc, const char *name, const void *buf) {
+  const std::vector<uintptr_t> key = {(uintptr_t)sc->body_scene, (uintptr_t)sc->n_bodies, (uintptr_t)sc->n_scenes,
+                                      (uintptr_t)buf};
+  std::vector<uintptr_t> &k = ctx->scene_tables[name];
+  if (k == key) return true;
+  k = key;
+  return false;
+}
+
 int op_scene_offsets(abd_ctx *ctx, const abd_scene *sc, const int32_t **off, hipStream_t s) {
   int32_t *o;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   ABD_TRY(ws(ctx, "scene_body_off", S + 1, &o, s));
+  *off = o;
+  if (scene_table_cached(ctx, sc, "scene_body_off", o)) return ABD_OK;
   hipLaunchKernelGGL(k_scene_offsets, dim3(grid_for(S + 1, 256)), dim3(256), 0, s, sc->n_bodies, sc->body_scene, S,
                      o);
-  *off = o;
   return abd_hip_check(ctx, hipGetLastError(), "k_scene_offsets");
 }
 
 int seg_sum_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out_accum,
                    hipStream_t s) {
   if (n_scenes <= 1) return n > 0 ? reduce_sum_f64(ctx, vals, n, out_accum, s) : ABD_OK;
-  hipLaunchKernelGGL(k_seg_reduce<0>, dim3(n_scenes), dim3(SB), 0, s, vals, keys, n, out_accum, 1);
-  return abd_hip_check(ctx, hipGetLastError(), "k_seg_reduce");
-}
-
-int seg_max_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_reduce<1>, dim3(n_scenes > 0 ? n_scenes : 1), dim3(SB), 0, s, vals, keys, n, out, 0);
+  hipLaunchKernelGGL(k_seg_reduce, dim3(n_scenes), dim3(SB), 0, s, vals, keys, n, out_accum, 1);
   return abd_hip_check(ctx, hipGetLastError(), "k_seg_reduce");
 }
 

@@ -56,9 +56,6 @@ struct abd_ctx {
   int device = 0;
   // launch shapes (abd_tune_set / abd_autotune); none changes a result
   abd_tune tune = {16, 1, 256, 1024, 256, 16, 64, 1};
-  // the last op_candidates call marked, per body, whether it is in an
-  // overlapping body pair (workspace "bp_involved"); false until it has
-  bool involved_valid = false;
   JointTables joints;
   std::string err;
   std::map<std::string, DevBuf> bufs;
@@ -111,6 +108,9 @@ struct abd_ctx {
   // and the total bytes of the per-scene pair matrices
   std::vector<uintptr_t> od_key;
   int64_t od_total = 0;
+  // tables that depend only on a scene's body-to-scene map (per workspace
+  // name: the scene key and the buffer they were written to)
+  std::map<std::string, std::vector<uintptr_t>> scene_tables;
   int64_t fr_n_pt = 0, fr_n_ee = 0;
   // swept candidates of the last accepted Newton step (the segment holds the
   // new iterate, so its static candidates are a subset of these)
@@ -145,6 +145,10 @@ int abd_hip_check(abd_ctx *ctx, hipError_t e, const char *what);
 int ws_get(abd_ctx *ctx, const char *name, size_t bytes, void **out, hipStream_t stream);
 // frees the replaced buffers (synchronises the device when there are any)
 int ws_collect(abd_ctx *ctx);
+// true when workspace `buf` still holds the table `name` computed for the
+// scene's body-to-scene map (same map, counts and buffer); otherwise
+// records it as computed now (the caller then writes it)
+bool scene_table_cached(abd_ctx *ctx, const abd_scene *sc, const char *name, const void *buf);
 template <class T>
 int ws(abd_ctx *ctx, const char *name, size_t count, T **out, hipStream_t stream) {
   return ws_get(ctx, name, count * sizeof(T) + 256, reinterpret_cast<void **>(out), stream);
@@ -308,9 +312,11 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
 int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
               int64_t n_keys, const double *pre_diag, const double *rhs, double *x_out, double rtol, int max_iter,
               int *iters, hipStream_t s);
-int op_max_abs_disp(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s);
-// per-scene variants (out [n_scenes]; energies accumulated, maxima written)
-int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, double *out_dev, hipStream_t s);
+// per-scene max_k |J_k p|_inf at (*out)[j * *stride] (device, context
+// workspace; a NaN displacement gives NaN); per-scene energies accumulate
+// into out [n_scenes]
+int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, const double **out, int *stride,
+                           hipStream_t s);
 int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                           const double *qt, double *energy, hipStream_t s);
 int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
@@ -332,6 +338,17 @@ struct d3 {
 };
 
 __host__ __device__ __forceinline__ d3 ld3(const double *p, int64_t i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+
+// vertex v at the body state q (12 per body): p + A xbar_v, each component
+// p_i + ((a_i0 xb0 + a_i1 xb1) + a_i2 xb2), the vertex map's arithmetic
+__host__ __device__ __forceinline__ d3 map_vertex(const double *q, const int32_t *vert_body, const double *xbar,
+                                                  int64_t v) {
+#pragma clang fp contract(off)
+  const double *qb = q + 12 * (int64_t)vert_body[v];
+  const double xb0 = xbar[3 * v], xb1 = xbar[3 * v + 1], xb2 = xbar[3 * v + 2];
+  return {qb[0] + ((qb[3] * xb0 + qb[4] * xb1) + qb[5] * xb2), qb[1] + ((qb[6] * xb0 + qb[7] * xb1) + qb[8] * xb2),
+          qb[2] + ((qb[9] * xb0 + qb[10] * xb1) + qb[11] * xb2)};
+}
 
 __host__ __device__ __forceinline__ d3 xsub(d3 a, d3 b) {
 #pragma clang fp contract(off)
@@ -545,15 +562,16 @@ int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, doubl
 // (trial, scene) into out_accum[t * n_scenes + scene] (accumulated); keys
 // (non-decreasing item scenes) are needed when n_scenes > 1.
 // Energies of n_trials configurations at once (trial t's q, x at
-// q + 12 nb t, x + 3 nv t): each op accumulates into energy[t S + scene];
-// with items non-NULL it instead writes the per-item energies (trial t's
-// at items + t estride) and sums nothing.
+// q + 12 nb t, x + 3 nv t; the barrier maps its pairs' vertices from q
+// itself): each op accumulates into energy[t S + scene]; with items
+// non-NULL it instead writes the per-item energies (trial t's at
+// items + t estride) and sums nothing.
 int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int n_trials, double *x,
                          hipStream_t s);
 int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                           const double *qt, int n_trials, double *energy, hipStream_t s, double *items = nullptr,
                           int64_t estride = 0);
-int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
+int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                              int n_trials, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                              double *energy, hipStream_t s, double *items = nullptr, int64_t estride = 0);
 int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
@@ -563,8 +581,6 @@ int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, 
                    int n_scenes, double *out_accum, hipStream_t s,
                    bool assign = false);
 int seg_sum_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out_accum,
-                   hipStream_t s);
-int seg_max_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out,
                    hipStream_t s);
 // first body of every scene, [n_scenes + 1] (device, context workspace)
 int op_scene_offsets(abd_ctx *ctx, const abd_scene *sc, const int32_t **off, hipStream_t s);

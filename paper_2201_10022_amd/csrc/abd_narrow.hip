@@ -151,11 +151,14 @@ __global__ void k_records(int64_t n, const PairInfo *info, const uint8_t *fixed,
   const PairInfo pi = info[a];
   const int b0 = pi.body[0], b1 = pi.body[1];
   const bool f0 = fixed[b0] != 0, f1 = fixed[b1] != 0;
-  rkey[3 * a] = f0 ? 0xffffffffu : (uint32_t)b0;
+  // (records that belong to no block take key nb + n_keys, past the last
+  // block, so that the sort needs only the bits of that value)
+  const uint32_t none = (uint32_t)(nb + n_keys);
+  rkey[3 * a] = f0 ? none : (uint32_t)b0;
   rval[3 * a] = (uint32_t)(4 * a + 0);
-  rkey[3 * a + 1] = f1 ? 0xffffffffu : (uint32_t)b1;
+  rkey[3 * a + 1] = f1 ? none : (uint32_t)b1;
   rval[3 * a + 1] = (uint32_t)(4 * a + 1);
-  uint32_t ko = 0xffffffffu;
+  uint32_t ko = none;
   if (want_off && !f0 && !f1) {
     const int k = find_key(keys, n_keys, min(b0, b1), max(b0, b1));
     if (k < 0)
@@ -291,19 +294,28 @@ __global__ void k_assemble_final(int64_t nblocks, int nb, const int64_t *chunk_o
 
 // pair energies; key_out (may be NULL) receives each pair's scene
 // (grid.y > 1: trial t's positions at x + t xstride, energies at
-// e_out + t estride, estride 0: n)
+// e_out + t estride, estride 0: n).  With qmap non-NULL the positions are
+// mapped from the body states at qmap + t qstride instead (x unused): the
+// pairs' vertices only, with the vertex map's arithmetic.
 __global__ void k_energy_only(int64_t n_pt, int64_t n, const int32_t *pt, const int32_t *ee, const int32_t *tris,
                               const int32_t *edges, const double *x, const double *xbar, double dhat,
                               double kappa, double *e_out, const int32_t *vert_body, const int32_t *body_scene,
                               int32_t *key_out, int64_t xstride = 0, int64_t estride = 0,
-                              const double *kappa_sc = nullptr) {
+                              const double *kappa_sc = nullptr, const double *qmap = nullptr, int64_t qstride = 0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  x += blockIdx.y * xstride;
   e_out += blockIdx.y * (estride > 0 ? estride : n);
   int is_ee, vid[4];
   d3 X[4];
-  load_pair(i, n_pt, pt, ee, tris, edges, x, is_ee, vid, X);
+  if (qmap) {
+    is_ee = i >= n_pt;
+    pair_vids(is_ee, is_ee ? ee + 2 * (i - n_pt) : pt + 2 * i, tris, edges, vid);
+    qmap += blockIdx.y * qstride;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) X[k] = map_vertex(qmap, vert_body, xbar, vid[k]);
+  } else {
+    load_pair(i, n_pt, pt, ee, tris, edges, x + blockIdx.y * xstride, is_ee, vid, X);
+  }
   if (key_out && blockIdx.y == 0) key_out[i] = body_scene[vert_body[vid[0]]];
   int ty;
   double num, den;
@@ -428,7 +440,9 @@ int op_assemble(abd_ctx *ctx, const abd_scene *sc, int64_t n, const PairInfo *in
   ABD_TRY(ws(ctx, "br_rval", nrec, &rval, s));
   hipLaunchKernelGGL(k_records, dim3(grid_for(n, 256)), dim3(256), 0, s, n, info, sc->body_fixed, nb, keys, n_keys,
                      rkey, rval, off != nullptr ? 1 : 0, err);
-  ABD_TRY(sort_pairs_u32(ctx, &rkey, &rval, nrec, 32, s));
+  int key_bits = 1;
+  while (key_bits < 32 && (nblocks >> key_bits) != 0) ++key_bits;
+  ABD_TRY(sort_pairs_u32(ctx, &rkey, &rval, nrec, key_bits, s));
   int64_t *bstart, *nchunk, *choff, *nch_tot;
   ABD_TRY(ws(ctx, "br_bstart", nblocks + 1, &bstart, s));
   ABD_TRY(ws(ctx, "br_nchunk", nblocks + 1, &nchunk, s));
@@ -490,7 +504,7 @@ int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params
   return ABD_OK;
 }
 
-int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
+int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                              int n_trials, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                              double *energy, hipStream_t s, double *items, int64_t estride) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
@@ -503,8 +517,8 @@ int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params
   hipEvent_t pe = prof_begin(ctx, s);
   const int eb = ctx->tune.energy_block;
   hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb), n_trials), dim3(eb), 0, s, n_pt, n, pt, ee, sc->tris,
-                     sc->edges, x, sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key,
-                     3 * (int64_t)sc->n_verts, items ? estride : 0, ctx->kappa_sc);
+                     sc->edges, nullptr, sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key,
+                     (int64_t)0, items ? estride : 0, ctx->kappa_sc, q, 12 * (int64_t)sc->n_bodies);
   prof_end(ctx, pe, "energy_only", n * n_trials, s);
   HIP_TRY(ctx, hipGetLastError());
   if (items) return ABD_OK;

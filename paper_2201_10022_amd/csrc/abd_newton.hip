@@ -97,10 +97,10 @@ int err_check(abd_ctx *ctx, int e, hipStream_t s) {
 namespace {
 
 // small results straight into mapped host memory (one launch instead of a
-// copy per array): ha[0..na) = a, hb[0..nb) = b, *he = *e
+// copy per array): ha[0..na) = a[0, as, 2 as ..), hb[0..nb) = b, *he = *e
 __global__ void k_to_host(const double *a, int na, const double *b, int nb, const int *e, double *ha, double *hb,
-                          int *he) {
-  for (int i = threadIdx.x; i < na; i += blockDim.x) ha[i] = a[i];
+                          int *he, int as = 1) {
+  for (int i = threadIdx.x; i < na; i += blockDim.x) ha[i] = a[(int64_t)as * i];
   for (int i = threadIdx.x; i < nb; i += blockDim.x) hb[i] = b[i];
   if (e && threadIdx.x == 0) *he = *e;
 }
@@ -116,25 +116,48 @@ __global__ void k_zero_done(int nb, const int32_t *body_scene, const uint8_t *do
   if (i >= 12 * nb) return;
   if (done[body_scene[i / 12]]) p[i] = 0.0;
 }
-// trial t of n: out[t][i] = a[i] + alpha[t S + scene] b[i]
-__global__ void k_axpy_trials(int nb, int S, const int32_t *body_scene, const double *a, const double *alpha,
-                              const double *b, double *out) {
+// the accepted step, in place: q += alpha[scene] p as one fused multiply-add
+// per entry (the trial states' arithmetic); scenes with alpha 0 (done, or
+// not accepted yet) keep q bit for bit
+__global__ void k_step_scenes(int nb, const int32_t *body_scene, const double *alpha, const double *p, double *q) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 12 * nb) return;
-  const int t = blockIdx.y;
-  out[(int64_t)t * 12 * nb + i] = a[i] + alpha[(int64_t)t * S + body_scene[i / 12]] * b[i];
+  const double al = alpha[body_scene[i / 12]];
+  if (al != 0.0) q[i] = fma(al, p[i], q[i]);
+}
+// newly converged scenes: done[j] |= disp[j stride] <= tol (the host takes
+// the same decision on the same values for its own copy of the flags)
+__global__ void k_done_update(int S, const double *disp, int stride, double tol, uint8_t *done) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= S || done[j]) return;
+  if (disp[(int64_t)stride * j] <= tol) done[j] = 1;
+}
+// the first line-search batch's decision per scene: alpha[j] = the first
+// trial step alpha_ccd 2^-t (t < kb) whose energy e[S + t S + j] does not
+// exceed E(q) = e[j]; 0 for done scenes and scenes with no such trial
+__global__ void k_ls_accept(int S, int kb, const uint8_t *done, const double *a_ccd, const double *e,
+                            double *alpha) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= S) return;
+  double al = 0.0;
+  if (!done[j]) {
+    int t = 0;
+    while (t < kb && !(e[S + (int64_t)t * S + j] <= e[j])) ++t;
+    if (t < kb) al = ldexp(a_ccd[j], -t);
+  }
+  alpha[j] = al;
 }
 // The trial states of a line-search batch in one launch (trial in grid.y):
-// blocks [0, nqb) form q_t = q + alpha_t p per entry, as k_axpy_trials does
-// (one fused multiply-add); the others map the vertices, x_t = x(q_t), with
-// the same arithmetic as the vertex map and q_t formed in place by that
-// same fused multiply-add, so they need not wait for the first part.
-// Vertices of bodies in no overlapping body pair of the sweep (only_bodies
-// non-NULL and 0) are skipped: no candidate pair reads them.
+// blocks [0, nqb) form q_t = q + alpha_t p per entry with one fused
+// multiply-add, as the accepted step does; the others (launched only when lagged friction
+// reads vertex positions; the barrier maps its pairs' vertices from q_t
+// itself) map every vertex, x_t = x(q_t), with the same arithmetic as the
+// vertex map and q_t formed in place by that same fused multiply-add, so
+// they need not wait for the first part.
 __global__ void __launch_bounds__(256) k_trial_states(int nb, int S, const int32_t *body_scene, const double *q,
                                                       const double *alpha, const double *p, double *qn, int nv,
                                                       const double *xbar, const int32_t *vert_body, double *xn,
-                                                      int nqb, const uint8_t *only_bodies) {
+                                                      int nqb) {
 #pragma clang fp contract(off)
   const int t = blockIdx.y;
   if ((int)blockIdx.x < nqb) {
@@ -146,7 +169,6 @@ __global__ void __launch_bounds__(256) k_trial_states(int nb, int S, const int32
   const int k = ((int)blockIdx.x - nqb) * 256 + threadIdx.x;
   if (k >= nv) return;
   const int64_t b = vert_body[k];
-  if (only_bodies && !only_bodies[b]) return;
   const double al = alpha[(int64_t)t * S + body_scene[b]];
   double qb[12];
 #pragma unroll
@@ -184,25 +206,21 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int nb = sc->n_bodies;
   const int64_t n12 = 12 * (int64_t)nb;
-  double *qn, *xn;
+  double *qn, *xn = nullptr;
   ABD_TRY(ws(ctx, "ls_q", (size_t)n * n12, &qn, s));
-  ABD_TRY(ws(ctx, "ls_x", (size_t)n * 3 * sc->n_verts, &xn, s));
+  if (fr) ABD_TRY(ws(ctx, "ls_x", (size_t)n * 3 * sc->n_verts, &xn, s));
   // (one scene with items: the row sums below are assigned, not added)
   if (S > 1 || (int64_t)nb + npt + nee + (fr ? fr->n() : 0) == 0) ABD_TRY(zero(ctx, e_dev, (int64_t)n * S, s));
   {
-    // (the candidates are those of the sweep just culled: vertices of bodies
-    // it found in no overlapping pair are read by no pair; lagged friction
-    // pairs may lie elsewhere, so with friction every vertex is mapped)
-    uint8_t *only = nullptr;
-    if (!fr && ctx->involved_valid) ABD_TRY(ws(ctx, "bp_involved", nb, &only, s));
     const int nqb = (int)grid_for(n12, 256);
-    hipLaunchKernelGGL(k_trial_states, dim3(nqb + grid_for(sc->n_verts, 256), n), dim3(256), 0, s, nb, S,
-                       sc->body_scene, q, alpha, p, qn, sc->n_verts, sc->xbar, sc->vert_body, xn, nqb, only);
+    const int nvb = fr ? (int)grid_for(sc->n_verts, 256) : 0;
+    hipLaunchKernelGGL(k_trial_states, dim3(nqb + nvb, n), dim3(256), 0, s, nb, S, sc->body_scene, q, alpha, p, qn,
+                       sc->n_verts, sc->xbar, sc->vert_body, xn, nqb);
     HIP_TRY(ctx, hipGetLastError());
   }
   if (S > 1) {
     ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, e_dev, s));
-    ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, xn, n, pt, npt, ee, nee, e_dev, s));
+    ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, qn, n, pt, npt, ee, nee, e_dev, s));
     if (fr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, e_dev, s));
     return ABD_OK;
   }
@@ -213,7 +231,7 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
   double *items;
   ABD_TRY(ws(ctx, "ls_items", (size_t)n * nt, &items, s));
   ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, nullptr, s, items, nt));
-  if (npt + nee) ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, xn, n, pt, npt, ee, nee, nullptr, s, items + nb, nt));
+  if (npt + nee) ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, qn, n, pt, npt, ee, nee, nullptr, s, items + nb, nt));
   if (nfr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, nullptr, s, items + nb + npt + nee, nt));
   return seg_sum_trials(ctx, items, nt, nt, nullptr, n, 1, e_dev, s, true);
 }
@@ -234,15 +252,13 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   const int nb = sc->n_bodies, nv = sc->n_verts;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int n12 = 12 * nb;
-  double *x, *x1, *g, *diag, *off, *p, *qa, *e, *sv, *alpha_dev;
+  double *x, *x1, *g, *diag, *off, *p, *qa, *alpha_dev;
   ABD_TRY(ws(ctx, "nt_x", 3 * (size_t)nv, &x, s));
   ABD_TRY(ws(ctx, "nt_x1", 3 * (size_t)nv, &x1, s));
   ABD_TRY(ws(ctx, "nt_g", n12, &g, s));
   ABD_TRY(ws(ctx, "nt_diag", 144 * (size_t)nb, &diag, s));
   ABD_TRY(ws(ctx, "nt_p", n12, &p, s));
   ABD_TRY(ws(ctx, "nt_qa", n12, &qa, s));
-  ABD_TRY(ws(ctx, "nt_e", 4, &e, s));
-  ABD_TRY(ws(ctx, "nt_sv", 2 * (size_t)S, &sv, s));
   ABD_TRY(ws(ctx, "nt_alpha", (size_t)(LS_BATCH + 1) * S, &alpha_dev, s));
   double *e_sc, *a_ccd;  // e_sc: E0 [S], then the trials' energies [LS_BATCH][S]
   ABD_TRY(ws(ctx, "nt_escene", (size_t)(LS_BATCH + 1) * S, &e_sc, s));
@@ -291,14 +307,15 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   st->n_offdiag = nk;
   st->t_candidates_ms += ms_since(t0);
   ABD_TRY(ws(ctx, "nt_off", 144 * (size_t)(nk + 1), &off, s));
-  ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, off, 144 * nk, e, 1, s));
+  ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, off, 144 * nk, nullptr, 0, s));
   // adaptive barrier stiffness: the doubling rule at this iterate, before
   // the barrier's derivatives and this iteration's energies
   if (ctx->kappa_sc) ABD_TRY(op_kappa_update(ctx, sc, prm, x, pt, npt, ee, nee, s));
   t0 = std::chrono::steady_clock::now();
-  ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, e, g, diag, 1, s));
+  // (the energy at q comes with the line search's trials: none is summed here)
+  ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, nullptr, g, diag, 1, s));
   int64_t nap = 0, nae = 0;
-  ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, e, g, diag, off, 1, &nap, &nae, s, fr));
+  ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, nullptr, g, diag, off, 1, &nap, &nae, s, fr));
   if (sc->n_joints > 0 && prm->kappa_j > 0.0)
     ABD_TRY(op_joint_off(ctx, sc, prm->kappa_j * prm->dt * prm->dt, keys, nk, off, s));
   st->t_barrier_ms += ms_since(t0);
@@ -317,12 +334,18 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s, nullptr, nullptr, &pat));
   st->pcg_iters = its;
   st->t_solve_ms += ms_since(t0);
-  ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, sv, s));
+  const double *dsp_first;
+  int dsp_stride;
   {
+    ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, &dsp_first, &dsp_stride, s));
     int *errf;
     ABD_TRY(ws(ctx, "err_flag", 1, &errf, s));
-    hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, sv, S, nullptr, 0, errf, d_disp, nullptr, d_err);
+    hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, dsp_first, S, nullptr, 0, errf, d_disp, nullptr, d_err,
+                       dsp_stride);
   }
+  const double tol_disp = prm->newton_tol * prm->dt;
+  hipLaunchKernelGGL(k_done_update, dim3(grid_for(S, 256)), dim3(256), 0, s, S, dsp_first, dsp_stride, tol_disp,
+                     done_dev);
   HIP_TRY(ctx, hipStreamSynchronize(s));
   ABD_TRY(err_check(ctx, h_err[0], s));
   double dmax = 0.0;
@@ -331,7 +354,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     if (h_done[j]) continue;
     if (!std::isfinite(h_disp[j])) return abd_fail(ctx, ABD_E_PCG, "non-finite Newton direction (scene %d)", j);
     dmax = h_disp[j] > dmax ? h_disp[j] : dmax;
-    if (h_disp[j] <= prm->newton_tol * prm->dt) {
+    if (h_disp[j] <= tol_disp) {
       h_done[j] = 1;
       ++st->newly_converged;
     } else {
@@ -339,7 +362,6 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     }
   }
   st->disp = dmax;
-  if (st->newly_converged > 0) HIP_TRY(ctx, hipMemcpyAsync(done_dev, h_done, S, hipMemcpyHostToDevice, s));
   if (n_active == 0) {
     st->converged = 1;
     st->alpha = 0.0;
@@ -378,6 +400,15 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb0 + 1, spt, nspt, see, nsee, fr, e_sc, s));
   hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, a_ccd, S, e_sc, (kb0 + 1) * S, nullptr, d_alpha, d_e0,
                      nullptr);
+  // (batches: the first batch's accepted steps are taken on the device
+  // before the host has read the energies; it takes the same decisions)
+  double *alpha_acc = nullptr;
+  if (S > 1) {
+    ABD_TRY(ws(ctx, "nt_alpha_acc", S, &alpha_acc, s));
+    hipLaunchKernelGGL(k_ls_accept, dim3(grid_for(S, 256)), dim3(256), 0, s, S, kb0, done_dev, a_ccd, e_sc,
+                       alpha_acc);
+    hipLaunchKernelGGL(k_step_scenes, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, alpha_acc, p, q);
+  }
   HIP_TRY(ctx, hipStreamSynchronize(s));
   ABD_TRY(ws_collect(ctx));  // (the stream is idle here)
   st->t_ccd_ms += ms_since(t0);
@@ -390,14 +421,14 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   int k = 0;
   int max_halvings = 0;
   std::vector<int> halv(S, 0);
-  std::vector<uint8_t> acc(S, 0);
+  std::vector<uint8_t> acc(S, 0), acc_first(S, 0);
   for (int j = 0; j < S; ++j) acc[j] = h_done[j];
   bool all_acc = false;
   while (k < prm->max_ls && !all_acc) {
     const int kb = k == 0 ? kb0 : (k + K <= prm->max_ls ? K : prm->max_ls - k);
     if (k > 0) {
       for (int t = 0; t < kb; ++t)
-        for (int j = 0; j < S; ++j) h_atr[(size_t)t * S + j] = acc[j] ? h_alpha[j] : std::ldexp(h_alpha[j], -t);
+        for (int j = 0; j < S; ++j) h_atr[(size_t)t * S + j] = acc[j] ? 0.0 : std::ldexp(h_alpha[j], -t);
       HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_atr, (size_t)kb * S * sizeof(double), hipMemcpyHostToDevice, s));
       ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb, spt, nspt, see, nsee, fr, e_sc + S, s));
       HIP_TRY(ctx, hipMemcpyAsync(h_e1, e_sc + S, (size_t)kb * S * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -410,6 +441,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
       while (t < kb && !(h_e1[(size_t)t * S + j] <= h_e0[j])) ++t;
       if (t < kb) {
         acc[j] = 1;
+        acc_first[j] = k == 0;
         h_alpha[j] = std::ldexp(h_alpha[j], -t);
         halv[j] += t;
         h_e1[j] = h_e1[(size_t)t * S + j];
@@ -428,9 +460,17 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   if (S == 1) {
     hipLaunchKernelGGL(k_axpy1, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, q, h_alpha[0], p, q);
   } else {
-    HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_alpha, S * sizeof(double), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_axpy_trials, dim3(grid_for(n12, 256), 1), dim3(256), 0, s, nb, S, sc->body_scene, q,
-                       alpha_dev, p, q);
+    // (scenes accepted in the first batch have taken their step already)
+    bool later = false;
+    for (int j = 0; j < S; ++j) {
+      h_atr[j] = h_done[j] || acc_first[j] ? 0.0 : h_alpha[j];
+      later = later || h_atr[j] != 0.0;
+    }
+    if (later) {
+      HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_atr, S * sizeof(double), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_step_scenes, dim3(grid_for(n12, 256)), dim3(256), 0, s, nb, sc->body_scene, alpha_dev,
+                         p, q);
+    }
   }
   double e0 = 0.0, e1 = 0.0, amin_acc = 1.0;
   for (int j = 0; j < S; ++j) {

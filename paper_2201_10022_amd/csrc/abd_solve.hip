@@ -1298,7 +1298,9 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
   hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed,
                      pre_diag ? pre_diag : diag, inv, err);
-  if (S <= SETUP_T) {
+  // (the block-to-scene maps depend on the scene alone)
+  if (scene_table_cached(ctx, sc, "pcg_scene_maps", c_scene)) {
+  } else if (S <= SETUP_T) {
     hipLaunchKernelGGL(k_pcg_scene_setup, dim3(1), dim3(SETUP_T), 0, s, S, sbo, (int64_t)nblk_u, (int64_t)nblk_s,
                        u_off, s_off, u_scene, s_scene);
     hipLaunchKernelGGL(k_pcg_scene_map, dim3(1), dim3(SETUP_T), 0, s, S, sbo, CBB, (int64_t)nblk_c, c_off, c_scene);

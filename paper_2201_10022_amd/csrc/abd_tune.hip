@@ -71,7 +71,7 @@ extern "C" int abd_autotune(abd_ctx *ctx, const abd_scene *sc, const abd_params 
   };
   // candidate values per entry (the struct's order)
   const std::vector<std::vector<int>> cand = {
-      {8, 16, 32, 64}, {1, 2, 4}, {64, 128, 256}, {256, 512, 1024, 2048, 4096}, {128, 256, 512}, {8, 16, 32},
+      {8, 16, 32, 64}, {1, 2, 4}, {64, 128, 256}, {256, 512, 1024, 2048, 4096}, {128, 256, 512}, {4, 8, 16, 32},
       {1, 3}};
   abd_tune cur = ctx->tune;
   double best = 0.0;

@@ -904,10 +904,17 @@ int dense_layout(abd_ctx *ctx, const abd_scene *sc, const int64_t **foff, int64_
   return ABD_OK;
 }
 
+int op_offdiag_count(abd_ctx *ctx, int64_t *n_keys) {
+  int64_t *hbuf, *hbuf_d;
+  ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
+  *n_keys = hbuf[MIR_OFFDIAG];
+  return mirror_counts_ok(ctx, {*n_keys}, "offdiag");
+}
+
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys_out, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2,
                int64_t n_pt2, const int32_t *ee2, int64_t n_ee2, KeyPattern *pat, const int32_t *pt3,
-               int64_t n_pt3) {
+               int64_t n_pt3, bool defer) {
   // (a scene's joints between two free bodies join the pattern)
   if (!pt3 && sc->n_joints > 0) {
     JointTables *jt = nullptr;
@@ -922,7 +929,15 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   if (pat) *pat = KeyPattern{};
   std::string nm = std::string(tag) + "_keys";
   ABD_TRY(ws(ctx, nm.c_str(), 2 * n + 2, keys_out, s));
-  if (n == 0) return ABD_OK;
+  if (n == 0) {
+    if (defer) {
+      // (the count the caller will read)
+      int64_t *hbuf, *hbuf_d;
+      ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
+      hbuf[MIR_OFFDIAG] = 0;
+    }
+    return ABD_OK;
+  }
   uint64_t *k, *k2;
   int64_t *flag, *pos, *tot;
   ABD_TRY(ws(ctx, "od_k", n, &k, s));
@@ -981,9 +996,9 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
       pat->tperm = tperm;
       pat->valid = true;
     }
+    if (defer) return abd_hip_check(ctx, hipGetLastError(), "offdiag");
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    *n_keys = hbuf[MIR_OFFDIAG];
-    ABD_TRY(mirror_counts_ok(ctx, {*n_keys}, "offdiag"));
+    ABD_TRY(op_offdiag_count(ctx, n_keys));
     return abd_hip_check(ctx, hipGetLastError(), "offdiag");
   }
   int64_t at = 0;
@@ -1003,9 +1018,9 @@ int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_p
   ABD_TRY(mirror_get(ctx, &hbuf, &hbuf_d));
   ABD_TRY(scan_exclusive_i64(ctx, flag, pos, n, tot, s, hbuf_d + MIR_OFFDIAG));
   hipLaunchKernelGGL(k_unique_write, dim3(grid_for(n, 256)), dim3(256), 0, s, n, k2, flag, pos, *keys_out);
+  if (defer) return abd_hip_check(ctx, hipGetLastError(), "offdiag");
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  *n_keys = hbuf[MIR_OFFDIAG];
-  ABD_TRY(mirror_counts_ok(ctx, {*n_keys}, "offdiag"));
+  ABD_TRY(op_offdiag_count(ctx, n_keys));
   return abd_hip_check(ctx, hipGetLastError(), "offdiag");
 }
 

@@ -255,23 +255,34 @@ __global__ void __launch_bounds__(LB_T) k_scan_lb(const int64_t *in, int64_t *ou
 }
 
 int lb_prepare(abd_ctx *ctx, int64_t words, unsigned long long **status, unsigned int *tag, hipStream_t s) {
-  if (ctx->lb_words < words) {
+  abd_ctx::LbState &lb = ctx->lb[s != nullptr && s == ctx->aux_stream ? 1 : 0];
+  if (lb.words < words) {
     // status words start untagged (tag 0 is never used)
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    if (ctx->lb_status) HIP_TRY(ctx, hipFree(ctx->lb_status));
-    ctx->lb_status = nullptr;
+    if (lb.status) HIP_TRY(ctx, hipFree(lb.status));
+    lb.status = nullptr;
     const int64_t cap = words + words / 2 + 64;
-    HIP_TRY(ctx, hipMalloc(&ctx->lb_status, cap * sizeof(unsigned long long)));
-    HIP_TRY(ctx, hipMemsetAsync(ctx->lb_status, 0, cap * sizeof(unsigned long long), s));
-    ctx->lb_words = cap;
+    HIP_TRY(ctx, hipMalloc(&lb.status, cap * sizeof(unsigned long long)));
+    HIP_TRY(ctx, hipMemsetAsync(lb.status, 0, cap * sizeof(unsigned long long), s));
+    lb.words = cap;
   }
-  if (++ctx->lb_tag >= (1u << LB_TAG_BITS)) {
+  if (++lb.tag >= (1u << LB_TAG_BITS)) {
     // tags wrap: clear the words so that none carries a reused tag
-    ctx->lb_tag = 1;
-    HIP_TRY(ctx, hipMemsetAsync(ctx->lb_status, 0, ctx->lb_words * sizeof(unsigned long long), s));
+    lb.tag = 1;
+    HIP_TRY(ctx, hipMemsetAsync(lb.status, 0, lb.words * sizeof(unsigned long long), s));
   }
-  *status = ctx->lb_status;
-  *tag = ctx->lb_tag;
+  *status = lb.status;
+  *tag = lb.tag;
+  return ABD_OK;
+}
+
+int aux_stream_get(abd_ctx *ctx, hipStream_t *aux) {
+  if (!ctx->aux_stream) {
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  }
+  *aux = ctx->aux_stream;
   return ABD_OK;
 }
 
@@ -297,10 +308,11 @@ int scan_exclusive_i64(abd_ctx *ctx, const int64_t *in, int64_t *out, int64_t n,
     return abd_hip_check(ctx, hipGetLastError(), "k_scan_lb");
   }
   // the last input for the total: a copy only when the scan is in place
+  const bool aux = s != nullptr && s == ctx->aux_stream;  // (its own scratch)
   const int64_t *last = in + n - 1;
   if ((total || host) && in == out) {
     int64_t *keep;
-    ABD_TRY(ws(ctx, "scan_last", 1, &keep, s));
+    ABD_TRY(ws(ctx, aux ? "scan_last_aux" : "scan_last", 1, &keep, s));
     HIP_TRY(ctx, hipMemcpyAsync(keep, in + n - 1, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     last = keep;
   }
@@ -714,7 +726,11 @@ extern "C" int abd_destroy(abd_ctx *ctx) {
   if (ctx->pinned) hipHostFree(ctx->pinned);
   if (ctx->pinned_nt) hipHostFree(ctx->pinned_nt);
   if (ctx->mirror_h) hipHostFree(ctx->mirror_h);
-  if (ctx->lb_status) hipFree(ctx->lb_status);
+  for (auto &lb : ctx->lb)
+    if (lb.status) hipFree(lb.status);
+  if (ctx->aux_stream) hipStreamDestroy(ctx->aux_stream);
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   for (auto &e : ctx->ev)
     if (e) hipEventDestroy(e);
   prof_flush(ctx);

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -75,11 +76,18 @@ struct abd_ctx {
   // (read after the stream synchronises; allocated once, so its address
   // can be baked into captured graphs)
   int64_t *mirror_h = nullptr, *mirror_d = nullptr;
-  // look-back status words (shared by all look-back launches: every launch
-  // takes a new tag) and the tag of the last launch
-  unsigned long long *lb_status = nullptr;
-  int64_t lb_words = 0;
-  unsigned int lb_tag = 0;
+  // look-back status words and the tag of the last launch, one set per
+  // stream that scans (the call's stream, the auxiliary stream): launches on
+  // one stream run in order and each takes a new tag
+  struct LbState {
+    unsigned long long *status = nullptr;
+    int64_t words = 0;
+    unsigned int tag = 0;
+  } lb[2];
+  // auxiliary stream (default priority) for work that overlaps the call's
+  // stream inside one call, and the events that order the two
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev[8] = {};
   bool profiling = false;
   bool count_box_tests = false;  // (abd_profile mode 2)
@@ -236,10 +244,15 @@ struct KeyPattern {
 // and point-triangle-shaped pairs pt3 (joints); pat (may be NULL) receives
 // the keys' row structure when the dense path builds it (else pat->valid =
 // false)
+// (defer: only enqueue; *n_keys is then read by op_offdiag_count after the
+// caller has synchronised s)
 int op_offdiag(abd_ctx *ctx, const abd_scene *sc, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
                int32_t **keys, int64_t *n_keys, const char *tag, hipStream_t s, const int32_t *pt2 = nullptr,
                int64_t n_pt2 = 0, const int32_t *ee2 = nullptr, int64_t n_ee2 = 0, KeyPattern *pat = nullptr,
-               const int32_t *pt3 = nullptr, int64_t n_pt3 = 0);
+               const int32_t *pt3 = nullptr, int64_t n_pt3 = 0, bool defer = false);
+int op_offdiag_count(abd_ctx *ctx, int64_t *n_keys);
+// the auxiliary stream and its events (created on first use)
+int aux_stream_get(abd_ctx *ctx, hipStream_t *aux);
 // joints: the scene's tables (NULL when it has none); per-body energy
 // (added to e_items + t estride for trial t, q at q + t qstride), gradient
 // and diagonal blocks, times c = kappa_j w; off-diagonal blocks into off
@@ -249,11 +262,15 @@ int op_joint_body(abd_ctx *ctx, const abd_scene *sc, double c, const double *q, 
 int op_joint_off(abd_ctx *ctx, const abd_scene *sc, double c, const int32_t *keys, int64_t n_keys, double *off,
                  hipStream_t s);
 // barrier (and, when fr is given, the lagged friction of fr) energy,
-// gradient and Hessian blocks, assembled in one pass
+// gradient and Hessian blocks, assembled in one pass.  With join non-NULL
+// the keys, their count and off are not known yet: join supplies them after
+// the local kernels are enqueued and before the assembly (when there is
+// nothing to assemble it is not called).
+using BarrierJoin = std::function<int(const int32_t **keys, int64_t *n_keys, double **off)>;
 int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                int64_t n_pt, const int32_t *ee, int64_t n_ee, const int32_t *keys, int64_t n_keys, double *energy,
                double *grad, double *diag, double *off, int project, int64_t *n_active_pt, int64_t *n_active_ee,
-               hipStream_t s, const FrictionSet *fr = nullptr);
+               hipStream_t s, const FrictionSet *fr = nullptr, const BarrierJoin *join = nullptr);
 // fixed-order assembly of n local records (info, g_loc [n][12], H_loc
 // [n][78] packed symmetric) into grad / diag / off (accumulated)
 int op_assemble(abd_ctx *ctx, const abd_scene *sc, int64_t n, const PairInfo *info, const double *g_loc,

@@ -360,7 +360,7 @@ __global__ void k_energy_only(int64_t n_pt, int64_t n, const int32_t *pt, const 
 int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                int64_t n_pt, const int32_t *ee, int64_t n_ee, const int32_t *keys, int64_t n_keys, double *energy,
                double *grad, double *diag, double *off, int project, int64_t *n_active_pt, int64_t *n_active_ee,
-               hipStream_t s, const FrictionSet *fr) {
+               hipStream_t s, const FrictionSet *fr, const BarrierJoin *join) {
   const int64_t n = n_pt + n_ee;
   const int64_t nf = fr ? fr->n() : 0;
   if (n_active_pt) *n_active_pt = 0;
@@ -421,6 +421,7 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   }
   if (nf > 0) ABD_TRY(op_friction_local(ctx, sc, fr, x, e_loc + na, g_loc + 12 * na, H_loc + 78 * na, info + na, s));
   if (energy) ABD_TRY(reduce_sum_f64(ctx, e_loc, nl, energy, s));
+  if (join) ABD_TRY((*join)(&keys, &n_keys, &off));
   if (!grad && !diag && !off) return ABD_OK;
   return op_assemble(ctx, sc, nl, info, g_loc, H_loc, keys, n_keys, grad, diag, off, s);
 }

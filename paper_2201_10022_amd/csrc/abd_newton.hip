@@ -298,16 +298,45 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   else
     ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s, done_dev));
   ctx->sw_valid = false;
-  // the pattern covers the candidates and the lagged friction pairs
+  // The pattern (it covers the candidates and the lagged friction pairs) is
+  // built on the auxiliary stream while this stream runs the body terms and
+  // the barrier's pair kernels, which do not read it; the assembly waits for
+  // it (join below).
   KeyPattern pat;
-  ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", s, fr ? fr->pt : nullptr, fr ? fr->n_pt : 0,
-                     fr ? fr->ee : nullptr, fr ? fr->n_ee : 0, &pat));
+  hipStream_t aux;
+  ABD_TRY(aux_stream_get(ctx, &aux));
+  {
+    // (cached scene tables that both streams read are made here, before
+    // the fork, so that their first build is ordered before every reader)
+    const int32_t *sbo;
+    ABD_TRY(op_scene_offsets(ctx, sc, &sbo, s));
+    JointTables *jt = nullptr;
+    if (sc->n_joints > 0) ABD_TRY(joint_tables(ctx, sc, &jt, s));
+  }
+  HIP_TRY(ctx, hipEventRecord(ctx->ev_fork, s));
+  HIP_TRY(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
+  ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", aux, fr ? fr->pt : nullptr, fr ? fr->n_pt : 0,
+                     fr ? fr->ee : nullptr, fr ? fr->n_ee : 0, &pat, nullptr, 0, true));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev_join, aux));
+  bool joined = false;
+  const BarrierJoin join = [&](const int32_t **keys_j, int64_t *nk_j, double **off_j) -> int {
+    if (!joined) {
+      HIP_TRY(ctx, hipStreamSynchronize(aux));
+      ABD_TRY(op_offdiag_count(ctx, &nk));
+      HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->ev_join, 0));
+      ABD_TRY(ws(ctx, "nt_off", 144 * (size_t)(nk + 1), &off, s));
+      ABD_TRY(zero4(ctx, off, 144 * nk, nullptr, 0, nullptr, 0, nullptr, 0, s));
+      joined = true;
+    }
+    if (keys_j) *keys_j = keys;
+    if (nk_j) *nk_j = nk;
+    if (off_j) *off_j = off;
+    return ABD_OK;
+  };
   st->n_pt = npt;
   st->n_ee = nee;
-  st->n_offdiag = nk;
   st->t_candidates_ms += ms_since(t0);
-  ABD_TRY(ws(ctx, "nt_off", 144 * (size_t)(nk + 1), &off, s));
-  ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, off, 144 * nk, nullptr, 0, s));
+  ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, nullptr, 0, nullptr, 0, s));
   // adaptive barrier stiffness: the doubling rule at this iterate, before
   // the barrier's derivatives and this iteration's energies
   if (ctx->kappa_sc) ABD_TRY(op_kappa_update(ctx, sc, prm, x, pt, npt, ee, nee, s));
@@ -315,7 +344,10 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   // (the energy at q comes with the line search's trials: none is summed here)
   ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, nullptr, g, diag, 1, s));
   int64_t nap = 0, nae = 0;
-  ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, keys, nk, nullptr, g, diag, off, 1, &nap, &nae, s, fr));
+  ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, nullptr, 0, nullptr, g, diag, nullptr, 1, &nap, &nae, s, fr,
+                     &join));
+  ABD_TRY(join(nullptr, nullptr, nullptr));  // (when the barrier had nothing to assemble)
+  st->n_offdiag = nk;
   if (sc->n_joints > 0 && prm->kappa_j > 0.0)
     ABD_TRY(op_joint_off(ctx, sc, prm->kappa_j * prm->dt * prm->dt, keys, nk, off, s));
   st->t_barrier_ms += ms_since(t0);

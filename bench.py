@@ -58,7 +58,7 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 # back to 12x12 2,106: 12,300 (point-triangle) to 13,200 (edge-edge).
 BARRIER_FLOP_PER_PAIR = 12700.0
 # Algorithmic bytes per CCD pair: pair ids, the 4 vertex ids and the 4
-# vertices' positions and displacements.
+# vertices' positions at the start and the end of the step.
 ACCD_BYTES_PER_PAIR = 8 + 16 + 4 * 48
 
 

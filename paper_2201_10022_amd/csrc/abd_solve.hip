@@ -140,7 +140,7 @@ __global__ void k_tkeys(int64_t nk, const int32_t *keys, uint64_t *tk, uint32_t 
 
 constexpr int PB = 192;  // init / update: 16 bodies x 12 rows per block
 constexpr int PBB = PB / 12;
-constexpr int SWB = 256;  // spmv: one 64-lane wave per body, 4 bodies per block
+constexpr int SWB = 256;  // SpMV-shaped blocks: four 64-lane waves
 constexpr int SWBB = SWB / 64;
 constexpr int CBB = 5 * SWBB;  // SpMV-shaped kernels: five bodies per wave, 12 lanes each
 

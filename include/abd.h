@@ -129,7 +129,9 @@ typedef struct abd_params {
 
 /* Per-iteration statistics (host struct). */
 typedef struct abd_stats {
-  int64_t n_pt, n_ee;             /* candidates at the current iterate */
+  int64_t n_pt, n_ee;             /* pairs tested for activity at the current
+                                     iterate: the last accepted step's swept
+                                     candidates, else the candidates at it */
   int64_t n_active_pt, n_active_ee;
   int64_t n_pt_swept, n_ee_swept; /* candidates over the step's sweep */
   int64_t n_offdiag;              /* off-diagonal blocks of the system */

@@ -262,15 +262,24 @@ int op_joint_body(abd_ctx *ctx, const abd_scene *sc, double c, const double *q, 
 int op_joint_off(abd_ctx *ctx, const abd_scene *sc, double c, const int32_t *keys, int64_t n_keys, double *off,
                  hipStream_t s);
 // barrier (and, when fr is given, the lagged friction of fr) energy,
-// gradient and Hessian blocks, assembled in one pass.  With join non-NULL
-// the keys, their count and off are not known yet: join supplies them after
-// the local kernels are enqueued and before the assembly (when there is
-// nothing to assemble it is not called).
-using BarrierJoin = std::function<int(const int32_t **keys, int64_t *n_keys, double **off)>;
+// gradient and Hessian blocks, assembled in one pass.  Hooks (may be NULL):
+// `active` runs once the active pairs are known (act [na]: indices into
+// the list PT then EE, the na_pt PT pairs first; valid on s), before the
+// pair kernels are enqueued; `join` supplies keys, their count and off
+// (then not known at the call) after the pair kernels are enqueued and
+// before the assembly.  Neither runs when there is nothing to assemble.
+struct BarrierHooks {
+  std::function<int(const int32_t *act, int64_t na, int64_t na_pt)> active;
+  std::function<int(const int32_t **keys, int64_t *n_keys, double **off)> join;
+};
 int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                int64_t n_pt, const int32_t *ee, int64_t n_ee, const int32_t *keys, int64_t n_keys, double *energy,
                double *grad, double *diag, double *off, int project, int64_t *n_active_pt, int64_t *n_active_ee,
-               hipStream_t s, const FrictionSet *fr = nullptr, const BarrierJoin *join = nullptr);
+               hipStream_t s, const FrictionSet *fr = nullptr, const BarrierHooks *hooks = nullptr);
+// the active pairs act [na] (as the hook above receives them) gathered into
+// pair lists: PT [na_pt][2], then EE [na - na_pt][2] (context workspace)
+int op_gather_active(abd_ctx *ctx, const int32_t *act, int64_t na, int64_t na_pt, int64_t n_pt, const int32_t *pt,
+                     const int32_t *ee, int32_t **pt_out, int32_t **ee_out, hipStream_t s);
 // fixed-order assembly of n local records (info, g_loc [n][12], H_loc
 // [n][78] packed symmetric) into grad / diag / off (accumulated)
 int op_assemble(abd_ctx *ctx, const abd_scene *sc, int64_t n, const PairInfo *info, const double *g_loc,

@@ -357,10 +357,33 @@ __global__ void k_energy_only(int64_t n_pt, int64_t n, const int32_t *pt, const 
 
 }  // namespace
 
+namespace {
+__global__ void k_gather_active(int64_t na, int64_t na_pt, int64_t n_pt, const int32_t *act, const int32_t *pt,
+                                const int32_t *ee, int32_t *pt_out, int32_t *ee_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= na) return;
+  const int64_t k = act[i];
+  const int32_t *src = k < n_pt ? pt + 2 * k : ee + 2 * (k - n_pt);
+  int32_t *dst = i < na_pt ? pt_out + 2 * i : ee_out + 2 * (i - na_pt);
+  dst[0] = src[0];
+  dst[1] = src[1];
+}
+}  // namespace
+
+int op_gather_active(abd_ctx *ctx, const int32_t *act, int64_t na, int64_t na_pt, int64_t n_pt, const int32_t *pt,
+                     const int32_t *ee, int32_t **pt_out, int32_t **ee_out, hipStream_t s) {
+  ABD_TRY(ws(ctx, "ba_pt", 2 * (size_t)na_pt + 2, pt_out, s));
+  ABD_TRY(ws(ctx, "ba_ee", 2 * (size_t)(na - na_pt) + 2, ee_out, s));
+  if (na > 0)
+    hipLaunchKernelGGL(k_gather_active, dim3(grid_for(na, 256)), dim3(256), 0, s, na, na_pt, n_pt, act, pt, ee,
+                       *pt_out, *ee_out);
+  return abd_hip_check(ctx, hipGetLastError(), "k_gather_active");
+}
+
 int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                int64_t n_pt, const int32_t *ee, int64_t n_ee, const int32_t *keys, int64_t n_keys, double *energy,
                double *grad, double *diag, double *off, int project, int64_t *n_active_pt, int64_t *n_active_ee,
-               hipStream_t s, const FrictionSet *fr, const BarrierJoin *join) {
+               hipStream_t s, const FrictionSet *fr, const BarrierHooks *hooks) {
   const int64_t n = n_pt + n_ee;
   const int64_t nf = fr ? fr->n() : 0;
   if (n_active_pt) *n_active_pt = 0;
@@ -395,6 +418,7 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   if (n_active_ee) *n_active_ee = na - na_pt;
   const int64_t nl = na + nf;  // local records: active barrier pairs, then friction pairs
   if (nl == 0) return ABD_OK;
+  if (hooks && hooks->active) ABD_TRY(hooks->active(act, na, na_pt));
 
   double *e_loc, *g_loc, *H_loc;
   PairInfo *info;
@@ -421,7 +445,7 @@ int op_barrier(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const d
   }
   if (nf > 0) ABD_TRY(op_friction_local(ctx, sc, fr, x, e_loc + na, g_loc + 12 * na, H_loc + 78 * na, info + na, s));
   if (energy) ABD_TRY(reduce_sum_f64(ctx, e_loc, nl, energy, s));
-  if (join) ABD_TRY((*join)(&keys, &n_keys, &off));
+  if (hooks && hooks->join) ABD_TRY(hooks->join(&keys, &n_keys, &off));
   if (!grad && !diag && !off) return ABD_OK;
   return op_assemble(ctx, sc, nl, info, g_loc, H_loc, keys, n_keys, grad, diag, off, s);
 }

@@ -288,20 +288,35 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   // gradient and projected Hessian at q
   auto t0 = std::chrono::steady_clock::now();
   ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
-  int32_t *pt, *ee, *keys;
-  int64_t npt, nee, nk;
-  // scenes already done take no part (their direction is zero); after an
-  // accepted step the candidates come from that step's sweep
-  if (reuse_sweep && ctx->sw_valid)
-    ABD_TRY(op_candidates_within(ctx, sc, x, prm->dhat, ctx->sw_pt, ctx->sw_n_pt, ctx->sw_ee, ctx->sw_n_ee, &pt, &npt,
-                                 &ee, &nee, "nt_st", s));
-  else
-    ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &pt, &npt, &ee, &nee, "nt_st", s, done_dev));
+  const int32_t *pt, *ee;
+  int32_t *keys = nullptr;
+  int64_t npt, nee, nk = 0;
+  // The pairs whose activity is tested: after an accepted step, that step's
+  // swept candidates (every pair within dhat at x lies in the sweep, since x
+  // is on the swept segment, and the active pairs come out in the same
+  // canonical order as from the static candidates at x); otherwise the
+  // static candidates at x.  Scenes already done take no part (their
+  // direction is zero).
+  if (reuse_sweep && ctx->sw_valid) {
+    pt = ctx->sw_pt;
+    npt = ctx->sw_n_pt;
+    ee = ctx->sw_ee;
+    nee = ctx->sw_n_ee;
+  } else {
+    int32_t *cpt, *cee;
+    ABD_TRY(op_candidates(ctx, sc, x, nullptr, prm->dhat, &cpt, &npt, &cee, &nee, "nt_st", s, done_dev));
+    pt = cpt;
+    ee = cee;
+  }
   ctx->sw_valid = false;
-  // The pattern (it covers the candidates and the lagged friction pairs) is
-  // built on the auxiliary stream while this stream runs the body terms and
-  // the barrier's pair kernels, which do not read it; the assembly waits for
-  // it (join below).
+  st->n_pt = npt;
+  st->n_ee = nee;
+  st->t_candidates_ms += ms_since(t0);
+  // The off-diagonal pattern covers the active pairs (the only pairs with
+  // Hessian blocks), the lagged friction pairs and the joints.  It is built
+  // on the auxiliary stream, from the moment the active pairs are known,
+  // while this stream runs the barrier's pair kernels, which do not read
+  // it; the assembly joins it.
   KeyPattern pat;
   hipStream_t aux;
   ABD_TRY(aux_stream_get(ctx, &aux));
@@ -313,13 +328,21 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     JointTables *jt = nullptr;
     if (sc->n_joints > 0) ABD_TRY(joint_tables(ctx, sc, &jt, s));
   }
-  HIP_TRY(ctx, hipEventRecord(ctx->ev_fork, s));
-  HIP_TRY(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
-  ABD_TRY(op_offdiag(ctx, sc, pt, npt, ee, nee, &keys, &nk, "nt_st", aux, fr ? fr->pt : nullptr, fr ? fr->n_pt : 0,
-                     fr ? fr->ee : nullptr, fr ? fr->n_ee : 0, &pat, nullptr, 0, true));
-  HIP_TRY(ctx, hipEventRecord(ctx->ev_join, aux));
-  bool joined = false;
-  const BarrierJoin join = [&](const int32_t **keys_j, int64_t *nk_j, double **off_j) -> int {
+  bool forked = false, joined = false;
+  BarrierHooks hooks;
+  hooks.active = [&](const int32_t *act, int64_t na, int64_t na_pt) -> int {
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_fork, s));
+    HIP_TRY(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
+    int32_t *apt, *aee;
+    ABD_TRY(op_gather_active(ctx, act, na, na_pt, npt, pt, ee, &apt, &aee, aux));
+    ABD_TRY(op_offdiag(ctx, sc, apt, na_pt, aee, na - na_pt, &keys, &nk, "nt_st", aux, fr ? fr->pt : nullptr,
+                       fr ? fr->n_pt : 0, fr ? fr->ee : nullptr, fr ? fr->n_ee : 0, &pat, nullptr, 0, true));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_join, aux));
+    forked = true;
+    return ABD_OK;
+  };
+  hooks.join = [&](const int32_t **keys_j, int64_t *nk_j, double **off_j) -> int {
+    if (!forked) ABD_TRY(hooks.active(nullptr, 0, 0));  // (no active pairs to hand over)
     if (!joined) {
       HIP_TRY(ctx, hipStreamSynchronize(aux));
       ABD_TRY(op_offdiag_count(ctx, &nk));
@@ -333,9 +356,6 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     if (off_j) *off_j = off;
     return ABD_OK;
   };
-  st->n_pt = npt;
-  st->n_ee = nee;
-  st->t_candidates_ms += ms_since(t0);
   ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, nullptr, 0, nullptr, 0, s));
   // adaptive barrier stiffness: the doubling rule at this iterate, before
   // the barrier's derivatives and this iteration's energies
@@ -345,8 +365,8 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, nullptr, g, diag, 1, s));
   int64_t nap = 0, nae = 0;
   ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, nullptr, 0, nullptr, g, diag, nullptr, 1, &nap, &nae, s, fr,
-                     &join));
-  ABD_TRY(join(nullptr, nullptr, nullptr));  // (when the barrier had nothing to assemble)
+                     &hooks));
+  ABD_TRY(hooks.join(nullptr, nullptr, nullptr));  // (when the barrier had nothing to assemble)
   st->n_offdiag = nk;
   if (sc->n_joints > 0 && prm->kappa_j > 0.0)
     ABD_TRY(op_joint_off(ctx, sc, prm->kappa_j * prm->dt * prm->dt, keys, nk, off, s));

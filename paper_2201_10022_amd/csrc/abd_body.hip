@@ -647,7 +647,7 @@ int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int
 
 int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                           const double *qt, int n_trials, double *energy, hipStream_t s, double *items,
-                          int64_t estride) {
+                          int64_t estride, TrialSums *defer) {
   const int nb = sc->n_bodies;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   if (nb <= 0 || n_trials <= 0) return ABD_OK;
@@ -662,6 +662,10 @@ int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
     ABD_TRY(op_joint_body(ctx, sc, prm->kappa_j * prm->dt * prm->dt, q, n_trials, 12 * (int64_t)nb, eb,
                           items ? estride : (int64_t)nb, nullptr, nullptr, s));
   if (items) return ABD_OK;
+  if (defer) {
+    defer->seg[defer->k++] = TrialSeg{eb, nb, nb, sc->body_scene};
+    return ABD_OK;
+  }
   return seg_sum_trials(ctx, eb, nb, nb, sc->body_scene, n_trials, S, energy, s);
 }
 

@@ -512,6 +512,31 @@ __global__ void __launch_bounds__(SB) k_seg_reduce_trials(const double *vals, in
   }
 }
 
+// Several segments per (trial, scene) block, each reduced exactly as
+// k_seg_reduce_trials reduces it, accumulated in segment order.
+__global__ void __launch_bounds__(SB) k_seg_reduce_trials_multi(TrialSums ts, int S, double *out) {
+  __shared__ double sh[SB / 64];
+  const int t = blockIdx.x / S, s = blockIdx.x % S;
+  double acc = 0.0;
+  for (int j = 0; j < ts.k; ++j) {
+    const TrialSeg g = ts.seg[j];
+    const int64_t lo = lower_bound_i32(g.keys, g.n, s), hi = lower_bound_i32(g.keys, g.n, s + 1);
+    const double *v = g.vals + (int64_t)t * g.stride;
+    double a = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += SB) a += v[i];
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r = sh[0];
+      for (int w = 1; w < SB / 64; ++w) r += sh[w];
+      acc += r;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
 // One scene: per trial, blocks of TRB*4 items into partials, then one
 // block per trial folds them (both in fixed order).
 constexpr int TRB = 256;
@@ -564,6 +589,14 @@ int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, 
   hipLaunchKernelGGL(k_trial_pass, dim3(nblk, n_trials), dim3(TRB), 0, s, vals, stride, n, part);
   hipLaunchKernelGGL(k_trial_final, dim3(n_trials), dim3(TRB), 0, s, part, nblk, out_accum, assign ? 1 : 0);
   return abd_hip_check(ctx, hipGetLastError(), "k_trial_pass");
+}
+
+int seg_sum_trials_multi(abd_ctx *ctx, const TrialSums &ts, int n_trials, int n_scenes, double *out,
+                         hipStream_t s) {
+  if (n_trials <= 0) return ABD_OK;
+  if (n_scenes <= 1) return abd_fail(ctx, ABD_E_INVALID, "seg_sum_trials_multi: needs several scenes");
+  hipLaunchKernelGGL(k_seg_reduce_trials_multi, dim3(n_trials * n_scenes), dim3(SB), 0, s, ts, n_scenes, out);
+  return abd_hip_check(ctx, hipGetLastError(), "k_seg_reduce_trials_multi");
 }
 
 bool scene_table_cached(abd_ctx *ctx, const abd_scene *sc, const char *name, const void *buf) {

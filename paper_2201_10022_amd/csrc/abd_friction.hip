@@ -627,7 +627,8 @@ int op_friction_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const FrictionS
 }
 
 int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
-                              int n_trials, double *energy, hipStream_t s, double *items, int64_t estride) {
+                              int n_trials, double *energy, hipStream_t s, double *items, int64_t estride,
+                              TrialSums *defer) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int64_t n = fr->n();
   if (n == 0 || n_trials <= 0) return ABD_OK;
@@ -641,6 +642,11 @@ int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionS
                      items ? estride : 0);
   HIP_TRY(ctx, hipGetLastError());
   if (items) return ABD_OK;
+  if (defer) {
+    if (fr->n_pt) defer->seg[defer->k++] = TrialSeg{e, n, fr->n_pt, key};
+    if (fr->n_ee) defer->seg[defer->k++] = TrialSeg{e + fr->n_pt, n, fr->n_ee, key + fr->n_pt};
+    return ABD_OK;
+  }
   if (fr->n_pt) ABD_TRY(seg_sum_trials(ctx, e, n, fr->n_pt, key, n_trials, S, energy, s));
   if (fr->n_ee) ABD_TRY(seg_sum_trials(ctx, e + fr->n_pt, n, fr->n_ee, key + fr->n_pt, n_trials, S, energy, s));
   return ABD_OK;

@@ -594,15 +594,34 @@ int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, doubl
 // items + t estride) and sums nothing.
 int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int n_trials, double *x,
                          hipStream_t s);
+// With defer non-NULL (several scenes) an op writes its per-item energies
+// and their scenes and appends the segments to *defer instead of summing;
+// seg_sum_trials_multi then sums every segment in one launch.
+struct TrialSeg {
+  const double *vals;  // trial t's items at vals + t stride
+  int64_t stride, n;
+  const int32_t *keys;  // non-decreasing item scenes
+};
+struct TrialSums {
+  TrialSeg seg[5];
+  int k = 0;
+};
 int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                           const double *qt, int n_trials, double *energy, hipStream_t s, double *items = nullptr,
-                          int64_t estride = 0);
+                          int64_t estride = 0, TrialSums *defer = nullptr);
 int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                              int n_trials, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
-                             double *energy, hipStream_t s, double *items = nullptr, int64_t estride = 0);
+                             double *energy, hipStream_t s, double *items = nullptr, int64_t estride = 0,
+                             TrialSums *defer = nullptr);
 int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
                               int n_trials, double *energy, hipStream_t s, double *items = nullptr,
-                              int64_t estride = 0);
+                              int64_t estride = 0, TrialSums *defer = nullptr);
+// out[t S + scene] = the sum, segment after segment in order, of each
+// segment's sum over the scene's items (each in the fixed order of
+// seg_sum_trials, so the result equals accumulating the segments one by
+// one into zeros); n_scenes > 1
+int seg_sum_trials_multi(abd_ctx *ctx, const TrialSums &ts, int n_trials, int n_scenes, double *out,
+                         hipStream_t s);
 int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, const int32_t *keys, int n_trials,
                    int n_scenes, double *out_accum, hipStream_t s,
                    bool assign = false);

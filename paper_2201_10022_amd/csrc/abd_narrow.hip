@@ -531,7 +531,7 @@ int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params
 
 int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                              int n_trials, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
-                             double *energy, hipStream_t s, double *items, int64_t estride) {
+                             double *energy, hipStream_t s, double *items, int64_t estride, TrialSums *defer) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int64_t n = n_pt + n_ee;
   if (n == 0 || n_trials <= 0) return ABD_OK;
@@ -548,6 +548,11 @@ int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params
   HIP_TRY(ctx, hipGetLastError());
   if (items) return ABD_OK;
   // PT and EE lists are each ordered by scene
+  if (defer) {
+    if (n_pt) defer->seg[defer->k++] = TrialSeg{e, n, n_pt, key};
+    if (n_ee) defer->seg[defer->k++] = TrialSeg{e + n_pt, n, n_ee, key + n_pt};
+    return ABD_OK;
+  }
   if (n_pt) ABD_TRY(seg_sum_trials(ctx, e, n, n_pt, key, n_trials, S, energy, s));
   if (n_ee) ABD_TRY(seg_sum_trials(ctx, e + n_pt, n, n_ee, key + n_pt, n_trials, S, energy, s));
   return ABD_OK;

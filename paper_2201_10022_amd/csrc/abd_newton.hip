@@ -209,8 +209,9 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
   double *qn, *xn = nullptr;
   ABD_TRY(ws(ctx, "ls_q", (size_t)n * n12, &qn, s));
   if (fr) ABD_TRY(ws(ctx, "ls_x", (size_t)n * 3 * sc->n_verts, &xn, s));
-  // (one scene with items: the row sums below are assigned, not added)
-  if (S > 1 || (int64_t)nb + npt + nee + (fr ? fr->n() : 0) == 0) ABD_TRY(zero(ctx, e_dev, (int64_t)n * S, s));
+  // (one scene with items: the row sums below are assigned, not added; a
+  // batch's per-scene sums are assigned by one launch over all segments)
+  if (S == 1 && (int64_t)nb + npt + nee + (fr ? fr->n() : 0) == 0) ABD_TRY(zero(ctx, e_dev, (int64_t)n, s));
   {
     const int nqb = (int)grid_for(n12, 256);
     const int nvb = fr ? (int)grid_for(sc->n_verts, 256) : 0;
@@ -219,10 +220,11 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
     HIP_TRY(ctx, hipGetLastError());
   }
   if (S > 1) {
-    ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, e_dev, s));
-    ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, qn, n, pt, npt, ee, nee, e_dev, s));
-    if (fr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, e_dev, s));
-    return ABD_OK;
+    TrialSums ts;
+    ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, e_dev, s, nullptr, 0, &ts));
+    ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, qn, n, pt, npt, ee, nee, e_dev, s, nullptr, 0, &ts));
+    if (fr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, e_dev, s, nullptr, 0, &ts));
+    return seg_sum_trials_multi(ctx, ts, n, S, e_dev, s);
   }
   // one scene: every item's energy of a trial in one row (bodies, barrier
   // pairs, friction pairs), one sum per row

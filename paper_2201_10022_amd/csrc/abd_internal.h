@@ -329,9 +329,21 @@ int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, con
 // x0 (may be NULL = 0, may alias p): initial guess
 // pre_diag: preconditioner blocks (NULL: diag); pat: the keys' row
 // structure if already built (else built here)
+// pre_sync (may be NULL) is enqueued after the iterations queued in a
+// round, before the host synchronises to read the solver's state; it gets
+// that state on the device (int[4]: iteration base, scenes stopped, largest
+// final count, scenes stopped by the cap or a breakdown).  *pre_sync_final
+// (may be NULL) tells whether its last enqueue followed the solve's final
+// iterations with nothing changing p afterwards.
+using PcgHook = std::function<int(const int *cg_state)>;
+// relative tolerance at and above which a one-kernel solve whose scenes all
+// stopped on the tolerance skips the residual check (nothing then changes
+// its result after the last iterations)
+constexpr double PCG_CHECK_RTOL = 1e-6;
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *p, double rtol, int max_iter, int *iters, hipStream_t s,
-           const double *x0 = nullptr, const double *pre_diag = nullptr, const KeyPattern *pat = nullptr);
+           const double *x0 = nullptr, const double *pre_diag = nullptr, const KeyPattern *pat = nullptr,
+           const PcgHook *pre_sync = nullptr, bool *pre_sync_final = nullptr);
 // preconditioned MINRES on the (possibly indefinite) symmetric block matrix,
 // block-Jacobi preconditioner from the SPD diagonal blocks pre_diag; stops
 // at |r|_{P} <= rtol |b|_{P} (syncs every iteration)

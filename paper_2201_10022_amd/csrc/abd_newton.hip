@@ -126,10 +126,14 @@ __global__ void k_step_scenes(int nb, const int32_t *body_scene, const double *a
   if (al != 0.0) q[i] = fma(al, p[i], q[i]);
 }
 // newly converged scenes: done[j] |= disp[j stride] <= tol (the host takes
-// the same decision on the same values for its own copy of the flags)
-__global__ void k_done_update(int S, const double *disp, int stride, double tol, uint8_t *done) {
+// the same decision on the same values for its own copy of the flags).
+// With cg_state (the solver's state, int[4]) only when the solve that made
+// the direction has stopped every scene on its tolerance.
+__global__ void k_done_update(int S, const double *disp, int stride, double tol, uint8_t *done,
+                              const int *cg_state) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= S || done[j]) return;
+  if (cg_state && !(cg_state[1] >= S && cg_state[3] == 0)) return;
   if (disp[(int64_t)stride * j] <= tol) done[j] = 1;
 }
 // the first line-search batch's decision per scene: alpha[j] = the first
@@ -385,22 +389,35 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   // (errors of the assembly and the solve are read with the displacement:
   // a failed assembly or block inverse leaves non-finite values that stop
   // the solve at once)
-  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s, nullptr, nullptr, &pat));
-  st->pcg_iters = its;
-  st->t_solve_ms += ms_since(t0);
-  const double *dsp_first;
-  int dsp_stride;
-  {
-    ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, &dsp_first, &dsp_stride, s));
+  // The displacement pass (per-scene max |J p|, errors, the done flags) is
+  // enqueued behind each round of PCG replays, before the solver's own
+  // synchronisation; its results stand when that round was the solve's
+  // last (the flags change only then), else it runs again here.
+  const double tol_disp = prm->newton_tol * prm->dt;
+  auto disp_pass = [&](const int *cg_state) -> int {
+    const double *dsp;
+    int dstride;
+    ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, &dsp, &dstride, s));
     int *errf;
     ABD_TRY(ws(ctx, "err_flag", 1, &errf, s));
-    hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, dsp_first, S, nullptr, 0, errf, d_disp, nullptr, d_err,
-                       dsp_stride);
+    hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, dsp, S, nullptr, 0, errf, d_disp, nullptr, d_err,
+                       dstride);
+    hipLaunchKernelGGL(k_done_update, dim3(grid_for(S, 256)), dim3(256), 0, s, S, dsp, dstride, tol_disp, done_dev,
+                       cg_state);
+    return abd_hip_check(ctx, hipGetLastError(), "k_done_update");
+  };
+  // (below the check's tolerance the direction may change after the last
+  // iterations: no early pass)
+  const PcgHook pre_sync = disp_pass;
+  bool disp_done = false;
+  ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s, nullptr, nullptr, &pat,
+                 prm->pcg_rtol >= PCG_CHECK_RTOL ? &pre_sync : nullptr, &disp_done));
+  st->pcg_iters = its;
+  st->t_solve_ms += ms_since(t0);
+  if (!disp_done) {
+    ABD_TRY(disp_pass(nullptr));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
   }
-  const double tol_disp = prm->newton_tol * prm->dt;
-  hipLaunchKernelGGL(k_done_update, dim3(grid_for(S, 256)), dim3(256), 0, s, S, dsp_first, dsp_stride, tol_disp,
-                     done_dev);
-  HIP_TRY(ctx, hipStreamSynchronize(s));
   ABD_TRY(err_check(ctx, h_err[0], s));
   double dmax = 0.0;
   int n_active = 0;

@@ -639,6 +639,7 @@ struct CgState {
   int max_final;  // largest iteration count of a stopped scene
   int n_bad;      // scenes stopped by the iteration cap or a breakdown, not by the tolerance
 };
+static_assert(sizeof(CgState) == 4 * sizeof(int), "the pre-sync hook reads the state as int[4]");
 
 __device__ __forceinline__ void cg_step(double r, double w, double s_prev, double alpha, double beta, double &s_new,
                                         double &r_new) {
@@ -1107,7 +1108,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
              const double *inv, const double *rhs, const double *x0, const double *Hx0, double *x_out,
              const PcgBlk *ublk, int nblk_u, const int32_t *s_scene, const int64_t *s_off, const int32_t *sbo,
              const int64_t *eoff, const int2 *ent, int nblk_c, double rtol2, int max_iter, int *iters,
-             hipStream_t s, int *n_bad) {
+             hipStream_t s, int *n_bad, const PcgHook *pre_sync) {
   const int iter_g[2] = {ctx->tune.pcg_short, ctx->tune.pcg_long};
   double *rv[2], *wv[2], *sv[2], *pt[2], *u, *p;
   PcgBlk *cblk;
@@ -1219,6 +1220,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
       planned += iter_g[gi];
       ++round;
     } while (round < max_rounds && ctx->pcg_hint - (done + planned) >= iter_g[0]);
+    if (pre_sync) ABD_TRY((*pre_sync)(reinterpret_cast<const int *>(st)));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     all = hst[1] >= S;
     done = all ? hst[2] : hst[0];  // iterations: the largest count over the scenes
@@ -1245,7 +1247,9 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
 
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *x_out, double rtol, int max_iter, int *iters, hipStream_t s,
-           const double *x0, const double *pre_diag, const KeyPattern *pat) {
+           const double *x0, const double *pre_diag, const KeyPattern *pat, const PcgHook *pre_sync,
+           bool *pre_sync_final) {
+  if (pre_sync_final) *pre_sync_final = false;
   const int nb = sc->n_bodies;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int iter_g[2] = {ctx->tune.pcg_short, ctx->tune.pcg_long};
@@ -1373,14 +1377,16 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   if (one_kernel) {
     int n_bad = 0;
     ABD_TRY(cg_solve(ctx, sc, S, nb, n_keys, diag, off, keys, tv2, lo_beg, hi_beg, inv, rhs, x0, Hx0, x_out, ublk,
-                     nblk_u, s_scene, s_off, sbo, eoff, ent, nblk_c, rtol2, max_iter, &it0, s, &n_bad));
+                     nblk_u, s_scene, s_off, sbo, eoff, ent, nblk_c, rtol2, max_iter, &it0, s, &n_bad,
+                     pre_sync));
     // At a tolerance of 1e-6 or looser, a recursive residual that drifted
     // by the one-reduction form's rounding (about 1e-12 of |b|) cannot turn
     // a stop on the tolerance into a wrong one, so when every scene stopped
     // on it the check below is skipped.
-    if (rtol >= 1e-6 && n_bad == 0) {
+    if (rtol >= PCG_CHECK_RTOL && n_bad == 0) {
       *iters = it0;
       ctx->pcg_hint = it0;
+      if (pre_sync_final) *pre_sync_final = pre_sync != nullptr;
       return ABD_OK;
     }
     // The one-reduction recurrences may stop on a recursive residual that

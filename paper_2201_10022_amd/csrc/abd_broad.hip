@@ -293,17 +293,39 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
                                                     const double *bb, const float *vb32, const int32_t *tris,
                                                     const int32_t *edges, int32_t *lists, int64_t *list_start,
                                                     int32_t *list_len, int64_t *tiles_pt, int64_t *tiles_ee,
-                                                    int trows, float *crec, double *tests) {
+                                                    int trows, float *crec, double *tests, const int64_t *nbp_dev,
+                                                    int64_t cap_lists) {
   const int64_t p = blockIdx.x;
   const int sub = blockIdx.y;
-  const int a = bpairs[2 * p], b = bpairs[2 * p + 1];
+  const int lane = threadIdx.x;
+  // (the grid covers a capacity: slots past the device count, and body
+  // pairs whose lists would end past the list capacity, which the caller
+  // detects from the total and repeats at the exact size, record no tiles)
+  bool skip = p >= *nbp_dev;
+  int a = 0, b = 0;
+  if (!skip) {
+    a = bpairs[2 * p];
+    b = bpairs[2 * p + 1];
+  }
   const int la = voff[a + 1] - voff[a], lb = voff[b + 1] - voff[b];
   const int ta = toff[a + 1] - toff[a], tb = toff[b + 1] - toff[b];
-  const int ea = eoff[a + 1] - eoff[a];
+  const int ea = eoff[a + 1] - eoff[a], eb = eoff[b + 1] - eoff[b];
   // list starts inside the body pair's region (capacities rounded to 64)
   const int64_t s1 = round64(la), s2 = s1 + round64(tb), s3 = s2 + round64(lb), s4 = s3 + round64(ta),
                 s5 = s4 + round64(ea);
-  const int lane = threadIdx.x;
+  skip = skip || region[p] + s5 + round64(eb) > cap_lists;
+  if (skip) {
+    if (lane == 0) {
+      list_len[6 * p + 2 * sub] = 0;
+      list_len[6 * p + 2 * sub + 1] = 0;
+      if (sub < 2)
+        tiles_pt[2 * p + sub] = 0;
+      else
+        tiles_ee[p] = 0;
+      if (tests) tests[3 * p + sub] = 0.0;
+    }
+    return;
+  }
   int len[2], pkh[2];
   int64_t sth[2];
 #pragma unroll
@@ -628,62 +650,56 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   hbuf += MIR_BROAD;
   hbuf_d += MIR_BROAD;
   ABD_TRY(scan_exclusive_i64(ctx, bcnt, boff, nb, btot, s, hbuf_d));
-  // Body pairs and their list regions are sized by the last call's count
-  // (with room to grow) so that one synchronisation reads both totals; a
-  // count beyond the capacity repeats the two steps at the exact size.
-  const std::string key_bp = std::string(tag) + "_bp";
-  int64_t cap_bp = ctx->cap_hint[key_bp];
-  cap_bp = cap_bp + cap_bp / 4 + 256;
+  // Body pairs, their list regions and the culled lists are sized by the
+  // last call's counts (with room to grow); the search's one
+  // synchronisation, after the tile counts, reads every total, and a count
+  // beyond its capacity repeats the search from here at the exact sizes.
+  const std::string key_bp = std::string(tag) + "_bp", key_lt = std::string(tag) + "_lt";
+  // (twice the last counts: contact counts rise step after step while
+  // bodies land, and an overflow repeats the whole search)
+  int64_t cap_bp = ctx->cap_hint[key_bp], cap_lt = ctx->cap_hint[key_lt];
+  cap_bp = 2 * cap_bp + 256;
+  cap_lt = 2 * cap_lt + 4096;
   int64_t nbp = 0, list_total = 0;
+  const int trows = ctx->tune.tile_rows;
+  for (int attempt = 0;; ++attempt) {
   int32_t *bpairs;
   int64_t *cap, *region, *rtot = btot + 1;
-  for (int pass = 0;; ++pass) {
-    ABD_TRY(ws(ctx, "bp_pairs", 2 * cap_bp + 2, &bpairs, s));
-    ABD_TRY(ws(ctx, "bp_cap", cap_bp + 1, &cap, s));
-    ABD_TRY(ws(ctx, "bp_region", cap_bp + 1, &region, s));
-    hipLaunchKernelGGL(k_body_pairs<1>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
-                       skip_scene, nullptr, boff, bpairs, cap_bp);
-    hipLaunchKernelGGL(k_list_caps, dim3(grid_for(cap_bp, 256)), dim3(256), 0, s, cap_bp, btot, bpairs,
-                       sc->body_vert_off, sc->body_tri_off, sc->body_edge_off, cap, involved);
-    ABD_TRY(scan_exclusive_i64(ctx, cap, region, cap_bp, rtot, s, hbuf_d + 1));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    nbp = hbuf[0];
-    list_total = hbuf[1];
-    ABD_TRY(mirror_counts_ok(ctx, {nbp, list_total}, "candidates"));
-    if (nbp <= cap_bp) break;
-    if (pass > 0) return abd_fail(ctx, ABD_E_INVALID, "candidates: body-pair count changed between passes");
-    cap_bp = nbp;
-  }
-  ctx->cap_hint[key_bp] = nbp;
-  if (nbp == 0) return ABD_OK;
+  ABD_TRY(ws(ctx, "bp_pairs", 2 * cap_bp + 2, &bpairs, s));
+  ABD_TRY(ws(ctx, "bp_cap", cap_bp + 1, &cap, s));
+  ABD_TRY(ws(ctx, "bp_region", cap_bp + 1, &region, s));
+  hipLaunchKernelGGL(k_body_pairs<1>, dim3(nb), dim3(64), 0, s, nb, sc->body_scene, sc->body_fixed, bbox, send,
+                     skip_scene, nullptr, boff, bpairs, cap_bp);
+  hipLaunchKernelGGL(k_list_caps, dim3(grid_for(cap_bp, 256)), dim3(256), 0, s, cap_bp, btot, bpairs,
+                     sc->body_vert_off, sc->body_tri_off, sc->body_edge_off, cap, involved);
+  ABD_TRY(scan_exclusive_i64(ctx, cap, region, cap_bp, rtot, s, hbuf_d + 1));
   // culling boxes of the vertices of bodies in overlapping pairs only
   hipLaunchKernelGGL(k_vert_boxes, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv, sc->vert_body, involved, x0, x1,
                      inflate, vbox32);
   HIP_TRY(ctx, hipGetLastError());
 
   // culled primitive lists per body pair
-  const int trows = ctx->tune.tile_rows;
   int32_t *lists, *llen;
   int64_t *lstart;
-  ABD_TRY(ws(ctx, "bp_lists", list_total + 1, &lists, s));
-  ABD_TRY(ws(ctx, "bp_llen", 6 * nbp, &llen, s));
-  ABD_TRY(ws(ctx, "bp_lstart", 6 * nbp, &lstart, s));
+  ABD_TRY(ws(ctx, "bp_lists", cap_lt + 1, &lists, s));
+  ABD_TRY(ws(ctx, "bp_llen", 6 * cap_bp, &llen, s));
+  ABD_TRY(ws(ctx, "bp_lstart", 6 * cap_bp, &lstart, s));
 
-  // tiles: the count pass is sized like the body pairs (one
-  // synchronisation reads the tile and pair totals).  Tile counts per
-  // sub-problem: PT [0, 2 nbp), EE [2 nbp, 3 nbp), scanned as one array.
+  // tiles: the count pass is sized like the body pairs.  Tile counts per
+  // sub-problem: PT [0, 2 cap_bp), EE [2 cap_bp, 3 cap_bp), scanned as one
+  // array (slots past the body-pair count hold 0).
   int64_t *tcnt, *toff, *ttot = btot + 2, *otot = btot + 4;
-  ABD_TRY(ws(ctx, "bp_tcnt", 3 * nbp, &tcnt, s));
-  ABD_TRY(ws(ctx, "bp_toff", 3 * nbp + 1, &toff, s));
+  ABD_TRY(ws(ctx, "bp_tcnt", 3 * cap_bp, &tcnt, s));
+  ABD_TRY(ws(ctx, "bp_toff", 3 * cap_bp + 1, &toff, s));
   float *crec = nullptr;  // three-level tree: chunk records of the column lists
-  if (ctx->tune.cull_levels == 3) ABD_TRY(ws(ctx, "bp_crec", CREC * (list_total / 64 + 1), &crec, s));
+  if (ctx->tune.cull_levels == 3) ABD_TRY(ws(ctx, "bp_crec", CREC * (cap_lt / 64 + 1), &crec, s));
   double *tests = nullptr;  // box-test counting: single-level tests per sub-problem
-  if (ctx->count_box_tests) ABD_TRY(ws(ctx, "bp_tests", 3 * nbp, &tests, s));
-  hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)nbp, 3), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
+  if (ctx->count_box_tests) ABD_TRY(ws(ctx, "bp_tests", 3 * cap_bp, &tests, s));
+  hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)cap_bp, 3), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
                      sc->body_tri_off, sc->body_edge_off, bbox, vbox32, sc->tris, sc->edges, lists, lstart, llen,
-                     tcnt, tcnt + 2 * nbp, trows, crec, tests);
+                     tcnt, tcnt + 2 * cap_bp, trows, crec, tests, btot, cap_lt);
   // hbuf[2] = all tiles, hbuf[3] = PT tiles
-  ABD_TRY(scan_exclusive_i64(ctx, tcnt, toff, 3 * nbp, ttot, s, hbuf_d + 2, 2 * nbp));
+  ABD_TRY(scan_exclusive_i64(ctx, tcnt, toff, 3 * cap_bp, ttot, s, hbuf_d + 2, 2 * cap_bp));
   const std::string key_tp = std::string(tag) + "_tpt", key_te = std::string(tag) + "_tee";
   int64_t cap_tp = ctx->cap_hint[key_tp], cap_te = ctx->cap_hint[key_te];
   cap_tp = cap_tp + cap_tp / 4 + 256;
@@ -698,16 +714,19 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     ABD_TRY(ws(ctx, "bp_coff", cap_tp + cap_te + 1, &coff, s));
     ABD_TRY(ws(ctx, "bp_tsub_pt", cap_tp + 1, &tsub_pt, s));
     ABD_TRY(ws(ctx, "bp_tsub_ee", cap_te + 1, &tsub_ee, s));
-    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(3 * nbp, 256)), dim3(256), 0, s, nbp, tcnt, toff, tsub_pt, cap_tp,
-                       tsub_ee, cap_te);
+    hipLaunchKernelGGL(k_tile_sub, dim3(grid_for(3 * cap_bp, 256)), dim3(256), 0, s, cap_bp, tcnt, toff, tsub_pt,
+                       cap_tp, tsub_ee, cap_te);
     if (tests) ABD_TRY(ws(ctx, "bp_tile_tests", cap_tp + cap_te, &tile_tests, s));
-    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)(cap_tp + cap_te)), dim3(64), 0, s, nbp, cap_tp, cap_te, cap_tp,
-                       tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0, x1, inflate,
-                       ccnt, nullptr, nullptr, nullptr, trows, crec, tile_tests);
+    hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)(cap_tp + cap_te)), dim3(64), 0, s, cap_bp, cap_tp, cap_te,
+                       cap_tp, tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0, x1,
+                       inflate, ccnt, nullptr, nullptr, nullptr, trows, crec, tile_tests);
     // hbuf[4] = all pairs, hbuf[5] = PT pairs
     ABD_TRY(scan_exclusive_i64(ctx, ccnt, coff, cap_tp + cap_te, otot, s, hbuf_d + 4, cap_tp));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    ABD_TRY(mirror_counts_ok(ctx, {hbuf[2], hbuf[3], hbuf[4], hbuf[5]}, "candidates"));
+    ABD_TRY(mirror_counts_ok(ctx, {hbuf[0], hbuf[1], hbuf[2], hbuf[3], hbuf[4], hbuf[5]}, "candidates"));
+    nbp = hbuf[0];
+    list_total = hbuf[1];
+    if (nbp > cap_bp || list_total > cap_lt) break;  // (the search repeats at the exact sizes)
     ntile_pt = hbuf[3];
     ntile_ee = hbuf[2] - hbuf[3];
     if (ntile_pt <= cap_tp && ntile_ee <= cap_te) break;
@@ -715,6 +734,16 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     cap_tp = ntile_pt > cap_tp ? ntile_pt : cap_tp;
     cap_te = ntile_ee > cap_te ? ntile_ee : cap_te;
   }
+  if (nbp > cap_bp || list_total > cap_lt) {
+    // (a list total read with too few body pairs covers only those: one
+    // more pass then sizes the lists)
+    if (attempt > 1) return abd_fail(ctx, ABD_E_INVALID, "candidates: body-pair or list count changed between passes");
+    cap_bp = nbp > cap_bp ? nbp : cap_bp;
+    cap_lt = list_total > cap_lt ? list_total : cap_lt;
+    continue;
+  }
+  ctx->cap_hint[key_bp] = nbp;
+  ctx->cap_hint[key_lt] = list_total;
   ctx->cap_hint[key_tp] = ntile_pt;
   ctx->cap_hint[key_te] = ntile_ee;
   if (tests) {
@@ -725,7 +754,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     if (ctx->prof_box_tests_clear) hipLaunchKernelGGL(k_clear_f64, dim3(1), dim3(64), 0, s, 2, acc);
     ctx->prof_box_tests_clear = false;
     ABD_TRY(reduce_sum_f64(ctx, tile_tests, cap_tp + cap_te, acc, s));
-    ABD_TRY(reduce_sum_f64(ctx, tests, 3 * nbp, acc + 1, s));
+    ABD_TRY(reduce_sum_f64(ctx, tests, 3 * cap_bp, acc + 1, s));
     ctx->kstats["box_tests"].launches += 1;
     ctx->kstats["box_tests_single_level"].launches += 1;
   }
@@ -736,11 +765,12 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   ABD_TRY(ws(ctx, tee_name.c_str(), 2 * (*n_ee) + 2, ee_out, s));
   hipEvent_t pe = prof_begin(ctx, s);
   if (*n_pt + *n_ee > 0)
-    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)(ntile_pt + ntile_ee)), dim3(64), 0, s, nbp, ntile_pt,
+    hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)(ntile_pt + ntile_ee)), dim3(64), 0, s, cap_bp, ntile_pt,
                        ntile_ee, cap_tp, tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0,
                        x1, inflate, nullptr, coff, *pt_out, *ee_out, trows, crec, nullptr);
   prof_end(ctx, pe, "pair_tiles_write", ntile_pt + ntile_ee, s);
   return abd_hip_check(ctx, hipGetLastError(), "candidates");
+  }
 }
 
 // ----------------------------------------------------- off-diag pattern ----

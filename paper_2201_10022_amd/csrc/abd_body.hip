@@ -49,10 +49,12 @@ __global__ void __launch_bounds__(64) k_body_mass(int nb, const int32_t *tri_off
 __global__ void __launch_bounds__(256) k_vertex_map(int nv, const double *__restrict__ xbar,
                                                     const int32_t *__restrict__ vert_body,
                                                     const double *__restrict__ q, double *__restrict__ x,
-                                                    int64_t qstride = 0) {
+                                                    int64_t qstride = 0, const uint8_t *skip_scene = nullptr,
+                                                    const int32_t *body_scene = nullptr) {
 #pragma clang fp contract(off)
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nv) return;
+  if (skip_scene && skip_scene[body_scene[vert_body[k]]]) return;
   q += blockIdx.y * qstride;
   x += blockIdx.y * 3 * (int64_t)nv;
   const double *qb = q + 12 * (int64_t)vert_body[k];
@@ -76,7 +78,8 @@ constexpr int DISP_PAD = 16;
 __global__ void __launch_bounds__(256) k_disp_scene_max(int nv, const double *__restrict__ xbar,
                                                         const int32_t *__restrict__ vert_body,
                                                         const int32_t *__restrict__ body_scene,
-                                                        const double *__restrict__ p, unsigned long long *out) {
+                                                        const double *__restrict__ p, unsigned long long *out,
+                                                        const uint8_t *skip_scene) {
   __shared__ unsigned long long sm[4];
   __shared__ int ss[4];
   const int k = blockIdx.x * 256 + threadIdx.x;
@@ -85,6 +88,9 @@ __global__ void __launch_bounds__(256) k_disp_scene_max(int nv, const double *__
   if (k < nv) {
     const int b = vert_body[k];
     sc = body_scene[b];
+  }
+  if (k < nv && !(skip_scene && skip_scene[sc])) {
+    const int b = vert_body[k];
     const double *qb = p + 12 * (int64_t)b;
     const double xb0 = xbar[3 * k], xb1 = xbar[3 * k + 1], xb2 = xbar[3 * k + 2];
 #pragma unroll
@@ -494,14 +500,16 @@ __global__ void __launch_bounds__(64) k_body_terms(int nb, const uint8_t *fixed,
                                                   const double *volume, const double *q, const double *qt,
                                                   double kappa_o, double w, int do_inertia, int do_ortho,
                                                   int project, int want_grad, double *e_out, double *grad,
-                                                  double *diag, int64_t estride = 0) {
+                                                  double *diag, int64_t estride = 0,
+                                                  const uint8_t *skip_scene = nullptr,
+                                                  const int32_t *body_scene = nullptr) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   // energy-only trials (grid.y > 1): trial t's q at q + 12 nb t, energies at
   // e_out + t estride (estride 0: nb)
   q += blockIdx.y * 12 * (int64_t)nb;
   e_out += blockIdx.y * (estride > 0 ? estride : (int64_t)nb);
-  if (fixed[b]) {
+  if (fixed[b] || (skip_scene && skip_scene[body_scene[b]])) {
     e_out[b] = 0.0;
     return;
   }
@@ -578,23 +586,24 @@ __global__ void k_q_tilde(int nb, const uint8_t *fixed, const double *q, const d
 
 }  // namespace
 
-int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t s) {
+int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t s,
+                  const uint8_t *skip_scene) {
   if (sc->n_verts <= 0) return ABD_OK;
   hipLaunchKernelGGL(k_vertex_map, dim3(grid_for(sc->n_verts, 256)), dim3(256), 0, s, sc->n_verts, sc->xbar,
-                     sc->vert_body, q, x);
+                     sc->vert_body, q, x, (int64_t)0, skip_scene, sc->body_scene);
   return abd_hip_check(ctx, hipGetLastError(), "k_vertex_map");
 }
 
 // per-scene max_k |J_k p|_inf into out [n_scenes]
 int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, const double **out, int *stride,
-                           hipStream_t s) {
+                           hipStream_t s, const uint8_t *skip_scene) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   unsigned long long *pad;
   ABD_TRY(ws(ctx, "disp_pad", DISP_PAD * (size_t)S, &pad, s));
   hipLaunchKernelGGL(k_clear_u64n, dim3(grid_for(DISP_PAD * S, 256)), dim3(256), 0, s, DISP_PAD * S, pad);
   if (sc->n_verts > 0)
     hipLaunchKernelGGL(k_disp_scene_max, dim3(grid_for(sc->n_verts, 256)), dim3(256), 0, s, sc->n_verts, sc->xbar,
-                       sc->vert_body, sc->body_scene, p, pad);
+                       sc->vert_body, sc->body_scene, p, pad, skip_scene);
   *out = reinterpret_cast<const double *>(pad);
   *stride = DISP_PAD;
   return abd_hip_check(ctx, hipGetLastError(), "k_disp_scene_max");
@@ -603,7 +612,7 @@ int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, c
 // (kappa_j > 0: the scene's joint penalties are added, times w)
 static int body_terms(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double kappa_o,
                       double w, int do_inertia, int do_ortho, int project, double *energy, double *grad,
-                      double *diag, hipStream_t s, double kappa_j = 0.0) {
+                      double *diag, hipStream_t s, double kappa_j = 0.0, const uint8_t *skip_scene = nullptr) {
   if (sc->n_bodies <= 0) return ABD_OK;
   if (!sc->mass && do_inertia) return abd_fail(ctx, ABD_E_INVALID, "scene mass is NULL");
   if (!sc->volume && do_ortho) return abd_fail(ctx, ABD_E_INVALID, "scene volume is NULL");
@@ -613,7 +622,7 @@ static int body_terms(abd_ctx *ctx, const abd_scene *sc, const double *q, const 
   if (grad || diag)
     hipLaunchKernelGGL(k_body_terms<1>, dim3(grid_for(sc->n_bodies, 64)), dim3(64), 0, s, sc->n_bodies,
                        sc->body_fixed, sc->mass, sc->volume, q, qt, kappa_o, w, do_inertia, do_ortho, project,
-                       grad != nullptr ? 1 : 0, eb, grad, diag, (int64_t)0);
+                       grad != nullptr ? 1 : 0, eb, grad, diag, (int64_t)0, skip_scene, sc->body_scene);
   else
     hipLaunchKernelGGL(k_body_terms<0>, dim3(grid_for(sc->n_bodies, 64)), dim3(64), 0, s, sc->n_bodies,
                        sc->body_fixed, sc->mass, sc->volume, q, qt, kappa_o, w, do_inertia, do_ortho, project, 0, eb,
@@ -626,9 +635,10 @@ static int body_terms(abd_ctx *ctx, const abd_scene *sc, const double *q, const 
 }
 
 int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
-                  double *energy, double *grad, double *diag, int project, hipStream_t s) {
+                  double *energy, double *grad, double *diag, int project, hipStream_t s,
+                  const uint8_t *skip_scene) {
   return body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1 + prm->rigidity, project, energy, grad, diag,
-                    s, prm->kappa_j);
+                    s, prm->kappa_j, skip_scene);
 }
 
 int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,

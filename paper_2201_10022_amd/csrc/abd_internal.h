@@ -220,7 +220,9 @@ struct FrictionSet {
 
 // ------------------------------------------------- internal operations ----
 // (shared by the ABI wrappers and the Newton driver)
-int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t s);
+// (skip_scene, device, may be NULL: vertices of the scenes it marks keep x)
+int op_vertex_map(abd_ctx *ctx, const abd_scene *sc, const double *q, double *x, hipStream_t s,
+                  const uint8_t *skip_scene = nullptr);
 // candidates; sub-scenes s with skip_scene[s] != 0 (device, may be NULL)
 // contribute none
 int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const double *x1, double inflate,
@@ -322,8 +324,11 @@ int op_kappa_init(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
                   hipStream_t s);
 int op_kappa_update(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x, const int32_t *pt,
                     int64_t npt, const int32_t *ee, int64_t nee, hipStream_t s);
+// (skip_scene, device, may be NULL: bodies of the scenes it marks add
+// nothing and get energy 0)
 int op_body_terms(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
-                  double *energy, double *grad, double *diag, int project, hipStream_t s);
+                  double *energy, double *grad, double *diag, int project, hipStream_t s,
+                  const uint8_t *skip_scene = nullptr);
 int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *qt,
                    double *energy, hipStream_t s);
 // x0 (may be NULL = 0, may alias p): initial guess
@@ -334,7 +339,9 @@ int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, con
 // that state on the device (int[4]: iteration base, scenes stopped, largest
 // final count, scenes stopped by the cap or a breakdown).  *pre_sync_final
 // (may be NULL) tells whether its last enqueue followed the solve's final
-// iterations with nothing changing p afterwards.
+// iterations with nothing changing p afterwards.  skip_scene (device, may be
+// NULL) marks scenes whose right-hand side is zero and whose diagonal
+// blocks need not be invertible: their preconditioner blocks are zero.
 using PcgHook = std::function<int(const int *cg_state)>;
 // relative tolerance at and above which a one-kernel solve whose scenes all
 // stopped on the tolerance skips the residual check (nothing then changes
@@ -343,7 +350,8 @@ constexpr double PCG_CHECK_RTOL = 1e-6;
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *p, double rtol, int max_iter, int *iters, hipStream_t s,
            const double *x0 = nullptr, const double *pre_diag = nullptr, const KeyPattern *pat = nullptr,
-           const PcgHook *pre_sync = nullptr, bool *pre_sync_final = nullptr);
+           const PcgHook *pre_sync = nullptr, bool *pre_sync_final = nullptr,
+           const uint8_t *skip_scene = nullptr);
 // preconditioned MINRES on the (possibly indefinite) symmetric block matrix,
 // block-Jacobi preconditioner from the SPD diagonal blocks pre_diag; stops
 // at |r|_{P} <= rtol |b|_{P} (syncs every iteration)
@@ -353,8 +361,9 @@ int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const doubl
 // per-scene max_k |J_k p|_inf at (*out)[j * *stride] (device, context
 // workspace; a NaN displacement gives NaN); per-scene energies accumulate
 // into out [n_scenes]
+// (skip_scene, device, may be NULL: scenes it marks get 0)
 int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, const double **out, int *stride,
-                           hipStream_t s);
+                           hipStream_t s, const uint8_t *skip_scene = nullptr);
 int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                           const double *qt, double *energy, hipStream_t s);
 int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,

@@ -293,7 +293,9 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
 
   // gradient and projected Hessian at q
   auto t0 = std::chrono::steady_clock::now();
-  ABD_TRY(op_vertex_map(ctx, sc, q, x, s));
+  // (without lagged friction no kernel of this iteration reads the vertices
+  // of a scene already done, so they are not mapped)
+  ABD_TRY(op_vertex_map(ctx, sc, q, x, s, done_mode == 1 || fr ? nullptr : done_dev));
   const int32_t *pt, *ee;
   int32_t *keys = nullptr;
   int64_t npt, nee, nk = 0;
@@ -368,7 +370,8 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   if (ctx->kappa_sc) ABD_TRY(op_kappa_update(ctx, sc, prm, x, pt, npt, ee, nee, s));
   t0 = std::chrono::steady_clock::now();
   // (the energy at q comes with the line search's trials: none is summed here)
-  ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, nullptr, g, diag, 1, s));
+  // (done scenes get a zero right-hand side: their body terms are not needed)
+  ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, nullptr, g, diag, 1, s, done_dev));
   int64_t nap = 0, nae = 0;
   ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, nullptr, 0, nullptr, g, diag, nullptr, 1, &nap, &nae, s, fr,
                      &hooks));
@@ -397,7 +400,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   auto disp_pass = [&](const int *cg_state) -> int {
     const double *dsp;
     int dstride;
-    ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, &dsp, &dstride, s));
+    ABD_TRY(op_max_abs_disp_scenes(ctx, sc, p, &dsp, &dstride, s, done_dev));
     int *errf;
     ABD_TRY(ws(ctx, "err_flag", 1, &errf, s));
     hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, dsp, S, nullptr, 0, errf, d_disp, nullptr, d_err,
@@ -411,7 +414,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   const PcgHook pre_sync = disp_pass;
   bool disp_done = false;
   ABD_TRY(op_pcg(ctx, sc, diag, off, keys, nk, rhs, p, prm->pcg_rtol, prm->max_pcg, &its, s, nullptr, nullptr, &pat,
-                 prm->pcg_rtol >= PCG_CHECK_RTOL ? &pre_sync : nullptr, &disp_done));
+                 prm->pcg_rtol >= PCG_CHECK_RTOL ? &pre_sync : nullptr, &disp_done, done_dev));
   st->pcg_iters = its;
   st->t_solve_ms += ms_since(t0);
   if (!disp_done) {

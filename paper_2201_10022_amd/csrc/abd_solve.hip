@@ -34,13 +34,15 @@
 namespace {
 
 
-// inverse of each free body's diagonal block via Cholesky (thread per body)
+// inverse of each free body's diagonal block via Cholesky (thread per
+// body); bodies of the scenes skip_scene marks (may be NULL) get zeros
 __global__ void __launch_bounds__(64) k_block_inverse(int nb, const uint8_t *fixed, const double *diag, double *inv,
-                                                      int *err) {
+                                                      int *err, const uint8_t *skip_scene = nullptr,
+                                                      const int32_t *body_scene = nullptr) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   double *Iv = inv + 144 * (int64_t)b;
-  if (fixed[b]) {
+  if (fixed[b] || (skip_scene && skip_scene[body_scene[b]])) {
     for (int i = 0; i < 144; ++i) Iv[i] = 0.0;
     return;
   }
@@ -1248,7 +1250,7 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
 int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *off, const int32_t *keys,
            int64_t n_keys, const double *rhs, double *x_out, double rtol, int max_iter, int *iters, hipStream_t s,
            const double *x0, const double *pre_diag, const KeyPattern *pat, const PcgHook *pre_sync,
-           bool *pre_sync_final) {
+           bool *pre_sync_final, const uint8_t *skip_scene) {
   if (pre_sync_final) *pre_sync_final = false;
   const int nb = sc->n_bodies;
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
@@ -1301,7 +1303,7 @@ int op_pcg(abd_ctx *ctx, const abd_scene *sc, const double *diag, const double *
   ABD_TRY(ws(ctx, "pcg_s_final", S, &scs.it_final, s));
   ABD_TRY(ws(ctx, "err_flag", 1, &err, s));
   hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(nb, 64)), dim3(64), 0, s, nb, sc->body_fixed,
-                     pre_diag ? pre_diag : diag, inv, err);
+                     pre_diag ? pre_diag : diag, inv, err, skip_scene, sc->body_scene);
   // (the block-to-scene maps depend on the scene alone)
   if (scene_table_cached(ctx, sc, "pcg_scene_maps", c_scene)) {
   } else if (S <= SETUP_T) {

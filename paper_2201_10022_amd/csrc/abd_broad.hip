@@ -313,7 +313,9 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
   // list starts inside the body pair's region (capacities rounded to 64)
   const int64_t s1 = round64(la), s2 = s1 + round64(tb), s3 = s2 + round64(lb), s4 = s3 + round64(ta),
                 s5 = s4 + round64(ea);
-  skip = skip || region[p] + s5 + round64(eb) > cap_lists;
+  // (a failed look-back scan leaves negative offsets: nothing is written
+  // and the host rejects the poisoned total)
+  skip = skip || region[p] < 0 || region[p] + s5 + round64(eb) > cap_lists;
   if (skip) {
     if (lane == 0) {
       list_len[6 * p + 2 * sub] = 0;
@@ -437,6 +439,7 @@ __global__ void k_tile_sub(int64_t nbp, const int64_t *cnt, const int64_t *off, 
   if (j >= 3 * nbp) return;
   const bool ee = j >= 2 * nbp;
   const int64_t o = ee ? off[j] - off[2 * nbp] : off[j], cap = ee ? cap_ee : cap_pt;
+  if (off[j] < 0 || (ee && off[2 * nbp] < 0)) return;  // (a failed scan: the host rejects its total)
   int2 *ts = ee ? tsub_ee : tsub_pt;
   const int sub = (int)(ee ? j - 2 * nbp : j);
   for (int64_t t = 0; t < cnt[j] && o + t < cap; ++t) ts[o + t] = make_int2(sub, (int)t);

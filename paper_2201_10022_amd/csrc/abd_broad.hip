@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
                                                     const int32_t *edges, int32_t *lists, int64_t *list_start,
                                                     int32_t *list_len, int64_t *tiles_pt, int64_t *tiles_ee,
                                                     int trows, float *crec, double *tests, const int64_t *nbp_dev,
-                                                    int64_t cap_lists) {
+                                                    int64_t cap_lists, int64_t *masks_pt, int64_t *masks_ee) {
   const int64_t p = blockIdx.x;
   const int sub = blockIdx.y;
   const int lane = threadIdx.x;
@@ -320,10 +320,13 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
     if (lane == 0) {
       list_len[6 * p + 2 * sub] = 0;
       list_len[6 * p + 2 * sub + 1] = 0;
-      if (sub < 2)
+      if (sub < 2) {
         tiles_pt[2 * p + sub] = 0;
-      else
+        masks_pt[2 * p + sub] = 0;
+      } else {
         tiles_ee[p] = 0;
+        masks_ee[p] = 0;
+      }
       if (tests) tests[3 * p + sub] = 0.0;
     }
     return;
@@ -420,10 +423,15 @@ __global__ void __launch_bounds__(64) k_cull_lists(const int32_t *bpairs, const 
   }
   if (lane == 0) {
     const int64_t t = len[1] > 0 ? (len[0] + trows - 1) / trows : 0;
-    if (sub < 2)
+    // (masks of the sub-problem's tiles: its rows x its column chunks)
+    const int64_t mk = t > 0 ? (int64_t)len[0] * ((len[1] + 63) / 64) : 0;
+    if (sub < 2) {
       tiles_pt[2 * p + sub] = t;
-    else
+      masks_pt[2 * p + sub] = mk;
+    } else {
       tiles_ee[p] = t;
+      masks_ee[p] = mk;
+    }
     if (tests) tests[3 * p + sub] = (double)len[0] * len[1];
   }
 }
@@ -452,13 +460,23 @@ __global__ void k_tile_sub(int64_t nbp, const int64_t *cnt, const int64_t *off, 
 // loaded up front, so the row loop runs on registers and shuffles; columns
 // beyond CPRE chunks are loaded in the loop.
 constexpr int CPRE = 8;
+// Hit masks: the count pass stores, per tile row and column chunk, the
+// ballot of its box tests (masks + mask_off[sub-problem] + row-major
+// (row, chunk)), when the tile's range lies inside the mask capacity; the
+// write pass then emits the same pairs from the masks without the tests.
+struct TileMasks {
+  unsigned long long *m;
+  const int64_t *off;  // per sub-problem, in the tile-count layout
+  int64_t cap;
+  int64_t ee_base;  // index of the first EE sub-problem in that layout
+};
 template <int WRITE>
 __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *tile_sub, int64_t n_tiles,
                                           const int64_t *list_start, const int32_t *list_len, const int32_t *lists,
                                           const int32_t *tris, const int32_t *edges, const double *x0,
                                           const double *x1, double inflate, int64_t *tile_cnt, int64_t pos0,
                                           int32_t *out, int64_t n_tiles_valid, int trows, const float *crec,
-                                          double *tile_tests) {
+                                          double *tile_tests, TileMasks tm) {
   // rows: vertices (PT) or edges (EE); columns: triangles (PT) or edges (EE)
   const int rk = is_ee ? 2 : 0, ck = is_ee ? 2 : 1;
   // (the count pass runs over a capacity: tiles beyond the device count
@@ -481,6 +499,32 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
   const int r1 = min(nr, r0 + trows);
   const int lane = threadIdx.x;
   const int nch = (nc + 63) / 64;
+  // this tile's masks (row-major over its rows and the column chunks)
+  unsigned long long *tmask = nullptr;
+  if (tm.m) {
+    const int64_t mb = tm.off[is_ee ? tm.ee_base + s : s];
+    const int64_t m0 = mb + (int64_t)r0 * nch, m1 = m0 + (int64_t)(r1 - r0) * nch;
+    if (mb >= 0 && m1 <= tm.cap) tmask = tm.m + m0;
+  }
+  if (WRITE && tmask) {
+    // the pairs from the count pass's masks, in the same order
+    int64_t cnt = 0;
+    for (int r = r0; r < r1; ++r) {
+      const int rp = lists[rstart + r];
+      const unsigned long long *mr = tmask + (int64_t)(r - r0) * nch;
+      for (int k = 0; k < nch; ++k) {
+        const unsigned long long m = mr[k];
+        if (m == 0ull) continue;  // (uniform over the wave)
+        if ((m >> lane) & 1ull) {
+          const int64_t o = pos0 + cnt + __popcll(m & ((1ull << lane) - 1ull));
+          out[2 * o] = rp;
+          out[2 * o + 1] = lists[cstart + 64 * k + lane];
+        }
+        cnt += __popcll(m);
+      }
+    }
+    return;
+  }
   // row r0 + lane (lanes < trows) and the lane's first CPRE column chunks
   int my_rp = 0;
   double my_rb[6];
@@ -544,6 +588,7 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
       if (k < nch) {  // uniform over the wave
         const bool ok = cpv[k] >= 0 && box_overlap(rb, cb[k]);
         const unsigned long long m = __ballot(ok);
+        if (!WRITE && tmask && lane == 0) tmask[(int64_t)src * nch + k] = m;
         if (WRITE && ok) {
           const int64_t o = pos + cnt + __popcll(m & ((1ull << lane) - 1ull));
           out[2 * o] = rp;
@@ -553,7 +598,10 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
       }
     }
     for (int c0 = 64 * CPRE; c0 < nc; c0 += 64) {
-      if (crec && !chunk_reached(crec, g0, c0 >> 6, tb)) continue;  // (uniform over the wave)
+      if (crec && !chunk_reached(crec, g0, c0 >> 6, tb)) {  // (uniform over the wave)
+        if (!WRITE && tmask && lane == 0) tmask[(int64_t)src * nch + (c0 >> 6)] = 0ull;
+        continue;
+      }
       const int c = c0 + lane;
       int cp = 0;
       bool ok = false;
@@ -564,6 +612,7 @@ __device__ __forceinline__ void pair_tile(int is_ee, int64_t tile, const int2 *t
         ok = box_overlap(rb, cbx);
       }
       const unsigned long long m = __ballot(ok);
+      if (!WRITE && tmask && lane == 0) tmask[(int64_t)src * nch + (c0 >> 6)] = m;
       if (WRITE && ok) {
         const int64_t o = pos + cnt + __popcll(m & ((1ull << lane) - 1ull));
         out[2 * o] = rp;
@@ -601,18 +650,18 @@ __global__ void __launch_bounds__(64) k_pair_tiles(int64_t nbp, int64_t n_pt_blo
                                                    const double *x0, const double *x1, double inflate,
                                                    int64_t *cnt, const int64_t *off, int32_t *out_pt,
                                                    int32_t *out_ee, int trows, const float *crec,
-                                                   double *tile_tests) {
+                                                   double *tile_tests, TileMasks tm) {
   const int64_t b = blockIdx.x;
   if (b < n_pt_blocks) {
     const int64_t valid = WRITE ? n_pt_blocks : toff[2 * nbp];
     pair_tile<WRITE>(0, b, tsub_pt, n_pt_blocks, list_start, list_len, lists, tris, edges, x0, x1, inflate, cnt,
-                     WRITE ? off[b] : 0, out_pt, valid, trows, crec, tile_tests);
+                     WRITE ? off[b] : 0, out_pt, valid, trows, crec, tile_tests, tm);
   } else if (b < n_pt_blocks + n_ee_blocks) {
     const int64_t t = b - n_pt_blocks;
     const int64_t valid = WRITE ? n_ee_blocks : *ttotal - toff[2 * nbp];
     pair_tile<WRITE>(1, t, tsub_ee, n_ee_blocks, list_start, list_len, lists, tris, edges, x0, x1, inflate,
                      cnt + cap_pt, WRITE ? off[cap_pt + t] - off[cap_pt] : 0, out_ee, valid, trows, crec,
-                     tile_tests ? tile_tests + cap_pt : nullptr);
+                     tile_tests ? tile_tests + cap_pt : nullptr, tm);
   }
 }
 
@@ -698,11 +747,22 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   if (ctx->tune.cull_levels == 3) ABD_TRY(ws(ctx, "bp_crec", CREC * (cap_lt / 64 + 1), &crec, s));
   double *tests = nullptr;  // box-test counting: single-level tests per sub-problem
   if (ctx->count_box_tests) ABD_TRY(ws(ctx, "bp_tests", 3 * cap_bp, &tests, s));
+  // hit masks of the tiles (per sub-problem counts in the tile-count layout,
+  // their offsets, and the masks on a capacity of twice the last total)
+  int64_t *mcnt, *moff;
+  ABD_TRY(ws(ctx, "bp_mcnt", 3 * cap_bp, &mcnt, s));
+  ABD_TRY(ws(ctx, "bp_moff", 3 * cap_bp + 1, &moff, s));
+  const std::string key_mk = std::string(tag) + "_mk";
+  const int64_t cap_mk = 2 * ctx->cap_hint[key_mk] + 4096;
+  unsigned long long *masks;
+  ABD_TRY(ws(ctx, "bp_masks", cap_mk, &masks, s));
+  const TileMasks tm{masks, moff, cap_mk, 2 * cap_bp};
   hipLaunchKernelGGL(k_cull_lists, dim3((unsigned)cap_bp, 3), dim3(64), 0, s, bpairs, region, sc->body_vert_off,
                      sc->body_tri_off, sc->body_edge_off, bbox, vbox32, sc->tris, sc->edges, lists, lstart, llen,
-                     tcnt, tcnt + 2 * cap_bp, trows, crec, tests, btot, cap_lt);
-  // hbuf[2] = all tiles, hbuf[3] = PT tiles
+                     tcnt, tcnt + 2 * cap_bp, trows, crec, tests, btot, cap_lt, mcnt, mcnt + 2 * cap_bp);
+  // hbuf[2] = all tiles, hbuf[3] = PT tiles; hbuf[6] = all masks
   ABD_TRY(scan_exclusive_i64(ctx, tcnt, toff, 3 * cap_bp, ttot, s, hbuf_d + 2, 2 * cap_bp));
+  ABD_TRY(scan_exclusive_i64(ctx, mcnt, moff, 3 * cap_bp, btot + 6, s, hbuf_d + 6));
   const std::string key_tp = std::string(tag) + "_tpt", key_te = std::string(tag) + "_tee";
   int64_t cap_tp = ctx->cap_hint[key_tp], cap_te = ctx->cap_hint[key_te];
   cap_tp = cap_tp + cap_tp / 4 + 256;
@@ -722,11 +782,11 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
     if (tests) ABD_TRY(ws(ctx, "bp_tile_tests", cap_tp + cap_te, &tile_tests, s));
     hipLaunchKernelGGL(k_pair_tiles<0>, dim3((unsigned)(cap_tp + cap_te)), dim3(64), 0, s, cap_bp, cap_tp, cap_te,
                        cap_tp, tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0, x1,
-                       inflate, ccnt, nullptr, nullptr, nullptr, trows, crec, tile_tests);
+                       inflate, ccnt, nullptr, nullptr, nullptr, trows, crec, tile_tests, tm);
     // hbuf[4] = all pairs, hbuf[5] = PT pairs
     ABD_TRY(scan_exclusive_i64(ctx, ccnt, coff, cap_tp + cap_te, otot, s, hbuf_d + 4, cap_tp));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    ABD_TRY(mirror_counts_ok(ctx, {hbuf[0], hbuf[1], hbuf[2], hbuf[3], hbuf[4], hbuf[5]}, "candidates"));
+    ABD_TRY(mirror_counts_ok(ctx, {hbuf[0], hbuf[1], hbuf[2], hbuf[3], hbuf[4], hbuf[5], hbuf[6]}, "candidates"));
     nbp = hbuf[0];
     list_total = hbuf[1];
     if (nbp > cap_bp || list_total > cap_lt) break;  // (the search repeats at the exact sizes)
@@ -747,6 +807,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   }
   ctx->cap_hint[key_bp] = nbp;
   ctx->cap_hint[key_lt] = list_total;
+  ctx->cap_hint[key_mk] = hbuf[6];
   ctx->cap_hint[key_tp] = ntile_pt;
   ctx->cap_hint[key_te] = ntile_ee;
   if (tests) {
@@ -770,7 +831,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   if (*n_pt + *n_ee > 0)
     hipLaunchKernelGGL(k_pair_tiles<1>, dim3((unsigned)(ntile_pt + ntile_ee)), dim3(64), 0, s, cap_bp, ntile_pt,
                        ntile_ee, cap_tp, tsub_pt, tsub_ee, toff, ttot, lstart, llen, lists, sc->tris, sc->edges, x0,
-                       x1, inflate, nullptr, coff, *pt_out, *ee_out, trows, crec, nullptr);
+                       x1, inflate, nullptr, coff, *pt_out, *ee_out, trows, crec, nullptr, tm);
   prof_end(ctx, pe, "pair_tiles_write", ntile_pt + ntile_ee, s);
   return abd_hip_check(ctx, hipGetLastError(), "candidates");
   }

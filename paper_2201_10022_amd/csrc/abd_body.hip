@@ -666,7 +666,7 @@ int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
   if (!eb) ABD_TRY(ws(ctx, "body_e_tr", (size_t)nb * n_trials, &eb, s));
   hipLaunchKernelGGL(k_body_terms<0>, dim3(grid_for(nb, 64), n_trials), dim3(64), 0, s, nb, sc->body_fixed, sc->mass,
                      sc->volume, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1 + prm->rigidity, 0, 0, eb, nullptr, nullptr,
-                     items ? estride : (int64_t)0);
+                     items ? estride : (int64_t)0, defer ? defer->skip : nullptr, sc->body_scene);
   HIP_TRY(ctx, hipGetLastError());
   if (prm->kappa_j > 0.0 && sc->n_joints > 0)
     ABD_TRY(op_joint_body(ctx, sc, prm->kappa_j * prm->dt * prm->dt, q, n_trials, 12 * (int64_t)nb, eb,

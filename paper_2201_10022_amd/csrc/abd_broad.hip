@@ -95,11 +95,18 @@ __device__ __forceinline__ void prim_box32(int kind, int64_t i, const int32_t *t
 
 // Body boxes (min / max over the body's vertex boxes), one wave per body;
 // clears the body's mark of being in an overlapping body pair.
+// (bodies of the scenes skip_scene marks, which take part in no pair, get
+// no box)
 __global__ void __launch_bounds__(256) k_body_boxes(int nb, const int32_t *voff, const double *x0,
                                                     const double *x1, double inflate, double *bb,
-                                                    uint8_t *involved) {
+                                                    uint8_t *involved, const uint8_t *skip_scene,
+                                                    const int32_t *body_scene) {
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (b >= nb) return;  // (uniform over the wave)
+  if (skip_scene && skip_scene[body_scene[b]]) {
+    if (lane == 0) involved[b] = 0;
+    return;
+  }
   double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
   for (int v = voff[b] + lane; v < voff[b + 1]; v += 64) {
     double vbx[6];
@@ -681,7 +688,7 @@ int op_candidates(abd_ctx *ctx, const abd_scene *sc, const double *x0, const dou
   uint8_t *involved;
   ABD_TRY(ws(ctx, "bp_involved", nb, &involved, s));
   hipLaunchKernelGGL(k_body_boxes, dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, sc->body_vert_off, x0, x1, inflate,
-                     bbox, involved);
+                     bbox, involved, skip_scene, sc->body_scene);
   HIP_TRY(ctx, hipGetLastError());
 
   // body pairs

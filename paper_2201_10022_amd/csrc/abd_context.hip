@@ -517,6 +517,10 @@ __global__ void __launch_bounds__(SB) k_seg_reduce_trials(const double *vals, in
 __global__ void __launch_bounds__(SB) k_seg_reduce_trials_multi(TrialSums ts, int S, double *out) {
   __shared__ double sh[SB / 64];
   const int t = blockIdx.x / S, s = blockIdx.x % S;
+  if (ts.skip && ts.skip[s]) {  // (uniform over the block)
+    if (threadIdx.x == 0) out[blockIdx.x] = 0.0;
+    return;
+  }
   double acc = 0.0;
   for (int j = 0; j < ts.k; ++j) {
     const TrialSeg g = ts.seg[j];

@@ -626,7 +626,9 @@ struct TrialSeg {
 struct TrialSums {
   TrialSeg seg[5];
   int k = 0;
+  const uint8_t *skip = nullptr;  // (device, may be NULL) scenes whose sums are 0
 };
+// (with defer, bodies of the scenes defer->skip marks get energy 0)
 int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                           const double *qt, int n_trials, double *energy, hipStream_t s, double *items = nullptr,
                           int64_t estride = 0, TrialSums *defer = nullptr);

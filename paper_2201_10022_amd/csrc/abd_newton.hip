@@ -206,7 +206,8 @@ __global__ void k_ls_trials(int S, int n, const uint8_t *done, const double *a_c
 // same launches (a trial dimension in the grid), enqueued only
 int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, const double *p,
                   const double *qt, const double *alpha, int n, const int32_t *pt, int64_t npt, const int32_t *ee,
-                  int64_t nee, const FrictionSet *fr, double *e_dev, hipStream_t s) {
+                  int64_t nee, const FrictionSet *fr, double *e_dev, hipStream_t s,
+                  const uint8_t *skip_scene = nullptr) {
   const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
   const int nb = sc->n_bodies;
   const int64_t n12 = 12 * (int64_t)nb;
@@ -224,7 +225,9 @@ int energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, cons
     HIP_TRY(ctx, hipGetLastError());
   }
   if (S > 1) {
+    // (scenes already done: their energies are read by nobody)
     TrialSums ts;
+    ts.skip = skip_scene;
     ABD_TRY(op_body_energy_trials(ctx, sc, prm, qn, qt, n, e_dev, s, nullptr, 0, &ts));
     ABD_TRY(op_barrier_energy_trials(ctx, sc, prm, qn, n, pt, npt, ee, nee, e_dev, s, nullptr, 0, &ts));
     if (fr) ABD_TRY(op_friction_energy_trials(ctx, sc, fr, xn, n, e_dev, s, nullptr, 0, &ts));
@@ -449,7 +452,8 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   // CCD over the swept candidates of x(q) -> x(q + p)
   t0 = std::chrono::steady_clock::now();
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(n12, 256)), dim3(256), 0, s, n12, q, 1.0, p, qa);
-  ABD_TRY(op_vertex_map(ctx, sc, qa, x1, s));
+  // (the sweep and the CCD read no pair of a scene already done)
+  ABD_TRY(op_vertex_map(ctx, sc, qa, x1, s, done_dev));
   int32_t *spt, *see;
   int64_t nspt, nsee;
   ABD_TRY(op_candidates(ctx, sc, x, x1, prm->dhat, &spt, &nspt, &see, &nsee, "nt_sw", s, done_dev));
@@ -471,7 +475,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   const int kb0 = K <= prm->max_ls ? K : (prm->max_ls > 0 ? prm->max_ls : 0);
   hipLaunchKernelGGL(k_ls_trials, dim3(grid_for((kb0 + 1) * S, 256)), dim3(256), 0, s, S, kb0 + 1, done_dev, a_ccd,
                      alpha_dev);
-  ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb0 + 1, spt, nspt, see, nsee, fr, e_sc, s));
+  ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb0 + 1, spt, nspt, see, nsee, fr, e_sc, s, done_dev));
   hipLaunchKernelGGL(k_to_host, dim3(1), dim3(256), 0, s, a_ccd, S, e_sc, (kb0 + 1) * S, nullptr, d_alpha, d_e0,
                      nullptr);
   // (batches: the first batch's accepted steps are taken on the device
@@ -504,7 +508,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
       for (int t = 0; t < kb; ++t)
         for (int j = 0; j < S; ++j) h_atr[(size_t)t * S + j] = acc[j] ? 0.0 : std::ldexp(h_alpha[j], -t);
       HIP_TRY(ctx, hipMemcpyAsync(alpha_dev, h_atr, (size_t)kb * S * sizeof(double), hipMemcpyHostToDevice, s));
-      ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb, spt, nspt, see, nsee, fr, e_sc + S, s));
+      ABD_TRY(energy_trials(ctx, sc, prm, q, p, qt, alpha_dev, kb, spt, nspt, see, nsee, fr, e_sc + S, s, done_dev));
       HIP_TRY(ctx, hipMemcpyAsync(h_e1, e_sc + S, (size_t)kb * S * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(ctx, hipStreamSynchronize(s));
     }

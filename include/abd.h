@@ -419,7 +419,9 @@ int abd_barrier_stiffness(abd_ctx *ctx, const abd_scene *sc, double *kappa_out);
  *   ccd_block       threads per block of the CCD kernel: 64, 128, 256
  *   ccd_max_blocks  grid cap of the persistent CCD kernel: 64 .. 16384
  *   energy_block    threads per block of the energy-only kernel: 64 .. 1024 (powers of 2)
- *   pcg_short, pcg_long  PCG iterations per short / long graph replay:
+ *   pcg_short, pcg_long  shortest and longest PCG graph replay
+ *                   (iterations; replays are powers of two between them,
+ *                   chosen per solve to cover the last solve's count):
  *                   even, 2 <= pcg_short <= pcg_long <= 256
  *   cull_levels     i-AABB culling (sec. 4.2, Fig. iBVH): 1, the single
  *                   i-AABB per overlapping body pair; 3, inside each

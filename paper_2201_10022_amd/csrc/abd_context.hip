@@ -774,6 +774,8 @@ extern "C" int abd_destroy(abd_ctx *ctx) {
   for (auto &e : ctx->ev_pool) hipEventDestroy(e);
   for (int g = 0; g < 2; ++g)
     if (ctx->pcg_exec[g]) hipGraphExecDestroy(ctx->pcg_exec[g]);
+  for (auto &e : ctx->cg_exec)
+    if (e) hipGraphExecDestroy(e);
   if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
   delete ctx;
   return ABD_OK;

@@ -102,6 +102,10 @@ struct abd_ctx {
   // argument changes; pcg_hint: iterations of the last solve
   hipGraphExec_t pcg_exec[2] = {nullptr, nullptr};
   std::vector<uintptr_t> pcg_key[2];
+  // one-kernel PCG replays of 2, 4, ..., 256 iterations (slot k: 2^(k+1)),
+  // captured when first needed
+  hipGraphExec_t cg_exec[8] = {};
+  std::vector<uintptr_t> cg_key[8];
   int pcg_hint = 0;
   int ls_hint = 0;  // line-search halvings of the last Newton iteration
   hipStream_t capture_stream = nullptr;

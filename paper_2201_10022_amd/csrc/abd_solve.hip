@@ -1166,62 +1166,79 @@ int cg_solve(abd_ctx *ctx, const abd_scene *sc, int S, int nb, int64_t n_keys, c
   };
   const char *env = getenv("ABD_PCG_GRAPH");
   const bool use_graph = !(env && env[0] == '0');
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
-  if (use_graph) {
-    // every value baked into the captured kernels' arguments is part of the
-    // key (rtol2 by its bit pattern)
-    uint64_t rtol_bits;
-    std::memcpy(&rtol_bits, &rtol2, sizeof(rtol_bits));
-    const std::vector<uintptr_t> key = {
-        (uintptr_t)Bm,       (uintptr_t)off,      (uintptr_t)inv,          (uintptr_t)x_out,      (uintptr_t)u,
-        (uintptr_t)p,        (uintptr_t)rv[0],    (uintptr_t)rv[1],        (uintptr_t)wv[0],      (uintptr_t)wv[1],
-        (uintptr_t)sv[0],    (uintptr_t)sv[1],    (uintptr_t)pt[0],        (uintptr_t)pt[1],      (uintptr_t)cblk,
-        (uintptr_t)ent,      (uintptr_t)st,       (uintptr_t)sc->body_fixed, (uintptr_t)eoff,
-        (uintptr_t)nblk_c,   (uintptr_t)max_iter, (uintptr_t)rtol_bits,    (uintptr_t)scs.gam,    (uintptr_t)scs.alp,
-        (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)hst_d, (uintptr_t)S,
-        (uintptr_t)iter_g[0], (uintptr_t)iter_g[1], (uintptr_t)1};
-    if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-    for (int gi = 0; gi < 2; ++gi) {
-      if (ctx->pcg_exec[gi] == nullptr || ctx->pcg_key[gi] != key) {
-        HostTimer ht(ctx, "pcg_capture", iter_g[gi]);
-        if (ctx->pcg_exec[gi]) HIP_TRY(ctx, hipGraphExecDestroy(ctx->pcg_exec[gi]));
-        ctx->pcg_exec[gi] = nullptr;
-        hipGraph_t g = nullptr;
-        HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-        enqueue(ctx->capture_stream, iter_g[gi]);
-        HIP_TRY(ctx, hipStreamEndCapture(ctx->capture_stream, &g));
-        HIP_TRY(ctx, hipGraphInstantiate(&ctx->pcg_exec[gi], g, nullptr, nullptr, 0));
-        HIP_TRY(ctx, hipGraphDestroy(g));
-        ctx->pcg_key[gi] = key;
-      }
-      exec[gi] = ctx->pcg_exec[gi];
+  // every value baked into the captured kernels' arguments is part of a
+  // replay's key (rtol2 by its bit pattern), with its length
+  uint64_t rtol_bits;
+  std::memcpy(&rtol_bits, &rtol2, sizeof(rtol_bits));
+  const std::vector<uintptr_t> key = {
+      (uintptr_t)Bm,       (uintptr_t)off,      (uintptr_t)inv,          (uintptr_t)x_out,      (uintptr_t)u,
+      (uintptr_t)p,        (uintptr_t)rv[0],    (uintptr_t)rv[1],        (uintptr_t)wv[0],      (uintptr_t)wv[1],
+      (uintptr_t)sv[0],    (uintptr_t)sv[1],    (uintptr_t)pt[0],        (uintptr_t)pt[1],      (uintptr_t)cblk,
+      (uintptr_t)ent,      (uintptr_t)st,       (uintptr_t)sc->body_fixed, (uintptr_t)eoff,
+      (uintptr_t)nblk_c,   (uintptr_t)max_iter, (uintptr_t)rtol_bits,    (uintptr_t)scs.gam,    (uintptr_t)scs.alp,
+      (uintptr_t)scs.bb,   (uintptr_t)scs.stop, (uintptr_t)scs.it_final, (uintptr_t)hst_d, (uintptr_t)S, (uintptr_t)1};
+  // replay L iterations (L a power of two in [2, 256]): its captured graph,
+  // captured on first use, or the launches themselves without graphs
+  auto replay = [&](int L) -> int {
+    if (!use_graph) {
+      enqueue(s, L);
+      return ABD_OK;
     }
-  }
-  const int max_rounds = max_iter / iter_g[0] + 2;
+    int k = 0;
+    while ((2 << k) < L) ++k;
+    std::vector<uintptr_t> kk = key;
+    kk.push_back((uintptr_t)L);
+    if (ctx->cg_exec[k] == nullptr || ctx->cg_key[k] != kk) {
+      HostTimer ht(ctx, "pcg_capture", L);
+      if (!ctx->capture_stream)
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+      if (ctx->cg_exec[k]) HIP_TRY(ctx, hipGraphExecDestroy(ctx->cg_exec[k]));
+      ctx->cg_exec[k] = nullptr;
+      hipGraph_t g = nullptr;
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+      enqueue(ctx->capture_stream, L);
+      HIP_TRY(ctx, hipStreamEndCapture(ctx->capture_stream, &g));
+      HIP_TRY(ctx, hipGraphInstantiate(&ctx->cg_exec[k], g, nullptr, nullptr, 0));
+      HIP_TRY(ctx, hipGraphDestroy(g));
+      ctx->cg_key[k] = kk;
+    }
+    HIP_TRY(ctx, hipGraphLaunch(ctx->cg_exec[k], s));
+    return ABD_OK;
+  };
+  // Replay lengths are powers of two from Lmin (pcg_short) to Lmax
+  // (pcg_long).  A round covers the last solve's iteration count (once
+  // that count is passed, as many iterations again as done so far, at
+  // least Lmin) with the fewest replays whose total overshoots it by at
+  // most half: launches past a scene's stop return at once but still cost
+  // a launch, and each round costs a host round trip.
+  int Lmin = 2, Lmax = 2;
+  while (Lmin < iter_g[0] && Lmin < 256) Lmin <<= 1;
+  while (2 * Lmax <= iter_g[1] && Lmax < 256) Lmax <<= 1;
+  if (Lmax < Lmin) Lmax = Lmin;
+  auto pick = [&](int target) {
+    int L = Lmin;
+    while (L < target && L < Lmax) L <<= 1;
+    if (L > Lmin && L - target > target / 2) L >>= 1;
+    return L;
+  };
+  const int max_rounds = max_iter / Lmin + 2;
   int done = 0;
   bool all = false;
   bool profiled = false;
   for (int round = 0; round < max_rounds && !all;) {
-    // replays are queued back to back, without reading the state in
-    // between, while the last solve's count says that at least a short
-    // replay's worth of iterations remains after them: a long replay while
-    // that many remain, else a short one.  Launches past a scene's stop
-    // return at once, so queueing too many costs little next to a host
-    // round trip per replay.
+    int target = ctx->pcg_hint - done;
+    if (target < Lmin) target = done > Lmin ? done : Lmin;
     int planned = 0;
     do {
-      const int gi = ctx->pcg_hint - (done + planned) >= iter_g[1] ? 1 : 0;
+      const int L = pick(target - planned);
       hipEvent_t pe = prof_begin(ctx, s);
       profiled = profiled || pe != nullptr;
-      if (exec[gi])
-        HIP_TRY(ctx, hipGraphLaunch(exec[gi], s));
-      else
-        enqueue(s, iter_g[gi]);
+      ABD_TRY(replay(L));
       prof_end(ctx, pe, "pcg_round", 0, s);
       HIP_TRY(ctx, hipGetLastError());
-      planned += iter_g[gi];
+      planned += L;
       ++round;
-    } while (round < max_rounds && ctx->pcg_hint - (done + planned) >= iter_g[0]);
+    } while (round < max_rounds && planned < target);
     if (pre_sync) ABD_TRY((*pre_sync)(reinterpret_cast<const int *>(st)));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     all = hst[1] >= S;

@@ -71,7 +71,7 @@ extern "C" int abd_autotune(abd_ctx *ctx, const abd_scene *sc, const abd_params 
   };
   // candidate values per entry (the struct's order)
   const std::vector<std::vector<int>> cand = {
-      {8, 16, 32, 64}, {1, 2, 4}, {64, 128, 256}, {256, 512, 1024, 2048, 4096}, {128, 256, 512}, {4, 8, 16, 32},
+      {8, 16, 32, 64}, {1, 2, 4}, {64, 128, 256}, {256, 512, 1024, 2048, 4096}, {128, 256, 512}, {2, 4, 8, 16, 32},
       {1, 3}};
   abd_tune cur = ctx->tune;
   double best = 0.0;
@@ -83,7 +83,7 @@ extern "C" int abd_autotune(abd_ctx *ctx, const abd_scene *sc, const abd_params 
                        &t.pcg_short, &t.cull_levels};
       if (*f[e] == v) continue;
       *f[e] = v;
-      if (e == 5) t.pcg_long = 4 * v;  // (long replays stay 4 short ones)
+      if (e == 5) t.pcg_long = 4 * v < 64 ? 64 : 4 * v;  // (the longest replay: at least 64)
       if (!tune_valid(t)) continue;
       ctx->tune = t;
       double ms = 0.0;

@@ -344,6 +344,10 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   hooks.active = [&](const int32_t *act, int64_t na, int64_t na_pt) -> int {
     HIP_TRY(ctx, hipEventRecord(ctx->ev_fork, s));
     HIP_TRY(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
+    // the body terms (they read q and q~ only; the assembly adds into the
+    // same blocks after the join), then the pattern
+    // (done scenes get a zero right-hand side: their body terms are not needed)
+    ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, nullptr, g, diag, 1, aux, done_dev));
     int32_t *apt, *aee;
     ABD_TRY(op_gather_active(ctx, act, na, na_pt, npt, pt, ee, &apt, &aee, aux));
     ABD_TRY(op_offdiag(ctx, sc, apt, na_pt, aee, na - na_pt, &keys, &nk, "nt_st", aux, fr ? fr->pt : nullptr,
@@ -372,9 +376,8 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
   // the barrier's derivatives and this iteration's energies
   if (ctx->kappa_sc) ABD_TRY(op_kappa_update(ctx, sc, prm, x, pt, npt, ee, nee, s));
   t0 = std::chrono::steady_clock::now();
-  // (the energy at q comes with the line search's trials: none is summed here)
-  // (done scenes get a zero right-hand side: their body terms are not needed)
-  ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, nullptr, g, diag, 1, s, done_dev));
+  // (the energy at q comes with the line search's trials: none is summed
+  // here; the body terms run in the hook)
   int64_t nap = 0, nae = 0;
   ABD_TRY(op_barrier(ctx, sc, prm, x, pt, npt, ee, nee, nullptr, 0, nullptr, g, diag, nullptr, 1, &nap, &nae, s, fr,
                      &hooks));

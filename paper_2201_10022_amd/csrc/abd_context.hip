@@ -516,15 +516,22 @@ __global__ void __launch_bounds__(SB) k_seg_reduce_trials(const double *vals, in
 // k_seg_reduce_trials reduces it, accumulated in segment order.
 __global__ void __launch_bounds__(SB) k_seg_reduce_trials_multi(TrialSums ts, int S, double *out) {
   __shared__ double sh[SB / 64];
+  __shared__ int64_t bound[10];
   const int t = blockIdx.x / S, s = blockIdx.x % S;
   if (ts.skip && ts.skip[s]) {  // (uniform over the block)
     if (threadIdx.x == 0) out[blockIdx.x] = 0.0;
     return;
   }
+  // every segment's range of the scene, one binary search per thread
+  if ((int)threadIdx.x < 2 * ts.k) {
+    const TrialSeg g = ts.seg[threadIdx.x >> 1];
+    bound[threadIdx.x] = lower_bound_i32(g.keys, g.n, s + (int)(threadIdx.x & 1));
+  }
+  __syncthreads();
   double acc = 0.0;
   for (int j = 0; j < ts.k; ++j) {
     const TrialSeg g = ts.seg[j];
-    const int64_t lo = lower_bound_i32(g.keys, g.n, s), hi = lower_bound_i32(g.keys, g.n, s + 1);
+    const int64_t lo = bound[2 * j], hi = bound[2 * j + 1];
     const double *v = g.vals + (int64_t)t * g.stride;
     double a = 0.0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += SB) a += v[i];

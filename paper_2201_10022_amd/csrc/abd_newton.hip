@@ -347,6 +347,7 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     // the body terms (they read q and q~ only; the assembly adds into the
     // same blocks after the join), then the pattern
     // (done scenes get a zero right-hand side: their body terms are not needed)
+    ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, nullptr, 0, nullptr, 0, aux));
     ABD_TRY(op_body_terms(ctx, sc, prm, q, qt, nullptr, g, diag, 1, aux, done_dev));
     int32_t *apt, *aee;
     ABD_TRY(op_gather_active(ctx, act, na, na_pt, npt, pt, ee, &apt, &aee, aux));
@@ -371,7 +372,6 @@ int newton_iteration(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, d
     if (off_j) *off_j = off;
     return ABD_OK;
   };
-  ABD_TRY(zero4(ctx, g, n12, diag, 144 * (int64_t)nb, nullptr, 0, nullptr, 0, s));
   // adaptive barrier stiffness: the doubling rule at this iterate, before
   // the barrier's derivatives and this iteration's energies
   if (ctx->kappa_sc) ABD_TRY(op_kappa_update(ctx, sc, prm, x, pt, npt, ee, nee, s));

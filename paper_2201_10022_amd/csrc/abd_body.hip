@@ -647,13 +647,6 @@ int op_body_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, con
                     s, prm->kappa_j);
 }
 
-int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int n_trials, double *x,
-                         hipStream_t s) {
-  if (sc->n_verts <= 0 || n_trials <= 0) return ABD_OK;
-  hipLaunchKernelGGL(k_vertex_map, dim3(grid_for(sc->n_verts, 256), n_trials), dim3(256), 0, s, sc->n_verts, sc->xbar,
-                     sc->vert_body, q, x, 12 * (int64_t)sc->n_bodies);
-  return abd_hip_check(ctx, hipGetLastError(), "k_vertex_map");
-}
 
 int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                           const double *qt, int n_trials, double *energy, hipStream_t s, double *items,
@@ -679,16 +672,6 @@ int op_body_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *p
   return seg_sum_trials(ctx, eb, nb, nb, sc->body_scene, n_trials, S, energy, s);
 }
 
-int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
-                          const double *qt, double *energy, hipStream_t s) {
-  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
-  if (S <= 1) return op_body_energy(ctx, sc, prm, q, qt, energy, s);
-  ABD_TRY(body_terms(ctx, sc, q, qt, prm->kappa_o, prm->dt * prm->dt, 1, 1 + prm->rigidity, 0, nullptr, nullptr, nullptr,
-                     s, prm->kappa_j));
-  double *eb;
-  ABD_TRY(ws(ctx, "body_e", sc->n_bodies, &eb, s));
-  return seg_sum_scenes(ctx, eb, sc->body_scene, sc->n_bodies, S, energy, s);
-}
 
 int op_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,
                      double *energy, double *grad, double *diag, int project, hipStream_t s) {

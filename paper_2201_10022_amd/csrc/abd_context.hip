@@ -473,25 +473,6 @@ __global__ void k_scene_offsets(int nb, const int32_t *body_scene, int n_scenes,
   off[s] = (int32_t)lower_bound_i32(body_scene, nb, s);
 }
 
-// one block per scene: fixed-order sum of the items whose (non-decreasing)
-// key equals the scene
-__global__ void __launch_bounds__(SB) k_seg_reduce(const double *vals, const int32_t *keys, int64_t n, double *out,
-                                                   int accumulate) {
-  __shared__ double sh[SB / 64];
-  const int s = blockIdx.x;
-  const int64_t lo = lower_bound_i32(keys, n, s), hi = lower_bound_i32(keys, n, s + 1);
-  double v = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += SB) v = v + vals[i];
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = sh[0];
-    for (int w = 1; w < SB / 64; ++w) r = r + sh[w];
-    out[s] = accumulate ? out[s] + r : r;
-  }
-}
-
 // Trial-major values (trial t's items at vals + t * stride): one block per
 // (trial, scene) sums the scene's items in fixed order into out[t S + s].
 __global__ void __launch_bounds__(SB) k_seg_reduce_trials(const double *vals, int64_t stride, int64_t n,
@@ -628,13 +609,6 @@ int op_scene_offsets(abd_ctx *ctx, const abd_scene *sc, const int32_t **off, hip
   hipLaunchKernelGGL(k_scene_offsets, dim3(grid_for(S + 1, 256)), dim3(256), 0, s, sc->n_bodies, sc->body_scene, S,
                      o);
   return abd_hip_check(ctx, hipGetLastError(), "k_scene_offsets");
-}
-
-int seg_sum_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out_accum,
-                   hipStream_t s) {
-  if (n_scenes <= 1) return n > 0 ? reduce_sum_f64(ctx, vals, n, out_accum, s) : ABD_OK;
-  hipLaunchKernelGGL(k_seg_reduce, dim3(n_scenes), dim3(SB), 0, s, vals, keys, n, out_accum, 1);
-  return abd_hip_check(ctx, hipGetLastError(), "k_seg_reduce");
 }
 
 // ----------------------------------------------------------- profiling ----

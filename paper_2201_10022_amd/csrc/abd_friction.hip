@@ -607,24 +607,6 @@ int op_friction_energy(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr,
   return reduce_sum_f64(ctx, e, n, energy, s);
 }
 
-int op_friction_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
-                              double *energy, hipStream_t s) {
-  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
-  if (S <= 1) return op_friction_energy(ctx, sc, fr, x, energy, s);
-  const int64_t n = fr->n();
-  if (n == 0) return ABD_OK;
-  double *e;
-  int32_t *key;
-  ABD_TRY(ws(ctx, "fe_e", n, &e, s));
-  ABD_TRY(ws(ctx, "fe_key", n, &key, s));
-  hipLaunchKernelGGL(k_friction_local<true>, dim3(grid_for(n, 128)), dim3(128), 0, s, n, fr->n_pt, fr->pt, fr->ee,
-                     sc->tris, sc->edges, sc->vert_body, x, fr->xt, fr->lam, fr->T, fr->w, fr->mu, fr->eps, e,
-                     nullptr, nullptr, nullptr, sc->body_scene, key);
-  HIP_TRY(ctx, hipGetLastError());
-  if (fr->n_pt) ABD_TRY(seg_sum_scenes(ctx, e, key, fr->n_pt, S, energy, s));
-  if (fr->n_ee) ABD_TRY(seg_sum_scenes(ctx, e + fr->n_pt, key + fr->n_pt, fr->n_ee, S, energy, s));
-  return ABD_OK;
-}
 
 int op_friction_energy_trials(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
                               int n_trials, double *energy, hipStream_t s, double *items, int64_t estride,

@@ -363,18 +363,10 @@ int op_minres(abd_ctx *ctx, const abd_scene *sc, const double *diag, const doubl
               int64_t n_keys, const double *pre_diag, const double *rhs, double *x_out, double rtol, int max_iter,
               int *iters, hipStream_t s);
 // per-scene max_k |J_k p|_inf at (*out)[j * *stride] (device, context
-// workspace; a NaN displacement gives NaN); per-scene energies accumulate
-// into out [n_scenes]
-// (skip_scene, device, may be NULL: scenes it marks get 0)
+// workspace; a NaN displacement gives NaN; scenes skip_scene marks, device,
+// may be NULL, get 0)
 int op_max_abs_disp_scenes(abd_ctx *ctx, const abd_scene *sc, const double *p, const double **out, int *stride,
                            hipStream_t s, const uint8_t *skip_scene = nullptr);
-int op_body_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
-                          const double *qt, double *energy, hipStream_t s);
-int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
-                             const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy,
-                             hipStream_t s);
-int op_friction_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const FrictionSet *fr, const double *x,
-                              double *energy, hipStream_t s);
 int op_orthogonality(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q, double weight,
                      double *energy, double *grad, double *diag, int project, hipStream_t s);
 int op_inertia(abd_ctx *ctx, const abd_scene *sc, const double *q, const double *qt, double *energy, double *grad,
@@ -617,8 +609,6 @@ int reduce_min_f64(abd_ctx *ctx, const double *in, int64_t n, double init, doubl
 // itself): each op accumulates into energy[t S + scene]; with items
 // non-NULL it instead writes the per-item energies (trial t's at
 // items + t estride) and sums nothing.
-int op_vertex_map_trials(abd_ctx *ctx, const abd_scene *sc, const double *q, int n_trials, double *x,
-                         hipStream_t s);
 // With defer non-NULL (several scenes) an op writes its per-item energies
 // and their scenes and appends the segments to *defer instead of summing;
 // seg_sum_trials_multi then sums every segment in one launch.
@@ -652,7 +642,5 @@ int seg_sum_trials_multi(abd_ctx *ctx, const TrialSums &ts, int n_trials, int n_
 int seg_sum_trials(abd_ctx *ctx, const double *vals, int64_t stride, int64_t n, const int32_t *keys, int n_trials,
                    int n_scenes, double *out_accum, hipStream_t s,
                    bool assign = false);
-int seg_sum_scenes(abd_ctx *ctx, const double *vals, const int32_t *keys, int64_t n, int n_scenes, double *out_accum,
-                   hipStream_t s);
 // first body of every scene, [n_scenes + 1] (device, context workspace)
 int op_scene_offsets(abd_ctx *ctx, const abd_scene *sc, const int32_t **off, hipStream_t s);

@@ -505,29 +505,6 @@ int op_barrier_energy(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, 
   return reduce_sum_f64(ctx, e, n, energy, s);
 }
 
-int op_barrier_energy_scenes(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *x,
-                             const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee, double *energy,
-                             hipStream_t s) {
-  const int S = sc->n_scenes > 0 ? sc->n_scenes : 1;
-  if (S <= 1) return op_barrier_energy(ctx, sc, prm, x, pt, n_pt, ee, n_ee, energy, s);
-  const int64_t n = n_pt + n_ee;
-  if (n == 0) return ABD_OK;
-  double *e;
-  int32_t *key;
-  ABD_TRY(ws(ctx, "be_e", n, &e, s));
-  ABD_TRY(ws(ctx, "be_key", n, &key, s));
-  hipEvent_t pe = prof_begin(ctx, s);
-  const int eb = ctx->tune.energy_block;
-  hipLaunchKernelGGL(k_energy_only, dim3(grid_for(n, eb)), dim3(eb), 0, s, n_pt, n, pt, ee, sc->tris, sc->edges, x,
-                     sc->xbar, prm->dhat, prm->kappa_b, e, sc->vert_body, sc->body_scene, key, 0, 0,
-                     ctx->kappa_sc);
-  prof_end(ctx, pe, "energy_only", n, s);
-  HIP_TRY(ctx, hipGetLastError());
-  // PT and EE lists are each ordered by scene
-  if (n_pt) ABD_TRY(seg_sum_scenes(ctx, e, key, n_pt, S, energy, s));
-  if (n_ee) ABD_TRY(seg_sum_scenes(ctx, e + n_pt, key + n_pt, n_ee, S, energy, s));
-  return ABD_OK;
-}
 
 int op_barrier_energy_trials(abd_ctx *ctx, const abd_scene *sc, const abd_params *prm, const double *q,
                              int n_trials, const int32_t *pt, int64_t n_pt, const int32_t *ee, int64_t n_ee,
